@@ -1,0 +1,79 @@
+"""Literal brute force for the exists-exists-forall triadic query (tiny graphs).
+
+Test infrastructure only.  Independent of ``folty_oracle.c``: it reads the
+quantifiers off the definitions (paper, Definition of a thresholded FOL triadic
+query and the delta-temporal triangle of Section "Main Ideas") with no
+adjacency shortcut, no sorting and no greedy step:
+
+    count[e] = #{ w in V \\ {a, b} : exists e2 in L2(w), e3 in L3(w) with
+                  t(e) <= t(e2) <= t(e3) <= t(e) + delta }
+
+where, for the 3-bit predicate code, edge 2 hangs off a (bit 2 clear) or b,
+edge 3 off the other endpoint, and bits 0/1 flip edge 2/edge 3 to point at that
+endpoint instead of away from it.  Cost O(m * n * m^2) in the worst case: use
+n <= 200 and m <= 2,000.
+"""
+from __future__ import annotations
+
+
+def counts(n, src, dst, t, delta, variant=0):
+    src = [int(x) for x in src]
+    dst = [int(x) for x in dst]
+    t = [int(x) for x in t]
+    m = len(src)
+    by_pair = {}
+    for i in range(m):
+        if src[i] != dst[i]:
+            by_pair.setdefault((src[i], dst[i]), []).append(t[i])
+    out = []
+    for i in range(m):
+        a, b, te = src[i], dst[i], t[i]
+        if a == b:
+            out.append(0xFFFFFFFF)
+            continue
+        X, Y = (b, a) if variant & 4 else (a, b)
+        c = 0
+        for w in range(n):
+            if w == a or w == b:
+                continue
+            L2 = by_pair.get((w, X) if variant & 1 else (X, w), [])
+            L3 = by_pair.get((w, Y) if variant & 2 else (Y, w), [])
+            if any(te <= t2 <= t3 <= te + delta for t2 in L2 for t3 in L3):
+                c += 1
+        out.append(c)
+    return out
+
+
+def neighbours(n, src, dst):
+    nb = [set() for _ in range(n)]
+    for a, b in zip(src, dst):
+        a, b = int(a), int(b)
+        if a != b:
+            nb[a].add(b)
+            nb[b].add(a)
+    return nb
+
+
+def query(n, src, dst, t, delta, theta_num, theta_den, variant=0, universe=0,
+          exclude_other=False):
+    """Certificates and solution pairs, all by the definitions."""
+    cnt = counts(n, src, dst, t, delta, variant)
+    nb = neighbours(n, src, dst)
+    pairs = {}
+    ncert = 0
+    for i, (a, b) in enumerate(zip(src, dst)):
+        a, b = int(a), int(b)
+        if a == b:
+            continue
+        if universe == 0:
+            U = len(nb[b]) - (1 if exclude_other else 0)
+        elif universe == 1:
+            U = len(nb[a]) - (1 if exclude_other else 0)
+        else:
+            U = len(nb[a] & nb[b])
+        if cnt[i] * theta_den >= theta_num * U:
+            ncert += 1
+            pairs[(a, b)] = pairs.get((a, b), 0) + 1
+    keys = sorted(pairs)
+    return dict(pairs=[(a, b, pairs[(a, b)]) for a, b in keys], n_certificates=ncert,
+                counts=cnt)

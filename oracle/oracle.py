@@ -1,0 +1,194 @@
+"""Python front of the CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this module.  It loads ``libfolty_oracle.so`` built from ``folty_oracle.c`` in
+this directory with plain ``gcc`` (compiled on first use if missing or older
+than the source) and adds the threshold step and the pair reduction with numpy.
+
+Threshold step (paper, Algorithm ExistExistForAll, final loop): a temporal edge
+e = (a, b, t) is a certificate when count[e] >= theta * |U(e)|, with the
+universe U(e) = N(b) by default.  theta is an exact rational num/den, so the
+comparison is count * den >= num * |U| in integers.  Other universes: N(a), and
+N(a) intersect N(b) (Section "Insights"); ``exclude_other`` removes the other
+endpoint from N(b) / N(a).
+
+Solutions (paper, Definition of a solution): the pairs (a, b) with at least one
+certificate on them, listed in (a, b) order with their certificate counts;
+n_certificates is |Sol|.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "folty_oracle.c")
+_LIB = os.path.join(_HERE, "libfolty_oracle.so")
+U32_MAX = np.uint32(0xFFFFFFFF)
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        lib.og_build.restype = P
+        lib.og_build.argtypes = [i32, i64, P, P, P]
+        lib.og_free.argtypes = [P]
+        lib.og_counts.restype = ctypes.c_int
+        lib.og_counts.argtypes = [P, i64, P, i64, ctypes.c_int, P, ctypes.c_int]
+        lib.og_counts_pool.restype = ctypes.c_int
+        lib.og_counts_pool.argtypes = [P, i64, P, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int]
+        lib.og_degrees.argtypes = [P, P]
+        lib.og_common_counts.argtypes = [P, i64, P, P, ctypes.c_int]
+        lib.og_sizes.argtypes = [P, P, ctypes.c_int]
+        lib.og_core_numbers.argtypes = [P, P]
+        lib.og_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Oracle:
+    """The plain CPU statement of the query for one temporal graph."""
+
+    def __init__(self, n: int, src, dst, t, threads: int = 0):
+        lib = _load()
+        self.n = int(n)
+        self.src = np.ascontiguousarray(src, dtype=np.int32)
+        self.dst = np.ascontiguousarray(dst, dtype=np.int32)
+        self.t = np.ascontiguousarray(t, dtype=np.int64)
+        self.m = int(self.src.shape[0])
+        self.threads = int(threads)
+        if self.m and (self.src.min() < 0 or self.dst.min() < 0
+                       or self.src.max() >= n or self.dst.max() >= n):
+            raise ValueError("vertex id out of range")
+        self._h = lib.og_build(self.n, self.m, _ptr(self.src), _ptr(self.dst), _ptr(self.t))
+        if not self._h:
+            raise MemoryError("oracle build failed")
+        self._deg = None
+
+    def close(self):
+        if self._h:
+            _load().og_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- counts ---------------------------------------------------------------
+    def counts(self, delta: int, variant: int = 0, idx=None) -> np.ndarray:
+        """count[e] for the edges ``idx`` (input positions) or for all edges.
+        Self-loops read 0xFFFFFFFF."""
+        lib = _load()
+        if idx is None:
+            out = np.zeros(self.m, dtype=np.uint32)
+            rc = lib.og_counts(self._h, 0, None, int(delta), int(variant), _ptr(out), self.threads)
+        else:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            out = np.zeros(idx.shape[0], dtype=np.uint32)
+            rc = lib.og_counts(self._h, idx.shape[0], _ptr(idx), int(delta), int(variant),
+                               _ptr(out), self.threads)
+        if rc != 0:
+            raise ValueError("bad delta or variant")
+        return out
+
+    def counts_pool(self, deltas, variant: int = 0, idx=None) -> np.ndarray:
+        """count[e] for several windows at once, shape (edges, len(deltas))."""
+        lib = _load()
+        d = np.ascontiguousarray(deltas, dtype=np.int64)
+        k = self.m if idx is None else len(idx)
+        out = np.zeros((k, d.shape[0]), dtype=np.uint32)
+        if idx is None:
+            rc = lib.og_counts_pool(self._h, 0, None, int(variant), d.shape[0], _ptr(d), _ptr(out),
+                                    self.threads)
+        else:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            rc = lib.og_counts_pool(self._h, k, _ptr(idx), int(variant), d.shape[0], _ptr(d),
+                                    _ptr(out), self.threads)
+        if rc != 0:
+            raise ValueError("bad variant or pool")
+        return out
+
+    # -- static quantities ------------------------------------------------------
+    def degrees(self) -> np.ndarray:
+        if self._deg is None:
+            out = np.zeros(self.n, dtype=np.int32)
+            _load().og_degrees(self._h, _ptr(out))
+            self._deg = out
+        return self._deg
+
+    def common_counts(self, idx) -> np.ndarray:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.zeros(idx.shape[0], dtype=np.int64)
+        _load().og_common_counts(self._h, idx.shape[0], _ptr(idx), _ptr(out), self.threads)
+        return out
+
+    def sizes(self) -> dict:
+        out = np.zeros(4, dtype=np.int64)
+        _load().og_sizes(self._h, _ptr(out), self.threads)
+        return dict(directed_pairs=int(out[0]), static_edges=int(out[1]),
+                    triangles=int(out[2]), max_degree=int(out[3]))
+
+    def core_numbers(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int32)
+        _load().og_core_numbers(self._h, _ptr(out))
+        return out
+
+    # -- threshold step and solutions ----------------------------------------------
+    def universe_sizes(self, idx=None, universe: int = 0, exclude_other: bool = False):
+        idx = np.arange(self.m, dtype=np.int64) if idx is None else np.asarray(idx, np.int64)
+        a, b = self.src[idx], self.dst[idx]
+        deg = self.degrees()
+        if universe == 0:
+            u = deg[b].astype(np.int64) - (1 if exclude_other else 0)
+        elif universe == 1:
+            u = deg[a].astype(np.int64) - (1 if exclude_other else 0)
+        elif universe == 2:
+            if exclude_other:
+                raise ValueError("exclude_other applies to universes 0 and 1 only")
+            u = self.common_counts(idx)
+        else:
+            raise ValueError("universe")
+        return u
+
+    def query(self, delta: int, theta_num: int, theta_den: int, variant: int = 0,
+              universe: int = 0, exclude_other: bool = False, counts=None) -> dict:
+        if theta_den <= 0 or theta_num < 0 or theta_num > theta_den:
+            raise ValueError("theta must be num/den in [0, 1]")
+        cnt = self.counts(delta, variant) if counts is None else counts
+        loop = self.src == self.dst
+        keep = ~loop
+        idx = np.nonzero(keep)[0]
+        u = self.universe_sizes(idx, universe, exclude_other)
+        lhs = cnt[idx].astype(np.uint64) * np.uint64(theta_den)
+        rhs = u.astype(np.uint64) * np.uint64(theta_num)
+        cert = lhs >= rhs
+        ci = idx[cert]
+        keys = self.src[ci].astype(np.int64) * self.n + self.dst[ci].astype(np.int64)
+        uk, nc = np.unique(keys, return_counts=True)
+        return dict(pair_u=(uk // self.n).astype(np.int32), pair_v=(uk % self.n).astype(np.int32),
+                    n_cert=nc.astype(np.uint32), n_certificates=int(cert.sum()),
+                    counts=cnt, self_loops=int(loop.sum()))

@@ -1,0 +1,269 @@
+"""Pins for the CPU oracle: it is checked against things other than itself.
+
+* hand-derived values for small worked cases (tests/golden/hand_cases.json),
+* a literal brute force of the quantifiers on hundreds of tiny random graphs,
+* the all-equal-timestamps reduction to products of the 0/1 adjacency matrix
+  (scipy.sparse), and networkx for common neighbours and core numbers,
+* closed forms (complete digraph, triangle-free graphs, single triangles),
+* invariants the definitions imply (relabelling, time shift and scale, input
+  order, monotonicity in delta and theta).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import bruteforce as bf
+from oracle.oracle import Oracle, U32_MAX
+from paper_2507_17215_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")
+INF = np.iinfo(np.int64).max
+
+
+def _graph_cases():
+    d = json.load(open(GOLD))
+    for g in d["graphs"]:
+        for c in g["cases"]:
+            yield g, c
+
+
+@pytest.mark.parametrize("g,c", list(_graph_cases()),
+                         ids=lambda x: x.get("name", "") if isinstance(x, dict) and "name" in x else "")
+def test_hand_cases(g, c):
+    e = np.array(g["edges"], dtype=np.int64)
+    o = Oracle(g["n"], e[:, 0], e[:, 1], e[:, 2])
+    q = o.query(c["delta"], c["theta"][0], c["theta"][1], c["variant"],
+                c.get("universe", 0), bool(c.get("exclude_other", 0)))
+    assert q["counts"].tolist() == c["counts"]
+    got = [[int(a), int(b), int(k)] for a, b, k in zip(q["pair_u"], q["pair_v"], q["n_cert"])]
+    assert got == c["pairs"]
+    assert q["n_certificates"] == c["n_certificates"]
+    # the brute force agrees with the hand values too
+    bq = bf.query(g["n"], e[:, 0], e[:, 1], e[:, 2], c["delta"], c["theta"][0], c["theta"][1],
+                  c["variant"], c.get("universe", 0), bool(c.get("exclude_other", 0)))
+    assert bq["counts"] == c["counts"]
+    assert [list(p) for p in bq["pairs"]] == c["pairs"]
+
+
+def test_bruteforce_random_tiny():
+    rng = np.random.default_rng(1234)
+    for it in range(240):
+        g = synth.random_small(rng)
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        for variant in range(8):
+            for delta in (0, 1, 5, INF):
+                want = np.array(bf.counts(g.n, g.src, g.dst, g.t, delta, variant), dtype=np.uint32)
+                got = o.counts(delta, variant)
+                assert np.array_equal(want, got), (it, variant, delta)
+
+
+def test_bruteforce_small_generator():
+    g = synth.bruteforce_size()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    for variant in (0, 3, 6):
+        for delta in (3600, 100_000, 10**6):
+            want = np.array(bf.counts(g.n, g.src, g.dst, g.t, delta, variant), dtype=np.uint32)
+            assert np.array_equal(want, o.counts(delta, variant))
+    for th in ((0, 1), (1, 4), (1, 2), (1, 1)):
+        for uni, ex in ((0, False), (1, False), (2, False), (0, True), (1, True)):
+            q = o.query(10**6, th[0], th[1], 0, uni, ex)
+            b = bf.query(g.n, g.src, g.dst, g.t, 10**6, th[0], th[1], 0, uni, ex)
+            assert q["n_certificates"] == b["n_certificates"]
+            assert [(int(a), int(c), int(k)) for a, c, k in
+                    zip(q["pair_u"], q["pair_v"], q["n_cert"])] == b["pairs"]
+
+
+def _adj(n, src, dst):
+    keep = src != dst
+    a = sp.coo_matrix((np.ones(keep.sum()), (src[keep], dst[keep])), shape=(n, n)).tocsr()
+    a.data[:] = 1.0
+    a.sum_duplicates()
+    a.data[:] = 1.0
+    return a
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_equal_timestamps_reduce_to_matrix_products(variant):
+    """All timestamps equal: e = (a, b) counts every w with both lists non-empty,
+    which is an entry of a product of the directed 0/1 adjacency matrix A."""
+    rng = np.random.default_rng(7 + variant)
+    n, m = 60, 900
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    t = np.full(m, 12345, dtype=np.int64)
+    A = _adj(n, src, dst)
+    At = A.T.tocsr()
+    # edge 2 between X and w, edge 3 between Y and w
+    M2 = At if variant & 1 else A   # row X: w with (w->X) if bit0 else (X->w)
+    M3 = At if variant & 2 else A
+    P = (M2 @ M3.T).toarray()       # P[X, Y] = #w with both lists non-empty
+    o = Oracle(n, src, dst, t)
+    for delta in (0, 5, INF):
+        got = o.counts(delta, variant)
+        for i in range(m):
+            a, b = int(src[i]), int(dst[i])
+            if a == b:
+                assert got[i] == U32_MAX
+                continue
+            X, Y = (b, a) if variant & 4 else (a, b)
+            assert got[i] == int(round(P[X, Y])), (i, a, b)
+
+
+def test_complete_digraph_equal_times():
+    n = 9
+    src, dst = zip(*[(a, b) for a in range(n) for b in range(n) if a != b])
+    src, dst = np.array(src, np.int32), np.array(dst, np.int32)
+    t = np.zeros(src.shape[0], np.int64)
+    o = Oracle(n, src, dst, t)
+    for variant in range(8):
+        assert (o.counts(0, variant) == n - 2).all()
+
+
+def test_triangle_free_graphs_count_zero():
+    rng = np.random.default_rng(3)
+    # star
+    m = 300
+    leaves = rng.integers(1, 50, m)
+    flip = rng.random(m) < 0.5
+    src = np.where(flip, 0, leaves).astype(np.int32)
+    dst = np.where(flip, leaves, 0).astype(np.int32)
+    t = rng.integers(0, 10, m).astype(np.int64)
+    o = Oracle(50, src, dst, t)
+    for v in range(8):
+        assert (o.counts(INF, v) == 0).all()
+    # bipartite
+    a = rng.integers(0, 20, m)
+    b = rng.integers(20, 40, m)
+    flip = rng.random(m) < 0.5
+    src = np.where(flip, a, b).astype(np.int32)
+    dst = np.where(flip, b, a).astype(np.int32)
+    o = Oracle(40, src, dst, t)
+    for v in range(8):
+        assert (o.counts(INF, v) == 0).all()
+
+
+def _nx_graph(n, src, dst):
+    import networkx as nx
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from((int(a), int(b)) for a, b in zip(src, dst) if a != b)
+    return G
+
+
+def test_common_neighbours_and_degrees_match_networkx():
+    import networkx as nx
+    g = synth.tiny()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    G = _nx_graph(g.n, g.src, g.dst)
+    deg = o.degrees()
+    assert all(deg[x] == G.degree(x) for x in range(g.n))
+    idx = np.arange(0, g.m, 37)
+    cc = o.common_counts(idx)
+    for q, i in enumerate(idx):
+        a, b = int(g.src[i]), int(g.dst[i])
+        want = -1 if a == b else len(list(nx.common_neighbors(G, a, b)))
+        assert cc[q] == want
+    s = o.sizes()
+    assert s["static_edges"] == G.number_of_edges()
+    assert s["triangles"] == sum(nx.triangles(G).values()) // 3
+
+
+def test_counts_bounded_by_common_neighbours():
+    g = synth.tiny()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    c = o.counts(INF, 0)
+    cc = o.common_counts(np.arange(g.m))
+    keep = cc >= 0
+    assert (c[keep].astype(np.int64) <= cc[keep]).all()
+
+
+def test_core_numbers_match_networkx():
+    import networkx as nx
+    for gen in (synth.tiny(), synth.bruteforce_size(),
+                synth.generate(3000, 40000, 2.0, law="pareto", cap=50, times="uniform",
+                               t_range=1000, seed=5, communities=3, c_min=40, c_max=80, c_p=0.5)):
+        o = Oracle(gen.n, gen.src, gen.dst, gen.t)
+        G = _nx_graph(gen.n, gen.src, gen.dst)
+        want = nx.core_number(G)
+        core = o.core_numbers()
+        assert all(core[x] == want[x] for x in range(gen.n))
+
+
+def test_theta_zero_and_one():
+    g = synth.bruteforce_size()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    q = o.query(3600, 0, 1)
+    loops = g.src == g.dst
+    assert q["n_certificates"] == int((~loops).sum())
+    pairs = set(zip(g.src[~loops].tolist(), g.dst[~loops].tolist()))
+    assert set(zip(q["pair_u"].tolist(), q["pair_v"].tolist())) == pairs
+    c = o.counts(INF, 0)
+    q1 = o.query(INF, 1, 1, counts=c)
+    deg = o.degrees()
+    full = (~loops) & (c.astype(np.int64) == deg[g.dst])
+    assert q1["n_certificates"] == int(full.sum())
+
+
+def test_invariants_relabel_shift_scale_shuffle():
+    rng = np.random.default_rng(11)
+    g = synth.bruteforce_size()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    base = {v: o.counts(200_000, v) for v in (0, 3, 6)}
+    perm = rng.permutation(g.n).astype(np.int32)
+    o2 = Oracle(g.n, perm[g.src], perm[g.dst], g.t)
+    o3 = Oracle(g.n, g.src, g.dst, g.t + 987_654_321)
+    o4 = Oracle(g.n, g.src, g.dst, g.t * 7)
+    order = rng.permutation(g.m)
+    o5 = Oracle(g.n, g.src[order], g.dst[order], g.t[order])
+    for v, c in base.items():
+        assert np.array_equal(o2.counts(200_000, v), c)
+        assert np.array_equal(o3.counts(200_000, v), c)
+        assert np.array_equal(o4.counts(1_400_000, v), c)
+        assert np.array_equal(o5.counts(200_000, v), c[order])
+
+
+def test_monotone_in_delta_and_nested_in_theta():
+    g = synth.tiny()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    prev = None
+    for d in (0, 600, 3600, 86400, 400_000, 10**6, INF):
+        c = o.counts(d, 0)
+        if prev is not None:
+            assert (c >= prev).all()
+        prev = c
+    sets = []
+    for num in (0, 1, 2, 3, 4):
+        q = o.query(10**6, num, 4, counts=prev)
+        sets.append(set(zip(q["pair_u"].tolist(), q["pair_v"].tolist())))
+    for hi, lo in zip(sets[1:], sets[:-1]):
+        assert hi <= lo
+
+
+def test_pool_mode_matches_direct_mode():
+    g = synth.tiny()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    deltas = [0, 60, 3600, 86400, 500_000, INF]
+    for v in (0, 3):
+        pool = o.counts_pool(deltas, v)
+        for j, d in enumerate(deltas):
+            assert np.array_equal(pool[:, j], o.counts(d, v))
+    idx = np.array([0, 5, 17, 1999, 19999])
+    pool = o.counts_pool(deltas, 0, idx)
+    for j, d in enumerate(deltas):
+        assert np.array_equal(pool[:, j], o.counts(d, 0, idx))
+
+
+def test_bad_arguments_rejected():
+    g = synth.bruteforce_size()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    with pytest.raises(ValueError):
+        o.counts(-1, 0)
+    with pytest.raises(ValueError):
+        o.counts(5, 8)
+    with pytest.raises(ValueError):
+        o.query(5, 3, 2)
+    with pytest.raises(ValueError):
+        Oracle(3, np.array([0, 3], np.int32), np.array([1, 1], np.int32), np.array([0, 0]))
