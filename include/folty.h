@@ -1,0 +1,232 @@
+/*
+ * folty.h - C ABI of the MI355X (gfx950) library for thresholded
+ * exists-exists-forall triadic queries on temporal multigraphs.
+ *
+ * The query (paper: Definition of a thresholded FOL triadic query; Section
+ * "Main Ideas"; Algorithm ExistExistForAll):
+ *
+ *   A temporal edge e = (a, b, t) forms a delta-temporal triangle with a third
+ *   vertex w when temporal edges e2 and e3 exist, on the lists the predicate
+ *   picks, with t <= t(e2) <= t(e3) <= t + delta.  For the paper's predicate
+ *   e2 runs a -> w and e3 runs b -> w.  count[e] is the number of distinct such
+ *   w.  e is a certificate when count[e] >= theta * |U(e)|, where the universe
+ *   U(e) is N(b) by default (N(x) = neighbours of x in the static graph that
+ *   drops directions, parallel edges and self-loops).  A solution is a pair
+ *   (a, b) with at least one certificate on it.
+ *
+ * Conventions for every call:
+ *   - Every call returns FOLTY_OK (0) or a negative FOLTY_E* code; on error
+ *     folty_last_error() returns a message for the calling thread.
+ *   - Pointers marked "host" are CPU memory; "device" are HIP device memory of
+ *     the current device.  Input arrays are only read during the call and are
+ *     copied; the library never keeps a caller pointer.
+ *   - Handles belong to the caller until the matching *_free call.  Result
+ *     arrays returned by accessors stay valid until folty_result_free.
+ *   - A built graph is read-only: several threads may query one graph at the
+ *     same time, each with its own folty_workspace (see folty_run_fol_query_ws).
+ *   - All work runs on the HIP stream given at load time (NULL = the library
+ *     creates one stream per graph).
+ *   - The library needs a HIP device; without one every call that touches the
+ *     GPU fails with FOLTY_EDEVICE.  There is no CPU fallback.
+ */
+#ifndef FOLTY_H
+#define FOLTY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FOLTY_OK = 0,
+    FOLTY_EINVAL = -1,    /* bad argument: id out of range, t out of [0, 2^62), delta < 0,
+                             theta not in [0, 1], den = 0, unknown variant or universe */
+    FOLTY_ENOTBUILT = -2, /* query on a graph whose index was not built */
+    FOLTY_ENOMEM = -3,    /* device allocation failed or an admission budget was exceeded */
+    FOLTY_EDEVICE = -4,   /* a HIP call failed (no device, launch failure, ...) */
+    FOLTY_EOVERFLOW = -5, /* m >= 2^31 or a count that does not fit the index types */
+    FOLTY_EBUSY = -6      /* server: result not ready yet */
+};
+
+enum { FOLTY_MEM_HOST = 0, FOLTY_MEM_DEVICE = 1 };
+
+/* delta meaning "no window" */
+#define FOLTY_DELTA_INF INT64_MAX
+
+/* Universe of the thresholded universal quantifier */
+enum {
+    FOLTY_UNIVERSE_DST = 0,    /* N(b): Algorithm ExistExistForAll, the paper's default */
+    FOLTY_UNIVERSE_SRC = 1,    /* N(a) */
+    FOLTY_UNIVERSE_COMMON = 2  /* N(a) intersect N(b): Section "Insights" */
+};
+
+/* Ordering used to orient the static graph (result-neutral; only speed changes) */
+enum {
+    FOLTY_RANK_DEGENERACY = 0, /* min-degree peeling (core, peel round, id): out-degree <= degeneracy */
+    FOLTY_RANK_DEGREE = 1,     /* (degree, id) */
+    FOLTY_RANK_RANDOM = 2      /* hash of (id, seed); for orientation-independence tests */
+};
+
+typedef struct folty_graph folty_graph;
+typedef struct folty_result folty_result;
+typedef struct folty_workspace folty_workspace;
+
+typedef struct {
+    int32_t rank_mode;       /* FOLTY_RANK_*; default FOLTY_RANK_DEGENERACY */
+    int32_t cache_triangles; /* 1: keep the static triangle list in the index, so queries
+                                skip wedge enumeration; 0 (default): enumerate per query */
+    uint64_t rank_seed;      /* seed for FOLTY_RANK_RANDOM */
+} folty_build_opts;
+
+/*
+ * One query.  theta = theta_num / theta_den, compared exactly in integers:
+ * count[e] * theta_den >= theta_num * |U(e)|.
+ *
+ * variant: 3-bit predicate code.  With X, Y the endpoints edge 2 and edge 3
+ * hang off (X = a, Y = b when bit 2 is clear; X = b, Y = a when set):
+ *   bit 0 clear: e2 runs X -> w; set: w -> X.
+ *   bit 1 clear: e3 runs Y -> w; set: w -> Y.
+ * 0 is the paper's temporal triangle (a->w, b->w); 3 has both closing edges
+ * leave w (w->a, w->b); 6 is the cyclic triangle a->b, b->w, w->a.
+ */
+typedef struct {
+    int64_t delta;          /* >= 0, seconds (same unit as t); FOLTY_DELTA_INF = no window */
+    uint32_t theta_num;     /* theta_num <= theta_den */
+    uint32_t theta_den;     /* > 0 */
+    uint8_t variant;        /* 0..7 */
+    uint8_t universe;       /* FOLTY_UNIVERSE_* */
+    uint8_t exclude_other;  /* 1: |U| - 1 (drop the other endpoint); universes DST/SRC only */
+    uint8_t flags;          /* FOLTY_QUERY_* bits; other bits must be 0 */
+} folty_query;
+
+/* Query flag: do not keep per-edge counts in the result (folty_result_counts then
+ * gives |Sol| only).  Saves 4 bytes per input edge of device memory and a pass. */
+#define FOLTY_QUERY_NO_COUNTS 1u
+
+/* Sizes and timings of a graph's index (folty_graph_stats) or of one query
+ * (folty_result_stats; then the graph fields are copied in as well). */
+typedef struct {
+    int64_t n;                /* vertices */
+    int64_t m_input;          /* temporal edges given */
+    int64_t m;                /* temporal edges kept (self-loops dropped) */
+    int64_t self_loops;
+    int64_t static_edges;     /* |E(G_S)| */
+    int64_t directed_pairs;   /* non-empty lists E_{x,y} */
+    int64_t max_core;         /* degeneracy (largest core number) */
+    int64_t max_out_degree;   /* largest |N+(x)| of the orientation used */
+    int64_t wedges;           /* sum over x of C(|N+(x)|, 2): oriented wedges, one closing probe each */
+    int64_t triangles;        /* static triangles */
+    int64_t max_multiplicity; /* sigma_max: longest list E_{x,y} */
+    int64_t peel_rounds;      /* rounds of the min-degree peeling */
+    /* query only */
+    int64_t tests;            /* temporal tests: sum over (triangle, list E_{a,b} with both
+                                 closing lists non-empty) of |E_{a,b}| */
+    int64_t n_pairs;          /* solution pairs */
+    int64_t n_certificates;   /* |Sol| */
+    double build_ms;          /* device time of folty_build_index */
+    double wedge_ms;          /* device time of wedge enumeration + closing probe */
+    double temporal_ms;       /* device time of the temporal tests */
+    double threshold_ms;      /* device time of threshold, pair reduction and compaction */
+    double query_ms;          /* device time of the whole query */
+} folty_stats;
+
+/* Message for the last failed call on this thread ("" if none).  Valid until the
+ * thread's next failing call. */
+const char *folty_last_error(void);
+
+/* Library version string. */
+const char *folty_version(void);
+
+/*
+ * Load a temporal edge list (paper, Section "Main Ideas": a list of triples
+ * (u, v, t), u the head, v the destination; a multigraph).
+ *   n         vertices; ids must lie in [0, n); 1 <= n < 2^31.
+ *   m         edges; 0 <= m < 2^31 (FOLTY_EOVERFLOW otherwise).
+ *   src, dst  int32[m], t int64[m] with 0 <= t < 2^62; host or device memory as
+ *             mem_kind says.  Order is free (the paper assumes time order; this
+ *             library sorts).  Self-loops are accepted and ignored by the query.
+ *   stream    hipStream_t to run on, or NULL.
+ *   out       receives the graph handle.
+ * Validates ids and timestamps on the device (FOLTY_EINVAL with the first bad
+ * position in the message).  The inputs are copied.
+ */
+int folty_load_temporal_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                              const int64_t *t, int32_t mem_kind, void *stream,
+                              folty_graph **out);
+
+/*
+ * Build the index (paper, Section "Main Ideas" and Section 3 preamble):
+ * group edges into time-sorted lists E_{x,y} and static edges, compute degrees
+ * and core numbers, orient G_S by the chosen ordering, count static
+ * triangles.  opts may be NULL (defaults).  Calling it again rebuilds.
+ */
+int folty_build_index(folty_graph *g, const folty_build_opts *opts);
+
+/*
+ * Run one query and wait for it (paper, Algorithm ExistExistForAll).  *out
+ * receives a result holding the sorted solution pairs; per-edge counts are
+ * fetched on demand by folty_result_counts.
+ */
+int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out);
+
+/* The same with caller-owned scratch memory, for concurrent queries on one
+ * graph from several threads (one workspace per thread). */
+int folty_workspace_create(folty_workspace **out);
+void folty_workspace_free(folty_workspace *ws);
+int folty_run_fol_query_ws(folty_graph *g, const folty_query *q, folty_workspace *ws,
+                           folty_result **out);
+
+/*
+ * Several queries on one graph in one pass (paper, proof of Theorem 3.1: the
+ * greedy pair (first t2 >= t, then first t3 >= t2) gives the smallest window
+ * t3 - t, so each (e, w) is resolved once for every delta).  Queries may mix
+ * delta, theta, universe and variant.  outs[i] receives the result of qs[i].
+ */
+int folty_run_batch(folty_graph *g, const folty_query *qs, int32_t nq, folty_result **outs);
+
+/*
+ * One query on each of several graphs in one launch sequence (graphs of
+ * uneven size share one load-balanced pass).  outs[i] is the result of qs[i]
+ * on gs[i].  All graphs must be built and loaded on the same device.
+ */
+int folty_run_multi(folty_graph *const *gs, const folty_query *qs, int32_t ng,
+                    folty_result **outs);
+
+/*
+ * Solution pairs of a result, sorted by (u, v), with the number of
+ * certificates on each pair.  Host pointers, valid until folty_result_free.
+ */
+int folty_result_pairs(const folty_result *r, int64_t *n_pairs, const int32_t **u,
+                       const int32_t **v, const uint32_t **n_cert);
+
+/*
+ * |Sol| and, if edge_count is not NULL, the per-temporal-edge counts in input
+ * order (host, m_input entries; 0xFFFFFFFF marks a dropped self-loop).  The
+ * counts are copied from the device on the first call.
+ */
+int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t **edge_count);
+
+int folty_result_stats(const folty_result *r, folty_stats *s);
+void folty_result_free(folty_result *r);
+
+/* Index sizes and build timing. */
+int folty_graph_stats(const folty_graph *g, folty_stats *s);
+
+/*
+ * Copies of index arrays, indexed by original vertex id (host int32[n]):
+ *   what = 0: |N(x)|; 1: core number; 2: rank of x in the orientation order;
+ *          3: |N+(x)| under that orientation.
+ */
+int folty_graph_vertex_array(const folty_graph *g, int32_t what, int32_t *out);
+
+/* Device memory held by the index, in bytes. */
+int folty_graph_device_bytes(const folty_graph *g, int64_t *bytes);
+
+void folty_graph_free(folty_graph *g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOLTY_H */

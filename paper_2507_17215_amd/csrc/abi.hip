@@ -1,0 +1,225 @@
+// extern "C" entry points of include/folty.h: argument checks, error codes,
+// handle lifetimes.  Every call catches internal errors and turns them into a
+// return code plus a thread-local message.
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "folty_internal.h"
+
+struct folty_graph {
+    folty::Graph g;
+};
+struct folty_result {
+    folty::Result r;
+};
+struct folty_workspace {
+    folty::Workspace ws;
+};
+
+namespace folty {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
+
+void fail(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error(code, buf);
+}
+
+Graph::~Graph() {
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+template <class F> static int guarded(F &&f) {
+    try {
+        f();
+        return FOLTY_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return FOLTY_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return FOLTY_EDEVICE;
+    }
+}
+
+} // namespace folty
+
+using namespace folty;
+
+extern "C" {
+
+const char *folty_last_error(void) { return g_last_error.c_str(); }
+
+const char *folty_version(void) { return "folty-gfx950 0.1"; }
+
+int folty_load_temporal_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t,
+                              int32_t mem_kind, void *stream, folty_graph **out) {
+    return guarded([&] {
+        if (!out) fail(FOLTY_EINVAL, "out is null");
+        *out = nullptr;
+        std::unique_ptr<folty_graph> h(new folty_graph());
+        load_graph(&h->g, n, m, src, dst, t, mem_kind, stream);
+        *out = h.release();
+    });
+}
+
+int folty_build_index(folty_graph *g, const folty_build_opts *opts) {
+    return guarded([&] {
+        if (!g) fail(FOLTY_EINVAL, "graph is null");
+        FOLTY_HIP(hipSetDevice(g->g.device));
+        build_index(&g->g, opts);
+    });
+}
+
+int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out) {
+    return guarded([&] {
+        if (!g || !q || !out) fail(FOLTY_EINVAL, "null argument");
+        *out = nullptr;
+        Result *r = run_query(&g->g, *q, g->g.ws);
+        folty_result *h = new folty_result();
+        h->r = std::move(*r);
+        delete r;
+        *out = h;
+    });
+}
+
+int folty_workspace_create(folty_workspace **out) {
+    return guarded([&] {
+        if (!out) fail(FOLTY_EINVAL, "out is null");
+        *out = new folty_workspace();
+    });
+}
+
+void folty_workspace_free(folty_workspace *ws) { delete ws; }
+
+int folty_run_fol_query_ws(folty_graph *g, const folty_query *q, folty_workspace *ws, folty_result **out) {
+    return guarded([&] {
+        if (!g || !q || !ws || !out) fail(FOLTY_EINVAL, "null argument");
+        *out = nullptr;
+        Result *r = run_query(&g->g, *q, ws->ws);
+        folty_result *h = new folty_result();
+        h->r = std::move(*r);
+        delete r;
+        *out = h;
+    });
+}
+
+int folty_run_batch(folty_graph *g, const folty_query *qs, int32_t nq, folty_result **outs) {
+    return guarded([&] {
+        if (!g || (nq > 0 && (!qs || !outs))) fail(FOLTY_EINVAL, "null argument");
+        std::vector<Result *> rs(nq > 0 ? nq : 0, nullptr);
+        run_batch(&g->g, qs, nq, g->g.ws, rs.data());
+        for (int i = 0; i < nq; i++) {
+            folty_result *h = new folty_result();
+            h->r = std::move(*rs[i]);
+            delete rs[i];
+            outs[i] = h;
+        }
+    });
+}
+
+int folty_run_multi(folty_graph *const *gs, const folty_query *qs, int32_t ng, folty_result **outs) {
+    return guarded([&] {
+        if (ng > 0 && (!gs || !qs || !outs)) fail(FOLTY_EINVAL, "null argument");
+        std::vector<Graph *> g(ng > 0 ? ng : 0);
+        for (int i = 0; i < ng; i++) {
+            if (!gs[i]) fail(FOLTY_EINVAL, "graph %d is null", i);
+            g[i] = &gs[i]->g;
+        }
+        std::vector<Result *> rs(ng > 0 ? ng : 0, nullptr);
+        Workspace ws;
+        run_multi(g.data(), qs, ng, ws, rs.data());
+        for (int i = 0; i < ng; i++) {
+            folty_result *h = new folty_result();
+            h->r = std::move(*rs[i]);
+            delete rs[i];
+            outs[i] = h;
+        }
+    });
+}
+
+int folty_result_pairs(const folty_result *r, int64_t *n_pairs, const int32_t **u, const int32_t **v,
+                       const uint32_t **n_cert) {
+    return guarded([&] {
+        if (!r) fail(FOLTY_EINVAL, "result is null");
+        if (n_pairs) *n_pairs = (int64_t)r->r.u.size();
+        if (u) *u = r->r.u.data();
+        if (v) *v = r->r.v.data();
+        if (n_cert) *n_cert = r->r.n_cert.data();
+    });
+}
+
+int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t **edge_count) {
+    return guarded([&] {
+        if (!r) fail(FOLTY_EINVAL, "result is null");
+        if (n_certificates) *n_certificates = r->r.n_certificates;
+        if (!edge_count) return;
+        *edge_count = nullptr;
+        if (!r->r.has_counts) fail(FOLTY_EINVAL, "query ran with FOLTY_QUERY_NO_COUNTS");
+        if (!r->r.counts_fetched) {
+            FOLTY_HIP(hipSetDevice(r->r.device));
+            size_t n = (size_t)r->r.stats.m_input;
+            r->r.counts_host.resize(n);
+            if (n) FOLTY_HIP(hipMemcpy(r->r.counts_host.data(), r->r.counts_dev.p, 4 * n, hipMemcpyDeviceToHost));
+            r->r.counts_fetched = true;
+            r->r.counts_dev.release();
+        }
+        *edge_count = r->r.counts_host.data();
+    });
+}
+
+int folty_result_stats(const folty_result *r, folty_stats *s) {
+    return guarded([&] {
+        if (!r || !s) fail(FOLTY_EINVAL, "null argument");
+        *s = r->r.stats;
+    });
+}
+
+void folty_result_free(folty_result *r) { delete r; }
+
+int folty_graph_stats(const folty_graph *g, folty_stats *s) {
+    return guarded([&] {
+        if (!g || !s) fail(FOLTY_EINVAL, "null argument");
+        *s = folty_stats{};
+        fill_stats_from_index(g->g.ix, s);
+    });
+}
+
+int folty_graph_vertex_array(const folty_graph *g, int32_t what, int32_t *out) {
+    return guarded([&] {
+        if (!g || !out) fail(FOLTY_EINVAL, "null argument");
+        const Index &ix = g->g.ix;
+        if (!ix.built) fail(FOLTY_ENOTBUILT, "index not built");
+        const DevBuf *b = what == 0 ? &ix.deg : what == 1 ? &ix.core : what == 2 ? &ix.rank : what == 3 ? &ix.outdeg : nullptr;
+        if (!b) fail(FOLTY_EINVAL, "unknown vertex array %d", what);
+        FOLTY_HIP(hipSetDevice(g->g.device));
+        FOLTY_HIP(hipStreamSynchronize(g->g.stream));
+        FOLTY_HIP(hipMemcpy(out, b->p, 4 * (size_t)ix.n, hipMemcpyDeviceToHost));
+    });
+}
+
+int folty_graph_device_bytes(const folty_graph *g, int64_t *bytes) {
+    return guarded([&] {
+        if (!g || !bytes) fail(FOLTY_EINVAL, "null argument");
+        *bytes = (int64_t)g->g.ix.device_bytes();
+    });
+}
+
+void folty_graph_free(folty_graph *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->g.device);
+    if (g->g.stream) (void)hipStreamSynchronize(g->g.stream);
+    delete g;
+}
+
+} // extern "C"

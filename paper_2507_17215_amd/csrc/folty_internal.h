@@ -1,0 +1,242 @@
+// Internal declarations of the gfx950 library behind include/folty.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "folty.h"
+
+namespace folty {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &msg) : std::runtime_error(msg), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const char *fmt, ...);
+void set_last_error(const char *msg);
+
+#define FOLTY_HIP(expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            ::folty::fail(e_ == hipErrorOutOfMemory ? FOLTY_ENOMEM : FOLTY_EDEVICE,          \
+                          "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define FOLTY_LAUNCHED()                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess)                                                                \
+            ::folty::fail(FOLTY_EDEVICE, "kernel launch: %s (%s:%d)", hipGetErrorString(e_),  \
+                          __FILE__, __LINE__);                                               \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory: a growable buffer owned by one object
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow to at least b bytes; contents are not kept
+    void ensure(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        size_t want = b ? b : 256;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(FOLTY_ENOMEM, "hipMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
+        }
+        bytes = want;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// pinned host scratch for small read-backs
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+    void ensure(size_t b) {
+        if (b <= bytes && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        FOLTY_HIP(hipHostMalloc(&p, b ? b : 64, hipHostMallocDefault));
+        bytes = b ? b : 64;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// the index of one temporal graph (all device arrays)
+//
+// Temporal edges without self-loops are sorted by (lo, hi, dir, t, input
+// position) where lo < hi are the endpoints and dir = 1 for hi -> lo.  Static
+// edge s owns the sorted range [soff[s], soff[s+1]); its lo -> hi list is
+// [soff[s], smid[s]) and its hi -> lo list [smid[s], soff[s+1]).
+//
+// Vertices are renumbered by the orientation order ("new ids").  The oriented
+// CSR holds, for each new id x, the heads y > x of its out-edges in ascending
+// order; oeid packs the static edge id with bit 31 set when the tail of the
+// oriented edge is the static edge's lo endpoint (so E_{tail,head} is the
+// [soff, smid) part).
+// ---------------------------------------------------------------------------
+struct Index {
+    int32_t n = 0;
+    int64_t m_input = 0;
+    int32_t m = 0;           // kept temporal edges
+    int64_t self_loops = 0;
+    int32_t S = 0;           // static edges
+    int64_t P = 0;           // non-empty directed lists
+    int64_t sigma_max = 0;
+    int64_t T = 0;           // static triangles
+    int64_t W = 0;           // oriented wedges
+    int32_t max_core = 0;
+    int32_t max_out = 0;
+    int64_t peel_rounds = 0;
+    int32_t rank_mode = 0;
+    bool built = false;
+    bool tri_cached = false;
+    double build_ms = 0;
+
+    DevBuf ts;      // int64[m]
+    DevBuf perm;    // int32[m]  input position of each sorted edge
+    DevBuf sid;     // int32[m]  static edge of each sorted edge
+    DevBuf soff;    // int32[S+1]
+    DevBuf smid;    // int32[S]
+    DevBuf slo;     // int32[S]
+    DevBuf shi;     // int32[S]
+    DevBuf deg;     // int32[n]  |N(x)|, original ids
+    DevBuf core;    // int32[n]  core number, original ids
+    DevBuf rank;    // int32[n]  original id -> new id
+    DevBuf outdeg;  // int32[n]  |N+(x)|, original ids
+    DevBuf ooff;    // int32[n+1] oriented CSR rows (new ids)
+    DevBuf oadj;    // int32[S]  heads (new ids)
+    DevBuf oeid;    // uint32[S] static edge id | direction bit
+    DevBuf osrc;    // int32[S]  tails (new ids)
+    DevBuf tri_off; // int64[S+1] triangles found from each oriented edge
+    DevBuf tcnt;    // int32[S]  triangles on each static edge = |N(lo) & N(hi)|
+    DevBuf tri;     // uint32[3T] cached triangle list (optional)
+
+    size_t device_bytes() const;
+};
+
+// per-query scratch; one per concurrent caller
+struct Workspace {
+    DevBuf count;   // uint32[m]
+    DevBuf tri;     // uint32[3T]
+    DevBuf work;    // int64[T+1] (work, then exclusive offsets)
+    DevBuf ncert;   // uint32[2S]
+    DevBuf pairs_k; // uint64[2S]
+    DevBuf pairs_v; // uint32[2S]
+    DevBuf pairs_k2;
+    DevBuf pairs_v2;
+    DevBuf scal;    // small device scalars
+    DevBuf cub;     // library scan/sort temporaries
+    DevBuf hist;    // uint32[levels * m] multi-window counts
+    DevBuf aux;     // misc
+    PinnedBuf host;
+    hipEvent_t ev[8] = {};
+    bool events = false;
+    ~Workspace();
+    void ensure_events();
+};
+
+struct Graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // inputs (device copies) until the index is built
+    DevBuf src, dst, t;
+    bool sorted_by_time = false;
+    int64_t tmax = 0;
+    Index ix;
+    Workspace ws; // default workspace for the synchronous API
+    ~Graph();
+};
+
+struct Result {
+    std::vector<int32_t> u, v;
+    std::vector<uint32_t> n_cert;
+    int64_t n_certificates = 0;
+    folty_stats stats{};
+    bool has_counts = false;
+    DevBuf counts_dev;                // uint32[m_input], input order
+    std::vector<uint32_t> counts_host;
+    bool counts_fetched = false;
+    int device = 0;
+};
+
+// ---------------------------------------------------------------------------
+// entry points used by the C ABI layer
+// ---------------------------------------------------------------------------
+void load_graph(Graph *g, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                const int64_t *t, int32_t mem_kind, void *stream);
+void build_index(Graph *g, const folty_build_opts *opts);
+void check_query(const Graph *g, const folty_query &q);
+Result *run_query(Graph *g, const folty_query &q, Workspace &ws);
+void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
+void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);
+void fill_stats_from_index(const Index &ix, folty_stats *s);
+
+// library-primitive wrappers (rocPRIM through hipCUB), all on `stream`
+size_t sort_pairs_u64_i32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,
+                          const int32_t *vin, int32_t *vout, int64_t n, int end_bit,
+                          hipStream_t stream);
+size_t sort_pairs_u64_u32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,
+                          const uint32_t *vin, uint32_t *vout, int64_t n, int end_bit,
+                          hipStream_t stream);
+size_t sort_pairs_u32_i32(void *tmp, size_t tmp_bytes, const uint32_t *kin, uint32_t *kout,
+                          const int32_t *vin, int32_t *vout, int64_t n, int end_bit,
+                          hipStream_t stream);
+size_t exclusive_scan_i64(void *tmp, size_t tmp_bytes, const int64_t *in, int64_t *out, int64_t n,
+                          hipStream_t stream);
+size_t exclusive_scan_i32_to_i64(void *tmp, size_t tmp_bytes, const int32_t *in, int64_t *out,
+                                 int64_t n, hipStream_t stream);
+size_t inclusive_scan_i32(void *tmp, size_t tmp_bytes, const int32_t *in, int32_t *out, int64_t n,
+                          hipStream_t stream);
+size_t exclusive_scan_i32(void *tmp, size_t tmp_bytes, const int32_t *in, int32_t *out, int64_t n,
+                          hipStream_t stream);
+
+inline int bit_length(uint64_t x) {
+    int b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+inline unsigned grid_for(int64_t items, int block, int64_t cap = 1 << 20) {
+    int64_t g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+} // namespace folty

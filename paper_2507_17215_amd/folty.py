@@ -1,0 +1,312 @@
+"""Python binding of ``libfolty.so`` (include/folty.h), argument marshalling only.
+
+Every step of the query runs in the library's HIP kernels.  If the library is
+missing this module raises instead of computing anything itself.  PyTorch is
+used only to hand over device memory and streams: inputs may be numpy arrays
+(host) or torch tensors (host or device).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfolty.so")
+
+OK, EINVAL, ENOTBUILT, ENOMEM, EDEVICE, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+DELTA_INF = (1 << 63) - 1
+UNIVERSE_DST, UNIVERSE_SRC, UNIVERSE_COMMON = 0, 1, 2
+RANK_DEGENERACY, RANK_DEGREE, RANK_RANDOM = 0, 1, 2
+QUERY_NO_COUNTS = 1
+U32_MAX = 0xFFFFFFFF
+
+EXPORTS = (
+    "folty_last_error", "folty_version", "folty_load_temporal_graph", "folty_build_index",
+    "folty_run_fol_query", "folty_workspace_create", "folty_workspace_free",
+    "folty_run_fol_query_ws", "folty_run_batch", "folty_run_multi", "folty_result_pairs",
+    "folty_result_counts", "folty_result_stats", "folty_result_free", "folty_graph_stats",
+    "folty_graph_vertex_array", "folty_graph_device_bytes", "folty_graph_free",
+)
+
+
+class FoltyError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"folty error {code}: {msg}")
+        self.code = code
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("rank_mode", ctypes.c_int32), ("cache_triangles", ctypes.c_int32),
+                ("rank_seed", ctypes.c_uint64)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_int64), ("theta_num", ctypes.c_uint32),
+                ("theta_den", ctypes.c_uint32), ("variant", ctypes.c_uint8),
+                ("universe", ctypes.c_uint8), ("exclude_other", ctypes.c_uint8),
+                ("flags", ctypes.c_uint8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "n", "m_input", "m", "self_loops", "static_edges", "directed_pairs", "max_core",
+        "max_out_degree", "wedges", "triangles", "max_multiplicity", "peel_rounds", "tests",
+        "n_pairs", "n_certificates")] + [(f, ctypes.c_double) for f in (
+            "build_ms", "wedge_ms", "temporal_ms", "threshold_ms", "query_ms")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FoltyError(EDEVICE, f"{path} is missing: build it with "
+                                  "`python -m paper_2507_17215_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, PP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)
+    lib.folty_last_error.restype = ctypes.c_char_p
+    lib.folty_version.restype = ctypes.c_char_p
+    lib.folty_load_temporal_graph.argtypes = [I32, I64, P, P, P, I32, P, PP]
+    lib.folty_build_index.argtypes = [P, ctypes.POINTER(BuildOpts)]
+    lib.folty_run_fol_query.argtypes = [P, ctypes.POINTER(Query), PP]
+    lib.folty_workspace_create.argtypes = [PP]
+    lib.folty_workspace_free.argtypes = [P]
+    lib.folty_workspace_free.restype = None
+    lib.folty_run_fol_query_ws.argtypes = [P, ctypes.POINTER(Query), P, PP]
+    lib.folty_run_batch.argtypes = [P, ctypes.POINTER(Query), I32, PP]
+    lib.folty_run_multi.argtypes = [PP, ctypes.POINTER(Query), I32, PP]
+    lib.folty_result_pairs.argtypes = [P, ctypes.POINTER(I64), PP, PP, PP]
+    lib.folty_result_counts.argtypes = [P, ctypes.POINTER(I64), PP]
+    lib.folty_result_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.folty_result_free.argtypes = [P]
+    lib.folty_result_free.restype = None
+    lib.folty_graph_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.folty_graph_vertex_array.argtypes = [P, I32, P]
+    lib.folty_graph_device_bytes.argtypes = [P, ctypes.POINTER(I64)]
+    lib.folty_graph_free.argtypes = [P]
+    lib.folty_graph_free.restype = None
+    for name in EXPORTS:
+        if name not in ("folty_workspace_free", "folty_result_free", "folty_graph_free",
+                        "folty_last_error", "folty_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FoltyError(rc, load_library().folty_last_error().decode(errors="replace"))
+
+
+def to_theta(theta) -> tuple:
+    """theta as an exact (num, den): a pair, a Fraction, or a float/str read as a
+    decimal and limited to denominators up to 10**6."""
+    if isinstance(theta, tuple):
+        num, den = theta
+    else:
+        f = theta if isinstance(theta, Fraction) else Fraction(str(theta)).limit_denominator(10**6)
+        num, den = f.numerator, f.denominator
+    return int(num), int(den)
+
+
+def make_query(delta, theta=(1, 2), variant=0, universe=UNIVERSE_DST, exclude_other=False,
+               counts=True) -> Query:
+    num, den = to_theta(theta)
+    if delta is None or delta == float("inf"):
+        delta = DELTA_INF
+    return Query(int(delta), num, den, int(variant), int(universe), 1 if exclude_other else 0,
+                 0 if counts else QUERY_NO_COUNTS)
+
+
+def _array_arg(x, dtype):
+    """(pointer, mem_kind, keepalive) for a numpy array or a torch tensor."""
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            want = {np.int32: torch.int32, np.int64: torch.int64}[dtype]
+            if x.dtype != want:
+                raise TypeError(f"expected {want}, got {x.dtype}")
+            x = x.contiguous()
+            if x.is_cuda:
+                torch.cuda.current_stream(x.device).synchronize()
+                return ctypes.c_void_p(x.data_ptr()), MEM_DEVICE, x
+            return ctypes.c_void_p(x.data_ptr()), MEM_HOST, x
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return ctypes.c_void_p(a.ctypes.data), MEM_HOST, a
+
+
+class Result:
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        lib = load_library()
+        n = ctypes.c_int64()
+        u, v, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib.folty_result_pairs(self._h, ctypes.byref(n), ctypes.byref(u), ctypes.byref(v),
+                                      ctypes.byref(c)))
+        k = n.value
+        self.pair_u = np.ctypeslib.as_array(ctypes.cast(u, ctypes.POINTER(ctypes.c_int32)), (k,)).copy() if k else np.zeros(0, np.int32)
+        self.pair_v = np.ctypeslib.as_array(ctypes.cast(v, ctypes.POINTER(ctypes.c_int32)), (k,)).copy() if k else np.zeros(0, np.int32)
+        self.n_cert = np.ctypeslib.as_array(ctypes.cast(c, ctypes.POINTER(ctypes.c_uint32)), (k,)).copy() if k else np.zeros(0, np.uint32)
+        nc = ctypes.c_int64()
+        _check(lib.folty_result_counts(self._h, ctypes.byref(nc), None))
+        self.n_certificates = nc.value
+        st = Stats()
+        _check(lib.folty_result_stats(self._h, ctypes.byref(st)))
+        self.stats = st.as_dict()
+
+    def counts(self) -> np.ndarray:
+        """Per temporal edge counts in input order (0xFFFFFFFF = self-loop)."""
+        lib = load_library()
+        p = ctypes.c_void_p()
+        _check(lib.folty_result_counts(self._h, None, ctypes.byref(p)))
+        m = int(self.stats["m_input"])
+        if m == 0:
+            return np.zeros(0, np.uint32)
+        return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)), (m,)).copy()
+
+    def pairs(self):
+        return list(zip(self.pair_u.tolist(), self.pair_v.tolist(), self.n_cert.tolist()))
+
+    def close(self):
+        if self._h:
+            load_library().folty_result_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Workspace:
+    """Scratch memory for one concurrent caller."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+        _check(load_library().folty_workspace_create(ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            load_library().folty_workspace_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A temporal multigraph resident on the GPU with its query index."""
+
+    def __init__(self, n: int, src, dst, t, stream=None):
+        lib = load_library()
+        ps, ks, a1 = _array_arg(src, np.int32)
+        pd, kd, a2 = _array_arg(dst, np.int32)
+        pt, kt, a3 = _array_arg(t, np.int64)
+        if not (ks == kd == kt):
+            raise ValueError("src, dst and t must all be host or all be device arrays")
+        m = int(a1.shape[0])
+        if int(a2.shape[0]) != m or int(a3.shape[0]) != m:
+            raise ValueError("src, dst and t must have the same length")
+        self._h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(lib.folty_load_temporal_graph(int(n), m, ps, pd, pt, ks, st, ctypes.byref(self._h)))
+        self.n, self.m = int(n), m
+
+    def build(self, rank_mode: int = RANK_DEGENERACY, cache_triangles: bool = False,
+              rank_seed: int = 0) -> "Graph":
+        o = BuildOpts(int(rank_mode), 1 if cache_triangles else 0, int(rank_seed))
+        _check(load_library().folty_build_index(self._h, ctypes.byref(o)))
+        return self
+
+    def query(self, delta, theta=(1, 2), variant=0, universe=UNIVERSE_DST,
+              exclude_other=False, counts=True, workspace: Workspace | None = None) -> Result:
+        q = make_query(delta, theta, variant, universe, exclude_other, counts)
+        out = ctypes.c_void_p()
+        lib = load_library()
+        if workspace is None:
+            _check(lib.folty_run_fol_query(self._h, ctypes.byref(q), ctypes.byref(out)))
+        else:
+            _check(lib.folty_run_fol_query_ws(self._h, ctypes.byref(q), workspace._h,
+                                              ctypes.byref(out)))
+        return Result(out)
+
+    def query_raw(self, q: Query) -> Result:
+        out = ctypes.c_void_p()
+        _check(load_library().folty_run_fol_query(self._h, ctypes.byref(q), ctypes.byref(out)))
+        return Result(out)
+
+    def batch(self, queries) -> list:
+        qs = (Query * len(queries))(*[q if isinstance(q, Query) else make_query(**q) for q in queries])
+        outs = (ctypes.c_void_p * len(queries))()
+        _check(load_library().folty_run_batch(self._h, qs, len(queries), outs))
+        return [Result(ctypes.c_void_p(o)) for o in outs]
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(load_library().folty_graph_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def vertex_array(self, what: int) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int32)
+        _check(load_library().folty_graph_vertex_array(self._h, int(what),
+                                                       ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def degrees(self):
+        return self.vertex_array(0)
+
+    def core_numbers(self):
+        return self.vertex_array(1)
+
+    def ranks(self):
+        return self.vertex_array(2)
+
+    def out_degrees(self):
+        return self.vertex_array(3)
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_int64()
+        _check(load_library().folty_graph_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().folty_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_multi(graphs, queries) -> list:
+    """One query per graph, all graphs in one call."""
+    n = len(graphs)
+    gs = (ctypes.c_void_p * n)(*[g._h.value for g in graphs])
+    qs = (Query * n)(*[q if isinstance(q, Query) else make_query(**q) for q in queries])
+    outs = (ctypes.c_void_p * n)()
+    _check(load_library().folty_run_multi(gs, qs, n, outs))
+    return [Result(ctypes.c_void_p(o)) for o in outs]
+
+
+def version() -> str:
+    return load_library().folty_version().decode()

@@ -1,0 +1,75 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls).
+
+* the shared library loads and exports every function include/folty.h declares;
+* the binding's argument conversion (exact theta, query struct layout);
+* without a GPU, loading a graph fails loudly with FOLTY_EDEVICE - there is no
+  CPU fallback.
+"""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2507_17215_amd import folty
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "folty.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(folty_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = folty.load_library()
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(folty.EXPORTS)
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(folty.Query) == 20 or ctypes.sizeof(folty.Query) == 24
+    assert folty.Query.delta.offset == 0
+    assert folty.Query.theta_num.offset == 8
+    assert folty.Query.variant.offset == 16
+    assert folty.Query.flags.offset == 19
+    assert ctypes.sizeof(folty.BuildOpts) == 16
+    assert ctypes.sizeof(folty.Stats) == 15 * 8 + 5 * 8
+
+
+def test_theta_is_exact():
+    assert folty.to_theta(0.5) == (1, 2)
+    assert folty.to_theta(0.25) == (1, 4)
+    assert folty.to_theta(0.1) == (1, 10)
+    assert folty.to_theta((3, 7)) == (3, 7)
+    assert folty.to_theta(Fraction(2, 3)) == (2, 3)
+    assert folty.to_theta(0) == (0, 1)
+    assert folty.to_theta(1.0) == (1, 1)
+    q = folty.make_query(None, 0.75, variant=3, universe=2, counts=False)
+    assert (q.delta, q.theta_num, q.theta_den, q.variant, q.universe, q.flags) == (
+        folty.DELTA_INF, 3, 4, 3, 2, folty.QUERY_NO_COUNTS)
+
+
+def test_no_gpu_means_loud_failure():
+    from tests.conftest import gpu_available
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(folty.FoltyError) as ei:
+        folty.Graph(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([0, 1]))
+    assert ei.value.code == folty.EDEVICE
+
+
+def test_missing_library_is_an_error(tmp_path):
+    old = folty._lib
+    try:
+        folty._lib = None
+        with pytest.raises(folty.FoltyError):
+            folty.load_library(str(tmp_path / "nope.so"))
+    finally:
+        folty._lib = old
