@@ -44,7 +44,23 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=300_000,
                    help="temporal edges in the oracle's timed sample")
     p.add_argument("--parity-sample", type=int, default=4000)
+    p.add_argument("--cache-dir", default=None,
+                   help="keep the generated graph here as .npy files and reuse it")
     return p.parse_args()
+
+
+def load_or_generate(synth, n, m, comm, cache_dir):
+    if cache_dir:
+        base = os.path.join(cache_dir, f"large_{n}_{m}_{comm}")
+        if os.path.exists(base + "_t.npy"):
+            return synth.TemporalGraph(n=n, src=np.load(base + "_src.npy"), dst=np.load(base + "_dst.npy"),
+                                       t=np.load(base + "_t.npy"))
+    g = synth.large(n=n, m=m, communities=comm)
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        for k in ("src", "dst", "t"):
+            np.save(f"{base}_{k}.npy", getattr(g, k))
+    return g
 
 
 def main():
@@ -61,7 +77,7 @@ def main():
     m = int(round(70_000_000 * a.scale))
     comm = max(1, int(round(200 * a.scale)))
     t0 = time.time()
-    g = synth.large(n=n, m=m, communities=comm)
+    g = load_or_generate(synth, n, m, comm, a.cache_dir)
     log(f"generated n={n} m={m} in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

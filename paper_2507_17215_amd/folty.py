@@ -73,6 +73,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise FoltyError(EDEVICE, f"{path} is missing: build it with "
                                   "`python -m paper_2507_17215_amd.build_lib`")
+    try:
+        # torch ships its own HIP runtime under the same soname; loading it first
+        # makes libfolty.so bind to that one copy, so torch and the library share
+        # one runtime (and one view of the device) in this process
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I32, I64, PP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)
     lib.folty_last_error.restype = ctypes.c_char_p
