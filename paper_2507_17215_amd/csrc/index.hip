@@ -157,96 +157,288 @@ __global__ void k_fix_smid_stats(const int32_t *__restrict__ soff, int32_t *__re
         pairs = (l0 > 0) + (l1 > 0);
         smax = l0 > l1 ? l0 : l1;
     }
-    // block reduction through one atomic per wave
+    // wave, then block reduction: one atomic per block
+    __shared__ unsigned long long s_p[BLK / 64], s_m[BLK / 64];
     for (int o = 32; o > 0; o >>= 1) {
         pairs += __shfl_xor(pairs, o);
         unsigned long long other = __shfl_xor(smax, o);
         smax = other > smax ? other : smax;
     }
     if (lane_id() == 0) {
+        s_p[threadIdx.x >> 6] = pairs;
+        s_m[threadIdx.x >> 6] = smax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLK / 64; w++) {
+            pairs += s_p[w];
+            smax = s_m[w] > smax ? s_m[w] : smax;
+        }
         if (pairs) atomicAdd(&ps->pairs, pairs);
         if (smax) atomicMax(&ps->sigma_max, smax);
     }
 }
 
-__global__ void k_degrees(const int32_t *__restrict__ slo, const int32_t *__restrict__ shi, int32_t S,
-                          int32_t *__restrict__ deg) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    atomicAdd(&deg[slo[s]], 1);
-    atomicAdd(&deg[shi[s]], 1);
-}
-
-__global__ void k_fill_uadj(const int32_t *__restrict__ slo, const int32_t *__restrict__ shi, int32_t S,
-                            unsigned long long *__restrict__ cursor, int32_t *__restrict__ uadj) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    int32_t a = slo[s], b = shi[s];
-    unsigned long long p = atomicAdd(&cursor[a], 1ull);
-    uadj[p] = b;
-    p = atomicAdd(&cursor[b], 1ull);
-    uadj[p] = a;
-}
-
 // ---- min-degree peeling -------------------------------------------------------
+// The peel runs as identical launches of one kernel over a fixed grid, one step
+// per launch: either a level's collect (live vertices of degree <= k, taken from
+// the compacted live list) or one peel round (remove the frontier, decrement its
+// neighbours; neighbours crossing k+1 -> k form the next frontier).  Step i reads
+// the state of step i-1 and the counters step i-1 produced, and every block
+// derives step i's state from them identically, so no block waits for another.
+// Block 0 publishes step i's state (double buffer by step parity) and clears
+// the counters of step i+1 (triple buffer by step % 3).
+constexpr int PEEL_BLOCKS = 512;
+constexpr int32_t BIG_DEG = 2048; // frontier vertices above this degree share the grid
+
+enum : int32_t { PEEL_BOOT = -1, PEEL_COLLECT = 0, PEEL_ROUND = 1, PEEL_DONE = 2 };
+
+struct PeelState {   // what step i does
+    int32_t mode;
+    int32_t k;
+    int32_t r;        // round number (the rank key) of the next round
+    int32_t lp;       // current live list
+    int32_t alive_n;  // entries in the current live list
+    int32_t n_in;     // frontier size a round step consumes
+    int32_t removed;  // vertices removed before this step
+    int32_t pad;
+};
+
+struct PeelCount {   // what step i produced
+    int32_t nS, nB;   // frontier written (degree <= BIG_DEG / above)
+    int32_t nA;       // live list written (collect)
+    int32_t min_above;
+};
+
+struct PeelBufs {
+    const int64_t *uoff;
+    const int32_t *uadj;
+    const int32_t *deg;
+    int32_t *dcur, *rnd, *core;
+    int32_t *FS[3], *FB[3];
+    int32_t *alive[2];
+    PeelState *state;  // [2]
+    PeelCount *count;  // [3]
+    int32_t n;
+};
+
 __global__ void k_peel_init(const int32_t *__restrict__ deg, int32_t *__restrict__ dcur,
-                            int32_t *__restrict__ rnd, int32_t n) {
+                            int32_t *__restrict__ rnd, int32_t *__restrict__ alive0, int32_t n) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     dcur[x] = deg[x];
     rnd[x] = -1;
+    alive0[x] = (int32_t)x;
 }
 
-// all live vertices with current degree <= k, plus the smallest live degree above k
-__global__ void k_collect(const int32_t *__restrict__ dcur, const int32_t *__restrict__ rnd, int32_t n,
-                          int32_t k, int32_t *__restrict__ F, int32_t *__restrict__ counters) {
-    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool live = x < n && rnd[x] < 0;
-    int32_t d = live ? dcur[x] : 0x7fffffff;
-    int32_t slot = wave_append(&counters[0], live && d <= k);
-    if (slot >= 0) F[slot] = (int32_t)x;
-    int32_t above = (live && d > k) ? d : 0x7fffffff;
-    for (int o = 32; o > 0; o >>= 1) {
-        int32_t other = __shfl_xor(above, o);
-        above = other < above ? other : above;
+__device__ inline PeelState peel_next(const PeelState &p, const PeelCount &c, int32_t n) {
+    PeelState s = p;
+    if (p.mode == PEEL_BOOT) {
+        s.mode = PEEL_COLLECT;
+        s.k = 0;
+        s.r = 0;
+        s.lp = 0;
+        s.alive_n = n;
+        s.n_in = 0;
+        s.removed = 0;
+    } else if (p.mode == PEEL_COLLECT) {
+        s.lp = p.lp ^ 1;
+        s.alive_n = c.nA;
+        if (c.nS + c.nB > 0) {
+            s.mode = PEEL_ROUND;
+            s.n_in = c.nS + c.nB;
+        } else if (c.nA == 0) {
+            s.mode = PEEL_DONE;
+        } else {
+            s.k = c.min_above; // nothing at degree <= k: jump to the smallest live degree
+        }
+    } else if (p.mode == PEEL_ROUND) {
+        s.removed = p.removed + p.n_in;
+        s.r = p.r + 1;
+        if (c.nS + c.nB > 0) {
+            s.n_in = c.nS + c.nB;
+        } else {
+            s.mode = PEEL_COLLECT;
+            s.k = p.k + 1;
+            s.n_in = 0;
+        }
     }
-    if (lane_id() == 0 && above != 0x7fffffff) atomicMin(&counters[1], above);
+    return s;
 }
 
-__global__ void k_mark(const int32_t *__restrict__ F, int32_t nF, int32_t r, int32_t k,
-                       int32_t *__restrict__ rnd, int32_t *__restrict__ core) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nF) return;
-    int32_t x = F[i];
-    rnd[x] = r;
-    core[x] = k;
+__device__ inline void peel_neighbour(int32_t y, bool valid, int32_t k, const PeelBufs &B, PeelCount *out,
+                                      int32_t *FS, int32_t *FB) {
+    bool push = false;
+    if (valid && B.rnd[y] < 0) {
+        int32_t old = atomicSub(&B.dcur[y], 1);
+        push = (old == k + 1);
+    }
+    bool big = push && B.deg[y] > BIG_DEG;
+    int32_t a = wave_append(&out->nS, push && !big);
+    if (a >= 0) FS[a] = y;
+    int32_t b = wave_append(&out->nB, big);
+    if (b >= 0) FB[b] = y;
 }
 
-// one wave per removed vertex; a neighbour whose degree crosses from k+1 to k
-// joins the next round
-__global__ void k_peel(const int32_t *__restrict__ F, int32_t nF, const int64_t *__restrict__ uoff,
-                       const int32_t *__restrict__ uadj, int32_t k, int32_t *__restrict__ dcur,
-                       const int32_t *__restrict__ rnd, int32_t *__restrict__ next,
-                       int32_t *__restrict__ counters) {
-    int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (wave >= nF) return;
-    int lane = lane_id();
-    int32_t x = F[wave];
-    int64_t b = uoff[x], e = uoff[x + 1];
-    for (int64_t base = b; base < e; base += 64) {
-        int64_t p = base + lane;
-        bool push = false;
-        int32_t y = -1;
-        if (p < e) {
-            y = uadj[p];
-            if (rnd[y] < 0) {
-                int32_t old = atomicSub(&dcur[y], 1);
-                push = (old == k + 1);
+// block-aggregated append of up to three predicates: one global atomic per block
+// and per predicate; slot[j] is this thread's index in list j or -1
+__device__ inline void block_append3(bool p0, bool p1, bool p2, int32_t *g0, int32_t *g1, int32_t *g2,
+                                     int32_t slot[3]) {
+    __shared__ int32_t s_cnt[3], s_base[3];
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    bool p[3] = {p0, p1, p2};
+    int32_t local[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        unsigned long long mask = __ballot(p[j]);
+        int32_t woff = 0;
+        int leader = mask ? __ffsll((long long)mask) - 1 : 0;
+        if (mask && lane == leader) woff = atomicAdd(&s_cnt[j], (int32_t)__popcll(mask));
+        woff = __shfl(woff, leader);
+        local[j] = p[j] ? woff + (int32_t)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int32_t *g = threadIdx.x == 0 ? g0 : (threadIdx.x == 1 ? g1 : g2);
+        s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(g, s_cnt[threadIdx.x]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; j++) slot[j] = local[j] >= 0 ? s_base[j] + local[j] : -1;
+}
+
+__global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
+    __shared__ PeelState s_st;
+    __shared__ PeelCount s_prev;
+    const int cur = (int)(step % 3), prv = (int)((step + 2) % 3), nxt = (int)((step + 1) % 3);
+    if (threadIdx.x == 0) {
+        PeelState p = B.state[(step + 1) & 1];
+        PeelCount c = B.count[prv];
+        s_prev = c;
+        s_st = peel_next(p, c, B.n);
+    }
+    __syncthreads();
+    const PeelState st = s_st;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        B.state[step & 1] = st;
+        PeelCount z = {0, 0, 0, 0x7fffffff};
+        B.count[nxt] = z;
+    }
+    if (st.mode == PEEL_DONE) return;
+    const int lane = lane_id();
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gwave = gtid >> 6, nwaves = stride >> 6;
+    const int32_t n = B.n, k = st.k;
+    PeelCount *out = &B.count[cur];
+
+    if (st.mode == PEEL_COLLECT) {
+        int32_t na = st.alive_n < n ? st.alive_n : n;
+        const int32_t *A = B.alive[st.lp];
+        int32_t *A2 = B.alive[st.lp ^ 1];
+        int32_t *FS = B.FS[cur], *FB = B.FB[cur];
+        int32_t local_min = 0x7fffffff;
+        for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += stride) {
+            int64_t i = base + threadIdx.x;
+            bool valid = i < na;
+            int32_t x = valid ? A[i] : 0;
+            bool live = valid && B.rnd[x] < 0;
+            int32_t d = live ? B.dcur[x] : 0;
+            bool take = live && d <= k;
+            bool big = take && B.deg[x] > BIG_DEG;
+            bool keep = live && d > k;
+            if (keep && d < local_min) local_min = d;
+            int32_t slot[3];
+            block_append3(take && !big, big, keep, &out->nS, &out->nB, &out->nA, slot);
+            if (slot[0] >= 0) FS[slot[0]] = x;
+            if (slot[1] >= 0) FB[slot[1]] = x;
+            if (slot[2] >= 0) A2[slot[2]] = x;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            int32_t other = __shfl_xor(local_min, o);
+            local_min = other < local_min ? other : local_min;
+        }
+        __shared__ int32_t s_min[BLK / 64];
+        if (lane == 0) s_min[threadIdx.x >> 6] = local_min;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t mm = s_min[0];
+            for (int w = 1; w < BLK / 64; w++) mm = s_min[w] < mm ? s_min[w] : mm;
+            if (mm != 0x7fffffff) atomicMin(&out->min_above, mm);
+        }
+    } else {
+        // the frontier is what the previous step wrote
+        int32_t nS = s_prev.nS < n ? s_prev.nS : n, nB = s_prev.nB < n ? s_prev.nB : n;
+        const int32_t *FS = B.FS[prv], *FB = B.FB[prv];
+        int32_t *NS = B.FS[cur], *NB = B.FB[cur];
+        const int32_t r = st.r;
+        for (int64_t i = gtid; i < nS; i += stride) {
+            int32_t x = FS[i];
+            B.rnd[x] = r;
+            B.core[x] = k;
+        }
+        for (int64_t i = gtid; i < nB; i += stride) {
+            int32_t x = FB[i];
+            B.rnd[x] = r;
+            B.core[x] = k;
+        }
+        // a frontier vertex seen as live here is only decremented, never pushed:
+        // its degree is already <= k
+        for (int64_t w = gwave; w < nS; w += nwaves) {
+            int32_t x = FS[w];
+            int64_t b = B.uoff[x], e = B.uoff[x + 1];
+            for (int64_t p0 = b; p0 < e; p0 += 64) {
+                int64_t p = p0 + lane;
+                bool valid = p < e;
+                peel_neighbour(valid ? B.uadj[p] : 0, valid, k, B, out, NS, NB);
             }
         }
-        int32_t slot = wave_append(&counters[2], push);
-        if (slot >= 0) next[slot] = y;
+        for (int32_t j = 0; j < nB; j++) {
+            int32_t x = FB[j];
+            int64_t b = B.uoff[x], e = B.uoff[x + 1];
+            for (int64_t p0 = b + gwave * 64; p0 < e; p0 += nwaves * 64) {
+                int64_t p = p0 + lane;
+                bool valid = p < e;
+                peel_neighbour(valid ? B.uadj[p] : 0, valid, k, B, out, NS, NB);
+            }
+        }
     }
+}
+
+// undirected adjacency from the static edge table: both (x, y) keys per edge
+__global__ void k_adj_keys(const int32_t *__restrict__ slo, const int32_t *__restrict__ shi, int32_t S,
+                           uint64_t *__restrict__ key) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    uint64_t a = (uint32_t)slo[s], b = (uint32_t)shi[s];
+    key[2 * s] = (a << 32) | b;
+    key[2 * s + 1] = (b << 32) | a;
+}
+
+__global__ void k_adj_unpack(const uint64_t *__restrict__ key, int64_t E, int32_t *__restrict__ uadj) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < E) uadj[i] = (int32_t)(key[i] & 0xffffffffu);
+}
+
+// row starts by binary search over the sorted keys; degrees from consecutive starts
+__global__ void k_adj_rows(const uint64_t *__restrict__ key, int64_t E, int32_t n, int64_t *__restrict__ uoff) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > n) return;
+    uint64_t want = (uint64_t)x << 32;
+    int64_t a = 0, b = E;
+    while (a < b) {
+        int64_t mid = (a + b) >> 1;
+        if (key[mid] < want) a = mid + 1;
+        else b = mid;
+    }
+    uoff[x] = a;
+}
+
+__global__ void k_adj_deg(const int64_t *__restrict__ uoff, int32_t n, int32_t *__restrict__ deg) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) deg[x] = (int32_t)(uoff[x + 1] - uoff[x]);
 }
 
 __device__ inline uint32_t mix32(uint32_t x) {
@@ -318,6 +510,8 @@ __global__ void k_orient_stats(const int32_t *__restrict__ outdeg_new, const int
         mo = d;
         mc = core[x];
     }
+    __shared__ unsigned long long s_w[BLK / 64];
+    __shared__ int32_t s_o[BLK / 64], s_c[BLK / 64];
     for (int o = 32; o > 0; o >>= 1) {
         w += __shfl_xor(w, o);
         int32_t a = __shfl_xor(mo, o), c = __shfl_xor(mc, o);
@@ -325,6 +519,17 @@ __global__ void k_orient_stats(const int32_t *__restrict__ outdeg_new, const int
         mc = c > mc ? c : mc;
     }
     if (lane_id() == 0) {
+        s_w[threadIdx.x >> 6] = w;
+        s_o[threadIdx.x >> 6] = mo;
+        s_c[threadIdx.x >> 6] = mc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < BLK / 64; i++) {
+            w += s_w[i];
+            mo = s_o[i] > mo ? s_o[i] : mo;
+            mc = s_c[i] > mc ? s_c[i] : mc;
+        }
         if (w) atomicAdd(&os->wedges, w);
         if (mo) atomicMax(&os->max_out, mo);
         if (mc) atomicMax(&os->max_core, mc);
@@ -533,81 +738,90 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     }
     pkey2.release();
 
-    // ---- degrees and undirected adjacency ----------------------------------------
+    // ---- degrees and undirected adjacency (sorted (x, y) keys) -----------------------
     ix.deg.ensure(4 * ((size_t)n + 1));
-    FOLTY_HIP(hipMemsetAsync(ix.deg.p, 0, 4 * ((size_t)n + 1), s));
-    DevBuf uoff, uadj, cursor;
+    DevBuf uoff, uadj;
     uoff.ensure(8 * ((size_t)n + 1));
     uadj.ensure(8 * (size_t)S + 8);
-    if (S > 0) {
-        k_degrees<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
-                                                   ix.deg.as<int32_t>());
-        FOLTY_LAUNCHED();
-    }
     {
-        size_t need = exclusive_scan_i32_to_i64(nullptr, 0, ix.deg.as<int32_t>(), uoff.as<int64_t>(), n + 1, s);
-        exclusive_scan_i32_to_i64(cub_ensure(need), need, ix.deg.as<int32_t>(), uoff.as<int64_t>(), n + 1, s);
-    }
-    if (S > 0) {
-        cursor.ensure(8 * ((size_t)n + 1));
-        FOLTY_HIP(hipMemcpyAsync(cursor.p, uoff.p, 8 * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
-        k_fill_uadj<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
-                                                     cursor.as<unsigned long long>(), uadj.as<int32_t>());
+        const int64_t E = 2 * (int64_t)S;
+        DevBuf k1, k2;
+        k1.ensure(8 * (size_t)E + 8);
+        k2.ensure(8 * (size_t)E + 8);
+        if (S > 0) {
+            k_adj_keys<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
+                                                        k1.as<uint64_t>());
+            FOLTY_LAUNCHED();
+            int kb = 32 + bit_length((uint64_t)n);
+            size_t need = sort_keys_u64(nullptr, 0, k1.as<uint64_t>(), k2.as<uint64_t>(), E, kb, s);
+            sort_keys_u64(cub_ensure(need), need, k1.as<uint64_t>(), k2.as<uint64_t>(), E, kb, s);
+            k_adj_unpack<<<grid_for(E, BLK), BLK, 0, s>>>(k2.as<uint64_t>(), E, uadj.as<int32_t>());
+            FOLTY_LAUNCHED();
+        }
+        k_adj_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(k2.as<uint64_t>(), E, n, uoff.as<int64_t>());
+        k_adj_deg<<<grid_for(n, BLK), BLK, 0, s>>>(uoff.as<int64_t>(), n, ix.deg.as<int32_t>());
         FOLTY_LAUNCHED();
-        cursor.release();
     }
 
     // ---- a.3: core numbers by min-degree peeling ------------------------------------
     ix.core.ensure(4 * (size_t)n);
-    DevBuf dcur, rnd, F0, F1, ctr;
+    DevBuf dcur, rnd, fr, alive, pst;
     dcur.ensure(4 * (size_t)n);
     rnd.ensure(4 * (size_t)n);
-    F0.ensure(4 * (size_t)n);
-    F1.ensure(4 * (size_t)n);
-    ctr.ensure(16);
-    k_peel_init<<<grid_for(n, BLK), BLK, 0, s>>>(ix.deg.as<int32_t>(), dcur.as<int32_t>(), rnd.as<int32_t>(), n);
+    fr.ensure(4 * 6 * (size_t)n);
+    alive.ensure(4 * 2 * (size_t)n);
+    pst.ensure(2 * sizeof(PeelState) + 3 * sizeof(PeelCount));
+    k_peel_init<<<grid_for(n, BLK), BLK, 0, s>>>(ix.deg.as<int32_t>(), dcur.as<int32_t>(), rnd.as<int32_t>(),
+                                                 alive.as<int32_t>(), n);
     FOLTY_LAUNCHED();
     {
-        int64_t remaining = n;
-        int32_t k = 0, r = 0;
-        int32_t *hc = hb.as<int32_t>();
-        int32_t *F = F0.as<int32_t>(), *Nx = F1.as<int32_t>();
-        while (remaining > 0) {
-            int32_t init[4] = {0, 0x7fffffff, 0, 0};
-            FOLTY_HIP(hipMemcpyAsync(ctr.p, init, 16, hipMemcpyHostToDevice, s));
-            k_collect<<<grid_for(n, BLK), BLK, 0, s>>>(dcur.as<int32_t>(), rnd.as<int32_t>(), n, k, F,
-                                                      ctr.as<int32_t>());
-            FOLTY_LAUNCHED();
-            FOLTY_HIP(hipMemcpyAsync(hc, ctr.p, 16, hipMemcpyDeviceToHost, s));
-            FOLTY_HIP(hipStreamSynchronize(s));
-            int32_t nF = hc[0];
-            if (nF == 0) {
-                // every live vertex has degree > k: the next level is the smallest live degree
-                if (hc[1] == 0x7fffffff || hc[1] <= k)
-                    fail(FOLTY_EDEVICE, "peeling lost track of %lld vertices", (long long)remaining);
-                k = hc[1];
-                continue;
-            }
-            while (nF > 0) {
-                k_mark<<<grid_for(nF, BLK), BLK, 0, s>>>(F, nF, r, k, rnd.as<int32_t>(), ix.core.as<int32_t>());
-                FOLTY_HIP(hipMemsetAsync(ctr.as<int32_t>() + 2, 0, 4, s));
-                k_peel<<<grid_for((int64_t)nF * 64, BLK), BLK, 0, s>>>(F, nF, uoff.as<int64_t>(), uadj.as<int32_t>(),
-                                                                       k, dcur.as<int32_t>(), rnd.as<int32_t>(),
-                                                                       Nx, ctr.as<int32_t>());
-                FOLTY_LAUNCHED();
-                remaining -= nF;
-                r++;
-                std::swap(F, Nx);
-                FOLTY_HIP(hipMemcpyAsync(hc + 2, ctr.as<int32_t>() + 2, 4, hipMemcpyDeviceToHost, s));
-                FOLTY_HIP(hipStreamSynchronize(s));
-                nF = hc[2];
-            }
+        // step 0 reads state[1] (boot) and count[2] (empty)
+        char init[2 * sizeof(PeelState) + 3 * sizeof(PeelCount)];
+        PeelState boot{};
+        boot.mode = PEEL_BOOT;
+        PeelCount zero = {0, 0, 0, 0x7fffffff};
+        memcpy(init, &boot, sizeof boot);
+        memcpy(init + sizeof(PeelState), &boot, sizeof boot);
+        for (int i = 0; i < 3; i++) memcpy(init + 2 * sizeof(PeelState) + i * sizeof(PeelCount), &zero, sizeof zero);
+        FOLTY_HIP(hipMemcpyAsync(pst.p, init, sizeof init, hipMemcpyHostToDevice, s));
+        PeelBufs B;
+        B.uoff = uoff.as<int64_t>();
+        B.uadj = uadj.as<int32_t>();
+        B.deg = ix.deg.as<int32_t>();
+        B.dcur = dcur.as<int32_t>();
+        B.rnd = rnd.as<int32_t>();
+        B.core = ix.core.as<int32_t>();
+        for (int i = 0; i < 3; i++) {
+            B.FS[i] = fr.as<int32_t>() + (size_t)i * n;
+            B.FB[i] = fr.as<int32_t>() + (size_t)(3 + i) * n;
         }
-        ix.peel_rounds = r;
+        B.alive[0] = alive.as<int32_t>();
+        B.alive[1] = alive.as<int32_t>() + (size_t)n;
+        B.state = pst.as<PeelState>();
+        B.count = reinterpret_cast<PeelCount *>(pst.as<char>() + 2 * sizeof(PeelState));
+        B.n = n;
+        // every step removes a vertex or raises k past a live degree, so the peel
+        // ends within about 3n steps; the cap turns a logic error into an error code
+        const int64_t cap = 3 * (int64_t)n + 4096;
+        int64_t step = 0;
+        int batch = 64;
+        PeelState h{};
+        for (;;) {
+            for (int i = 0; i < batch; i++, step++) k_peel_step<<<PEEL_BLOCKS, BLK, 0, s>>>(B, step);
+            FOLTY_LAUNCHED();
+            FOLTY_HIP(hipMemcpyAsync(hb.p, B.state + ((step - 1) & 1), sizeof(PeelState), hipMemcpyDeviceToHost, s));
+            FOLTY_HIP(hipStreamSynchronize(s));
+            memcpy(&h, hb.p, sizeof h);
+            if (h.mode == PEEL_DONE) break;
+            if (step > cap) fail(FOLTY_EDEVICE, "core peeling did not finish in %lld steps", (long long)step);
+            batch = batch < 512 ? 2 * batch : 512;
+        }
+        if (h.removed != n) fail(FOLTY_EDEVICE, "core peeling removed %d of %d vertices", h.removed, n);
+        ix.peel_rounds = h.r;
     }
     dcur.release();
-    F0.release();
-    F1.release();
+    fr.release();
+    alive.release();
 
     // ---- orientation order and oriented CSR ---------------------------------------------
     ix.rank.ensure(4 * (size_t)n);
