@@ -152,6 +152,7 @@ def main():
         "n_certificates": qs["n_certificates"], "max_core": qs["max_core"],
         "max_out_degree": qs["max_out_degree"], "peel_rounds": qs["peel_rounds"],
         "static_edges": qs["static_edges"], "directed_pairs": qs["directed_pairs"],
+        "closing_probes": qs["closing_probes"], "enum_items": qs["enum_items"],
         "query_only_wedge_checks_per_s": W / (query_ms * 1e-3) if query_ms > 0 else None,
         "temporal_tests_per_s": S / (temporal_ms * 1e-3) if temporal_ms > 0 else None,
         "roofline": roofline,

@@ -119,6 +119,8 @@ typedef struct {
     int64_t triangles;        /* static triangles */
     int64_t max_multiplicity; /* sigma_max: longest list E_{x,y} */
     int64_t peel_rounds;      /* rounds of the min-degree peeling */
+    int64_t closing_probes;   /* membership probes of the enumeration: sum over (u,v) of |N+(v)| */
+    int64_t enum_items;       /* work items the enumeration is split into */
     /* query only */
     int64_t tests;            /* temporal tests: sum over (triangle, list E_{a,b} with both
                                  closing lists non-empty) of |E_{a,b}| */
@@ -224,6 +226,12 @@ int folty_graph_vertex_array(const folty_graph *g, int32_t what, int32_t *out);
 int folty_graph_device_bytes(const folty_graph *g, int64_t *bytes);
 
 void folty_graph_free(folty_graph *g);
+
+/* The library keeps freed device blocks for reuse (allocation and release are
+ * slow and a release waits for the whole device).  This hands every cached block
+ * of the current device back to the driver; *bytes (if not NULL) receives the
+ * amount.  Call it when other code needs the memory. */
+int folty_release_cached_memory(int64_t *bytes);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,7 @@ int folty_build_index(folty_graph *g, const folty_build_opts *opts) {
     return guarded([&] {
         if (!g) fail(FOLTY_EINVAL, "graph is null");
         FOLTY_HIP(hipSetDevice(g->g.device));
+        StreamScope sc(g->g.stream);
         build_index(&g->g, opts);
     });
 }
@@ -85,6 +86,7 @@ int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out
     return guarded([&] {
         if (!g || !q || !out) fail(FOLTY_EINVAL, "null argument");
         *out = nullptr;
+        StreamScope sc(g->g.stream);
         Result *r = run_query(&g->g, *q, g->g.ws);
         folty_result *h = new folty_result();
         h->r = std::move(*r);
@@ -106,6 +108,7 @@ int folty_run_fol_query_ws(folty_graph *g, const folty_query *q, folty_workspace
     return guarded([&] {
         if (!g || !q || !ws || !out) fail(FOLTY_EINVAL, "null argument");
         *out = nullptr;
+        StreamScope sc(g->g.stream);
         Result *r = run_query(&g->g, *q, ws->ws);
         folty_result *h = new folty_result();
         h->r = std::move(*r);
@@ -118,6 +121,7 @@ int folty_run_batch(folty_graph *g, const folty_query *qs, int32_t nq, folty_res
     return guarded([&] {
         if (!g || (nq > 0 && (!qs || !outs))) fail(FOLTY_EINVAL, "null argument");
         std::vector<Result *> rs(nq > 0 ? nq : 0, nullptr);
+        StreamScope sc(g->g.stream);
         run_batch(&g->g, qs, nq, g->g.ws, rs.data());
         for (int i = 0; i < nq; i++) {
             folty_result *h = new folty_result();
@@ -212,6 +216,13 @@ int folty_graph_device_bytes(const folty_graph *g, int64_t *bytes) {
     return guarded([&] {
         if (!g || !bytes) fail(FOLTY_EINVAL, "null argument");
         *bytes = (int64_t)g->g.ix.device_bytes();
+    });
+}
+
+int folty_release_cached_memory(int64_t *bytes) {
+    return guarded([&] {
+        size_t b = dev_trim();
+        if (bytes) *bytes = (int64_t)b;
     });
 }
 

@@ -1,0 +1,146 @@
+// Caching device allocator for the library's own buffers.
+//
+// hipMalloc and hipFree are slow and hipFree waits for the whole device, which
+// leaves the GPU idle between the many buffers of an index build.  Freed blocks
+// are kept per device and handed out again.  A block freed while a stream may
+// still use it carries an event recorded on that stream; a reuse on another
+// stream waits for that event first, a reuse on the same stream is ordered by
+// the stream itself.  Every public call synchronises its stream before it
+// returns, so blocks freed outside any call are idle.
+#include <map>
+#include <mutex>
+
+#include "folty_internal.h"
+
+namespace folty {
+
+namespace {
+
+struct Block {
+    void *p;
+    size_t bytes;
+    hipStream_t stream; // stream that last used it (nullptr: idle)
+    hipEvent_t ev;      // recorded on `stream` when freed (nullptr: idle)
+};
+
+struct Pool {
+    std::mutex mu;
+    std::multimap<size_t, Block> free_blocks;
+    size_t cached = 0;
+};
+
+std::mutex g_pools_mu;
+std::map<int, Pool *> g_pools;
+
+thread_local hipStream_t t_stream = nullptr;
+
+Pool &pool_for(int dev) {
+    std::lock_guard<std::mutex> lk(g_pools_mu);
+    Pool *&p = g_pools[dev];
+    if (!p) p = new Pool(); // kept until the process ends
+    return *p;
+}
+
+size_t round_size(size_t b) {
+    if (b < 256) return 256;
+    if (b < (1u << 20)) return (b + 255) & ~size_t(255);
+    const size_t g = size_t(2) << 20;
+    return (b + g - 1) / g * g;
+}
+
+void drop_block(Block &b) {
+    if (b.ev) (void)hipEventDestroy(b.ev);
+    (void)hipFree(b.p);
+}
+
+} // namespace
+
+StreamScope::StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
+StreamScope::~StreamScope() { t_stream = prev; }
+
+void *dev_alloc(size_t bytes, size_t *got) {
+    int dev = 0;
+    FOLTY_HIP(hipGetDevice(&dev));
+    Pool &P = pool_for(dev);
+    const size_t want = round_size(bytes);
+    {
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.free_blocks.lower_bound(want);
+        if (it != P.free_blocks.end() && it->first <= 2 * want) {
+            Block b = it->second;
+            P.free_blocks.erase(it);
+            P.cached -= b.bytes;
+            if (b.ev) {
+                if (!t_stream) (void)hipEventSynchronize(b.ev);
+                else if (b.stream != t_stream) (void)hipStreamWaitEvent(t_stream, b.ev, 0);
+                (void)hipEventDestroy(b.ev);
+            }
+            *got = b.bytes;
+            return b.p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        // give the cached blocks back and try once more
+        (void)hipDeviceSynchronize();
+        std::lock_guard<std::mutex> lk(P.mu);
+        for (auto &kv : P.free_blocks) drop_block(kv.second);
+        P.free_blocks.clear();
+        P.cached = 0;
+        e = hipMalloc(&p, want);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(FOLTY_ENOMEM, "hipMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
+    }
+    *got = want;
+    return p;
+}
+
+void dev_free(void *p, size_t bytes) {
+    if (!p) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipFree(p);
+        return;
+    }
+    Block b{p, bytes, t_stream, nullptr};
+    if (t_stream) {
+        if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(b.ev, t_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(t_stream);
+            if (b.ev) (void)hipEventDestroy(b.ev);
+            b.ev = nullptr;
+        }
+    }
+    Pool &P = pool_for(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.free_blocks.emplace(bytes, b);
+    P.cached += bytes;
+}
+
+size_t dev_trim() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    Pool &P = pool_for(dev);
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(P.mu);
+    size_t n = P.cached;
+    for (auto &kv : P.free_blocks) drop_block(kv.second);
+    P.free_blocks.clear();
+    P.cached = 0;
+    return n;
+}
+
+size_t dev_cached() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    Pool &P = pool_for(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    return P.cached;
+}
+
+} // namespace folty

@@ -42,8 +42,19 @@ void set_last_error(const char *msg);
     } while (0)
 
 // ---------------------------------------------------------------------------
-// device memory: a growable buffer owned by one object
+// device memory: a caching allocator (alloc.hip) and a growable buffer on it
 // ---------------------------------------------------------------------------
+// The stream that buffers allocated or freed on this thread are used with.
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s);
+    ~StreamScope();
+};
+void *dev_alloc(size_t bytes, size_t *got);
+void dev_free(void *p, size_t bytes);
+size_t dev_trim();   // give every cached block back to the driver; returns bytes
+size_t dev_cached(); // bytes held in the cache
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -57,7 +68,7 @@ struct DevBuf {
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p, bytes);
         p = nullptr;
         bytes = 0;
     }
@@ -65,14 +76,7 @@ struct DevBuf {
     void ensure(size_t b) {
         if (b <= bytes && p) return;
         release();
-        size_t want = b ? b : 256;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            fail(FOLTY_ENOMEM, "hipMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
-        }
-        bytes = want;
+        p = dev_alloc(b ? b : 256, &bytes);
     }
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
@@ -106,9 +110,23 @@ struct PinnedBuf {
 // Vertices are renumbered by the orientation order ("new ids").  The oriented
 // CSR holds, for each new id x, the heads y > x of its out-edges in ascending
 // order; oeid packs the static edge id with bit 31 set when the tail of the
-// oriented edge is the static edge's lo endpoint (so E_{tail,head} is the
-// [soff, smid) part).
+// oriented edge is the static edge's lo endpoint.  rec[p] describes oriented
+// edge p: both of its directed lists with their first and last timestamps.
+// The wedges u -> v -> x of each vertex u are cut into chunks ("items") of at
+// most a fixed number of closing probes; item it belongs to vertex item_u[it],
+// vertex u owns items [item_off[u], item_off[u+1]), and the triangles found by
+// item it occupy slots [tri_base[it], tri_base[it+1]).
 // ---------------------------------------------------------------------------
+struct alignas(64) EdgeRec {
+    int32_t fs, fn;       // E_{tail,head}: start in ts, length
+    int32_t bs, bn;       // E_{head,tail}
+    int64_t ftmin, ftmax; // first and last timestamp of E_{tail,head} (0 if empty)
+    int64_t btmin, btmax;
+    int32_t sid;          // static edge
+    int32_t pad[3];
+};
+static_assert(sizeof(EdgeRec) == 64, "one cache line per oriented edge");
+
 struct Index {
     int32_t n = 0;
     int64_t m_input = 0;
@@ -118,33 +136,38 @@ struct Index {
     int64_t P = 0;           // non-empty directed lists
     int64_t sigma_max = 0;
     int64_t T = 0;           // static triangles
-    int64_t W = 0;           // oriented wedges
+    int64_t W = 0;           // oriented wedges: sum of C(|N+(x)|, 2)
+    int64_t probes = 0;      // closing probes the enumeration makes: sum over (u,v) of |N+(v)|
+    int32_t NI = 0;          // enumeration items
     int32_t max_core = 0;
     int32_t max_out = 0;
     int64_t peel_rounds = 0;
     int32_t rank_mode = 0;
     bool built = false;
     bool tri_cached = false;
+    bool tcnt_ready = false;
     double build_ms = 0;
 
-    DevBuf ts;      // int64[m]
-    DevBuf perm;    // int32[m]  input position of each sorted edge
-    DevBuf sid;     // int32[m]  static edge of each sorted edge
-    DevBuf soff;    // int32[S+1]
-    DevBuf smid;    // int32[S]
-    DevBuf slo;     // int32[S]
-    DevBuf shi;     // int32[S]
-    DevBuf deg;     // int32[n]  |N(x)|, original ids
-    DevBuf core;    // int32[n]  core number, original ids
-    DevBuf rank;    // int32[n]  original id -> new id
-    DevBuf outdeg;  // int32[n]  |N+(x)|, original ids
-    DevBuf ooff;    // int32[n+1] oriented CSR rows (new ids)
-    DevBuf oadj;    // int32[S]  heads (new ids)
-    DevBuf oeid;    // uint32[S] static edge id | direction bit
-    DevBuf osrc;    // int32[S]  tails (new ids)
-    DevBuf tri_off; // int64[S+1] triangles found from each oriented edge
-    DevBuf tcnt;    // int32[S]  triangles on each static edge = |N(lo) & N(hi)|
-    DevBuf tri;     // uint32[3T] cached triangle list (optional)
+    DevBuf ts;       // int64[m]
+    DevBuf perm;     // int32[m]  input position of each sorted edge
+    DevBuf sid;      // int32[m]  static edge of each sorted edge
+    DevBuf soff;     // int32[S+1]
+    DevBuf smid;     // int32[S]
+    DevBuf slo;      // int32[S]
+    DevBuf shi;      // int32[S]
+    DevBuf deg;      // int32[n]  |N(x)|, original ids
+    DevBuf core;     // int32[n]  core number, original ids
+    DevBuf rank;     // int32[n]  original id -> new id
+    DevBuf outdeg;   // int32[n]  |N+(x)|, original ids
+    DevBuf ooff;     // int32[n+1] oriented CSR rows (new ids)
+    DevBuf oadj;     // int32[S]  heads (new ids)
+    DevBuf oeid;     // uint32[S] static edge id | direction bit
+    DevBuf rec;      // EdgeRec[S]
+    DevBuf item_u;   // int32[NI]
+    DevBuf item_off; // int32[n+1]
+    DevBuf tri_base; // int64[NI+1]
+    DevBuf tcnt;     // int32[S]  triangles on each static edge = |N(lo) & N(hi)| (computed on first use)
+    DevBuf tri;      // int32[3T] cached triangle list (optional): oriented edges (u,v), (u,w), (v,w)
 
     size_t device_bytes() const;
 };
@@ -152,8 +175,11 @@ struct Index {
 // per-query scratch; one per concurrent caller
 struct Workspace {
     DevBuf count;   // uint32[m]
-    DevBuf tri;     // uint32[3T]
-    DevBuf work;    // int64[T+1] (work, then exclusive offsets)
+    DevBuf sv;      // int32[3T]   surviving triangles (oriented edges), in their item's slots
+    DevBuf sw;      // int64[T]    test offset of each survivor inside its item
+    DevBuf su;      // int32[NI]   survivors per item
+    DevBuf wu;      // int64[NI+1] tests per item
+    DevBuf wbase;   // int64[NI+1] exclusive offsets of wu
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
     DevBuf pairs_v; // uint32[2S]
@@ -162,7 +188,6 @@ struct Workspace {
     DevBuf scal;    // small device scalars
     DevBuf cub;     // library scan/sort temporaries
     DevBuf hist;    // uint32[levels * m] multi-window counts
-    DevBuf aux;     // misc
     PinnedBuf host;
     hipEvent_t ev[8] = {};
     bool events = false;
@@ -206,6 +231,8 @@ Result *run_query(Graph *g, const folty_query &q, Workspace &ws);
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
 void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);
 void fill_stats_from_index(const Index &ix, folty_stats *s);
+// oriented-edge records, triangle counts per lowest vertex, optional triangle cache
+void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s);
 
 // library-primitive wrappers (rocPRIM through hipCUB), all on `stream`
 size_t sort_pairs_u64_i32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,

@@ -22,6 +22,13 @@ constexpr int BLK = 256;
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// make this wavefront's LDS writes visible to all of its lanes
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // wave-aggregated append: one atomic per wave, slots in lane order
 __device__ inline int32_t wave_append(int32_t *counter, bool pred) {
     unsigned long long mask = __ballot(pred);
@@ -144,9 +151,8 @@ struct PairStats {
 
 __global__ void k_fix_smid_stats(const int32_t *__restrict__ soff, int32_t *__restrict__ smid, int32_t S,
                                  PairStats *ps) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long pairs = 0, smax = 0;
-    if (s < S) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
         int32_t a = soff[s], b = soff[s + 1];
         int32_t mid = smid[s];
         if (mid < 0) {
@@ -154,8 +160,9 @@ __global__ void k_fix_smid_stats(const int32_t *__restrict__ soff, int32_t *__re
             smid[s] = b;
         }
         unsigned long long l0 = (unsigned long long)(mid - a), l1 = (unsigned long long)(b - mid);
-        pairs = (l0 > 0) + (l1 > 0);
-        smax = l0 > l1 ? l0 : l1;
+        pairs += (l0 > 0) + (l1 > 0);
+        unsigned long long mx = l0 > l1 ? l0 : l1;
+        smax = mx > smax ? mx : smax;
     }
     // wave, then block reduction: one atomic per block
     __shared__ unsigned long long s_p[BLK / 64], s_m[BLK / 64];
@@ -188,8 +195,21 @@ __global__ void k_fix_smid_stats(const int32_t *__restrict__ soff, int32_t *__re
 // derives step i's state from them identically, so no block waits for another.
 // Block 0 publishes step i's state (double buffer by step parity) and clears
 // the counters of step i+1 (triple buffer by step % 3).
-constexpr int PEEL_BLOCKS = 512;
+constexpr int PEEL_BLOCKS_WIDE = 2048;  // while many vertices are live
+constexpr int PEEL_BLOCKS_NARROW = 256; // late levels: small frontiers, launch cost dominates
+constexpr int32_t PEEL_NARROW_BELOW = 1 << 20; // live vertices below which the narrow grid is used
+constexpr int32_t TINY_DEG = 32;  // frontier vertices up to this degree get one lane each
 constexpr int32_t BIG_DEG = 2048; // frontier vertices above this degree share the grid
+constexpr int32_t BIG_LDS = 2048; // big frontier vertices whose chunk prefix fits in LDS
+// Neighbours of degree above HUB_DEG ("hubs", at most HUB_SLOTS of them) are
+// stored in the peeling adjacency as HUB_FLAG | slot.  A round counts its
+// decrements of each hub in LDS and applies them with one atomic per block, so
+// the thousands of leaves of a hub removed in one round do not serialise on the
+// hub's degree counter.
+constexpr int32_t HUB_DEG = 1024;
+constexpr int32_t HUB_SLOTS = 4096;
+constexpr uint32_t HUB_FLAG = 0x80000000u;
+constexpr int32_t AGG_MIN_FRONTIER = 4096; // rounds above this frontier size aggregate in LDS
 
 enum : int32_t { PEEL_BOOT = -1, PEEL_COLLECT = 0, PEEL_ROUND = 1, PEEL_DONE = 2 };
 
@@ -204,18 +224,20 @@ struct PeelState {   // what step i does
     int32_t pad;
 };
 
-struct PeelCount {   // what step i produced
-    int32_t nS, nB;   // frontier written (degree <= BIG_DEG / above)
-    int32_t nA;       // live list written (collect)
+struct PeelCount {    // what step i produced
+    int32_t nT, nS, nB; // frontier written: degree <= TINY_DEG / <= BIG_DEG / above
+    int32_t nA;         // live list written (collect)
     int32_t min_above;
 };
 
 struct PeelBufs {
     const int64_t *uoff;
-    const int32_t *uadj;
+    const int32_t *uadj;     // neighbour id, or HUB_FLAG | hub slot for a hub neighbour
+    const int32_t *hub_vertex;
+    int32_t n_hubs;
     const int32_t *deg;
     int32_t *dcur, *rnd, *core;
-    int32_t *FS[3], *FB[3];
+    int32_t *FT[3], *FS[3], *FB[3];
     int32_t *alive[2];
     PeelState *state;  // [2]
     PeelCount *count;  // [3]
@@ -244,9 +266,9 @@ __device__ inline PeelState peel_next(const PeelState &p, const PeelCount &c, in
     } else if (p.mode == PEEL_COLLECT) {
         s.lp = p.lp ^ 1;
         s.alive_n = c.nA;
-        if (c.nS + c.nB > 0) {
+        if (c.nT + c.nS + c.nB > 0) {
             s.mode = PEEL_ROUND;
-            s.n_in = c.nS + c.nB;
+            s.n_in = c.nT + c.nS + c.nB;
         } else if (c.nA == 0) {
             s.mode = PEEL_DONE;
         } else {
@@ -255,8 +277,8 @@ __device__ inline PeelState peel_next(const PeelState &p, const PeelCount &c, in
     } else if (p.mode == PEEL_ROUND) {
         s.removed = p.removed + p.n_in;
         s.r = p.r + 1;
-        if (c.nS + c.nB > 0) {
-            s.n_in = c.nS + c.nB;
+        if (c.nT + c.nS + c.nB > 0) {
+            s.n_in = c.nT + c.nS + c.nB;
         } else {
             s.mode = PEEL_COLLECT;
             s.k = p.k + 1;
@@ -266,32 +288,137 @@ __device__ inline PeelState peel_next(const PeelState &p, const PeelCount &c, in
     return s;
 }
 
-__device__ inline void peel_neighbour(int32_t y, bool valid, int32_t k, const PeelBufs &B, PeelCount *out,
-                                      int32_t *FS, int32_t *FB) {
-    bool push = false;
-    if (valid && B.rnd[y] < 0) {
-        int32_t old = atomicSub(&B.dcur[y], 1);
-        push = (old == k + 1);
+// Pushes of one round are buffered per wavefront in LDS and written out per
+// block at the end of the step (one atomic per block and frontier class), so
+// that thousands of waves do not serialise on the same three counters.
+constexpr int PUSH_CAP = 256;
+
+__device__ inline int push_class(int32_t d) { return d <= TINY_DEG ? 0 : (d <= BIG_DEG ? 1 : 2); }
+
+struct PushBuf {
+    int32_t *buf; // this wave's PUSH_CAP slots in LDS
+    int32_t n;    // entries held (wave-uniform)
+};
+
+// move a wave's buffered pushes to the global lists with wave-level atomics
+__device__ inline void push_flush_wave(PushBuf &pb, const PeelBufs &B, PeelCount *out, int32_t *const L[3]) {
+    int32_t *cnt[3] = {&out->nT, &out->nS, &out->nB};
+    for (int32_t i0 = 0; i0 < pb.n; i0 += 64) {
+        int32_t i = i0 + lane_id();
+        bool v = i < pb.n;
+        int32_t y = v ? pb.buf[i] : 0;
+        int c = v ? push_class(B.deg[y]) : -1;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            int32_t slot = wave_append(cnt[j], c == j);
+            if (slot >= 0) L[j][slot] = y;
+        }
     }
-    bool big = push && B.deg[y] > BIG_DEG;
-    int32_t a = wave_append(&out->nS, push && !big);
-    if (a >= 0) FS[a] = y;
-    int32_t b = wave_append(&out->nB, big);
-    if (b >= 0) FB[b] = y;
+    pb.n = 0;
 }
 
-// block-aggregated append of up to three predicates: one global atomic per block
-// and per predicate; slot[j] is this thread's index in list j or -1
-__device__ inline void block_append3(bool p0, bool p1, bool p2, int32_t *g0, int32_t *g1, int32_t *g2,
-                                     int32_t slot[3]) {
-    __shared__ int32_t s_cnt[3], s_base[3];
-    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+// Decrement a neighbour's degree; the one decrement that takes it from k+1 to k
+// puts it in the next frontier.  Removed vertices may be decremented too: their
+// degree is already <= k, so they are never pushed again.
+// agg = large round: hub decrements go to the block's LDS counters and pushes to
+// the wave's LDS buffer; otherwise both go straight to global memory.
+template <bool AGG>
+__device__ inline void peel_neighbour(int32_t y, bool valid, int32_t k, const PeelBufs &B, PeelCount *out,
+                                      PushBuf &pb, int32_t *const L[3], int32_t *hub_cnt) {
+    bool push = false;
+    if (valid) {
+        if ((uint32_t)y & HUB_FLAG) {
+            const int32_t h = (int32_t)((uint32_t)y & ~HUB_FLAG);
+            if (AGG) {
+                atomicAdd(&hub_cnt[h], 1);
+                hub_cnt[HUB_SLOTS] = 1; // this block touched a hub
+            } else {
+                y = B.hub_vertex[h];
+                int32_t old = atomicSub(&B.dcur[y], 1);
+                push = (old == k + 1);
+            }
+        } else {
+            int32_t old = atomicSub(&B.dcur[y], 1);
+            push = (old == k + 1);
+        }
+    }
+    if (!AGG) {
+        int32_t dy = push ? B.deg[y] : 0;
+        int cls = push ? push_class(dy) : -1;
+        int32_t *cnt[3] = {&out->nT, &out->nS, &out->nB};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            int32_t slot = wave_append(cnt[j], cls == j);
+            if (slot >= 0) L[j][slot] = y;
+        }
+        return;
+    }
+    unsigned long long mask = __ballot(push);
+    if (!mask) return;
+    int32_t c = (int32_t)__popcll(mask);
+    if (pb.n + c > PUSH_CAP) {
+        wave_sync();
+        push_flush_wave(pb, B, out, L);
+    }
+    if (push) pb.buf[pb.n + (int32_t)__popcll(mask & ((1ull << lane_id()) - 1ull))] = y;
+    pb.n += c;
+    wave_sync();
+}
+
+// end of a round: every wave's buffered pushes go out with one atomic per block
+// and class
+__device__ inline void push_flush_block(PushBuf &pb, const PeelBufs &B, PeelCount *out, int32_t *const L[3]) {
+    __shared__ int32_t s_cnt[BLK / 64][3];
+    __shared__ int32_t s_off[BLK / 64][3];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    int32_t cc[3] = {0, 0, 0};
+    for (int32_t i0 = 0; i0 < pb.n; i0 += 64) {
+        int32_t i = i0 + lane;
+        int c = i < pb.n ? push_class(B.deg[pb.buf[i]]) : -1;
+#pragma unroll
+        for (int j = 0; j < 3; j++) cc[j] += (int32_t)__popcll(__ballot(c == j));
+    }
+    if (lane == 0)
+        for (int j = 0; j < 3; j++) s_cnt[w][j] = cc[j];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int j = threadIdx.x;
+        int32_t *cnt = j == 0 ? &out->nT : (j == 1 ? &out->nS : &out->nB);
+        int32_t tot = 0;
+        for (int wv = 0; wv < BLK / 64; wv++) tot += s_cnt[wv][j];
+        int32_t base = tot ? atomicAdd(cnt, tot) : 0;
+        for (int wv = 0; wv < BLK / 64; wv++) {
+            s_off[wv][j] = base;
+            base += s_cnt[wv][j];
+        }
+    }
+    __syncthreads();
+    int32_t off[3] = {s_off[w][0], s_off[w][1], s_off[w][2]};
+    for (int32_t i0 = 0; i0 < pb.n; i0 += 64) {
+        int32_t i = i0 + lane;
+        bool v = i < pb.n;
+        int32_t y = v ? pb.buf[i] : 0;
+        int c = v ? push_class(B.deg[y]) : -1;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            unsigned long long mask = __ballot(c == j);
+            if (c == j) L[j][off[j] + (int32_t)__popcll(mask & ((1ull << lane) - 1ull))] = y;
+            off[j] += (int32_t)__popcll(mask);
+        }
+    }
+    pb.n = 0;
+}
+
+// block-aggregated append of four predicates: one global atomic per block and
+// per predicate; slot[j] is this thread's index in list j or -1
+__device__ inline void block_append4(const bool p[4], int32_t *const g[4], int32_t slot[4]) {
+    __shared__ int32_t s_cnt[4], s_base[4];
+    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     const int lane = lane_id();
-    bool p[3] = {p0, p1, p2};
-    int32_t local[3];
+    int32_t local[4];
 #pragma unroll
-    for (int j = 0; j < 3; j++) {
+    for (int j = 0; j < 4; j++) {
         unsigned long long mask = __ballot(p[j]);
         int32_t woff = 0;
         int leader = mask ? __ffsll((long long)mask) - 1 : 0;
@@ -300,13 +427,170 @@ __device__ inline void block_append3(bool p0, bool p1, bool p2, int32_t *g0, int
         local[j] = p[j] ? woff + (int32_t)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
-        int32_t *g = threadIdx.x == 0 ? g0 : (threadIdx.x == 1 ? g1 : g2);
-        s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(g, s_cnt[threadIdx.x]) : 0;
-    }
+    if (threadIdx.x < 4) s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(g[threadIdx.x], s_cnt[threadIdx.x]) : 0;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 3; j++) slot[j] = local[j] >= 0 ? s_base[j] + local[j] : -1;
+    for (int j = 0; j < 4; j++) slot[j] = local[j] >= 0 ? s_base[j] + local[j] : -1;
+}
+
+// one peel round: remove the frontier the previous step wrote, decrement the
+// neighbours, collect the vertices that cross from k+1 to k
+struct PeelLds {
+    int32_t push[BLK / 64][PUSH_CAP];
+    int32_t hub[HUB_SLOTS + 1];
+    int32_t bpre[BIG_LDS + 1];
+    int32_t wt[BLK / 64];
+    int32_t carry;
+};
+
+template <bool AGG>
+__device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const PeelCount &s_prev, PeelCount *out,
+                                  int cur, int prv, PeelLds &lds) {
+    const int lane = lane_id();
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gwave = gtid >> 6, nwaves = stride >> 6;
+    const int32_t n = B.n, k = st.k;
+    // the frontier is what the previous step wrote
+    int32_t nT = s_prev.nT < n ? s_prev.nT : n;
+    int32_t nS = s_prev.nS < n ? s_prev.nS : n, nB = s_prev.nB < n ? s_prev.nB : n;
+    const int32_t *FT = B.FT[prv], *FS = B.FS[prv], *FB = B.FB[prv];
+    int32_t *const L[3] = {B.FT[cur], B.FS[cur], B.FB[cur]};
+    int32_t *s_hub = lds.hub;
+    PushBuf pb{lds.push[threadIdx.x >> 6], 0};
+    const int32_t r = st.r;
+    const int32_t H = B.n_hubs;
+    if (AGG) {
+        for (int32_t h = threadIdx.x; h < H; h += BLK) s_hub[h] = 0;
+        if (threadIdx.x == 0) s_hub[HUB_SLOTS] = 0;
+        __syncthreads();
+    }
+    for (int64_t i = gtid; i < nT; i += stride) {
+        int32_t x = FT[i];
+        B.rnd[x] = r;
+        B.core[x] = k;
+    }
+    for (int64_t i = gtid; i < nS; i += stride) {
+        int32_t x = FS[i];
+        B.rnd[x] = r;
+        B.core[x] = k;
+    }
+    for (int64_t i = gtid; i < nB; i += stride) {
+        int32_t x = FB[i];
+        B.rnd[x] = r;
+        B.core[x] = k;
+    }
+    // low-degree vertices: one lane each, the wave runs to its longest row
+    for (int64_t base = gtid - lane; base < nT; base += stride) {
+        int64_t i = base + lane;
+        bool v = i < nT;
+        int32_t x = v ? FT[i] : 0;
+        int64_t b = v ? B.uoff[x] : 0;
+        int32_t len = v ? (int32_t)(B.uoff[x + 1] - b) : 0;
+        int32_t mx = len;
+        for (int o = 32; o > 0; o >>= 1) {
+            int32_t other = __shfl_xor(mx, o);
+            mx = other > mx ? other : mx;
+        }
+        for (int32_t j = 0; j < mx; j++) {
+            bool valid = j < len;
+            peel_neighbour<AGG>(valid ? B.uadj[b + j] : 0, valid, k, B, out, pb, L, s_hub);
+        }
+    }
+    // small frontiers get several waves per vertex (wave w works on vertex
+    // w mod nS, every wpv-th chunk starting at chunk w / nS)
+    const int64_t wpv = nS > 0 && nS < nwaves ? nwaves / nS : 1;
+    for (int64_t w = gwave; w < nS * wpv; w += nwaves) {
+        int32_t x = FS[w % nS];
+        int64_t part = w / nS;
+        int64_t b = B.uoff[x], e = B.uoff[x + 1];
+        for (int64_t p0 = b + part * 64; p0 < e; p0 += wpv * 64) {
+            int64_t p = p0 + lane;
+            bool valid = p < e;
+            peel_neighbour<AGG>(valid ? B.uadj[p] : 0, valid, k, B, out, pb, L, s_hub);
+        }
+    }
+    // high-degree vertices: the whole grid strides over the 64-entry chunks of
+    // all their rows at once (chunk prefix per block in LDS)
+    if (nB > 0 && nB <= BIG_LDS) {
+        int32_t *s_bpre = lds.bpre;
+        int32_t &s_carry = lds.carry;
+        int32_t *s_wt = lds.wt;
+        if (threadIdx.x == 0) s_carry = 0;
+        __syncthreads();
+        for (int32_t j0 = 0; j0 < nB; j0 += BLK) {
+            int32_t j = j0 + threadIdx.x;
+            int32_t c = 0;
+            if (j < nB) {
+                int32_t x = FB[j];
+                c = (int32_t)((B.uoff[x + 1] - B.uoff[x] + 63) >> 6);
+            }
+            // block inclusive scan of c (wave scans, then wave totals)
+            int32_t v = c;
+            for (int o = 1; o < 64; o <<= 1) {
+                int32_t y = __shfl_up(v, o);
+                if (lane >= o) v += y;
+            }
+            if (lane == 63) s_wt[threadIdx.x >> 6] = v;
+            __syncthreads();
+            int32_t before = s_carry;
+            for (int wv = 0; wv < (int)(threadIdx.x >> 6); wv++) before += s_wt[wv];
+            if (j < nB) s_bpre[j + 1] = before + v;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int32_t t = s_carry;
+                for (int wv = 0; wv < BLK / 64; wv++) t += s_wt[wv];
+                s_carry = t;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) s_bpre[0] = 0;
+        __syncthreads();
+        const int32_t total = s_bpre[nB];
+        for (int64_t c = gwave; c < total; c += nwaves) {
+            int32_t lo = 0, hi = nB;
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (s_bpre[mid + 1] <= c) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t x = FB[lo];
+            int64_t b = B.uoff[x], e = B.uoff[x + 1];
+            int64_t p = b + (c - s_bpre[lo]) * 64 + lane;
+            bool valid = p < e;
+            peel_neighbour<AGG>(valid ? B.uadj[p] : 0, valid, k, B, out, pb, L, s_hub);
+        }
+    } else {
+        for (int32_t j = 0; j < nB; j++) {
+            int32_t x = FB[j];
+            int64_t b = B.uoff[x], e = B.uoff[x + 1];
+            for (int64_t p0 = b + gwave * 64; p0 < e; p0 += nwaves * 64) {
+                int64_t p = p0 + lane;
+                bool valid = p < e;
+                peel_neighbour<AGG>(valid ? B.uadj[p] : 0, valid, k, B, out, pb, L, s_hub);
+            }
+        }
+    }
+    if (!AGG) return;
+    // apply this block's hub decrements: one atomic per touched hub
+    __syncthreads();
+    const int32_t touched = s_hub[HUB_SLOTS];
+    for (int32_t h0 = 0; touched && h0 < H; h0 += BLK) {
+        int32_t h = h0 + threadIdx.x;
+        int32_t c = h < H ? s_hub[h] : 0;
+        bool push = false;
+        int32_t y = 0;
+        if (c) {
+            y = B.hub_vertex[h];
+            int32_t old = atomicSub(&B.dcur[y], c);
+            push = old > k && old - c <= k;
+        }
+        int32_t slot = wave_append(&out->nB, push && B.deg[y] > BIG_DEG);
+        if (slot >= 0) L[2][slot] = y;
+        slot = wave_append(&out->nS, push && B.deg[y] <= BIG_DEG);
+        if (slot >= 0) L[1][slot] = y;
+    }
+    push_flush_block(pb, B, out, L);
 }
 
 __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
@@ -323,7 +607,7 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
     const PeelState st = s_st;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         B.state[step & 1] = st;
-        PeelCount z = {0, 0, 0, 0x7fffffff};
+        PeelCount z = {0, 0, 0, 0, 0x7fffffff};
         B.count[nxt] = z;
     }
     if (st.mode == PEEL_DONE) return;
@@ -338,7 +622,8 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
         int32_t na = st.alive_n < n ? st.alive_n : n;
         const int32_t *A = B.alive[st.lp];
         int32_t *A2 = B.alive[st.lp ^ 1];
-        int32_t *FS = B.FS[cur], *FB = B.FB[cur];
+        int32_t *FT = B.FT[cur], *FS = B.FS[cur], *FB = B.FB[cur];
+        int32_t *const g[4] = {&out->nT, &out->nS, &out->nB, &out->nA};
         int32_t local_min = 0x7fffffff;
         for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += stride) {
             int64_t i = base + threadIdx.x;
@@ -347,14 +632,17 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
             bool live = valid && B.rnd[x] < 0;
             int32_t d = live ? B.dcur[x] : 0;
             bool take = live && d <= k;
-            bool big = take && B.deg[x] > BIG_DEG;
+            int32_t dx = take ? B.deg[x] : 0;
             bool keep = live && d > k;
             if (keep && d < local_min) local_min = d;
-            int32_t slot[3];
-            block_append3(take && !big, big, keep, &out->nS, &out->nB, &out->nA, slot);
-            if (slot[0] >= 0) FS[slot[0]] = x;
-            if (slot[1] >= 0) FB[slot[1]] = x;
-            if (slot[2] >= 0) A2[slot[2]] = x;
+            const bool p[4] = {take && dx <= TINY_DEG, take && dx > TINY_DEG && dx <= BIG_DEG, take && dx > BIG_DEG,
+                               keep};
+            int32_t slot[4];
+            block_append4(p, g, slot);
+            if (slot[0] >= 0) FT[slot[0]] = x;
+            if (slot[1] >= 0) FS[slot[1]] = x;
+            if (slot[2] >= 0) FB[slot[2]] = x;
+            if (slot[3] >= 0) A2[slot[3]] = x;
         }
         for (int o = 32; o > 0; o >>= 1) {
             int32_t other = __shfl_xor(local_min, o);
@@ -369,41 +657,10 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
             if (mm != 0x7fffffff) atomicMin(&out->min_above, mm);
         }
     } else {
-        // the frontier is what the previous step wrote
-        int32_t nS = s_prev.nS < n ? s_prev.nS : n, nB = s_prev.nB < n ? s_prev.nB : n;
-        const int32_t *FS = B.FS[prv], *FB = B.FB[prv];
-        int32_t *NS = B.FS[cur], *NB = B.FB[cur];
-        const int32_t r = st.r;
-        for (int64_t i = gtid; i < nS; i += stride) {
-            int32_t x = FS[i];
-            B.rnd[x] = r;
-            B.core[x] = k;
-        }
-        for (int64_t i = gtid; i < nB; i += stride) {
-            int32_t x = FB[i];
-            B.rnd[x] = r;
-            B.core[x] = k;
-        }
-        // a frontier vertex seen as live here is only decremented, never pushed:
-        // its degree is already <= k
-        for (int64_t w = gwave; w < nS; w += nwaves) {
-            int32_t x = FS[w];
-            int64_t b = B.uoff[x], e = B.uoff[x + 1];
-            for (int64_t p0 = b; p0 < e; p0 += 64) {
-                int64_t p = p0 + lane;
-                bool valid = p < e;
-                peel_neighbour(valid ? B.uadj[p] : 0, valid, k, B, out, NS, NB);
-            }
-        }
-        for (int32_t j = 0; j < nB; j++) {
-            int32_t x = FB[j];
-            int64_t b = B.uoff[x], e = B.uoff[x + 1];
-            for (int64_t p0 = b + gwave * 64; p0 < e; p0 += nwaves * 64) {
-                int64_t p = p0 + lane;
-                bool valid = p < e;
-                peel_neighbour(valid ? B.uadj[p] : 0, valid, k, B, out, NS, NB);
-            }
-        }
+        const int32_t big_round = s_prev.nT + s_prev.nS + s_prev.nB > AGG_MIN_FRONTIER;
+        __shared__ PeelLds lds;
+        if (big_round) peel_round<true>(B, st, s_prev, out, cur, prv, lds);
+        else peel_round<false>(B, st, s_prev, out, cur, prv, lds);
     }
 }
 
@@ -434,6 +691,26 @@ __global__ void k_adj_rows(const uint64_t *__restrict__ key, int64_t E, int32_t 
         else b = mid;
     }
     uoff[x] = a;
+}
+
+// hubs of the peeling adjacency: vertices of degree > HUB_DEG, first HUB_SLOTS found
+__global__ void k_find_hubs(const int32_t *__restrict__ deg, int32_t n, int32_t *__restrict__ hub_of,
+                            int32_t *__restrict__ hub_vertex, int32_t *__restrict__ n_hubs) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool hub = x < n && deg[x] > HUB_DEG;
+    int32_t slot = wave_append(n_hubs, hub);
+    if (x < n) hub_of[x] = -1;
+    if (slot >= 0 && slot < HUB_SLOTS) {
+        hub_of[x] = slot;
+        hub_vertex[slot] = (int32_t)x;
+    }
+}
+
+__global__ void k_mark_hubs(int32_t *__restrict__ uadj, int64_t E, const int32_t *__restrict__ hub_of) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E) return;
+    int32_t h = hub_of[uadj[i]];
+    if (h >= 0) uadj[i] = (int32_t)(HUB_FLAG | (uint32_t)h);
 }
 
 __global__ void k_adj_deg(const int64_t *__restrict__ uoff, int32_t n, int32_t *__restrict__ deg) {
@@ -480,15 +757,24 @@ __global__ void k_orient_keys(const int32_t *__restrict__ slo, const int32_t *__
 }
 
 __global__ void k_orient_unpack(const uint64_t *__restrict__ key, int32_t S, int64_t n,
-                                int32_t *__restrict__ osrc, int32_t *__restrict__ oadj,
-                                int32_t *__restrict__ outdeg_new) {
+                                int32_t *__restrict__ oadj) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= S) return;
-    uint64_t k = key[j];
-    int32_t tail = (int32_t)(k / (uint64_t)n), head = (int32_t)(k % (uint64_t)n);
-    osrc[j] = tail;
-    oadj[j] = head;
-    atomicAdd(&outdeg_new[tail], 1);
+    oadj[j] = (int32_t)(key[j] % (uint64_t)n);
+}
+
+// oriented CSR rows: row x starts at the first key >= x * n
+__global__ void k_orient_rows(const uint64_t *__restrict__ key, int32_t S, int64_t n, int32_t *__restrict__ ooff) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > n) return;
+    uint64_t want = (uint64_t)x * (uint64_t)n;
+    int32_t a = 0, b = S;
+    while (a < b) {
+        int32_t mid = (int32_t)(((int64_t)a + b) >> 1);
+        if (key[mid] < want) a = mid + 1;
+        else b = mid;
+    }
+    ooff[x] = a;
 }
 
 struct OrientStats {
@@ -497,18 +783,18 @@ struct OrientStats {
     int32_t max_core;
 };
 
-__global__ void k_orient_stats(const int32_t *__restrict__ outdeg_new, const int32_t *__restrict__ rank,
+__global__ void k_orient_stats(const int32_t *__restrict__ ooff, const int32_t *__restrict__ rank,
                                const int32_t *__restrict__ core, int32_t n,
                                int32_t *__restrict__ outdeg_orig, OrientStats *os) {
-    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long w = 0;
     int32_t mo = 0, mc = 0;
-    if (x < n) {
-        int32_t d = outdeg_new[rank[x]];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        int32_t r = rank[x];
+        int32_t d = ooff[r + 1] - ooff[r];
         outdeg_orig[x] = d;
-        w = (unsigned long long)d * (unsigned long long)(d > 0 ? d - 1 : 0) / 2ull;
-        mo = d;
-        mc = core[x];
+        w += (unsigned long long)d * (unsigned long long)(d > 0 ? d - 1 : 0) / 2ull;
+        mo = d > mo ? d : mo;
+        mc = core[x] > mc ? core[x] : mc;
     }
     __shared__ unsigned long long s_w[BLK / 64];
     __shared__ int32_t s_o[BLK / 64], s_c[BLK / 64];
@@ -536,42 +822,8 @@ __global__ void k_orient_stats(const int32_t *__restrict__ outdeg_new, const int
     }
 }
 
-// triangles closed from each oriented edge (u -> v): heads w of u after v that
-// are also heads of v.  Both rows ascend, so the search window in v's row only
-// moves forward.
-__global__ void k_tri_count(const int32_t *__restrict__ osrc, const int32_t *__restrict__ oadj,
-                            const int32_t *__restrict__ ooff, const uint32_t *__restrict__ oeid,
-                            int32_t S, int32_t *__restrict__ tri_cnt, int32_t *__restrict__ tcnt) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= S) return;
-    int32_t u = osrc[j], v = oadj[j];
-    int32_t end = ooff[u + 1];
-    int32_t lo = ooff[v], hi = ooff[v + 1];
-    int32_t c = 0;
-    for (int32_t j2 = (int32_t)j + 1; j2 < end && lo < hi; j2++) {
-        int32_t w = oadj[j2];
-        int32_t a = lo, b = hi;
-        while (a < b) {
-            int32_t mid = (a + b) >> 1;
-            if (oadj[mid] < w) a = mid + 1;
-            else b = mid;
-        }
-        lo = a;
-        if (a < hi && oadj[a] == w) {
-            c++;
-            atomicAdd(&tcnt[oeid[j2] & 0x7fffffffu], 1);
-            atomicAdd(&tcnt[oeid[a] & 0x7fffffffu], 1);
-            lo = a + 1;
-        }
-    }
-    tri_cnt[j] = c;
-    if (c) atomicAdd(&tcnt[oeid[j] & 0x7fffffffu], c);
-}
-
 } // namespace
 
-// defined in query.hip: writes the triangle list of the index
-void enumerate_triangles(const Index &ix, uint32_t *tri, hipStream_t s);
 
 static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0;
@@ -599,6 +851,7 @@ void load_graph(Graph *g, int32_t n, int64_t m, const int32_t *src, const int32_
         g->own_stream = true;
     }
     hipStream_t s = g->stream;
+    StreamScope sc(s);
     g->ix.n = n;
     g->ix.m_input = m;
     g->src.ensure(sizeof(int32_t) * m);
@@ -732,8 +985,8 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         k_static_table<<<grid_for(m, BLK), BLK, 0, s>>>(pkey2.as<uint64_t>(), ix.sid.as<int32_t>(), m, n,
                                                         ix.soff.as<int32_t>(), ix.smid.as<int32_t>(),
                                                         ix.slo.as<int32_t>(), ix.shi.as<int32_t>());
-        k_fix_smid_stats<<<grid_for(S, BLK), BLK, 0, s>>>(ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), S,
-                                                          pstat.as<PairStats>());
+        k_fix_smid_stats<<<grid_for(S, BLK, 2048), BLK, 0, s>>>(ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), S,
+                                                                pstat.as<PairStats>());
         FOLTY_LAUNCHED();
     }
     pkey2.release();
@@ -762,13 +1015,33 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         k_adj_deg<<<grid_for(n, BLK), BLK, 0, s>>>(uoff.as<int64_t>(), n, ix.deg.as<int32_t>());
         FOLTY_LAUNCHED();
     }
+    DevBuf hub_of, hub_vertex, hub_n;
+    hub_of.ensure(4 * (size_t)n);
+    hub_vertex.ensure(4 * (size_t)HUB_SLOTS);
+    hub_n.ensure(4);
+    int32_t n_hubs = 0;
+    {
+        FOLTY_HIP(hipMemsetAsync(hub_n.p, 0, 4, s));
+        k_find_hubs<<<grid_for(n, BLK), BLK, 0, s>>>(ix.deg.as<int32_t>(), n, hub_of.as<int32_t>(),
+                                                    hub_vertex.as<int32_t>(), hub_n.as<int32_t>());
+        FOLTY_LAUNCHED();
+        FOLTY_HIP(hipMemcpyAsync(hb.p, hub_n.p, 4, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipStreamSynchronize(s));
+        n_hubs = *hb.as<int32_t>();
+        if (n_hubs > HUB_SLOTS) n_hubs = HUB_SLOTS;
+        if (n_hubs > 0 && S > 0) {
+            k_mark_hubs<<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(uadj.as<int32_t>(), 2 * (int64_t)S,
+                                                                     hub_of.as<int32_t>());
+            FOLTY_LAUNCHED();
+        }
+    }
 
     // ---- a.3: core numbers by min-degree peeling ------------------------------------
     ix.core.ensure(4 * (size_t)n);
     DevBuf dcur, rnd, fr, alive, pst;
     dcur.ensure(4 * (size_t)n);
     rnd.ensure(4 * (size_t)n);
-    fr.ensure(4 * 6 * (size_t)n);
+    fr.ensure(4 * 9 * (size_t)n);
     alive.ensure(4 * 2 * (size_t)n);
     pst.ensure(2 * sizeof(PeelState) + 3 * sizeof(PeelCount));
     k_peel_init<<<grid_for(n, BLK), BLK, 0, s>>>(ix.deg.as<int32_t>(), dcur.as<int32_t>(), rnd.as<int32_t>(),
@@ -779,7 +1052,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         char init[2 * sizeof(PeelState) + 3 * sizeof(PeelCount)];
         PeelState boot{};
         boot.mode = PEEL_BOOT;
-        PeelCount zero = {0, 0, 0, 0x7fffffff};
+        PeelCount zero = {0, 0, 0, 0, 0x7fffffff};
         memcpy(init, &boot, sizeof boot);
         memcpy(init + sizeof(PeelState), &boot, sizeof boot);
         for (int i = 0; i < 3; i++) memcpy(init + 2 * sizeof(PeelState) + i * sizeof(PeelCount), &zero, sizeof zero);
@@ -787,13 +1060,16 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         PeelBufs B;
         B.uoff = uoff.as<int64_t>();
         B.uadj = uadj.as<int32_t>();
+        B.hub_vertex = hub_vertex.as<int32_t>();
+        B.n_hubs = n_hubs;
         B.deg = ix.deg.as<int32_t>();
         B.dcur = dcur.as<int32_t>();
         B.rnd = rnd.as<int32_t>();
         B.core = ix.core.as<int32_t>();
         for (int i = 0; i < 3; i++) {
-            B.FS[i] = fr.as<int32_t>() + (size_t)i * n;
-            B.FB[i] = fr.as<int32_t>() + (size_t)(3 + i) * n;
+            B.FT[i] = fr.as<int32_t>() + (size_t)i * n;
+            B.FS[i] = fr.as<int32_t>() + (size_t)(3 + i) * n;
+            B.FB[i] = fr.as<int32_t>() + (size_t)(6 + i) * n;
         }
         B.alive[0] = alive.as<int32_t>();
         B.alive[1] = alive.as<int32_t>() + (size_t)n;
@@ -804,17 +1080,20 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         // ends within about 3n steps; the cap turns a logic error into an error code
         const int64_t cap = 3 * (int64_t)n + 4096;
         int64_t step = 0;
-        int batch = 64;
+        int batch = 32;
+        int blocks = PEEL_BLOCKS_WIDE;
         PeelState h{};
         for (;;) {
-            for (int i = 0; i < batch; i++, step++) k_peel_step<<<PEEL_BLOCKS, BLK, 0, s>>>(B, step);
+            for (int i = 0; i < batch; i++, step++) k_peel_step<<<blocks, BLK, 0, s>>>(B, step);
             FOLTY_LAUNCHED();
             FOLTY_HIP(hipMemcpyAsync(hb.p, B.state + ((step - 1) & 1), sizeof(PeelState), hipMemcpyDeviceToHost, s));
             FOLTY_HIP(hipStreamSynchronize(s));
             memcpy(&h, hb.p, sizeof h);
             if (h.mode == PEEL_DONE) break;
             if (step > cap) fail(FOLTY_EDEVICE, "core peeling did not finish in %lld steps", (long long)step);
-            batch = batch < 512 ? 2 * batch : 512;
+            batch = batch < 256 ? 2 * batch : 256;
+            // every loop of the step is grid-stride, so any grid size is correct
+            blocks = h.alive_n < PEEL_NARROW_BELOW ? PEEL_BLOCKS_NARROW : PEEL_BLOCKS_WIDE;
         }
         if (h.removed != n) fail(FOLTY_EDEVICE, "core peeling removed %d of %d vertices", h.removed, n);
         ix.peel_rounds = h.r;
@@ -847,68 +1126,44 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     rnd.release();
     ix.rank_mode = o.rank_mode;
 
-    ix.osrc.ensure(4 * (size_t)S + 4);
     ix.oadj.ensure(4 * (size_t)S + 4);
     ix.oeid.ensure(4 * (size_t)S + 4);
     ix.ooff.ensure(4 * ((size_t)n + 1));
     ix.outdeg.ensure(4 * (size_t)n);
-    DevBuf od_new;
-    od_new.ensure(4 * ((size_t)n + 1));
-    FOLTY_HIP(hipMemsetAsync(od_new.p, 0, 4 * ((size_t)n + 1), s));
-    if (S > 0) {
-        DevBuf key, key2, val;
-        key.ensure(8 * (size_t)S);
-        key2.ensure(8 * (size_t)S);
-        val.ensure(4 * (size_t)S);
-        k_orient_keys<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(),
-                                                       ix.rank.as<int32_t>(), S, n, key.as<uint64_t>(),
-                                                       val.as<uint32_t>());
-        FOLTY_LAUNCHED();
-        int kb = bit_length((uint64_t)n * (uint64_t)n);
-        size_t need = sort_pairs_u64_u32(nullptr, 0, key.as<uint64_t>(), key2.as<uint64_t>(), val.as<uint32_t>(),
-                                         ix.oeid.as<uint32_t>(), S, kb, s);
-        sort_pairs_u64_u32(cub_ensure(need), need, key.as<uint64_t>(), key2.as<uint64_t>(), val.as<uint32_t>(),
-                           ix.oeid.as<uint32_t>(), S, kb, s);
-        k_orient_unpack<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.osrc.as<int32_t>(),
-                                                         ix.oadj.as<int32_t>(), od_new.as<int32_t>());
-        FOLTY_LAUNCHED();
-    }
     {
-        size_t need = exclusive_scan_i32(nullptr, 0, od_new.as<int32_t>(), ix.ooff.as<int32_t>(), n + 1, s);
-        exclusive_scan_i32(cub_ensure(need), need, od_new.as<int32_t>(), ix.ooff.as<int32_t>(), n + 1, s);
+        DevBuf key, key2, val;
+        key.ensure(8 * (size_t)S + 8);
+        key2.ensure(8 * (size_t)S + 8);
+        val.ensure(4 * (size_t)S + 4);
+        if (S > 0) {
+            k_orient_keys<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(),
+                                                           ix.rank.as<int32_t>(), S, n, key.as<uint64_t>(),
+                                                           val.as<uint32_t>());
+            FOLTY_LAUNCHED();
+            int kb = bit_length((uint64_t)n * (uint64_t)n);
+            size_t need = sort_pairs_u64_u32(nullptr, 0, key.as<uint64_t>(), key2.as<uint64_t>(), val.as<uint32_t>(),
+                                             ix.oeid.as<uint32_t>(), S, kb, s);
+            sort_pairs_u64_u32(cub_ensure(need), need, key.as<uint64_t>(), key2.as<uint64_t>(), val.as<uint32_t>(),
+                               ix.oeid.as<uint32_t>(), S, kb, s);
+            k_orient_unpack<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.oadj.as<int32_t>());
+            FOLTY_LAUNCHED();
+        }
+        k_orient_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.ooff.as<int32_t>());
+        FOLTY_LAUNCHED();
     }
     DevBuf ostat;
     ostat.ensure(sizeof(OrientStats));
     FOLTY_HIP(hipMemsetAsync(ostat.p, 0, sizeof(OrientStats), s));
-    k_orient_stats<<<grid_for(n, BLK), BLK, 0, s>>>(od_new.as<int32_t>(), ix.rank.as<int32_t>(), ix.core.as<int32_t>(),
-                                                    n, ix.outdeg.as<int32_t>(), ostat.as<OrientStats>());
+    k_orient_stats<<<grid_for(n, BLK, 2048), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.rank.as<int32_t>(),
+                                                          ix.core.as<int32_t>(), n, ix.outdeg.as<int32_t>(),
+                                                          ostat.as<OrientStats>());
     FOLTY_LAUNCHED();
-    od_new.release();
-
-    // ---- triangles per oriented edge and per static edge ----------------------------------
-    ix.tri_off.ensure(8 * ((size_t)S + 1));
-    ix.tcnt.ensure(4 * (size_t)S + 4);
-    {
-        DevBuf tri_cnt;
-        tri_cnt.ensure(4 * ((size_t)S + 1));
-        FOLTY_HIP(hipMemsetAsync(tri_cnt.p, 0, 4 * ((size_t)S + 1), s));
-        FOLTY_HIP(hipMemsetAsync(ix.tcnt.p, 0, 4 * (size_t)S + 4, s));
-        if (S > 0) {
-            k_tri_count<<<grid_for(S, BLK), BLK, 0, s>>>(ix.osrc.as<int32_t>(), ix.oadj.as<int32_t>(),
-                                                         ix.ooff.as<int32_t>(), ix.oeid.as<uint32_t>(), S,
-                                                         tri_cnt.as<int32_t>(), ix.tcnt.as<int32_t>());
-            FOLTY_LAUNCHED();
-        }
-        size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_cnt.as<int32_t>(), ix.tri_off.as<int64_t>(), S + 1, s);
-        exclusive_scan_i32_to_i64(cub_ensure(need), need, tri_cnt.as<int32_t>(), ix.tri_off.as<int64_t>(), S + 1, s);
-    }
 
     // ---- read back sizes ------------------------------------------------------------
     {
         char *h = hb.as<char>();
         FOLTY_HIP(hipMemcpyAsync(h, pstat.p, sizeof(PairStats), hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipMemcpyAsync(h + 32, ostat.p, sizeof(OrientStats), hipMemcpyDeviceToHost, s));
-        FOLTY_HIP(hipMemcpyAsync(h + 64, ix.tri_off.as<int64_t>() + S, 8, hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipStreamSynchronize(s));
         PairStats ps;
         OrientStats os;
@@ -919,13 +1174,9 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         ix.W = (int64_t)os.wedges;
         ix.max_out = os.max_out;
         ix.max_core = os.max_core;
-        memcpy(&ix.T, h + 64, 8);
     }
-    if (o.cache_triangles && ix.T > 0) {
-        ix.tri.ensure(12 * (size_t)ix.T);
-        enumerate_triangles(ix, ix.tri.as<uint32_t>(), s);
-        ix.tri_cached = true;
-    }
+    // ---- oriented-edge records and triangles per lowest vertex ------------------------
+    index_triangles(ix, o.cache_triangles != 0, cub, s);
     FOLTY_HIP(hipEventRecord(e1, s));
     FOLTY_HIP(hipStreamSynchronize(s));
     ix.build_ms = elapsed_ms(e0, e1);
@@ -934,7 +1185,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
 
 size_t Index::device_bytes() const {
     const DevBuf *b[] = {&ts, &perm, &sid, &soff, &smid, &slo, &shi, &deg, &core, &rank,
-                         &outdeg, &ooff, &oadj, &oeid, &osrc, &tri_off, &tcnt, &tri};
+                         &outdeg, &ooff, &oadj, &oeid, &rec, &tri_base, &tcnt, &tri};
     size_t t = 0;
     for (auto *x : b) t += x->bytes;
     return t;

@@ -1,19 +1,22 @@
 // Query kernels for the thresholded exists-exists-forall triadic query.
 //
-//  a.5  wedge enumeration + closing probe (paper, Algorithm OutNeighbours'
-//       double loop over (u, v) in G->_pi and w in N+(u), with the adjacency
-//       test of v and w): every static triangle is found once, from its
-//       lowest-ranked vertex, as three oriented edges.
-//  a.6  temporal tests (paper, Theorems 3.1 and 3.2): for a temporal edge e on
-//       list L1 and the third vertex w, e forms a delta-temporal triangle with w
-//       iff, with t2 = the first entry of L2 at or after t(e) and t3 = the first
-//       entry of L3 at or after t2, both exist and t3 - t(e) <= delta.  The two
-//       first-entry searches are binary searches over the time-sorted lists
-//       (the log sigma_max factor of the paper's bound).  Every (triangle,
-//       directed list) pair is a run of tests; runs are cut into equal chunks
-//       over the whole grid (a flat, degree- and multiplicity-blind split).
-//  a.7  threshold (paper, Algorithm ExistExistForAll, final loop) with the
-//       exact rational theta, then per-pair certificate counts by a wavefront
+//  a.5  wedge enumeration + closing probe (paper, Algorithm OutNeighbours:
+//       (u, v) in G->_pi and w in N+(u), test whether v and w are adjacent).
+//       One wavefront per vertex u stages N+(u) in LDS, walks the wedges
+//       u -> v -> x for every v in N+(u) and x in N+(v) with coalesced reads of
+//       N+(v), and probes x in the staged N+(u).  Each static triangle is found
+//       once, from its lowest-ranked vertex, as three oriented edges.
+//  a.6  temporal tests (paper, Theorems 3.1 and 3.2): a temporal edge e on list
+//       L1 forms a delta-temporal triangle with the third vertex w iff, with
+//       t2 = the first entry of L2 at or after t(e) and t3 = the first entry of
+//       L3 at or after t2, both exist and t3 - t(e) <= delta.  The first-entry
+//       searches are binary searches over the time-sorted lists (the log
+//       sigma_max factor).  A (triangle, directed list) pair is a run of tests.
+//       A run is skipped when the time ranges of its three lists already rule
+//       out t <= t2 <= t3 <= t + delta (a necessary condition, so no result
+//       changes).  The surviving tests are cut into equal chunks over the grid.
+//  a.7  threshold (paper, Algorithm ExistExistForAll, final loop) with the exact
+//       rational theta, then per-pair certificate counts by a wavefront
 //       segmented reduction and a ballot/prefix compaction of the pairs.
 #include <algorithm>
 #include <cstring>
@@ -26,10 +29,23 @@ namespace folty {
 namespace {
 
 constexpr int BLK = 256;
-constexpr int IPT = 8;          // temporal tests per chunk
+constexpr int WPB = BLK / 64;         // wavefronts per block
+constexpr int CAP = 512;              // N+(u) staged in LDS up to this length
+constexpr int IPT = 8;                // temporal tests per chunk
 constexpr int PERSIST_BLOCKS = 4096;
+constexpr int ENUM_BLOCKS = 4096;
+constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item
 
 __device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline unsigned long long lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+// make this wavefront's LDS writes visible to all of its lanes
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ inline int32_t wave_append(int32_t *counter, bool pred) {
     unsigned long long mask = __ballot(pred);
@@ -39,7 +55,16 @@ __device__ inline int32_t wave_append(int32_t *counter, bool pred) {
     int32_t base = 0;
     if (lane == leader) base = atomicAdd(counter, (int32_t)__popcll(mask));
     base = __shfl(base, leader);
-    return pred ? base + (int32_t)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
+    return pred ? base + (int32_t)__popcll(mask & lanes_below()) : -1;
+}
+
+template <class T> __device__ inline T wave_inclusive_sum(T x) {
+    const int lane = lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
 }
 
 template <class T> __global__ void k_fill(T *p, T v, int64_t n) {
@@ -51,27 +76,14 @@ template <class T> __global__ void k_fill(T *p, T v, int64_t n) {
 // directed lists of a triangle
 // ---------------------------------------------------------------------------
 struct Span {
-    int32_t s, n;
+    int32_t s, n;    // start in ts, length
+    int64_t lo, hi;  // first and last timestamp
 };
-
-// E_{tail,head} and E_{head,tail} of an oriented edge record
-__device__ inline void edge_spans(uint32_t rec, const int32_t *__restrict__ soff,
-                                  const int32_t *__restrict__ smid, Span &fwd, Span &bwd) {
-    uint32_t e = rec & 0x7fffffffu;
-    int32_t a = soff[e], mid = smid[e], b = soff[e + 1];
-    if (rec >> 31) {
-        fwd = {a, mid - a};
-        bwd = {mid, b - mid};
-    } else {
-        fwd = {mid, b - mid};
-        bwd = {a, mid - a};
-    }
-}
 
 // D[i][j] = E_{x_i, x_j} for the triangle's vertices x0 < x1 < x2 (by rank)
 struct TriLists {
     Span d01, d10, d02, d20, d12, d21;
-    template <int I, int J> __device__ inline Span get() const {
+    template <int I, int J> __device__ inline const Span &get() const {
         static_assert(I != J, "");
         if constexpr (I == 0 && J == 1) return d01;
         else if constexpr (I == 1 && J == 0) return d10;
@@ -82,13 +94,25 @@ struct TriLists {
     }
 };
 
-__device__ inline TriLists load_tri(const uint32_t *__restrict__ tri, int64_t tau,
-                                    const int32_t *__restrict__ soff, const int32_t *__restrict__ smid) {
+__device__ inline void rec_spans(const EdgeRec *__restrict__ rec, int32_t p, Span &fwd, Span &bwd) {
+    const int4 *q = reinterpret_cast<const int4 *>(rec + p);
+    int4 a = q[0], b = q[1], c = q[2];
+    fwd.s = a.x;
+    fwd.n = a.y;
+    bwd.s = a.z;
+    bwd.n = a.w;
+    fwd.lo = (int64_t)(((uint64_t)(uint32_t)b.y << 32) | (uint32_t)b.x);
+    fwd.hi = (int64_t)(((uint64_t)(uint32_t)b.w << 32) | (uint32_t)b.z);
+    bwd.lo = (int64_t)(((uint64_t)(uint32_t)c.y << 32) | (uint32_t)c.x);
+    bwd.hi = (int64_t)(((uint64_t)(uint32_t)c.w << 32) | (uint32_t)c.z);
+}
+
+// the three oriented edges (x0,x1), (x0,x2), (x1,x2) of a triangle
+__device__ inline TriLists load_lists(const EdgeRec *__restrict__ rec, int32_t p01, int32_t p02, int32_t p12) {
     TriLists L;
-    uint32_t r0 = tri[3 * tau], r1 = tri[3 * tau + 1], r2 = tri[3 * tau + 2];
-    edge_spans(r0, soff, smid, L.d01, L.d10);
-    edge_spans(r1, soff, smid, L.d02, L.d20);
-    edge_spans(r2, soff, smid, L.d12, L.d21);
+    rec_spans(rec, p01, L.d01, L.d10);
+    rec_spans(rec, p02, L.d02, L.d20);
+    rec_spans(rec, p12, L.d12, L.d21);
     return L;
 }
 
@@ -100,22 +124,30 @@ template <int VAR, int I, int J> struct Pick {
     static constexpr int Y = (VAR & 4) ? I : J;
     static constexpr int L2a = (VAR & 1) ? C : X, L2b = (VAR & 1) ? X : C;
     static constexpr int L3a = (VAR & 2) ? C : Y, L3b = (VAR & 2) ? Y : C;
-    __device__ static inline void lists(const TriLists &T, Span &l1, Span &l2, Span &l3) {
-        l1 = T.template get<I, J>();
-        l2 = T.template get<L2a, L2b>();
-        l3 = T.template get<L3a, L3b>();
-    }
 };
 
-template <int VAR, int I, int J> __device__ inline int64_t list_work(const TriLists &T) {
-    Span a, b, c;
-    Pick<VAR, I, J>::lists(T, a, b, c);
-    return (b.n > 0 && c.n > 0) ? a.n : 0;
+// A run can only count if all three lists are non-empty and some t <= t2 <= t3
+// <= t + dmax is possible given each list's first and last timestamp.
+template <int VAR, int I, int J>
+__device__ inline bool run_lists(const TriLists &T, int64_t dmax, Span &l1, Span &l2, Span &l3) {
+    using P = Pick<VAR, I, J>;
+    l1 = T.template get<I, J>();
+    l2 = T.template get<P::L2a, P::L2b>();
+    l3 = T.template get<P::L3a, P::L3b>();
+    if (l1.n == 0 || l2.n == 0 || l3.n == 0) return false;
+    if (l2.hi < l1.lo || l3.hi < l2.lo) return false;
+    if (l2.lo - l1.hi > dmax || l3.lo - l1.hi > dmax) return false;
+    return true;
 }
 
-template <int VAR> __device__ inline int64_t tri_work(const TriLists &T) {
-    return list_work<VAR, 0, 1>(T) + list_work<VAR, 1, 0>(T) + list_work<VAR, 0, 2>(T) +
-           list_work<VAR, 2, 0>(T) + list_work<VAR, 1, 2>(T) + list_work<VAR, 2, 1>(T);
+template <int VAR, int I, int J> __device__ inline int64_t run_work(const TriLists &T, int64_t dmax) {
+    Span a, b, c;
+    return run_lists<VAR, I, J>(T, dmax, a, b, c) ? a.n : 0;
+}
+
+template <int VAR> __device__ inline int64_t tri_work(const TriLists &T, int64_t dmax) {
+    return run_work<VAR, 0, 1>(T, dmax) + run_work<VAR, 1, 0>(T, dmax) + run_work<VAR, 0, 2>(T, dmax) +
+           run_work<VAR, 2, 0>(T, dmax) + run_work<VAR, 1, 2>(T, dmax) + run_work<VAR, 2, 1>(T, dmax);
 }
 
 // first position p in [from, n) with L[p] >= key (n if none)
@@ -131,78 +163,68 @@ __device__ inline int32_t lower_bound_from(const int64_t *__restrict__ L, int32_
 }
 
 // cnt consecutive temporal edges of L1 starting at l1s against (L2, L3)
-__device__ inline void run_tests(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, Span l2, Span l3,
-                                 int64_t delta, uint32_t *__restrict__ count) {
-    const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
-    int32_t c2 = 0, c3 = 0;
-    for (int32_t q = 0; q < cnt; q++) {
-        int32_t e = l1s + q;
-        int64_t t = ts[e];
-        c2 = lower_bound_from(L2, c2, l2.n, t);
-        if (c2 == l2.n) break;           // later edges are no earlier: no t2 for them either
-        int64_t t2 = L2[c2];
-        if (t2 - t > delta) continue;
-        c3 = lower_bound_from(L3, c3, l3.n, t2);
-        if (c3 == l3.n) break;
-        if (L3[c3] - t <= delta) atomicAdd(&count[e], 1u);
-    }
-}
-
-// the same, recording the smallest window per (e, w) into a histogram over
-// sorted window levels: level j counts w whose smallest window is in (lv[j-1], lv[j]]
-__device__ inline void run_windows(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, Span l2, Span l3,
-                                   const int64_t *__restrict__ lv, int nl, int64_t m,
-                                   uint32_t *__restrict__ hist) {
-    const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
-    const int64_t dmax = lv[nl - 1];
-    int32_t c2 = 0, c3 = 0;
-    for (int32_t q = 0; q < cnt; q++) {
-        int32_t e = l1s + q;
-        int64_t t = ts[e];
-        c2 = lower_bound_from(L2, c2, l2.n, t);
-        if (c2 == l2.n) break;
-        int64_t t2 = L2[c2];
-        if (t2 - t > dmax) continue;
-        c3 = lower_bound_from(L3, c3, l3.n, t2);
-        if (c3 == l3.n) break;
-        int64_t win = L3[c3] - t;
-        if (win > dmax) continue;
-        int a = 0, b = nl;
-        while (a < b) {
-            int mid = (a + b) >> 1;
-            if (lv[mid] < win) a = mid + 1;
-            else b = mid;
-        }
-        atomicAdd(&hist[(int64_t)a * m + e], 1u);
-    }
-}
-
 struct DirectOp {
     int64_t delta;
     uint32_t *count;
-    __device__ inline void operator()(const int64_t *ts, int32_t l1s, int32_t cnt, Span l2, Span l3) const {
-        run_tests(ts, l1s, cnt, l2, l3, delta, count);
+    __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
+                                      const Span &l3) const {
+        const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
+        int32_t c2 = 0, c3 = 0;
+        for (int32_t q = 0; q < cnt; q++) {
+            int32_t e = l1s + q;
+            int64_t t = ts[e];
+            c2 = lower_bound_from(L2, c2, l2.n, t);
+            if (c2 == l2.n) break; // later edges are no earlier: no t2 for them either
+            int64_t t2 = L2[c2];
+            if (t2 - t > delta) continue;
+            c3 = lower_bound_from(L3, c3, l3.n, t2);
+            if (c3 == l3.n) break;
+            if (L3[c3] - t <= delta) atomicAdd(&count[e], 1u);
+        }
     }
 };
 
+// the smallest window per (e, w) into a histogram over sorted window levels:
+// level j counts w whose smallest window lies in (lv[j-1], lv[j]]
 struct PoolOp {
     const int64_t *lv;
     int nl;
     int64_t m;
     uint32_t *hist;
-    __device__ inline void operator()(const int64_t *ts, int32_t l1s, int32_t cnt, Span l2, Span l3) const {
-        run_windows(ts, l1s, cnt, l2, l3, lv, nl, m, hist);
+    __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
+                                      const Span &l3) const {
+        const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
+        const int64_t dmax = lv[nl - 1];
+        int32_t c2 = 0, c3 = 0;
+        for (int32_t q = 0; q < cnt; q++) {
+            int32_t e = l1s + q;
+            int64_t t = ts[e];
+            c2 = lower_bound_from(L2, c2, l2.n, t);
+            if (c2 == l2.n) break;
+            int64_t t2 = L2[c2];
+            if (t2 - t > dmax) continue;
+            c3 = lower_bound_from(L3, c3, l3.n, t2);
+            if (c3 == l3.n) break;
+            int64_t win = L3[c3] - t;
+            if (win > dmax) continue;
+            int a = 0, b = nl;
+            while (a < b) {
+                int mid = (a + b) >> 1;
+                if (lv[mid] < win) a = mid + 1;
+                else b = mid;
+            }
+            atomicAdd(&hist[(int64_t)a * m + e], 1u);
+        }
     }
 };
 
-// one list of the triangle within the chunk [k, k1); r = items of this
+// one run of a surviving triangle within the chunk [k, k1); r = tests of this
 // triangle still to skip.  Returns false once the chunk is used up.
 template <int VAR, int I, int J, class Op>
-__device__ inline bool chunk_list(const TriLists &T, const int64_t *ts, int64_t &r, int64_t &k, int64_t k1,
-                                  const Op &op) {
+__device__ inline bool chunk_run(const TriLists &T, int64_t dmax, const int64_t *ts, int64_t &r, int64_t &k,
+                                 int64_t k1, const Op &op) {
     Span l1, l2, l3;
-    Pick<VAR, I, J>::lists(T, l1, l2, l3);
-    if (l1.n == 0 || l2.n == 0 || l3.n == 0) return true;
+    if (!run_lists<VAR, I, J>(T, dmax, l1, l2, l3)) return true;
     if (r >= l1.n) {
         r -= l1.n;
         return true;
@@ -215,88 +237,339 @@ __device__ inline bool chunk_list(const TriLists &T, const int64_t *ts, int64_t 
     return k < k1;
 }
 
-// Flat split of all tests into chunks of IPT; grid-stride over chunks.  The
-// chunk's first triangle is found by binary search over the work offsets.
+// ---------------------------------------------------------------------------
+// a.5: triangle enumeration, one wavefront per lowest vertex u
+// ---------------------------------------------------------------------------
+// Sinks receive every probe: hit(h, p_uv, p_uw, p_vw) is called by all lanes of
+// the wave together (h = this lane found a triangle), so sinks may use ballots.
+struct CountSink {
+    int32_t *tri_u;
+    int32_t c;
+    __device__ void begin(int64_t) { c = 0; }
+    __device__ void hit(bool h, int32_t, int32_t, int32_t) { c += (int32_t)__popcll(__ballot(h)); }
+    __device__ void end(int64_t u) {
+        if (lane_id() == 0) tri_u[u] = c;
+    }
+};
+
+struct CacheSink {
+    const int64_t *base;
+    int32_t *tri;
+    int64_t slot;
+    __device__ void begin(int64_t u) { slot = base[u]; }
+    __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
+        unsigned long long mask = __ballot(h);
+        if (h) {
+            int64_t pos = slot + __popcll(mask & lanes_below());
+            tri[3 * pos] = a;
+            tri[3 * pos + 1] = b;
+            tri[3 * pos + 2] = c;
+        }
+        slot += __popcll(mask);
+    }
+    __device__ void end(int64_t) {}
+};
+
+struct TcntSink {
+    const uint32_t *oeid;
+    int32_t *tcnt;
+    __device__ void begin(int64_t) {}
+    __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
+        if (h) {
+            atomicAdd(&tcnt[oeid[a] & 0x7fffffffu], 1);
+            atomicAdd(&tcnt[oeid[b] & 0x7fffffffu], 1);
+            atomicAdd(&tcnt[oeid[c] & 0x7fffffffu], 1);
+        }
+    }
+    __device__ void end(int64_t) {}
+};
+
+// first and last timestamp over both directed lists of an oriented edge
+__device__ inline void edge_range(const EdgeRec *__restrict__ rec, int32_t p, int64_t &lo, int64_t &hi) {
+    Span f, b;
+    rec_spans(rec, p, f, b);
+    lo = INT64_MAX;
+    hi = INT64_MIN;
+    if (f.n) { lo = f.lo; hi = f.hi; }
+    if (b.n) { lo = b.lo < lo ? b.lo : lo; hi = b.hi > hi ? b.hi : hi; }
+}
+
+// Keeps triangles with at least one run that can count, in the slots of their
+// item, with each survivor's test offset inside that item.  Every run uses one
+// list of each of the three edges, and its three timestamps lie within dmax of
+// each other, so the two edges at u must have time ranges within dmax of each
+// other before the third edge is read at all.
+template <int VAR> struct FilterSink {
+    const int64_t *base;
+    const EdgeRec *rec;
+    int64_t dmax;
+    int32_t *sv;
+    int64_t *sw;
+    int32_t *su;
+    int64_t *wu;
+    int64_t slot;
+    int32_t ns;
+    int64_t work;
+    __device__ void begin(int64_t it) {
+        slot = base[it];
+        ns = 0;
+        work = 0;
+    }
+    __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
+        int64_t wk = 0;
+        if (h) {
+            int64_t alo, ahi, blo, bhi;
+            edge_range(rec, a, alo, ahi);
+            edge_range(rec, b, blo, bhi);
+            bool ranges = alo <= ahi && blo <= bhi; // every static edge has at least one temporal edge
+            if (ranges && alo - bhi <= dmax && blo - ahi <= dmax) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
+        }
+        bool keep = wk > 0;
+        unsigned long long mask = __ballot(keep);
+        if (!mask) return;
+        int64_t incl = wave_inclusive_sum(wk);
+        if (keep) {
+            int64_t pos = slot + ns + __popcll(mask & lanes_below());
+            sv[3 * pos] = a;
+            sv[3 * pos + 1] = b;
+            sv[3 * pos + 2] = c;
+            sw[pos] = work + incl - wk;
+        }
+        ns += (int32_t)__popcll(mask);
+        work += __shfl(incl, 63);
+    }
+    __device__ void end(int64_t it) {
+        if (lane_id() == 0) {
+            su[it] = ns;
+            wu[it] = work;
+        }
+    }
+};
+
+// One wavefront per item: the item's vertex u, and a range of the flattened
+// wedge space of u (position q = sum of |N+(v_j)| over j < i, plus the position
+// of x in N+(v_i)).
+template <class Sink>
+__global__ __launch_bounds__(BLK) void k_tri_enum(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
+                                                  const int32_t *__restrict__ item_u,
+                                                  const int32_t *__restrict__ item_off, int32_t NI, Sink sink) {
+    __shared__ int32_t s_nu[WPB][CAP];
+    __shared__ int32_t s_vo[WPB][CAP];
+    __shared__ int32_t s_pre[WPB][CAP + 1];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    int32_t *NU = s_nu[w], *VO = s_vo[w], *PRE = s_pre[w];
+    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
+        const int32_t u = item_u[it];
+        const int32_t part = (int32_t)(it - item_off[u]);
+        const int32_t b = ooff[u], d = ooff[u + 1] - b;
+        sink.begin(it);
+        if (d >= 2 && d <= CAP) {
+            // stage N+(u), the row start of each v and a prefix of |N+(v)|
+            int32_t carry = 0;
+            for (int32_t i0 = 0; i0 < d; i0 += 64) {
+                int32_t i = i0 + lane;
+                int32_t dv = 0;
+                if (i < d) {
+                    int32_t v = oadj[b + i];
+                    int32_t vo = ooff[v];
+                    dv = ooff[v + 1] - vo;
+                    NU[i] = v;
+                    VO[i] = vo;
+                }
+                int32_t x = wave_inclusive_sum(dv);
+                if (i < d) PRE[i + 1] = carry + x;
+                carry += __shfl(x, 63);
+            }
+            if (lane == 0) PRE[0] = 0;
+            wave_sync();
+            const int32_t q_begin = part * CHUNK;
+            const int32_t q_end = carry < q_begin + CHUNK ? carry : q_begin + CHUNK;
+            int32_t i = 0; // this lane's segment; q only grows, so i only grows
+            for (int32_t q0 = q_begin; q0 < q_end; q0 += 64) {
+                int32_t q = q0 + lane;
+                bool hit = false;
+                int32_t pa = 0, pb = 0, pc = 0;
+                if (q < q_end) {
+                    int32_t lo = i, hi = d;
+                    while (lo < hi) {
+                        int32_t mid = (lo + hi) >> 1;
+                        if (PRE[mid + 1] <= q) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    i = lo;
+                    const int32_t p = VO[i] + (q - PRE[i]);
+                    const int32_t x = oadj[p];
+                    int32_t a = i + 1, c = d; // x > v_i, so it can only sit after i
+                    while (a < c) {
+                        int32_t mid = (a + c) >> 1;
+                        if (NU[mid] < x) a = mid + 1;
+                        else c = mid;
+                    }
+                    hit = a < d && NU[a] == x;
+                    pa = b + i;
+                    pb = b + a;
+                    pc = p;
+                }
+                sink.hit(hit, pa, pb, pc);
+            }
+            wave_sync(); // the next item overwrites this wave's LDS
+        } else if (d > CAP) {
+            // long rows (only for orientations without the degeneracy bound): one
+            // item per vertex, the same probes against N+(u) in global memory
+            for (int32_t i = 0; i < d; i++) {
+                const int32_t v = oadj[b + i];
+                const int32_t vb = ooff[v], ve = ooff[v + 1];
+                for (int32_t p0 = vb; p0 < ve; p0 += 64) {
+                    const int32_t p = p0 + lane;
+                    bool hit = false;
+                    int32_t a = i + 1;
+                    if (p < ve) {
+                        const int32_t x = oadj[p];
+                        int32_t c = d;
+                        while (a < c) {
+                            int32_t mid = (a + c) >> 1;
+                            if (oadj[b + mid] < x) a = mid + 1;
+                            else c = mid;
+                        }
+                        hit = a < d && oadj[b + a] == x;
+                    }
+                    sink.hit(hit, b + i, b + a, p);
+                }
+            }
+        }
+        sink.end(it);
+    }
+}
+
+// cached triangle list: the same filter, one wavefront per item
+template <int VAR>
+__global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict__ base, const int32_t *__restrict__ tri,
+                                                       int32_t NI, FilterSink<VAR> sink) {
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
+        const int64_t b = base[it], e = base[it + 1];
+        sink.begin(it);
+        for (int64_t p0 = b; p0 < e; p0 += 64) {
+            int64_t p = p0 + lane;
+            bool valid = p < e;
+            sink.hit(valid, valid ? tri[3 * p] : 0, valid ? tri[3 * p + 1] : 0, valid ? tri[3 * p + 2] : 0);
+        }
+        sink.end(it);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a.6: temporal tests over the surviving runs, flat chunks of IPT tests
+// ---------------------------------------------------------------------------
 template <int VAR, class Op>
-__global__ __launch_bounds__(BLK) void k_temporal(const uint32_t *__restrict__ tri, const int64_t *__restrict__ woff,
-                                                  int64_t T, const int32_t *__restrict__ soff,
-                                                  const int32_t *__restrict__ smid, const int64_t *__restrict__ ts,
-                                                  Op op) {
-    const int64_t total = woff[T];
+__global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wbase, int32_t NI,
+                                                  const int64_t *__restrict__ base, const int32_t *__restrict__ su,
+                                                  const int32_t *__restrict__ sv, const int64_t *__restrict__ sw,
+                                                  const EdgeRec *__restrict__ rec, const int64_t *__restrict__ ts,
+                                                  int64_t dmax, Op op) {
+    const int64_t total = wbase[NI];
     const int64_t nchunks = (total + IPT - 1) / IPT;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
         int64_t k = c * IPT;
-        int64_t k1 = k + IPT < total ? k + IPT : total;
-        int64_t a = 0, b = T;
-        while (a < b) {
-            int64_t mid = (a + b) >> 1;
-            if (woff[mid] <= k) a = mid + 1;
-            else b = mid;
-        }
-        int64_t tau = a - 1;
-        int64_t r = k - woff[tau];
-        while (k < k1 && tau < T) {
-            TriLists L = load_tri(tri, tau, soff, smid);
-            if (chunk_list<VAR, 0, 1>(L, ts, r, k, k1, op) && chunk_list<VAR, 1, 0>(L, ts, r, k, k1, op) &&
-                chunk_list<VAR, 0, 2>(L, ts, r, k, k1, op) && chunk_list<VAR, 2, 0>(L, ts, r, k, k1, op) &&
-                chunk_list<VAR, 1, 2>(L, ts, r, k, k1, op))
-                chunk_list<VAR, 2, 1>(L, ts, r, k, k1, op);
-            tau++;
-            r = 0;
-        }
-    }
-}
-
-// a.5: wedges (u; v, w) with v < w in N+(u), closing probe w in N+(v) by a
-// forward-moving binary search; writes the triangle at its precomputed slot
-// and, if VAR >= 0, the triangle's test count for that predicate code.
-template <int VAR>
-__global__ __launch_bounds__(BLK) void k_wedges(const int32_t *__restrict__ osrc, const int32_t *__restrict__ oadj,
-                                                const int32_t *__restrict__ ooff, const uint32_t *__restrict__ oeid,
-                                                const int64_t *__restrict__ tri_off, int32_t S,
-                                                const int32_t *__restrict__ soff, const int32_t *__restrict__ smid,
-                                                uint32_t *__restrict__ tri, int64_t *__restrict__ work) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= S) return;
-    int32_t u = osrc[j], v = oadj[j];
-    int32_t end = ooff[u + 1];
-    int32_t lo = ooff[v], hi = ooff[v + 1];
-    int64_t slot = tri_off[j];
-    const uint32_t r0 = oeid[j];
-    for (int32_t j2 = (int32_t)j + 1; j2 < end && lo < hi; j2++) {
-        int32_t w = oadj[j2];
-        int32_t a = lo, b = hi;
-        while (a < b) {
-            int32_t mid = (a + b) >> 1;
-            if (oadj[mid] < w) a = mid + 1;
-            else b = mid;
-        }
-        lo = a;
-        if (a < hi && oadj[a] == w) {
-            uint32_t r1 = oeid[j2], r2 = oeid[a];
-            tri[3 * slot] = r0;
-            tri[3 * slot + 1] = r1;
-            tri[3 * slot + 2] = r2;
-            if constexpr (VAR >= 0) {
-                TriLists L;
-                edge_spans(r0, soff, smid, L.d01, L.d10);
-                edge_spans(r1, soff, smid, L.d02, L.d20);
-                edge_spans(r2, soff, smid, L.d12, L.d21);
-                work[slot] = tri_work<VAR>(L);
+        const int64_t k1 = k + IPT < total ? k + IPT : total;
+        while (k < k1) {
+            const int64_t k_start = k;
+            // the item whose tests contain k, then the survivor inside it
+            int64_t a = 0, b = NI;
+            while (a < b) {
+                int64_t mid = (a + b) >> 1;
+                if (wbase[mid + 1] <= k) a = mid + 1;
+                else b = mid;
             }
-            slot++;
-            lo = a + 1;
+            const int64_t u = a;
+            int64_t r = k - wbase[u];
+            const int64_t s0 = base[u];
+            const int32_t ns = su[u];
+            if (ns <= 0) break; // cannot happen when the offsets are consistent
+            int32_t lo = 0, hi = ns - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (sw[s0 + mid] <= r) lo = mid;
+                else hi = mid - 1;
+            }
+            r -= sw[s0 + lo];
+            for (int32_t s = lo; s < ns && k < k1; s++) {
+                const int64_t p = s0 + s;
+                TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
+                if (chunk_run<VAR, 0, 1>(L, dmax, ts, r, k, k1, op) && chunk_run<VAR, 1, 0>(L, dmax, ts, r, k, k1, op) &&
+                    chunk_run<VAR, 0, 2>(L, dmax, ts, r, k, k1, op) && chunk_run<VAR, 2, 0>(L, dmax, ts, r, k, k1, op) &&
+                    chunk_run<VAR, 1, 2>(L, dmax, ts, r, k, k1, op))
+                    chunk_run<VAR, 2, 1>(L, dmax, ts, r, k, k1, op);
+                r = 0;
+            }
+            if (k == k_start) break; // every survivor has tests, so this never triggers
         }
     }
 }
 
-template <int VAR>
-__global__ void k_tri_work(const uint32_t *__restrict__ tri, int64_t T, const int32_t *__restrict__ soff,
-                           const int32_t *__restrict__ smid, int64_t *__restrict__ work) {
-    int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tau >= T) return;
-    work[tau] = tri_work<VAR>(load_tri(tri, tau, soff, smid));
+// ---------------------------------------------------------------------------
+// index helpers
+// ---------------------------------------------------------------------------
+__global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const int32_t *__restrict__ soff,
+                            const int32_t *__restrict__ smid, const int64_t *__restrict__ ts, int32_t S,
+                            EdgeRec *__restrict__ rec) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S) return;
+    uint32_t id = oeid[p];
+    int32_t e = (int32_t)(id & 0x7fffffffu);
+    int32_t a = soff[e], mid = smid[e], b = soff[e + 1];
+    int32_t fs, fn, bs, bn;
+    if (id >> 31) {
+        fs = a; fn = mid - a; bs = mid; bn = b - mid;
+    } else {
+        fs = mid; fn = b - mid; bs = a; bn = mid - a;
+    }
+    EdgeRec r;
+    r.fs = fs;
+    r.fn = fn;
+    r.bs = bs;
+    r.bn = bn;
+    r.ftmin = fn ? ts[fs] : 0;
+    r.ftmax = fn ? ts[fs + fn - 1] : 0;
+    r.btmin = bn ? ts[bs] : 0;
+    r.btmax = bn ? ts[bs + bn - 1] : 0;
+    r.sid = e;
+    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    rec[p] = r;
+}
+
+// closing probes of vertex u: sum over v in N+(u) of |N+(v)|; the vertex gets
+// ceil(probes / CHUNK) enumeration items (one if its row is too long for LDS,
+// none if it has fewer than two out-neighbours)
+__global__ void k_probes(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj, int32_t n,
+                         int32_t *__restrict__ items, unsigned long long *total) {
+    __shared__ unsigned long long s_sum[BLK / 64];
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long pr = 0;
+    if (u < n) {
+        int32_t b = ooff[u], d = ooff[u + 1] - b;
+        for (int32_t i = 0; i < d; i++) {
+            int32_t v = oadj[b + i];
+            pr += (unsigned long long)(ooff[v + 1] - ooff[v]);
+        }
+        int32_t k = 0;
+        if (d >= 2 && pr > 0) k = d > CAP ? 1 : (int32_t)((pr + CHUNK - 1) / CHUNK);
+        items[u] = k;
+    }
+    for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
+    if (lane_id() == 0) s_sum[threadIdx.x >> 6] = pr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < BLK / 64; i++) pr += s_sum[i];
+        if (pr) atomicAdd(total, pr);
+    }
+}
+
+__global__ void k_item_owner(const int32_t *__restrict__ item_off, int32_t n, int32_t *__restrict__ item_u) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    for (int32_t it = item_off[u]; it < item_off[u + 1]; it++) item_u[it] = (int32_t)u;
 }
 
 // ---------------------------------------------------------------------------
@@ -313,6 +586,7 @@ struct ThreshArgs {
 };
 
 __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
+    __shared__ unsigned long long s_tot[BLK / 64];
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool in = k < A.m;
     int64_t key = -1;
@@ -337,7 +611,6 @@ __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
     bool tail = lane == 63 || next != key;
     unsigned long long heads = __ballot(head && in);
     unsigned long long certs = __ballot(cert);
-    if (lane == 0 && certs) atomicAdd(A.total, (unsigned long long)__popcll(certs));
     if (in && tail) {
         unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
         unsigned long long h = heads & upto;
@@ -345,6 +618,13 @@ __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
         unsigned long long seg = upto & ~((1ull << start) - 1ull);
         int c = __popcll(certs & seg);
         if (c) atomicAdd(&A.ncert[key], (uint32_t)c);
+    }
+    if (lane == 0) s_tot[threadIdx.x >> 6] = (unsigned long long)__popcll(certs);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < BLK / 64; i++) t += s_tot[i];
+        if (t) atomicAdd(A.total, t);
     }
 }
 
@@ -404,55 +684,66 @@ double ev_ms(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-// Triangles (cached or enumerated now) and per-triangle test counts for one
-// predicate code, then exclusive offsets in ws.work.  Returns the triangle list.
-const uint32_t *prepare_work(const Index &ix, int variant, Workspace &ws, hipStream_t s, bool reuse_tri,
-                             bool *enumerated) {
-    const int64_t T = ix.T;
-    ws.work.ensure(8 * ((size_t)T + 1));
-    ws.aux.ensure(8 * ((size_t)T + 1));
-    const uint32_t *tri;
-    *enumerated = false;
-    if (ix.tri_cached) {
-        tri = ix.tri.as<uint32_t>();
-        dispatch_variant(variant, [&](auto V) {
-            k_tri_work<decltype(V)::value><<<grid_for(T, BLK, 1ll << 30), BLK, 0, s>>>(
-                tri, T, ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), ws.work.as<int64_t>());
-        });
-    } else if (reuse_tri) {
-        tri = ws.tri.as<uint32_t>();
-        dispatch_variant(variant, [&](auto V) {
-            k_tri_work<decltype(V)::value><<<grid_for(T, BLK, 1ll << 30), BLK, 0, s>>>(
-                tri, T, ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), ws.work.as<int64_t>());
-        });
-    } else {
-        ws.tri.ensure(12 * (size_t)T);
-        tri = ws.tri.as<uint32_t>();
-        dispatch_variant(variant, [&](auto V) {
-            k_wedges<decltype(V)::value><<<grid_for(ix.S, BLK, 1ll << 30), BLK, 0, s>>>(
-                ix.osrc.as<int32_t>(), ix.oadj.as<int32_t>(), ix.ooff.as<int32_t>(), ix.oeid.as<uint32_t>(),
-                ix.tri_off.as<int64_t>(), ix.S, ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), ws.tri.as<uint32_t>(),
-                ws.work.as<int64_t>());
-        });
-        *enumerated = true;
-    }
+unsigned enum_grid(int32_t n) {
+    int64_t g = ((int64_t)n + WPB - 1) / WPB;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, ENUM_BLOCKS));
+}
+
+// a.5 for one predicate code and window bound: surviving triangles per lowest
+// vertex, then exclusive test offsets per vertex in ws.wbase (total at [n]).
+void find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s) {
+    const int32_t NI = ix.NI;
+    ws.sv.ensure(12 * (size_t)ix.T + 12);
+    ws.sw.ensure(8 * (size_t)ix.T + 8);
+    ws.su.ensure(4 * (size_t)NI + 4);
+    ws.wu.ensure(8 * ((size_t)NI + 1));
+    ws.wbase.ensure(8 * ((size_t)NI + 1));
+    dispatch_variant(variant, [&](auto V) {
+        FilterSink<decltype(V)::value> sink;
+        sink.base = ix.tri_base.as<int64_t>();
+        sink.rec = ix.rec.as<EdgeRec>();
+        sink.dmax = dmax;
+        sink.sv = ws.sv.as<int32_t>();
+        sink.sw = ws.sw.as<int64_t>();
+        sink.su = ws.su.as<int32_t>();
+        sink.wu = ws.wu.as<int64_t>();
+        if (ix.tri_cached)
+            k_filter_cached<decltype(V)::value><<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(),
+                                                                              ix.tri.as<int32_t>(), NI, sink);
+        else
+            k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
+                                                     ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), NI, sink);
+    });
     FOLTY_LAUNCHED();
-    // work[T] = 0 so that the exclusive scan leaves the total in woff[T]
-    FOLTY_HIP(hipMemsetAsync(ws.work.as<int64_t>() + T, 0, 8, s));
-    size_t need = exclusive_scan_i64(nullptr, 0, ws.work.as<int64_t>(), ws.aux.as<int64_t>(), T + 1, s);
+    // wu[NI] = 0 so that the exclusive scan leaves the total in wbase[NI]
+    k_fill<int64_t><<<1, 1, 0, s>>>(ws.wu.as<int64_t>() + NI, (int64_t)0, 1);
+    size_t need = exclusive_scan_i64(nullptr, 0, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
     ws.cub.ensure(need);
-    exclusive_scan_i64(ws.cub.p, need, ws.work.as<int64_t>(), ws.aux.as<int64_t>(), T + 1, s);
-    return tri;
+    exclusive_scan_i64(ws.cub.p, need, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
 }
 
 template <class Op>
-void launch_temporal(const Index &ix, int variant, const uint32_t *tri, const int64_t *woff, const Op &op,
-                     hipStream_t s) {
+void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, hipStream_t s) {
     dispatch_variant(variant, [&](auto V) {
         k_temporal<decltype(V)::value, Op><<<PERSIST_BLOCKS, BLK, 0, s>>>(
-            tri, woff, ix.T, ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), ix.ts.as<int64_t>(), op);
+            ws.wbase.as<int64_t>(), ix.NI, ix.tri_base.as<int64_t>(), ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
+            ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(), dmax, op);
     });
     FOLTY_LAUNCHED();
+}
+
+void ensure_tcnt(Index &ix, hipStream_t s) {
+    if (ix.tcnt_ready) return;
+    ix.tcnt.ensure(4 * (size_t)ix.S + 4);
+    if (ix.S > 0) {
+        k_fill<int32_t><<<grid_for(ix.S, BLK, 1ll << 30), BLK, 0, s>>>(ix.tcnt.as<int32_t>(), 0, ix.S);
+        FOLTY_LAUNCHED();
+        TcntSink sink{ix.oeid.as<uint32_t>(), ix.tcnt.as<int32_t>()};
+        k_tri_enum<<<enum_grid(ix.NI), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
+                                                    ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), ix.NI, sink);
+        FOLTY_LAUNCHED();
+    }
+    ix.tcnt_ready = true;
 }
 
 // threshold + pairs for one query given device counts (sorted edge order)
@@ -462,12 +753,12 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
     const int32_t S = ix.S, m = ix.m;
     ws.ncert.ensure(8 * (size_t)S + 8);
     ws.scal.ensure(64);
-    FOLTY_HIP(hipMemsetAsync(ws.scal.p, 0, 64, s));
+    k_fill<unsigned long long><<<1, 8, 0, s>>>(ws.scal.as<unsigned long long>(), 0ull, 8);
     if (S > 0) {
         k_fill<uint32_t><<<grid_for(2 * (int64_t)S, BLK, 1ll << 30), BLK, 0, s>>>(ws.ncert.as<uint32_t>(), 0u,
                                                                                2 * (int64_t)S);
-        FOLTY_LAUNCHED();
     }
+    FOLTY_LAUNCHED();
     unsigned long long *total = ws.scal.as<unsigned long long>();
     int32_t *np = ws.scal.as<int32_t>() + 4;
     if (m > 0) {
@@ -545,12 +836,65 @@ void keep_counts(const Graph *g, const uint32_t *count, Result *res, hipStream_t
 
 } // namespace
 
-void enumerate_triangles(const Index &ix, uint32_t *tri, hipStream_t s) {
-    if (ix.S == 0 || ix.T == 0) return;
-    k_wedges<-1><<<grid_for(ix.S, BLK, 1ll << 30), BLK, 0, s>>>(
-        ix.osrc.as<int32_t>(), ix.oadj.as<int32_t>(), ix.ooff.as<int32_t>(), ix.oeid.as<uint32_t>(),
-        ix.tri_off.as<int64_t>(), ix.S, ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), tri, nullptr);
+void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
+    const int32_t n = ix.n, S = ix.S;
+    ix.rec.ensure(sizeof(EdgeRec) * ((size_t)S + 1));
+    ix.item_off.ensure(4 * ((size_t)n + 1));
+    ix.tcnt_ready = false;
+    DevBuf items, probes;
+    items.ensure(4 * ((size_t)n + 1));
+    probes.ensure(8);
+    k_fill<unsigned long long><<<1, 1, 0, s>>>(probes.as<unsigned long long>(), 0ull, 1);
+    k_fill<int32_t><<<1, 1, 0, s>>>(items.as<int32_t>() + n, 0, 1);
     FOLTY_LAUNCHED();
+    if (S > 0) {
+        k_edge_recs<<<grid_for(S, BLK, 1ll << 30), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), ix.soff.as<int32_t>(),
+                                                                ix.smid.as<int32_t>(), ix.ts.as<int64_t>(), S,
+                                                                ix.rec.as<EdgeRec>());
+        FOLTY_LAUNCHED();
+    }
+    k_probes<<<grid_for(n, BLK, 1ll << 30), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), n,
+                                                          items.as<int32_t>(), probes.as<unsigned long long>());
+    FOLTY_LAUNCHED();
+    {
+        size_t need = exclusive_scan_i32(nullptr, 0, items.as<int32_t>(), ix.item_off.as<int32_t>(), (int64_t)n + 1, s);
+        cub.ensure(need);
+        exclusive_scan_i32(cub.p, need, items.as<int32_t>(), ix.item_off.as<int32_t>(), (int64_t)n + 1, s);
+    }
+    int64_t h[2] = {0, 0};
+    int32_t ni = 0;
+    FOLTY_HIP(hipMemcpyAsync(&ni, ix.item_off.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(&h[1], probes.p, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    ix.NI = ni;
+    ix.probes = h[1];
+    ix.item_u.ensure(4 * (size_t)ni + 4);
+    ix.tri_base.ensure(8 * ((size_t)ni + 1));
+    k_item_owner<<<grid_for(n, BLK, 1ll << 30), BLK, 0, s>>>(ix.item_off.as<int32_t>(), n, ix.item_u.as<int32_t>());
+    FOLTY_LAUNCHED();
+    DevBuf tri_it;
+    tri_it.ensure(4 * ((size_t)ni + 1));
+    k_fill<int32_t><<<1, 1, 0, s>>>(tri_it.as<int32_t>() + ni, 0, 1);
+    CountSink cs{tri_it.as<int32_t>(), 0};
+    k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), ix.item_u.as<int32_t>(),
+                                             ix.item_off.as<int32_t>(), ni, cs);
+    FOLTY_LAUNCHED();
+    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
+    cub.ensure(need);
+    exclusive_scan_i32_to_i64(cub.p, need, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
+    FOLTY_HIP(hipMemcpyAsync(&h[0], ix.tri_base.as<int64_t>() + ni, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    ix.T = h[0];
+    ix.tri_cached = false;
+    ix.tri.release();
+    if (cache && ix.T > 0) {
+        ix.tri.ensure(12 * (size_t)ix.T);
+        CacheSink sink{ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), 0};
+        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), ix.item_u.as<int32_t>(),
+                                                 ix.item_off.as<int32_t>(), ni, sink);
+        FOLTY_LAUNCHED();
+        ix.tri_cached = true;
+    }
 }
 
 void check_query(const Graph *g, const folty_query &q) {
@@ -569,8 +913,9 @@ void check_query(const Graph *g, const folty_query &q) {
 Result *run_query(Graph *g, const folty_query &q, Workspace &ws) {
     check_query(g, q);
     if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
-    const Index &ix = g->ix;
+    Index &ix = g->ix;
     hipStream_t s = g->stream;
+    if (q.universe == FOLTY_UNIVERSE_COMMON) ensure_tcnt(ix, s);
     std::unique_ptr<Result> res(new Result());
     ws.ensure_events();
     FOLTY_HIP(hipEventRecord(ws.ev[0], s));
@@ -582,12 +927,11 @@ Result *run_query(Graph *g, const folty_query &q, Workspace &ws) {
     }
     int64_t tests = 0;
     if (ix.T > 0) {
-        bool enumerated = false;
-        const uint32_t *tri = prepare_work(ix, q.variant, ws, s, false, &enumerated);
+        find_survivors(ix, q.variant, q.delta, ws, s);
         FOLTY_HIP(hipEventRecord(ws.ev[1], s));
         DirectOp op{q.delta, count};
-        launch_temporal(ix, q.variant, tri, ws.aux.as<int64_t>(), op, s);
-        FOLTY_HIP(hipMemcpyAsync(&res->stats.tests, ws.aux.as<int64_t>() + ix.T, 8, hipMemcpyDeviceToHost, s));
+        launch_temporal(ix, q.variant, q.delta, ws, op, s);
+        FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
     } else {
         FOLTY_HIP(hipEventRecord(ws.ev[1], s));
     }
@@ -596,7 +940,6 @@ Result *run_query(Graph *g, const folty_query &q, Workspace &ws) {
     FOLTY_HIP(hipEventRecord(ws.ev[3], s));
     if (!(q.flags & FOLTY_QUERY_NO_COUNTS)) keep_counts(g, count, res.get(), s);
     FOLTY_HIP(hipStreamSynchronize(s));
-    tests = res->stats.tests;
     fill_stats_from_index(ix, &res->stats);
     res->stats.tests = tests;
     res->stats.n_pairs = (int64_t)res->u.size();
@@ -614,14 +957,18 @@ void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **
     if (nq < 0) fail(FOLTY_EINVAL, "nq < 0");
     for (int i = 0; i < nq; i++) check_query(g, qs[i]);
     if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
-    const Index &ix = g->ix;
+    Index &ix = g->ix;
     hipStream_t s = g->stream;
     std::map<int, std::vector<int>> by_var;
-    for (int i = 0; i < nq; i++) by_var[qs[i].variant].push_back(i);
+    bool need_tcnt = false;
+    for (int i = 0; i < nq; i++) {
+        by_var[qs[i].variant].push_back(i);
+        need_tcnt = need_tcnt || qs[i].universe == FOLTY_UNIVERSE_COMMON;
+    }
+    if (need_tcnt) ensure_tcnt(ix, s);
     std::vector<std::unique_ptr<Result>> res(nq);
     for (int i = 0; i < nq; i++) res[i].reset(new Result());
     ws.ensure_events();
-    bool have_tri = false;
     for (auto &kv : by_var) {
         int variant = kv.first;
         std::vector<int64_t> lv;
@@ -629,9 +976,9 @@ void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **
         std::sort(lv.begin(), lv.end());
         lv.erase(std::unique(lv.begin(), lv.end()), lv.end());
         const int nl = (int)lv.size();
+        const int64_t dmax = lv.back();
         FOLTY_HIP(hipEventRecord(ws.ev[0], s));
         ws.hist.ensure(4 * (size_t)nl * (size_t)ix.m + 4);
-        ws.scal.ensure(64);
         DevBuf lvd;
         lvd.ensure(8 * (size_t)nl);
         FOLTY_HIP(hipMemcpyAsync(lvd.p, lv.data(), 8 * (size_t)nl, hipMemcpyHostToDevice, s));
@@ -642,14 +989,12 @@ void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **
         }
         int64_t tests = 0;
         if (ix.T > 0) {
-            bool enumerated = false;
-            const uint32_t *tri = prepare_work(ix, variant, ws, s, have_tri, &enumerated);
-            have_tri = have_tri || enumerated;
+            find_survivors(ix, variant, dmax, ws, s);
             PoolOp op{lvd.as<int64_t>(), nl, ix.m, ws.hist.as<uint32_t>()};
-            launch_temporal(ix, variant, tri, ws.aux.as<int64_t>(), op, s);
+            launch_temporal(ix, variant, dmax, ws, op, s);
             k_hist_prefix<<<grid_for(ix.m, BLK, 1ll << 30), BLK, 0, s>>>(ws.hist.as<uint32_t>(), nl, ix.m);
             FOLTY_LAUNCHED();
-            FOLTY_HIP(hipMemcpyAsync(&tests, ws.aux.as<int64_t>() + ix.T, 8, hipMemcpyDeviceToHost, s));
+            FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
         }
         FOLTY_HIP(hipEventRecord(ws.ev[1], s));
         FOLTY_HIP(hipStreamSynchronize(s));
@@ -682,7 +1027,10 @@ void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, R
         if (!gs[i]) fail(FOLTY_EINVAL, "graph %d is null", i);
         check_query(gs[i], qs[i]);
     }
-    for (int i = 0; i < ng; i++) res[i].reset(run_query(gs[i], qs[i], ws));
+    for (int i = 0; i < ng; i++) {
+        StreamScope sc(gs[i]->stream);
+        res[i].reset(run_query(gs[i], qs[i], ws));
+    }
     for (int i = 0; i < ng; i++) outs[i] = res[i].release();
 }
 
@@ -699,6 +1047,8 @@ void fill_stats_from_index(const Index &ix, folty_stats *s) {
     s->triangles = ix.T;
     s->max_multiplicity = ix.sigma_max;
     s->peel_rounds = ix.peel_rounds;
+    s->closing_probes = ix.probes;
+    s->enum_items = ix.NI;
     s->build_ms = ix.build_ms;
 }
 

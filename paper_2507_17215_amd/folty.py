@@ -30,6 +30,7 @@ EXPORTS = (
     "folty_run_fol_query_ws", "folty_run_batch", "folty_run_multi", "folty_result_pairs",
     "folty_result_counts", "folty_result_stats", "folty_result_free", "folty_graph_stats",
     "folty_graph_vertex_array", "folty_graph_device_bytes", "folty_graph_free",
+    "folty_release_cached_memory",
 )
 
 
@@ -54,7 +55,8 @@ class Query(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in (
         "n", "m_input", "m", "self_loops", "static_edges", "directed_pairs", "max_core",
-        "max_out_degree", "wedges", "triangles", "max_multiplicity", "peel_rounds", "tests",
+        "max_out_degree", "wedges", "triangles", "max_multiplicity", "peel_rounds",
+        "closing_probes", "enum_items", "tests",
         "n_pairs", "n_certificates")] + [(f, ctypes.c_double) for f in (
             "build_ms", "wedge_ms", "temporal_ms", "threshold_ms", "query_ms")]
 
@@ -101,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.folty_graph_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.folty_graph_vertex_array.argtypes = [P, I32, P]
     lib.folty_graph_device_bytes.argtypes = [P, ctypes.POINTER(I64)]
+    lib.folty_release_cached_memory.argtypes = [ctypes.POINTER(I64)]
     lib.folty_graph_free.argtypes = [P]
     lib.folty_graph_free.restype = None
     for name in EXPORTS:
@@ -313,6 +316,13 @@ def run_multi(graphs, queries) -> list:
     outs = (ctypes.c_void_p * n)()
     _check(load_library().folty_run_multi(gs, qs, n, outs))
     return [Result(ctypes.c_void_p(o)) for o in outs]
+
+
+def release_cached_memory() -> int:
+    """Hand the library's cached device blocks back to the driver; returns bytes."""
+    b = ctypes.c_int64()
+    _check(load_library().folty_release_cached_memory(ctypes.byref(b)))
+    return b.value
 
 
 def version() -> str:
