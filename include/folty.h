@@ -121,6 +121,7 @@ typedef struct {
     int64_t peel_rounds;      /* rounds of the min-degree peeling */
     int64_t closing_probes;   /* membership probes of the enumeration: sum over (u,v) of |N+(v)| */
     int64_t enum_items;       /* work items the enumeration is split into */
+    int64_t batch_size;       /* server: requests that shared this request's pass */
     /* query only */
     int64_t tests;            /* temporal tests: sum over (triangle, list E_{a,b} with both
                                  closing lists non-empty) of |E_{a,b}| */
@@ -131,6 +132,8 @@ typedef struct {
     double temporal_ms;       /* device time of the temporal tests */
     double threshold_ms;      /* device time of threshold, pair reduction and compaction */
     double query_ms;          /* device time of the whole query */
+    double latency_ms;        /* server: submit to result ready on the host */
+    double queue_ms;          /* server: submit to start of its pass */
 } folty_stats;
 
 /* Message for the last failed call on this thread ("" if none).  Valid until the
@@ -194,6 +197,71 @@ int folty_run_batch(folty_graph *g, const folty_query *qs, int32_t nq, folty_res
  */
 int folty_run_multi(folty_graph *const *gs, const folty_query *qs, int32_t ng,
                     folty_result **outs);
+
+/*
+ * Batched plans: a fixed set of queries over a fixed set of resident graphs,
+ * prepared once and run many times.  query_graph[i] is the graph (index into
+ * graphs) that qs[i] runs on.  A run executes one launch sequence for all
+ * queries (queries sharing a graph and a predicate code share one pass; see
+ * folty_run_batch); its launches are captured in a HIP graph on the first run
+ * and replayed afterwards.  The graphs must stay alive and unchanged while the
+ * plan exists.  One thread at a time may run a given plan.
+ */
+typedef struct folty_plan folty_plan;
+typedef struct {
+    int32_t n_jobs;          /* (graph, predicate code) passes */
+    int32_t n_queries;
+    int64_t items;           /* enumeration items over all jobs */
+    int64_t tests;           /* temporal tests that survived the time-range filter */
+    int32_t tests_per_chunk; /* temporal launch shape chosen by timing candidates */
+    int32_t temporal_blocks;
+    int32_t captured;        /* 1 if runs replay a captured HIP graph */
+    int32_t reserved;
+    double last_run_ms;      /* device time of the last run (launch sequence to sorted pairs) */
+} folty_plan_info;
+
+int folty_plan_create(folty_graph *const *graphs, int32_t n_graphs, const folty_query *qs,
+                      const int32_t *query_graph, int32_t nq, folty_plan **out);
+int folty_plan_run(folty_plan *p, folty_result **outs);
+int folty_plan_get_info(const folty_plan *p, folty_plan_info *info);
+void folty_plan_free(folty_plan *p);
+
+/*
+ * Query server (continuous batching).  Worker threads, each with its own HIP
+ * stream, take the oldest waiting request together with the other waiting
+ * requests on the same graph (up to max_batch) and run them as one pass, so
+ * requests that arrive while others run join the next pass.  A request is
+ * started only when its device memory (estimated from its graph's index sizes)
+ * fits in the budget beside the requests in flight; requests whose estimate
+ * exceeds the whole budget are rejected at submit with FOLTY_ENOMEM.
+ *   workers           concurrent passes (streams); 0 = 4
+ *   max_batch         requests per pass; 0 = 16
+ *   hbm_budget_bytes  0 = the FOLTY_HBM_BUDGET environment variable (bytes) if
+ *                     set, else 80% of the free device memory at creation
+ * Graphs must outlive the requests that name them.  Results are taken with
+ * folty_server_poll (FOLTY_EBUSY while not ready) or folty_server_wait; each
+ * ticket can be taken once.  folty_server_destroy finishes the queued requests
+ * first.  All calls are thread-safe.
+ */
+typedef struct folty_server folty_server;
+typedef struct {
+    int32_t workers;
+    int32_t max_batch;
+    int64_t hbm_budget_bytes;
+} folty_server_opts;
+typedef struct {
+    int64_t submitted, completed, rejected, queued;
+    int64_t batches;          /* passes that served more than one request */
+    int64_t batched_requests; /* requests served in such passes */
+    int64_t budget_bytes, in_use_bytes, peak_in_use_bytes;
+} folty_server_info;
+
+int folty_server_create(const folty_server_opts *opts, folty_server **out);
+int folty_server_submit(folty_server *s, folty_graph *g, const folty_query *q, int64_t *ticket);
+int folty_server_poll(folty_server *s, int64_t ticket, folty_result **out);
+int folty_server_wait(folty_server *s, int64_t ticket, folty_result **out);
+int folty_server_get_info(folty_server *s, folty_server_info *info);
+void folty_server_destroy(folty_server *s);
 
 /*
  * Solution pairs of a result, sorted by (u, v), with the number of

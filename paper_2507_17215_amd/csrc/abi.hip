@@ -3,6 +3,7 @@
 // return code plus a thread-local message.
 #include <cstdarg>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 
 #include "folty_internal.h"
@@ -15,6 +16,12 @@ struct folty_result {
 };
 struct folty_workspace {
     folty::Workspace ws;
+};
+struct folty_plan {
+    folty::Plan *p;
+};
+struct folty_server {
+    folty::Server *s;
 };
 
 namespace folty {
@@ -150,6 +157,104 @@ int folty_run_multi(folty_graph *const *gs, const folty_query *qs, int32_t ng, f
             outs[i] = h;
         }
     });
+}
+
+int folty_plan_create(folty_graph *const *graphs, int32_t n_graphs, const folty_query *qs,
+                      const int32_t *query_graph, int32_t nq, folty_plan **out) {
+    return guarded([&] {
+        if (!out || !graphs || n_graphs <= 0 || nq < 0 || (nq > 0 && (!qs || !query_graph)))
+            fail(FOLTY_EINVAL, "bad plan arguments");
+        *out = nullptr;
+        std::vector<Graph *> g(n_graphs);
+        for (int i = 0; i < n_graphs; i++) {
+            if (!graphs[i]) fail(FOLTY_EINVAL, "graph %d is null", i);
+            g[i] = &graphs[i]->g;
+        }
+        std::unique_ptr<folty_plan> h(new folty_plan{nullptr});
+        h->p = plan_create(g.data(), n_graphs, qs, query_graph, nq);
+        *out = h.release();
+    });
+}
+
+int folty_plan_run(folty_plan *p, folty_result **outs) {
+    return guarded([&] {
+        if (!p || !p->p || !outs) fail(FOLTY_EINVAL, "null argument");
+        folty_plan_info info{};
+        plan_info(p->p, &info);
+        std::vector<Result *> rs(info.n_queries, nullptr);
+        plan_run(p->p, rs.data());
+        for (int i = 0; i < info.n_queries; i++) {
+            folty_result *h = new folty_result();
+            h->r = std::move(*rs[i]);
+            delete rs[i];
+            outs[i] = h;
+        }
+    });
+}
+
+int folty_plan_get_info(const folty_plan *p, folty_plan_info *info) {
+    return guarded([&] {
+        if (!p || !p->p || !info) fail(FOLTY_EINVAL, "null argument");
+        plan_info(p->p, info);
+    });
+}
+
+void folty_plan_free(folty_plan *p) {
+    if (!p) return;
+    if (p->p) plan_free(p->p);
+    delete p;
+}
+
+int folty_server_create(const folty_server_opts *opts, folty_server **out) {
+    return guarded([&] {
+        if (!out) fail(FOLTY_EINVAL, "out is null");
+        *out = nullptr;
+        folty_server_opts o{};
+        if (opts) o = *opts;
+        if (o.hbm_budget_bytes <= 0) {
+            const char *env = getenv("FOLTY_HBM_BUDGET");
+            if (env && *env) o.hbm_budget_bytes = strtoll(env, nullptr, 10);
+        }
+        std::unique_ptr<folty_server> h(new folty_server{nullptr});
+        h->s = server_create(&o);
+        *out = h.release();
+    });
+}
+
+int folty_server_submit(folty_server *s, folty_graph *g, const folty_query *q, int64_t *ticket) {
+    return guarded([&] {
+        if (!s || !g || !q || !ticket) fail(FOLTY_EINVAL, "null argument");
+        *ticket = server_submit(s->s, &g->g, *q);
+    });
+}
+
+static int server_take_abi(folty_server *s, int64_t ticket, folty_result **out, bool wait) {
+    return guarded([&] {
+        if (!s || !out) fail(FOLTY_EINVAL, "null argument");
+        *out = nullptr;
+        Result *r = server_take(s->s, ticket, wait);
+        folty_result *h = new folty_result();
+        h->r = std::move(*r);
+        delete r;
+        *out = h;
+    });
+}
+
+int folty_server_poll(folty_server *s, int64_t ticket, folty_result **out) { return server_take_abi(s, ticket, out, false); }
+
+int folty_server_wait(folty_server *s, int64_t ticket, folty_result **out) { return server_take_abi(s, ticket, out, true); }
+
+int folty_server_get_info(folty_server *s, folty_server_info *info) {
+    return guarded([&] {
+        if (!s || !info) fail(FOLTY_EINVAL, "null argument");
+        server_info(s->s, info);
+    });
+}
+
+void folty_server_destroy(folty_server *s) {
+    if (!s) return;
+    if (s->s) server_destroy(s->s);
+    delete s;
 }
 
 int folty_result_pairs(const folty_result *r, int64_t *n_pairs, const int32_t **u, const int32_t **v,

@@ -1,0 +1,706 @@
+// Batched queries: many queries over many resident graphs in one fixed launch
+// sequence.
+//
+// Queries sharing a graph and a predicate code form a job.  A job resolves each
+// (temporal edge e, third vertex w) once: by the proof of Theorem 3.1 the
+// greedy pair (first t2 >= t, then first t3 >= t2) gives the smallest window
+// t3 - t, so the job records that window in a histogram over its sorted
+// distinct deltas, and a running sum over the levels yields count[e] for every
+// delta of the job.  theta and the universe only enter the threshold step.
+//
+// One plan runs, whatever the number of queries and graphs:
+//   filter   one grid over the enumeration items of all jobs (wave per item)
+//   scan     one exclusive scan over all items' test counts
+//   temporal one persistent grid over all surviving tests of all jobs
+//   prefix   one grid over the edges of all jobs
+//   threshold, pairs   one grid each over all queries' edges / pair slots
+//   sort     one radix sort of (query, u, v) keys
+// The launches from filter to pairs are captured once in a hipGraph and
+// replayed.  The temporal kernel's chunk size and grid are picked by timing a
+// few candidates on the plan's own work and remembered per workload size.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "tri_device.h"
+
+namespace folty {
+
+namespace {
+
+struct JobDev {
+    const int32_t *ooff, *oadj, *item_u, *item_off, *tri;
+    const int64_t *tri_base, *ts;
+    const EdgeRec *rec;
+    int32_t NI, variant;
+    int64_t dmax;
+    const int64_t *lv;
+    int32_t nl, m;
+    uint32_t *hist; // nl * m
+    int32_t *sv;
+    int64_t *sw;
+    int32_t *su;
+    int64_t *wu; // this job's slice of the concatenated per-item test counts
+};
+
+struct QueryDev {
+    const uint32_t *count; // the job's histogram at the query's level
+    const int32_t *sid, *smid, *slo, *shi, *deg, *tcnt;
+    int32_t m, S;
+    uint32_t num, den;
+    int32_t universe, excl;
+    int64_t p_base; // first slot of this query in the concatenated 2S pair slots
+};
+
+// the largest index i in [0, n) with base[i] <= x (base ascending, base[0] <= x)
+__device__ inline int32_t owner_of(const int64_t *__restrict__ base, int32_t n, int64_t x) {
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__ jobs, int32_t nj,
+                                                      const int64_t *__restrict__ job_item_base, int64_t items) {
+    __shared__ int32_t s_nu[WPB][CAP];
+    __shared__ int32_t s_vo[WPB][CAP];
+    __shared__ int32_t s_pre[WPB][CAP + 1];
+    const int w = threadIdx.x >> 6;
+    for (int64_t g = (int64_t)blockIdx.x * WPB + w; g < items; g += (int64_t)gridDim.x * WPB) {
+        const int32_t j = owner_of(job_item_base, nj, g);
+        const JobDev &J = jobs[j];
+        const int64_t it = g - job_item_base[j];
+        FilterSink<-1> sink;
+        sink.base = J.tri_base;
+        sink.rec = J.rec;
+        sink.dmax = J.dmax;
+        sink.variant = J.variant;
+        sink.sv = J.sv;
+        sink.sw = J.sw;
+        sink.su = J.su;
+        sink.wu = J.wu;
+        if (J.tri) cached_item(J.tri_base, J.tri, it, sink);
+        else enum_item(J.ooff, J.oadj, J.item_u, J.item_off, it, sink, s_nu[w], s_vo[w], s_pre[w]);
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict__ jobs, int32_t nj,
+                                                        const int64_t *__restrict__ job_item_base, int64_t items,
+                                                        const int64_t *__restrict__ wbase, int ipt) {
+    const int64_t total = wbase[items];
+    const int64_t nchunks = (total + ipt - 1) / ipt;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
+        int64_t k = c * ipt;
+        const int64_t k1 = k + ipt < total ? k + ipt : total;
+        while (k < k1) {
+            const int64_t k_start = k;
+            // the global item whose tests contain k, its job, the survivor
+            int64_t a = 0, b = items;
+            while (a < b) {
+                int64_t mid = (a + b) >> 1;
+                if (wbase[mid + 1] <= k) a = mid + 1;
+                else b = mid;
+            }
+            const int64_t g = a;
+            const int32_t j = owner_of(job_item_base, nj, g);
+            const JobDev &J = jobs[j];
+            const int64_t it = g - job_item_base[j];
+            int64_t r = k - wbase[g];
+            const int64_t s0 = J.tri_base[it];
+            const int32_t ns = J.su[it];
+            if (ns <= 0) break; // cannot happen when the offsets are consistent
+            int32_t lo = 0, hi = ns - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (J.sw[s0 + mid] <= r) lo = mid;
+                else hi = mid - 1;
+            }
+            r -= J.sw[s0 + lo];
+            PoolOp op{J.lv, J.nl, J.m, J.hist};
+            for (int32_t s = lo; s < ns && k < k1; s++) {
+                const int64_t p = s0 + s;
+                TriLists L = load_lists(J.rec, J.sv[3 * p], J.sv[3 * p + 1], J.sv[3 * p + 2]);
+                chunk_runs_rt(J.variant, L, J.dmax, J.ts, r, k, k1, op);
+                r = 0;
+            }
+            if (k == k_start) break; // every survivor has tests, so this never triggers
+        }
+    }
+}
+
+// running sums over each job's window levels
+__global__ void k_multi_prefix(const JobDev *__restrict__ jobs, int32_t nj, const int64_t *__restrict__ job_m_base,
+                               int64_t total_m) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total_m; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = owner_of(job_m_base, nj, x);
+        const JobDev &J = jobs[j];
+        const int64_t e = x - job_m_base[j];
+        uint32_t acc = 0;
+        for (int l = 0; l < J.nl; l++) {
+            acc += J.hist[(int64_t)l * J.m + e];
+            J.hist[(int64_t)l * J.m + e] = acc;
+        }
+    }
+}
+
+// segmented count of set flags over runs of equal keys inside the wave: one
+// atomic per run
+__device__ inline void wave_segment_count(int64_t key, bool in, bool flag, uint32_t *target_base) {
+    const int lane = lane_id();
+    int64_t prev = __shfl_up(key, 1);
+    int64_t next = __shfl_down(key, 1);
+    bool head = lane == 0 || prev != key;
+    bool tail = lane == 63 || next != key;
+    unsigned long long heads = __ballot(head && in);
+    unsigned long long flags = __ballot(flag);
+    if (in && tail) {
+        unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        unsigned long long h = heads & upto;
+        int start = 63 - __clzll((long long)h);
+        unsigned long long seg = upto & ~((1ull << start) - 1ull);
+        int c = __popcll(flags & seg);
+        if (c) atomicAdd(&target_base[key], (uint32_t)c);
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_multi_threshold(const QueryDev *__restrict__ qs, int32_t nq,
+                                                         const int64_t *__restrict__ q_e_base, int64_t total_e,
+                                                         uint32_t *__restrict__ ncert, uint32_t *__restrict__ qcert) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_e; x0 += stride) {
+        const int64_t x = x0 + lane_id();
+        const bool in = x < total_e;
+        int64_t key = -1, qkey = -1;
+        bool cert = false;
+        if (in) {
+            const int32_t q = owner_of(q_e_base, nq, x);
+            const QueryDev &Q = qs[q];
+            const int64_t k = x - q_e_base[q];
+            int32_t s = Q.sid[k];
+            int dir = k >= Q.smid[s] ? 1 : 0;
+            int32_t a = dir ? Q.shi[s] : Q.slo[s];
+            int32_t b = dir ? Q.slo[s] : Q.shi[s];
+            int64_t U;
+            if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)Q.deg[b] - Q.excl;
+            else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)Q.deg[a] - Q.excl;
+            else U = Q.tcnt[s];
+            cert = (uint64_t)Q.count[k] * Q.den >= (uint64_t)Q.num * (uint64_t)U;
+            key = Q.p_base + 2 * (int64_t)s + dir;
+            qkey = q;
+        }
+        wave_segment_count(key, in, cert, ncert);
+        wave_segment_count(qkey, in, cert, qcert);
+    }
+}
+
+// pairs with certificates, as (query, u, v) keys for one sort of all queries
+__global__ void k_multi_pairs(const QueryDev *__restrict__ qs, int32_t nq, int64_t total_p,
+                              const uint32_t *__restrict__ ncert, int nbits, uint64_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals, int32_t *__restrict__ npairs) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_p; x0 += stride) {
+        const int64_t x = x0 + lane_id();
+        const bool in = x < total_p;
+        uint32_t c = in ? ncert[x] : 0;
+        int32_t slot = wave_append(npairs, c > 0);
+        if (slot >= 0) {
+            int32_t lo = 0, hi = nq - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (qs[mid].p_base <= x) lo = mid;
+                else hi = mid - 1;
+            }
+            const QueryDev &Q = qs[lo];
+            const int64_t i = x - Q.p_base;
+            const int32_t s = (int32_t)(i >> 1);
+            const int dir = (int)(i & 1);
+            uint64_t a = (uint64_t)(dir ? Q.shi[s] : Q.slo[s]);
+            uint64_t b = (uint64_t)(dir ? Q.slo[s] : Q.shi[s]);
+            keys[slot] = ((uint64_t)lo << (2 * nbits)) | (a << nbits) | b;
+            vals[slot] = c;
+        }
+    }
+}
+
+__global__ void k_scatter_counts(const uint32_t *__restrict__ count, const int32_t *__restrict__ perm, int32_t m,
+                                 uint32_t *__restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) out[perm[k]] = count[k];
+}
+
+double ev_ms2(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    FOLTY_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+}
+
+// temporal-kernel launch shape chosen per workload size (log2 of the test count)
+std::mutex g_tune_mu;
+std::map<int, std::pair<int, int>> g_tune; // bucket -> (ipt, blocks)
+
+} // namespace
+
+struct Plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Graph *> graphs;
+    std::vector<folty_query> queries;
+    std::vector<int32_t> qgraph;
+    // jobs
+    struct Job {
+        int32_t graph;
+        int variant;
+        std::vector<int64_t> levels;
+    };
+    std::vector<Job> jobs;
+    std::vector<int32_t> qjob, qlevel;
+    std::vector<int64_t> job_item_base, job_m_base, q_e_base;
+    int64_t items = 0, total_m = 0, total_e = 0, total_p = 0;
+    int nbits = 0;
+    // device memory
+    DevBuf d_jobs, d_job_item_base, d_job_m_base, d_queries, d_q_e_base;
+    std::vector<DevBuf> hist, lv, sv, sw, su;
+    DevBuf wu, wbase, ncert, qcert, npairs, keys, vals, keys2, vals2, cub;
+    size_t scan_bytes = 0;
+    // launch shape and capture
+    int ipt = 8, tblocks = 4096;
+    bool tuned = false;
+    bool eager = false; // capture refused: launch directly
+    bool oneshot = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[4] = {};
+    double last_ms = 0, last_compute_ms = 0;
+    int64_t last_tests = 0;
+    ~Plan();
+};
+
+Plan::~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        StreamScope sc(stream);
+        hist.clear();
+        lv.clear();
+        sv.clear();
+        sw.clear();
+        su.clear();
+        d_jobs.release();
+        d_job_item_base.release();
+        d_job_m_base.release();
+        d_queries.release();
+        d_q_e_base.release();
+        wu.release();
+        wbase.release();
+        ncert.release();
+        qcert.release();
+        npairs.release();
+        keys.release();
+        vals.release();
+        keys2.release();
+        vals2.release();
+        cub.release();
+        (void)hipStreamDestroy(stream);
+    }
+}
+
+static void enqueue_compute(Plan &P, hipStream_t s) {
+    const int nj = (int)P.jobs.size(), nq = (int)P.queries.size();
+    // clear what accumulates: histograms, survivor counts, certificates
+    for (int j = 0; j < nj; j++) {
+        const Index &ix = P.graphs[P.jobs[j].graph]->ix;
+        int64_t hn = (int64_t)P.jobs[j].levels.size() * ix.m;
+        if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1ll << 20), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
+    }
+    if (P.total_p > 0)
+        k_fill<uint32_t><<<grid_for(P.total_p, BLK, 1ll << 20), BLK, 0, s>>>(P.ncert.as<uint32_t>(), 0u, P.total_p);
+    k_fill<uint32_t><<<grid_for(nq + 1, BLK), BLK, 0, s>>>(P.qcert.as<uint32_t>(), 0u, nq + 1);
+    k_fill<int32_t><<<1, 1, 0, s>>>(P.npairs.as<int32_t>(), 0, 1);
+    k_fill<int64_t><<<1, 1, 0, s>>>(P.wu.as<int64_t>() + P.items, (int64_t)0, 1);
+    FOLTY_LAUNCHED();
+    if (P.items > 0) {
+        unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((P.items + WPB - 1) / WPB, ENUM_BLOCKS));
+        k_multi_filter<<<g, BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj, P.d_job_item_base.as<int64_t>(), P.items);
+        FOLTY_LAUNCHED();
+    }
+    exclusive_scan_i64(P.cub.p, P.scan_bytes, P.wu.as<int64_t>(), P.wbase.as<int64_t>(), P.items + 1, s);
+    if (P.items > 0) {
+        k_multi_temporal<<<P.tblocks, BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj, P.d_job_item_base.as<int64_t>(), P.items,
+                                                   P.wbase.as<int64_t>(), P.ipt);
+        FOLTY_LAUNCHED();
+    }
+    if (P.total_m > 0) {
+        k_multi_prefix<<<grid_for(P.total_m, BLK, 8192), BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj,
+                                                                      P.d_job_m_base.as<int64_t>(), P.total_m);
+        FOLTY_LAUNCHED();
+    }
+    if (P.total_e > 0) {
+        k_multi_threshold<<<grid_for(P.total_e, BLK, 8192), BLK, 0, s>>>(
+            P.d_queries.as<QueryDev>(), nq, P.d_q_e_base.as<int64_t>(), P.total_e, P.ncert.as<uint32_t>(),
+            P.qcert.as<uint32_t>());
+        FOLTY_LAUNCHED();
+    }
+    if (P.total_p > 0) {
+        k_multi_pairs<<<grid_for(P.total_p, BLK, 8192), BLK, 0, s>>>(P.d_queries.as<QueryDev>(), nq, P.total_p,
+                                                                     P.ncert.as<uint32_t>(), P.nbits,
+                                                                     P.keys.as<uint64_t>(), P.vals.as<uint32_t>(),
+                                                                     P.npairs.as<int32_t>());
+        FOLTY_LAUNCHED();
+    }
+}
+
+// time a few temporal launch shapes on the plan's own work (histograms are
+// cleared before each try), keep the fastest
+static void tune(Plan &P) {
+    const int nj = (int)P.jobs.size();
+    hipStream_t s = P.stream;
+    int64_t tests = 0;
+    FOLTY_HIP(hipMemcpyAsync(&tests, P.wbase.as<int64_t>() + P.items, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    P.last_tests = tests;
+    int bucket = 0;
+    while ((1ll << bucket) < tests && bucket < 62) bucket++;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(bucket);
+        if (it != g_tune.end()) {
+            P.ipt = it->second.first;
+            P.tblocks = it->second.second;
+            P.tuned = true;
+            return;
+        }
+    }
+    if (tests < (1 << 20)) { // too little work to measure; the default shape
+        P.tuned = true;
+        return;
+    }
+    const int ipts[] = {4, 8, 16, 32};
+    const int blocks[] = {1024, 2048, 4096, 8192};
+    double best = 1e30;
+    int bi = P.ipt, bb = P.tblocks;
+    for (int ip : ipts)
+        for (int bl : blocks) {
+            for (int j = 0; j < nj; j++) {
+                const Index &ix = P.graphs[P.jobs[j].graph]->ix;
+                int64_t hn = (int64_t)P.jobs[j].levels.size() * ix.m;
+                if (hn > 0)
+                    k_fill<uint32_t><<<grid_for(hn, BLK, 1ll << 20), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
+            }
+            FOLTY_HIP(hipEventRecord(P.ev[1], s));
+            k_multi_temporal<<<bl, BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj, P.d_job_item_base.as<int64_t>(), P.items,
+                                                P.wbase.as<int64_t>(), ip);
+            FOLTY_LAUNCHED();
+            FOLTY_HIP(hipEventRecord(P.ev[2], s));
+            FOLTY_HIP(hipEventSynchronize(P.ev[2]));
+            double ms = ev_ms2(P.ev[1], P.ev[2]);
+            if (ms < best) {
+                best = ms;
+                bi = ip;
+                bb = bl;
+            }
+        }
+    P.ipt = bi;
+    P.tblocks = bb;
+    P.tuned = true;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[bucket] = {bi, bb};
+}
+
+Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t *qgraph, int nq, bool oneshot) {
+    if (ng <= 0 || nq < 0) fail(FOLTY_EINVAL, "a plan needs at least one graph");
+    for (int i = 0; i < ng; i++)
+        if (!gs[i]) fail(FOLTY_EINVAL, "graph %d is null", i);
+    int dev = gs[0]->device;
+    for (int i = 0; i < ng; i++)
+        if (gs[i]->device != dev) fail(FOLTY_EINVAL, "all graphs of a plan must be on one device");
+    for (int q = 0; q < nq; q++) {
+        if (qgraph[q] < 0 || qgraph[q] >= ng) fail(FOLTY_EINVAL, "query %d names graph %d", q, qgraph[q]);
+        check_query(gs[qgraph[q]], qs[q]);
+    }
+    FOLTY_HIP(hipSetDevice(dev));
+    std::unique_ptr<Plan> P(new Plan());
+    P->device = dev;
+    P->oneshot = oneshot;
+    FOLTY_HIP(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
+    for (auto &e : P->ev) FOLTY_HIP(hipEventCreate(&e));
+    hipStream_t s = P->stream;
+    StreamScope sc(s);
+    // the graphs' own streams may still hold work
+    for (int i = 0; i < ng; i++) FOLTY_HIP(hipStreamSynchronize(gs[i]->stream));
+    P->graphs.assign(gs, gs + ng);
+    P->queries.assign(qs, qs + nq);
+    P->qgraph.assign(qgraph, qgraph + nq);
+    for (int q = 0; q < nq; q++)
+        if (qs[q].universe == FOLTY_UNIVERSE_COMMON) {
+            std::lock_guard<std::mutex> lk(gs[qgraph[q]]->lazy_mu);
+            ensure_tcnt(gs[qgraph[q]]->ix, s);
+            FOLTY_HIP(hipStreamSynchronize(s));
+        }
+    // jobs: (graph, predicate code) with their distinct windows
+    std::map<std::pair<int, int>, int> jid;
+    P->qjob.resize(nq);
+    P->qlevel.resize(nq);
+    for (int q = 0; q < nq; q++) {
+        auto key = std::make_pair((int)qgraph[q], (int)qs[q].variant);
+        auto it = jid.find(key);
+        if (it == jid.end()) {
+            it = jid.emplace(key, (int)P->jobs.size()).first;
+            P->jobs.push_back({key.first, key.second, {}});
+        }
+        P->qjob[q] = it->second;
+        P->jobs[it->second].levels.push_back(qs[q].delta);
+    }
+    for (auto &J : P->jobs) {
+        std::sort(J.levels.begin(), J.levels.end());
+        J.levels.erase(std::unique(J.levels.begin(), J.levels.end()), J.levels.end());
+    }
+    for (int q = 0; q < nq; q++) {
+        const auto &lv = P->jobs[P->qjob[q]].levels;
+        P->qlevel[q] = (int32_t)(std::lower_bound(lv.begin(), lv.end(), qs[q].delta) - lv.begin());
+    }
+    const int nj = (int)P->jobs.size();
+    // per-job buffers and descriptors
+    P->hist.resize(nj);
+    P->lv.resize(nj);
+    P->sv.resize(nj);
+    P->sw.resize(nj);
+    P->su.resize(nj);
+    std::vector<JobDev> jd(nj);
+    P->job_item_base.assign(nj + 1, 0);
+    P->job_m_base.assign(nj + 1, 0);
+    for (int j = 0; j < nj; j++) {
+        P->job_item_base[j + 1] = P->job_item_base[j] + P->graphs[P->jobs[j].graph]->ix.NI;
+        P->job_m_base[j + 1] = P->job_m_base[j] + P->graphs[P->jobs[j].graph]->ix.m;
+    }
+    P->items = P->job_item_base[nj];
+    P->total_m = P->job_m_base[nj];
+    P->wu.ensure(8 * ((size_t)P->items + 1));
+    P->wbase.ensure(8 * ((size_t)P->items + 1));
+    for (int j = 0; j < nj; j++) {
+        const Index &ix = P->graphs[P->jobs[j].graph]->ix;
+        const auto &lvs = P->jobs[j].levels;
+        P->hist[j].ensure(4 * lvs.size() * (size_t)ix.m + 4);
+        P->lv[j].ensure(8 * lvs.size());
+        FOLTY_HIP(hipMemcpyAsync(P->lv[j].p, lvs.data(), 8 * lvs.size(), hipMemcpyHostToDevice, s));
+        P->sv[j].ensure(12 * (size_t)ix.T + 12);
+        P->sw[j].ensure(8 * (size_t)ix.T + 8);
+        P->su[j].ensure(4 * (size_t)ix.NI + 4);
+        JobDev &d = jd[j];
+        d.ooff = ix.ooff.as<int32_t>();
+        d.oadj = ix.oadj.as<int32_t>();
+        d.item_u = ix.item_u.as<int32_t>();
+        d.item_off = ix.item_off.as<int32_t>();
+        d.tri = ix.tri_cached ? ix.tri.as<int32_t>() : nullptr;
+        d.tri_base = ix.tri_base.as<int64_t>();
+        d.ts = ix.ts.as<int64_t>();
+        d.rec = ix.rec.as<EdgeRec>();
+        d.NI = ix.NI;
+        d.variant = P->jobs[j].variant;
+        d.dmax = lvs.back();
+        d.lv = P->lv[j].as<int64_t>();
+        d.nl = (int32_t)lvs.size();
+        d.m = ix.m;
+        d.hist = P->hist[j].as<uint32_t>();
+        d.sv = P->sv[j].as<int32_t>();
+        d.sw = P->sw[j].as<int64_t>();
+        d.su = P->su[j].as<int32_t>();
+        d.wu = P->wu.as<int64_t>() + P->job_item_base[j];
+    }
+    // queries
+    std::vector<QueryDev> qd(nq);
+    P->q_e_base.assign(nq + 1, 0);
+    int64_t pb = 0;
+    int32_t nmax = 1;
+    for (int q = 0; q < nq; q++) {
+        const Graph *g = P->graphs[qgraph[q]];
+        const Index &ix = g->ix;
+        const JobDev &J = jd[P->qjob[q]];
+        QueryDev &d = qd[q];
+        d.count = J.hist + (int64_t)P->qlevel[q] * ix.m;
+        d.sid = ix.sid.as<int32_t>();
+        d.smid = ix.smid.as<int32_t>();
+        d.slo = ix.slo.as<int32_t>();
+        d.shi = ix.shi.as<int32_t>();
+        d.deg = ix.deg.as<int32_t>();
+        d.tcnt = ix.tcnt.as<int32_t>();
+        d.m = ix.m;
+        d.S = ix.S;
+        d.num = qs[q].theta_num;
+        d.den = qs[q].theta_den;
+        d.universe = qs[q].universe;
+        d.excl = qs[q].exclude_other ? 1 : 0;
+        d.p_base = pb;
+        pb += 2 * (int64_t)ix.S;
+        P->q_e_base[q + 1] = P->q_e_base[q] + ix.m;
+        nmax = std::max(nmax, ix.n);
+    }
+    P->total_e = P->q_e_base[nq];
+    P->total_p = pb;
+    P->nbits = bit_length((uint64_t)nmax);
+    if (bit_length((uint64_t)std::max(1, nq)) + 2 * P->nbits > 64)
+        fail(FOLTY_EOVERFLOW, "too many queries for one plan at this graph size");
+    P->d_jobs.ensure(sizeof(JobDev) * (size_t)std::max(1, nj));
+    P->d_job_item_base.ensure(8 * ((size_t)nj + 1));
+    P->d_job_m_base.ensure(8 * ((size_t)nj + 1));
+    P->d_queries.ensure(sizeof(QueryDev) * (size_t)std::max(1, nq));
+    P->d_q_e_base.ensure(8 * ((size_t)nq + 1));
+    if (nj) FOLTY_HIP(hipMemcpyAsync(P->d_jobs.p, jd.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice, s));
+    FOLTY_HIP(hipMemcpyAsync(P->d_job_item_base.p, P->job_item_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
+    FOLTY_HIP(hipMemcpyAsync(P->d_job_m_base.p, P->job_m_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
+    if (nq) FOLTY_HIP(hipMemcpyAsync(P->d_queries.p, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
+    FOLTY_HIP(hipMemcpyAsync(P->d_q_e_base.p, P->q_e_base.data(), 8 * (nq + 1), hipMemcpyHostToDevice, s));
+    P->ncert.ensure(4 * (size_t)P->total_p + 4);
+    P->qcert.ensure(4 * ((size_t)nq + 1));
+    P->npairs.ensure(4);
+    P->keys.ensure(8 * (size_t)P->total_p + 8);
+    P->vals.ensure(4 * (size_t)P->total_p + 4);
+    P->scan_bytes = exclusive_scan_i64(nullptr, 0, P->wu.as<int64_t>(), P->wbase.as<int64_t>(), P->items + 1, s);
+    P->cub.ensure(P->scan_bytes);
+    FOLTY_HIP(hipStreamSynchronize(s));
+    return P.release();
+}
+
+void plan_run(Plan *P, Result **outs) {
+    FOLTY_HIP(hipSetDevice(P->device));
+    hipStream_t s = P->stream;
+    StreamScope sc(s);
+    const int nq = (int)P->queries.size();
+    if (P->oneshot) {
+        // a shape already chosen for this much work, else the default; no capture
+        P->eager = true;
+        P->tuned = true;
+    }
+    if (!P->tuned) {
+        // first run: eager, with the autotuner between the filter and the tests
+        enqueue_compute(*P, s);
+        tune(*P);
+    }
+    if (!P->exec && !P->eager) {
+        // capture once; if the runtime refuses, keep launching eagerly
+        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            try {
+                enqueue_compute(*P, s);
+            } catch (...) {
+                ok = false;
+            }
+            hipGraph_t g = nullptr;
+            ok = hipStreamEndCapture(s, &g) == hipSuccess && ok;
+            if (ok && hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                P->graph = g;
+            } else {
+                if (g) (void)hipGraphDestroy(g);
+                P->exec = nullptr;
+                ok = false;
+            }
+        }
+        if (!ok) {
+            (void)hipGetLastError();
+            P->eager = true;
+        }
+    }
+    FOLTY_HIP(hipEventRecord(P->ev[0], s));
+    if (P->exec) FOLTY_HIP(hipGraphLaunch(P->exec, s));
+    else enqueue_compute(*P, s);
+    FOLTY_HIP(hipEventRecord(P->ev[3], s));
+    // read back how many pairs and certificates, then sort (query, u, v)
+    std::vector<uint32_t> qcert(nq + 1, 0);
+    int32_t npairs = 0;
+    FOLTY_HIP(hipMemcpyAsync(&npairs, P->npairs.p, 4, hipMemcpyDeviceToHost, s));
+    if (nq) FOLTY_HIP(hipMemcpyAsync(qcert.data(), P->qcert.p, 4 * (size_t)nq, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    std::vector<uint64_t> keys(npairs);
+    std::vector<uint32_t> vals(npairs);
+    if (npairs > 0) {
+        P->keys2.ensure(8 * (size_t)npairs);
+        P->vals2.ensure(4 * (size_t)npairs);
+        int kb = bit_length((uint64_t)std::max(1, nq)) + 2 * P->nbits;
+        size_t need = sort_pairs_u64_u32(nullptr, 0, P->keys.as<uint64_t>(), P->keys2.as<uint64_t>(),
+                                         P->vals.as<uint32_t>(), P->vals2.as<uint32_t>(), npairs, kb, s);
+        DevBuf tmp;
+        tmp.ensure(need);
+        sort_pairs_u64_u32(tmp.p, need, P->keys.as<uint64_t>(), P->keys2.as<uint64_t>(), P->vals.as<uint32_t>(),
+                           P->vals2.as<uint32_t>(), npairs, kb, s);
+        FOLTY_HIP(hipMemcpyAsync(keys.data(), P->keys2.p, 8 * (size_t)npairs, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipMemcpyAsync(vals.data(), P->vals2.p, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipStreamSynchronize(s));
+    }
+    P->last_ms = ev_ms2(P->ev[0], P->ev[3]);
+    // split per query
+    std::vector<std::unique_ptr<Result>> res(nq);
+    for (int q = 0; q < nq; q++) res[q].reset(new Result());
+    const uint64_t nmask = (1ull << P->nbits) - 1ull;
+    for (int32_t i = 0; i < npairs; i++) {
+        int q = (int)(keys[i] >> (2 * P->nbits));
+        Result *r = res[q].get();
+        r->u.push_back((int32_t)((keys[i] >> P->nbits) & nmask));
+        r->v.push_back((int32_t)(keys[i] & nmask));
+        r->n_cert.push_back(vals[i]);
+    }
+    for (int q = 0; q < nq; q++) {
+        Result *r = res[q].get();
+        const Graph *g = P->graphs[P->qgraph[q]];
+        r->n_certificates = qcert[q];
+        fill_stats_from_index(g->ix, &r->stats);
+        r->stats.n_pairs = (int64_t)r->u.size();
+        r->stats.n_certificates = r->n_certificates;
+        r->stats.query_ms = P->last_ms / std::max(1, nq);
+        r->stats.temporal_ms = r->stats.query_ms;
+        if (!(P->queries[q].flags & FOLTY_QUERY_NO_COUNTS)) {
+            const Index &ix = g->ix;
+            const uint32_t *count = P->hist[P->qjob[q]].as<uint32_t>() + (int64_t)P->qlevel[q] * ix.m;
+            r->counts_dev.ensure(4 * (size_t)ix.m_input + 4);
+            if (ix.m_input > 0)
+                k_fill<uint32_t><<<grid_for(ix.m_input, BLK, 1ll << 30), BLK, 0, s>>>(r->counts_dev.as<uint32_t>(),
+                                                                                    0xffffffffu, ix.m_input);
+            if (ix.m > 0)
+                k_scatter_counts<<<grid_for(ix.m, BLK, 1ll << 30), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
+                                                                               r->counts_dev.as<uint32_t>());
+            FOLTY_LAUNCHED();
+            r->has_counts = true;
+            r->device = P->device;
+        }
+    }
+    FOLTY_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < nq; q++) outs[q] = res[q].release();
+}
+
+void plan_free(Plan *P) { delete P; }
+
+void plan_info(const Plan *P, folty_plan_info *info) {
+    info->n_jobs = (int32_t)P->jobs.size();
+    info->n_queries = (int32_t)P->queries.size();
+    info->items = P->items;
+    info->tests = P->last_tests;
+    info->tests_per_chunk = P->ipt;
+    info->temporal_blocks = P->tblocks;
+    info->captured = P->exec != nullptr;
+    info->last_run_ms = P->last_ms;
+}
+
+void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &, Result **outs) {
+    if (nq < 0) fail(FOLTY_EINVAL, "nq < 0");
+    if (nq == 0) return;
+    std::vector<int32_t> qg(nq, 0);
+    std::unique_ptr<Plan> P(plan_create(&g, 1, qs, qg.data(), nq));
+    plan_run(P.get(), outs);
+}
+
+void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &, Result **outs) {
+    if (ng < 0) fail(FOLTY_EINVAL, "ng < 0");
+    if (ng == 0) return;
+    std::vector<int32_t> qg(ng);
+    for (int i = 0; i < ng; i++) qg[i] = i;
+    std::unique_ptr<Plan> P(plan_create(gs, ng, qs, qg.data(), ng));
+    plan_run(P.get(), outs);
+}
+
+} // namespace folty

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -204,7 +205,8 @@ struct Graph {
     bool sorted_by_time = false;
     int64_t tmax = 0;
     Index ix;
-    Workspace ws; // default workspace for the synchronous API
+    Workspace ws;          // default workspace for the synchronous API
+    std::mutex lazy_mu;    // guards index parts computed on first use
     ~Graph();
 };
 
@@ -228,9 +230,28 @@ void load_graph(Graph *g, int32_t n, int64_t m, const int32_t *src, const int32_
 void build_index(Graph *g, const folty_build_opts *opts);
 void check_query(const Graph *g, const folty_query &q);
 Result *run_query(Graph *g, const folty_query &q, Workspace &ws);
+Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t stream);
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
 void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);
 void fill_stats_from_index(const Index &ix, folty_stats *s);
+void ensure_tcnt(Index &ix, hipStream_t s); // per-static-edge triangle counts on first use
+
+// batched plans (batch.hip)
+struct Plan;
+// oneshot: the plan runs once (no capture, no timing of launch shapes)
+Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t *qgraph, int nq,
+                  bool oneshot = false);
+void plan_run(Plan *p, Result **outs);
+void plan_free(Plan *p);
+void plan_info(const Plan *p, folty_plan_info *info);
+
+// query server (server.hip)
+struct Server;
+Server *server_create(const folty_server_opts *o);
+int64_t server_submit(Server *s, Graph *g, const folty_query &q);
+Result *server_take(Server *s, int64_t ticket, bool wait);
+void server_info(Server *s, folty_server_info *info);
+void server_destroy(Server *s);
 // oriented-edge records, triangle counts per lowest vertex, optional triangle cache
 void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s);
 

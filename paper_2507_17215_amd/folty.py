@@ -30,7 +30,9 @@ EXPORTS = (
     "folty_run_fol_query_ws", "folty_run_batch", "folty_run_multi", "folty_result_pairs",
     "folty_result_counts", "folty_result_stats", "folty_result_free", "folty_graph_stats",
     "folty_graph_vertex_array", "folty_graph_device_bytes", "folty_graph_free",
-    "folty_release_cached_memory",
+    "folty_release_cached_memory", "folty_plan_create", "folty_plan_run", "folty_plan_get_info",
+    "folty_plan_free", "folty_server_create", "folty_server_submit", "folty_server_poll",
+    "folty_server_wait", "folty_server_get_info", "folty_server_destroy",
 )
 
 
@@ -52,13 +54,38 @@ class Query(ctypes.Structure):
                 ("flags", ctypes.c_uint8)]
 
 
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_jobs", ctypes.c_int32), ("n_queries", ctypes.c_int32), ("items", ctypes.c_int64),
+                ("tests", ctypes.c_int64), ("tests_per_chunk", ctypes.c_int32),
+                ("temporal_blocks", ctypes.c_int32), ("captured", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("last_run_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "submitted", "completed", "rejected", "queued", "batches", "batched_requests",
+        "budget_bytes", "in_use_bytes", "peak_in_use_bytes")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in (
         "n", "m_input", "m", "self_loops", "static_edges", "directed_pairs", "max_core",
         "max_out_degree", "wedges", "triangles", "max_multiplicity", "peel_rounds",
-        "closing_probes", "enum_items", "tests",
+        "closing_probes", "enum_items", "batch_size", "tests",
         "n_pairs", "n_certificates")] + [(f, ctypes.c_double) for f in (
-            "build_ms", "wedge_ms", "temporal_ms", "threshold_ms", "query_ms")]
+            "build_ms", "wedge_ms", "temporal_ms", "threshold_ms", "query_ms", "latency_ms",
+            "queue_ms")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -104,11 +131,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.folty_graph_vertex_array.argtypes = [P, I32, P]
     lib.folty_graph_device_bytes.argtypes = [P, ctypes.POINTER(I64)]
     lib.folty_release_cached_memory.argtypes = [ctypes.POINTER(I64)]
+    lib.folty_plan_create.argtypes = [PP, I32, ctypes.POINTER(Query), ctypes.POINTER(I32), I32, PP]
+    lib.folty_plan_run.argtypes = [P, PP]
+    lib.folty_plan_get_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    lib.folty_plan_free.argtypes = [P]
+    lib.folty_plan_free.restype = None
+    lib.folty_server_create.argtypes = [ctypes.POINTER(ServerOpts), PP]
+    lib.folty_server_submit.argtypes = [P, P, ctypes.POINTER(Query), ctypes.POINTER(I64)]
+    lib.folty_server_poll.argtypes = [P, I64, PP]
+    lib.folty_server_wait.argtypes = [P, I64, PP]
+    lib.folty_server_get_info.argtypes = [P, ctypes.POINTER(ServerInfo)]
+    lib.folty_server_destroy.argtypes = [P]
+    lib.folty_server_destroy.restype = None
     lib.folty_graph_free.argtypes = [P]
     lib.folty_graph_free.restype = None
     for name in EXPORTS:
         if name not in ("folty_workspace_free", "folty_result_free", "folty_graph_free",
-                        "folty_last_error", "folty_version"):
+                        "folty_plan_free", "folty_server_destroy", "folty_last_error",
+                        "folty_version"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -316,6 +356,88 @@ def run_multi(graphs, queries) -> list:
     outs = (ctypes.c_void_p * n)()
     _check(load_library().folty_run_multi(gs, qs, n, outs))
     return [Result(ctypes.c_void_p(o)) for o in outs]
+
+
+class Plan:
+    """A fixed batch of queries over resident graphs, run as one captured launch
+    sequence.  `queries` is a list of (graph_index, query) where query is a dict
+    of make_query's arguments or a Query."""
+
+    def __init__(self, graphs, queries):
+        self.graphs = list(graphs)  # keep the graphs alive as long as the plan
+        n = len(queries)
+        gs = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
+        qs = (Query * max(1, n))(*[q if isinstance(q, Query) else make_query(**q) for _, q in queries])
+        qg = (ctypes.c_int32 * max(1, n))(*[int(gi) for gi, _ in queries])
+        self.n = n
+        self._h = ctypes.c_void_p()
+        _check(load_library().folty_plan_create(gs, len(self.graphs), qs, qg, n, ctypes.byref(self._h)))
+
+    def run(self) -> list:
+        outs = (ctypes.c_void_p * max(1, self.n))()
+        _check(load_library().folty_plan_run(self._h, outs))
+        return [Result(ctypes.c_void_p(outs[i])) for i in range(self.n)]
+
+    def info(self) -> dict:
+        info = PlanInfo()
+        _check(load_library().folty_plan_get_info(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().folty_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching query server over resident graphs (thread-safe)."""
+
+    def __init__(self, workers: int = 4, max_batch: int = 16, hbm_budget_bytes: int = 0):
+        o = ServerOpts(int(workers), int(max_batch), int(hbm_budget_bytes))
+        self._h = ctypes.c_void_p()
+        _check(load_library().folty_server_create(ctypes.byref(o), ctypes.byref(self._h)))
+
+    def submit(self, graph: "Graph", **query) -> int:
+        q = query.pop("query", None) or make_query(**query)
+        t = ctypes.c_int64()
+        _check(load_library().folty_server_submit(self._h, graph._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """The result, or None while the request is not done."""
+        out = ctypes.c_void_p()
+        rc = load_library().folty_server_poll(self._h, int(ticket), ctypes.byref(out))
+        if rc == EBUSY:
+            return None
+        _check(rc)
+        return Result(out)
+
+    def wait(self, ticket: int) -> Result:
+        out = ctypes.c_void_p()
+        _check(load_library().folty_server_wait(self._h, int(ticket), ctypes.byref(out)))
+        return Result(out)
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        _check(load_library().folty_server_get_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().folty_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_cached_memory() -> int:

@@ -166,6 +166,50 @@ def test_multi_graph_call():
         assert_same(r, o.query(q["delta"], 1, 4, q["variant"]))
 
 
+def test_plan_replays_match_single_queries_and_oracle():
+    """A plan over several graphs and mixed predicates: every replay (with other
+    GPU work in between) equals the single-query path and the oracle."""
+    gs = [synth.tiny(seed=11), synth.c1_family(5000, seed=12), synth.bruteforce_size(seed=13)]
+    Gs = [gpu_graph(g) for g in gs]
+    Gs[1] = gpu_graph(gs[1], cache_triangles=True)
+    rng = np.random.default_rng(5)
+    queries = []
+    for i in range(24):
+        gi = int(rng.integers(0, len(gs)))
+        queries.append((gi, dict(delta=int(rng.choice([0, 600, 86400, 400_000, 10**6, INF])),
+                                 theta=(int(rng.integers(0, 5)), 4), variant=int(rng.choice([0, 3, 6])),
+                                 universe=int(rng.integers(0, 3)))))
+    plan = folty.Plan(Gs, queries)
+    oracles = [Oracle(g.n, g.src, g.dst, g.t) for g in gs]
+    want = [oracles[gi].query(q["delta"], q["theta"][0], q["theta"][1], q["variant"], q["universe"])
+            for gi, q in queries]
+    for rep in range(4):
+        say("plan replay", rep, plan.info())
+        rs = plan.run()
+        for (gi, q), r, w in zip(queries, rs, want):
+            assert_same(r, w)
+        # unrelated eager work between replays
+        Gs[rep % 3].query(1000, (1, 2), 0)
+    info = plan.info()
+    assert info["n_queries"] == len(queries)
+    assert info["n_jobs"] <= len(queries)
+
+
+def test_plan_with_empty_and_loop_only_graphs():
+    e0 = folty.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64)).build()
+    e1 = folty.Graph(3, np.array([1, 1], np.int32), np.array([1, 1], np.int32), np.array([0, 5])).build()
+    g = synth.bruteforce_size(seed=3)
+    G = gpu_graph(g)
+    plan = folty.Plan([e0, e1, G], [(0, dict(delta=5)), (1, dict(delta=5, theta=(0, 1))), (2, dict(delta=10**6))])
+    say("plan with empty graphs")
+    for _ in range(2):
+        r = plan.run()
+        assert r[0].pairs() == [] and r[0].n_certificates == 0
+        assert r[1].pairs() == [] and r[1].n_certificates == 0
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        assert_same(r[2], o.query(10**6, 1, 2, 0))
+
+
 def test_device_tensor_inputs():
     import torch
     g = synth.tiny(seed=6)
