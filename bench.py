@@ -46,6 +46,10 @@ def parse():
     p.add_argument("--parity-sample", type=int, default=4000)
     p.add_argument("--cache-dir", default=None,
                    help="keep the generated graph here as .npy files and reuse it")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched section")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    p.add_argument("--serve-full", action="store_true",
+                   help="serving on all eight graphs (up to 7e7 edges) at five arrival rates")
     return p.parse_args()
 
 
@@ -61,6 +65,102 @@ def load_or_generate(synth, n, m, comm, cache_dir):
         for k in ("src", "dst", "t"):
             np.save(f"{base}_{k}.npy", getattr(g, k))
     return g
+
+
+def batched_section(folty, synth, steps):
+    """64 mixed queries on one resident 10M-edge graph, and one query on each of
+    32 graphs of 1e3..1e6 edges: plans (one launch sequence each, replayed from a
+    HIP graph) against the same queries run one at a time."""
+    import torch
+    out = {}
+    g = synth.c1_family(10_000_000, seed=0)
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    qs = [dict(q, counts=False) for q in synth.query_pool(4, 64, variants=(0, 3))]
+    graphs = [synth.c1_family(int(round(10 ** (3 + 3 * i / 31))), seed=i) for i in range(32)]
+    Gs = [folty.Graph(x.n, x.src, x.dst, x.t).build() for x in graphs]
+    q32 = [dict(synth.query_pool(100 + i, 1)[0], counts=False) for i in range(32)]
+    log(f"batched: resident graph m={g.m}, {len(graphs)} graphs with {sum(x.m for x in graphs)} edges")
+    for name, plan_graphs, plan_queries, singles in (
+            ("one_graph_64_queries", [G], [(0, q) for q in qs], [(G, q) for q in qs]),
+            ("graphs_32_one_query_each", Gs, [(i, q) for i, q in enumerate(q32)], list(zip(Gs, q32)))):
+        plan = folty.Plan(plan_graphs, plan_queries)
+        first = plan.run()  # tunes the temporal launch shape, then captures
+        plan.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = plan.run()
+        plan_s = (time.perf_counter() - t0) / steps
+        # the same queries one at a time through the single-query path
+        seq = [gr.query(**q) for gr, q in singles]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            seq = [gr.query(**q) for gr, q in singles]
+        seq_s = (time.perf_counter() - t0) / steps
+        same = all(r.pairs() == s_.pairs() and r.n_certificates == s_.n_certificates
+                   for r, s_ in zip(res, seq))
+        n = len(plan_queries)
+        out[name] = {"queries": n, "plan_ms": plan_s * 1e3, "queries_per_s": n / plan_s,
+                     "sequential_ms": seq_s * 1e3, "sequential_queries_per_s": n / seq_s,
+                     "speedup": seq_s / plan_s, "same_as_single_queries": same, "plan": plan.info()}
+        log(f"batched {name}: plan {plan_s * 1e3:.2f} ms ({n / plan_s:.0f} q/s), sequential "
+            f"{seq_s * 1e3:.2f} ms ({n / seq_s:.0f} q/s), identical results: {same}")
+        plan.close()
+    return out
+
+
+def serving_section(folty, synth, full):
+    """Poisson arrivals of queries on resident graphs through the continuous-
+    batching server; per-request latency is submit to result on the host."""
+    import threading
+    sizes = [100_000, 300_000, 1_000_000, 3_000_000, 10_000_000]
+    gs = [synth.c1_family(m, seed=10 + i) for i, m in enumerate(sizes)]
+    if full:
+        gs += [synth.large_family(m, seed=20 + i) for i, m in enumerate((20_000_000, 40_000_000, 70_000_000))]
+    Gs = [folty.Graph(x.n, x.src, x.dst, x.t).build() for x in gs]
+    rng = np.random.default_rng(5)
+    pool = sorted({int(round(np.exp(rng.uniform(np.log(60), np.log(604800))))) for _ in range(16)})
+    rates = (10, 30, 100, 300, 1000) if full else (100, 1000)
+    per_rate = 2000 if full else 400
+    srv = folty.Server(workers=4, max_batch=16)
+    out = {"graphs_edges": [x.m for x in gs], "delta_pool": pool, "rates": {}}
+    for rate in rates:
+        reqs = [(int(rng.integers(0, len(Gs))),
+                 dict(delta=int(rng.choice(pool)), theta=(int(rng.integers(1, 10)), 10),
+                      variant=int(rng.choice([0, 3])), counts=False)) for _ in range(per_rate)]
+        gaps = rng.exponential(1.0 / rate, size=per_rate)
+        tickets = [None] * per_rate
+
+        def submit():
+            t_next = time.perf_counter()
+            for i, (gi, q) in enumerate(reqs):
+                t_next += gaps[i]
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(Gs[gi], **q)
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=submit)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        lat = np.array([r.stats["latency_ms"] for r in res])
+        bs = np.array([r.stats["batch_size"] for r in res])
+        # a sample of requests rerun alone must give the same answer
+        pick = rng.choice(per_rate, size=min(20, per_rate), replace=False)
+        same = all(res[i].pairs() == Gs[reqs[i][0]].query(**reqs[i][1]).pairs() for i in pick)
+        out["rates"][str(rate)] = {"requests": per_rate, "p50_ms": float(np.percentile(lat, 50)),
+                                   "p99_ms": float(np.percentile(lat, 99)),
+                                   "achieved_queries_per_s": per_rate / wall,
+                                   "mean_batch": float(bs.mean()), "same_as_alone": same}
+        log(f"serving {rate} q/s: p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms, "
+            f"achieved {per_rate / wall:.0f} q/s, mean batch {bs.mean():.2f}, same as alone: {same}")
+    out["server"] = srv.info()
+    srv.close()
+    return out
 
 
 def main():
@@ -195,6 +295,10 @@ def main():
                       f"{k} uniformly sampled edges ({sample_s:.1f}s), extrapolated linearly in "
                       f"edges to the whole job ({est_full_s:.1f}s); W from the GPU orientation",
             "est_full_job_s": est_full_s}
+    if not a.no_batch:
+        out["batched"] = batched_section(folty, synth, max(3, a.steps))
+    if not a.no_serve:
+        out["serving"] = serving_section(folty, synth, a.serve_full)
     print(json.dumps(out))
 
 

@@ -318,10 +318,10 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
     for (int j = 0; j < nj; j++) {
         const Index &ix = P.graphs[P.jobs[j].graph]->ix;
         int64_t hn = (int64_t)P.jobs[j].levels.size() * ix.m;
-        if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1ll << 20), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
+        if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
     }
     if (P.total_p > 0)
-        k_fill<uint32_t><<<grid_for(P.total_p, BLK, 1ll << 20), BLK, 0, s>>>(P.ncert.as<uint32_t>(), 0u, P.total_p);
+        k_fill<uint32_t><<<grid_for(P.total_p, BLK, 1 << 16), BLK, 0, s>>>(P.ncert.as<uint32_t>(), 0u, P.total_p);
     k_fill<uint32_t><<<grid_for(nq + 1, BLK), BLK, 0, s>>>(P.qcert.as<uint32_t>(), 0u, nq + 1);
     k_fill<int32_t><<<1, 1, 0, s>>>(P.npairs.as<int32_t>(), 0, 1);
     k_fill<int64_t><<<1, 1, 0, s>>>(P.wu.as<int64_t>() + P.items, (int64_t)0, 1);
@@ -392,7 +392,7 @@ static void tune(Plan &P) {
                 const Index &ix = P.graphs[P.jobs[j].graph]->ix;
                 int64_t hn = (int64_t)P.jobs[j].levels.size() * ix.m;
                 if (hn > 0)
-                    k_fill<uint32_t><<<grid_for(hn, BLK, 1ll << 20), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
+                    k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
             }
             FOLTY_HIP(hipEventRecord(P.ev[1], s));
             k_multi_temporal<<<bl, BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj, P.d_job_item_base.as<int64_t>(), P.items,
@@ -659,10 +659,10 @@ void plan_run(Plan *P, Result **outs) {
             const uint32_t *count = P->hist[P->qjob[q]].as<uint32_t>() + (int64_t)P->qlevel[q] * ix.m;
             r->counts_dev.ensure(4 * (size_t)ix.m_input + 4);
             if (ix.m_input > 0)
-                k_fill<uint32_t><<<grid_for(ix.m_input, BLK, 1ll << 30), BLK, 0, s>>>(r->counts_dev.as<uint32_t>(),
+                k_fill<uint32_t><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(r->counts_dev.as<uint32_t>(),
                                                                                     0xffffffffu, ix.m_input);
             if (ix.m > 0)
-                k_scatter_counts<<<grid_for(ix.m, BLK, 1ll << 30), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
+                k_scatter_counts<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
                                                                                r->counts_dev.as<uint32_t>());
             FOLTY_LAUNCHED();
             r->has_counts = true;

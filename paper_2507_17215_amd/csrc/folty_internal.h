@@ -282,10 +282,19 @@ inline int bit_length(uint64_t x) {
     return b;
 }
 
-inline unsigned grid_for(int64_t items, int block, int64_t cap = 1 << 20) {
+// Blocks for a launch over `items`.  With cap = 0 the kernel handles one item
+// per thread, so the grid must cover every item; a dispatch holds fewer than
+// 2^32 work-items, and a larger range is an error rather than a silently
+// truncated grid.  With cap > 0 the kernel is grid-stride and at most cap
+// blocks are launched.
+inline unsigned grid_for(int64_t items, int block, int64_t cap = 0) {
     int64_t g = (items + block - 1) / block;
     if (g < 1) g = 1;
-    if (g > cap) g = cap;
+    if (cap > 0) {
+        if (g > cap) g = cap;
+    } else if (g * (int64_t)block > (int64_t)UINT32_MAX) {
+        fail(FOLTY_EOVERFLOW, "a launch over %lld items exceeds one dispatch", (long long)items);
+    }
     return (unsigned)g;
 }
 

@@ -75,8 +75,8 @@ __global__ void k_init_val(ValOut *o) {
 }
 
 template <class T> __global__ void k_fill(T *p, T v, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 __global__ void k_iota_tkeys(const int64_t *__restrict__ t, uint64_t *__restrict__ keys,

@@ -263,7 +263,7 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
     ws.scal.ensure(64);
     k_fill<unsigned long long><<<1, 8, 0, s>>>(ws.scal.as<unsigned long long>(), 0ull, 8);
     if (S > 0) {
-        k_fill<uint32_t><<<grid_for(2 * (int64_t)S, BLK, 1ll << 30), BLK, 0, s>>>(ws.ncert.as<uint32_t>(), 0u,
+        k_fill<uint32_t><<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(ws.ncert.as<uint32_t>(), 0u,
                                                                                2 * (int64_t)S);
     }
     FOLTY_LAUNCHED();
@@ -285,11 +285,11 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
         A.excl = q.exclude_other ? 1 : 0;
         A.ncert = ws.ncert.as<uint32_t>();
         A.total = total;
-        k_threshold<<<grid_for(m, BLK, 1ll << 30), BLK, 0, s>>>(A);
+        k_threshold<<<grid_for(m, BLK), BLK, 0, s>>>(A);
         FOLTY_LAUNCHED();
         ws.pairs_k.ensure(16 * (size_t)S);
         ws.pairs_v.ensure(8 * (size_t)S);
-        k_pairs_compact<<<grid_for(2 * (int64_t)S, BLK, 1ll << 30), BLK, 0, s>>>(
+        k_pairs_compact<<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(
             ws.ncert.as<uint32_t>(), S, ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), ws.pairs_k.as<uint64_t>(),
             ws.pairs_v.as<uint32_t>(), np);
         FOLTY_LAUNCHED();
@@ -329,12 +329,12 @@ void keep_counts(const Graph *g, const uint32_t *count, Result *res, hipStream_t
     const Index &ix = g->ix;
     res->counts_dev.ensure(4 * (size_t)ix.m_input + 4);
     if (ix.m_input > 0) {
-        k_fill<uint32_t><<<grid_for(ix.m_input, BLK, 1ll << 30), BLK, 0, s>>>(res->counts_dev.as<uint32_t>(),
+        k_fill<uint32_t><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(res->counts_dev.as<uint32_t>(),
                                                                             0xffffffffu, ix.m_input);
         FOLTY_LAUNCHED();
     }
     if (ix.m > 0) {
-        k_counts_scatter<<<grid_for(ix.m, BLK, 1ll << 30), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
+        k_counts_scatter<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
                                                                        res->counts_dev.as<uint32_t>());
         FOLTY_LAUNCHED();
     }
@@ -356,12 +356,12 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     k_fill<int32_t><<<1, 1, 0, s>>>(items.as<int32_t>() + n, 0, 1);
     FOLTY_LAUNCHED();
     if (S > 0) {
-        k_edge_recs<<<grid_for(S, BLK, 1ll << 30), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), ix.soff.as<int32_t>(),
+        k_edge_recs<<<grid_for(S, BLK), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), ix.soff.as<int32_t>(),
                                                                 ix.smid.as<int32_t>(), ix.ts.as<int64_t>(), S,
                                                                 ix.rec.as<EdgeRec>());
         FOLTY_LAUNCHED();
     }
-    k_probes<<<grid_for(n, BLK, 1ll << 30), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), n,
+    k_probes<<<grid_for(n, BLK), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), n,
                                                           items.as<int32_t>(), probes.as<unsigned long long>());
     FOLTY_LAUNCHED();
     {
@@ -378,7 +378,7 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     ix.probes = h[1];
     ix.item_u.ensure(4 * (size_t)ni + 4);
     ix.tri_base.ensure(8 * ((size_t)ni + 1));
-    k_item_owner<<<grid_for(n, BLK, 1ll << 30), BLK, 0, s>>>(ix.item_off.as<int32_t>(), n, ix.item_u.as<int32_t>());
+    k_item_owner<<<grid_for(n, BLK), BLK, 0, s>>>(ix.item_off.as<int32_t>(), n, ix.item_u.as<int32_t>());
     FOLTY_LAUNCHED();
     DevBuf tri_it;
     tri_it.ensure(4 * ((size_t)ni + 1));
@@ -409,7 +409,7 @@ void ensure_tcnt(Index &ix, hipStream_t s) {
     if (ix.tcnt_ready) return;
     ix.tcnt.ensure(4 * (size_t)ix.S + 4);
     if (ix.S > 0) {
-        k_fill<int32_t><<<grid_for(ix.S, BLK, 1ll << 30), BLK, 0, s>>>(ix.tcnt.as<int32_t>(), 0, ix.S);
+        k_fill<int32_t><<<grid_for(ix.S, BLK), BLK, 0, s>>>(ix.tcnt.as<int32_t>(), 0, ix.S);
         FOLTY_LAUNCHED();
         TcntSink sink{ix.oeid.as<uint32_t>(), ix.tcnt.as<int32_t>()};
         k_tri_enum<<<enum_grid(ix.NI), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
@@ -449,7 +449,7 @@ Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t 
     ws.count.ensure(4 * (size_t)ix.m + 4);
     uint32_t *count = ws.count.as<uint32_t>();
     if (ix.m > 0) {
-        k_fill<uint32_t><<<grid_for(ix.m, BLK, 1ll << 30), BLK, 0, s>>>(count, 0u, ix.m);
+        k_fill<uint32_t><<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, 0u, ix.m);
         FOLTY_LAUNCHED();
     }
     int64_t tests = 0;

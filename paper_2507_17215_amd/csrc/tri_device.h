@@ -48,8 +48,8 @@ template <class T> __device__ inline T wave_inclusive_sum(T x) {
 }
 
 template <class T> __global__ void k_fill(T *p, T v, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 // ---------------------------------------------------------------------------

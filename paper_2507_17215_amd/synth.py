@@ -251,5 +251,5 @@ def query_pool(seed: int, count: int, variants=(0, 3)):
         d = int(round(math.exp(rng.uniform(math.log(60), math.log(604800)))))
         th = int(rng.integers(1, 10))
         var = int(variants[int(rng.integers(0, len(variants)))])
-        out.append(dict(delta=d, theta_num=th, theta_den=10, variant=var))
+        out.append(dict(delta=d, theta=(th, 10), variant=var))
     return out
