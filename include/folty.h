@@ -128,8 +128,9 @@ typedef struct {
     int64_t n_pairs;          /* solution pairs */
     int64_t n_certificates;   /* |Sol| */
     double build_ms;          /* device time of folty_build_index */
-    double wedge_ms;          /* device time of wedge enumeration + closing probe */
-    double temporal_ms;       /* device time of the temporal tests */
+    double wedge_ms;          /* device time of the enumeration kernel alone: wedges, closing
+                                 probes and the time-range filter of each triangle's lists */
+    double temporal_ms;       /* device time of the survivor scan and the temporal tests */
     double threshold_ms;      /* device time of threshold, pair reduction and compaction */
     double query_ms;          /* device time of the whole query */
     double latency_ms;        /* server: submit to result ready on the host */
