@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # the query's dominant kernel, the sources it is compiled from, and the committed
 # counter summary (FETCH_SIZE / WRITE_SIZE per dispatch and the copy-kernel
 # calibration) that gives its measured HBM traffic
-ROOF_KERNEL = "k_tri_enum<FilterSink<0> >"
+ROOF_KERNEL = "k_tri_enum<FilterSink<0, 0> >"
 ROOF_SOURCES = ("paper_2507_17215_amd/csrc/tri_device.h", "paper_2507_17215_amd/csrc/query.hip")
 TRAFFIC_SUMMARY = "profiles/k_tri_enum_filter_large_70M_pmc.md"
 COPY_PROBE_BYTES = 1 << 30

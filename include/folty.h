@@ -116,7 +116,7 @@ typedef struct {
     int64_t max_core;         /* degeneracy (largest core number) */
     int64_t max_out_degree;   /* largest |N+(x)| of the orientation used */
     int64_t wedges;           /* sum over x of C(|N+(x)|, 2): oriented wedges, one closing probe each */
-    int64_t triangles;        /* static triangles */
+    int64_t triangles;        /* static triangles (counted by the first query or stats call) */
     int64_t max_multiplicity; /* sigma_max: longest list E_{x,y} */
     int64_t peel_rounds;      /* rounds of the min-degree peeling */
     int64_t closing_probes;   /* membership probes of the enumeration: sum over (u,v) of |N+(v)| */
@@ -128,9 +128,10 @@ typedef struct {
     int64_t n_pairs;          /* solution pairs */
     int64_t n_certificates;   /* |Sol| */
     double build_ms;          /* device time of folty_build_index */
-    double wedge_ms;          /* device time of the enumeration kernel alone: wedges, closing
-                                 probes and the time-range filter of each triangle's lists */
-    double temporal_ms;       /* device time of the survivor scan and the temporal tests */
+    double wedge_ms;          /* device time of the counting enumeration pass alone: wedges,
+                                 closing probes and the time-range filter of each triangle */
+    double temporal_ms;       /* device time of the survivor scans, the emitting pass over the
+                                 items with survivors, and the temporal tests */
     double threshold_ms;      /* device time of threshold, pair reduction and compaction */
     double query_ms;          /* device time of the whole query */
     double latency_ms;        /* server: submit to result ready on the host */
@@ -281,7 +282,9 @@ int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t
 int folty_result_stats(const folty_result *r, folty_stats *s);
 void folty_result_free(folty_result *r);
 
-/* Index sizes and build timing. */
+/* Index sizes and build timing.  The build does not count triangles (a query
+ * does, in its own filter pass); if no query has run yet this call counts them
+ * with one enumeration pass on the graph's stream, once. */
 int folty_graph_stats(const folty_graph *g, folty_stats *s);
 
 /*

@@ -300,6 +300,7 @@ int folty_graph_stats(const folty_graph *g, folty_stats *s) {
     return guarded([&] {
         if (!g || !s) fail(FOLTY_EINVAL, "null argument");
         *s = folty_stats{};
+        if (g->g.ix.built && g->g.ix.T < 0) ensure_triangles(const_cast<Graph *>(&g->g));
         fill_stats_from_index(g->g.ix, s);
     });
 }

@@ -33,8 +33,9 @@ struct JobDev {
     const int32_t *ooff, *oadj, *item_u, *item_off, *tri;
     const int64_t *tri_base, *ts;
     const EdgeRec *rec;
+    const uint2 *rng;
     int32_t NI, variant;
-    int64_t dmax;
+    int64_t dmax, dq;
     const int64_t *lv;
     int32_t nl, m;
     uint32_t *hist; // nl * m
@@ -74,9 +75,11 @@ __global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__
         const int32_t j = owner_of(job_item_base, nj, g);
         const JobDev &J = jobs[j];
         const int64_t it = g - job_item_base[j];
-        FilterSink<-1> sink;
+        FilterSink<-1, FILTER_BOTH> sink;
         sink.base = J.tri_base;
         sink.rec = J.rec;
+        sink.rng = J.rng;
+        sink.dq = J.dq;
         sink.dmax = J.dmax;
         sink.variant = J.variant;
         sink.sv = J.sv;
@@ -433,8 +436,12 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     for (auto &e : P->ev) FOLTY_HIP(hipEventCreate(&e));
     hipStream_t s = P->stream;
     StreamScope sc(s);
-    // the graphs' own streams may still hold work
-    for (int i = 0; i < ng; i++) FOLTY_HIP(hipStreamSynchronize(gs[i]->stream));
+    // the graphs' own streams may still hold work; the one-pass filter writes
+    // survivors into per-item triangle slots
+    for (int i = 0; i < ng; i++) {
+        FOLTY_HIP(hipStreamSynchronize(gs[i]->stream));
+        ensure_triangles(gs[i]);
+    }
     P->graphs.assign(gs, gs + ng);
     P->queries.assign(qs, qs + nq);
     P->qgraph.assign(qgraph, qgraph + nq);
@@ -502,9 +509,11 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         d.tri_base = ix.tri_base.as<int64_t>();
         d.ts = ix.ts.as<int64_t>();
         d.rec = ix.rec.as<EdgeRec>();
+        d.rng = ix.erng.as<uint2>();
         d.NI = ix.NI;
         d.variant = P->jobs[j].variant;
         d.dmax = lvs.back();
+        d.dq = range_slack(d.dmax, ix.tshift);
         d.lv = P->lv[j].as<int64_t>();
         d.nl = (int32_t)lvs.size();
         d.m = ix.m;

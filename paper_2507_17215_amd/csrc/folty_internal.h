@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <memory>
+#include <atomic>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -136,7 +137,8 @@ struct Index {
     int32_t S = 0;           // static edges
     int64_t P = 0;           // non-empty directed lists
     int64_t sigma_max = 0;
-    int64_t T = 0;           // static triangles
+    std::atomic<int64_t> T{-1}; // static triangles (-1 until a query or ensure_tri_base counted them)
+    bool tri_base_ready = false; // tri_base holds per-item triangle offsets
     int64_t W = 0;           // oriented wedges: sum of C(|N+(x)|, 2)
     int64_t probes = 0;      // closing probes the enumeration makes: sum over (u,v) of |N+(v)|
     int32_t NI = 0;          // enumeration items
@@ -148,6 +150,7 @@ struct Index {
     bool tri_cached = false;
     bool tcnt_ready = false;
     double build_ms = 0;
+    int32_t tshift = 0; // timestamps >> tshift fit 32 bits (0 for t < 2^32)
 
     DevBuf ts;       // int64[m]
     DevBuf perm;     // int32[m]  input position of each sorted edge
@@ -164,6 +167,7 @@ struct Index {
     DevBuf oadj;     // int32[S]  heads (new ids)
     DevBuf oeid;     // uint32[S] static edge id | direction bit
     DevBuf rec;      // EdgeRec[S]
+    DevBuf erng;     // uint2[S]  first and last timestamp >> tshift over both lists of each oriented edge
     DevBuf item_u;   // int32[NI]
     DevBuf item_off; // int32[n+1]
     DevBuf tri_base; // int64[NI+1]
@@ -176,11 +180,12 @@ struct Index {
 // per-query scratch; one per concurrent caller
 struct Workspace {
     DevBuf count;   // uint32[m]
-    DevBuf sv;      // int32[3T]   surviving triangles (oriented edges), in their item's slots
-    DevBuf sw;      // int64[T]    test offset of each survivor inside its item
+    DevBuf sv;      // int32[3 x survivors] surviving triangles (oriented edges), in their item's slots
+    DevBuf sw;      // int64[survivors]     test offset of each survivor inside its item
     DevBuf su;      // int32[NI]   survivors per item
     DevBuf wu;      // int64[NI+1] tests per item
     DevBuf wbase;   // int64[NI+1] exclusive offsets of wu
+    DevBuf sbase;   // int64[NI+1] first survivor slot of each item
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
     DevBuf pairs_v; // uint32[2S]
@@ -254,6 +259,8 @@ void server_info(Server *s, folty_server_info *info);
 void server_destroy(Server *s);
 // oriented-edge records, triangle counts per lowest vertex, optional triangle cache
 void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s);
+void ensure_tri_base(Index &ix, hipStream_t s); // caller holds Graph::lazy_mu once the graph is shared
+void ensure_triangles(Graph *g);                 // ensure_tri_base on the graph's stream, under lazy_mu
 
 // library-primitive wrappers (rocPRIM through hipCUB), all on `stream`
 size_t sort_pairs_u64_i32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,

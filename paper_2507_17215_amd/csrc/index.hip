@@ -1176,6 +1176,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         ix.max_core = os.max_core;
     }
     // ---- oriented-edge records and triangles per lowest vertex ------------------------
+    ix.tshift = std::max(0, bit_length((uint64_t)g->tmax) - 32);
     index_triangles(ix, o.cache_triangles != 0, cub, s);
     FOLTY_HIP(hipEventRecord(e1, s));
     FOLTY_HIP(hipStreamSynchronize(s));
@@ -1185,7 +1186,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
 
 size_t Index::device_bytes() const {
     const DevBuf *b[] = {&ts, &perm, &sid, &soff, &smid, &slo, &shi, &deg, &core, &rank,
-                         &outdeg, &ooff, &oadj, &oeid, &rec, &tri_base, &tcnt, &tri};
+                         &outdeg, &ooff, &oadj, &oeid, &rec, &erng, &item_u, &item_off, &tri_base, &tcnt, &tri};
     size_t t = 0;
     for (auto *x : b) t += x->bytes;
     return t;

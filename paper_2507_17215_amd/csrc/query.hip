@@ -34,7 +34,7 @@ namespace {
 // ---------------------------------------------------------------------------
 __global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const int32_t *__restrict__ soff,
                             const int32_t *__restrict__ smid, const int64_t *__restrict__ ts, int32_t S,
-                            EdgeRec *__restrict__ rec) {
+                            int32_t tshift, EdgeRec *__restrict__ rec, uint2 *__restrict__ erng) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S) return;
     uint32_t id = oeid[p];
@@ -58,6 +58,13 @@ __global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const int32_t *__
     r.sid = e;
     r.pad[0] = r.pad[1] = r.pad[2] = 0;
     rec[p] = r;
+    // a static edge has at least one temporal edge, so one of the lists is non-empty
+    int64_t lo = fn ? r.ftmin : r.btmin, hi = fn ? r.ftmax : r.btmax;
+    if (fn && bn) {
+        lo = r.btmin < lo ? r.btmin : lo;
+        hi = r.btmax > hi ? r.btmax : hi;
+    }
+    erng[p] = make_uint2((uint32_t)(lo >> tshift), (uint32_t)(hi >> tshift));
 }
 
 // closing probes of vertex u: sum over v in N+(u) of |N+(v)|; the vertex gets
@@ -210,50 +217,86 @@ unsigned enum_grid(int32_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, ENUM_BLOCKS));
 }
 
-// a.5 for one predicate code and window bound: surviving triangles per lowest
-// vertex, then exclusive test offsets per vertex in ws.wbase (total at [n]).
-// e0 and e1 bracket the enumeration launch alone, so its duration is measured
-// on the stream it runs on
-void find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                    hipEvent_t e1) {
+// a.5 for one predicate code and window bound, in two passes over the
+// enumeration items.  The counting pass keeps, per item, how many triangles
+// survive the time-range filter and how many tests they carry, and counts all
+// triangles; exclusive scans give each item its first survivor slot (ws.sbase)
+// and its first test (ws.wbase, total at [NI]); the emitting pass then
+// enumerates only the items that have survivors and writes them.  e0 and e1
+// bracket the counting launch alone, so its duration is measured on the stream
+// it runs on.  Returns the number of survivors; *tri gets the triangle count.
+int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1, int64_t *tri) {
     const int32_t NI = ix.NI;
-    ws.sv.ensure(12 * (size_t)ix.T + 12);
-    ws.sw.ensure(8 * (size_t)ix.T + 8);
-    ws.su.ensure(4 * (size_t)NI + 4);
+    ws.su.ensure(4 * ((size_t)NI + 1));
     ws.wu.ensure(8 * ((size_t)NI + 1));
     ws.wbase.ensure(8 * ((size_t)NI + 1));
-    FOLTY_HIP(hipEventRecord(e0, s));
-    dispatch_variant(variant, [&](auto V) {
-        FilterSink<decltype(V)::value> sink;
-        sink.base = ix.tri_base.as<int64_t>();
+    ws.sbase.ensure(8 * ((size_t)NI + 1));
+    ws.scal.ensure(128);
+    ws.host.ensure(64);
+    unsigned long long *hits = ws.scal.as<unsigned long long>() + 8; // [0, 8) belong to the threshold step
+    k_fill<unsigned long long><<<1, 1, 0, s>>>(hits, 0ull, 1);
+    FOLTY_LAUNCHED();
+    auto sink_for = [&](auto V, auto M) {
+        FilterSink<decltype(V)::value, decltype(M)::value> sink{};
+        sink.base = ws.sbase.as<int64_t>();
         sink.rec = ix.rec.as<EdgeRec>();
+        sink.rng = ix.erng.as<uint2>();
+        sink.dq = range_slack(dmax, ix.tshift);
         sink.dmax = dmax;
         sink.variant = variant;
         sink.sv = ws.sv.as<int32_t>();
         sink.sw = ws.sw.as<int64_t>();
         sink.su = ws.su.as<int32_t>();
         sink.wu = ws.wu.as<int64_t>();
+        sink.hits = hits;
+        return sink;
+    };
+    auto run = [&](auto V, auto M, const int32_t *only) {
+        auto sink = sink_for(V, M);
         if (ix.tri_cached)
-            k_filter_cached<decltype(V)::value><<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(),
-                                                                              ix.tri.as<int32_t>(), NI, sink);
+            k_filter_cached<<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI, sink,
+                                                          only);
         else
             k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
-                                                     ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), NI, sink);
-    });
-    FOLTY_LAUNCHED();
+                                                     ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), NI, sink,
+                                                     only);
+        FOLTY_LAUNCHED();
+    };
+    using CountM = std::integral_constant<int, FILTER_COUNT>;
+    using EmitM = std::integral_constant<int, FILTER_EMIT>;
+    FOLTY_HIP(hipEventRecord(e0, s));
+    dispatch_variant(variant, [&](auto V) { run(V, CountM{}, nullptr); });
     FOLTY_HIP(hipEventRecord(e1, s));
-    // wu[NI] = 0 so that the exclusive scan leaves the total in wbase[NI]
+    // su[NI] = wu[NI] = 0 so that the exclusive scans leave the totals at [NI]
+    k_fill<int32_t><<<1, 1, 0, s>>>(ws.su.as<int32_t>() + NI, 0, 1);
     k_fill<int64_t><<<1, 1, 0, s>>>(ws.wu.as<int64_t>() + NI, (int64_t)0, 1);
-    size_t need = exclusive_scan_i64(nullptr, 0, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
+    FOLTY_LAUNCHED();
+    size_t need = std::max(
+        exclusive_scan_i64(nullptr, 0, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s),
+        exclusive_scan_i32_to_i64(nullptr, 0, ws.su.as<int32_t>(), ws.sbase.as<int64_t>(), (int64_t)NI + 1, s));
     ws.cub.ensure(need);
     exclusive_scan_i64(ws.cub.p, need, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
+    exclusive_scan_i32_to_i64(ws.cub.p, need, ws.su.as<int32_t>(), ws.sbase.as<int64_t>(), (int64_t)NI + 1, s);
+    int64_t *h = ws.host.as<int64_t>();
+    FOLTY_HIP(hipMemcpyAsync(h, ws.sbase.as<int64_t>() + NI, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(h + 1, hits, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    const int64_t survivors = h[0];
+    *tri = h[1];
+    if (survivors > 0) {
+        ws.sv.ensure(12 * (size_t)survivors);
+        ws.sw.ensure(8 * (size_t)survivors);
+        dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.su.as<int32_t>()); });
+    }
+    return survivors;
 }
 
 template <class Op>
 void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, hipStream_t s) {
     dispatch_variant(variant, [&](auto V) {
         k_temporal<decltype(V)::value, Op><<<PERSIST_BLOCKS, BLK, 0, s>>>(
-            ws.wbase.as<int64_t>(), ix.NI, ix.tri_base.as<int64_t>(), ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
+            ws.wbase.as<int64_t>(), ix.NI, ws.sbase.as<int64_t>(), ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
             ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(), dmax, op, IPT);
     });
     FOLTY_LAUNCHED();
@@ -352,6 +395,7 @@ void keep_counts(const Graph *g, const uint32_t *count, Result *res, hipStream_t
 void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     const int32_t n = ix.n, S = ix.S;
     ix.rec.ensure(sizeof(EdgeRec) * ((size_t)S + 1));
+    ix.erng.ensure(sizeof(uint2) * ((size_t)S + 1));
     ix.item_off.ensure(4 * ((size_t)n + 1));
     ix.tcnt_ready = false;
     DevBuf items, probes;
@@ -363,7 +407,7 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     if (S > 0) {
         k_edge_recs<<<grid_for(S, BLK), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), ix.soff.as<int32_t>(),
                                                                 ix.smid.as<int32_t>(), ix.ts.as<int64_t>(), S,
-                                                                ix.rec.as<EdgeRec>());
+                                                                ix.tshift, ix.rec.as<EdgeRec>(), ix.erng.as<uint2>());
         FOLTY_LAUNCHED();
     }
     k_probes<<<grid_for(n, BLK), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), n,
@@ -382,32 +426,60 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     ix.NI = ni;
     ix.probes = h[1];
     ix.item_u.ensure(4 * (size_t)ni + 4);
-    ix.tri_base.ensure(8 * ((size_t)ni + 1));
     k_item_owner<<<grid_for(n, BLK), BLK, 0, s>>>(ix.item_off.as<int32_t>(), n, ix.item_u.as<int32_t>());
     FOLTY_LAUNCHED();
-    DevBuf tri_it;
-    tri_it.ensure(4 * ((size_t)ni + 1));
-    k_fill<int32_t><<<1, 1, 0, s>>>(tri_it.as<int32_t>() + ni, 0, 1);
-    CountSink cs{tri_it.as<int32_t>(), 0};
-    k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), ix.item_u.as<int32_t>(),
-                                             ix.item_off.as<int32_t>(), ni, cs);
-    FOLTY_LAUNCHED();
-    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
-    cub.ensure(need);
-    exclusive_scan_i32_to_i64(cub.p, need, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
-    FOLTY_HIP(hipMemcpyAsync(&h[0], ix.tri_base.as<int64_t>() + ni, 8, hipMemcpyDeviceToHost, s));
-    FOLTY_HIP(hipStreamSynchronize(s));
-    ix.T = h[0];
+    // triangle slots per item are made on first use (plans, the server's memory
+    // estimate, the cached list): a single query counts its survivors itself
+    ix.T = -1;
+    ix.tri_base_ready = false;
     ix.tri_cached = false;
     ix.tri.release();
-    if (cache && ix.T > 0) {
-        ix.tri.ensure(12 * (size_t)ix.T);
-        CacheSink sink{ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), 0};
-        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), ix.item_u.as<int32_t>(),
-                                                 ix.item_off.as<int32_t>(), ni, sink);
-        FOLTY_LAUNCHED();
-        ix.tri_cached = true;
+    if (cache) {
+        ensure_tri_base(ix, s);
+        if (ix.T > 0) {
+            ix.tri.ensure(12 * (size_t)ix.T);
+            CacheSink sink{ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), 0};
+            k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
+                                                     ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), ni, sink);
+            FOLTY_LAUNCHED();
+            ix.tri_cached = true;
+        }
     }
+}
+
+// triangles of each enumeration item, their exclusive offsets (the slots of a
+// one-pass filter and of the cached list) and the triangle count
+void ensure_tri_base(Index &ix, hipStream_t s) {
+    if (ix.tri_base_ready) return;
+    const int32_t ni = ix.NI;
+    ix.tri_base.ensure(8 * ((size_t)ni + 1));
+    DevBuf tri_it, cub;
+    tri_it.ensure(4 * ((size_t)ni + 1));
+    k_fill<int32_t><<<1, 1, 0, s>>>(tri_it.as<int32_t>() + ni, 0, 1);
+    FOLTY_LAUNCHED();
+    if (ni > 0) {
+        CountSink cs{tri_it.as<int32_t>(), 0};
+        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
+                                                 ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), ni, cs);
+        FOLTY_LAUNCHED();
+    }
+    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(),
+                                            (int64_t)ni + 1, s);
+    cub.ensure(need);
+    exclusive_scan_i32_to_i64(cub.p, need, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
+    int64_t T = 0;
+    FOLTY_HIP(hipMemcpyAsync(&T, ix.tri_base.as<int64_t>() + ni, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    ix.T = T;
+    ix.tri_base_ready = true;
+}
+
+void ensure_triangles(Graph *g) {
+    std::lock_guard<std::mutex> lk(g->lazy_mu);
+    if (g->ix.tri_base_ready || !g->ix.built) return;
+    FOLTY_HIP(hipSetDevice(g->device));
+    StreamScope sc(g->stream);
+    ensure_tri_base(g->ix, g->stream);
 }
 
 void ensure_tcnt(Index &ix, hipStream_t s) {
@@ -457,16 +529,19 @@ Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t 
         k_fill<uint32_t><<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, 0u, ix.m);
         FOLTY_LAUNCHED();
     }
-    int64_t tests = 0;
-    if (ix.T > 0) {
-        find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5]);
-        DirectOp op{q.delta, count};
-        launch_temporal(ix, q.variant, q.delta, ws, op, s);
-        FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
+    int64_t tests = 0, tri = 0;
+    if (ix.NI > 0) {
+        const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri);
+        if (survivors > 0) {
+            DirectOp op{q.delta, count};
+            launch_temporal(ix, q.variant, q.delta, ws, op, s);
+            FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
+        }
     } else {
         FOLTY_HIP(hipEventRecord(ws.ev[4], s));
         FOLTY_HIP(hipEventRecord(ws.ev[5], s));
     }
+    if (ix.T < 0) ix.T = tri; // every query enumerates every triangle once
     FOLTY_HIP(hipEventRecord(ws.ev[2], s));
     finish_query(g, q, count, ws, res.get(), s);
     FOLTY_HIP(hipEventRecord(ws.ev[3], s));

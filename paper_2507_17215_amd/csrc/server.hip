@@ -31,7 +31,7 @@ int64_t query_footprint(const Graph *g) {
     const Index &ix = g->ix;
     int64_t b = 0;
     b += 4 * (int64_t)ix.m;                // counts (or one histogram level)
-    b += 20 * ix.T;                        // survivors
+    b += 20 * ix.T + 8 * (int64_t)ix.NI;   // survivors and their slots
     b += 4 * (int64_t)ix.NI + 16 * ((int64_t)ix.NI + 1);
     b += 8 * (int64_t)ix.S + 24 * (int64_t)ix.S; // certificates per pair + pair keys
     b += 4 * ix.m_input;                   // per-edge counts handed back
@@ -194,6 +194,7 @@ Server *server_create(const folty_server_opts *o) {
 
 int64_t server_submit(Server *S, Graph *g, const folty_query &q) {
     check_query(g, q);
+    ensure_triangles(g); // the footprint bound needs the triangle count
     const int64_t bytes = query_footprint(g);
     std::lock_guard<std::mutex> lk(S->mu);
     if (bytes > S->budget) {

@@ -244,6 +244,7 @@ struct CountSink {
     __device__ void end(int64_t u) {
         if (lane_id() == 0) tri_u[u] = c;
     }
+    __device__ void finish() {}
 };
 
 struct CacheSink {
@@ -262,6 +263,7 @@ struct CacheSink {
         slot += __popcll(mask);
     }
     __device__ void end(int64_t) {}
+    __device__ void finish() {}
 };
 
 struct TcntSink {
@@ -276,71 +278,96 @@ struct TcntSink {
         }
     }
     __device__ void end(int64_t) {}
+    __device__ void finish() {}
 };
 
-// first and last timestamp over both directed lists of an oriented edge
-__device__ inline void edge_range(const EdgeRec *__restrict__ rec, int32_t p, int64_t &lo, int64_t &hi) {
-    Span f, b;
-    rec_spans(rec, p, f, b);
-    lo = INT64_MAX;
-    hi = INT64_MIN;
-    if (f.n) { lo = f.lo; hi = f.hi; }
-    if (b.n) { lo = b.lo < lo ? b.lo : lo; hi = b.hi > hi ? b.hi : hi; }
+// Slack of the range test on timestamps shifted right by `shift`: floors of two
+// values differ by at most one unit more than their difference does.
+__host__ __device__ inline int64_t range_slack(int64_t dmax, int32_t shift) {
+    return shift ? (dmax >> shift) + 1 : dmax;
 }
 
-// Keeps triangles with at least one run that can count, in the slots of their
-// item, with each survivor's test offset inside that item.  Every run uses one
-// list of each of the three edges, and its three timestamps lie within dmax of
-// each other, so the two edges at u must have time ranges within dmax of each
-// other before the third edge is read at all.
+// two oriented edges can share a run only if their time ranges come within dmax
+__device__ inline bool ranges_meet(uint2 x, uint2 y, int64_t dq) {
+    return (int64_t)x.x - (int64_t)y.y <= dq && (int64_t)y.x - (int64_t)x.y <= dq;
+}
+
+// What a filter pass does with the triangles it keeps.
+enum FilterMode {
+    FILTER_COUNT = 0, // survivors and tests per item, triangles seen; writes no survivor
+    FILTER_EMIT = 1,  // survivors into their item's slots (offsets from a counting pass)
+    FILTER_BOTH = 2,  // both, into slots sized by the item's triangle count
+};
+
+// Keeps triangles with at least one run that can count, with each survivor's
+// test offset inside its item.  Every run uses one list of each of the three
+// edges, and its three timestamps lie within dmax of each other, so the edges'
+// time ranges must pairwise come within dmax: the two edges at u are tested
+// first, the third edge's range next (8 bytes each), and only then are the three
+// edge records read.  The enumeration order inside an item is fixed, so a
+// counting pass and a later emitting pass agree on every survivor's position.
 // VAR < 0: the predicate code is read from `variant` at run time
-template <int VAR> struct FilterSink {
-    const int64_t *base;
+template <int VAR, int MODE> struct FilterSink {
+    const int64_t *base; // EMIT, BOTH: first survivor slot of each item
     const EdgeRec *rec;
+    const uint2 *rng; // per oriented edge: (first, last) timestamp >> shift
+    int64_t dq;       // range_slack(dmax, shift)
     int64_t dmax;
     int variant;
-    int32_t *sv;
-    int64_t *sw;
-    int32_t *su;
-    int64_t *wu;
+    int32_t *sv;      // EMIT, BOTH: survivors (three oriented edges each)
+    int64_t *sw;      // EMIT, BOTH: test offset of each survivor inside its item
+    int32_t *su;      // COUNT, BOTH: survivors per item
+    int64_t *wu;      // COUNT, BOTH: tests per item
+    unsigned long long *hits; // COUNT: triangles seen (added once per wavefront)
     int64_t slot;
     int32_t ns;
     int64_t work;
+    unsigned long long nhit;
     __device__ void begin(int64_t it) {
-        slot = base[it];
+        if constexpr (MODE != FILTER_COUNT) slot = base[it];
         ns = 0;
         work = 0;
     }
     __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
+        if constexpr (MODE == FILTER_COUNT) nhit += (unsigned long long)__popcll(__ballot(h));
         int64_t wk = 0;
         if (h) {
-            int64_t alo, ahi, blo, bhi;
-            edge_range(rec, a, alo, ahi);
-            edge_range(rec, b, blo, bhi);
-            bool ranges = alo <= ahi && blo <= bhi; // every static edge has at least one temporal edge
-            if (ranges && alo - bhi <= dmax && blo - ahi <= dmax) {
-                if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
-                else wk = tri_work_rt(variant, load_lists(rec, a, b, c), dmax);
+            const uint2 ra = rng[a], rb = rng[b];
+            if (ranges_meet(ra, rb, dq)) {
+                const uint2 rc = rng[c];
+                if (ranges_meet(ra, rc, dq) && ranges_meet(rb, rc, dq)) {
+                    if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
+                    else wk = tri_work_rt(variant, load_lists(rec, a, b, c), dmax);
+                }
             }
         }
         bool keep = wk > 0;
         unsigned long long mask = __ballot(keep);
         if (!mask) return;
         int64_t incl = wave_inclusive_sum(wk);
-        if (keep) {
-            int64_t pos = slot + ns + __popcll(mask & lanes_below());
-            sv[3 * pos] = a;
-            sv[3 * pos + 1] = b;
-            sv[3 * pos + 2] = c;
-            sw[pos] = work + incl - wk;
+        if constexpr (MODE != FILTER_COUNT) {
+            if (keep) {
+                int64_t pos = slot + ns + __popcll(mask & lanes_below());
+                sv[3 * pos] = a;
+                sv[3 * pos + 1] = b;
+                sv[3 * pos + 2] = c;
+                sw[pos] = work + incl - wk;
+            }
         }
         ns += (int32_t)__popcll(mask);
         work += __shfl(incl, 63);
     }
     __device__ void end(int64_t it) {
-        if (lane_id() == 0) {
-            su[it] = ns;
-            wu[it] = work;
+        if constexpr (MODE != FILTER_EMIT) {
+            if (lane_id() == 0) {
+                su[it] = ns;
+                wu[it] = work;
+            }
+        }
+    }
+    __device__ void finish() {
+        if constexpr (MODE == FILTER_COUNT) {
+            if (lane_id() == 0 && nhit) atomicAdd(hits, nhit);
         }
     }
 };
@@ -384,13 +411,19 @@ __device__ inline void enum_item(const int32_t *__restrict__ ooff, const int32_t
             bool hit = false;
             int32_t pa = 0, pb = 0, pc = 0;
             if (q < q_end) {
-                int32_t lo = i, hi = d;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi) >> 1;
-                    if (PRE[mid + 1] <= q) lo = mid + 1;
-                    else hi = mid;
+                // the segment of q (the i with PRE[i] <= q < PRE[i+1]); q grows by 64
+                // per step and segments average far more than that, so walk a few
+                // segments forward before bisecting.  PRE[d] > q stops both.
+                for (int k = 0; k < 4 && PRE[i + 1] <= q; k++) i++;
+                if (PRE[i + 1] <= q) {
+                    int32_t lo = i + 1, hi = d;
+                    while (lo < hi) {
+                        int32_t mid = (lo + hi) >> 1;
+                        if (PRE[mid + 1] <= q) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    i = lo;
                 }
-                i = lo;
                 const int32_t p = VO[i] + (q - PRE[i]);
                 const int32_t x = oadj[p];
                 int32_t a = i + 1, c = d; // x > v_i, so it can only sit after i
@@ -452,25 +485,34 @@ __device__ inline void cached_item(const int64_t *__restrict__ base, const int32
 // One wavefront per item: the item's vertex u, and a range of the flattened
 // wedge space of u (position q = sum of |N+(v_j)| over j < i, plus the position
 // of x in N+(v_i)).
+// only != nullptr: items with only[it] == 0 are skipped
 template <class Sink>
 __global__ __launch_bounds__(BLK) void k_tri_enum(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
                                                   const int32_t *__restrict__ item_u,
-                                                  const int32_t *__restrict__ item_off, int32_t NI, Sink sink) {
+                                                  const int32_t *__restrict__ item_off, int32_t NI, Sink sink,
+                                                  const int32_t *__restrict__ only = nullptr) {
     __shared__ int32_t s_nu[WPB][CAP];
     __shared__ int32_t s_vo[WPB][CAP];
     __shared__ int32_t s_pre[WPB][CAP + 1];
     const int w = threadIdx.x >> 6;
-    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB)
+    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
+        if (only && only[it] == 0) continue;
         enum_item(ooff, oadj, item_u, item_off, it, sink, s_nu[w], s_vo[w], s_pre[w]);
+    }
+    sink.finish();
 }
 
 // cached triangle list: the same filter, one wavefront per item
-template <int VAR>
+template <int VAR, int MODE>
 __global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict__ base, const int32_t *__restrict__ tri,
-                                                       int32_t NI, FilterSink<VAR> sink) {
+                                                       int32_t NI, FilterSink<VAR, MODE> sink,
+                                                       const int32_t *__restrict__ only = nullptr) {
     const int w = threadIdx.x >> 6;
-    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB)
+    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
+        if (only && only[it] == 0) continue;
         cached_item(base, tri, it, sink);
+    }
+    sink.finish();
 }
 
 // ---------------------------------------------------------------------------
