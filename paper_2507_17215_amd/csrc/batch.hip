@@ -67,9 +67,7 @@ __device__ inline int32_t owner_of(const int64_t *__restrict__ base, int32_t n, 
 
 __global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__ jobs, int32_t nj,
                                                       const int64_t *__restrict__ job_item_base, int64_t items) {
-    __shared__ int32_t s_nu[WPB][CAP];
-    __shared__ int32_t s_vo[WPB][CAP];
-    __shared__ int32_t s_pre[WPB][CAP + 1];
+    __shared__ EnumLds lds[WPB];
     const int w = threadIdx.x >> 6;
     for (int64_t g = (int64_t)blockIdx.x * WPB + w; g < items; g += (int64_t)gridDim.x * WPB) {
         const int32_t j = owner_of(job_item_base, nj, g);
@@ -87,7 +85,7 @@ __global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__
         sink.su = J.su;
         sink.wu = J.wu;
         if (J.tri) cached_item(J.tri_base, J.tri, it, sink);
-        else enum_item(J.ooff, J.oadj, J.item_u, J.item_off, it, sink, s_nu[w], s_vo[w], s_pre[w]);
+        else enum_item(J.ooff, J.oadj, J.item_u, J.item_off, it, sink, lds[w]);
     }
 }
 

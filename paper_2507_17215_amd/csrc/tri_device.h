@@ -244,6 +244,7 @@ struct CountSink {
     __device__ void end(int64_t u) {
         if (lane_id() == 0) tri_u[u] = c;
     }
+    __device__ void prefetch(int32_t, int32_t) {}
     __device__ void finish() {}
 };
 
@@ -263,6 +264,7 @@ struct CacheSink {
         slot += __popcll(mask);
     }
     __device__ void end(int64_t) {}
+    __device__ void prefetch(int32_t, int32_t) {}
     __device__ void finish() {}
 };
 
@@ -278,6 +280,7 @@ struct TcntSink {
         }
     }
     __device__ void end(int64_t) {}
+    __device__ void prefetch(int32_t, int32_t) {}
     __device__ void finish() {}
 };
 
@@ -323,6 +326,13 @@ template <int VAR, int MODE> struct FilterSink {
     int32_t ns;
     int64_t work;
     unsigned long long nhit;
+    uint2 pra, prc; // ranges of the edges (u, v) and (v, w) of the next hit, loaded early
+    // called for every probe that may hit, before hit(): edges (u, v) and (v, w)
+    // are known before the search that finds (u, w)
+    __device__ void prefetch(int32_t a, int32_t c) {
+        pra = rng[a];
+        prc = rng[c];
+    }
     __device__ void begin(int64_t it) {
         if constexpr (MODE != FILTER_COUNT) slot = base[it];
         ns = 0;
@@ -332,13 +342,10 @@ template <int VAR, int MODE> struct FilterSink {
         if constexpr (MODE == FILTER_COUNT) nhit += (unsigned long long)__popcll(__ballot(h));
         int64_t wk = 0;
         if (h) {
-            const uint2 ra = rng[a], rb = rng[b];
-            if (ranges_meet(ra, rb, dq)) {
-                const uint2 rc = rng[c];
-                if (ranges_meet(ra, rc, dq) && ranges_meet(rb, rc, dq)) {
-                    if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
-                    else wk = tri_work_rt(variant, load_lists(rec, a, b, c), dmax);
-                }
+            const uint2 rb = rng[b];
+            if (ranges_meet(pra, rb, dq) && ranges_meet(pra, prc, dq) && ranges_meet(rb, prc, dq)) {
+                if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
+                else wk = tri_work_rt(variant, load_lists(rec, a, b, c), dmax);
             }
         }
         bool keep = wk > 0;
@@ -372,72 +379,163 @@ template <int VAR, int MODE> struct FilterSink {
     }
 };
 
+// LDS of one wavefront's enumeration item.  The bitmap holds one hash bit per
+// vertex of N+(u), so a probe whose bit is clear misses without a search; the
+// other probes (the hits and a few collisions) wait in a queue until 64 of them
+// fill a wavefront, which then searches N+(u) exactly and hands its triangles
+// to the sink.  Only about one probe in seven reaches the search.  8 KB per
+// wavefront.
+constexpr int BM_LOG = 13;                  // 8192 bits
+constexpr int BM_WORDS = 1 << (BM_LOG - 5);
+constexpr int QCAP = 128;                   // < 64 waiting + one step's 64
+constexpr int ENUM_UNROLL = 4;              // probe steps whose loads overlap
+constexpr int Q_SHIFT = 12;                 // CHUNK = 2^12 probes per item
+struct EnumLds {
+    int32_t nu[CAP];      // N+(u), ascending
+    int32_t off[CAP];     // row start of v_i minus PRE[i]: probe q reads oadj[off[i] + q]
+    int32_t pre[CAP];     // PRE[i+1] = sum of |N+(v_j)| over j <= i
+    uint32_t bm[BM_WORDS];
+    int32_t qx[QCAP];     // waiting probes: x
+    int32_t qr[QCAP];     // and (q - first probe of the item) | i << Q_SHIFT
+};
+static_assert(CHUNK == (1 << Q_SHIFT) && CAP <= (1 << (31 - Q_SHIFT)), "queue packing");
+
+__device__ inline uint32_t bm_hash(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - BM_LOG); }
+
+// the first cnt waiting probes, one per lane: exact search of x in N+(u) after v_i
+template <class Sink>
+__device__ inline void enum_batch(int32_t b, int32_t d, int32_t q_begin, const EnumLds &L, int32_t cnt,
+                                  Sink &sink) {
+    const int lane = lane_id();
+    bool hit = false;
+    int32_t pa = 0, pb = 0, pc = 0;
+    if (lane < cnt) {
+        const int32_t x = L.qx[lane], r = L.qr[lane];
+        const int32_t i = r >> Q_SHIFT;
+        pa = b + i;
+        pc = L.off[i] + q_begin + (r & (CHUNK - 1));
+        sink.prefetch(pa, pc);
+        int32_t a = i + 1, c = d; // x > v_i, so it can only sit after i
+        while (a < c) {
+            int32_t mid = (a + c) >> 1;
+            if (L.nu[mid] < x) a = mid + 1;
+            else c = mid;
+        }
+        hit = a < d && L.nu[a] == x;
+        pb = b + a;
+    }
+    sink.hit(hit, pa, pb, pc);
+}
+
 // One wavefront per item: the item's vertex u, and a range of the flattened
 // wedge space of u (position q = sum of |N+(v_j)| over j < i, plus the position
-// of x in N+(v_i)).
+// of x in N+(v_i)).  Sinks see the triangles of an item in a fixed order.
 template <class Sink>
 __device__ inline void enum_item(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
                                  const int32_t *__restrict__ item_u, const int32_t *__restrict__ item_off, int64_t it,
-                                 Sink &sink, int32_t *NU, int32_t *VO, int32_t *PRE) {
+                                 Sink &sink, EnumLds &L) {
     const int lane = lane_id();
     const int32_t u = item_u[it];
     const int32_t part = (int32_t)(it - item_off[u]);
     const int32_t b = ooff[u], d = ooff[u + 1] - b;
     sink.begin(it);
     if (d >= 2 && d <= CAP) {
-        // stage N+(u), the row start of each v and a prefix of |N+(v)|
+        // stage N+(u), each v's row start and a prefix of |N+(v)|
         int32_t carry = 0;
         for (int32_t i0 = 0; i0 < d; i0 += 64) {
-            int32_t i = i0 + lane;
-            int32_t dv = 0;
+            const int32_t i = i0 + lane;
+            int32_t dv = 0, vo = 0;
             if (i < d) {
-                int32_t v = oadj[b + i];
-                int32_t vo = ooff[v];
+                const int32_t v = oadj[b + i];
+                vo = ooff[v];
                 dv = ooff[v + 1] - vo;
-                NU[i] = v;
-                VO[i] = vo;
+                L.nu[i] = v;
             }
-            int32_t x = wave_inclusive_sum(dv);
-            if (i < d) PRE[i + 1] = carry + x;
+            const int32_t x = wave_inclusive_sum(dv);
+            if (i < d) {
+                L.pre[i] = carry + x;
+                L.off[i] = vo - (carry + x - dv);
+            }
             carry += __shfl(x, 63);
         }
-        if (lane == 0) PRE[0] = 0;
+        for (int w = lane; w < BM_WORDS; w += 64) L.bm[w] = 0;
+        wave_sync();
+        for (int32_t i = lane; i < d; i += 64) {
+            const uint32_t h = bm_hash(L.nu[i]);
+            atomicOr(&L.bm[h >> 5], 1u << (h & 31));
+        }
         wave_sync();
         const int32_t q_begin = part * CHUNK;
         const int32_t q_end = carry < q_begin + CHUNK ? carry : q_begin + CHUNK;
         int32_t i = 0; // this lane's segment; q only grows, so i only grows
-        for (int32_t q0 = q_begin; q0 < q_end; q0 += 64) {
-            int32_t q = q0 + lane;
-            bool hit = false;
-            int32_t pa = 0, pb = 0, pc = 0;
-            if (q < q_end) {
-                // the segment of q (the i with PRE[i] <= q < PRE[i+1]); q grows by 64
-                // per step and segments average far more than that, so walk a few
-                // segments forward before bisecting.  PRE[d] > q stops both.
-                for (int k = 0; k < 4 && PRE[i + 1] <= q; k++) i++;
-                if (PRE[i + 1] <= q) {
-                    int32_t lo = i + 1, hi = d;
-                    while (lo < hi) {
-                        int32_t mid = (lo + hi) >> 1;
-                        if (PRE[mid + 1] <= q) lo = mid + 1;
-                        else hi = mid;
+        int32_t qn = 0; // waiting probes (wave-uniform)
+        // ENUM_UNROLL steps of 64 probes at a time: their loads of x are all in
+        // flight before the first is used
+        for (int32_t q0 = q_begin; q0 < q_end; q0 += 64 * ENUM_UNROLL) {
+            int32_t rk[ENUM_UNROLL], xk[ENUM_UNROLL];
+            bool vk[ENUM_UNROLL];
+#pragma unroll
+            for (int k = 0; k < ENUM_UNROLL; k++) {
+                const int32_t q = q0 + 64 * k + lane;
+                vk[k] = q < q_end;
+                xk[k] = 0;
+                rk[k] = 0;
+                if (vk[k]) {
+                    // the segment of q (the i with PRE[i] <= q < PRE[i+1]); q grows by
+                    // 64 per step and segments average far more than that, so walk a
+                    // few segments forward before bisecting.  PRE[d] > q stops both.
+                    for (int w = 0; w < 4 && L.pre[i] <= q; w++) i++;
+                    if (L.pre[i] <= q) {
+                        int32_t lo = i + 1, hi = d;
+                        while (lo < hi) {
+                            int32_t mid = (lo + hi) >> 1;
+                            if (L.pre[mid] <= q) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        i = lo;
                     }
-                    i = lo;
+                    xk[k] = L.off[i] + q; // position of x, replaced by x below
+                    rk[k] = (q - q_begin) | (i << Q_SHIFT);
                 }
-                const int32_t p = VO[i] + (q - PRE[i]);
-                const int32_t x = oadj[p];
-                int32_t a = i + 1, c = d; // x > v_i, so it can only sit after i
-                while (a < c) {
-                    int32_t mid = (a + c) >> 1;
-                    if (NU[mid] < x) a = mid + 1;
-                    else c = mid;
-                }
-                hit = a < d && NU[a] == x;
-                pa = b + i;
-                pb = b + a;
-                pc = p;
             }
-            sink.hit(hit, pa, pb, pc);
+#pragma unroll
+            for (int k = 0; k < ENUM_UNROLL; k++) xk[k] = vk[k] ? oadj[xk[k]] : 0;
+#pragma unroll
+            for (int k = 0; k < ENUM_UNROLL; k++) {
+                bool cand = false;
+                if (vk[k]) {
+                    const uint32_t h = bm_hash(xk[k]);
+                    cand = (L.bm[h >> 5] >> (h & 31)) & 1u;
+                }
+                const unsigned long long mask = __ballot(cand);
+                if (cand) {
+                    const int32_t slot = qn + (int32_t)__popcll(mask & lanes_below());
+                    L.qx[slot] = xk[k];
+                    L.qr[slot] = rk[k];
+                }
+                qn += (int32_t)__popcll(mask);
+                if (qn >= 64) {
+                    wave_sync();
+                    enum_batch(b, d, q_begin, L, 64, sink);
+                    const int32_t rest = qn - 64;
+                    int32_t tx = 0, tr = 0;
+                    if (lane < rest) {
+                        tx = L.qx[64 + lane];
+                        tr = L.qr[64 + lane];
+                    }
+                    wave_sync();
+                    if (lane < rest) {
+                        L.qx[lane] = tx;
+                        L.qr[lane] = tr;
+                    }
+                    qn = rest;
+                    wave_sync();
+                }
+            }
+        }
+        if (qn > 0) {
+            wave_sync();
+            enum_batch(b, d, q_begin, L, qn, sink);
         }
         wave_sync(); // the next item overwrites this wave's LDS
     } else if (d > CAP) {
@@ -451,6 +549,7 @@ __device__ inline void enum_item(const int32_t *__restrict__ ooff, const int32_t
                 bool hit = false;
                 int32_t a = i + 1;
                 if (p < ve) {
+                    sink.prefetch(b + i, p);
                     const int32_t x = oadj[p];
                     int32_t c = d;
                     while (a < c) {
@@ -477,6 +576,7 @@ __device__ inline void cached_item(const int64_t *__restrict__ base, const int32
     for (int64_t p0 = b; p0 < e; p0 += 64) {
         int64_t p = p0 + lane;
         bool valid = p < e;
+        if (valid) sink.prefetch(tri[3 * p], tri[3 * p + 2]);
         sink.hit(valid, valid ? tri[3 * p] : 0, valid ? tri[3 * p + 1] : 0, valid ? tri[3 * p + 2] : 0);
     }
     sink.end(it);
@@ -491,13 +591,11 @@ __global__ __launch_bounds__(BLK) void k_tri_enum(const int32_t *__restrict__ oo
                                                   const int32_t *__restrict__ item_u,
                                                   const int32_t *__restrict__ item_off, int32_t NI, Sink sink,
                                                   const int32_t *__restrict__ only = nullptr) {
-    __shared__ int32_t s_nu[WPB][CAP];
-    __shared__ int32_t s_vo[WPB][CAP];
-    __shared__ int32_t s_pre[WPB][CAP + 1];
+    __shared__ EnumLds lds[WPB];
     const int w = threadIdx.x >> 6;
     for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
         if (only && only[it] == 0) continue;
-        enum_item(ooff, oadj, item_u, item_off, it, sink, s_nu[w], s_vo[w], s_pre[w]);
+        enum_item(ooff, oadj, item_u, item_off, it, sink, lds[w]);
     }
     sink.finish();
 }
