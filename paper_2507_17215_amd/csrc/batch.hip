@@ -12,8 +12,9 @@
 //   filter   one grid over the enumeration items of all jobs (wave per item)
 //   scan     one exclusive scan over all items' test counts
 //   temporal one persistent grid over all surviving tests of all jobs
-//   prefix   one grid over the edges of all jobs
-//   threshold, pairs   one grid each over all queries' edges / pair slots
+//   threshold one grid over the edges of all jobs: running sum over the levels
+//            and every query of the job at its level, each edge read once
+//   pairs    one grid over all queries' pair slots
 //   sort     one radix sort of (query, u, v) keys
 // The launches from filter to pairs are captured once in a hipGraph and
 // replayed.  The temporal kernel's chunk size and grid are picked by timing a
@@ -30,7 +31,9 @@ namespace folty {
 namespace {
 
 struct JobDev {
-    const int32_t *ooff, *oadj, *item_u, *item_off, *tri;
+    const int4 *item;
+    const int2 *vrow;
+    const int32_t *oadj, *tri;
     const int64_t *tri_base, *ts;
     const EdgeRec *rec;
     const uint2 *rng;
@@ -43,12 +46,16 @@ struct JobDev {
     int64_t *sw;
     int32_t *su;
     int64_t *wu; // this job's slice of the concatenated per-item test counts
+    // threshold step: the graph's static edge table and degrees, and the job's
+    // queries (positions jq[q0, q1) of the plan's job-sorted query order, by level)
+    const int32_t *sid, *smid, *slo, *shi, *deg, *tcnt;
+    int32_t q0, q1;
+    int32_t keep_prefix; // some query of the job hands back its per-edge counts
 };
 
 struct QueryDev {
-    const uint32_t *count; // the job's histogram at the query's level
-    const int32_t *sid, *smid, *slo, *shi, *deg, *tcnt;
-    int32_t m, S;
+    const int32_t *slo, *shi; // the graph's static edge endpoints (pair output)
+    int32_t level;            // index of the query's delta among its job's levels
     uint32_t num, den;
     int32_t universe, excl;
     int64_t p_base; // first slot of this query in the concatenated 2S pair slots
@@ -85,7 +92,10 @@ __global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__
         sink.su = J.su;
         sink.wu = J.wu;
         if (J.tri) cached_item(J.tri_base, J.tri, it, sink);
-        else enum_item(J.ooff, J.oadj, J.item_u, J.item_off, it, sink, lds[w]);
+        else {
+            const int4 item = J.item[it];
+            enum_item(item, stage_ahead(item, J.oadj, J.vrow), J.oadj, J.vrow, it, sink, lds[w]);
+        }
     }
 }
 
@@ -134,21 +144,6 @@ __global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict
     }
 }
 
-// running sums over each job's window levels
-__global__ void k_multi_prefix(const JobDev *__restrict__ jobs, int32_t nj, const int64_t *__restrict__ job_m_base,
-                               int64_t total_m) {
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total_m; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t j = owner_of(job_m_base, nj, x);
-        const JobDev &J = jobs[j];
-        const int64_t e = x - job_m_base[j];
-        uint32_t acc = 0;
-        for (int l = 0; l < J.nl; l++) {
-            acc += J.hist[(int64_t)l * J.m + e];
-            J.hist[(int64_t)l * J.m + e] = acc;
-        }
-    }
-}
-
 // segmented count of set flags over runs of equal keys inside the wave: one
 // atomic per run
 __device__ inline void wave_segment_count(int64_t key, bool in, bool flag, uint32_t *target_base) {
@@ -169,33 +164,59 @@ __device__ inline void wave_segment_count(int64_t key, bool in, bool flag, uint3
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_multi_threshold(const QueryDev *__restrict__ qs, int32_t nq,
-                                                         const int64_t *__restrict__ q_e_base, int64_t total_e,
-                                                         uint32_t *__restrict__ ncert, uint32_t *__restrict__ qcert) {
+// Threshold step of every query, one pass per job: each temporal edge is read
+// once, its histogram over the job's window levels is summed level by level
+// in a register (count[e] at each delta of the job), and at each level the
+// job's queries of that delta test count * den >= num * |U|.  Certificates are
+// counted per (query, directed pair) with one atomic per run of a wavefront,
+// and per query.  Every wavefront lies inside one job (job slices are padded to
+// 64 edges), so the per-query loop and its ballots are uniform.
+__global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict__ jobs, int32_t nj,
+                                                       const int64_t *__restrict__ job_w_base, int64_t total_w,
+                                                       const QueryDev *__restrict__ qs,
+                                                       const int32_t *__restrict__ jq,
+                                                       uint32_t *__restrict__ ncert, uint32_t *__restrict__ qcert) {
+    const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_e; x0 += stride) {
-        const int64_t x = x0 + lane_id();
-        const bool in = x < total_e;
-        int64_t key = -1, qkey = -1;
-        bool cert = false;
+    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_w; x0 += stride) {
+        const int32_t j = owner_of(job_w_base, nj, x0);
+        const JobDev &J = jobs[j];
+        const int64_t e = x0 - job_w_base[j] + lane;
+        const bool in = e < J.m;
+        int32_t s = 0, dir = 0, du = 0, da = 0, tc = 0;
         if (in) {
-            const int32_t q = owner_of(q_e_base, nq, x);
-            const QueryDev &Q = qs[q];
-            const int64_t k = x - q_e_base[q];
-            int32_t s = Q.sid[k];
-            int dir = k >= Q.smid[s] ? 1 : 0;
-            int32_t a = dir ? Q.shi[s] : Q.slo[s];
-            int32_t b = dir ? Q.slo[s] : Q.shi[s];
-            int64_t U;
-            if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)Q.deg[b] - Q.excl;
-            else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)Q.deg[a] - Q.excl;
-            else U = Q.tcnt[s];
-            cert = (uint64_t)Q.count[k] * Q.den >= (uint64_t)Q.num * (uint64_t)U;
-            key = Q.p_base + 2 * (int64_t)s + dir;
-            qkey = q;
+            s = J.sid[e];
+            dir = e >= J.smid[s] ? 1 : 0;
+            const int32_t a = dir ? J.shi[s] : J.slo[s];
+            const int32_t b = dir ? J.slo[s] : J.shi[s];
+            du = J.deg[b];
+            da = J.deg[a];
+            if (J.tcnt) tc = J.tcnt[s];
         }
-        wave_segment_count(key, in, cert, ncert);
-        wave_segment_count(qkey, in, cert, qcert);
+        uint32_t acc = 0;
+        int32_t qi = J.q0;
+        for (int32_t l = 0; l < J.nl; l++) {
+            if (in) {
+                uint32_t *h = J.hist + (int64_t)l * J.m + e;
+                acc += *h;
+                if (J.keep_prefix) *h = acc;
+            }
+            for (; qi < J.q1; qi++) {
+                const int32_t q = jq[qi];
+                const QueryDev &Q = qs[q];
+                if (Q.level != l) break;
+                int64_t U;
+                if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)du - Q.excl;
+                else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)da - Q.excl;
+                else U = tc;
+                const bool cert = in && (uint64_t)acc * Q.den >= (uint64_t)Q.num * (uint64_t)U;
+                const unsigned long long mask = __ballot(cert);
+                if (mask) {
+                    wave_segment_count(in ? Q.p_base + 2 * (int64_t)s + dir : -1, in, cert, ncert);
+                    if (lane == 0) atomicAdd(&qcert[q], (uint32_t)__popcll(mask));
+                }
+            }
+        }
     }
 }
 
@@ -260,11 +281,11 @@ struct Plan {
     };
     std::vector<Job> jobs;
     std::vector<int32_t> qjob, qlevel;
-    std::vector<int64_t> job_item_base, job_m_base, q_e_base;
-    int64_t items = 0, total_m = 0, total_e = 0, total_p = 0;
+    std::vector<int64_t> job_item_base, job_w_base;
+    int64_t items = 0, total_w = 0, total_p = 0;
     int nbits = 0;
     // device memory
-    DevBuf d_jobs, d_job_item_base, d_job_m_base, d_queries, d_q_e_base;
+    DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_jq;
     std::vector<DevBuf> hist, lv, sv, sw, su;
     DevBuf wu, wbase, ncert, qcert, npairs, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
@@ -296,9 +317,9 @@ Plan::~Plan() {
         su.clear();
         d_jobs.release();
         d_job_item_base.release();
-        d_job_m_base.release();
+        d_job_w_base.release();
         d_queries.release();
-        d_q_e_base.release();
+        d_jq.release();
         wu.release();
         wbase.release();
         ncert.release();
@@ -338,15 +359,10 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
                                                    P.wbase.as<int64_t>(), P.ipt);
         FOLTY_LAUNCHED();
     }
-    if (P.total_m > 0) {
-        k_multi_prefix<<<grid_for(P.total_m, BLK, 8192), BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj,
-                                                                      P.d_job_m_base.as<int64_t>(), P.total_m);
-        FOLTY_LAUNCHED();
-    }
-    if (P.total_e > 0) {
-        k_multi_threshold<<<grid_for(P.total_e, BLK, 8192), BLK, 0, s>>>(
-            P.d_queries.as<QueryDev>(), nq, P.d_q_e_base.as<int64_t>(), P.total_e, P.ncert.as<uint32_t>(),
-            P.qcert.as<uint32_t>());
+    if (P.total_w > 0) {
+        k_job_threshold<<<grid_for(P.total_w, BLK, 8192), BLK, 0, s>>>(
+            P.d_jobs.as<JobDev>(), nj, P.d_job_w_base.as<int64_t>(), P.total_w, P.d_queries.as<QueryDev>(),
+            P.d_jq.as<int32_t>(), P.ncert.as<uint32_t>(), P.qcert.as<uint32_t>());
         FOLTY_LAUNCHED();
     }
     if (P.total_p > 0) {
@@ -480,13 +496,23 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     P->su.resize(nj);
     std::vector<JobDev> jd(nj);
     P->job_item_base.assign(nj + 1, 0);
-    P->job_m_base.assign(nj + 1, 0);
+    P->job_w_base.assign(nj + 1, 0);
     for (int j = 0; j < nj; j++) {
         P->job_item_base[j + 1] = P->job_item_base[j] + P->graphs[P->jobs[j].graph]->ix.NI;
-        P->job_m_base[j + 1] = P->job_m_base[j] + P->graphs[P->jobs[j].graph]->ix.m;
+        // each job's edges start on a wavefront boundary
+        P->job_w_base[j + 1] = P->job_w_base[j] + (((int64_t)P->graphs[P->jobs[j].graph]->ix.m + 63) & ~63ll);
     }
     P->items = P->job_item_base[nj];
-    P->total_m = P->job_m_base[nj];
+    P->total_w = P->job_w_base[nj];
+    // the plan's queries grouped by job, each job's by level
+    std::vector<int32_t> jq(nq);
+    for (int q = 0; q < nq; q++) jq[q] = q;
+    std::stable_sort(jq.begin(), jq.end(), [&](int32_t x, int32_t y) {
+        return P->qjob[x] != P->qjob[y] ? P->qjob[x] < P->qjob[y] : P->qlevel[x] < P->qlevel[y];
+    });
+    std::vector<int32_t> jq0(nj, 0), jq1(nj, 0);
+    for (int i = nq - 1; i >= 0; i--) jq0[P->qjob[jq[i]]] = i;
+    for (int i = 0; i < nq; i++) jq1[P->qjob[jq[i]]] = i + 1;
     P->wu.ensure(8 * ((size_t)P->items + 1));
     P->wbase.ensure(8 * ((size_t)P->items + 1));
     for (int j = 0; j < nj; j++) {
@@ -499,10 +525,9 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         P->sw[j].ensure(8 * (size_t)ix.T + 8);
         P->su[j].ensure(4 * (size_t)ix.NI + 4);
         JobDev &d = jd[j];
-        d.ooff = ix.ooff.as<int32_t>();
+        d.item = ix.item.as<int4>();
+        d.vrow = ix.vrow.as<int2>();
         d.oadj = ix.oadj.as<int32_t>();
-        d.item_u = ix.item_u.as<int32_t>();
-        d.item_off = ix.item_off.as<int32_t>();
         d.tri = ix.tri_cached ? ix.tri.as<int32_t>() : nullptr;
         d.tri_base = ix.tri_base.as<int64_t>();
         d.ts = ix.ts.as<int64_t>();
@@ -520,50 +545,55 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         d.sw = P->sw[j].as<int64_t>();
         d.su = P->su[j].as<int32_t>();
         d.wu = P->wu.as<int64_t>() + P->job_item_base[j];
-    }
-    // queries
-    std::vector<QueryDev> qd(nq);
-    P->q_e_base.assign(nq + 1, 0);
-    int64_t pb = 0;
-    int32_t nmax = 1;
-    for (int q = 0; q < nq; q++) {
-        const Graph *g = P->graphs[qgraph[q]];
-        const Index &ix = g->ix;
-        const JobDev &J = jd[P->qjob[q]];
-        QueryDev &d = qd[q];
-        d.count = J.hist + (int64_t)P->qlevel[q] * ix.m;
         d.sid = ix.sid.as<int32_t>();
         d.smid = ix.smid.as<int32_t>();
         d.slo = ix.slo.as<int32_t>();
         d.shi = ix.shi.as<int32_t>();
         d.deg = ix.deg.as<int32_t>();
-        d.tcnt = ix.tcnt.as<int32_t>();
-        d.m = ix.m;
-        d.S = ix.S;
+        d.tcnt = nullptr;
+        d.q0 = jq0[j];
+        d.q1 = jq1[j];
+        d.keep_prefix = 0;
+        for (int i = d.q0; i < d.q1; i++) {
+            if (qs[jq[i]].universe == FOLTY_UNIVERSE_COMMON) d.tcnt = ix.tcnt.as<int32_t>();
+            if (!(qs[jq[i]].flags & FOLTY_QUERY_NO_COUNTS)) d.keep_prefix = 1;
+        }
+    }
+    // queries
+    std::vector<QueryDev> qd(nq);
+    int64_t pb = 0;
+    int32_t nmax = 1;
+    for (int q = 0; q < nq; q++) {
+        const Graph *g = P->graphs[qgraph[q]];
+        const Index &ix = g->ix;
+        QueryDev &d = qd[q];
+        d.slo = ix.slo.as<int32_t>();
+        d.shi = ix.shi.as<int32_t>();
+        d.level = P->qlevel[q];
         d.num = qs[q].theta_num;
         d.den = qs[q].theta_den;
         d.universe = qs[q].universe;
         d.excl = qs[q].exclude_other ? 1 : 0;
         d.p_base = pb;
         pb += 2 * (int64_t)ix.S;
-        P->q_e_base[q + 1] = P->q_e_base[q] + ix.m;
         nmax = std::max(nmax, ix.n);
     }
-    P->total_e = P->q_e_base[nq];
     P->total_p = pb;
     P->nbits = bit_length((uint64_t)nmax);
     if (bit_length((uint64_t)std::max(1, nq)) + 2 * P->nbits > 64)
         fail(FOLTY_EOVERFLOW, "too many queries for one plan at this graph size");
     P->d_jobs.ensure(sizeof(JobDev) * (size_t)std::max(1, nj));
     P->d_job_item_base.ensure(8 * ((size_t)nj + 1));
-    P->d_job_m_base.ensure(8 * ((size_t)nj + 1));
+    P->d_job_w_base.ensure(8 * ((size_t)nj + 1));
     P->d_queries.ensure(sizeof(QueryDev) * (size_t)std::max(1, nq));
-    P->d_q_e_base.ensure(8 * ((size_t)nq + 1));
+    P->d_jq.ensure(4 * ((size_t)nq + 1));
     if (nj) FOLTY_HIP(hipMemcpyAsync(P->d_jobs.p, jd.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice, s));
     FOLTY_HIP(hipMemcpyAsync(P->d_job_item_base.p, P->job_item_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
-    FOLTY_HIP(hipMemcpyAsync(P->d_job_m_base.p, P->job_m_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
-    if (nq) FOLTY_HIP(hipMemcpyAsync(P->d_queries.p, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
-    FOLTY_HIP(hipMemcpyAsync(P->d_q_e_base.p, P->q_e_base.data(), 8 * (nq + 1), hipMemcpyHostToDevice, s));
+    FOLTY_HIP(hipMemcpyAsync(P->d_job_w_base.p, P->job_w_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
+    if (nq) {
+        FOLTY_HIP(hipMemcpyAsync(P->d_queries.p, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
+        FOLTY_HIP(hipMemcpyAsync(P->d_jq.p, jq.data(), 4 * (size_t)nq, hipMemcpyHostToDevice, s));
+    }
     P->ncert.ensure(4 * (size_t)P->total_p + 4);
     P->qcert.ensure(4 * ((size_t)nq + 1));
     P->npairs.ensure(4);

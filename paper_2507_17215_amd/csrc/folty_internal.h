@@ -115,9 +115,9 @@ struct PinnedBuf {
 // oriented edge is the static edge's lo endpoint.  rec[p] describes oriented
 // edge p: both of its directed lists with their first and last timestamps.
 // The wedges u -> v -> x of each vertex u are cut into chunks ("items") of at
-// most a fixed number of closing probes; item it belongs to vertex item_u[it],
-// vertex u owns items [item_off[u], item_off[u+1]), and the triangles found by
-// item it occupy slots [tri_base[it], tri_base[it+1]).
+// most a fixed number of closing probes; item[it] holds its vertex, its part
+// and the vertex's row, vertex u owns items [item_off[u], item_off[u+1]), and
+// the triangles found by item it occupy slots [tri_base[it], tri_base[it+1]).
 // ---------------------------------------------------------------------------
 struct alignas(64) EdgeRec {
     int32_t fs, fn;       // E_{tail,head}: start in ts, length
@@ -168,7 +168,8 @@ struct Index {
     DevBuf oeid;     // uint32[S] static edge id | direction bit
     DevBuf rec;      // EdgeRec[S]
     DevBuf erng;     // uint2[S]  first and last timestamp >> tshift over both lists of each oriented edge
-    DevBuf item_u;   // int32[NI]
+    DevBuf item;     // int4[NI]  enumeration item: (u, part, row start of u, |N+(u)|)
+    DevBuf vrow;     // int2[S]   per oriented edge: (row start, length) of its head's row
     DevBuf item_off; // int32[n+1]
     DevBuf tri_base; // int64[NI+1]
     DevBuf tcnt;     // int32[S]  triangles on each static edge = |N(lo) & N(hi)| (computed on first use)
@@ -186,6 +187,7 @@ struct Workspace {
     DevBuf wu;      // int64[NI+1] tests per item
     DevBuf wbase;   // int64[NI+1] exclusive offsets of wu
     DevBuf sbase;   // int64[NI+1] first survivor slot of each item
+    const int64_t *slots = nullptr; // survivor slots of the last filter: sbase or the index's tri_base
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
     DevBuf pairs_v; // uint32[2S]

@@ -1186,7 +1186,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
 
 size_t Index::device_bytes() const {
     const DevBuf *b[] = {&ts, &perm, &sid, &soff, &smid, &slo, &shi, &deg, &core, &rank,
-                         &outdeg, &ooff, &oadj, &oeid, &rec, &erng, &item_u, &item_off, &tri_base, &tcnt, &tri};
+                         &outdeg, &ooff, &oadj, &oeid, &rec, &erng, &item, &vrow, &item_off, &tri_base, &tcnt, &tri};
     size_t t = 0;
     for (auto *x : b) t += x->bytes;
     return t;

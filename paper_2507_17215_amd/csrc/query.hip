@@ -94,10 +94,22 @@ __global__ void k_probes(const int32_t *__restrict__ ooff, const int32_t *__rest
     }
 }
 
-__global__ void k_item_owner(const int32_t *__restrict__ item_off, int32_t n, int32_t *__restrict__ item_u) {
+// the items of vertex u: (u, part, row start, |N+(u)|)
+__global__ void k_item_recs(const int32_t *__restrict__ item_off, const int32_t *__restrict__ ooff, int32_t n,
+                            int4 *__restrict__ item) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
-    for (int32_t it = item_off[u]; it < item_off[u + 1]; it++) item_u[it] = (int32_t)u;
+    const int32_t b = ooff[u], d = ooff[u + 1] - b, i0 = item_off[u];
+    for (int32_t it = i0; it < item_off[u + 1]; it++) item[it] = make_int4((int32_t)u, it - i0, b, d);
+}
+
+// per oriented edge (u, v): where v's own row starts and how long it is
+__global__ void k_vrow(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj, int32_t S,
+                       int2 *__restrict__ vrow) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S) return;
+    const int32_t v = oadj[p];
+    vrow[p] = make_int2(ooff[v], ooff[v + 1] - ooff[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,9 +234,12 @@ unsigned enum_grid(int32_t n) {
 // survive the time-range filter and how many tests they carry, and counts all
 // triangles; exclusive scans give each item its first survivor slot (ws.sbase)
 // and its first test (ws.wbase, total at [NI]); the emitting pass then
-// enumerates only the items that have survivors and writes them.  e0 and e1
-// bracket the counting launch alone, so its duration is measured on the stream
-// it runs on.  Returns the number of survivors; *tri gets the triangle count.
+// enumerates only the items that have survivors and writes them.  When the
+// index already holds per-item triangle offsets (after a plan, a server
+// submission or a stats call) one pass writes survivors into those slots
+// instead.  e0 and e1 bracket the (first) enumeration launch alone, so its
+// duration is measured on the stream it runs on.  Returns the number of
+// survivors (an upper bound in the one-pass case); *tri gets the triangle count.
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
                        hipEvent_t e1, int64_t *tri) {
     const int32_t NI = ix.NI;
@@ -258,13 +273,40 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
             k_filter_cached<<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI, sink,
                                                           only);
         else
-            k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
-                                                     ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), NI, sink,
-                                                     only);
+            k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(), ix.vrow.as<int2>(),
+                                                     NI, sink, only);
         FOLTY_LAUNCHED();
     };
     using CountM = std::integral_constant<int, FILTER_COUNT>;
     using EmitM = std::integral_constant<int, FILTER_EMIT>;
+    using BothM = std::integral_constant<int, FILTER_BOTH>;
+    if (ix.tri_base_ready) {
+        // per-item triangle offsets exist: one pass writes survivors into them
+        ws.sv.ensure(12 * (size_t)ix.T + 12);
+        ws.sw.ensure(8 * (size_t)ix.T + 8);
+        FOLTY_HIP(hipEventRecord(e0, s));
+        dispatch_variant(variant, [&](auto V) {
+            auto sink = sink_for(V, BothM{});
+            sink.base = ix.tri_base.as<int64_t>();
+            if (ix.tri_cached)
+                k_filter_cached<<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI,
+                                                              sink);
+            else
+                k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
+                                                         ix.vrow.as<int2>(), NI, sink);
+            FOLTY_LAUNCHED();
+        });
+        FOLTY_HIP(hipEventRecord(e1, s));
+        k_fill<int64_t><<<1, 1, 0, s>>>(ws.wu.as<int64_t>() + NI, (int64_t)0, 1);
+        FOLTY_LAUNCHED();
+        size_t need = exclusive_scan_i64(nullptr, 0, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
+        ws.cub.ensure(need);
+        exclusive_scan_i64(ws.cub.p, need, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
+        *tri = ix.T;
+        ws.slots = ix.tri_base.as<int64_t>();
+        return ix.T; // an upper bound: the temporal kernel reads the exact counts
+    }
+    ws.slots = ws.sbase.as<int64_t>();
     FOLTY_HIP(hipEventRecord(e0, s));
     dispatch_variant(variant, [&](auto V) { run(V, CountM{}, nullptr); });
     FOLTY_HIP(hipEventRecord(e1, s));
@@ -296,7 +338,7 @@ template <class Op>
 void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, hipStream_t s) {
     dispatch_variant(variant, [&](auto V) {
         k_temporal<decltype(V)::value, Op><<<PERSIST_BLOCKS, BLK, 0, s>>>(
-            ws.wbase.as<int64_t>(), ix.NI, ws.sbase.as<int64_t>(), ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
+            ws.wbase.as<int64_t>(), ix.NI, ws.slots, ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
             ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(), dmax, op, IPT);
     });
     FOLTY_LAUNCHED();
@@ -425,8 +467,11 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     FOLTY_HIP(hipStreamSynchronize(s));
     ix.NI = ni;
     ix.probes = h[1];
-    ix.item_u.ensure(4 * (size_t)ni + 4);
-    k_item_owner<<<grid_for(n, BLK), BLK, 0, s>>>(ix.item_off.as<int32_t>(), n, ix.item_u.as<int32_t>());
+    ix.item.ensure(sizeof(int4) * ((size_t)ni + 1));
+    k_item_recs<<<grid_for(n, BLK), BLK, 0, s>>>(ix.item_off.as<int32_t>(), ix.ooff.as<int32_t>(), n,
+                                                 ix.item.as<int4>());
+    ix.vrow.ensure(sizeof(int2) * ((size_t)S + 1));
+    if (S > 0) k_vrow<<<grid_for(S, BLK), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), S, ix.vrow.as<int2>());
     FOLTY_LAUNCHED();
     // triangle slots per item are made on first use (plans, the server's memory
     // estimate, the cached list): a single query counts its survivors itself
@@ -439,8 +484,8 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
         if (ix.T > 0) {
             ix.tri.ensure(12 * (size_t)ix.T);
             CacheSink sink{ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), 0};
-            k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
-                                                     ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), ni, sink);
+            k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
+                                                     ix.vrow.as<int2>(), ni, sink);
             FOLTY_LAUNCHED();
             ix.tri_cached = true;
         }
@@ -459,8 +504,8 @@ void ensure_tri_base(Index &ix, hipStream_t s) {
     FOLTY_LAUNCHED();
     if (ni > 0) {
         CountSink cs{tri_it.as<int32_t>(), 0};
-        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
-                                                 ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), ni, cs);
+        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
+                                                 ix.vrow.as<int2>(), ni, cs);
         FOLTY_LAUNCHED();
     }
     size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(),
@@ -489,8 +534,8 @@ void ensure_tcnt(Index &ix, hipStream_t s) {
         k_fill<int32_t><<<grid_for(ix.S, BLK), BLK, 0, s>>>(ix.tcnt.as<int32_t>(), 0, ix.S);
         FOLTY_LAUNCHED();
         TcntSink sink{ix.oeid.as<uint32_t>(), ix.tcnt.as<int32_t>()};
-        k_tri_enum<<<enum_grid(ix.NI), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
-                                                    ix.item_u.as<int32_t>(), ix.item_off.as<int32_t>(), ix.NI, sink);
+        k_tri_enum<<<enum_grid(ix.NI), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
+                                                    ix.vrow.as<int2>(), ix.NI, sink);
         FOLTY_LAUNCHED();
     }
     ix.tcnt_ready = true;

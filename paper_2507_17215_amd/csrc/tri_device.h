@@ -430,14 +430,28 @@ __device__ inline void enum_batch(int32_t b, int32_t d, int32_t q_begin, const E
 // One wavefront per item: the item's vertex u, and a range of the flattened
 // wedge space of u (position q = sum of |N+(v_j)| over j < i, plus the position
 // of x in N+(v_i)).  Sinks see the triangles of an item in a fixed order.
-template <class Sink>
-__device__ inline void enum_item(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
-                                 const int32_t *__restrict__ item_u, const int32_t *__restrict__ item_off, int64_t it,
-                                 Sink &sink, EnumLds &L) {
+// The first 64 entries of an item's row (this lane's), loaded one item ahead.
+struct StageAhead {
+    int32_t v;
+    int2 row;
+};
+
+__device__ inline StageAhead stage_ahead(const int4 &item, const int32_t *__restrict__ oadj,
+                                         const int2 *__restrict__ vrow) {
+    StageAhead a{0, make_int2(0, 0)};
     const int lane = lane_id();
-    const int32_t u = item_u[it];
-    const int32_t part = (int32_t)(it - item_off[u]);
-    const int32_t b = ooff[u], d = ooff[u + 1] - b;
+    if (item.w >= 2 && item.w <= CAP && lane < item.w) {
+        a.v = oadj[item.z + lane];
+        a.row = vrow[item.z + lane];
+    }
+    return a;
+}
+
+template <class Sink>
+__device__ inline void enum_item(const int4 item, const StageAhead &ahead, const int32_t *__restrict__ oadj,
+                                 const int2 *__restrict__ vrow, int64_t it, Sink &sink, EnumLds &L) {
+    const int lane = lane_id();
+    const int32_t part = item.y, b = item.z, d = item.w;
     sink.begin(it);
     if (d >= 2 && d <= CAP) {
         // stage N+(u), each v's row start and a prefix of |N+(v)|
@@ -446,10 +460,16 @@ __device__ inline void enum_item(const int32_t *__restrict__ ooff, const int32_t
             const int32_t i = i0 + lane;
             int32_t dv = 0, vo = 0;
             if (i < d) {
-                const int32_t v = oadj[b + i];
-                vo = ooff[v];
-                dv = ooff[v + 1] - vo;
-                L.nu[i] = v;
+                int2 row;
+                if (i0 == 0) {
+                    row = ahead.row;
+                    L.nu[i] = ahead.v;
+                } else {
+                    row = vrow[b + i];
+                    L.nu[i] = oadj[b + i];
+                }
+                vo = row.x;
+                dv = row.y;
             }
             const int32_t x = wave_inclusive_sum(dv);
             if (i < d) {
@@ -542,8 +562,8 @@ __device__ inline void enum_item(const int32_t *__restrict__ ooff, const int32_t
         // long rows (only for orientations without the degeneracy bound): one
         // item per vertex, the same probes against N+(u) in global memory
         for (int32_t i = 0; i < d; i++) {
-            const int32_t v = oadj[b + i];
-            const int32_t vb = ooff[v], ve = ooff[v + 1];
+            const int2 row = vrow[b + i];
+            const int32_t vb = row.x, ve = row.x + row.y;
             for (int32_t p0 = vb; p0 < ve; p0 += 64) {
                 const int32_t p = p0 + lane;
                 bool hit = false;
@@ -587,15 +607,36 @@ __device__ inline void cached_item(const int64_t *__restrict__ base, const int32
 // of x in N+(v_i)).
 // only != nullptr: items with only[it] == 0 are skipped
 template <class Sink>
-__global__ __launch_bounds__(BLK) void k_tri_enum(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
-                                                  const int32_t *__restrict__ item_u,
-                                                  const int32_t *__restrict__ item_off, int32_t NI, Sink sink,
+__global__ __launch_bounds__(BLK) void k_tri_enum(const int4 *__restrict__ items, const int32_t *__restrict__ oadj,
+                                                  const int2 *__restrict__ vrow, int32_t NI, Sink sink,
                                                   const int32_t *__restrict__ only = nullptr) {
     __shared__ EnumLds lds[WPB];
     const int w = threadIdx.x >> 6;
-    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
-        if (only && only[it] == 0) continue;
-        enum_item(ooff, oadj, item_u, item_off, it, sink, lds[w]);
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+    int64_t it = (int64_t)blockIdx.x * WPB + w;
+    if (only) {
+        // a pass over a few marked items: no loads ahead for the skipped ones
+        for (; it < NI; it += stride) {
+            if (only[it] == 0) continue;
+            const int4 item = items[it];
+            enum_item(item, stage_ahead(item, oadj, vrow), oadj, vrow, it, sink, lds[w]);
+        }
+        sink.finish();
+        return;
+    }
+    // item headers run two items ahead and the first row chunk one item ahead,
+    // so a wavefront starts each item with its data already loaded
+    const int4 none = make_int4(0, 0, 0, 0);
+    int4 h0 = it < NI ? items[it] : none;
+    int4 h1 = it + stride < NI ? items[it + stride] : none;
+    StageAhead a0 = stage_ahead(h0, oadj, vrow);
+    for (; it < NI; it += stride) {
+        const int4 cur = h0;
+        const StageAhead ca = a0;
+        h0 = h1;
+        a0 = stage_ahead(h0, oadj, vrow);
+        h1 = it + 2 * stride < NI ? items[it + 2 * stride] : none;
+        enum_item(cur, ca, oadj, vrow, it, sink, lds[w]);
     }
     sink.finish();
 }

@@ -238,6 +238,25 @@ def test_plan_buffers_larger_than_one_fill_grid():
             assert np.array_equal(got[idx], pool[q["variant"]][q["delta"]]), q
 
 
+def test_single_query_one_pass_and_two_pass_agree():
+    """A fresh index filters in two passes (count, then emit only items with
+    survivors); once a plan has made the per-item triangle offsets, single
+    queries filter in one pass into those slots.  Both equal the oracle."""
+    g = synth.tiny(seed=21)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    G = gpu_graph(g)
+    qs = [(10**6, (1, 4), 0), (3600, (1, 2), 3), (0, (0, 1), 6), (INF, (1, 3), 0)]
+    first = [G.query(d, th, v) for d, th, v in qs]
+    say("two-pass stats", first[0].stats["triangles"], first[0].stats["tests"])
+    folty.Plan([G], [(0, dict(delta=qs[0][0], theta=qs[0][1], variant=qs[0][2]))])
+    for (d, th, v), r1 in zip(qs, first):
+        r2 = G.query(d, th, v)
+        want = o.query(d, th[0], th[1], v)
+        assert_same(r1, want)
+        assert_same(r2, want)
+        assert r2.stats["triangles"] == r1.stats["triangles"]
+
+
 def test_device_tensor_inputs():
     import torch
     g = synth.tiny(seed=6)
