@@ -31,8 +31,8 @@ namespace folty {
 namespace {
 
 struct JobDev {
-    const int4 *item;
-    const int2 *vrow;
+    const EnumItem *item;
+    const int4 *seg;
     const int32_t *oadj, *tri;
     const int64_t *tri_base, *ts;
     const EdgeRec *rec;
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__
         sink.wu = J.wu;
         if (J.tri) cached_item(J.tri_base, J.tri, it, sink);
         else {
-            const int4 item = J.item[it];
-            enum_item(item, stage_ahead(item, J.oadj, J.vrow), J.oadj, J.vrow, it, sink, lds[w]);
+            const EnumItem item = J.item[it];
+            enum_item(item, stage_ahead(item, J.oadj, J.seg), J.oadj, J.seg, it, sink, lds[w]);
         }
     }
 }
@@ -525,8 +525,8 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         P->sw[j].ensure(8 * (size_t)ix.T + 8);
         P->su[j].ensure(4 * (size_t)ix.NI + 4);
         JobDev &d = jd[j];
-        d.item = ix.item.as<int4>();
-        d.vrow = ix.vrow.as<int2>();
+        d.item = ix.item.as<EnumItem>();
+        d.seg = ix.seg.as<int4>();
         d.oadj = ix.oadj.as<int32_t>();
         d.tri = ix.tri_cached ? ix.tri.as<int32_t>() : nullptr;
         d.tri_base = ix.tri_base.as<int64_t>();

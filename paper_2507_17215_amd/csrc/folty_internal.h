@@ -114,11 +114,25 @@ struct PinnedBuf {
 // order; oeid packs the static edge id with bit 31 set when the tail of the
 // oriented edge is the static edge's lo endpoint.  rec[p] describes oriented
 // edge p: both of its directed lists with their first and last timestamps.
-// The wedges u -> v -> x of each vertex u are cut into chunks ("items") of at
-// most a fixed number of closing probes; item[it] holds its vertex, its part
-// and the vertex's row, vertex u owns items [item_off[u], item_off[u+1]), and
-// the triangles found by item it occupy slots [tri_base[it], tri_base[it+1]).
+// Triangle enumeration: every triangle u < v < x (orientation order) is found
+// from its lowest edge (u, v) by probing the members x of one endpoint's out-row
+// for membership in the other's.  The edge is owned by the endpoint with the
+// longer out-row, which is staged in LDS; the shorter row is scanned ("probe
+// segment"):
+//   mode A, |N+(v)| <= |N+(u)|: owner u, segment = row of v (x in N+(v)),
+//   mode B, |N+(u)| <  |N+(v)|: owner v, segment = row of u (x in N+(u)).
+// seg[j] = (row start, row length, oriented edge (u, v) | mode B << 31, owner),
+// grouped by owner and mode.  Items are runs of at most ITEM_SEGS segments and
+// about CHUNK probes of one owner; the triangles found by item it occupy slots
+// [tri_base[it], tri_base[it+1]).
 // ---------------------------------------------------------------------------
+struct alignas(32) EnumItem {
+    int32_t g0, ng; // segments [g0, g0 + ng) of the owner
+    int32_t nq;     // probes: the total length of those segments' rows
+    int32_t b, d;   // the owner's out-row: start and length
+    int32_t pad[3];
+};
+
 struct alignas(64) EdgeRec {
     int32_t fs, fn;       // E_{tail,head}: start in ts, length
     int32_t bs, bn;       // E_{head,tail}
@@ -168,9 +182,9 @@ struct Index {
     DevBuf oeid;     // uint32[S] static edge id | direction bit
     DevBuf rec;      // EdgeRec[S]
     DevBuf erng;     // uint2[S]  first and last timestamp >> tshift over both lists of each oriented edge
-    DevBuf item;     // int4[NI]  enumeration item: (u, part, row start of u, |N+(u)|)
-    DevBuf vrow;     // int2[S]   per oriented edge: (row start, length) of its head's row
-    DevBuf item_off; // int32[n+1]
+    DevBuf otail;    // int32[S]  tail of each oriented edge (new id; released after the build)
+    DevBuf seg;      // int4[S]   probe segments grouped by owner (see EnumItem)
+    DevBuf item;     // EnumItem[NI]
     DevBuf tri_base; // int64[NI+1]
     DevBuf tcnt;     // int32[S]  triangles on each static edge = |N(lo) & N(hi)| (computed on first use)
     DevBuf tri;      // int32[3T] cached triangle list (optional): oriented edges (u,v), (u,w), (v,w)

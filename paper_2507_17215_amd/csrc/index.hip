@@ -757,10 +757,11 @@ __global__ void k_orient_keys(const int32_t *__restrict__ slo, const int32_t *__
 }
 
 __global__ void k_orient_unpack(const uint64_t *__restrict__ key, int32_t S, int64_t n,
-                                int32_t *__restrict__ oadj) {
+                                int32_t *__restrict__ oadj, int32_t *__restrict__ otail) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= S) return;
     oadj[j] = (int32_t)(key[j] % (uint64_t)n);
+    otail[j] = (int32_t)(key[j] / (uint64_t)n);
 }
 
 // oriented CSR rows: row x starts at the first key >= x * n
@@ -1127,6 +1128,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     ix.rank_mode = o.rank_mode;
 
     ix.oadj.ensure(4 * (size_t)S + 4);
+    ix.otail.ensure(4 * (size_t)S + 4);
     ix.oeid.ensure(4 * (size_t)S + 4);
     ix.ooff.ensure(4 * ((size_t)n + 1));
     ix.outdeg.ensure(4 * (size_t)n);
@@ -1145,7 +1147,8 @@ void build_index(Graph *g, const folty_build_opts *opts) {
                                              ix.oeid.as<uint32_t>(), S, kb, s);
             sort_pairs_u64_u32(cub_ensure(need), need, key.as<uint64_t>(), key2.as<uint64_t>(), val.as<uint32_t>(),
                                ix.oeid.as<uint32_t>(), S, kb, s);
-            k_orient_unpack<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.oadj.as<int32_t>());
+            k_orient_unpack<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.oadj.as<int32_t>(),
+                                                             ix.otail.as<int32_t>());
             FOLTY_LAUNCHED();
         }
         k_orient_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.ooff.as<int32_t>());
@@ -1186,7 +1189,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
 
 size_t Index::device_bytes() const {
     const DevBuf *b[] = {&ts, &perm, &sid, &soff, &smid, &slo, &shi, &deg, &core, &rank,
-                         &outdeg, &ooff, &oadj, &oeid, &rec, &erng, &item, &vrow, &item_off, &tri_base, &tcnt, &tri};
+                         &outdeg, &ooff, &oadj, &oeid, &rec, &erng, &item, &seg, &tri_base, &tcnt, &tri};
     size_t t = 0;
     for (auto *x : b) t += x->bytes;
     return t;

@@ -67,49 +67,83 @@ __global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const int32_t *__
     erng[p] = make_uint2((uint32_t)(lo >> tshift), (uint32_t)(hi >> tshift));
 }
 
-// closing probes of vertex u: sum over v in N+(u) of |N+(v)|; the vertex gets
-// ceil(probes / CHUNK) enumeration items (one if its row is too long for LDS,
-// none if it has fewer than two out-neighbours)
-__global__ void k_probes(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj, int32_t n,
-                         int32_t *__restrict__ items, unsigned long long *total) {
-    __shared__ unsigned long long s_sum[BLK / 64];
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long pr = 0;
-    if (u < n) {
-        int32_t b = ooff[u], d = ooff[u + 1] - b;
-        for (int32_t i = 0; i < d; i++) {
-            int32_t v = oadj[b + i];
-            pr += (unsigned long long)(ooff[v + 1] - ooff[v]);
-        }
-        int32_t k = 0;
-        if (d >= 2 && pr > 0) k = d > CAP ? 1 : (int32_t)((pr + CHUNK - 1) / CHUNK);
-        items[u] = k;
-    }
-    for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
-    if (lane_id() == 0) s_sum[threadIdx.x >> 6] = pr;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < BLK / 64; i++) pr += s_sum[i];
-        if (pr) atomicAdd(total, pr);
-    }
-}
-
-// the items of vertex u: (u, part, row start, |N+(u)|)
-__global__ void k_item_recs(const int32_t *__restrict__ item_off, const int32_t *__restrict__ ooff, int32_t n,
-                            int4 *__restrict__ item) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    const int32_t b = ooff[u], d = ooff[u + 1] - b, i0 = item_off[u];
-    for (int32_t it = i0; it < item_off[u + 1]; it++) item[it] = make_int4((int32_t)u, it - i0, b, d);
-}
-
-// per oriented edge (u, v): where v's own row starts and how long it is
-__global__ void k_vrow(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj, int32_t S,
-                       int2 *__restrict__ vrow) {
+// Probe segments: the oriented edge (u, v) at position p goes to the endpoint
+// with the longer out-row (mode A: u, scanning v's row; mode B: v, scanning
+// u's row).  Sort key: owner * 2 + mode.
+__global__ void k_seg_keys(const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
+                           const int32_t *__restrict__ otail, int32_t S, uint32_t *__restrict__ key,
+                           int32_t *__restrict__ val) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S) return;
-    const int32_t v = oadj[p];
-    vrow[p] = make_int2(ooff[v], ooff[v + 1] - ooff[v]);
+    const int32_t u = otail[p], v = oadj[p];
+    const int32_t du = ooff[u + 1] - ooff[u], dv = ooff[v + 1] - ooff[v];
+    const bool mode_b = du < dv;
+    key[p] = ((uint32_t)(mode_b ? v : u) << 1) | (mode_b ? 1u : 0u);
+    val[p] = (int32_t)p;
+}
+
+// first sorted position of each key 0 .. 2n
+__global__ void k_part_off(const uint32_t *__restrict__ key, int32_t S, int64_t nk, int32_t *__restrict__ off) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > nk) return;
+    int32_t a = 0, b = S;
+    while (a < b) {
+        int32_t mid = (int32_t)(((int64_t)a + b) >> 1);
+        if ((int64_t)key[mid] < x) a = mid + 1;
+        else b = mid;
+    }
+    off[x] = a;
+}
+
+// seg[j] = (row start, row length, oriented edge | mode B << 31, owner)
+__global__ void k_seg_recs(const uint32_t *__restrict__ key, const int32_t *__restrict__ val,
+                           const int32_t *__restrict__ ooff, const int32_t *__restrict__ oadj,
+                           const int32_t *__restrict__ otail, int32_t S, int4 *__restrict__ seg,
+                           int32_t *__restrict__ len) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S) return;
+    const int32_t p = val[j];
+    const bool mode_b = key[j] & 1u;
+    const int32_t r = mode_b ? otail[p] : oadj[p]; // the vertex whose row is scanned
+    const int32_t rs = ooff[r], rl = ooff[r + 1] - rs;
+    seg[j] = make_int4(rs, rl, (int32_t)((uint32_t)p | (mode_b ? MODE_B : 0u)), (int32_t)(key[j] >> 1));
+    len[j] = rl;
+}
+
+// An item starts at the first segment of each (owner, mode) run and wherever
+// the run's probe count crosses a multiple of CHUNK or its segment count a
+// multiple of ITEM_SEGS (both indices only grow, so runs of equal value are
+// contiguous).
+__global__ void k_item_flags(const uint32_t *__restrict__ key, const int64_t *__restrict__ P,
+                             const int32_t *__restrict__ part_off, int32_t S, int32_t *__restrict__ flag) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S) return;
+    const int32_t p0 = part_off[key[j]];
+    const int64_t cj = (P[j] - P[p0]) / CHUNK + (j - p0) / ITEM_SEGS;
+    int f = j == p0;
+    if (!f) f = cj != (P[j - 1] - P[p0]) / CHUNK + (j - 1 - p0) / ITEM_SEGS;
+    flag[j] = f;
+}
+
+__global__ void k_item_starts(const int32_t *__restrict__ flag, const int32_t *__restrict__ fid, int32_t S,
+                              int32_t *__restrict__ start) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < S && flag[j]) start[fid[j] - 1] = (int32_t)j;
+}
+
+__global__ void k_items(const int32_t *__restrict__ start, const int4 *__restrict__ seg, const int64_t *__restrict__ P,
+                        const int32_t *__restrict__ ooff, int32_t NI, EnumItem *__restrict__ items) {
+    int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= NI) return;
+    const int32_t g0 = start[it], g1 = start[it + 1];
+    const int32_t w = seg[g0].w;
+    EnumItem e{};
+    e.g0 = g0;
+    e.ng = g1 - g0;
+    e.nq = (int32_t)(P[g1] - P[g0]);
+    e.b = ooff[w];
+    e.d = ooff[w + 1] - e.b;
+    items[it] = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -273,7 +307,7 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
             k_filter_cached<<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI, sink,
                                                           only);
         else
-            k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(), ix.vrow.as<int2>(),
+            k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(), ix.seg.as<int4>(),
                                                      NI, sink, only);
         FOLTY_LAUNCHED();
     };
@@ -292,8 +326,8 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
                 k_filter_cached<<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI,
                                                               sink);
             else
-                k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
-                                                         ix.vrow.as<int2>(), NI, sink);
+                k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(),
+                                                         ix.seg.as<int4>(), NI, sink);
             FOLTY_LAUNCHED();
         });
         FOLTY_HIP(hipEventRecord(e1, s));
@@ -438,41 +472,75 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     const int32_t n = ix.n, S = ix.S;
     ix.rec.ensure(sizeof(EdgeRec) * ((size_t)S + 1));
     ix.erng.ensure(sizeof(uint2) * ((size_t)S + 1));
-    ix.item_off.ensure(4 * ((size_t)n + 1));
     ix.tcnt_ready = false;
-    DevBuf items, probes;
-    items.ensure(4 * ((size_t)n + 1));
-    probes.ensure(8);
-    k_fill<unsigned long long><<<1, 1, 0, s>>>(probes.as<unsigned long long>(), 0ull, 1);
-    k_fill<int32_t><<<1, 1, 0, s>>>(items.as<int32_t>() + n, 0, 1);
-    FOLTY_LAUNCHED();
     if (S > 0) {
         k_edge_recs<<<grid_for(S, BLK), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), ix.soff.as<int32_t>(),
                                                                 ix.smid.as<int32_t>(), ix.ts.as<int64_t>(), S,
                                                                 ix.tshift, ix.rec.as<EdgeRec>(), ix.erng.as<uint2>());
         FOLTY_LAUNCHED();
     }
-    k_probes<<<grid_for(n, BLK), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), n,
-                                                          items.as<int32_t>(), probes.as<unsigned long long>());
-    FOLTY_LAUNCHED();
-    {
-        size_t need = exclusive_scan_i32(nullptr, 0, items.as<int32_t>(), ix.item_off.as<int32_t>(), (int64_t)n + 1, s);
-        cub.ensure(need);
-        exclusive_scan_i32(cub.p, need, items.as<int32_t>(), ix.item_off.as<int32_t>(), (int64_t)n + 1, s);
-    }
-    int64_t h[2] = {0, 0};
+    // probe segments grouped by (owner, mode), their probe prefix, and items
+    ix.seg.ensure(sizeof(int4) * ((size_t)S + 1));
     int32_t ni = 0;
-    FOLTY_HIP(hipMemcpyAsync(&ni, ix.item_off.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, s));
-    FOLTY_HIP(hipMemcpyAsync(&h[1], probes.p, 8, hipMemcpyDeviceToHost, s));
-    FOLTY_HIP(hipStreamSynchronize(s));
+    int64_t probes = 0;
+    {
+        DevBuf key, key2, val, val2, part_off, len, P, flag, fid, start;
+        key.ensure(4 * (size_t)S + 4);
+        key2.ensure(4 * (size_t)S + 4);
+        val.ensure(4 * (size_t)S + 4);
+        val2.ensure(4 * (size_t)S + 4);
+        len.ensure(4 * ((size_t)S + 1));
+        P.ensure(8 * ((size_t)S + 1));
+        flag.ensure(4 * (size_t)S + 4);
+        fid.ensure(4 * (size_t)S + 4);
+        start.ensure(4 * ((size_t)S + 1));
+        const int64_t nk = 2 * (int64_t)n;
+        part_off.ensure(4 * ((size_t)nk + 1));
+        if (S > 0) {
+            k_seg_keys<<<grid_for(S, BLK), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(),
+                                                        ix.otail.as<int32_t>(), S, key.as<uint32_t>(), val.as<int32_t>());
+            FOLTY_LAUNCHED();
+            const int kb = bit_length((uint64_t)nk);
+            size_t need = sort_pairs_u32_i32(nullptr, 0, key.as<uint32_t>(), key2.as<uint32_t>(), val.as<int32_t>(),
+                                             val2.as<int32_t>(), S, kb, s);
+            cub.ensure(need);
+            sort_pairs_u32_i32(cub.p, need, key.as<uint32_t>(), key2.as<uint32_t>(), val.as<int32_t>(),
+                               val2.as<int32_t>(), S, kb, s);
+            k_part_off<<<grid_for(nk + 1, BLK), BLK, 0, s>>>(key2.as<uint32_t>(), S, nk, part_off.as<int32_t>());
+            k_seg_recs<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint32_t>(), val2.as<int32_t>(), ix.ooff.as<int32_t>(),
+                                                        ix.oadj.as<int32_t>(), ix.otail.as<int32_t>(), S,
+                                                        ix.seg.as<int4>(), len.as<int32_t>());
+            k_fill<int32_t><<<1, 1, 0, s>>>(len.as<int32_t>() + S, 0, 1);
+            FOLTY_LAUNCHED();
+            need = exclusive_scan_i32_to_i64(nullptr, 0, len.as<int32_t>(), P.as<int64_t>(), (int64_t)S + 1, s);
+            cub.ensure(need);
+            exclusive_scan_i32_to_i64(cub.p, need, len.as<int32_t>(), P.as<int64_t>(), (int64_t)S + 1, s);
+            k_item_flags<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint32_t>(), P.as<int64_t>(), part_off.as<int32_t>(),
+                                                          S, flag.as<int32_t>());
+            FOLTY_LAUNCHED();
+            need = inclusive_scan_i32(nullptr, 0, flag.as<int32_t>(), fid.as<int32_t>(), S, s);
+            cub.ensure(need);
+            inclusive_scan_i32(cub.p, need, flag.as<int32_t>(), fid.as<int32_t>(), S, s);
+            k_item_starts<<<grid_for(S, BLK), BLK, 0, s>>>(flag.as<int32_t>(), fid.as<int32_t>(), S,
+                                                           start.as<int32_t>());
+            FOLTY_LAUNCHED();
+            FOLTY_HIP(hipMemcpyAsync(&ni, fid.as<int32_t>() + (S - 1), 4, hipMemcpyDeviceToHost, s));
+            FOLTY_HIP(hipMemcpyAsync(&probes, P.as<int64_t>() + S, 8, hipMemcpyDeviceToHost, s));
+            FOLTY_HIP(hipStreamSynchronize(s));
+            k_fill<int32_t><<<1, 1, 0, s>>>(start.as<int32_t>() + ni, S, 1);
+            FOLTY_LAUNCHED();
+        }
+        ix.item.ensure(sizeof(EnumItem) * ((size_t)ni + 1));
+        if (ni > 0) {
+            k_items<<<grid_for(ni, BLK), BLK, 0, s>>>(start.as<int32_t>(), ix.seg.as<int4>(), P.as<int64_t>(),
+                                                      ix.ooff.as<int32_t>(), ni, ix.item.as<EnumItem>());
+            FOLTY_LAUNCHED();
+        }
+        FOLTY_HIP(hipStreamSynchronize(s)); // the temporaries go back to the pool
+    }
+    ix.otail.release();
     ix.NI = ni;
-    ix.probes = h[1];
-    ix.item.ensure(sizeof(int4) * ((size_t)ni + 1));
-    k_item_recs<<<grid_for(n, BLK), BLK, 0, s>>>(ix.item_off.as<int32_t>(), ix.ooff.as<int32_t>(), n,
-                                                 ix.item.as<int4>());
-    ix.vrow.ensure(sizeof(int2) * ((size_t)S + 1));
-    if (S > 0) k_vrow<<<grid_for(S, BLK), BLK, 0, s>>>(ix.ooff.as<int32_t>(), ix.oadj.as<int32_t>(), S, ix.vrow.as<int2>());
-    FOLTY_LAUNCHED();
+    ix.probes = probes;
     // triangle slots per item are made on first use (plans, the server's memory
     // estimate, the cached list): a single query counts its survivors itself
     ix.T = -1;
@@ -484,8 +552,8 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
         if (ix.T > 0) {
             ix.tri.ensure(12 * (size_t)ix.T);
             CacheSink sink{ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), 0};
-            k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
-                                                     ix.vrow.as<int2>(), ni, sink);
+            k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(),
+                                                     ix.seg.as<int4>(), ni, sink);
             FOLTY_LAUNCHED();
             ix.tri_cached = true;
         }
@@ -504,8 +572,8 @@ void ensure_tri_base(Index &ix, hipStream_t s) {
     FOLTY_LAUNCHED();
     if (ni > 0) {
         CountSink cs{tri_it.as<int32_t>(), 0};
-        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
-                                                 ix.vrow.as<int2>(), ni, cs);
+        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(),
+                                                 ix.seg.as<int4>(), ni, cs);
         FOLTY_LAUNCHED();
     }
     size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(),
@@ -534,8 +602,8 @@ void ensure_tcnt(Index &ix, hipStream_t s) {
         k_fill<int32_t><<<grid_for(ix.S, BLK), BLK, 0, s>>>(ix.tcnt.as<int32_t>(), 0, ix.S);
         FOLTY_LAUNCHED();
         TcntSink sink{ix.oeid.as<uint32_t>(), ix.tcnt.as<int32_t>()};
-        k_tri_enum<<<enum_grid(ix.NI), BLK, 0, s>>>(ix.item.as<int4>(), ix.oadj.as<int32_t>(),
-                                                    ix.vrow.as<int2>(), ix.NI, sink);
+        k_tri_enum<<<enum_grid(ix.NI), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(),
+                                                    ix.seg.as<int4>(), ix.NI, sink);
         FOLTY_LAUNCHED();
     }
     ix.tcnt_ready = true;

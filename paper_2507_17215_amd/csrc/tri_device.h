@@ -14,7 +14,7 @@ constexpr int CAP = 512;              // N+(u) staged in LDS up to this length
 constexpr int IPT = 8;                // temporal tests per chunk
 constexpr int PERSIST_BLOCKS = 4096;
 constexpr int ENUM_BLOCKS = 4096;
-constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item
+constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item (about; whole segments)
 
 __device__ inline int lane_id() { return __lane_id(); }
 
@@ -244,7 +244,7 @@ struct CountSink {
     __device__ void end(int64_t u) {
         if (lane_id() == 0) tri_u[u] = c;
     }
-    __device__ void prefetch(int32_t, int32_t) {}
+    __device__ void prefetch(int32_t, int32_t, bool) {}
     __device__ void finish() {}
 };
 
@@ -264,7 +264,7 @@ struct CacheSink {
         slot += __popcll(mask);
     }
     __device__ void end(int64_t) {}
-    __device__ void prefetch(int32_t, int32_t) {}
+    __device__ void prefetch(int32_t, int32_t, bool) {}
     __device__ void finish() {}
 };
 
@@ -280,7 +280,7 @@ struct TcntSink {
         }
     }
     __device__ void end(int64_t) {}
-    __device__ void prefetch(int32_t, int32_t) {}
+    __device__ void prefetch(int32_t, int32_t, bool) {}
     __device__ void finish() {}
 };
 
@@ -326,12 +326,14 @@ template <int VAR, int MODE> struct FilterSink {
     int32_t ns;
     int64_t work;
     unsigned long long nhit;
-    uint2 pra, prc; // ranges of the edges (u, v) and (v, w) of the next hit, loaded early
-    // called for every probe that may hit, before hit(): edges (u, v) and (v, w)
-    // are known before the search that finds (u, w)
-    __device__ void prefetch(int32_t a, int32_t c) {
+    uint2 pra, prk; // ranges of edge (x0, x1) and of the known one of (x0, x2) / (x1, x2)
+    bool pkb;       // the known one is (x0, x2)
+    // called for every probe that may hit, before hit(): edge (x0, x1) and one of
+    // the other two are known before the search that finds the third
+    __device__ void prefetch(int32_t a, int32_t k, bool k_is_b) {
         pra = rng[a];
-        prc = rng[c];
+        prk = rng[k];
+        pkb = k_is_b;
     }
     __device__ void begin(int64_t it) {
         if constexpr (MODE != FILTER_COUNT) slot = base[it];
@@ -342,8 +344,9 @@ template <int VAR, int MODE> struct FilterSink {
         if constexpr (MODE == FILTER_COUNT) nhit += (unsigned long long)__popcll(__ballot(h));
         int64_t wk = 0;
         if (h) {
-            const uint2 rb = rng[b];
-            if (ranges_meet(pra, rb, dq) && ranges_meet(pra, prc, dq) && ranges_meet(rb, prc, dq)) {
+            const uint2 rb = pkb ? prk : rng[b];
+            const uint2 rc = pkb ? rng[c] : prk;
+            if (ranges_meet(pra, rb, dq) && ranges_meet(pra, rc, dq) && ranges_meet(rb, rc, dq)) {
                 if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
                 else wk = tri_work_rt(variant, load_lists(rec, a, b, c), dmax);
             }
@@ -379,134 +382,141 @@ template <int VAR, int MODE> struct FilterSink {
     }
 };
 
-// LDS of one wavefront's enumeration item.  The bitmap holds one hash bit per
-// vertex of N+(u), so a probe whose bit is clear misses without a search; the
-// other probes (the hits and a few collisions) wait in a queue until 64 of them
-// fill a wavefront, which then searches N+(u) exactly and hands its triangles
-// to the sink.  Only about one probe in seven reaches the search.  8 KB per
-// wavefront.
+// LDS of one wavefront's enumeration item: the owner's out-row N+(w), the
+// item's probe segments, and a bitmap with one hash bit per vertex of N+(w), so
+// a probe whose bit is clear misses without a search.  The other probes (the
+// hits and a few collisions) wait in a queue until 64 of them fill a wavefront,
+// which then searches N+(w) exactly and hands its triangles to the sink.  7 KB
+// per wavefront.
+constexpr int ITEM_SEGS = 256;              // probe segments per item
 constexpr int BM_LOG = 13;                  // 8192 bits
 constexpr int BM_WORDS = 1 << (BM_LOG - 5);
 constexpr int QCAP = 128;                   // < 64 waiting + one step's 64
 constexpr int ENUM_UNROLL = 4;              // probe steps whose loads overlap
-constexpr int Q_SHIFT = 12;                 // CHUNK = 2^12 probes per item
+constexpr int Q_SHIFT = 13;                 // probes of an item < CHUNK + CAP <= 2^13
 struct EnumLds {
-    int32_t nu[CAP];      // N+(u), ascending
-    int32_t off[CAP];     // row start of v_i minus PRE[i]: probe q reads oadj[off[i] + q]
-    int32_t pre[CAP];     // PRE[i+1] = sum of |N+(v_j)| over j <= i
+    int32_t nu[CAP];        // N+(w), ascending
+    int32_t off[ITEM_SEGS]; // row start of segment i minus PRE[i]: probe q reads oadj[off[i] + q]
+    int32_t pre[ITEM_SEGS]; // PRE[i+1] = total row length of segments j <= i
+    int32_t pm[ITEM_SEGS];  // oriented edge (u, v) of segment i | mode B << 31
     uint32_t bm[BM_WORDS];
-    int32_t qx[QCAP];     // waiting probes: x
-    int32_t qr[QCAP];     // and (q - first probe of the item) | i << Q_SHIFT
+    int32_t qx[QCAP];       // waiting probes: x
+    int32_t qr[QCAP];       // and q | i << Q_SHIFT
 };
-static_assert(CHUNK == (1 << Q_SHIFT) && CAP <= (1 << (31 - Q_SHIFT)), "queue packing");
+static_assert(CHUNK + CAP <= (1 << Q_SHIFT) && ITEM_SEGS <= (1 << (31 - Q_SHIFT)), "queue packing");
 
 __device__ inline uint32_t bm_hash(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - BM_LOG); }
 
-// the first cnt waiting probes, one per lane: exact search of x in N+(u) after v_i
+constexpr uint32_t MODE_B = 0x80000000u;
+
+// Hands the triangle of segment edge (u, v) = pm, probe position p and owner-row
+// position pw to the sink as (edge (x0,x1), edge (x0,x2), edge (x1,x2)):
+// mode A: p is in v's row, pw in u's;  mode B: p is in u's row, pw in v's.
+__device__ inline void tri_edges(int32_t pm, int32_t p, int32_t pw, int32_t &e01, int32_t &e02, int32_t &e12) {
+    e01 = (int32_t)((uint32_t)pm & ~MODE_B);
+    if ((uint32_t)pm & MODE_B) {
+        e02 = p;
+        e12 = pw;
+    } else {
+        e02 = pw;
+        e12 = p;
+    }
+}
+
+// the first cnt waiting probes, one per lane: exact search of x in N+(w)
 template <class Sink>
-__device__ inline void enum_batch(int32_t b, int32_t d, int32_t q_begin, const EnumLds &L, int32_t cnt,
-                                  Sink &sink) {
+__device__ inline void enum_batch(int32_t b, int32_t d, const EnumLds &L, int32_t cnt, Sink &sink) {
     const int lane = lane_id();
     bool hit = false;
-    int32_t pa = 0, pb = 0, pc = 0;
+    int32_t e01 = 0, e02 = 0, e12 = 0;
     if (lane < cnt) {
         const int32_t x = L.qx[lane], r = L.qr[lane];
         const int32_t i = r >> Q_SHIFT;
-        pa = b + i;
-        pc = L.off[i] + q_begin + (r & (CHUNK - 1));
-        sink.prefetch(pa, pc);
-        int32_t a = i + 1, c = d; // x > v_i, so it can only sit after i
+        const int32_t pm = L.pm[i];
+        const int32_t p = L.off[i] + (r & ((1 << Q_SHIFT) - 1));
+        sink.prefetch((int32_t)((uint32_t)pm & ~MODE_B), p, ((uint32_t)pm & MODE_B) != 0);
+        int32_t a = 0, c = d;
         while (a < c) {
             int32_t mid = (a + c) >> 1;
             if (L.nu[mid] < x) a = mid + 1;
             else c = mid;
         }
         hit = a < d && L.nu[a] == x;
-        pb = b + a;
+        tri_edges(pm, p, b + a, e01, e02, e12);
     }
-    sink.hit(hit, pa, pb, pc);
+    sink.hit(hit, e01, e02, e12);
 }
 
-// One wavefront per item: the item's vertex u, and a range of the flattened
-// wedge space of u (position q = sum of |N+(v_j)| over j < i, plus the position
-// of x in N+(v_i)).  Sinks see the triangles of an item in a fixed order.
-// The first 64 entries of an item's row (this lane's), loaded one item ahead.
+// The first 64 entries of an item's owner row and of its segments (this
+// lane's), loaded one item ahead.
 struct StageAhead {
     int32_t v;
-    int2 row;
+    int4 sg;
 };
 
-__device__ inline StageAhead stage_ahead(const int4 &item, const int32_t *__restrict__ oadj,
-                                         const int2 *__restrict__ vrow) {
-    StageAhead a{0, make_int2(0, 0)};
+__device__ inline StageAhead stage_ahead(const EnumItem &item, const int32_t *__restrict__ oadj,
+                                         const int4 *__restrict__ seg) {
+    StageAhead a{0, make_int4(0, 0, 0, 0)};
     const int lane = lane_id();
-    if (item.w >= 2 && item.w <= CAP && lane < item.w) {
-        a.v = oadj[item.z + lane];
-        a.row = vrow[item.z + lane];
+    if (item.d >= 1 && item.d <= CAP && item.nq > 0) {
+        if (lane < item.d) a.v = oadj[item.b + lane];
+        if (lane < item.ng) a.sg = seg[item.g0 + lane];
     }
     return a;
 }
 
+// One wavefront per item: the owner's out-row and the item's segments, whose
+// rows are probed as one flat range q in [0, nq).  Sinks see the triangles of
+// an item in a fixed order.
 template <class Sink>
-__device__ inline void enum_item(const int4 item, const StageAhead &ahead, const int32_t *__restrict__ oadj,
-                                 const int2 *__restrict__ vrow, int64_t it, Sink &sink, EnumLds &L) {
+__device__ inline void enum_item(const EnumItem &item, const StageAhead &ahead, const int32_t *__restrict__ oadj,
+                                 const int4 *__restrict__ seg, int64_t it, Sink &sink, EnumLds &L) {
     const int lane = lane_id();
-    const int32_t part = item.y, b = item.z, d = item.w;
+    const int32_t b = item.b, d = item.d, ng = item.ng, nq = item.nq;
     sink.begin(it);
-    if (d >= 2 && d <= CAP) {
-        // stage N+(u), each v's row start and a prefix of |N+(v)|
-        int32_t carry = 0;
-        for (int32_t i0 = 0; i0 < d; i0 += 64) {
-            const int32_t i = i0 + lane;
-            int32_t dv = 0, vo = 0;
-            if (i < d) {
-                int2 row;
-                if (i0 == 0) {
-                    row = ahead.row;
-                    L.nu[i] = ahead.v;
-                } else {
-                    row = vrow[b + i];
-                    L.nu[i] = oadj[b + i];
-                }
-                vo = row.x;
-                dv = row.y;
-            }
-            const int32_t x = wave_inclusive_sum(dv);
-            if (i < d) {
-                L.pre[i] = carry + x;
-                L.off[i] = vo - (carry + x - dv);
-            }
-            carry += __shfl(x, 63);
-        }
+    if (d >= 1 && d <= CAP && nq > 0) {
+        // stage N+(w) and its hash bits, then the segments with a prefix of
+        // their row lengths
         for (int w = lane; w < BM_WORDS; w += 64) L.bm[w] = 0;
+        for (int32_t i = lane; i < d; i += 64) L.nu[i] = i < 64 ? ahead.v : oadj[b + i];
         wave_sync();
         for (int32_t i = lane; i < d; i += 64) {
             const uint32_t h = bm_hash(L.nu[i]);
             atomicOr(&L.bm[h >> 5], 1u << (h & 31));
         }
+        int32_t carry = 0;
+        for (int32_t i0 = 0; i0 < ng; i0 += 64) {
+            const int32_t i = i0 + lane;
+            int4 sg = make_int4(0, 0, 0, 0);
+            if (i < ng) sg = i0 == 0 ? ahead.sg : seg[item.g0 + i];
+            const int32_t x = wave_inclusive_sum(sg.y);
+            if (i < ng) {
+                L.pre[i] = carry + x;
+                L.off[i] = sg.x - (carry + x - sg.y);
+                L.pm[i] = sg.z;
+            }
+            carry += __shfl(x, 63);
+        }
         wave_sync();
-        const int32_t q_begin = part * CHUNK;
-        const int32_t q_end = carry < q_begin + CHUNK ? carry : q_begin + CHUNK;
-        int32_t i = 0; // this lane's segment; q only grows, so i only grows
+        int32_t i = 0;  // this lane's segment; q only grows, so i only grows
         int32_t qn = 0; // waiting probes (wave-uniform)
         // ENUM_UNROLL steps of 64 probes at a time: their loads of x are all in
         // flight before the first is used
-        for (int32_t q0 = q_begin; q0 < q_end; q0 += 64 * ENUM_UNROLL) {
+        for (int32_t q0 = 0; q0 < nq; q0 += 64 * ENUM_UNROLL) {
             int32_t rk[ENUM_UNROLL], xk[ENUM_UNROLL];
             bool vk[ENUM_UNROLL];
 #pragma unroll
             for (int k = 0; k < ENUM_UNROLL; k++) {
                 const int32_t q = q0 + 64 * k + lane;
-                vk[k] = q < q_end;
+                vk[k] = q < nq;
                 xk[k] = 0;
                 rk[k] = 0;
                 if (vk[k]) {
-                    // the segment of q (the i with PRE[i] <= q < PRE[i+1]); q grows by
-                    // 64 per step and segments average far more than that, so walk a
-                    // few segments forward before bisecting.  PRE[d] > q stops both.
+                    // the segment of q (the i with PRE[i] <= q < PRE[i+1]); walk a few
+                    // segments forward before bisecting.  PRE[ng] = nq > q stops both.
                     for (int w = 0; w < 4 && L.pre[i] <= q; w++) i++;
                     if (L.pre[i] <= q) {
-                        int32_t lo = i + 1, hi = d;
+                        int32_t lo = i + 1, hi = ng;
                         while (lo < hi) {
                             int32_t mid = (lo + hi) >> 1;
                             if (L.pre[mid] <= q) lo = mid + 1;
@@ -515,7 +525,7 @@ __device__ inline void enum_item(const int4 item, const StageAhead &ahead, const
                         i = lo;
                     }
                     xk[k] = L.off[i] + q; // position of x, replaced by x below
-                    rk[k] = (q - q_begin) | (i << Q_SHIFT);
+                    rk[k] = q | (i << Q_SHIFT);
                 }
             }
 #pragma unroll
@@ -536,7 +546,7 @@ __device__ inline void enum_item(const int4 item, const StageAhead &ahead, const
                 qn += (int32_t)__popcll(mask);
                 if (qn >= 64) {
                     wave_sync();
-                    enum_batch(b, d, q_begin, L, 64, sink);
+                    enum_batch(b, d, L, 64, sink);
                     const int32_t rest = qn - 64;
                     int32_t tx = 0, tr = 0;
                     if (lane < rest) {
@@ -555,31 +565,31 @@ __device__ inline void enum_item(const int4 item, const StageAhead &ahead, const
         }
         if (qn > 0) {
             wave_sync();
-            enum_batch(b, d, q_begin, L, qn, sink);
+            enum_batch(b, d, L, qn, sink);
         }
         wave_sync(); // the next item overwrites this wave's LDS
-    } else if (d > CAP) {
-        // long rows (only for orientations without the degeneracy bound): one
-        // item per vertex, the same probes against N+(u) in global memory
-        for (int32_t i = 0; i < d; i++) {
-            const int2 row = vrow[b + i];
-            const int32_t vb = row.x, ve = row.x + row.y;
-            for (int32_t p0 = vb; p0 < ve; p0 += 64) {
+    } else if (d > CAP && nq > 0) {
+        // long owner rows (only for orientations without the degeneracy bound):
+        // the same probes, searched in N+(w) in global memory
+        for (int32_t g = item.g0; g < item.g0 + ng; g++) {
+            const int4 sg = seg[g];
+            for (int32_t p0 = sg.x; p0 < sg.x + sg.y; p0 += 64) {
                 const int32_t p = p0 + lane;
                 bool hit = false;
-                int32_t a = i + 1;
-                if (p < ve) {
-                    sink.prefetch(b + i, p);
+                int32_t e01 = 0, e02 = 0, e12 = 0;
+                if (p < sg.x + sg.y) {
+                    sink.prefetch((int32_t)((uint32_t)sg.z & ~MODE_B), p, ((uint32_t)sg.z & MODE_B) != 0);
                     const int32_t x = oadj[p];
-                    int32_t c = d;
+                    int32_t a = 0, c = d;
                     while (a < c) {
                         int32_t mid = (a + c) >> 1;
                         if (oadj[b + mid] < x) a = mid + 1;
                         else c = mid;
                     }
                     hit = a < d && oadj[b + a] == x;
+                    tri_edges(sg.z, p, b + a, e01, e02, e12);
                 }
-                sink.hit(hit, b + i, b + a, p);
+                sink.hit(hit, e01, e02, e12);
             }
         }
     }
@@ -596,19 +606,16 @@ __device__ inline void cached_item(const int64_t *__restrict__ base, const int32
     for (int64_t p0 = b; p0 < e; p0 += 64) {
         int64_t p = p0 + lane;
         bool valid = p < e;
-        if (valid) sink.prefetch(tri[3 * p], tri[3 * p + 2]);
+        if (valid) sink.prefetch(tri[3 * p], tri[3 * p + 2], false);
         sink.hit(valid, valid ? tri[3 * p] : 0, valid ? tri[3 * p + 1] : 0, valid ? tri[3 * p + 2] : 0);
     }
     sink.end(it);
 }
 
-// One wavefront per item: the item's vertex u, and a range of the flattened
-// wedge space of u (position q = sum of |N+(v_j)| over j < i, plus the position
-// of x in N+(v_i)).
-// only != nullptr: items with only[it] == 0 are skipped
+// One wavefront per item; only != nullptr: items with only[it] == 0 are skipped
 template <class Sink>
-__global__ __launch_bounds__(BLK) void k_tri_enum(const int4 *__restrict__ items, const int32_t *__restrict__ oadj,
-                                                  const int2 *__restrict__ vrow, int32_t NI, Sink sink,
+__global__ __launch_bounds__(BLK) void k_tri_enum(const EnumItem *__restrict__ items, const int32_t *__restrict__ oadj,
+                                                  const int4 *__restrict__ seg, int32_t NI, Sink sink,
                                                   const int32_t *__restrict__ only = nullptr) {
     __shared__ EnumLds lds[WPB];
     const int w = threadIdx.x >> 6;
@@ -618,25 +625,25 @@ __global__ __launch_bounds__(BLK) void k_tri_enum(const int4 *__restrict__ items
         // a pass over a few marked items: no loads ahead for the skipped ones
         for (; it < NI; it += stride) {
             if (only[it] == 0) continue;
-            const int4 item = items[it];
-            enum_item(item, stage_ahead(item, oadj, vrow), oadj, vrow, it, sink, lds[w]);
+            const EnumItem item = items[it];
+            enum_item(item, stage_ahead(item, oadj, seg), oadj, seg, it, sink, lds[w]);
         }
         sink.finish();
         return;
     }
-    // item headers run two items ahead and the first row chunk one item ahead,
-    // so a wavefront starts each item with its data already loaded
-    const int4 none = make_int4(0, 0, 0, 0);
-    int4 h0 = it < NI ? items[it] : none;
-    int4 h1 = it + stride < NI ? items[it + stride] : none;
-    StageAhead a0 = stage_ahead(h0, oadj, vrow);
+    // item headers run two items ahead and the first row and segment chunks
+    // one item ahead, so a wavefront starts each item with its data loaded
+    const EnumItem none{};
+    EnumItem h0 = it < NI ? items[it] : none;
+    EnumItem h1 = it + stride < NI ? items[it + stride] : none;
+    StageAhead a0 = stage_ahead(h0, oadj, seg);
     for (; it < NI; it += stride) {
-        const int4 cur = h0;
+        const EnumItem cur = h0;
         const StageAhead ca = a0;
         h0 = h1;
-        a0 = stage_ahead(h0, oadj, vrow);
+        a0 = stage_ahead(h0, oadj, seg);
         h1 = it + 2 * stride < NI ? items[it + 2 * stride] : none;
-        enum_item(cur, ca, oadj, vrow, it, sink, lds[w]);
+        enum_item(cur, ca, oadj, seg, it, sink, lds[w]);
     }
     sink.finish();
 }
