@@ -119,7 +119,8 @@ typedef struct {
     int64_t triangles;        /* static triangles (counted by the first query or stats call) */
     int64_t max_multiplicity; /* sigma_max: longest list E_{x,y} */
     int64_t peel_rounds;      /* rounds of the min-degree peeling */
-    int64_t closing_probes;   /* membership probes of the enumeration: sum over (u,v) of |N+(v)| */
+    int64_t closing_probes;   /* membership probes of the enumeration: sum over oriented edges
+                                 (u,v) of min(|N+(u)|, |N+(v)|) */
     int64_t enum_items;       /* work items the enumeration is split into */
     int64_t batch_size;       /* server: requests that shared this request's pass */
     /* query only */

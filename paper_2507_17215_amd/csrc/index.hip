@@ -230,14 +230,22 @@ struct PeelCount {    // what step i produced
     int32_t min_above;
 };
 
+// a frontier vertex with its adjacency row, so that a round reads the row
+// without another lookup
+struct alignas(16) FEntry {
+    int32_t x, len;
+    int64_t start;
+};
+
 struct PeelBufs {
     const int64_t *uoff;
-    const int32_t *uadj;     // neighbour id, or HUB_FLAG | hub slot for a hub neighbour
+    const int32_t *uadj;       // neighbour id, or HUB_FLAG | hub slot for a hub neighbour
+    const int32_t *uadj_plain; // neighbour ids only (rounds that do not aggregate hubs)
     const int32_t *hub_vertex;
     int32_t n_hubs;
     const int32_t *deg;
     int32_t *dcur, *rnd, *core;
-    int32_t *FT[3], *FS[3], *FB[3];
+    FEntry *FT[3], *FS[3], *FB[3];
     int32_t *alive[2];
     PeelState *state;  // [2]
     PeelCount *count;  // [3]
@@ -301,17 +309,26 @@ struct PushBuf {
 };
 
 // move a wave's buffered pushes to the global lists with wave-level atomics
-__device__ inline void push_flush_wave(PushBuf &pb, const PeelBufs &B, PeelCount *out, int32_t *const L[3]) {
+__device__ inline FEntry row_entry(const PeelBufs &B, int32_t y) {
+    FEntry e;
+    e.x = y;
+    e.start = B.uoff[y];
+    e.len = (int32_t)(B.uoff[y + 1] - e.start);
+    return e;
+}
+
+__device__ inline void push_flush_wave(PushBuf &pb, const PeelBufs &B, PeelCount *out, FEntry *const L[3]) {
     int32_t *cnt[3] = {&out->nT, &out->nS, &out->nB};
     for (int32_t i0 = 0; i0 < pb.n; i0 += 64) {
         int32_t i = i0 + lane_id();
         bool v = i < pb.n;
-        int32_t y = v ? pb.buf[i] : 0;
-        int c = v ? push_class(B.deg[y]) : -1;
+        FEntry e{};
+        if (v) e = row_entry(B, pb.buf[i]);
+        int c = v ? push_class(e.len) : -1;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             int32_t slot = wave_append(cnt[j], c == j);
-            if (slot >= 0) L[j][slot] = y;
+            if (slot >= 0) L[j][slot] = e;
         }
     }
     pb.n = 0;
@@ -322,34 +339,30 @@ __device__ inline void push_flush_wave(PushBuf &pb, const PeelBufs &B, PeelCount
 // degree is already <= k, so they are never pushed again.
 // agg = large round: hub decrements go to the block's LDS counters and pushes to
 // the wave's LDS buffer; otherwise both go straight to global memory.
+// AGG reads the hub-flagged adjacency, otherwise plain neighbour ids.
 template <bool AGG>
 __device__ inline void peel_neighbour(int32_t y, bool valid, int32_t k, const PeelBufs &B, PeelCount *out,
-                                      PushBuf &pb, int32_t *const L[3], int32_t *hub_cnt) {
+                                      PushBuf &pb, FEntry *const L[3], int32_t *hub_cnt) {
     bool push = false;
+    FEntry e{};
     if (valid) {
-        if ((uint32_t)y & HUB_FLAG) {
+        if (AGG && ((uint32_t)y & HUB_FLAG)) {
             const int32_t h = (int32_t)((uint32_t)y & ~HUB_FLAG);
-            if (AGG) {
-                atomicAdd(&hub_cnt[h], 1);
-                hub_cnt[HUB_SLOTS] = 1; // this block touched a hub
-            } else {
-                y = B.hub_vertex[h];
-                int32_t old = atomicSub(&B.dcur[y], 1);
-                push = (old == k + 1);
-            }
+            atomicAdd(&hub_cnt[h], 1);
+            hub_cnt[HUB_SLOTS] = 1; // this block touched a hub
         } else {
             int32_t old = atomicSub(&B.dcur[y], 1);
             push = (old == k + 1);
         }
     }
     if (!AGG) {
-        int32_t dy = push ? B.deg[y] : 0;
-        int cls = push ? push_class(dy) : -1;
+        if (push) e = row_entry(B, y);
+        int cls = push ? push_class(e.len) : -1;
         int32_t *cnt[3] = {&out->nT, &out->nS, &out->nB};
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             int32_t slot = wave_append(cnt[j], cls == j);
-            if (slot >= 0) L[j][slot] = y;
+            if (slot >= 0) L[j][slot] = e;
         }
         return;
     }
@@ -367,14 +380,14 @@ __device__ inline void peel_neighbour(int32_t y, bool valid, int32_t k, const Pe
 
 // end of a round: every wave's buffered pushes go out with one atomic per block
 // and class
-__device__ inline void push_flush_block(PushBuf &pb, const PeelBufs &B, PeelCount *out, int32_t *const L[3]) {
+__device__ inline void push_flush_block(PushBuf &pb, const PeelBufs &B, PeelCount *out, FEntry *const L[3]) {
     __shared__ int32_t s_cnt[BLK / 64][3];
     __shared__ int32_t s_off[BLK / 64][3];
     const int w = threadIdx.x >> 6, lane = lane_id();
     int32_t cc[3] = {0, 0, 0};
     for (int32_t i0 = 0; i0 < pb.n; i0 += 64) {
         int32_t i = i0 + lane;
-        int c = i < pb.n ? push_class(B.deg[pb.buf[i]]) : -1;
+        int c = i < pb.n ? push_class(B.deg[pb.buf[i]]) : -1; // deg[y] is the row length
 #pragma unroll
         for (int j = 0; j < 3; j++) cc[j] += (int32_t)__popcll(__ballot(c == j));
     }
@@ -397,12 +410,13 @@ __device__ inline void push_flush_block(PushBuf &pb, const PeelBufs &B, PeelCoun
     for (int32_t i0 = 0; i0 < pb.n; i0 += 64) {
         int32_t i = i0 + lane;
         bool v = i < pb.n;
-        int32_t y = v ? pb.buf[i] : 0;
-        int c = v ? push_class(B.deg[y]) : -1;
+        FEntry e{};
+        if (v) e = row_entry(B, pb.buf[i]);
+        int c = v ? push_class(e.len) : -1;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             unsigned long long mask = __ballot(c == j);
-            if (c == j) L[j][off[j] + (int32_t)__popcll(mask & ((1ull << lane) - 1ull))] = y;
+            if (c == j) L[j][off[j] + (int32_t)__popcll(mask & ((1ull << lane) - 1ull))] = e;
             off[j] += (int32_t)__popcll(mask);
         }
     }
@@ -454,8 +468,9 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
     // the frontier is what the previous step wrote
     int32_t nT = s_prev.nT < n ? s_prev.nT : n;
     int32_t nS = s_prev.nS < n ? s_prev.nS : n, nB = s_prev.nB < n ? s_prev.nB : n;
-    const int32_t *FT = B.FT[prv], *FS = B.FS[prv], *FB = B.FB[prv];
-    int32_t *const L[3] = {B.FT[cur], B.FS[cur], B.FB[cur]};
+    const FEntry *FT = B.FT[prv], *FS = B.FS[prv], *FB = B.FB[prv];
+    FEntry *const L[3] = {B.FT[cur], B.FS[cur], B.FB[cur]};
+    const int32_t *adj = AGG ? B.uadj : B.uadj_plain;
     int32_t *s_hub = lds.hub;
     PushBuf pb{lds.push[threadIdx.x >> 6], 0};
     const int32_t r = st.r;
@@ -466,17 +481,17 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
         __syncthreads();
     }
     for (int64_t i = gtid; i < nT; i += stride) {
-        int32_t x = FT[i];
+        int32_t x = FT[i].x;
         B.rnd[x] = r;
         B.core[x] = k;
     }
     for (int64_t i = gtid; i < nS; i += stride) {
-        int32_t x = FS[i];
+        int32_t x = FS[i].x;
         B.rnd[x] = r;
         B.core[x] = k;
     }
     for (int64_t i = gtid; i < nB; i += stride) {
-        int32_t x = FB[i];
+        int32_t x = FB[i].x;
         B.rnd[x] = r;
         B.core[x] = k;
     }
@@ -484,9 +499,10 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
     for (int64_t base = gtid - lane; base < nT; base += stride) {
         int64_t i = base + lane;
         bool v = i < nT;
-        int32_t x = v ? FT[i] : 0;
-        int64_t b = v ? B.uoff[x] : 0;
-        int32_t len = v ? (int32_t)(B.uoff[x + 1] - b) : 0;
+        FEntry fe{};
+        if (v) fe = FT[i];
+        int64_t b = fe.start;
+        int32_t len = fe.len;
         int32_t mx = len;
         for (int o = 32; o > 0; o >>= 1) {
             int32_t other = __shfl_xor(mx, o);
@@ -494,20 +510,20 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
         }
         for (int32_t j = 0; j < mx; j++) {
             bool valid = j < len;
-            peel_neighbour<AGG>(valid ? B.uadj[b + j] : 0, valid, k, B, out, pb, L, s_hub);
+            peel_neighbour<AGG>(valid ? adj[b + j] : 0, valid, k, B, out, pb, L, s_hub);
         }
     }
     // small frontiers get several waves per vertex (wave w works on vertex
     // w mod nS, every wpv-th chunk starting at chunk w / nS)
     const int64_t wpv = nS > 0 && nS < nwaves ? nwaves / nS : 1;
     for (int64_t w = gwave; w < nS * wpv; w += nwaves) {
-        int32_t x = FS[w % nS];
+        const FEntry fe = FS[w % nS];
         int64_t part = w / nS;
-        int64_t b = B.uoff[x], e = B.uoff[x + 1];
+        int64_t b = fe.start, e = fe.start + fe.len;
         for (int64_t p0 = b + part * 64; p0 < e; p0 += wpv * 64) {
             int64_t p = p0 + lane;
             bool valid = p < e;
-            peel_neighbour<AGG>(valid ? B.uadj[p] : 0, valid, k, B, out, pb, L, s_hub);
+            peel_neighbour<AGG>(valid ? adj[p] : 0, valid, k, B, out, pb, L, s_hub);
         }
     }
     // high-degree vertices: the whole grid strides over the 64-entry chunks of
@@ -521,10 +537,7 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
         for (int32_t j0 = 0; j0 < nB; j0 += BLK) {
             int32_t j = j0 + threadIdx.x;
             int32_t c = 0;
-            if (j < nB) {
-                int32_t x = FB[j];
-                c = (int32_t)((B.uoff[x + 1] - B.uoff[x] + 63) >> 6);
-            }
+            if (j < nB) c = (FB[j].len + 63) >> 6;
             // block inclusive scan of c (wave scans, then wave totals)
             int32_t v = c;
             for (int o = 1; o < 64; o <<= 1) {
@@ -554,20 +567,20 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
                 if (s_bpre[mid + 1] <= c) lo = mid + 1;
                 else hi = mid;
             }
-            int32_t x = FB[lo];
-            int64_t b = B.uoff[x], e = B.uoff[x + 1];
+            const FEntry fe = FB[lo];
+            int64_t b = fe.start, e = fe.start + fe.len;
             int64_t p = b + (c - s_bpre[lo]) * 64 + lane;
             bool valid = p < e;
-            peel_neighbour<AGG>(valid ? B.uadj[p] : 0, valid, k, B, out, pb, L, s_hub);
+            peel_neighbour<AGG>(valid ? adj[p] : 0, valid, k, B, out, pb, L, s_hub);
         }
     } else {
         for (int32_t j = 0; j < nB; j++) {
-            int32_t x = FB[j];
-            int64_t b = B.uoff[x], e = B.uoff[x + 1];
+            const FEntry fe = FB[j];
+            int64_t b = fe.start, e = fe.start + fe.len;
             for (int64_t p0 = b + gwave * 64; p0 < e; p0 += nwaves * 64) {
                 int64_t p = p0 + lane;
                 bool valid = p < e;
-                peel_neighbour<AGG>(valid ? B.uadj[p] : 0, valid, k, B, out, pb, L, s_hub);
+                peel_neighbour<AGG>(valid ? adj[p] : 0, valid, k, B, out, pb, L, s_hub);
             }
         }
     }
@@ -579,16 +592,17 @@ __device__ inline void peel_round(const PeelBufs &B, const PeelState &st, const 
         int32_t h = h0 + threadIdx.x;
         int32_t c = h < H ? s_hub[h] : 0;
         bool push = false;
-        int32_t y = 0;
+        FEntry fe{};
         if (c) {
-            y = B.hub_vertex[h];
+            const int32_t y = B.hub_vertex[h];
             int32_t old = atomicSub(&B.dcur[y], c);
             push = old > k && old - c <= k;
+            if (push) fe = row_entry(B, y);
         }
-        int32_t slot = wave_append(&out->nB, push && B.deg[y] > BIG_DEG);
-        if (slot >= 0) L[2][slot] = y;
-        slot = wave_append(&out->nS, push && B.deg[y] <= BIG_DEG);
-        if (slot >= 0) L[1][slot] = y;
+        int32_t slot = wave_append(&out->nB, push && fe.len > BIG_DEG);
+        if (slot >= 0) L[2][slot] = fe;
+        slot = wave_append(&out->nS, push && fe.len <= BIG_DEG);
+        if (slot >= 0) L[1][slot] = fe;
     }
     push_flush_block(pb, B, out, L);
 }
@@ -622,7 +636,7 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
         int32_t na = st.alive_n < n ? st.alive_n : n;
         const int32_t *A = B.alive[st.lp];
         int32_t *A2 = B.alive[st.lp ^ 1];
-        int32_t *FT = B.FT[cur], *FS = B.FS[cur], *FB = B.FB[cur];
+        FEntry *FT = B.FT[cur], *FS = B.FS[cur], *FB = B.FB[cur];
         int32_t *const g[4] = {&out->nT, &out->nS, &out->nB, &out->nA};
         int32_t local_min = 0x7fffffff;
         for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += stride) {
@@ -632,16 +646,18 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
             bool live = valid && B.rnd[x] < 0;
             int32_t d = live ? B.dcur[x] : 0;
             bool take = live && d <= k;
-            int32_t dx = take ? B.deg[x] : 0;
+            FEntry fe{};
+            if (take) fe = row_entry(B, x);
+            const int32_t dx = fe.len;
             bool keep = live && d > k;
             if (keep && d < local_min) local_min = d;
             const bool p[4] = {take && dx <= TINY_DEG, take && dx > TINY_DEG && dx <= BIG_DEG, take && dx > BIG_DEG,
                                keep};
             int32_t slot[4];
             block_append4(p, g, slot);
-            if (slot[0] >= 0) FT[slot[0]] = x;
-            if (slot[1] >= 0) FS[slot[1]] = x;
-            if (slot[2] >= 0) FB[slot[2]] = x;
+            if (slot[0] >= 0) FT[slot[0]] = fe;
+            if (slot[1] >= 0) FS[slot[1]] = fe;
+            if (slot[2] >= 0) FB[slot[2]] = fe;
             if (slot[3] >= 0) A2[slot[3]] = x;
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -706,11 +722,14 @@ __global__ void k_find_hubs(const int32_t *__restrict__ deg, int32_t n, int32_t 
     }
 }
 
-__global__ void k_mark_hubs(int32_t *__restrict__ uadj, int64_t E, const int32_t *__restrict__ hub_of) {
+// the peeling adjacency of large rounds: hub neighbours as HUB_FLAG | slot
+__global__ void k_mark_hubs(const int32_t *__restrict__ uadj, int64_t E, const int32_t *__restrict__ hub_of,
+                            int32_t *__restrict__ uadj_h) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= E) return;
-    int32_t h = hub_of[uadj[i]];
-    if (h >= 0) uadj[i] = (int32_t)(HUB_FLAG | (uint32_t)h);
+    const int32_t y = uadj[i];
+    const int32_t h = hub_of[y];
+    uadj_h[i] = h >= 0 ? (int32_t)(HUB_FLAG | (uint32_t)h) : y;
 }
 
 __global__ void k_adj_deg(const int64_t *__restrict__ uoff, int32_t n, int32_t *__restrict__ deg) {
@@ -994,7 +1013,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
 
     // ---- degrees and undirected adjacency (sorted (x, y) keys) -----------------------
     ix.deg.ensure(4 * ((size_t)n + 1));
-    DevBuf uoff, uadj;
+    DevBuf uoff, uadj, uadj_h;
     uoff.ensure(8 * ((size_t)n + 1));
     uadj.ensure(8 * (size_t)S + 8);
     {
@@ -1031,8 +1050,9 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         n_hubs = *hb.as<int32_t>();
         if (n_hubs > HUB_SLOTS) n_hubs = HUB_SLOTS;
         if (n_hubs > 0 && S > 0) {
+            uadj_h.ensure(8 * (size_t)S + 8);
             k_mark_hubs<<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(uadj.as<int32_t>(), 2 * (int64_t)S,
-                                                                     hub_of.as<int32_t>());
+                                                                     hub_of.as<int32_t>(), uadj_h.as<int32_t>());
             FOLTY_LAUNCHED();
         }
     }
@@ -1042,7 +1062,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     DevBuf dcur, rnd, fr, alive, pst;
     dcur.ensure(4 * (size_t)n);
     rnd.ensure(4 * (size_t)n);
-    fr.ensure(4 * 9 * (size_t)n);
+    fr.ensure(sizeof(FEntry) * 9 * (size_t)n);
     alive.ensure(4 * 2 * (size_t)n);
     pst.ensure(2 * sizeof(PeelState) + 3 * sizeof(PeelCount));
     k_peel_init<<<grid_for(n, BLK), BLK, 0, s>>>(ix.deg.as<int32_t>(), dcur.as<int32_t>(), rnd.as<int32_t>(),
@@ -1060,7 +1080,8 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         FOLTY_HIP(hipMemcpyAsync(pst.p, init, sizeof init, hipMemcpyHostToDevice, s));
         PeelBufs B;
         B.uoff = uoff.as<int64_t>();
-        B.uadj = uadj.as<int32_t>();
+        B.uadj = n_hubs > 0 ? uadj_h.as<int32_t>() : uadj.as<int32_t>();
+        B.uadj_plain = uadj.as<int32_t>();
         B.hub_vertex = hub_vertex.as<int32_t>();
         B.n_hubs = n_hubs;
         B.deg = ix.deg.as<int32_t>();
@@ -1068,9 +1089,9 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         B.rnd = rnd.as<int32_t>();
         B.core = ix.core.as<int32_t>();
         for (int i = 0; i < 3; i++) {
-            B.FT[i] = fr.as<int32_t>() + (size_t)i * n;
-            B.FS[i] = fr.as<int32_t>() + (size_t)(3 + i) * n;
-            B.FB[i] = fr.as<int32_t>() + (size_t)(6 + i) * n;
+            B.FT[i] = fr.as<FEntry>() + (size_t)i * n;
+            B.FS[i] = fr.as<FEntry>() + (size_t)(3 + i) * n;
+            B.FB[i] = fr.as<FEntry>() + (size_t)(6 + i) * n;
         }
         B.alive[0] = alive.as<int32_t>();
         B.alive[1] = alive.as<int32_t>() + (size_t)n;

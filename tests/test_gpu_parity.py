@@ -126,6 +126,30 @@ def test_orientation_does_not_change_results():
         assert np.array_equal(gpu_graph(g, rank_mode=mode, rank_seed=seed).query(10**6, (1, 4), 0).counts(), base)
 
 
+def test_long_out_rows_under_other_orientations():
+    """A hub with ~1500 neighbours: under a random order (seed 5 ranks it below
+    most of them) its out-row is longer than the rows staged in LDS, so its
+    items take the global-memory search.  Every orientation gives the oracle's
+    counts."""
+    rng = np.random.default_rng(17)
+    g = synth.tiny(seed=23)
+    hub_src = np.full(1500, 7, np.int32)
+    hub_dst = rng.choice(np.arange(8, g.n, dtype=np.int32), size=1500, replace=False)
+    flip = rng.random(1500) < 0.5
+    src = np.concatenate([g.src, np.where(flip, hub_dst, hub_src)]).astype(np.int32)
+    dst = np.concatenate([g.dst, np.where(flip, hub_src, hub_dst)]).astype(np.int32)
+    t = np.concatenate([g.t, rng.integers(0, 1_000_000, 1500)]).astype(np.int64)
+    o = Oracle(g.n, src, dst, t)
+    want = {v: o.query(10**6, 1, 4, v) for v in (0, 3)}
+    for mode, seed in ((folty.RANK_DEGENERACY, 0), (folty.RANK_DEGREE, 0), (folty.RANK_RANDOM, 5)):
+        G = folty.Graph(g.n, src, dst, t).build(rank_mode=mode, rank_seed=seed)
+        say("long rows", mode, "max out-degree", G.stats()["max_out_degree"])
+        if mode == folty.RANK_RANDOM:
+            assert G.stats()["max_out_degree"] > 512
+        for v in (0, 3):
+            assert_same(G.query(10**6, (1, 4), v), want[v])
+
+
 def test_cached_triangles_and_determinism():
     g = synth.tiny(seed=4)
     G = gpu_graph(g)
