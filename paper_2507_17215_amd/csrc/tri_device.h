@@ -388,8 +388,8 @@ template <int VAR, int MODE> struct FilterSink {
 // hits and a few collisions) wait in a queue until 64 of them fill a wavefront,
 // which then searches N+(w) exactly and hands its triangles to the sink.  7 KB
 // per wavefront.
-constexpr int ITEM_SEGS = 256;              // probe segments per item
-constexpr int BM_LOG = 13;                  // 8192 bits
+constexpr int ITEM_SEGS = 128;              // probe segments per item
+constexpr int BM_LOG = 12;                  // 4096 bits
 constexpr int BM_WORDS = 1 << (BM_LOG - 5);
 constexpr int QCAP = 128;                   // < 64 waiting + one step's 64
 constexpr int ENUM_UNROLL = 4;              // probe steps whose loads overlap
