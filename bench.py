@@ -337,8 +337,12 @@ def main():
         G = folty.Graph(n, src, dst, tt).build()
         ok = True
         checked = {}
+        by_delta = {}
         for d in (a.delta, 86_400, synth.YEAR_S):
-            got = G.query(d, theta, 0).counts()
+            rq = G.query(d, theta, 0)
+            by_delta[str(d)] = {k: rq.stats[k] for k in ("query_ms", "wedge_ms", "temporal_ms", "threshold_ms",
+                                                         "tests", "n_pairs", "n_certificates")}
+            got = rq.counts()
             nz = np.nonzero((got != 0xFFFFFFFF) & (got > 0))[0]
             if nz.size > a.parity_sample:
                 nz = np.sort(rng.choice(nz, size=a.parity_sample, replace=False))
@@ -352,6 +356,8 @@ def main():
                 f"{nz.size} the GPU counts as non-zero; oracle non-zero: {int((want > 0).sum())})")
         G.close()
         out["parity_sampled"] = {"bit_exact": ok, "deltas": checked}
+        # the same index queried at wider windows (device times; per-edge counts kept)
+        out["query_by_delta"] = by_delta
     if not a.no_cpu_baseline:
         rng = np.random.default_rng(7)
         k = min(a.cpu_sample, m)

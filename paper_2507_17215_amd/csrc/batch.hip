@@ -40,8 +40,8 @@ struct JobDev {
     int32_t NI, variant;
     int64_t dmax, dq;
     const int64_t *lv;
-    int32_t nl, m;
-    uint32_t *hist; // nl * m
+    int32_t nl, nls, m;
+    uint32_t *hist; // m * nls, edge-major (nls = nl rounded up to 4)
     int32_t *sv;
     int64_t *sw;
     int32_t *su;
@@ -54,11 +54,9 @@ struct JobDev {
 };
 
 struct QueryDev {
-    const int32_t *slo, *shi; // the graph's static edge endpoints (pair output)
-    int32_t level;            // index of the query's delta among its job's levels
+    int32_t level; // index of the query's delta among its job's levels
     uint32_t num, den;
     int32_t universe, excl;
-    int64_t p_base; // first slot of this query in the concatenated 2S pair slots
 };
 
 // the largest index i in [0, n) with base[i] <= x (base ascending, base[0] <= x)
@@ -132,7 +130,7 @@ __global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict
                 else hi = mid - 1;
             }
             r -= J.sw[s0 + lo];
-            PoolOp op{J.lv, J.nl, J.m, J.hist};
+            PoolOp op{J.lv, J.nl, J.nls, J.hist};
             for (int32_t s = lo; s < ns && k < k1; s++) {
                 const int64_t p = s0 + s;
                 TriLists L = load_lists(J.rec, J.sv[3 * p], J.sv[3 * p + 1], J.sv[3 * p + 2]);
@@ -144,38 +142,47 @@ __global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict
     }
 }
 
-// segmented count of set flags over runs of equal keys inside the wave: one
-// atomic per run
-__device__ inline void wave_segment_count(int64_t key, bool in, bool flag, uint32_t *target_base) {
+// Certificates of one query over a wavefront of edges: per run of equal
+// (static edge, direction) keys, the number of certifying edges.  The tail lane
+// of each run with certificates appends one record (query, a, b) -> count.
+__device__ inline void wave_run_records(int64_t key, bool in, bool cert, uint64_t rec_key,
+                                        uint64_t *__restrict__ rk, uint32_t *__restrict__ rv,
+                                        int32_t *__restrict__ nrec, int64_t cap) {
     const int lane = lane_id();
-    int64_t prev = __shfl_up(key, 1);
-    int64_t next = __shfl_down(key, 1);
-    bool head = lane == 0 || prev != key;
-    bool tail = lane == 63 || next != key;
-    unsigned long long heads = __ballot(head && in);
-    unsigned long long flags = __ballot(flag);
+    const int64_t prev = __shfl_up(key, 1);
+    const int64_t next = __shfl_down(key, 1);
+    const bool head = lane == 0 || prev != key;
+    const bool tail = lane == 63 || next != key;
+    const unsigned long long heads = __ballot(head && in);
+    const unsigned long long flags = __ballot(cert);
+    int c = 0;
     if (in && tail) {
-        unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-        unsigned long long h = heads & upto;
-        int start = 63 - __clzll((long long)h);
-        unsigned long long seg = upto & ~((1ull << start) - 1ull);
-        int c = __popcll(flags & seg);
-        if (c) atomicAdd(&target_base[key], (uint32_t)c);
+        const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int start = 63 - __clzll((long long)(heads & upto));
+        c = __popcll(flags & upto & ~((1ull << start) - 1ull));
+    }
+    const int32_t slot = wave_append(nrec, c > 0);
+    if (slot >= 0 && slot < cap) {
+        rk[slot] = rec_key;
+        rv[slot] = (uint32_t)c;
     }
 }
 
 // Threshold step of every query, one pass per job: each temporal edge is read
-// once, its histogram over the job's window levels is summed level by level
-// in a register (count[e] at each delta of the job), and at each level the
-// job's queries of that delta test count * den >= num * |U|.  Certificates are
-// counted per (query, directed pair) with one atomic per run of a wavefront,
-// and per query.  Every wavefront lies inside one job (job slices are padded to
-// 64 edges), so the per-query loop and its ballots are uniform.
+// once, its histogram over the job's window levels (edge-major, four levels per
+// load) is summed level by level in a register (count[e] at each delta of the
+// job), and at each level the job's queries of that delta test
+// count * den >= num * |U|.  Certificates are counted per query and emitted as
+// (query, a, b) records, one per run of a wavefront.  Every wavefront lies
+// inside one job (job slices are padded to 64 edges), so the per-query loop and
+// its ballots are uniform.
 __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict__ jobs, int32_t nj,
                                                        const int64_t *__restrict__ job_w_base, int64_t total_w,
                                                        const QueryDev *__restrict__ qs,
-                                                       const int32_t *__restrict__ jq,
-                                                       uint32_t *__restrict__ ncert, uint32_t *__restrict__ qcert) {
+                                                       const int32_t *__restrict__ jq, int nbits,
+                                                       uint64_t *__restrict__ rk, uint32_t *__restrict__ rv,
+                                                       int32_t *__restrict__ nrec, int64_t cap,
+                                                       uint32_t *__restrict__ qcert) {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_w; x0 += stride) {
@@ -184,6 +191,7 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
         const int64_t e = x0 - job_w_base[j] + lane;
         const bool in = e < J.m;
         int32_t s = 0, dir = 0, du = 0, da = 0, tc = 0;
+        uint64_t ab = 0;
         if (in) {
             s = J.sid[e];
             dir = e >= J.smid[s] ? 1 : 0;
@@ -192,68 +200,53 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
             du = J.deg[b];
             da = J.deg[a];
             if (J.tcnt) tc = J.tcnt[s];
+            ab = ((uint64_t)(uint32_t)a << nbits) | (uint64_t)(uint32_t)b;
         }
+        const int64_t run = in ? 2 * (int64_t)s + dir : -1;
+        uint4 *hrow = reinterpret_cast<uint4 *>(J.hist + (in ? e : 0) * (int64_t)J.nls);
         uint32_t acc = 0;
         int32_t qi = J.q0;
-        for (int32_t l = 0; l < J.nl; l++) {
-            if (in) {
-                uint32_t *h = J.hist + (int64_t)l * J.m + e;
-                acc += *h;
-                if (J.keep_prefix) *h = acc;
-            }
-            for (; qi < J.q1; qi++) {
-                const int32_t q = jq[qi];
-                const QueryDev &Q = qs[q];
-                if (Q.level != l) break;
-                int64_t U;
-                if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)du - Q.excl;
-                else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)da - Q.excl;
-                else U = tc;
-                const bool cert = in && (uint64_t)acc * Q.den >= (uint64_t)Q.num * (uint64_t)U;
-                const unsigned long long mask = __ballot(cert);
-                if (mask) {
-                    wave_segment_count(in ? Q.p_base + 2 * (int64_t)s + dir : -1, in, cert, ncert);
-                    if (lane == 0) atomicAdd(&qcert[q], (uint32_t)__popcll(mask));
+        uint4 next = in ? hrow[0] : make_uint4(0, 0, 0, 0);
+        for (int32_t l0 = 0; l0 < J.nl; l0 += 4) {
+            const uint4 cur = next;
+            if (l0 + 4 < J.nl) next = in ? hrow[(l0 >> 2) + 1] : make_uint4(0, 0, 0, 0); // one chunk ahead
+            uint32_t hv[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+            for (int jj = 0; jj < 4; jj++) {
+                const int32_t l = l0 + jj;
+                if (l >= J.nl) break;
+                acc += hv[jj];
+                hv[jj] = acc;
+                for (; qi < J.q1; qi++) {
+                    const int32_t q = jq[qi];
+                    const QueryDev &Q = qs[q];
+                    if (Q.level != l) break;
+                    int64_t U;
+                    if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)du - Q.excl;
+                    else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)da - Q.excl;
+                    else U = tc;
+                    const bool cert = in && (uint64_t)acc * Q.den >= (uint64_t)Q.num * (uint64_t)U;
+                    const unsigned long long mask = __ballot(cert);
+                    if (mask) {
+                        wave_run_records(run, in, cert, ((uint64_t)q << (2 * nbits)) | ab, rk, rv, nrec, cap);
+                        if (lane == 0) atomicAdd(&qcert[q], (uint32_t)__popcll(mask));
+                    }
                 }
             }
+            if (J.keep_prefix && in) hrow[l0 >> 2] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
         }
     }
 }
 
-// pairs with certificates, as (query, u, v) keys for one sort of all queries
-__global__ void k_multi_pairs(const QueryDev *__restrict__ qs, int32_t nq, int64_t total_p,
-                              const uint32_t *__restrict__ ncert, int nbits, uint64_t *__restrict__ keys,
-                              uint32_t *__restrict__ vals, int32_t *__restrict__ npairs) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_p; x0 += stride) {
-        const int64_t x = x0 + lane_id();
-        const bool in = x < total_p;
-        uint32_t c = in ? ncert[x] : 0;
-        int32_t slot = wave_append(npairs, c > 0);
-        if (slot >= 0) {
-            int32_t lo = 0, hi = nq - 1;
-            while (lo < hi) {
-                int32_t mid = (lo + hi + 1) >> 1;
-                if (qs[mid].p_base <= x) lo = mid;
-                else hi = mid - 1;
-            }
-            const QueryDev &Q = qs[lo];
-            const int64_t i = x - Q.p_base;
-            const int32_t s = (int32_t)(i >> 1);
-            const int dir = (int)(i & 1);
-            uint64_t a = (uint64_t)(dir ? Q.shi[s] : Q.slo[s]);
-            uint64_t b = (uint64_t)(dir ? Q.slo[s] : Q.shi[s]);
-            keys[slot] = ((uint64_t)lo << (2 * nbits)) | (a << nbits) | b;
-            vals[slot] = c;
-        }
-    }
-}
-
-__global__ void k_scatter_counts(const uint32_t *__restrict__ count, const int32_t *__restrict__ perm, int32_t m,
-                                 uint32_t *__restrict__ out) {
+// count[k * stride] is the count of sorted edge k; out is in input order
+__global__ void k_scatter_counts(const uint32_t *__restrict__ count, int32_t stride, const int32_t *__restrict__ perm,
+                                 int32_t m, uint32_t *__restrict__ out) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) out[perm[k]] = count[k];
+    if (k < m) out[perm[k]] = count[k * stride];
 }
+
+// histogram levels per edge, padded so that an edge's levels are 16-byte aligned
+int32_t padded_levels(size_t nl) { return (int32_t)((nl + 3) & ~(size_t)3); }
 
 double ev_ms2(hipEvent_t a, hipEvent_t b) {
     float ms = 0;
@@ -282,12 +275,12 @@ struct Plan {
     std::vector<Job> jobs;
     std::vector<int32_t> qjob, qlevel;
     std::vector<int64_t> job_item_base, job_w_base;
-    int64_t items = 0, total_w = 0, total_p = 0;
+    int64_t items = 0, total_w = 0, rec_cap = 0;
     int nbits = 0;
     // device memory
     DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_jq;
     std::vector<DevBuf> hist, lv, sv, sw, su;
-    DevBuf wu, wbase, ncert, qcert, npairs, keys, vals, keys2, vals2, cub;
+    DevBuf wu, wbase, qcert, nrec, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
     // launch shape and capture
     int ipt = 8, tblocks = 4096;
@@ -322,9 +315,8 @@ Plan::~Plan() {
         d_jq.release();
         wu.release();
         wbase.release();
-        ncert.release();
         qcert.release();
-        npairs.release();
+        nrec.release();
         keys.release();
         vals.release();
         keys2.release();
@@ -339,13 +331,11 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
     // clear what accumulates: histograms, survivor counts, certificates
     for (int j = 0; j < nj; j++) {
         const Index &ix = P.graphs[P.jobs[j].graph]->ix;
-        int64_t hn = (int64_t)P.jobs[j].levels.size() * ix.m;
+        int64_t hn = (int64_t)padded_levels(P.jobs[j].levels.size()) * ix.m;
         if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
     }
-    if (P.total_p > 0)
-        k_fill<uint32_t><<<grid_for(P.total_p, BLK, 1 << 16), BLK, 0, s>>>(P.ncert.as<uint32_t>(), 0u, P.total_p);
     k_fill<uint32_t><<<grid_for(nq + 1, BLK), BLK, 0, s>>>(P.qcert.as<uint32_t>(), 0u, nq + 1);
-    k_fill<int32_t><<<1, 1, 0, s>>>(P.npairs.as<int32_t>(), 0, 1);
+    k_fill<int32_t><<<1, 1, 0, s>>>(P.nrec.as<int32_t>(), 0, 1);
     k_fill<int64_t><<<1, 1, 0, s>>>(P.wu.as<int64_t>() + P.items, (int64_t)0, 1);
     FOLTY_LAUNCHED();
     if (P.items > 0) {
@@ -362,14 +352,8 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
     if (P.total_w > 0) {
         k_job_threshold<<<grid_for(P.total_w, BLK, 8192), BLK, 0, s>>>(
             P.d_jobs.as<JobDev>(), nj, P.d_job_w_base.as<int64_t>(), P.total_w, P.d_queries.as<QueryDev>(),
-            P.d_jq.as<int32_t>(), P.ncert.as<uint32_t>(), P.qcert.as<uint32_t>());
-        FOLTY_LAUNCHED();
-    }
-    if (P.total_p > 0) {
-        k_multi_pairs<<<grid_for(P.total_p, BLK, 8192), BLK, 0, s>>>(P.d_queries.as<QueryDev>(), nq, P.total_p,
-                                                                     P.ncert.as<uint32_t>(), P.nbits,
-                                                                     P.keys.as<uint64_t>(), P.vals.as<uint32_t>(),
-                                                                     P.npairs.as<int32_t>());
+            P.d_jq.as<int32_t>(), P.nbits, P.keys.as<uint64_t>(), P.vals.as<uint32_t>(), P.nrec.as<int32_t>(),
+            P.rec_cap, P.qcert.as<uint32_t>());
         FOLTY_LAUNCHED();
     }
 }
@@ -407,7 +391,7 @@ static void tune(Plan &P) {
         for (int bl : blocks) {
             for (int j = 0; j < nj; j++) {
                 const Index &ix = P.graphs[P.jobs[j].graph]->ix;
-                int64_t hn = (int64_t)P.jobs[j].levels.size() * ix.m;
+                int64_t hn = (int64_t)padded_levels(P.jobs[j].levels.size()) * ix.m;
                 if (hn > 0)
                     k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
             }
@@ -518,7 +502,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     for (int j = 0; j < nj; j++) {
         const Index &ix = P->graphs[P->jobs[j].graph]->ix;
         const auto &lvs = P->jobs[j].levels;
-        P->hist[j].ensure(4 * lvs.size() * (size_t)ix.m + 4);
+        P->hist[j].ensure(4 * (size_t)padded_levels(lvs.size()) * (size_t)ix.m + 16);
         P->lv[j].ensure(8 * lvs.size());
         FOLTY_HIP(hipMemcpyAsync(P->lv[j].p, lvs.data(), 8 * lvs.size(), hipMemcpyHostToDevice, s));
         P->sv[j].ensure(12 * (size_t)ix.T + 12);
@@ -539,6 +523,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         d.dq = range_slack(d.dmax, ix.tshift);
         d.lv = P->lv[j].as<int64_t>();
         d.nl = (int32_t)lvs.size();
+        d.nls = padded_levels(lvs.size());
         d.m = ix.m;
         d.hist = P->hist[j].as<uint32_t>();
         d.sv = P->sv[j].as<int32_t>();
@@ -561,24 +546,24 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     }
     // queries
     std::vector<QueryDev> qd(nq);
-    int64_t pb = 0;
+    int64_t cap = 0;
     int32_t nmax = 1;
     for (int q = 0; q < nq; q++) {
         const Graph *g = P->graphs[qgraph[q]];
         const Index &ix = g->ix;
         QueryDev &d = qd[q];
-        d.slo = ix.slo.as<int32_t>();
-        d.shi = ix.shi.as<int32_t>();
         d.level = P->qlevel[q];
         d.num = qs[q].theta_num;
         d.den = qs[q].theta_den;
         d.universe = qs[q].universe;
         d.excl = qs[q].exclude_other ? 1 : 0;
-        d.p_base = pb;
-        pb += 2 * (int64_t)ix.S;
+        // records of this query: at most one per run of equal (static edge,
+        // direction) keys within a wavefront, i.e. one per directed pair plus one
+        // per wavefront boundary
+        cap += 2 * (int64_t)ix.S + ix.m / 64 + 2;
         nmax = std::max(nmax, ix.n);
     }
-    P->total_p = pb;
+    P->rec_cap = cap;
     P->nbits = bit_length((uint64_t)nmax);
     if (bit_length((uint64_t)std::max(1, nq)) + 2 * P->nbits > 64)
         fail(FOLTY_EOVERFLOW, "too many queries for one plan at this graph size");
@@ -594,11 +579,10 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         FOLTY_HIP(hipMemcpyAsync(P->d_queries.p, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
         FOLTY_HIP(hipMemcpyAsync(P->d_jq.p, jq.data(), 4 * (size_t)nq, hipMemcpyHostToDevice, s));
     }
-    P->ncert.ensure(4 * (size_t)P->total_p + 4);
     P->qcert.ensure(4 * ((size_t)nq + 1));
-    P->npairs.ensure(4);
-    P->keys.ensure(8 * (size_t)P->total_p + 8);
-    P->vals.ensure(4 * (size_t)P->total_p + 4);
+    P->nrec.ensure(4);
+    P->keys.ensure(8 * (size_t)P->rec_cap + 8);
+    P->vals.ensure(4 * (size_t)P->rec_cap + 4);
     P->scan_bytes = exclusive_scan_i64(nullptr, 0, P->wu.as<int64_t>(), P->wbase.as<int64_t>(), P->items + 1, s);
     P->cub.ensure(P->scan_bytes);
     FOLTY_HIP(hipStreamSynchronize(s));
@@ -648,12 +632,15 @@ void plan_run(Plan *P, Result **outs) {
     if (P->exec) FOLTY_HIP(hipGraphLaunch(P->exec, s));
     else enqueue_compute(*P, s);
     FOLTY_HIP(hipEventRecord(P->ev[3], s));
-    // read back how many pairs and certificates, then sort (query, u, v)
+    // read back how many records and certificates, then sort the (query, u, v)
+    // records; records of one pair from several wavefronts are merged below
     std::vector<uint32_t> qcert(nq + 1, 0);
     int32_t npairs = 0;
-    FOLTY_HIP(hipMemcpyAsync(&npairs, P->npairs.p, 4, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(&npairs, P->nrec.p, 4, hipMemcpyDeviceToHost, s));
     if (nq) FOLTY_HIP(hipMemcpyAsync(qcert.data(), P->qcert.p, 4 * (size_t)nq, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
+    if (npairs < 0 || npairs > P->rec_cap)
+        fail(FOLTY_EDEVICE, "certificate records exceed their bound (%d > %lld)", npairs, (long long)P->rec_cap);
     std::vector<uint64_t> keys(npairs);
     std::vector<uint32_t> vals(npairs);
     if (npairs > 0) {
@@ -675,12 +662,16 @@ void plan_run(Plan *P, Result **outs) {
     std::vector<std::unique_ptr<Result>> res(nq);
     for (int q = 0; q < nq; q++) res[q].reset(new Result());
     const uint64_t nmask = (1ull << P->nbits) - 1ull;
-    for (int32_t i = 0; i < npairs; i++) {
+    for (int32_t i = 0; i < npairs;) {
+        uint32_t c = 0;
+        int32_t e = i;
+        while (e < npairs && keys[e] == keys[i]) c += vals[e++];
         int q = (int)(keys[i] >> (2 * P->nbits));
         Result *r = res[q].get();
         r->u.push_back((int32_t)((keys[i] >> P->nbits) & nmask));
         r->v.push_back((int32_t)(keys[i] & nmask));
-        r->n_cert.push_back(vals[i]);
+        r->n_cert.push_back(c);
+        i = e;
     }
     for (int q = 0; q < nq; q++) {
         Result *r = res[q].get();
@@ -693,13 +684,15 @@ void plan_run(Plan *P, Result **outs) {
         r->stats.temporal_ms = r->stats.query_ms;
         if (!(P->queries[q].flags & FOLTY_QUERY_NO_COUNTS)) {
             const Index &ix = g->ix;
-            const uint32_t *count = P->hist[P->qjob[q]].as<uint32_t>() + (int64_t)P->qlevel[q] * ix.m;
+            // the job's histogram holds running sums: level l of edge k at k * nls + l
+            const int32_t nls = padded_levels(P->jobs[P->qjob[q]].levels.size());
+            const uint32_t *count = P->hist[P->qjob[q]].as<uint32_t>() + P->qlevel[q];
             r->counts_dev.ensure(4 * (size_t)ix.m_input + 4);
             if (ix.m_input > 0)
                 k_fill<uint32_t><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(r->counts_dev.as<uint32_t>(),
                                                                                     0xffffffffu, ix.m_input);
             if (ix.m > 0)
-                k_scatter_counts<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
+                k_scatter_counts<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, nls, ix.perm.as<int32_t>(), ix.m,
                                                                                r->counts_dev.as<uint32_t>());
             FOLTY_LAUNCHED();
             r->has_counts = true;

@@ -179,11 +179,11 @@ struct DirectOp {
 };
 
 // the smallest window per (e, w) into a histogram over sorted window levels:
-// level j counts w whose smallest window lies in (lv[j-1], lv[j]]
+// level j counts w whose smallest window lies in (lv[j-1], lv[j]].  Edge-major:
+// edge e's levels are hist[e * nls .. e * nls + nl) (nls = nl rounded up to 4).
 struct PoolOp {
     const int64_t *lv;
-    int nl;
-    int64_t m;
+    int nl, nls;
     uint32_t *hist;
     __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
                                       const Span &l3) const {
@@ -207,7 +207,7 @@ struct PoolOp {
                 if (lv[mid] < win) a = mid + 1;
                 else b = mid;
             }
-            atomicAdd(&hist[(int64_t)a * m + e], 1u);
+            atomicAdd(&hist[(int64_t)e * nls + a], 1u);
         }
     }
 };
