@@ -9,7 +9,8 @@
 // delta of the job.  theta and the universe only enter the threshold step.
 //
 // One plan runs, whatever the number of queries and graphs:
-//   filter   one grid over the enumeration items of all jobs (wave per item)
+//   filter   one grid over the enumeration items of all graphs (wave per
+//            item); up to two jobs of a graph share each enumeration
 //   scan     one exclusive scan over all items' test counts
 //   temporal one persistent grid over all surviving tests of all jobs
 //   threshold one grid over the edges of all jobs: running sum over the levels
@@ -70,29 +71,53 @@ __device__ inline int32_t owner_of(const int64_t *__restrict__ base, int32_t n, 
     return lo;
 }
 
-__global__ __launch_bounds__(BLK) void k_multi_filter(const JobDev *__restrict__ jobs, int32_t nj,
-                                                      const int64_t *__restrict__ job_item_base, int64_t items) {
+// up to two jobs (predicate codes) of one graph share one enumeration
+struct GroupDev {
+    const EnumItem *item;
+    const int4 *seg;
+    const int32_t *oadj, *tri;
+    const int64_t *tri_base;
+    const EdgeRec *rec;
+    const uint2 *rng;
+    int32_t nj;
+    int32_t job[2];
+};
+
+// NJ jobs per group: the groups of two come first in the plan's group list,
+// so each instantiation covers one contiguous range of group items
+template <int NJ>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) void k_multi_filter(const GroupDev *__restrict__ groups, int32_t ngr,
+                                                      const int64_t *__restrict__ group_item_base, int64_t g0,
+                                                      int64_t g1, const JobDev *__restrict__ jobs) {
     __shared__ EnumLds lds[WPB];
     const int w = threadIdx.x >> 6;
-    for (int64_t g = (int64_t)blockIdx.x * WPB + w; g < items; g += (int64_t)gridDim.x * WPB) {
-        const int32_t j = owner_of(job_item_base, nj, g);
-        const JobDev &J = jobs[j];
-        const int64_t it = g - job_item_base[j];
-        FilterSink<-1, FILTER_BOTH> sink;
-        sink.base = J.tri_base;
-        sink.rec = J.rec;
-        sink.rng = J.rng;
-        sink.dq = J.dq;
-        sink.dmax = J.dmax;
-        sink.variant = J.variant;
-        sink.sv = J.sv;
-        sink.sw = J.sw;
-        sink.su = J.su;
-        sink.wu = J.wu;
-        if (J.tri) cached_item(J.tri_base, J.tri, it, sink);
+    for (int64_t g = g0 + (int64_t)blockIdx.x * WPB + w; g < g1; g += (int64_t)gridDim.x * WPB) {
+        const int32_t gi = owner_of(group_item_base, ngr, g);
+        const GroupDev &G = groups[gi];
+        const int64_t it = g - group_item_base[gi];
+        using Sink = std::conditional_t<NJ == 2, PairFilterSink, FilterSink<-1, FILTER_BOTH> >;
+        Sink sink;
+        sink.base = G.tri_base;
+        sink.rec = G.rec;
+        sink.rng = G.rng;
+        if constexpr (NJ == 2) {
+            for (int jj = 0; jj < 2; jj++) {
+                const JobDev &J = jobs[G.job[jj]];
+                sink.f[jj] = JobFilter{J.dq, J.variant, J.sv, J.sw, J.su, J.wu};
+            }
+        } else {
+            const JobDev &J = jobs[G.job[0]];
+            sink.dq = J.dq;
+            sink.variant = J.variant;
+            sink.sv = J.sv;
+            sink.sw = J.sw;
+            sink.su = J.su;
+            sink.wu = J.wu;
+        }
+        if (G.tri) cached_item(G.tri_base, G.tri, it, sink);
         else {
-            const EnumItem item = J.item[it];
-            enum_item(item, stage_ahead(item, J.oadj, J.seg), J.oadj, J.seg, it, sink, lds[w]);
+            const EnumItem item = G.item[it];
+            enum_item(item, stage_ahead(item, G.oadj, G.seg), G.oadj, G.seg, it, sink, lds[w]);
         }
     }
 }
@@ -134,7 +159,7 @@ __global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict
             for (int32_t s = lo; s < ns && k < k1; s++) {
                 const int64_t p = s0 + s;
                 TriLists L = load_lists(J.rec, J.sv[3 * p], J.sv[3 * p + 1], J.sv[3 * p + 2]);
-                chunk_runs_rt(J.variant, L, J.dmax, J.ts, r, k, k1, op);
+                chunk_runs_rt(J.variant, L, run_slack(J.dq), J.ts, r, k, k1, op);
                 r = 0;
             }
             if (k == k_start) break; // every survivor has tests, so this never triggers
@@ -274,11 +299,13 @@ struct Plan {
     };
     std::vector<Job> jobs;
     std::vector<int32_t> qjob, qlevel;
-    std::vector<int64_t> job_item_base, job_w_base;
+    std::vector<int64_t> job_item_base, job_w_base, group_item_base;
+    int32_t ngroups = 0, npairs = 0; // groups; the first npairs hold two jobs
+    int64_t gitems = 0;
     int64_t items = 0, total_w = 0, rec_cap = 0;
     int nbits = 0;
     // device memory
-    DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_jq;
+    DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_jq, d_groups, d_group_item_base;
     std::vector<DevBuf> hist, lv, sv, sw, su;
     DevBuf wu, wbase, qcert, nrec, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
@@ -310,6 +337,8 @@ Plan::~Plan() {
         su.clear();
         d_jobs.release();
         d_job_item_base.release();
+        d_groups.release();
+        d_group_item_base.release();
         d_job_w_base.release();
         d_queries.release();
         d_jq.release();
@@ -338,9 +367,18 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
     k_fill<int32_t><<<1, 1, 0, s>>>(P.nrec.as<int32_t>(), 0, 1);
     k_fill<int64_t><<<1, 1, 0, s>>>(P.wu.as<int64_t>() + P.items, (int64_t)0, 1);
     FOLTY_LAUNCHED();
-    if (P.items > 0) {
-        unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((P.items + WPB - 1) / WPB, ENUM_BLOCKS));
-        k_multi_filter<<<g, BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj, P.d_job_item_base.as<int64_t>(), P.items);
+    // groups of two jobs, then groups of one
+    const int64_t gsplit = P.group_item_base[P.npairs];
+    if (gsplit > 0) {
+        unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((gsplit + WPB - 1) / WPB, ENUM_BLOCKS));
+        k_multi_filter<2><<<g, BLK, 0, s>>>(P.d_groups.as<GroupDev>(), P.ngroups, P.d_group_item_base.as<int64_t>(),
+                                            0, gsplit, P.d_jobs.as<JobDev>());
+        FOLTY_LAUNCHED();
+    }
+    if (P.gitems > gsplit) {
+        unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((P.gitems - gsplit + WPB - 1) / WPB, ENUM_BLOCKS));
+        k_multi_filter<1><<<g, BLK, 0, s>>>(P.d_groups.as<GroupDev>(), P.ngroups, P.d_group_item_base.as<int64_t>(),
+                                            gsplit, P.gitems, P.d_jobs.as<JobDev>());
         FOLTY_LAUNCHED();
     }
     exclusive_scan_i64(P.cub.p, P.scan_bytes, P.wu.as<int64_t>(), P.wbase.as<int64_t>(), P.items + 1, s);
@@ -544,6 +582,40 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
             if (!(qs[jq[i]].flags & FOLTY_QUERY_NO_COUNTS)) d.keep_prefix = 1;
         }
     }
+    // groups: the jobs of each graph, two at a time, share one enumeration
+    std::vector<GroupDev> gd, singles;
+    for (int gi = 0; gi < ng; gi++) {
+        std::vector<int> js;
+        for (int j = 0; j < nj; j++)
+            if (P->jobs[j].graph == gi) js.push_back(j);
+        for (size_t k = 0; k < js.size(); k += 2) {
+            const Index &ix = P->graphs[gi]->ix;
+            GroupDev G{};
+            G.item = ix.item.as<EnumItem>();
+            G.seg = ix.seg.as<int4>();
+            G.oadj = ix.oadj.as<int32_t>();
+            G.tri = ix.tri_cached ? ix.tri.as<int32_t>() : nullptr;
+            G.tri_base = ix.tri_base.as<int64_t>();
+            G.rec = ix.rec.as<EdgeRec>();
+            G.rng = ix.erng.as<uint2>();
+            G.nj = k + 1 < js.size() ? 2 : 1;
+            G.job[0] = js[k];
+            G.job[1] = G.nj == 2 ? js[k + 1] : js[k];
+            (G.nj == 2 ? gd : singles).push_back(G);
+        }
+    }
+    P->npairs = (int32_t)gd.size();
+    gd.insert(gd.end(), singles.begin(), singles.end());
+    P->ngroups = (int32_t)gd.size();
+    P->group_item_base.assign(gd.size() + 1, 0);
+    for (size_t k = 0; k < gd.size(); k++)
+        P->group_item_base[k + 1] = P->group_item_base[k] + P->graphs[P->jobs[gd[k].job[0]].graph]->ix.NI;
+    P->gitems = P->group_item_base[gd.size()];
+    P->d_groups.ensure(sizeof(GroupDev) * std::max<size_t>(1, gd.size()));
+    P->d_group_item_base.ensure(8 * (gd.size() + 1));
+    if (!gd.empty()) FOLTY_HIP(hipMemcpyAsync(P->d_groups.p, gd.data(), sizeof(GroupDev) * gd.size(), hipMemcpyHostToDevice, s));
+    FOLTY_HIP(hipMemcpyAsync(P->d_group_item_base.p, P->group_item_base.data(), 8 * (gd.size() + 1),
+                             hipMemcpyHostToDevice, s));
     // queries
     std::vector<QueryDev> qd(nq);
     int64_t cap = 0;

@@ -133,15 +133,13 @@ struct alignas(32) EnumItem {
     int32_t pad[3];
 };
 
-struct alignas(64) EdgeRec {
-    int32_t fs, fn;       // E_{tail,head}: start in ts, length
-    int32_t bs, bn;       // E_{head,tail}
-    int64_t ftmin, ftmax; // first and last timestamp of E_{tail,head} (0 if empty)
-    int64_t btmin, btmax;
-    int32_t sid;          // static edge
-    int32_t pad[3];
+struct alignas(32) EdgeRec {
+    int32_t fn, bn;   // lengths of E_{tail,head} and E_{head,tail}
+    int32_t fs, bs;   // their starts in ts
+    uint32_t flo, fhi; // first and last timestamp of E_{tail,head} >> tshift (0 if empty)
+    uint32_t blo, bhi; // the same for E_{head,tail}
 };
-static_assert(sizeof(EdgeRec) == 64, "one cache line per oriented edge");
+static_assert(sizeof(EdgeRec) == 32, "two records per cache line");
 
 struct Index {
     int32_t n = 0;

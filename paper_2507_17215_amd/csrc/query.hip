@@ -47,24 +47,22 @@ __global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const int32_t *__
         fs = mid; fn = b - mid; bs = a; bn = mid - a;
     }
     EdgeRec r;
-    r.fs = fs;
     r.fn = fn;
-    r.bs = bs;
     r.bn = bn;
-    r.ftmin = fn ? ts[fs] : 0;
-    r.ftmax = fn ? ts[fs + fn - 1] : 0;
-    r.btmin = bn ? ts[bs] : 0;
-    r.btmax = bn ? ts[bs + bn - 1] : 0;
-    r.sid = e;
-    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    r.fs = fs;
+    r.bs = bs;
+    r.flo = fn ? (uint32_t)(ts[fs] >> tshift) : 0;
+    r.fhi = fn ? (uint32_t)(ts[fs + fn - 1] >> tshift) : 0;
+    r.blo = bn ? (uint32_t)(ts[bs] >> tshift) : 0;
+    r.bhi = bn ? (uint32_t)(ts[bs + bn - 1] >> tshift) : 0;
     rec[p] = r;
     // a static edge has at least one temporal edge, so one of the lists is non-empty
-    int64_t lo = fn ? r.ftmin : r.btmin, hi = fn ? r.ftmax : r.btmax;
+    uint32_t lo = fn ? r.flo : r.blo, hi = fn ? r.fhi : r.bhi;
     if (fn && bn) {
-        lo = r.btmin < lo ? r.btmin : lo;
-        hi = r.btmax > hi ? r.btmax : hi;
+        lo = r.blo < lo ? r.blo : lo;
+        hi = r.bhi > hi ? r.bhi : hi;
     }
-    erng[p] = make_uint2((uint32_t)(lo >> tshift), (uint32_t)(hi >> tshift));
+    erng[p] = make_uint2(lo, hi);
 }
 
 // Probe segments: the oriented edge (u, v) at position p goes to the endpoint
@@ -292,7 +290,6 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
         sink.rec = ix.rec.as<EdgeRec>();
         sink.rng = ix.erng.as<uint2>();
         sink.dq = range_slack(dmax, ix.tshift);
-        sink.dmax = dmax;
         sink.variant = variant;
         sink.sv = ws.sv.as<int32_t>();
         sink.sw = ws.sw.as<int64_t>();
@@ -373,7 +370,8 @@ void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace
     dispatch_variant(variant, [&](auto V) {
         k_temporal<decltype(V)::value, Op><<<PERSIST_BLOCKS, BLK, 0, s>>>(
             ws.wbase.as<int64_t>(), ix.NI, ws.slots, ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
-            ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(), dmax, op, IPT);
+            ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(),
+            run_slack(range_slack(dmax, ix.tshift)), op, IPT);
     });
     FOLTY_LAUNCHED();
 }

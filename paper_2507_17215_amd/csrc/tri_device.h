@@ -56,8 +56,8 @@ template <class T> __global__ void k_fill(T *p, T v, int64_t n) {
 // directed lists of a triangle
 // ---------------------------------------------------------------------------
 struct Span {
-    int32_t s, n;    // start in ts, length
-    int64_t lo, hi;  // first and last timestamp
+    int32_t s, n;     // start in ts, length
+    uint32_t lo, hi;  // first and last timestamp >> tshift
 };
 
 // D[i][j] = E_{x_i, x_j} for the triangle's vertices x0 < x1 < x2 (by rank)
@@ -74,26 +74,43 @@ struct TriLists {
     }
 };
 
+// STARTS: also the lists' starts in ts (the filter needs only lengths and ranges)
+template <bool STARTS>
 __device__ inline void rec_spans(const EdgeRec *__restrict__ rec, int32_t p, Span &fwd, Span &bwd) {
-    const int4 *q = reinterpret_cast<const int4 *>(rec + p);
-    int4 a = q[0], b = q[1], c = q[2];
-    fwd.s = a.x;
-    fwd.n = a.y;
-    bwd.s = a.z;
-    bwd.n = a.w;
-    fwd.lo = (int64_t)(((uint64_t)(uint32_t)b.y << 32) | (uint32_t)b.x);
-    fwd.hi = (int64_t)(((uint64_t)(uint32_t)b.w << 32) | (uint32_t)b.z);
-    bwd.lo = (int64_t)(((uint64_t)(uint32_t)c.y << 32) | (uint32_t)c.x);
-    bwd.hi = (int64_t)(((uint64_t)(uint32_t)c.w << 32) | (uint32_t)c.z);
+    const uint4 *q = reinterpret_cast<const uint4 *>(rec + p);
+    if constexpr (STARTS) {
+        const uint4 a = q[0];
+        fwd.n = (int32_t)a.x;
+        bwd.n = (int32_t)a.y;
+        fwd.s = (int32_t)a.z;
+        bwd.s = (int32_t)a.w;
+    } else {
+        const uint2 a = *reinterpret_cast<const uint2 *>(q);
+        fwd.n = (int32_t)a.x;
+        bwd.n = (int32_t)a.y;
+        fwd.s = bwd.s = 0;
+    }
+    const uint4 b = q[1];
+    fwd.lo = b.x;
+    fwd.hi = b.y;
+    bwd.lo = b.z;
+    bwd.hi = b.w;
 }
 
 // the three oriented edges (x0,x1), (x0,x2), (x1,x2) of a triangle
+template <bool STARTS = true>
 __device__ inline TriLists load_lists(const EdgeRec *__restrict__ rec, int32_t p01, int32_t p02, int32_t p12) {
     TriLists L;
-    rec_spans(rec, p01, L.d01, L.d10);
-    rec_spans(rec, p02, L.d02, L.d20);
-    rec_spans(rec, p12, L.d12, L.d21);
+    rec_spans<STARTS>(rec, p01, L.d01, L.d10);
+    rec_spans<STARTS>(rec, p02, L.d02, L.d20);
+    rec_spans<STARTS>(rec, p12, L.d12, L.d21);
     return L;
+}
+
+// Slack of the run test below in timestamps >> tshift: the range slack of the
+// window bound, saturated to 32 bits (no difference of two such values exceeds it).
+__host__ __device__ inline uint32_t run_slack(int64_t dq) {
+    return dq >= (int64_t)0xffffffffu ? 0xffffffffu : (uint32_t)dq;
 }
 
 // The predicate code picks, for L1 = E_{a,b} (a = x_I, b = x_J, third w = x_C),
@@ -107,40 +124,45 @@ template <int VAR, int I, int J> struct Pick {
 };
 
 // A run can only count if all three lists are non-empty and some t <= t2 <= t3
-// <= t + dmax is possible given each list's first and last timestamp.
+// <= t + dmax is possible given each list's first and last timestamp.  The test
+// reads the timestamps shifted right by tshift with slack dq = run_slack(
+// range_slack(dmax, tshift)): a run it drops has no such t, t2, t3 (floors keep
+// order, and floors of two values differ by at most one more unit than the
+// values do); with tshift = 0 it is exact.  A run it keeps without such a
+// window only adds tests that find nothing.
 template <int VAR, int I, int J>
-__device__ inline bool run_lists(const TriLists &T, int64_t dmax, Span &l1, Span &l2, Span &l3) {
+__device__ inline bool run_lists(const TriLists &T, uint32_t dq, Span &l1, Span &l2, Span &l3) {
     using P = Pick<VAR, I, J>;
     l1 = T.template get<I, J>();
     l2 = T.template get<P::L2a, P::L2b>();
     l3 = T.template get<P::L3a, P::L3b>();
     if (l1.n == 0 || l2.n == 0 || l3.n == 0) return false;
     if (l2.hi < l1.lo || l3.hi < l2.lo) return false;
-    if (l2.lo - l1.hi > dmax || l3.lo - l1.hi > dmax) return false;
+    if ((l2.lo > l1.hi && l2.lo - l1.hi > dq) || (l3.lo > l1.hi && l3.lo - l1.hi > dq)) return false;
     return true;
 }
 
-template <int VAR, int I, int J> __device__ inline int64_t run_work(const TriLists &T, int64_t dmax) {
+template <int VAR, int I, int J> __device__ inline int64_t run_work(const TriLists &T, uint32_t dq) {
     Span a, b, c;
-    return run_lists<VAR, I, J>(T, dmax, a, b, c) ? a.n : 0;
+    return run_lists<VAR, I, J>(T, dq, a, b, c) ? a.n : 0;
 }
 
-template <int VAR> __device__ inline int64_t tri_work(const TriLists &T, int64_t dmax) {
-    return run_work<VAR, 0, 1>(T, dmax) + run_work<VAR, 1, 0>(T, dmax) + run_work<VAR, 0, 2>(T, dmax) +
-           run_work<VAR, 2, 0>(T, dmax) + run_work<VAR, 1, 2>(T, dmax) + run_work<VAR, 2, 1>(T, dmax);
+template <int VAR> __device__ inline int64_t tri_work(const TriLists &T, uint32_t dq) {
+    return run_work<VAR, 0, 1>(T, dq) + run_work<VAR, 1, 0>(T, dq) + run_work<VAR, 0, 2>(T, dq) +
+           run_work<VAR, 2, 0>(T, dq) + run_work<VAR, 1, 2>(T, dq) + run_work<VAR, 2, 1>(T, dq);
 }
 
 // runtime predicate code (one code per job in a batch)
-__device__ inline int64_t tri_work_rt(int variant, const TriLists &T, int64_t dmax) {
+__device__ inline int64_t tri_work_rt(int variant, const TriLists &T, uint32_t dq) {
     switch (variant) {
-    case 0: return tri_work<0>(T, dmax);
-    case 1: return tri_work<1>(T, dmax);
-    case 2: return tri_work<2>(T, dmax);
-    case 3: return tri_work<3>(T, dmax);
-    case 4: return tri_work<4>(T, dmax);
-    case 5: return tri_work<5>(T, dmax);
-    case 6: return tri_work<6>(T, dmax);
-    default: return tri_work<7>(T, dmax);
+    case 0: return tri_work<0>(T, dq);
+    case 1: return tri_work<1>(T, dq);
+    case 2: return tri_work<2>(T, dq);
+    case 3: return tri_work<3>(T, dq);
+    case 4: return tri_work<4>(T, dq);
+    case 5: return tri_work<5>(T, dq);
+    case 6: return tri_work<6>(T, dq);
+    default: return tri_work<7>(T, dq);
     }
 }
 
@@ -215,10 +237,10 @@ struct PoolOp {
 // one run of a surviving triangle within the chunk [k, k1); r = tests of this
 // triangle still to skip.  Returns false once the chunk is used up.
 template <int VAR, int I, int J, class Op>
-__device__ inline bool chunk_run(const TriLists &T, int64_t dmax, const int64_t *ts, int64_t &r, int64_t &k,
+__device__ inline bool chunk_run(const TriLists &T, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k,
                                  int64_t k1, const Op &op) {
     Span l1, l2, l3;
-    if (!run_lists<VAR, I, J>(T, dmax, l1, l2, l3)) return true;
+    if (!run_lists<VAR, I, J>(T, dq, l1, l2, l3)) return true;
     if (r >= l1.n) {
         r -= l1.n;
         return true;
@@ -315,7 +337,6 @@ template <int VAR, int MODE> struct FilterSink {
     const EdgeRec *rec;
     const uint2 *rng; // per oriented edge: (first, last) timestamp >> shift
     int64_t dq;       // range_slack(dmax, shift)
-    int64_t dmax;
     int variant;
     int32_t *sv;      // EMIT, BOTH: survivors (three oriented edges each)
     int64_t *sw;      // EMIT, BOTH: test offset of each survivor inside its item
@@ -347,8 +368,8 @@ template <int VAR, int MODE> struct FilterSink {
             const uint2 rb = pkb ? prk : rng[b];
             const uint2 rc = pkb ? rng[c] : prk;
             if (ranges_meet(pra, rb, dq) && ranges_meet(pra, rc, dq) && ranges_meet(rb, rc, dq)) {
-                if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists(rec, a, b, c), dmax);
-                else wk = tri_work_rt(variant, load_lists(rec, a, b, c), dmax);
+                if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists<false>(rec, a, b, c), run_slack(dq));
+                else wk = tri_work_rt(variant, load_lists<false>(rec, a, b, c), run_slack(dq));
             }
         }
         bool keep = wk > 0;
@@ -380,6 +401,78 @@ template <int VAR, int MODE> struct FilterSink {
             if (lane_id() == 0 && nhit) atomicAdd(hits, nhit);
         }
     }
+};
+
+// What the filter needs of one predicate code and window bound.
+struct JobFilter {
+    int64_t dq;
+    int variant;
+    int32_t *sv;
+    int64_t *sw;
+    int32_t *su;
+    int64_t *wu;
+};
+
+// FILTER_BOTH for two predicate codes over the same triangles (a plan's two
+// jobs on one graph): one enumeration and one read of the edges' ranges per
+// triangle; each code then reads the three edge records for itself (the second
+// read hits the cache), so only one code's lists are live at a time, and keeps
+// its survivors in its own slots.
+struct PairFilterSink {
+    const int64_t *base; // first slot of each item (the graph's triangle offsets)
+    const EdgeRec *rec;
+    const uint2 *rng;
+    JobFilter f[2];
+    int64_t slot;
+    int32_t ns[2];
+    int64_t work[2];
+    uint2 pra, prk;
+    bool pkb;
+    __device__ void prefetch(int32_t a, int32_t k, bool k_is_b) {
+        pra = rng[a];
+        prk = rng[k];
+        pkb = k_is_b;
+    }
+    __device__ void begin(int64_t it) {
+        slot = base[it];
+        ns[0] = ns[1] = 0;
+        work[0] = work[1] = 0;
+    }
+    template <int J> __device__ void keep(bool pass, int32_t a, int32_t b, int32_t c) {
+        const int64_t wk = pass ? tri_work_rt(f[J].variant, load_lists<false>(rec, a, b, c), run_slack(f[J].dq)) : 0;
+        const bool kp = wk > 0;
+        const unsigned long long mask = __ballot(kp);
+        if (!mask) return;
+        const int64_t incl = wave_inclusive_sum(wk);
+        if (kp) {
+            const int64_t pos = slot + ns[J] + __popcll(mask & lanes_below());
+            f[J].sv[3 * pos] = a;
+            f[J].sv[3 * pos + 1] = b;
+            f[J].sv[3 * pos + 2] = c;
+            f[J].sw[pos] = work[J] + incl - wk;
+        }
+        ns[J] += (int32_t)__popcll(mask);
+        work[J] += __shfl(incl, 63);
+    }
+    __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
+        bool p0 = false, p1 = false;
+        if (h) {
+            const uint2 rb = pkb ? prk : rng[b];
+            const uint2 rc = pkb ? rng[c] : prk;
+            p0 = ranges_meet(pra, rb, f[0].dq) && ranges_meet(pra, rc, f[0].dq) && ranges_meet(rb, rc, f[0].dq);
+            p1 = ranges_meet(pra, rb, f[1].dq) && ranges_meet(pra, rc, f[1].dq) && ranges_meet(rb, rc, f[1].dq);
+        }
+        keep<0>(p0, a, b, c);
+        keep<1>(p1, a, b, c);
+    }
+    __device__ void end(int64_t it) {
+        if (lane_id() == 0)
+            for (int j = 0; j < 2; j++) {
+                f[j].su[it] = ns[j];
+                f[j].wu[it] = work[j];
+            }
+    }
+    __device__ void finish() {}
 };
 
 // LDS of one wavefront's enumeration item: the owner's out-row N+(w), the
@@ -661,6 +754,30 @@ __global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict
     sink.finish();
 }
 
+template <int VAR, class Op>
+__device__ inline void chunk_runs(const TriLists &L, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k, int64_t k1,
+                                  const Op &op) {
+    if (chunk_run<VAR, 0, 1>(L, dq, ts, r, k, k1, op) && chunk_run<VAR, 1, 0>(L, dq, ts, r, k, k1, op) &&
+        chunk_run<VAR, 0, 2>(L, dq, ts, r, k, k1, op) && chunk_run<VAR, 2, 0>(L, dq, ts, r, k, k1, op) &&
+        chunk_run<VAR, 1, 2>(L, dq, ts, r, k, k1, op))
+        chunk_run<VAR, 2, 1>(L, dq, ts, r, k, k1, op);
+}
+
+template <class Op>
+__device__ inline void chunk_runs_rt(int variant, const TriLists &L, uint32_t dq, const int64_t *ts, int64_t &r,
+                                     int64_t &k, int64_t k1, const Op &op) {
+    switch (variant) {
+    case 0: chunk_runs<0>(L, dq, ts, r, k, k1, op); break;
+    case 1: chunk_runs<1>(L, dq, ts, r, k, k1, op); break;
+    case 2: chunk_runs<2>(L, dq, ts, r, k, k1, op); break;
+    case 3: chunk_runs<3>(L, dq, ts, r, k, k1, op); break;
+    case 4: chunk_runs<4>(L, dq, ts, r, k, k1, op); break;
+    case 5: chunk_runs<5>(L, dq, ts, r, k, k1, op); break;
+    case 6: chunk_runs<6>(L, dq, ts, r, k, k1, op); break;
+    default: chunk_runs<7>(L, dq, ts, r, k, k1, op); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a.6: temporal tests over the surviving runs, flat chunks of IPT tests
 // ---------------------------------------------------------------------------
@@ -669,7 +786,7 @@ __global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wb
                                                   const int64_t *__restrict__ base, const int32_t *__restrict__ su,
                                                   const int32_t *__restrict__ sv, const int64_t *__restrict__ sw,
                                                   const EdgeRec *__restrict__ rec, const int64_t *__restrict__ ts,
-                                                  int64_t dmax, Op op, int ipt) {
+                                                  uint32_t dq, Op op, int ipt) {
     const int64_t total = wbase[NI];
     const int64_t nchunks = (total + ipt - 1) / ipt;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -700,38 +817,11 @@ __global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wb
             for (int32_t s = lo; s < ns && k < k1; s++) {
                 const int64_t p = s0 + s;
                 TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
-                if (chunk_run<VAR, 0, 1>(L, dmax, ts, r, k, k1, op) && chunk_run<VAR, 1, 0>(L, dmax, ts, r, k, k1, op) &&
-                    chunk_run<VAR, 0, 2>(L, dmax, ts, r, k, k1, op) && chunk_run<VAR, 2, 0>(L, dmax, ts, r, k, k1, op) &&
-                    chunk_run<VAR, 1, 2>(L, dmax, ts, r, k, k1, op))
-                    chunk_run<VAR, 2, 1>(L, dmax, ts, r, k, k1, op);
+                chunk_runs<VAR>(L, dq, ts, r, k, k1, op);
                 r = 0;
             }
             if (k == k_start) break; // every survivor has tests, so this never triggers
         }
-    }
-}
-
-template <int VAR, class Op>
-__device__ inline void chunk_runs(const TriLists &L, int64_t dmax, const int64_t *ts, int64_t &r, int64_t &k, int64_t k1,
-                                  const Op &op) {
-    if (chunk_run<VAR, 0, 1>(L, dmax, ts, r, k, k1, op) && chunk_run<VAR, 1, 0>(L, dmax, ts, r, k, k1, op) &&
-        chunk_run<VAR, 0, 2>(L, dmax, ts, r, k, k1, op) && chunk_run<VAR, 2, 0>(L, dmax, ts, r, k, k1, op) &&
-        chunk_run<VAR, 1, 2>(L, dmax, ts, r, k, k1, op))
-        chunk_run<VAR, 2, 1>(L, dmax, ts, r, k, k1, op);
-}
-
-template <class Op>
-__device__ inline void chunk_runs_rt(int variant, const TriLists &L, int64_t dmax, const int64_t *ts, int64_t &r,
-                                     int64_t &k, int64_t k1, const Op &op) {
-    switch (variant) {
-    case 0: chunk_runs<0>(L, dmax, ts, r, k, k1, op); break;
-    case 1: chunk_runs<1>(L, dmax, ts, r, k, k1, op); break;
-    case 2: chunk_runs<2>(L, dmax, ts, r, k, k1, op); break;
-    case 3: chunk_runs<3>(L, dmax, ts, r, k, k1, op); break;
-    case 4: chunk_runs<4>(L, dmax, ts, r, k, k1, op); break;
-    case 5: chunk_runs<5>(L, dmax, ts, r, k, k1, op); break;
-    case 6: chunk_runs<6>(L, dmax, ts, r, k, k1, op); break;
-    default: chunk_runs<7>(L, dmax, ts, r, k, k1, op); break;
     }
 }
 
