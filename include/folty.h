@@ -219,7 +219,8 @@ typedef struct {
     int32_t tests_per_chunk; /* temporal launch shape chosen by timing candidates */
     int32_t temporal_blocks;
     int32_t captured;        /* 1 if runs replay a captured HIP graph */
-    int32_t reserved;
+    int32_t records;         /* certificate records of the last run (one per run of a directed
+                                pair within a wavefront, before merging) */
     double last_run_ms;      /* device time of the last run (launch sequence to sorted pairs) */
 } folty_plan_info;
 

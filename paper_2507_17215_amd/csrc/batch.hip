@@ -48,16 +48,19 @@ struct JobDev {
     int32_t *su;
     int64_t *wu; // this job's slice of the concatenated per-item test counts
     // threshold step: the graph's static edge table and degrees, and the job's
-    // queries (positions jq[q0, q1) of the plan's job-sorted query order, by level)
+    // queries: positions [q0, q1) of the plan's query list (job order, each job's by level)
     const int32_t *sid, *smid, *slo, *shi, *deg, *tcnt;
     int32_t q0, q1;
     int32_t keep_prefix; // some query of the job hands back its per-edge counts
 };
 
-struct QueryDev {
+// a plan's queries in job order, each job's by level (one scalar load each)
+struct alignas(32) QueryDev {
     int32_t level; // index of the query's delta among its job's levels
     uint32_t num, den;
     int32_t universe, excl;
+    int32_t q;     // the query's index in the plan
+    int32_t pad[2];
 };
 
 // the largest index i in [0, n) with base[i] <= x (base ascending, base[0] <= x)
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                       const int64_t *__restrict__ group_item_base, int64_t g0,
                                                       int64_t g1, const JobDev *__restrict__ jobs) {
     __shared__ EnumLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     for (int64_t g = g0 + (int64_t)blockIdx.x * WPB + w; g < g1; g += (int64_t)gridDim.x * WPB) {
         const int32_t gi = owner_of(group_item_base, ngr, g);
         const GroupDev &G = groups[gi];
@@ -203,14 +206,12 @@ __device__ inline void wave_run_records(int64_t key, bool in, bool cert, uint64_
 // its ballots are uniform.
 __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict__ jobs, int32_t nj,
                                                        const int64_t *__restrict__ job_w_base, int64_t total_w,
-                                                       const QueryDev *__restrict__ qs,
-                                                       const int32_t *__restrict__ jq, int nbits,
+                                                       const QueryDev *__restrict__ qs, int nbits,
                                                        uint64_t *__restrict__ rk, uint32_t *__restrict__ rv,
-                                                       int32_t *__restrict__ nrec, int64_t cap,
-                                                       uint32_t *__restrict__ qcert) {
+                                                       int32_t *__restrict__ nrec, int64_t cap) {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); x0 < total_w; x0 += stride) {
+    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + 64 * wave_id(); x0 < total_w; x0 += stride) {
         const int32_t j = owner_of(job_w_base, nj, x0);
         const JobDev &J = jobs[j];
         const int64_t e = x0 - job_w_base[j] + lane;
@@ -228,13 +229,14 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
             ab = ((uint64_t)(uint32_t)a << nbits) | (uint64_t)(uint32_t)b;
         }
         const int64_t run = in ? 2 * (int64_t)s + dir : -1;
-        uint4 *hrow = reinterpret_cast<uint4 *>(J.hist + (in ? e : 0) * (int64_t)J.nls);
+        // this wavefront's tile: block c holds levels 4c..4c+3 of its 64 edges
+        uint4 *hrow = reinterpret_cast<uint4 *>(J.hist + hist_at(x0 - job_w_base[j], 0, J.nls)) + lane;
         uint32_t acc = 0;
         int32_t qi = J.q0;
-        uint4 next = in ? hrow[0] : make_uint4(0, 0, 0, 0);
+        uint4 next = hrow[0];
         for (int32_t l0 = 0; l0 < J.nl; l0 += 4) {
             const uint4 cur = next;
-            if (l0 + 4 < J.nl) next = in ? hrow[(l0 >> 2) + 1] : make_uint4(0, 0, 0, 0); // one chunk ahead
+            if (l0 + 4 < J.nl) next = hrow[((l0 >> 2) + 1) * 64]; // one block ahead
             uint32_t hv[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
             for (int jj = 0; jj < 4; jj++) {
@@ -243,34 +245,32 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
                 acc += hv[jj];
                 hv[jj] = acc;
                 for (; qi < J.q1; qi++) {
-                    const int32_t q = jq[qi];
-                    const QueryDev &Q = qs[q];
+                    // qi is the same in every lane; saying so keeps these loads scalar
+                    const QueryDev &Q = qs[__builtin_amdgcn_readfirstlane(qi)];
+                    const int32_t q = Q.q;
                     if (Q.level != l) break;
                     int64_t U;
                     if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)du - Q.excl;
                     else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)da - Q.excl;
                     else U = tc;
                     const bool cert = in && (uint64_t)acc * Q.den >= (uint64_t)Q.num * (uint64_t)U;
-                    const unsigned long long mask = __ballot(cert);
-                    if (mask) {
-                        wave_run_records(run, in, cert, ((uint64_t)q << (2 * nbits)) | ab, rk, rv, nrec, cap);
-                        if (lane == 0) atomicAdd(&qcert[q], (uint32_t)__popcll(mask));
-                    }
+                    if (__ballot(cert)) wave_run_records(run, in, cert, ((uint64_t)q << (2 * nbits)) | ab, rk, rv, nrec, cap);
                 }
             }
-            if (J.keep_prefix && in) hrow[l0 >> 2] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+            if (J.keep_prefix && in) hrow[(l0 >> 2) * 64] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
         }
     }
 }
 
-// count[k * stride] is the count of sorted edge k; out is in input order
-__global__ void k_scatter_counts(const uint32_t *__restrict__ count, int32_t stride, const int32_t *__restrict__ perm,
-                                 int32_t m, uint32_t *__restrict__ out) {
+// level l of a histogram holding running sums is the count of sorted edge k at
+// that level's delta; out is in input order
+__global__ void k_scatter_counts(const uint32_t *__restrict__ hist, int32_t l, int32_t nls,
+                                 const int32_t *__restrict__ perm, int32_t m, uint32_t *__restrict__ out) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) out[perm[k]] = count[k * stride];
+    if (k < m) out[perm[k]] = hist[hist_at(k, l, nls)];
 }
 
-// histogram levels per edge, padded so that an edge's levels are 16-byte aligned
+// histogram levels per edge, padded to whole blocks of four
 int32_t padded_levels(size_t nl) { return (int32_t)((nl + 3) & ~(size_t)3); }
 
 double ev_ms2(hipEvent_t a, hipEvent_t b) {
@@ -305,9 +305,9 @@ struct Plan {
     int64_t items = 0, total_w = 0, rec_cap = 0;
     int nbits = 0;
     // device memory
-    DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_jq, d_groups, d_group_item_base;
+    DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_groups, d_group_item_base;
     std::vector<DevBuf> hist, lv, sv, sw, su;
-    DevBuf wu, wbase, qcert, nrec, keys, vals, keys2, vals2, cub;
+    DevBuf wu, wbase, nrec, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
     // launch shape and capture
     int ipt = 8, tblocks = 4096;
@@ -319,6 +319,7 @@ struct Plan {
     hipEvent_t ev[4] = {};
     double last_ms = 0, last_compute_ms = 0;
     int64_t last_tests = 0;
+    int32_t last_records = 0;
     ~Plan();
 };
 
@@ -341,10 +342,8 @@ Plan::~Plan() {
         d_group_item_base.release();
         d_job_w_base.release();
         d_queries.release();
-        d_jq.release();
         wu.release();
         wbase.release();
-        qcert.release();
         nrec.release();
         keys.release();
         vals.release();
@@ -360,10 +359,9 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
     // clear what accumulates: histograms, survivor counts, certificates
     for (int j = 0; j < nj; j++) {
         const Index &ix = P.graphs[P.jobs[j].graph]->ix;
-        int64_t hn = (int64_t)padded_levels(P.jobs[j].levels.size()) * ix.m;
+        const int64_t hn = hist_words(ix.m, padded_levels(P.jobs[j].levels.size()));
         if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
     }
-    k_fill<uint32_t><<<grid_for(nq + 1, BLK), BLK, 0, s>>>(P.qcert.as<uint32_t>(), 0u, nq + 1);
     k_fill<int32_t><<<1, 1, 0, s>>>(P.nrec.as<int32_t>(), 0, 1);
     k_fill<int64_t><<<1, 1, 0, s>>>(P.wu.as<int64_t>() + P.items, (int64_t)0, 1);
     FOLTY_LAUNCHED();
@@ -390,8 +388,8 @@ static void enqueue_compute(Plan &P, hipStream_t s) {
     if (P.total_w > 0) {
         k_job_threshold<<<grid_for(P.total_w, BLK, 8192), BLK, 0, s>>>(
             P.d_jobs.as<JobDev>(), nj, P.d_job_w_base.as<int64_t>(), P.total_w, P.d_queries.as<QueryDev>(),
-            P.d_jq.as<int32_t>(), P.nbits, P.keys.as<uint64_t>(), P.vals.as<uint32_t>(), P.nrec.as<int32_t>(),
-            P.rec_cap, P.qcert.as<uint32_t>());
+            P.nbits, P.keys.as<uint64_t>(), P.vals.as<uint32_t>(), P.nrec.as<int32_t>(),
+            P.rec_cap);
         FOLTY_LAUNCHED();
     }
 }
@@ -429,7 +427,7 @@ static void tune(Plan &P) {
         for (int bl : blocks) {
             for (int j = 0; j < nj; j++) {
                 const Index &ix = P.graphs[P.jobs[j].graph]->ix;
-                int64_t hn = (int64_t)padded_levels(P.jobs[j].levels.size()) * ix.m;
+                const int64_t hn = hist_words(ix.m, padded_levels(P.jobs[j].levels.size()));
                 if (hn > 0)
                     k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
             }
@@ -532,6 +530,8 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     std::stable_sort(jq.begin(), jq.end(), [&](int32_t x, int32_t y) {
         return P->qjob[x] != P->qjob[y] ? P->qjob[x] < P->qjob[y] : P->qlevel[x] < P->qlevel[y];
     });
+    std::vector<int32_t> qpos(nq);
+    for (int i = 0; i < nq; i++) qpos[jq[i]] = i;
     std::vector<int32_t> jq0(nj, 0), jq1(nj, 0);
     for (int i = nq - 1; i >= 0; i--) jq0[P->qjob[jq[i]]] = i;
     for (int i = 0; i < nq; i++) jq1[P->qjob[jq[i]]] = i + 1;
@@ -540,7 +540,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     for (int j = 0; j < nj; j++) {
         const Index &ix = P->graphs[P->jobs[j].graph]->ix;
         const auto &lvs = P->jobs[j].levels;
-        P->hist[j].ensure(4 * (size_t)padded_levels(lvs.size()) * (size_t)ix.m + 16);
+        P->hist[j].ensure(4 * (size_t)hist_words(ix.m, padded_levels(lvs.size())) + 16);
         P->lv[j].ensure(8 * lvs.size());
         FOLTY_HIP(hipMemcpyAsync(P->lv[j].p, lvs.data(), 8 * lvs.size(), hipMemcpyHostToDevice, s));
         P->sv[j].ensure(12 * (size_t)ix.T + 12);
@@ -616,14 +616,15 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     if (!gd.empty()) FOLTY_HIP(hipMemcpyAsync(P->d_groups.p, gd.data(), sizeof(GroupDev) * gd.size(), hipMemcpyHostToDevice, s));
     FOLTY_HIP(hipMemcpyAsync(P->d_group_item_base.p, P->group_item_base.data(), 8 * (gd.size() + 1),
                              hipMemcpyHostToDevice, s));
-    // queries
+    // queries, in job order
     std::vector<QueryDev> qd(nq);
     int64_t cap = 0;
     int32_t nmax = 1;
     for (int q = 0; q < nq; q++) {
         const Graph *g = P->graphs[qgraph[q]];
         const Index &ix = g->ix;
-        QueryDev &d = qd[q];
+        QueryDev d{};
+        d.q = q;
         d.level = P->qlevel[q];
         d.num = qs[q].theta_num;
         d.den = qs[q].theta_den;
@@ -634,6 +635,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         // per wavefront boundary
         cap += 2 * (int64_t)ix.S + ix.m / 64 + 2;
         nmax = std::max(nmax, ix.n);
+        qd[qpos[q]] = d;
     }
     P->rec_cap = cap;
     P->nbits = bit_length((uint64_t)nmax);
@@ -643,15 +645,12 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     P->d_job_item_base.ensure(8 * ((size_t)nj + 1));
     P->d_job_w_base.ensure(8 * ((size_t)nj + 1));
     P->d_queries.ensure(sizeof(QueryDev) * (size_t)std::max(1, nq));
-    P->d_jq.ensure(4 * ((size_t)nq + 1));
     if (nj) FOLTY_HIP(hipMemcpyAsync(P->d_jobs.p, jd.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice, s));
     FOLTY_HIP(hipMemcpyAsync(P->d_job_item_base.p, P->job_item_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
     FOLTY_HIP(hipMemcpyAsync(P->d_job_w_base.p, P->job_w_base.data(), 8 * (nj + 1), hipMemcpyHostToDevice, s));
     if (nq) {
         FOLTY_HIP(hipMemcpyAsync(P->d_queries.p, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
-        FOLTY_HIP(hipMemcpyAsync(P->d_jq.p, jq.data(), 4 * (size_t)nq, hipMemcpyHostToDevice, s));
     }
-    P->qcert.ensure(4 * ((size_t)nq + 1));
     P->nrec.ensure(4);
     P->keys.ensure(8 * (size_t)P->rec_cap + 8);
     P->vals.ensure(4 * (size_t)P->rec_cap + 4);
@@ -704,15 +703,15 @@ void plan_run(Plan *P, Result **outs) {
     if (P->exec) FOLTY_HIP(hipGraphLaunch(P->exec, s));
     else enqueue_compute(*P, s);
     FOLTY_HIP(hipEventRecord(P->ev[3], s));
-    // read back how many records and certificates, then sort the (query, u, v)
-    // records; records of one pair from several wavefronts are merged below
-    std::vector<uint32_t> qcert(nq + 1, 0);
+    // read back how many records, then sort the (query, u, v) records; records
+    // of one pair from several wavefronts are merged below, and a query's
+    // certificates are the sum of its records
     int32_t npairs = 0;
     FOLTY_HIP(hipMemcpyAsync(&npairs, P->nrec.p, 4, hipMemcpyDeviceToHost, s));
-    if (nq) FOLTY_HIP(hipMemcpyAsync(qcert.data(), P->qcert.p, 4 * (size_t)nq, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
     if (npairs < 0 || npairs > P->rec_cap)
         fail(FOLTY_EDEVICE, "certificate records exceed their bound (%d > %lld)", npairs, (long long)P->rec_cap);
+    P->last_records = npairs;
     std::vector<uint64_t> keys(npairs);
     std::vector<uint32_t> vals(npairs);
     if (npairs > 0) {
@@ -743,12 +742,12 @@ void plan_run(Plan *P, Result **outs) {
         r->u.push_back((int32_t)((keys[i] >> P->nbits) & nmask));
         r->v.push_back((int32_t)(keys[i] & nmask));
         r->n_cert.push_back(c);
+        r->n_certificates += c;
         i = e;
     }
     for (int q = 0; q < nq; q++) {
         Result *r = res[q].get();
         const Graph *g = P->graphs[P->qgraph[q]];
-        r->n_certificates = qcert[q];
         fill_stats_from_index(g->ix, &r->stats);
         r->stats.n_pairs = (int64_t)r->u.size();
         r->stats.n_certificates = r->n_certificates;
@@ -756,16 +755,16 @@ void plan_run(Plan *P, Result **outs) {
         r->stats.temporal_ms = r->stats.query_ms;
         if (!(P->queries[q].flags & FOLTY_QUERY_NO_COUNTS)) {
             const Index &ix = g->ix;
-            // the job's histogram holds running sums: level l of edge k at k * nls + l
+            // the job's histogram holds running sums
             const int32_t nls = padded_levels(P->jobs[P->qjob[q]].levels.size());
-            const uint32_t *count = P->hist[P->qjob[q]].as<uint32_t>() + P->qlevel[q];
+            const uint32_t *hist = P->hist[P->qjob[q]].as<uint32_t>();
             r->counts_dev.ensure(4 * (size_t)ix.m_input + 4);
             if (ix.m_input > 0)
                 k_fill<uint32_t><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(r->counts_dev.as<uint32_t>(),
                                                                                     0xffffffffu, ix.m_input);
             if (ix.m > 0)
-                k_scatter_counts<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, nls, ix.perm.as<int32_t>(), ix.m,
-                                                                               r->counts_dev.as<uint32_t>());
+                k_scatter_counts<<<grid_for(ix.m, BLK), BLK, 0, s>>>(hist, P->qlevel[q], nls, ix.perm.as<int32_t>(),
+                                                                       ix.m, r->counts_dev.as<uint32_t>());
             FOLTY_LAUNCHED();
             r->has_counts = true;
             r->device = P->device;
@@ -782,6 +781,7 @@ void plan_info(const Plan *P, folty_plan_info *info) {
     info->n_queries = (int32_t)P->queries.size();
     info->items = P->items;
     info->tests = P->last_tests;
+    info->records = P->last_records;
     info->tests_per_chunk = P->ipt;
     info->temporal_blocks = P->tblocks;
     info->captured = P->exec != nullptr;

@@ -133,6 +133,16 @@ struct alignas(32) EnumItem {
     int32_t pad[3];
 };
 
+// Histogram layout over sorted window levels (nls = levels rounded up to 4):
+// tiles of 64 consecutive edges, each tile nls / 4 blocks of 64 x 4 counters
+// (edge-minor within a block, four levels per edge), so a wavefront reading
+// four levels of its 64 edges reads 1 KB contiguous.
+__host__ __device__ inline int64_t hist_at(int64_t e, int32_t l, int32_t nls) {
+    return ((((e >> 6) * (nls >> 2) + (l >> 2)) << 6) + (e & 63)) * 4 + (l & 3);
+}
+// counters of a histogram over m edges (whole tiles)
+__host__ __device__ inline int64_t hist_words(int64_t m, int32_t nls) { return ((m + 63) & ~(int64_t)63) * nls; }
+
 struct alignas(32) EdgeRec {
     int32_t fn, bn;   // lengths of E_{tail,head} and E_{head,tail}
     int32_t fs, bs;   // their starts in ts

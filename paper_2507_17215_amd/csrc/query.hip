@@ -223,17 +223,6 @@ __global__ void k_counts_scatter(const uint32_t *__restrict__ count, const int32
     if (k < m) out[perm[k]] = count[k];
 }
 
-// running sum over window levels: hist[j][e] becomes #w with smallest window <= lv[j]
-__global__ void k_hist_prefix(uint32_t *__restrict__ hist, int nl, int64_t m) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    uint32_t acc = 0;
-    for (int j = 0; j < nl; j++) {
-        acc += hist[(int64_t)j * m + e];
-        hist[(int64_t)j * m + e] = acc;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------

@@ -30,10 +30,11 @@ double now_ms() {
 int64_t query_footprint(const Graph *g) {
     const Index &ix = g->ix;
     int64_t b = 0;
-    b += 4 * (int64_t)ix.m;                // counts (or one histogram level)
+    b += 4 * hist_words(ix.m, 4);          // window histogram (one level, padded to four)
     b += 20 * ix.T + 8 * (int64_t)ix.NI;   // survivors and their slots
     b += 4 * (int64_t)ix.NI + 16 * ((int64_t)ix.NI + 1);
-    b += 8 * (int64_t)ix.S + 24 * (int64_t)ix.S; // certificates per pair + pair keys
+    // certificate records (key + count), their sorted copy and the sort's scratch
+    b += 36 * (2 * (int64_t)ix.S + (int64_t)ix.m / 64 + 2);
     b += 4 * ix.m_input;                   // per-edge counts handed back
     return b;
 }

@@ -18,6 +18,10 @@ constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item (ab
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// this wavefront's index in its block, as a value the compiler knows is uniform
+// (so what is indexed by it is loaded into scalar registers)
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ inline unsigned long long lanes_below() { return (1ull << lane_id()) - 1ull; }
 
 // make this wavefront's LDS writes visible to all of its lanes
@@ -201,8 +205,7 @@ struct DirectOp {
 };
 
 // the smallest window per (e, w) into a histogram over sorted window levels:
-// level j counts w whose smallest window lies in (lv[j-1], lv[j]].  Edge-major:
-// edge e's levels are hist[e * nls .. e * nls + nl) (nls = nl rounded up to 4).
+// level j counts w whose smallest window lies in (lv[j-1], lv[j]]
 struct PoolOp {
     const int64_t *lv;
     int nl, nls;
@@ -229,7 +232,7 @@ struct PoolOp {
                 if (lv[mid] < win) a = mid + 1;
                 else b = mid;
             }
-            atomicAdd(&hist[(int64_t)e * nls + a], 1u);
+            atomicAdd(&hist[hist_at(e, a, nls)], 1u);
         }
     }
 };
@@ -259,6 +262,7 @@ __device__ inline bool chunk_run(const TriLists &T, uint32_t dq, const int64_t *
 // Sinks receive every probe: hit(h, p_uv, p_uw, p_vw) is called by all lanes of
 // the wave together (h = this lane found a triangle), so sinks may use ballots.
 struct CountSink {
+    static constexpr bool kCompact = false;
     int32_t *tri_u;
     int32_t c;
     __device__ void begin(int64_t) { c = 0; }
@@ -271,6 +275,7 @@ struct CountSink {
 };
 
 struct CacheSink {
+    static constexpr bool kCompact = false;
     const int64_t *base;
     int32_t *tri;
     int64_t slot;
@@ -291,6 +296,7 @@ struct CacheSink {
 };
 
 struct TcntSink {
+    static constexpr bool kCompact = false;
     const uint32_t *oeid;
     int32_t *tcnt;
     __device__ void begin(int64_t) {}
@@ -333,6 +339,9 @@ enum FilterMode {
 // counting pass and a later emitting pass agree on every survivor's position.
 // VAR < 0: the predicate code is read from `variant` at run time
 template <int VAR, int MODE> struct FilterSink {
+    // a run-time predicate code inlines all eight tests: keep the enumeration's
+    // code small (one copy of the sink) for those
+    static constexpr bool kCompact = VAR < 0;
     const int64_t *base; // EMIT, BOTH: first survivor slot of each item
     const EdgeRec *rec;
     const uint2 *rng; // per oriented edge: (first, last) timestamp >> shift
@@ -419,6 +428,7 @@ struct JobFilter {
 // read hits the cache), so only one code's lists are live at a time, and keeps
 // its survivors in its own slots.
 struct PairFilterSink {
+    static constexpr bool kCompact = true;
     const int64_t *base; // first slot of each item (the graph's triangle offsets)
     const EdgeRec *rec;
     const uint2 *rng;
@@ -593,9 +603,45 @@ __device__ inline void enum_item(const EnumItem &item, const StageAhead &ahead, 
         wave_sync();
         int32_t i = 0;  // this lane's segment; q only grows, so i only grows
         int32_t qn = 0; // waiting probes (wave-uniform)
+        // one probe step's candidates into the queue; a full wavefront of them
+        // (or, at the end, whatever waits) goes to the sink
+        auto enqueue = [&](bool v, int32_t x, int32_t r, bool last) {
+            bool cand = false;
+            if (v) {
+                const uint32_t h = bm_hash(x);
+                cand = (L.bm[h >> 5] >> (h & 31)) & 1u;
+            }
+            const unsigned long long mask = __ballot(cand);
+            if (cand) {
+                const int32_t slot = qn + (int32_t)__popcll(mask & lanes_below());
+                L.qx[slot] = x;
+                L.qr[slot] = r;
+            }
+            qn += (int32_t)__popcll(mask);
+            if (qn >= 64 || (last && qn > 0)) {
+                const int32_t cnt = qn < 64 ? qn : 64;
+                wave_sync();
+                enum_batch(b, d, L, cnt, sink);
+                const int32_t rest = qn - cnt;
+                int32_t tx = 0, tr = 0;
+                if (lane < rest) {
+                    tx = L.qx[64 + lane];
+                    tr = L.qr[64 + lane];
+                }
+                wave_sync();
+                if (lane < rest) {
+                    L.qx[lane] = tx;
+                    L.qr[lane] = tr;
+                }
+                qn = rest;
+                wave_sync();
+            }
+        };
         // ENUM_UNROLL steps of 64 probes at a time: their loads of x are all in
-        // flight before the first is used
-        for (int32_t q0 = 0; q0 < nq; q0 += 64 * ENUM_UNROLL) {
+        // flight before the first is used.  A last pass without probes hands over
+        // the probes still waiting.
+        for (int32_t q0 = 0;; q0 += 64 * ENUM_UNROLL) {
+            const bool more = q0 < nq;
             int32_t rk[ENUM_UNROLL], xk[ENUM_UNROLL];
             bool vk[ENUM_UNROLL];
 #pragma unroll
@@ -623,42 +669,28 @@ __device__ inline void enum_item(const EnumItem &item, const StageAhead &ahead, 
             }
 #pragma unroll
             for (int k = 0; k < ENUM_UNROLL; k++) xk[k] = vk[k] ? oadj[xk[k]] : 0;
+            if constexpr (Sink::kCompact) {
+                // the steps enter the queue in a loop that is not unrolled (each
+                // step's values move down one register), so the sink's code is
+                // generated once
+                const int steps = more ? ENUM_UNROLL : 1;
+#pragma unroll 1
+                for (int k = 0; k < steps; k++) {
+                    enqueue(vk[0], xk[0], rk[0], !more);
 #pragma unroll
-            for (int k = 0; k < ENUM_UNROLL; k++) {
-                bool cand = false;
-                if (vk[k]) {
-                    const uint32_t h = bm_hash(xk[k]);
-                    cand = (L.bm[h >> 5] >> (h & 31)) & 1u;
-                }
-                const unsigned long long mask = __ballot(cand);
-                if (cand) {
-                    const int32_t slot = qn + (int32_t)__popcll(mask & lanes_below());
-                    L.qx[slot] = xk[k];
-                    L.qr[slot] = rk[k];
-                }
-                qn += (int32_t)__popcll(mask);
-                if (qn >= 64) {
-                    wave_sync();
-                    enum_batch(b, d, L, 64, sink);
-                    const int32_t rest = qn - 64;
-                    int32_t tx = 0, tr = 0;
-                    if (lane < rest) {
-                        tx = L.qx[64 + lane];
-                        tr = L.qr[64 + lane];
+                    for (int j = 0; j + 1 < ENUM_UNROLL; j++) {
+                        xk[j] = xk[j + 1];
+                        rk[j] = rk[j + 1];
+                        vk[j] = vk[j + 1];
                     }
-                    wave_sync();
-                    if (lane < rest) {
-                        L.qx[lane] = tx;
-                        L.qr[lane] = tr;
-                    }
-                    qn = rest;
-                    wave_sync();
                 }
+            } else if (more) {
+#pragma unroll
+                for (int k = 0; k < ENUM_UNROLL; k++) enqueue(vk[k], xk[k], rk[k], false);
+            } else {
+                enqueue(false, 0, 0, true);
             }
-        }
-        if (qn > 0) {
-            wave_sync();
-            enum_batch(b, d, L, qn, sink);
+            if (!more) break;
         }
         wave_sync(); // the next item overwrites this wave's LDS
     } else if (d > CAP && nq > 0) {
@@ -705,13 +737,18 @@ __device__ inline void cached_item(const int64_t *__restrict__ base, const int32
     sink.end(it);
 }
 
+// Waves per SIMD the compiler must fit a sink's enumeration into: the query's
+// counting filter is held to 72 VGPRs (7 waves); the others keep their own size.
+template <class S> struct enum_waves { static constexpr int value = 4; };
+template <int V> struct enum_waves<FilterSink<V, FILTER_COUNT> > { static constexpr int value = 7; };
+
 // One wavefront per item; only != nullptr: items with only[it] == 0 are skipped
 template <class Sink>
-__global__ __launch_bounds__(BLK) void k_tri_enum(const EnumItem *__restrict__ items, const int32_t *__restrict__ oadj,
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(enum_waves<Sink>::value))) void k_tri_enum(const EnumItem *__restrict__ items, const int32_t *__restrict__ oadj,
                                                   const int4 *__restrict__ seg, int32_t NI, Sink sink,
                                                   const int32_t *__restrict__ only = nullptr) {
     __shared__ EnumLds lds[WPB];
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const int64_t stride = (int64_t)gridDim.x * WPB;
     int64_t it = (int64_t)blockIdx.x * WPB + w;
     if (only) {
@@ -746,7 +783,7 @@ template <int VAR, int MODE>
 __global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict__ base, const int32_t *__restrict__ tri,
                                                        int32_t NI, FilterSink<VAR, MODE> sink,
                                                        const int32_t *__restrict__ only = nullptr) {
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
         if (only && only[it] == 0) continue;
         cached_item(base, tri, it, sink);

@@ -58,10 +58,10 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_jobs", ctypes.c_int32), ("n_queries", ctypes.c_int32), ("items", ctypes.c_int64),
                 ("tests", ctypes.c_int64), ("tests_per_chunk", ctypes.c_int32),
                 ("temporal_blocks", ctypes.c_int32), ("captured", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("last_run_ms", ctypes.c_double)]
+                ("records", ctypes.c_int32), ("last_run_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class ServerOpts(ctypes.Structure):
