@@ -32,17 +32,15 @@ namespace folty {
 namespace {
 
 struct JobDev {
-    const EnumItem *item;
-    const int4 *seg;
-    const int32_t *oadj, *tri;
+    // filter and temporal tests
     const int64_t *tri_base, *ts;
     const EdgeRec *rec;
-    const uint2 *rng;
-    int32_t NI, variant;
-    int64_t dmax, dq;
+    int32_t variant;
+    int64_t dq; // range slack of the job's largest delta
     const int64_t *lv;
     int32_t nl, nls, m;
-    uint32_t *hist; // m * nls, edge-major (nls = nl rounded up to 4)
+    uint32_t *hist;  // hist_words(m, nls) counters, tiled (see hist_at)
+    uint32_t *tflag; // per tile of 64 edges: some counter is non-zero
     int32_t *sv;
     int64_t *sw;
     int32_t *su;
@@ -52,6 +50,7 @@ struct JobDev {
     const int32_t *sid, *smid, *slo, *shi, *deg, *tcnt;
     int32_t q0, q1;
     int32_t keep_prefix; // some query of the job hands back its per-edge counts
+    int32_t reset;       // the threshold step clears the tiles it read (reused plans)
 };
 
 // a plan's queries in job order, each job's by level (one scalar load each)
@@ -158,7 +157,7 @@ __global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict
                 else hi = mid - 1;
             }
             r -= J.sw[s0 + lo];
-            PoolOp op{J.lv, J.nl, J.nls, J.hist};
+            PoolOp op{J.lv, J.nl, J.nls, J.hist, J.tflag};
             for (int32_t s = lo; s < ns && k < k1; s++) {
                 const int64_t p = s0 + s;
                 TriLists L = load_lists(J.rec, J.sv[3 * p], J.sv[3 * p + 1], J.sv[3 * p + 2]);
@@ -229,14 +228,18 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
             ab = ((uint64_t)(uint32_t)a << nbits) | (uint64_t)(uint32_t)b;
         }
         const int64_t run = in ? 2 * (int64_t)s + dir : -1;
-        // this wavefront's tile: block c holds levels 4c..4c+3 of its 64 edges
-        uint4 *hrow = reinterpret_cast<uint4 *>(J.hist + hist_at(x0 - job_w_base[j], 0, J.nls)) + lane;
+        // this wavefront's tile: block c holds levels 4c..4c+3 of its 64 edges.
+        // A tile no test added to holds zeros and is not read.
+        const int64_t tile = (x0 - job_w_base[j]) >> 6;
+        const bool touched = __builtin_amdgcn_readfirstlane((int)J.tflag[tile]) != 0;
+        uint4 *hrow = reinterpret_cast<uint4 *>(J.hist + hist_at(tile << 6, 0, J.nls)) + lane;
         uint32_t acc = 0;
         int32_t qi = J.q0;
-        uint4 next = hrow[0];
+        const uint4 zero4 = make_uint4(0, 0, 0, 0);
+        uint4 next = touched ? hrow[0] : zero4;
         for (int32_t l0 = 0; l0 < J.nl; l0 += 4) {
             const uint4 cur = next;
-            if (l0 + 4 < J.nl) next = hrow[((l0 >> 2) + 1) * 64]; // one block ahead
+            if (touched && l0 + 4 < J.nl) next = hrow[((l0 >> 2) + 1) * 64]; // one block ahead
             uint32_t hv[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
             for (int jj = 0; jj < 4; jj++) {
@@ -257,8 +260,14 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
                     if (__ballot(cert)) wave_run_records(run, in, cert, ((uint64_t)q << (2 * nbits)) | ab, rk, rv, nrec, cap);
                 }
             }
-            if (J.keep_prefix && in) hrow[(l0 >> 2) * 64] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+            // per-edge counts read back: the running sums stay; otherwise the
+            // tile is left cleared for the next run
+            if (touched) {
+                if (J.keep_prefix) hrow[(l0 >> 2) * 64] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+                else if (J.reset) hrow[(l0 >> 2) * 64] = zero4;
+            }
         }
+        if (touched && J.reset && lane == 0) J.tflag[tile] = 0u;
     }
 }
 
@@ -296,6 +305,7 @@ struct Plan {
         int32_t graph;
         int variant;
         std::vector<int64_t> levels;
+        bool reset = false; // its threshold step leaves the histogram cleared
     };
     std::vector<Job> jobs;
     std::vector<int32_t> qjob, qlevel;
@@ -306,7 +316,8 @@ struct Plan {
     int nbits = 0;
     // device memory
     DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_groups, d_group_item_base;
-    std::vector<DevBuf> hist, lv, sv, sw, su;
+    std::vector<DevBuf> hist, tflag, lv, sv, sw, su;
+    bool dirty = true; // some histogram may hold counts (fresh, tuned, or a run did not finish)
     DevBuf wu, wbase, nrec, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
     // launch shape and capture
@@ -332,6 +343,7 @@ Plan::~Plan() {
         (void)hipStreamSynchronize(stream);
         StreamScope sc(stream);
         hist.clear();
+        tflag.clear();
         lv.clear();
         sv.clear();
         sw.clear();
@@ -354,14 +366,22 @@ Plan::~Plan() {
     }
 }
 
+// zero job j's histogram and tile flags
+static void clear_hist(Plan &P, int j, hipStream_t s) {
+    const Index &ix = P.graphs[P.jobs[j].graph]->ix;
+    const int64_t hn = hist_words(ix.m, padded_levels(P.jobs[j].levels.size()));
+    if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
+    const int64_t nt = ((int64_t)ix.m + 63) / 64;
+    if (nt > 0) k_fill<uint32_t><<<grid_for(nt, BLK, 1 << 16), BLK, 0, s>>>(P.tflag[j].as<uint32_t>(), 0u, nt);
+    FOLTY_LAUNCHED();
+}
+
 static void enqueue_compute(Plan &P, hipStream_t s) {
-    const int nj = (int)P.jobs.size(), nq = (int)P.queries.size();
-    // clear what accumulates: histograms, survivor counts, certificates
-    for (int j = 0; j < nj; j++) {
-        const Index &ix = P.graphs[P.jobs[j].graph]->ix;
-        const int64_t hn = hist_words(ix.m, padded_levels(P.jobs[j].levels.size()));
-        if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
-    }
+    const int nj = (int)P.jobs.size();
+    // clear what accumulates: the histograms of jobs whose threshold step does
+    // not leave them cleared, the record count, the test total
+    for (int j = 0; j < nj; j++)
+        if (!P.jobs[j].reset) clear_hist(P, j, s);
     k_fill<int32_t><<<1, 1, 0, s>>>(P.nrec.as<int32_t>(), 0, 1);
     k_fill<int64_t><<<1, 1, 0, s>>>(P.wu.as<int64_t>() + P.items, (int64_t)0, 1);
     FOLTY_LAUNCHED();
@@ -425,12 +445,7 @@ static void tune(Plan &P) {
     int bi = P.ipt, bb = P.tblocks;
     for (int ip : ipts)
         for (int bl : blocks) {
-            for (int j = 0; j < nj; j++) {
-                const Index &ix = P.graphs[P.jobs[j].graph]->ix;
-                const int64_t hn = hist_words(ix.m, padded_levels(P.jobs[j].levels.size()));
-                if (hn > 0)
-                    k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
-            }
+            for (int j = 0; j < nj; j++) clear_hist(P, j, s);
             FOLTY_HIP(hipEventRecord(P.ev[1], s));
             k_multi_temporal<<<bl, BLK, 0, s>>>(P.d_jobs.as<JobDev>(), nj, P.d_job_item_base.as<int64_t>(), P.items,
                                                 P.wbase.as<int64_t>(), ip);
@@ -447,6 +462,7 @@ static void tune(Plan &P) {
     P.ipt = bi;
     P.tblocks = bb;
     P.tuned = true;
+    P.dirty = true; // the tries left counts behind
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[bucket] = {bi, bb};
 }
@@ -510,6 +526,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     const int nj = (int)P->jobs.size();
     // per-job buffers and descriptors
     P->hist.resize(nj);
+    P->tflag.resize(nj);
     P->lv.resize(nj);
     P->sv.resize(nj);
     P->sw.resize(nj);
@@ -541,29 +558,24 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         const Index &ix = P->graphs[P->jobs[j].graph]->ix;
         const auto &lvs = P->jobs[j].levels;
         P->hist[j].ensure(4 * (size_t)hist_words(ix.m, padded_levels(lvs.size())) + 16);
+        P->tflag[j].ensure(4 * (((size_t)ix.m + 63) / 64) + 4);
         P->lv[j].ensure(8 * lvs.size());
         FOLTY_HIP(hipMemcpyAsync(P->lv[j].p, lvs.data(), 8 * lvs.size(), hipMemcpyHostToDevice, s));
         P->sv[j].ensure(12 * (size_t)ix.T + 12);
         P->sw[j].ensure(8 * (size_t)ix.T + 8);
         P->su[j].ensure(4 * (size_t)ix.NI + 4);
         JobDev &d = jd[j];
-        d.item = ix.item.as<EnumItem>();
-        d.seg = ix.seg.as<int4>();
-        d.oadj = ix.oadj.as<int32_t>();
-        d.tri = ix.tri_cached ? ix.tri.as<int32_t>() : nullptr;
         d.tri_base = ix.tri_base.as<int64_t>();
         d.ts = ix.ts.as<int64_t>();
         d.rec = ix.rec.as<EdgeRec>();
-        d.rng = ix.erng.as<uint2>();
-        d.NI = ix.NI;
         d.variant = P->jobs[j].variant;
-        d.dmax = lvs.back();
-        d.dq = range_slack(d.dmax, ix.tshift);
+        d.dq = range_slack(lvs.back(), ix.tshift);
         d.lv = P->lv[j].as<int64_t>();
         d.nl = (int32_t)lvs.size();
         d.nls = padded_levels(lvs.size());
         d.m = ix.m;
         d.hist = P->hist[j].as<uint32_t>();
+        d.tflag = P->tflag[j].as<uint32_t>();
         d.sv = P->sv[j].as<int32_t>();
         d.sw = P->sw[j].as<int64_t>();
         d.su = P->su[j].as<int32_t>();
@@ -581,6 +593,8 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
             if (qs[jq[i]].universe == FOLTY_UNIVERSE_COMMON) d.tcnt = ix.tcnt.as<int32_t>();
             if (!(qs[jq[i]].flags & FOLTY_QUERY_NO_COUNTS)) d.keep_prefix = 1;
         }
+        d.reset = !d.keep_prefix && !oneshot;
+        P->jobs[j].reset = d.reset != 0;
     }
     // groups: the jobs of each graph, two at a time, share one enumeration
     std::vector<GroupDev> gd, singles;
@@ -670,10 +684,20 @@ void plan_run(Plan *P, Result **outs) {
         P->eager = true;
         P->tuned = true;
     }
+    // histograms that runs leave cleared must start cleared (jobs that keep
+    // their counts are cleared at the start of every run)
+    auto settle = [&] {
+        if (!P->dirty) return;
+        for (int j = 0; j < (int)P->jobs.size(); j++)
+            if (P->jobs[j].reset) clear_hist(*P, j, s);
+        P->dirty = false;
+    };
+    settle();
     if (!P->tuned) {
         // first run: eager, with the autotuner between the filter and the tests
         enqueue_compute(*P, s);
         tune(*P);
+        settle();
     }
     if (!P->exec && !P->eager) {
         // capture once; if the runtime refuses, keep launching eagerly
@@ -700,6 +724,7 @@ void plan_run(Plan *P, Result **outs) {
         }
     }
     FOLTY_HIP(hipEventRecord(P->ev[0], s));
+    P->dirty = true; // until the run is known to have finished
     if (P->exec) FOLTY_HIP(hipGraphLaunch(P->exec, s));
     else enqueue_compute(*P, s);
     FOLTY_HIP(hipEventRecord(P->ev[3], s));
@@ -709,6 +734,7 @@ void plan_run(Plan *P, Result **outs) {
     int32_t npairs = 0;
     FOLTY_HIP(hipMemcpyAsync(&npairs, P->nrec.p, 4, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
+    P->dirty = false;
     if (npairs < 0 || npairs > P->rec_cap)
         fail(FOLTY_EDEVICE, "certificate records exceed their bound (%d > %lld)", npairs, (long long)P->rec_cap);
     P->last_records = npairs;

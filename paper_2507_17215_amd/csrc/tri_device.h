@@ -210,6 +210,7 @@ struct PoolOp {
     const int64_t *lv;
     int nl, nls;
     uint32_t *hist;
+    uint32_t *tflag; // per tile of 64 edges: set once a counter of the tile is added to
     __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
                                       const Span &l3) const {
         const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
@@ -233,6 +234,7 @@ struct PoolOp {
                 else b = mid;
             }
             atomicAdd(&hist[hist_at(e, a, nls)], 1u);
+            tflag[e >> 6] = 1u;
         }
     }
 };

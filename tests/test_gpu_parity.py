@@ -262,6 +262,37 @@ def test_plan_buffers_larger_than_one_fill_grid():
             assert np.array_equal(got[idx], pool[q["variant"]][q["delta"]]), q
 
 
+def test_plan_without_counts_leaves_histograms_cleared():
+    """Plans whose queries hand back no per-edge counts skip the per-run clear:
+    the threshold step zeroes each histogram tile it read.  Replays (with other
+    plans and queries on the same graph in between) must keep giving the
+    single-query results, and so must a plan mixing both kinds on one job."""
+    g = synth.c1_family(300_000, seed=3)
+    G = gpu_graph(g)
+    rng = np.random.default_rng(21)
+    qs = [dict(delta=int(rng.choice([600, 3600, 86400, 400_000, 10**6])), theta=(int(rng.choice([1, 2, 5])), 20),
+               variant=int(rng.choice([0, 3])), universe=int(rng.integers(0, 3))) for _ in range(24)]
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    want = [o.query(q["delta"], q["theta"][0], q["theta"][1], q["variant"], q["universe"]) for q in qs]
+    assert sum(w["n_certificates"] > 0 for w in want) >= 12
+    lean = folty.Plan([G], [(0, dict(q, counts=False)) for q in qs])
+    mixed = folty.Plan([G], [(0, dict(q, counts=(i % 3 == 0))) for i, q in enumerate(qs)])
+    for rep in range(4):
+        say("plan without counts, run", rep)
+        for q, r, w in zip(qs, lean.run(), want):
+            assert r.n_certificates == w["n_certificates"], q
+            assert np.array_equal(r.pair_u, w["pair_u"]) and np.array_equal(r.pair_v, w["pair_v"]), q
+            assert np.array_equal(r.n_cert, w["n_cert"]), q
+        rs = mixed.run()
+        for i, (q, r, w) in enumerate(zip(qs, rs, want)):
+            if i % 3 == 0:
+                assert_same(r, w)
+            else:
+                assert r.n_certificates == w["n_certificates"], q
+                assert np.array_equal(r.n_cert, w["n_cert"]), q
+        G.query(qs[rep]["delta"], (1, 2), 0, counts=False)
+
+
 def test_single_query_one_pass_and_two_pass_agree():
     """A fresh index filters in two passes (count, then emit only items with
     survivors); once a plan has made the per-item triangle offsets, single
