@@ -40,7 +40,7 @@ struct JobDev {
     const int64_t *lv;
     int32_t nl, nls, m;
     uint32_t *hist;  // hist_words(m, nls) counters, tiled (see hist_at)
-    uint32_t *tflag; // per tile of 64 edges: some counter is non-zero
+    unsigned long long *tmask; // per tile of 64 edges: which edges have a non-zero counter
     int32_t *sv;
     int64_t *sw;
     int32_t *su;
@@ -57,7 +57,8 @@ struct JobDev {
 struct alignas(32) QueryDev {
     int32_t level; // index of the query's delta among its job's levels
     uint32_t num, den;
-    int32_t universe, excl;
+    int32_t universe;
+    int32_t excl;  // 1: the other endpoint is left out of the universe (never for the common one)
     int32_t q;     // the query's index in the plan
     int32_t pad[2];
 };
@@ -99,27 +100,31 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int64_t it = g - group_item_base[gi];
         using Sink = std::conditional_t<NJ == 2, PairFilterSink, FilterSink<-1, FILTER_BOTH> >;
         Sink sink;
-        sink.base = G.tri_base;
-        sink.rec = G.rec;
-        sink.rng = G.rng;
+        sink.base = global_ptr(G.tri_base);
+        sink.rec = global_ptr(G.rec);
+        sink.rng = global_ptr(G.rng);
         if constexpr (NJ == 2) {
             for (int jj = 0; jj < 2; jj++) {
                 const JobDev &J = jobs[G.job[jj]];
-                sink.f[jj] = JobFilter{J.dq, J.variant, J.sv, J.sw, J.su, J.wu};
+                sink.f[jj] = JobFilter{J.dq, J.variant, global_ptr(J.sv), global_ptr(J.sw), global_ptr(J.su),
+                                       global_ptr(J.wu)};
             }
         } else {
             const JobDev &J = jobs[G.job[0]];
             sink.dq = J.dq;
             sink.variant = J.variant;
-            sink.sv = J.sv;
-            sink.sw = J.sw;
-            sink.su = J.su;
-            sink.wu = J.wu;
+            sink.sv = global_ptr(J.sv);
+            sink.sw = global_ptr(J.sw);
+            sink.su = global_ptr(J.su);
+            sink.wu = global_ptr(J.wu);
         }
-        if (G.tri) cached_item(G.tri_base, G.tri, it, sink);
+        const int32_t *tri = global_ptr(G.tri);
+        if (tri) cached_item(sink.base, tri, it, sink);
         else {
-            const EnumItem item = G.item[it];
-            enum_item(item, stage_ahead(item, G.oadj, G.seg), G.oadj, G.seg, it, sink, lds[w]);
+            const int32_t *oadj = global_ptr(G.oadj);
+            const int4 *seg = global_ptr(G.seg);
+            const EnumItem item = global_ptr(G.item)[it];
+            enum_item(item, stage_ahead(item, oadj, seg), oadj, seg, it, sink, lds[w]);
         }
     }
 }
@@ -146,27 +151,41 @@ __global__ __launch_bounds__(BLK) void k_multi_temporal(const JobDev *__restrict
             const int32_t j = owner_of(job_item_base, nj, g);
             const JobDev &J = jobs[j];
             const int64_t it = g - job_item_base[j];
+            const int32_t *sv = global_ptr(J.sv);
+            const int64_t *sw = global_ptr(J.sw);
             int64_t r = k - wbase[g];
-            const int64_t s0 = J.tri_base[it];
-            const int32_t ns = J.su[it];
+            const int64_t s0 = global_ptr(J.tri_base)[it];
+            const int32_t ns = global_ptr(J.su)[it];
             if (ns <= 0) break; // cannot happen when the offsets are consistent
             int32_t lo = 0, hi = ns - 1;
             while (lo < hi) {
                 int32_t mid = (lo + hi + 1) >> 1;
-                if (J.sw[s0 + mid] <= r) lo = mid;
+                if (sw[s0 + mid] <= r) lo = mid;
                 else hi = mid - 1;
             }
-            r -= J.sw[s0 + lo];
-            PoolOp op{J.lv, J.nl, J.nls, J.hist, J.tflag};
+            r -= sw[s0 + lo];
+            PoolOp op{global_ptr(J.lv), J.nl, J.nls, global_ptr(J.hist), global_ptr(J.tmask)};
+            const EdgeRec *rec = global_ptr(J.rec);
+            const int64_t *ts = global_ptr(J.ts);
             for (int32_t s = lo; s < ns && k < k1; s++) {
                 const int64_t p = s0 + s;
-                TriLists L = load_lists(J.rec, J.sv[3 * p], J.sv[3 * p + 1], J.sv[3 * p + 2]);
-                chunk_runs_rt(J.variant, L, run_slack(J.dq), J.ts, r, k, k1, op);
+                TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
+                chunk_runs_rt(J.variant, L, run_slack(J.dq), ts, r, k, k1, op);
                 r = 0;
             }
             if (k == k_start) break; // every survivor has tests, so this never triggers
         }
     }
+}
+
+// the plan's query at position qi, or one with no level past the job's last
+// (qi is the same in every lane; saying so keeps the load scalar, all eight
+// words at once)
+__device__ inline QueryDev next_query(const QueryDev *__restrict__ qs, int32_t qi, int32_t q1) {
+    QueryDev Q{};
+    if (qi < q1) Q = qs[__builtin_amdgcn_readfirstlane(qi)];
+    else Q.level = INT32_MAX;
+    return Q;
 }
 
 // Certificates of one query over a wavefront of edges: per run of equal
@@ -217,24 +236,29 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
         const bool in = e < J.m;
         int32_t s = 0, dir = 0, du = 0, da = 0, tc = 0;
         uint64_t ab = 0;
+        const int32_t *tcnt = global_ptr(J.tcnt);
         if (in) {
-            s = J.sid[e];
-            dir = e >= J.smid[s] ? 1 : 0;
-            const int32_t a = dir ? J.shi[s] : J.slo[s];
-            const int32_t b = dir ? J.slo[s] : J.shi[s];
-            du = J.deg[b];
-            da = J.deg[a];
-            if (J.tcnt) tc = J.tcnt[s];
+            const int32_t *slo = global_ptr(J.slo), *shi = global_ptr(J.shi), *deg = global_ptr(J.deg);
+            s = global_ptr(J.sid)[e];
+            dir = e >= global_ptr(J.smid)[s] ? 1 : 0;
+            const int32_t a = dir ? shi[s] : slo[s];
+            const int32_t b = dir ? slo[s] : shi[s];
+            du = deg[b];
+            da = deg[a];
+            if (tcnt) tc = tcnt[s];
             ab = ((uint64_t)(uint32_t)a << nbits) | (uint64_t)(uint32_t)b;
         }
         const int64_t run = in ? 2 * (int64_t)s + dir : -1;
         // this wavefront's tile: block c holds levels 4c..4c+3 of its 64 edges.
-        // A tile no test added to holds zeros and is not read.
+        // Edges no test added to hold zeros and are not read.
         const int64_t tile = (x0 - job_w_base[j]) >> 6;
-        const bool touched = __builtin_amdgcn_readfirstlane((int)J.tflag[tile]) != 0;
-        uint4 *hrow = reinterpret_cast<uint4 *>(J.hist + hist_at(tile << 6, 0, J.nls)) + lane;
+        unsigned long long *tmask = global_ptr(J.tmask);
+        const unsigned long long tm = tmask[tile];
+        const bool touched = (tm >> lane) & 1ull;
+        uint4 *hrow = reinterpret_cast<uint4 *>(global_ptr(J.hist) + hist_at(tile << 6, 0, J.nls)) + lane;
         uint32_t acc = 0;
         int32_t qi = J.q0;
+        QueryDev Q = next_query(qs, qi, J.q1);
         const uint4 zero4 = make_uint4(0, 0, 0, 0);
         uint4 next = touched ? hrow[0] : zero4;
         for (int32_t l0 = 0; l0 < J.nl; l0 += 4) {
@@ -247,17 +271,16 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
                 if (l >= J.nl) break;
                 acc += hv[jj];
                 hv[jj] = acc;
-                for (; qi < J.q1; qi++) {
-                    // qi is the same in every lane; saying so keeps these loads scalar
-                    const QueryDev &Q = qs[__builtin_amdgcn_readfirstlane(qi)];
-                    const int32_t q = Q.q;
-                    if (Q.level != l) break;
-                    int64_t U;
-                    if (Q.universe == FOLTY_UNIVERSE_DST) U = (int64_t)du - Q.excl;
-                    else if (Q.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)da - Q.excl;
-                    else U = tc;
-                    const bool cert = in && (uint64_t)acc * Q.den >= (uint64_t)Q.num * (uint64_t)U;
-                    if (__ballot(cert)) wave_run_records(run, in, cert, ((uint64_t)q << (2 * nbits)) | ab, rk, rv, nrec, cap);
+                while (Q.level == l) {
+                    // |U| >= 0: an edge's endpoints have degree >= 1
+                    const uint32_t U = (uint32_t)(Q.universe == FOLTY_UNIVERSE_DST   ? du
+                                                  : Q.universe == FOLTY_UNIVERSE_SRC ? da
+                                                                                     : tc) -
+                                       (uint32_t)Q.excl;
+                    const bool cert = in && (uint64_t)acc * Q.den >= (uint64_t)Q.num * U;
+                    if (__ballot(cert))
+                        wave_run_records(run, in, cert, ((uint64_t)Q.q << (2 * nbits)) | ab, rk, rv, nrec, cap);
+                    Q = next_query(qs, ++qi, J.q1);
                 }
             }
             // per-edge counts read back: the running sums stay; otherwise the
@@ -267,7 +290,7 @@ __global__ __launch_bounds__(BLK) void k_job_threshold(const JobDev *__restrict_
                 else if (J.reset) hrow[(l0 >> 2) * 64] = zero4;
             }
         }
-        if (touched && J.reset && lane == 0) J.tflag[tile] = 0u;
+        if (tm && J.reset && lane == 0) tmask[tile] = 0ull;
     }
 }
 
@@ -316,7 +339,7 @@ struct Plan {
     int nbits = 0;
     // device memory
     DevBuf d_jobs, d_job_item_base, d_job_w_base, d_queries, d_groups, d_group_item_base;
-    std::vector<DevBuf> hist, tflag, lv, sv, sw, su;
+    std::vector<DevBuf> hist, tmask, lv, sv, sw, su;
     bool dirty = true; // some histogram may hold counts (fresh, tuned, or a run did not finish)
     DevBuf wu, wbase, nrec, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
@@ -343,7 +366,7 @@ Plan::~Plan() {
         (void)hipStreamSynchronize(stream);
         StreamScope sc(stream);
         hist.clear();
-        tflag.clear();
+        tmask.clear();
         lv.clear();
         sv.clear();
         sw.clear();
@@ -366,13 +389,14 @@ Plan::~Plan() {
     }
 }
 
-// zero job j's histogram and tile flags
+// zero job j's histogram and tile masks
 static void clear_hist(Plan &P, int j, hipStream_t s) {
     const Index &ix = P.graphs[P.jobs[j].graph]->ix;
     const int64_t hn = hist_words(ix.m, padded_levels(P.jobs[j].levels.size()));
     if (hn > 0) k_fill<uint32_t><<<grid_for(hn, BLK, 1 << 16), BLK, 0, s>>>(P.hist[j].as<uint32_t>(), 0u, hn);
     const int64_t nt = ((int64_t)ix.m + 63) / 64;
-    if (nt > 0) k_fill<uint32_t><<<grid_for(nt, BLK, 1 << 16), BLK, 0, s>>>(P.tflag[j].as<uint32_t>(), 0u, nt);
+    if (nt > 0)
+        k_fill<unsigned long long><<<grid_for(nt, BLK, 1 << 16), BLK, 0, s>>>(P.tmask[j].as<unsigned long long>(), 0ull, nt);
     FOLTY_LAUNCHED();
 }
 
@@ -526,7 +550,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     const int nj = (int)P->jobs.size();
     // per-job buffers and descriptors
     P->hist.resize(nj);
-    P->tflag.resize(nj);
+    P->tmask.resize(nj);
     P->lv.resize(nj);
     P->sv.resize(nj);
     P->sw.resize(nj);
@@ -558,7 +582,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         const Index &ix = P->graphs[P->jobs[j].graph]->ix;
         const auto &lvs = P->jobs[j].levels;
         P->hist[j].ensure(4 * (size_t)hist_words(ix.m, padded_levels(lvs.size())) + 16);
-        P->tflag[j].ensure(4 * (((size_t)ix.m + 63) / 64) + 4);
+        P->tmask[j].ensure(8 * (((size_t)ix.m + 63) / 64) + 8);
         P->lv[j].ensure(8 * lvs.size());
         FOLTY_HIP(hipMemcpyAsync(P->lv[j].p, lvs.data(), 8 * lvs.size(), hipMemcpyHostToDevice, s));
         P->sv[j].ensure(12 * (size_t)ix.T + 12);
@@ -575,7 +599,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         d.nls = padded_levels(lvs.size());
         d.m = ix.m;
         d.hist = P->hist[j].as<uint32_t>();
-        d.tflag = P->tflag[j].as<uint32_t>();
+        d.tmask = P->tmask[j].as<unsigned long long>();
         d.sv = P->sv[j].as<int32_t>();
         d.sw = P->sw[j].as<int64_t>();
         d.su = P->su[j].as<int32_t>();
@@ -643,7 +667,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
         d.num = qs[q].theta_num;
         d.den = qs[q].theta_den;
         d.universe = qs[q].universe;
-        d.excl = qs[q].exclude_other ? 1 : 0;
+        d.excl = qs[q].exclude_other && qs[q].universe != FOLTY_UNIVERSE_COMMON ? 1 : 0;
         // records of this query: at most one per run of equal (static edge,
         // direction) keys within a wavefront, i.e. one per directed pair plus one
         // per wavefront boundary

@@ -18,6 +18,17 @@ constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item (ab
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// A pointer field of a table in device memory (a plan's per-job records), read
+// as a pointer to global memory.  The compiler cannot tell where such a pointer
+// points and would use flat instructions, whose completion shares one wait
+// counter with LDS and scalar loads (so every LDS wait would also wait for the
+// global loads in flight).
+template <class T> __device__ inline T *global_ptr(T *const &field) {
+    __attribute__((address_space(1))) T *g;
+    __builtin_memcpy(&g, &field, sizeof g);
+    return (T *)g;
+}
+
 // this wavefront's index in its block, as a value the compiler knows is uniform
 // (so what is indexed by it is loaded into scalar registers)
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
@@ -210,7 +221,7 @@ struct PoolOp {
     const int64_t *lv;
     int nl, nls;
     uint32_t *hist;
-    uint32_t *tflag; // per tile of 64 edges: set once a counter of the tile is added to
+    unsigned long long *tmask; // per tile of 64 edges: bit e & 63 set once a counter of edge e is non-zero
     __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
                                       const Span &l3) const {
         const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
@@ -233,8 +244,7 @@ struct PoolOp {
                 if (lv[mid] < win) a = mid + 1;
                 else b = mid;
             }
-            atomicAdd(&hist[hist_at(e, a, nls)], 1u);
-            tflag[e >> 6] = 1u;
+            if (atomicAdd(&hist[hist_at(e, a, nls)], 1u) == 0u) atomicOr(&tmask[e >> 6], 1ull << (e & 63));
         }
     }
 };
