@@ -296,8 +296,6 @@ size_t sort_pairs_u64_u32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint
 size_t sort_pairs_u32_i32(void *tmp, size_t tmp_bytes, const uint32_t *kin, uint32_t *kout,
                           const int32_t *vin, int32_t *vout, int64_t n, int end_bit,
                           hipStream_t stream);
-size_t sort_keys_u64(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout, int64_t n,
-                     int end_bit, hipStream_t stream);
 size_t exclusive_scan_i64(void *tmp, size_t tmp_bytes, const int64_t *in, int64_t *out, int64_t n,
                           hipStream_t stream);
 size_t exclusive_scan_i32_to_i64(void *tmp, size_t tmp_bytes, const int32_t *in, int64_t *out,

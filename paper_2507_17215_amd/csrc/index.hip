@@ -680,33 +680,46 @@ __global__ __launch_bounds__(BLK) void k_peel_step(PeelBufs B, int64_t step) {
     }
 }
 
-// undirected adjacency from the static edge table: both (x, y) keys per edge
-__global__ void k_adj_keys(const int32_t *__restrict__ slo, const int32_t *__restrict__ shi, int32_t S,
-                           uint64_t *__restrict__ key) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    uint64_t a = (uint32_t)slo[s], b = (uint32_t)shi[s];
-    key[2 * s] = (a << 32) | b;
-    key[2 * s + 1] = (b << 32) | a;
+// The undirected adjacency from the static edge table, whose edges are sorted
+// by (lo, hi): vertex v's row is its lower neighbours (edges with hi = v, in lo
+// order) followed by its higher ones (edges with lo = v, in hi order), so both
+// halves are already ascending.  hkey/hval: the table's (hi, lo) pairs stably
+// sorted by hi.  With loff[v] = #edges with lo < v and hoff[v] = #edges with
+// hi < v, row v starts at loff[v] + hoff[v].
+__device__ inline int64_t lower_bound_i32(const int32_t *__restrict__ a, int64_t len, int32_t x) {
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
 }
 
-__global__ void k_adj_unpack(const uint64_t *__restrict__ key, int64_t E, int32_t *__restrict__ uadj) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < E) uadj[i] = (int32_t)(key[i] & 0xffffffffu);
-}
-
-// row starts by binary search over the sorted keys; degrees from consecutive starts
-__global__ void k_adj_rows(const uint64_t *__restrict__ key, int64_t E, int32_t n, int64_t *__restrict__ uoff) {
+__global__ void k_adj_rows(const int32_t *__restrict__ slo, const int32_t *__restrict__ hkey, int32_t S, int32_t n,
+                           int32_t *__restrict__ loff, int32_t *__restrict__ hoff, int64_t *__restrict__ uoff) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x > n) return;
-    uint64_t want = (uint64_t)x << 32;
-    int64_t a = 0, b = E;
-    while (a < b) {
-        int64_t mid = (a + b) >> 1;
-        if (key[mid] < want) a = mid + 1;
-        else b = mid;
-    }
-    uoff[x] = a;
+    const int64_t a = lower_bound_i32(slo, S, (int32_t)x), b = lower_bound_i32(hkey, S, (int32_t)x);
+    loff[x] = (int32_t)a;
+    hoff[x] = (int32_t)b;
+    uoff[x] = a + b;
+}
+
+// edge s = (lo, hi) in lo's row: after lo's hoff[lo + 1] - hoff[lo] lower
+// neighbours, at uoff[lo] + that + (s - loff[lo]) = hoff[lo + 1] + s
+__global__ void k_adj_fill_up(const int32_t *__restrict__ slo, const int32_t *__restrict__ shi, int32_t S,
+                              const int32_t *__restrict__ hoff, int32_t *__restrict__ uadj) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < S) uadj[(int64_t)hoff[slo[e] + 1] + e] = shi[e];
+}
+
+// sorted position q (hi = hkey[q], lo = hval[q]) in hi's row: at
+// uoff[hi] + (q - hoff[hi]) = loff[hi] + q
+__global__ void k_adj_fill_down(const int32_t *__restrict__ hkey, const int32_t *__restrict__ hval, int32_t S,
+                                const int32_t *__restrict__ loff, int32_t *__restrict__ uadj) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < S) uadj[(int64_t)loff[hkey[q]] + q] = hval[q];
 }
 
 // hubs of the peeling adjacency: vertices of degree > HUB_DEG, first HUB_SLOTS found
@@ -1017,21 +1030,29 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     uoff.ensure(8 * ((size_t)n + 1));
     uadj.ensure(8 * (size_t)S + 8);
     {
-        const int64_t E = 2 * (int64_t)S;
-        DevBuf k1, k2;
-        k1.ensure(8 * (size_t)E + 8);
-        k2.ensure(8 * (size_t)E + 8);
+        DevBuf hkey, hval, loff, hoff;
+        hkey.ensure(4 * (size_t)S + 4);
+        hval.ensure(4 * (size_t)S + 4);
+        loff.ensure(4 * ((size_t)n + 1));
+        hoff.ensure(4 * ((size_t)n + 1));
         if (S > 0) {
-            k_adj_keys<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
-                                                        k1.as<uint64_t>());
-            FOLTY_LAUNCHED();
-            int kb = 32 + bit_length((uint64_t)n);
-            size_t need = sort_keys_u64(nullptr, 0, k1.as<uint64_t>(), k2.as<uint64_t>(), E, kb, s);
-            sort_keys_u64(cub_ensure(need), need, k1.as<uint64_t>(), k2.as<uint64_t>(), E, kb, s);
-            k_adj_unpack<<<grid_for(E, BLK), BLK, 0, s>>>(k2.as<uint64_t>(), E, uadj.as<int32_t>());
+            int kb = bit_length((uint64_t)n);
+            size_t need = sort_pairs_u32_i32(nullptr, 0, reinterpret_cast<const uint32_t *>(ix.shi.as<int32_t>()),
+                                             hkey.as<uint32_t>(), ix.slo.as<int32_t>(), hval.as<int32_t>(), S, kb, s);
+            sort_pairs_u32_i32(cub_ensure(need), need, reinterpret_cast<const uint32_t *>(ix.shi.as<int32_t>()),
+                               hkey.as<uint32_t>(), ix.slo.as<int32_t>(), hval.as<int32_t>(), S, kb, s);
+        }
+        k_adj_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), hkey.as<int32_t>(), S, n,
+                                                                 loff.as<int32_t>(), hoff.as<int32_t>(),
+                                                                 uoff.as<int64_t>());
+        FOLTY_LAUNCHED();
+        if (S > 0) {
+            k_adj_fill_up<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
+                                                           hoff.as<int32_t>(), uadj.as<int32_t>());
+            k_adj_fill_down<<<grid_for(S, BLK), BLK, 0, s>>>(hkey.as<int32_t>(), hval.as<int32_t>(), S,
+                                                             loff.as<int32_t>(), uadj.as<int32_t>());
             FOLTY_LAUNCHED();
         }
-        k_adj_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(k2.as<uint64_t>(), E, n, uoff.as<int64_t>());
         k_adj_deg<<<grid_for(n, BLK), BLK, 0, s>>>(uoff.as<int64_t>(), n, ix.deg.as<int32_t>());
         FOLTY_LAUNCHED();
     }

@@ -46,18 +46,6 @@ size_t sort_pairs_u32_i32(void *tmp, size_t tb, const uint32_t *kin, uint32_t *k
     return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
 }
 
-size_t sort_keys_u64(void *tmp, size_t tb, const uint64_t *kin, uint64_t *kout, int64_t n, int end_bit,
-                     hipStream_t s) {
-    size_t need = 0;
-    if (end_bit < 1) end_bit = 1;
-    if (end_bit > 64) end_bit = 64;
-    FOLTY_CUB(hipcub::DeviceRadixSort::SortKeys(nullptr, need, kin, kout, (int)n, 0, end_bit, s));
-    if (!tmp) return need;
-    if (tb < need) fail(FOLTY_EDEVICE, "sort scratch too small");
-    FOLTY_CUB(hipcub::DeviceRadixSort::SortKeys(tmp, tb, kin, kout, (int)n, 0, end_bit, s));
-    return need;
-}
-
 size_t exclusive_scan_i64(void *tmp, size_t tb, const int64_t *in, int64_t *out, int64_t n,
                           hipStream_t s) {
     size_t need = 0;
