@@ -708,18 +708,31 @@ __global__ void k_adj_rows(const int32_t *__restrict__ slo, const int32_t *__res
 
 // edge s = (lo, hi) in lo's row: after lo's hoff[lo + 1] - hoff[lo] lower
 // neighbours, at uoff[lo] + that + (s - loff[lo]) = hoff[lo + 1] + s
+// the neighbour id in the plain adjacency, and in the peel's copy for large
+// rounds HUB_FLAG | slot for a hub (uadj_h null: no hubs)
+__device__ inline void adj_put(int64_t pos, int32_t y, const int32_t *__restrict__ hub_of, int32_t *__restrict__ uadj,
+                               int32_t *__restrict__ uadj_h) {
+    uadj[pos] = y;
+    if (uadj_h) {
+        const int32_t h = hub_of[y];
+        uadj_h[pos] = h >= 0 ? (int32_t)(HUB_FLAG | (uint32_t)h) : y;
+    }
+}
+
 __global__ void k_adj_fill_up(const int32_t *__restrict__ slo, const int32_t *__restrict__ shi, int32_t S,
-                              const int32_t *__restrict__ hoff, int32_t *__restrict__ uadj) {
+                              const int32_t *__restrict__ hoff, const int32_t *__restrict__ hub_of,
+                              int32_t *__restrict__ uadj, int32_t *__restrict__ uadj_h) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < S) uadj[(int64_t)hoff[slo[e] + 1] + e] = shi[e];
+    if (e < S) adj_put((int64_t)hoff[slo[e] + 1] + e, shi[e], hub_of, uadj, uadj_h);
 }
 
 // sorted position q (hi = hkey[q], lo = hval[q]) in hi's row: at
 // uoff[hi] + (q - hoff[hi]) = loff[hi] + q
 __global__ void k_adj_fill_down(const int32_t *__restrict__ hkey, const int32_t *__restrict__ hval, int32_t S,
-                                const int32_t *__restrict__ loff, int32_t *__restrict__ uadj) {
+                                const int32_t *__restrict__ loff, const int32_t *__restrict__ hub_of,
+                                int32_t *__restrict__ uadj, int32_t *__restrict__ uadj_h) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < S) uadj[(int64_t)loff[hkey[q]] + q] = hval[q];
+    if (q < S) adj_put((int64_t)loff[hkey[q]] + q, hval[q], hub_of, uadj, uadj_h);
 }
 
 // hubs of the peeling adjacency: vertices of degree > HUB_DEG, first HUB_SLOTS found
@@ -733,16 +746,6 @@ __global__ void k_find_hubs(const int32_t *__restrict__ deg, int32_t n, int32_t 
         hub_of[x] = slot;
         hub_vertex[slot] = (int32_t)x;
     }
-}
-
-// the peeling adjacency of large rounds: hub neighbours as HUB_FLAG | slot
-__global__ void k_mark_hubs(const int32_t *__restrict__ uadj, int64_t E, const int32_t *__restrict__ hub_of,
-                            int32_t *__restrict__ uadj_h) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= E) return;
-    const int32_t y = uadj[i];
-    const int32_t h = hub_of[y];
-    uadj_h[i] = h >= 0 ? (int32_t)(HUB_FLAG | (uint32_t)h) : y;
 }
 
 __global__ void k_adj_deg(const int64_t *__restrict__ uoff, int32_t n, int32_t *__restrict__ deg) {
@@ -1029,6 +1032,11 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     DevBuf uoff, uadj, uadj_h;
     uoff.ensure(8 * ((size_t)n + 1));
     uadj.ensure(8 * (size_t)S + 8);
+    DevBuf hub_of, hub_vertex, hub_n;
+    hub_of.ensure(4 * (size_t)n);
+    hub_vertex.ensure(4 * (size_t)HUB_SLOTS);
+    hub_n.ensure(4);
+    int32_t n_hubs = 0;
     {
         DevBuf hkey, hval, loff, hoff;
         hkey.ensure(4 * (size_t)S + 4);
@@ -1045,23 +1053,9 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         k_adj_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), hkey.as<int32_t>(), S, n,
                                                                  loff.as<int32_t>(), hoff.as<int32_t>(),
                                                                  uoff.as<int64_t>());
-        FOLTY_LAUNCHED();
-        if (S > 0) {
-            k_adj_fill_up<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
-                                                           hoff.as<int32_t>(), uadj.as<int32_t>());
-            k_adj_fill_down<<<grid_for(S, BLK), BLK, 0, s>>>(hkey.as<int32_t>(), hval.as<int32_t>(), S,
-                                                             loff.as<int32_t>(), uadj.as<int32_t>());
-            FOLTY_LAUNCHED();
-        }
         k_adj_deg<<<grid_for(n, BLK), BLK, 0, s>>>(uoff.as<int64_t>(), n, ix.deg.as<int32_t>());
         FOLTY_LAUNCHED();
-    }
-    DevBuf hub_of, hub_vertex, hub_n;
-    hub_of.ensure(4 * (size_t)n);
-    hub_vertex.ensure(4 * (size_t)HUB_SLOTS);
-    hub_n.ensure(4);
-    int32_t n_hubs = 0;
-    {
+        // the hubs first, so that each fill writes the plain row and the flagged copy together
         FOLTY_HIP(hipMemsetAsync(hub_n.p, 0, 4, s));
         k_find_hubs<<<grid_for(n, BLK), BLK, 0, s>>>(ix.deg.as<int32_t>(), n, hub_of.as<int32_t>(),
                                                     hub_vertex.as<int32_t>(), hub_n.as<int32_t>());
@@ -1070,10 +1064,15 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         FOLTY_HIP(hipStreamSynchronize(s));
         n_hubs = *hb.as<int32_t>();
         if (n_hubs > HUB_SLOTS) n_hubs = HUB_SLOTS;
-        if (n_hubs > 0 && S > 0) {
-            uadj_h.ensure(8 * (size_t)S + 8);
-            k_mark_hubs<<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(uadj.as<int32_t>(), 2 * (int64_t)S,
-                                                                     hub_of.as<int32_t>(), uadj_h.as<int32_t>());
+        if (n_hubs > 0 && S > 0) uadj_h.ensure(8 * (size_t)S + 8);
+        int32_t *flagged = n_hubs > 0 && S > 0 ? uadj_h.as<int32_t>() : nullptr;
+        if (S > 0) {
+            k_adj_fill_up<<<grid_for(S, BLK), BLK, 0, s>>>(ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), S,
+                                                           hoff.as<int32_t>(), hub_of.as<int32_t>(),
+                                                           uadj.as<int32_t>(), flagged);
+            k_adj_fill_down<<<grid_for(S, BLK), BLK, 0, s>>>(hkey.as<int32_t>(), hval.as<int32_t>(), S,
+                                                             loff.as<int32_t>(), hub_of.as<int32_t>(),
+                                                             uadj.as<int32_t>(), flagged);
             FOLTY_LAUNCHED();
         }
     }

@@ -153,6 +153,7 @@ struct ThreshArgs {
     int32_t m;
     uint32_t num, den;
     int universe, excl;
+    int zero_never;                  // theta > 0 and |U| >= 1 for every edge: count 0 never certifies
     uint32_t *ncert;                 // [2S]: 2 s + dir
     unsigned long long *total;       // certificates
 };
@@ -163,6 +164,10 @@ __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
     bool in = k < A.m;
     int64_t key = -1;
     bool cert = false;
+    const uint32_t cnt = in ? A.count[k] : 0u;
+    // a wavefront whose edges all count 0 has no certificate when 0 cannot
+    // reach theta * |U| (its lanes stay out of every run below)
+    if (A.zero_never && !__ballot(cnt != 0u)) in = false;
     if (in) {
         int32_t s = A.sid[k];
         int dir = k >= A.smid[s] ? 1 : 0;
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
         if (A.universe == FOLTY_UNIVERSE_DST) U = (int64_t)A.deg[b] - A.excl;
         else if (A.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)A.deg[a] - A.excl;
         else U = A.tcnt[s];
-        cert = (uint64_t)A.count[k] * A.den >= (uint64_t)A.num * (uint64_t)U;
+        cert = (uint64_t)cnt * A.den >= (uint64_t)A.num * (uint64_t)U;
         key = 2 * (int64_t)s + dir;
     }
     // segmented count of certificates over runs of equal keys inside the wave
@@ -394,6 +399,9 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
         A.den = q.theta_den;
         A.universe = q.universe;
         A.excl = q.exclude_other ? 1 : 0;
+        // N(b) and N(a) hold the other endpoint, so |U| >= 1 unless it is left out
+        A.zero_never = q.theta_num > 0 && !q.exclude_other &&
+                       (q.universe == FOLTY_UNIVERSE_DST || q.universe == FOLTY_UNIVERSE_SRC);
         A.ncert = ws.ncert.as<uint32_t>();
         A.total = total;
         k_threshold<<<grid_for(m, BLK), BLK, 0, s>>>(A);
