@@ -345,9 +345,9 @@ enum FilterMode {
 // Keeps triangles with at least one run that can count, with each survivor's
 // test offset inside its item.  Every run uses one list of each of the three
 // edges, and its three timestamps lie within dmax of each other, so the edges'
-// time ranges must pairwise come within dmax: the two edges at u are tested
-// first, the third edge's range next (8 bytes each), and only then are the three
-// edge records read.  The enumeration order inside an item is fixed, so a
+// time ranges must pairwise come within dmax: the two ranges loaded before the
+// exact search are tested first, the third edge's range is loaded only if they
+// meet (8 bytes each), and only then are the three edge records read.  The enumeration order inside an item is fixed, so a
 // counting pass and a later emitting pass agree on every survivor's position.
 // VAR < 0: the predicate code is read from `variant` at run time
 template <int VAR, int MODE> struct FilterSink {
@@ -385,10 +385,10 @@ template <int VAR, int MODE> struct FilterSink {
     __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
         if constexpr (MODE == FILTER_COUNT) nhit += (unsigned long long)__popcll(__ballot(h));
         int64_t wk = 0;
-        if (h) {
-            const uint2 rb = pkb ? prk : rng[b];
-            const uint2 rc = pkb ? rng[c] : prk;
-            if (ranges_meet(pra, rb, dq) && ranges_meet(pra, rc, dq) && ranges_meet(rb, rc, dq)) {
+        // the two ranges loaded ahead first; the third edge's only if they meet
+        if (h && ranges_meet(pra, prk, dq)) {
+            const uint2 r3 = rng[pkb ? c : b];
+            if (ranges_meet(pra, r3, dq) && ranges_meet(prk, r3, dq)) {
                 if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists<false>(rec, a, b, c), run_slack(dq));
                 else wk = tri_work_rt(variant, load_lists<false>(rec, a, b, c), run_slack(dq));
             }
@@ -478,11 +478,11 @@ struct PairFilterSink {
     }
     __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
         bool p0 = false, p1 = false;
-        if (h) {
-            const uint2 rb = pkb ? prk : rng[b];
-            const uint2 rc = pkb ? rng[c] : prk;
-            p0 = ranges_meet(pra, rb, f[0].dq) && ranges_meet(pra, rc, f[0].dq) && ranges_meet(rb, rc, f[0].dq);
-            p1 = ranges_meet(pra, rb, f[1].dq) && ranges_meet(pra, rc, f[1].dq) && ranges_meet(rb, rc, f[1].dq);
+        const int64_t dq = f[0].dq > f[1].dq ? f[0].dq : f[1].dq;
+        if (h && ranges_meet(pra, prk, dq)) {
+            const uint2 r3 = rng[pkb ? c : b];
+            p0 = ranges_meet(pra, prk, f[0].dq) && ranges_meet(pra, r3, f[0].dq) && ranges_meet(prk, r3, f[0].dq);
+            p1 = ranges_meet(pra, prk, f[1].dq) && ranges_meet(pra, r3, f[1].dq) && ranges_meet(prk, r3, f[1].dq);
         }
         keep<0>(p0, a, b, c);
         keep<1>(p1, a, b, c);
