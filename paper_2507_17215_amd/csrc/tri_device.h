@@ -13,7 +13,7 @@ constexpr int WPB = BLK / 64;         // wavefronts per block
 constexpr int CAP = 512;              // N+(u) staged in LDS up to this length
 constexpr int IPT = 8;                // temporal tests per chunk
 constexpr int PERSIST_BLOCKS = 4096;
-constexpr int ENUM_BLOCKS = 4096;
+constexpr int ENUM_BLOCKS = 32768; // 8 x the resident blocks: about a dozen items per wavefront, balanced by the dispatcher
 constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item (about; whole segments)
 
 __device__ inline int lane_id() { return __lane_id(); }
