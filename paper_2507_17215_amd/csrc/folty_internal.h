@@ -217,7 +217,7 @@ struct Workspace {
     DevBuf pairs_v2;
     DevBuf scal;    // small device scalars
     DevBuf cub;     // library scan/sort temporaries
-    DevBuf hist;    // uint32[levels * m] multi-window counts
+    DevBuf ilist;   // int32[NI] items with survivors
     PinnedBuf host;
     hipEvent_t ev[8] = {};
     bool events = false;

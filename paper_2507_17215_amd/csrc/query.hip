@@ -266,8 +266,18 @@ unsigned enum_grid(int32_t n) {
 // instead.  e0 and e1 bracket the (first) enumeration launch alone, so its
 // duration is measured on the stream it runs on.  Returns the number of
 // survivors (an upper bound in the one-pass case); *tri gets the triangle count.
+// the items with at least one survivor (any order: each item writes its own slots)
+__global__ void k_item_list(const int32_t *__restrict__ su, int32_t NI, int32_t *__restrict__ list,
+                            int32_t *__restrict__ nlist) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool take = it < NI && su[it] > 0;
+    const int32_t slot = wave_append(nlist, take);
+    if (take) list[slot] = (int32_t)it;
+}
+
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1, int64_t *tri) {
+                       hipEvent_t e1, int64_t *tri, int64_t *tests) {
+    *tests = -1; // known on the host only after the two-pass filter
     const int32_t NI = ix.NI;
     ws.su.ensure(4 * ((size_t)NI + 1));
     ws.wu.ensure(8 * ((size_t)NI + 1));
@@ -292,14 +302,15 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
         sink.hits = hits;
         return sink;
     };
-    auto run = [&](auto V, auto M, const int32_t *only) {
+    // all items, or the nlist items of list
+    auto run = [&](auto V, auto M, const int32_t *list, int32_t nlist) {
         auto sink = sink_for(V, M);
+        const unsigned g = enum_grid(list ? nlist : NI);
         if (ix.tri_cached)
-            k_filter_cached<<<enum_grid(NI), BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI, sink,
-                                                          only);
+            k_filter_cached<<<g, BLK, 0, s>>>(ix.tri_base.as<int64_t>(), ix.tri.as<int32_t>(), NI, sink, list, nlist);
         else
-            k_tri_enum<<<enum_grid(NI), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(), ix.seg.as<int4>(),
-                                                     NI, sink, only);
+            k_tri_enum<<<g, BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(), ix.seg.as<int4>(), NI, sink,
+                                         list, nlist);
         FOLTY_LAUNCHED();
     };
     using CountM = std::integral_constant<int, FILTER_COUNT>;
@@ -333,7 +344,7 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
     }
     ws.slots = ws.sbase.as<int64_t>();
     FOLTY_HIP(hipEventRecord(e0, s));
-    dispatch_variant(variant, [&](auto V) { run(V, CountM{}, nullptr); });
+    dispatch_variant(variant, [&](auto V) { run(V, CountM{}, nullptr, 0); });
     FOLTY_HIP(hipEventRecord(e1, s));
     // su[NI] = wu[NI] = 0 so that the exclusive scans leave the totals at [NI]
     k_fill<int32_t><<<1, 1, 0, s>>>(ws.su.as<int32_t>() + NI, 0, 1);
@@ -345,27 +356,45 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
     ws.cub.ensure(need);
     exclusive_scan_i64(ws.cub.p, need, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
     exclusive_scan_i32_to_i64(ws.cub.p, need, ws.su.as<int32_t>(), ws.sbase.as<int64_t>(), (int64_t)NI + 1, s);
+    // the items with survivors, for the emitting pass
+    ws.ilist.ensure(4 * ((size_t)NI + 1));
+    int32_t *nlist = reinterpret_cast<int32_t *>(ws.scal.as<unsigned long long>() + 9);
+    k_fill<int32_t><<<1, 1, 0, s>>>(nlist, 0, 1);
+    k_item_list<<<grid_for(NI, BLK), BLK, 0, s>>>(ws.su.as<int32_t>(), NI, ws.ilist.as<int32_t>(), nlist);
+    FOLTY_LAUNCHED();
     int64_t *h = ws.host.as<int64_t>();
+    h[3] = 0;
     FOLTY_HIP(hipMemcpyAsync(h, ws.sbase.as<int64_t>() + NI, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(h + 3, nlist, 4, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipMemcpyAsync(h + 1, hits, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(h + 2, ws.wbase.as<int64_t>() + NI, 8, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
     const int64_t survivors = h[0];
     *tri = h[1];
+    *tests = h[2];
     if (survivors > 0) {
         ws.sv.ensure(12 * (size_t)survivors);
         ws.sw.ensure(8 * (size_t)survivors);
-        dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.su.as<int32_t>()); });
+        const int32_t nl = (int32_t)h[3];
+        dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.ilist.as<int32_t>(), nl); });
     }
     return survivors;
 }
 
+// tests < 0: unknown on the host, the full persistent grid; else a thread per
+// chunk, and chunks of one test when there are few (each chunk's searches are a
+// chain of dependent loads, so few tests are done fastest all at once)
 template <class Op>
-void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, hipStream_t s) {
+void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, int64_t tests,
+                     hipStream_t s) {
+    const int ipt = tests >= 0 && tests < (int64_t)PERSIST_BLOCKS * BLK ? 1 : IPT;
+    const int64_t want = tests < 0 ? PERSIST_BLOCKS : ((tests + ipt - 1) / ipt + BLK - 1) / BLK;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PERSIST_BLOCKS));
     dispatch_variant(variant, [&](auto V) {
-        k_temporal<decltype(V)::value, Op><<<PERSIST_BLOCKS, BLK, 0, s>>>(
+        k_temporal<decltype(V)::value, Op><<<blocks, BLK, 0, s>>>(
             ws.wbase.as<int64_t>(), ix.NI, ws.slots, ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
             ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(),
-            run_slack(range_slack(dmax, ix.tshift)), op, IPT);
+            run_slack(range_slack(dmax, ix.tshift)), op, ipt);
     });
     FOLTY_LAUNCHED();
 }
@@ -639,10 +668,11 @@ Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t 
     }
     int64_t tests = 0, tri = 0;
     if (ix.NI > 0) {
-        const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri);
+        int64_t known = -1;
+        const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known);
         if (survivors > 0) {
             DirectOp op{q.delta, count};
-            launch_temporal(ix, q.variant, q.delta, ws, op, s);
+            launch_temporal(ix, q.variant, q.delta, ws, op, known, s);
             FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
         }
     } else {

@@ -749,26 +749,26 @@ __device__ inline void cached_item(const int64_t *__restrict__ base, const int32
     sink.end(it);
 }
 
-// Waves per SIMD the compiler must fit a sink's enumeration into: the query's
-// counting filter is held to 72 VGPRs (7 waves); the others keep their own size.
+// Waves per SIMD the compiler must fit a sink's enumeration into (a floor): at
+// least 7 (72 VGPRs) for the query's counting filter; the others keep their size.
 template <class S> struct enum_waves { static constexpr int value = 4; };
 template <int V> struct enum_waves<FilterSink<V, FILTER_COUNT> > { static constexpr int value = 7; };
 
-// One wavefront per item; only != nullptr: items with only[it] == 0 are skipped
+// One wavefront per item; list != nullptr: only the nlist items list[0..nlist)
 template <class Sink>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(enum_waves<Sink>::value))) void k_tri_enum(const EnumItem *__restrict__ items, const int32_t *__restrict__ oadj,
                                                   const int4 *__restrict__ seg, int32_t NI, Sink sink,
-                                                  const int32_t *__restrict__ only = nullptr) {
+                                                  const int32_t *__restrict__ list = nullptr, int32_t nlist = 0) {
     __shared__ EnumLds lds[WPB];
     const int w = wave_id();
     const int64_t stride = (int64_t)gridDim.x * WPB;
     int64_t it = (int64_t)blockIdx.x * WPB + w;
-    if (only) {
-        // a pass over a few marked items: no loads ahead for the skipped ones
-        for (; it < NI; it += stride) {
-            if (only[it] == 0) continue;
-            const EnumItem item = items[it];
-            enum_item(item, stage_ahead(item, oadj, seg), oadj, seg, it, sink, lds[w]);
+    if (list) {
+        // a pass over a few listed items
+        for (; it < nlist; it += stride) {
+            const int64_t li = list[it];
+            const EnumItem item = items[li];
+            enum_item(item, stage_ahead(item, oadj, seg), oadj, seg, li, sink, lds[w]);
         }
         sink.finish();
         return;
@@ -794,12 +794,11 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(enum_waves<
 template <int VAR, int MODE>
 __global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict__ base, const int32_t *__restrict__ tri,
                                                        int32_t NI, FilterSink<VAR, MODE> sink,
-                                                       const int32_t *__restrict__ only = nullptr) {
+                                                       const int32_t *__restrict__ list = nullptr, int32_t nlist = 0) {
     const int w = wave_id();
-    for (int64_t it = (int64_t)blockIdx.x * WPB + w; it < NI; it += (int64_t)gridDim.x * WPB) {
-        if (only && only[it] == 0) continue;
-        cached_item(base, tri, it, sink);
-    }
+    const int64_t n = list ? nlist : NI;
+    for (int64_t i = (int64_t)blockIdx.x * WPB + w; i < n; i += (int64_t)gridDim.x * WPB)
+        cached_item(base, tri, list ? (int64_t)list[i] : i, sink);
     sink.finish();
 }
 
