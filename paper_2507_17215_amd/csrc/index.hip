@@ -61,6 +61,15 @@ __global__ void k_validate(const int32_t *__restrict__ src, const int32_t *__res
         if (ok && (unsigned long long)ti > tmax) tmax = (unsigned long long)ti;
         if (i > 0 && t[i - 1] > ti) desc++;
     }
+    // one atomic per wavefront and quantity
+    for (int o = 32; o > 0; o >>= 1) {
+        loops += __shfl_xor(loops, o);
+        desc += __shfl_xor(desc, o);
+        const unsigned long long tm = __shfl_xor(tmax, o), bd = __shfl_xor(bad, o);
+        tmax = tm > tmax ? tm : tmax;
+        bad = bd < bad ? bd : bad;
+    }
+    if (lane_id() != 0) return;
     if (loops) atomicAdd(&out->loops, loops);
     if (desc) atomicAdd(&out->descents, desc);
     if (tmax) atomicMax(&out->tmax, tmax);
