@@ -194,7 +194,10 @@ def serving_section(folty, synth, full):
         t0 = time.perf_counter()
         th = threading.Thread(target=submit)
         th.start()
-        th.join()
+        while th.is_alive():
+            th.join(timeout=30.0)
+            if th.is_alive():
+                log(f"serving {rate} q/s: {sum(t is not None for t in tickets)} of {per_rate} submitted")
         res = [srv.wait(t) for t in tickets]
         wall = time.perf_counter() - t0
         lat = np.array([r.stats["latency_ms"] for r in res])
@@ -210,6 +213,32 @@ def serving_section(folty, synth, full):
             f"achieved {per_rate / wall:.0f} q/s, mean batch {bs.mean():.2f}, same as alone: {same}")
     out["server"] = srv.info()
     srv.close()
+    if full:
+        # the same mix under a 16 GB device budget: requests wait for admission
+        srv = folty.Server(workers=4, max_batch=16, hbm_budget_bytes=16 << 30)
+        n_req = 500
+        reqs = [(int(rng.integers(0, len(Gs))),
+                 dict(delta=int(rng.choice(pool)), theta=(int(rng.integers(1, 10)), 10),
+                      variant=int(rng.choice([0, 3])), counts=False)) for _ in range(n_req)]
+        t0 = time.perf_counter()
+        tickets = [srv.submit(Gs[gi], **q) for gi, q in reqs]
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        lat = np.array([r.stats["latency_ms"] for r in res])
+        qwait = np.array([r.stats["queue_ms"] for r in res])
+        pick = rng.choice(n_req, size=20, replace=False)
+        same = all(res[i].pairs() == Gs[reqs[i][0]].query(**reqs[i][1]).pairs() for i in pick)
+        info = srv.info()
+        srv.close()
+        out["budget_16GiB"] = {"requests": n_req, "submitted_at_once": True,
+                               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                               "queue_p50_ms": float(np.percentile(qwait, 50)),
+                               "queue_p99_ms": float(np.percentile(qwait, 99)),
+                               "achieved_queries_per_s": n_req / wall, "same_as_alone": same, "server": info}
+        log(f"serving under a 16 GiB budget: {n_req} requests at once, p50 {np.percentile(lat, 50):.2f} ms, "
+            f"p99 {np.percentile(lat, 99):.2f} ms, queue p99 {np.percentile(qwait, 99):.2f} ms, "
+            f"{n_req / wall:.0f} q/s, peak in use {info['peak_in_use_bytes'] / 2**30:.1f} GiB, "
+            f"rejected {info['rejected']}, same as alone: {same}")
     return out
 
 
