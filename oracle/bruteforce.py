@@ -77,3 +77,38 @@ def query(n, src, dst, t, delta, theta_num, theta_den, variant=0, universe=0,
     keys = sorted(pairs)
     return dict(pairs=[(a, b, pairs[(a, b)]) for a, b in keys], n_certificates=ncert,
                 counts=cnt)
+
+
+def vertex_query(n, src, dst, t, delta, theta_num, theta_den, variant=0, inner_forall=True,
+                 inner_num=0, inner_den=1, universe=0, exclude_other=False):
+    """exists u forall_theta v in N(u) (forall_inner | exists) w, by the definitions:
+    u is a solution when N(u) is not empty and at least theta * |N(u)| of its
+    neighbours v have a temporal edge (u, v, t) that certifies the inner query
+    (count >= inner * |U(e)|, or count >= 1 for an inner exists)."""
+    cnt = counts(n, src, dst, t, delta, variant)
+    nb = neighbours(n, src, dst)
+    ok_pairs = set()
+    for i, (a, b) in enumerate(zip(src, dst)):
+        a, b = int(a), int(b)
+        if a == b:
+            continue
+        if inner_forall:
+            if universe == 0:
+                U = len(nb[b]) - (1 if exclude_other else 0)
+            elif universe == 1:
+                U = len(nb[a]) - (1 if exclude_other else 0)
+            else:
+                U = len(nb[a] & nb[b])
+            ok = cnt[i] * inner_den >= inner_num * U
+        else:
+            ok = cnt[i] >= 1
+        if ok:
+            ok_pairs.add((a, b))
+    out = []
+    for u in range(n):
+        if not nb[u]:
+            continue
+        good = sum(1 for v in nb[u] if (u, v) in ok_pairs)
+        if good * theta_den >= theta_num * len(nb[u]):
+            out.append((u, good))
+    return out

@@ -15,6 +15,15 @@ endpoint from N(b) / N(a).
 Solutions (paper, Definition of a solution): the pairs (a, b) with at least one
 certificate on them, listed in (a, b) order with their certificate counts;
 n_certificates is |Sol|.
+
+Vertex queries (paper, Section on the exists-forall-forall and exists-forall-
+exists queries): exists u forall_{theta1} v in N(u) forall_{theta2} w, and
+exists u forall_{theta} v in N(u) exists w.  ``vertex_query`` follows the
+section's algorithm step by step: the edge-level solutions L (certificates of the
+exists-exists-forall query at theta2, or the edges with count >= 1 for the
+inner exists), the per-vertex marks L_u[v] for every e = (u, v, t) in L, their
+sums over N(u), and the threshold sum >= theta1 * |N(u)| for the vertices whose
+neighbourhood is not empty (the last step runs over N(u)).
 """
 from __future__ import annotations
 
@@ -192,3 +201,28 @@ class Oracle:
         return dict(pair_u=(uk // self.n).astype(np.int32), pair_v=(uk % self.n).astype(np.int32),
                     n_cert=nc.astype(np.uint32), n_certificates=int(cert.sum()),
                     counts=cnt, self_loops=int(loop.sum()))
+
+    def vertex_query(self, delta: int, theta_num: int, theta_den: int, variant: int = 0,
+                     inner_forall: bool = True, inner_num: int = 0, inner_den: int = 1,
+                     universe: int = 0, exclude_other: bool = False, counts=None) -> dict:
+        """Solution vertices of exists u forall_{theta} v (forall_{inner} | exists) w."""
+        if theta_den <= 0 or theta_num < 0 or theta_num > theta_den:
+            raise ValueError("theta must be num/den in [0, 1]")
+        cnt = self.counts(delta, variant) if counts is None else counts
+        # step 1: the edge-level solutions L
+        if inner_forall:
+            q = self.query(delta, inner_num, inner_den, variant, universe, exclude_other, counts=cnt)
+            head, tail = q["pair_u"], q["pair_v"]
+        else:
+            keep = (self.src != self.dst) & (cnt != U32_MAX) & (cnt >= 1)
+            keys = np.unique(self.src[keep].astype(np.int64) * self.n + self.dst[keep].astype(np.int64))
+            head, tail = (keys // self.n).astype(np.int32), (keys % self.n).astype(np.int32)
+        # steps 2-4: L_u[v] = 1 for every (u, v) with an edge of L from u to v; sums per u
+        good = np.zeros(self.n, dtype=np.int64)
+        np.add.at(good, head, 1)
+        # step 5: threshold against |N(u)| over non-empty neighbourhoods
+        deg = self.degrees().astype(np.int64)
+        sol = (deg >= 1) & (good * theta_den >= theta_num * deg)
+        v = np.nonzero(sol)[0].astype(np.int32)
+        return dict(vertices=v, good=good[v].astype(np.uint32), n_vertices=int(v.size),
+                    pair_u=head, pair_v=tail, counts=cnt)

@@ -267,3 +267,61 @@ def test_bad_arguments_rejected():
         o.query(5, 3, 2)
     with pytest.raises(ValueError):
         Oracle(3, np.array([0, 3], np.int32), np.array([1, 1], np.int32), np.array([0, 0]))
+
+
+# -- vertex queries (exists-forall-forall, exists-forall-exists) ----------------------
+def _vertex_cases():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "vertex_cases.json")) as f:
+        return json.load(f)
+
+
+def test_vertex_hand_cases():
+    d = _vertex_cases()
+    g = d["graph"]
+    e = np.array(g["edges"], dtype=np.int64)
+    o = Oracle(g["n"], e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2])
+    for c in d["cases"]:
+        inner = c["inner"] == "forall"
+        n2, d2 = c.get("inner_theta", [0, 1])
+        r = o.vertex_query(c["delta"], c["theta"][0], c["theta"][1], 0, inner, n2, d2)
+        assert r["vertices"].tolist() == c["vertices"], c
+        assert r["good"].tolist() == c["good"], c
+
+
+def test_vertex_queries_match_bruteforce():
+    rng = np.random.default_rng(31)
+    for it in range(40):
+        n = int(rng.integers(4, 14))
+        m = int(rng.integers(3, 40))
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        t = rng.integers(0, 30, m).astype(np.int64)
+        o = Oracle(n, src, dst, t)
+        for variant in (0, 3, 6):
+            delta = int(rng.choice([0, 3, 10, 100]))
+            inner = bool(rng.integers(0, 2))
+            n1 = int(rng.integers(0, 5))
+            n2 = int(rng.integers(0, 5))
+            universe = int(rng.integers(0, 3))
+            want = bf.vertex_query(n, src, dst, t, delta, n1, 4, variant, inner, n2, 4, universe)
+            r = o.vertex_query(delta, n1, 4, variant, inner, n2, 4, universe)
+            assert list(zip(r["vertices"].tolist(), r["good"].tolist())) == want, (it, variant, inner)
+
+
+def test_vertex_theta_zero_and_nesting():
+    g = synth.tiny(seed=4)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    deg = o.degrees()
+    cnt = o.counts(86400, 0)
+    r0 = o.vertex_query(86400, 0, 1, 0, False, counts=cnt)
+    assert r0["vertices"].tolist() == np.nonzero(deg >= 1)[0].tolist()
+    prev = set(r0["vertices"].tolist())
+    for th in (1, 2, 5, 9, 10):
+        cur = set(o.vertex_query(86400, th, 10, 0, False, counts=cnt)["vertices"].tolist())
+        assert cur <= prev
+        prev = cur
+    # with theta2 > 0 on N(b) (|N(b)| >= 1) a certificate has count >= 1, so the
+    # inner-forall solutions are a subset of the inner-exists ones
+    ex = set(o.vertex_query(86400, 1, 10, 0, False, counts=cnt)["vertices"].tolist())
+    fa = set(o.vertex_query(86400, 1, 10, 0, True, 1, 10, counts=cnt)["vertices"].tolist())
+    assert fa <= ex
