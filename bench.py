@@ -383,6 +383,32 @@ def main():
                                "oracle_nonzero": int((want > 0).sum()), "mismatches": bad}
             log(f"parity delta={d}: {bad} mismatches over {idx.size} edges ({sample.size} uniform + "
                 f"{nz.size} the GPU counts as non-zero; oracle non-zero: {int((want > 0).sum())})")
+        # vertex queries (exists-forall-forall, exists-forall-exists) on the same
+        # index, one-year window; checked against the oracle on sampled vertices
+        # (each decided from the counts of its own outgoing edges)
+        vq = {}
+        outdeg = np.bincount(g.src[g.src != g.dst], minlength=n)
+        small = np.nonzero((outdeg >= 1) & (outdeg <= 2000))[0]
+        for name, inner in (("exists_forall_forall", folty.INNER_FORALL), ("exists_forall_exists", folty.INNER_EXISTS)):
+            rv = G.vertex_query(synth.YEAR_S, (1, 10), inner, (1, 10), 0, counts=False)
+            verts, good = rv.vertices()
+            pick = np.union1d(rng.choice(small, size=min(200, small.size), replace=False),
+                              rng.choice(np.intersect1d(verts, small), size=min(200, np.intersect1d(verts, small).size),
+                                         replace=False) if verts.size else np.zeros(0, np.int64))
+            w = oracle.vertex_query_at(pick, synth.YEAR_S, 1, 10, 0, inner == folty.INNER_FORALL, 1, 10)
+            gpu_sol = np.isin(w["vertices"], verts)
+            gmap = dict(zip(verts.tolist(), good.tolist()))
+            bad = int((gpu_sol != w["solution"]).sum()) + sum(
+                1 for u, s_, gd in zip(w["vertices"].tolist(), w["solution"].tolist(), w["good"].tolist())
+                if s_ and gmap.get(u) != gd)
+            ok = ok and bad == 0
+            vq[name] = {"delta": synth.YEAR_S, "theta": "1/10", "inner_theta": "1/10" if inner == folty.INNER_FORALL else None,
+                        "solution_vertices": int(verts.size), "query_ms": rv.stats["query_ms"],
+                        "threshold_ms": rv.stats["threshold_ms"], "checked_vertices": int(pick.size),
+                        "oracle_edges_counted": w["edges_counted"], "mismatches": bad}
+            log(f"{name}: {verts.size} solution vertices in {rv.stats['query_ms']:.2f} ms; "
+                f"{bad} mismatches over {pick.size} sampled vertices ({w['edges_counted']} edges counted by the oracle)")
+        out["vertex_queries"] = vq
         G.close()
         out["parity_sampled"] = {"bit_exact": ok, "deltas": checked}
         # the same index queried at wider windows (device times; per-edge counts kept)

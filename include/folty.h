@@ -178,6 +178,38 @@ int folty_build_index(folty_graph *g, const folty_build_opts *opts);
  */
 int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out);
 
+/*
+ * Vertex queries (paper, Section on the exists-forall-forall and
+ * exists-forall-exists queries; a solution is a single vertex, Definition of a
+ * solution):
+ *   inner = FOLTY_INNER_FORALL:  exists u  forall_theta v in N(u)  forall_theta2 w  phi(u, v, w)
+ *   inner = FOLTY_INNER_EXISTS:  exists u  forall_theta v in N(u)  exists w  phi(u, v, w)
+ * A vertex u with at least one neighbour is a solution when at least
+ * theta * |N(u)| of its neighbours v (compared exactly: good * theta_den >=
+ * theta_num * |N(u)|) have a temporal edge e = (u, v, t), from u to v, that
+ * solves the inner query on the edges: a certificate of the exists-exists-forall
+ * query `edge` (its theta = theta2, universe and exclude_other), or, for the
+ * inner exists, an edge with count[e] >= 1.  edge.delta and edge.variant give
+ * the window and the predicate; with FOLTY_INNER_EXISTS edge.theta_* are not
+ * read.  Vertices without neighbours are never solutions (the section's last
+ * step runs over N(u)).
+ * The result holds the solution vertices (folty_result_vertices), the directed
+ * pairs (u, v) with a qualifying edge from u to v and the number of such edges
+ * on each (folty_result_pairs), their total (folty_result_counts) and, unless
+ * edge.flags has FOLTY_QUERY_NO_COUNTS, the per-edge counts.
+ */
+enum { FOLTY_INNER_FORALL = 0, FOLTY_INNER_EXISTS = 1 };
+
+typedef struct {
+    folty_query edge;      /* the query on the edges (see above) */
+    uint32_t theta_num;    /* outer threshold over N(u): theta_num <= theta_den */
+    uint32_t theta_den;    /* > 0 */
+    uint8_t inner;         /* FOLTY_INNER_* */
+    uint8_t reserved[7];   /* must be 0 */
+} folty_vertex_query;
+
+int folty_run_vertex_query(folty_graph *g, const folty_vertex_query *q, folty_result **out);
+
 /* The same with caller-owned scratch memory, for concurrent queries on one
  * graph from several threads (one workspace per thread). */
 int folty_workspace_create(folty_workspace **out);
@@ -280,6 +312,14 @@ int folty_result_pairs(const folty_result *r, int64_t *n_pairs, const int32_t **
  * counts are copied from the device on the first call.
  */
 int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t **edge_count);
+
+/*
+ * Solution vertices of a vertex query in ascending id order, and for each the
+ * number of its neighbours v with a qualifying edge from it to v.  Host
+ * pointers, valid until folty_result_free; *n_vertices = 0 for a pair query.
+ */
+int folty_result_vertices(const folty_result *r, int64_t *n_vertices, const int32_t **vertices,
+                          const uint32_t **good);
 
 int folty_result_stats(const folty_result *r, folty_stats *s);
 void folty_result_free(folty_result *r);

@@ -226,3 +226,27 @@ class Oracle:
         v = np.nonzero(sol)[0].astype(np.int32)
         return dict(vertices=v, good=good[v].astype(np.uint32), n_vertices=int(v.size),
                     pair_u=head, pair_v=tail, counts=cnt)
+
+    def vertex_query_at(self, us, delta: int, theta_num: int, theta_den: int, variant: int = 0,
+                        inner_forall: bool = True, inner_num: int = 0, inner_den: int = 1,
+                        universe: int = 0, exclude_other: bool = False) -> dict:
+        """The vertex query decided for the vertices us only: a vertex's answer
+        depends on the counts of its own outgoing edges alone, so those are the
+        only edges counted (for checks on graphs too large to count whole)."""
+        us = np.unique(np.asarray(us, dtype=np.int64))
+        idx = np.nonzero(np.isin(self.src, us) & (self.src != self.dst))[0]
+        cnt = self.counts(delta, variant, idx)
+        if inner_forall:
+            if theta_den <= 0 or inner_den <= 0 or inner_num > inner_den:
+                raise ValueError("theta")
+            ok = cnt.astype(np.uint64) * np.uint64(inner_den) >= \
+                self.universe_sizes(idx, universe, exclude_other).astype(np.uint64) * np.uint64(inner_num)
+        else:
+            ok = cnt >= 1
+        keys = np.unique(self.src[idx[ok]].astype(np.int64) * self.n + self.dst[idx[ok]].astype(np.int64))
+        good = np.zeros(self.n, dtype=np.int64)
+        np.add.at(good, keys // self.n, 1)
+        deg = self.degrees().astype(np.int64)
+        sol = (deg[us] >= 1) & (good[us] * theta_den >= theta_num * deg[us])
+        return dict(vertices=us.astype(np.int32), solution=sol, good=good[us].astype(np.uint32),
+                    edges_counted=int(idx.size))

@@ -102,6 +102,19 @@ int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out
     });
 }
 
+int folty_run_vertex_query(folty_graph *g, const folty_vertex_query *q, folty_result **out) {
+    return guarded([&] {
+        if (!g || !q || !out) fail(FOLTY_EINVAL, "null argument");
+        *out = nullptr;
+        StreamScope sc(g->g.stream);
+        Result *r = run_vertex_query(&g->g, *q, g->g.ws);
+        folty_result *h = new folty_result();
+        h->r = std::move(*r);
+        delete r;
+        *out = h;
+    });
+}
+
 int folty_workspace_create(folty_workspace **out) {
     return guarded([&] {
         if (!out) fail(FOLTY_EINVAL, "out is null");
@@ -265,6 +278,16 @@ int folty_result_pairs(const folty_result *r, int64_t *n_pairs, const int32_t **
         if (u) *u = r->r.u.data();
         if (v) *v = r->r.v.data();
         if (n_cert) *n_cert = r->r.n_cert.data();
+    });
+}
+
+int folty_result_vertices(const folty_result *r, int64_t *n_vertices, const int32_t **vertices,
+                          const uint32_t **good) {
+    return guarded([&] {
+        if (!r) fail(FOLTY_EINVAL, "result is null");
+        if (n_vertices) *n_vertices = (int64_t)r->r.vert.size();
+        if (vertices) *vertices = r->r.vert.data();
+        if (good) *good = r->r.vgood.data();
     });
 }
 

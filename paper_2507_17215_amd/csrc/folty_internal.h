@@ -218,6 +218,7 @@ struct Workspace {
     DevBuf scal;    // small device scalars
     DevBuf cub;     // library scan/sort temporaries
     DevBuf ilist;   // int32[NI] items with survivors
+    DevBuf vtmp;    // vertex queries: per-vertex counts, flags, offsets, output
     PinnedBuf host;
     hipEvent_t ev[8] = {};
     bool events = false;
@@ -242,6 +243,8 @@ struct Graph {
 struct Result {
     std::vector<int32_t> u, v;
     std::vector<uint32_t> n_cert;
+    std::vector<int32_t> vert;  // vertex queries: solution vertices, ascending
+    std::vector<uint32_t> vgood; // and their neighbours with a qualifying edge
     int64_t n_certificates = 0;
     folty_stats stats{};
     bool has_counts = false;
@@ -260,6 +263,7 @@ void build_index(Graph *g, const folty_build_opts *opts);
 void check_query(const Graph *g, const folty_query &q);
 Result *run_query(Graph *g, const folty_query &q, Workspace &ws);
 Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t stream);
+Result *run_vertex_query(Graph *g, const folty_vertex_query &q, Workspace &ws);
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
 void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);
 void fill_stats_from_index(const Index &ix, folty_stats *s);

@@ -154,6 +154,7 @@ struct ThreshArgs {
     uint32_t num, den;
     int universe, excl;
     int zero_never;                  // theta > 0 and |U| >= 1 for every edge: count 0 never certifies
+    int any;                         // the inner exists of a vertex query: count >= 1 qualifies
     uint32_t *ncert;                 // [2S]: 2 s + dir
     unsigned long long *total;       // certificates
 };
@@ -173,11 +174,15 @@ __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
         int dir = k >= A.smid[s] ? 1 : 0;
         int32_t a = dir ? A.shi[s] : A.slo[s];
         int32_t b = dir ? A.slo[s] : A.shi[s];
-        int64_t U;
-        if (A.universe == FOLTY_UNIVERSE_DST) U = (int64_t)A.deg[b] - A.excl;
-        else if (A.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)A.deg[a] - A.excl;
-        else U = A.tcnt[s];
-        cert = (uint64_t)cnt * A.den >= (uint64_t)A.num * (uint64_t)U;
+        if (A.any) {
+            cert = cnt >= 1u;
+        } else {
+            int64_t U;
+            if (A.universe == FOLTY_UNIVERSE_DST) U = (int64_t)A.deg[b] - A.excl;
+            else if (A.universe == FOLTY_UNIVERSE_SRC) U = (int64_t)A.deg[a] - A.excl;
+            else U = A.tcnt[s];
+            cert = (uint64_t)cnt * A.den >= (uint64_t)A.num * (uint64_t)U;
+        }
         key = 2 * (int64_t)s + dir;
     }
     // segmented count of certificates over runs of equal keys inside the wave
@@ -400,8 +405,78 @@ void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace
 }
 
 // threshold + pairs for one query given device counts (sorted edge order)
+// ---------------------------------------------------------------------------
+// vertex queries: per vertex u, its neighbours v with a qualifying edge u -> v
+// ---------------------------------------------------------------------------
+// good[u] += 1 for every directed pair (u, v) (key 2 s + dir) with a qualifying edge
+__global__ void k_vertex_good(const uint32_t *__restrict__ ncert, int32_t S, const int32_t *__restrict__ slo,
+                              const int32_t *__restrict__ shi, uint32_t *__restrict__ good) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * (int64_t)S || ncert[k] == 0) return;
+    const int32_t e = (int32_t)(k >> 1);
+    atomicAdd(&good[(k & 1) ? shi[e] : slo[e]], 1u);
+}
+
+// u is a solution: |N(u)| >= 1 and good[u] * den >= num * |N(u)|
+__global__ void k_vertex_flags(const uint32_t *__restrict__ good, const int32_t *__restrict__ deg, int32_t n,
+                               uint32_t num, uint32_t den, int32_t *__restrict__ flag) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const int32_t d = deg[u];
+    flag[u] = d >= 1 && (uint64_t)good[u] * den >= (uint64_t)num * (uint64_t)d;
+}
+
+// the solutions in id order, at their exclusive-scan positions
+__global__ void k_vertex_compact(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                                 const uint32_t *__restrict__ good, int32_t n, int32_t *__restrict__ vert,
+                                 uint32_t *__restrict__ vgood) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n || !flag[u]) return;
+    vert[pos[u]] = (int32_t)u;
+    vgood[pos[u]] = good[u];
+}
+
+// the vertex step after the edge-level threshold (ncert holds its per-pair counts)
+void finish_vertex(const Graph *g, const folty_vertex_query &vq, Workspace &ws, Result *res, hipStream_t s) {
+    const Index &ix = g->ix;
+    const int32_t n = ix.n, S = ix.S;
+    ws.vtmp.ensure(20 * (size_t)n + 16);
+    uint32_t *good = ws.vtmp.as<uint32_t>();
+    int32_t *flag = reinterpret_cast<int32_t *>(good + n);
+    int32_t *pos = flag + n;
+    int32_t *vert = pos + n;
+    uint32_t *vgood = reinterpret_cast<uint32_t *>(vert + n);
+    k_fill<uint32_t><<<grid_for(n, BLK), BLK, 0, s>>>(good, 0u, n);
+    FOLTY_LAUNCHED();
+    if (S > 0 && ix.m > 0) {
+        k_vertex_good<<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(ws.ncert.as<uint32_t>(), S, ix.slo.as<int32_t>(),
+                                                                  ix.shi.as<int32_t>(), good);
+        FOLTY_LAUNCHED();
+    }
+    k_vertex_flags<<<grid_for(n, BLK), BLK, 0, s>>>(good, ix.deg.as<int32_t>(), n, vq.theta_num, vq.theta_den, flag);
+    FOLTY_LAUNCHED();
+    size_t need = exclusive_scan_i32(nullptr, 0, flag, pos, n, s);
+    ws.cub.ensure(need);
+    exclusive_scan_i32(ws.cub.p, need, flag, pos, n, s);
+    k_vertex_compact<<<grid_for(n, BLK), BLK, 0, s>>>(flag, pos, good, n, vert, vgood);
+    FOLTY_LAUNCHED();
+    int32_t last[2] = {0, 0};
+    FOLTY_HIP(hipMemcpyAsync(&last[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(&last[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    const int32_t nv = last[0] + last[1];
+    res->vert.resize(nv);
+    res->vgood.resize(nv);
+    if (nv > 0) {
+        FOLTY_HIP(hipMemcpyAsync(res->vert.data(), vert, 4 * (size_t)nv, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipMemcpyAsync(res->vgood.data(), vgood, 4 * (size_t)nv, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// any: qualify edges with count >= 1 (the inner exists of a vertex query)
 void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, Workspace &ws, Result *res,
-                  hipStream_t s) {
+                  hipStream_t s, bool any = false) {
     const Index &ix = g->ix;
     const int32_t S = ix.S, m = ix.m;
     ws.ncert.ensure(8 * (size_t)S + 8);
@@ -429,8 +504,9 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
         A.universe = q.universe;
         A.excl = q.exclude_other ? 1 : 0;
         // N(b) and N(a) hold the other endpoint, so |U| >= 1 unless it is left out
-        A.zero_never = q.theta_num > 0 && !q.exclude_other &&
-                       (q.universe == FOLTY_UNIVERSE_DST || q.universe == FOLTY_UNIVERSE_SRC);
+        A.zero_never = any || (q.theta_num > 0 && !q.exclude_other &&
+                               (q.universe == FOLTY_UNIVERSE_DST || q.universe == FOLTY_UNIVERSE_SRC));
+        A.any = any ? 1 : 0;
         A.ncert = ws.ncert.as<uint32_t>();
         A.total = total;
         k_threshold<<<grid_for(m, BLK), BLK, 0, s>>>(A);
@@ -648,8 +724,31 @@ void check_query(const Graph *g, const folty_query &q) {
 
 Result *run_query(Graph *g, const folty_query &q, Workspace &ws) { return run_query_on(g, q, ws, g->stream); }
 
+static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s,
+                              const folty_vertex_query *vq);
+
 Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s) {
     check_query(g, q);
+    return run_query_impl(g, q, ws, s, nullptr);
+}
+
+Result *run_vertex_query(Graph *g, const folty_vertex_query &vq, Workspace &ws) {
+    if (vq.inner > FOLTY_INNER_EXISTS) fail(FOLTY_EINVAL, "unknown inner quantifier %u", (unsigned)vq.inner);
+    for (int i = 0; i < 7; i++)
+        if (vq.reserved[i]) fail(FOLTY_EINVAL, "reserved fields of the vertex query must be 0");
+    if (vq.theta_den == 0) fail(FOLTY_EINVAL, "theta_den must be > 0");
+    if (vq.theta_num > vq.theta_den) fail(FOLTY_EINVAL, "theta must lie in [0, 1]");
+    folty_query q = vq.edge;
+    if (vq.inner == FOLTY_INNER_EXISTS) { // the edge threshold is not read
+        q.theta_num = 1;
+        q.theta_den = 1;
+    }
+    check_query(g, q);
+    return run_query_impl(g, q, ws, g->stream, &vq);
+}
+
+static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s,
+                              const folty_vertex_query *vq) {
     if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
     Index &ix = g->ix;
     if (q.universe == FOLTY_UNIVERSE_COMMON) {
@@ -681,7 +780,8 @@ Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t 
     }
     if (ix.T < 0) ix.T = tri; // every query enumerates every triangle once
     FOLTY_HIP(hipEventRecord(ws.ev[2], s));
-    finish_query(g, q, count, ws, res.get(), s);
+    finish_query(g, q, count, ws, res.get(), s, vq && vq->inner == FOLTY_INNER_EXISTS);
+    if (vq) finish_vertex(g, *vq, ws, res.get(), s);
     FOLTY_HIP(hipEventRecord(ws.ev[3], s));
     if (!(q.flags & FOLTY_QUERY_NO_COUNTS)) keep_counts(g, count, res.get(), s);
     FOLTY_HIP(hipStreamSynchronize(s));

@@ -26,7 +26,8 @@ U32_MAX = 0xFFFFFFFF
 
 EXPORTS = (
     "folty_last_error", "folty_version", "folty_load_temporal_graph", "folty_build_index",
-    "folty_run_fol_query", "folty_workspace_create", "folty_workspace_free",
+    "folty_run_fol_query", "folty_run_vertex_query", "folty_result_vertices",
+    "folty_workspace_create", "folty_workspace_free",
     "folty_run_fol_query_ws", "folty_run_batch", "folty_run_multi", "folty_result_pairs",
     "folty_result_counts", "folty_result_stats", "folty_result_free", "folty_graph_stats",
     "folty_graph_vertex_array", "folty_graph_device_bytes", "folty_graph_free",
@@ -62,6 +63,15 @@ class PlanInfo(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+INNER_FORALL = 0  # exists u forall_theta v forall_theta2 w
+INNER_EXISTS = 1  # exists u forall_theta v exists w
+
+
+class VertexQuery(ctypes.Structure):
+    _fields_ = [("edge", Query), ("theta_num", ctypes.c_uint32), ("theta_den", ctypes.c_uint32),
+                ("inner", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 7)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -116,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.folty_load_temporal_graph.argtypes = [I32, I64, P, P, P, I32, P, PP]
     lib.folty_build_index.argtypes = [P, ctypes.POINTER(BuildOpts)]
     lib.folty_run_fol_query.argtypes = [P, ctypes.POINTER(Query), PP]
+    lib.folty_run_vertex_query.argtypes = [P, ctypes.POINTER(VertexQuery), PP]
+    lib.folty_result_vertices.argtypes = [P, ctypes.POINTER(I64), PP, PP]
     lib.folty_workspace_create.argtypes = [PP]
     lib.folty_workspace_free.argtypes = [P]
     lib.folty_workspace_free.restype = None
@@ -230,6 +242,17 @@ class Result:
     def pairs(self):
         return list(zip(self.pair_u.tolist(), self.pair_v.tolist(), self.n_cert.tolist()))
 
+    def vertices(self):
+        """Vertex query: (solution vertices ascending, their qualifying neighbour counts)."""
+        n = ctypes.c_int64()
+        v, g = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(load_library().folty_result_vertices(self._h, ctypes.byref(n), ctypes.byref(v), ctypes.byref(g)))
+        k = n.value
+        if k == 0:
+            return np.zeros(0, np.int32), np.zeros(0, np.uint32)
+        return (np.ctypeslib.as_array(ctypes.cast(v, ctypes.POINTER(ctypes.c_int32)), (k,)).copy(),
+                np.ctypeslib.as_array(ctypes.cast(g, ctypes.POINTER(ctypes.c_uint32)), (k,)).copy())
+
     def close(self):
         if self._h:
             load_library().folty_result_free(self._h)
@@ -295,6 +318,18 @@ class Graph:
         else:
             _check(lib.folty_run_fol_query_ws(self._h, ctypes.byref(q), workspace._h,
                                               ctypes.byref(out)))
+        return Result(out)
+
+    def vertex_query(self, delta, theta=(1, 2), inner=INNER_FORALL, inner_theta=(1, 2), variant=0,
+                     universe=UNIVERSE_DST, exclude_other=False, counts=True) -> Result:
+        """exists u forall_theta v in N(u) (forall_inner_theta | exists) w."""
+        vq = VertexQuery()
+        vq.edge = make_query(delta, inner_theta if inner == INNER_FORALL else (1, 1), variant, universe,
+                             exclude_other, counts)
+        vq.theta_num, vq.theta_den = to_theta(theta)
+        vq.inner = int(inner)
+        out = ctypes.c_void_p()
+        _check(load_library().folty_run_vertex_query(self._h, ctypes.byref(vq), ctypes.byref(out)))
         return Result(out)
 
     def query_raw(self, q: Query) -> Result:

@@ -38,6 +38,13 @@ def assert_same(res, want, counts=True):
     assert np.array_equal(res.n_cert, want["n_cert"])
 
 
+def assert_vertices(res, want):
+    v, good = res.vertices()
+    assert np.array_equal(v, want["vertices"]), f"{v.size} vs {want['vertices'].size} solution vertices"
+    assert np.array_equal(good, want["good"])
+    assert np.array_equal(res.pair_u, want["pair_u"]) and np.array_equal(res.pair_v, want["pair_v"])
+
+
 def test_hand_cases():
     d = json.load(open(GOLD))
     for g in d["graphs"]:
@@ -293,6 +300,52 @@ def test_plan_without_counts_leaves_histograms_cleared():
         G.query(qs[rep]["delta"], (1, 2), 0, counts=False)
 
 
+def test_vertex_queries_hand_cases():
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "vertex_cases.json")))
+    e = np.array(d["graph"]["edges"], dtype=np.int64)
+    G = folty.Graph(d["graph"]["n"], e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2]).build()
+    for c in d["cases"]:
+        say("vertex hand", c)
+        inner = folty.INNER_FORALL if c["inner"] == "forall" else folty.INNER_EXISTS
+        r = G.vertex_query(c["delta"], tuple(c["theta"]), inner, tuple(c.get("inner_theta", [1, 1])))
+        v, good = r.vertices()
+        assert v.tolist() == c["vertices"] and good.tolist() == c["good"]
+
+
+def test_vertex_queries_match_oracle():
+    """exists-forall-forall and exists-forall-exists: solution vertices, their
+    qualifying-neighbour counts and the qualifying directed pairs equal the
+    oracle's, over random tiny graphs (all predicate codes) and the tiny workload
+    (every universe, several thresholds)."""
+    rng = np.random.default_rng(17)
+    for it in range(12):
+        g = synth.random_small(rng, n_max=14, m_max=120, t_max=25)
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        G = gpu_graph(g)
+        for variant in range(8):
+            for inner in (folty.INNER_FORALL, folty.INNER_EXISTS):
+                delta = int(rng.choice([0, 2, 6, INF]))
+                th, th2 = (int(rng.integers(0, 5)), 4), (int(rng.integers(0, 5)), 4)
+                say("vertex tiny", it, variant, inner, delta, th, th2)
+                r = G.vertex_query(delta, th, inner, th2, variant)
+                cnt = o.counts(delta, variant)
+                assert np.array_equal(r.counts(), cnt)
+                assert_vertices(r, o.vertex_query(delta, th[0], th[1], variant, inner == folty.INNER_FORALL,
+                                                  th2[0], th2[1], counts=cnt))
+    g = synth.tiny()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    G = gpu_graph(g)
+    for delta in (3600, 10**6):
+        cnt = o.counts(delta, 0)
+        for uni, ex in ((0, False), (0, True), (1, False), (2, False)):
+            for th in ((0, 1), (1, 10), (1, 2), (1, 1)):
+                for inner in (folty.INNER_FORALL, folty.INNER_EXISTS):
+                    say("vertex workload", delta, uni, ex, th, inner)
+                    r = G.vertex_query(delta, th, inner, (1, 3), 0, uni, ex, counts=False)
+                    assert_vertices(r, o.vertex_query(delta, th[0], th[1], 0, inner == folty.INNER_FORALL,
+                                                      1, 3, uni, ex, counts=cnt))
+
+
 def test_single_query_one_pass_and_two_pass_agree():
     """A fresh index filters in two passes (count, then emit only items with
     survivors); once a plan has made the per-item triangle offsets, single
@@ -403,3 +456,9 @@ def test_medium_workload_full_counts():
     rb = G.batch([dict(delta=d, theta=(1, 2), variant=0) for d in deltas])
     for j, r in enumerate(rb):
         assert np.array_equal(r.counts(), pool[:, j])
+    say("medium: vertex queries")
+    for j, d in ((1, 3600), (3, synth.YEAR_S)):
+        for inner in (folty.INNER_FORALL, folty.INNER_EXISTS):
+            r = G.vertex_query(d, (1, 10), inner, (1, 4), 0, counts=False)
+            want = o.vertex_query(d, 1, 10, 0, inner == folty.INNER_FORALL, 1, 4, counts=pool[:, j])
+            assert_vertices(r, want)

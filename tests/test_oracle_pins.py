@@ -325,3 +325,18 @@ def test_vertex_theta_zero_and_nesting():
     ex = set(o.vertex_query(86400, 1, 10, 0, False, counts=cnt)["vertices"].tolist())
     fa = set(o.vertex_query(86400, 1, 10, 0, True, 1, 10, counts=cnt)["vertices"].tolist())
     assert fa <= ex
+
+
+def test_vertex_query_at_agrees_with_whole_graph():
+    g = synth.tiny(seed=5)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    for inner in (True, False):
+        full = o.vertex_query(86400, 1, 10, 0, inner, 1, 3)
+        us = np.random.default_rng(2).choice(g.n, size=300, replace=False)
+        part = o.vertex_query_at(us, 86400, 1, 10, 0, inner, 1, 3)
+        sol = set(full["vertices"].tolist())
+        goods = dict(zip(full["vertices"].tolist(), full["good"].tolist()))
+        for u, s_, gd in zip(part["vertices"].tolist(), part["solution"].tolist(), part["good"].tolist()):
+            assert s_ == (u in sol)
+            if s_:
+                assert gd == goods[u]
