@@ -367,22 +367,23 @@ def main():
         ok = True
         checked = {}
         by_delta = {}
-        for d in (a.delta, 86_400, synth.YEAR_S):
-            rq = G.query(d, theta, 0)
-            by_delta[str(d)] = {k: rq.stats[k] for k in ("query_ms", "wedge_ms", "temporal_ms", "threshold_ms",
-                                                         "tests", "n_pairs", "n_certificates")}
+        for d, variant in ((a.delta, 0), (86_400, 0), (synth.YEAR_S, 0), (synth.YEAR_S, 3), (synth.YEAR_S, 6)):
+            rq = G.query(d, theta, variant)
+            key = str(d) if variant == 0 else f"{d}/predicate{variant}"
+            by_delta[key] = {k: rq.stats[k] for k in ("query_ms", "wedge_ms", "temporal_ms", "threshold_ms",
+                                                      "tests", "n_pairs", "n_certificates")}
             got = rq.counts()
             nz = np.nonzero((got != 0xFFFFFFFF) & (got > 0))[0]
             if nz.size > a.parity_sample:
                 nz = np.sort(rng.choice(nz, size=a.parity_sample, replace=False))
             idx = np.union1d(sample, nz)
-            want = oracle.counts(d, 0, idx)
+            want = oracle.counts(d, variant, idx)
             bad = int((got[idx] != want).sum())
             ok = ok and bad == 0
-            checked[str(d)] = {"edges": int(idx.size), "gpu_nonzero_checked": int(nz.size),
-                               "oracle_nonzero": int((want > 0).sum()), "mismatches": bad}
-            log(f"parity delta={d}: {bad} mismatches over {idx.size} edges ({sample.size} uniform + "
-                f"{nz.size} the GPU counts as non-zero; oracle non-zero: {int((want > 0).sum())})")
+            checked[key] = {"edges": int(idx.size), "gpu_nonzero_checked": int(nz.size),
+                            "oracle_nonzero": int((want > 0).sum()), "mismatches": bad}
+            log(f"parity delta={d} predicate {variant}: {bad} mismatches over {idx.size} edges ({sample.size} "
+                f"uniform + {nz.size} the GPU counts as non-zero; oracle non-zero: {int((want > 0).sum())})")
         # vertex queries (exists-forall-forall, exists-forall-exists) on the same
         # index, one-year window; checked against the oracle on sampled vertices
         # (each decided from the counts of its own outgoing edges)

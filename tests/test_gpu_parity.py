@@ -456,6 +456,13 @@ def test_medium_workload_full_counts():
     rb = G.batch([dict(delta=d, theta=(1, 2), variant=0) for d in deltas])
     for j, r in enumerate(rb):
         assert np.array_equal(r.counts(), pool[:, j])
+    say("medium: other predicate codes and universes")
+    for variant in (3, 6):
+        cnt = o.counts(86400, variant)
+        for uni, ex in ((0, False), (1, True), (2, False)):
+            say("medium variant", variant, uni, ex)
+            r = G.query(86400, (1, 10), variant, uni, ex)
+            assert_same(r, o.query(86400, 1, 10, variant, uni, ex, counts=cnt), counts=(uni == 0))
     say("medium: vertex queries")
     for j, d in ((1, 3600), (3, synth.YEAR_S)):
         for inner in (folty.INNER_FORALL, folty.INNER_EXISTS):
