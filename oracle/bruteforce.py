@@ -112,3 +112,35 @@ def vertex_query(n, src, dst, t, delta, theta_num, theta_den, variant=0, inner_f
         if good * theta_den >= theta_num * len(nb[u]):
             out.append((u, good))
     return out
+
+
+def triads(n, src, dst, t, delta, variant=0):
+    """The exists-exists-exists query by its definition (paper, Definition of a
+    solution): every ordered triple (a, b, w) of distinct vertices with an edge
+    triple e1 = (a, b, t1), e2 in L2(w), e3 in L3(w), t1 <= t2 <= t3 <= t1 + delta
+    is a solution; inst[e1] counts those edge triples per first edge."""
+    src = [int(x) for x in src]
+    dst = [int(x) for x in dst]
+    t = [int(x) for x in t]
+    m = len(src)
+    by_pair = {}
+    for i in range(m):
+        if src[i] != dst[i]:
+            by_pair.setdefault((src[i], dst[i]), []).append(t[i])
+    inst = [0] * m
+    sols = set()
+    for i in range(m):
+        a, b, te = src[i], dst[i], t[i]
+        if a == b:
+            continue
+        X, Y = (b, a) if variant & 4 else (a, b)
+        for w in range(n):
+            if w == a or w == b:
+                continue
+            L2 = by_pair.get((w, X) if variant & 1 else (X, w), [])
+            L3 = by_pair.get((w, Y) if variant & 2 else (Y, w), [])
+            c = sum(1 for t2 in L2 for t3 in L3 if te <= t2 <= t3 <= te + delta)
+            if c:
+                inst[i] += c
+                sols.add((a, b, w))
+    return dict(triples=sorted(sols), instances=inst, n_instances=sum(inst))

@@ -406,3 +406,178 @@ void og_core_numbers(const og_graph *g, int32_t *core) {
 }
 
 int og_num_threads(void) { return omp_get_max_threads(); }
+
+/*
+ * ---------------------------------------------------------------------------
+ * Exists-exists-exists queries (paper, Definition of a solution: with three
+ * existential quantifiers a solution is a vertex triple; Section 1 and the
+ * problem statement: counting them is temporal triangle counting).
+ *
+ * For a predicate code, the temporal triangle on the ordered triple (a, b, w)
+ * is three temporal edges e1 in E_{a,b}, e2 in L2 and e3 in L3 (the lists the
+ * code picks, as above) with t(e1) <= t(e2) <= t(e3) <= t(e1) + delta.
+ *   - (a, b, w) is a solution when at least one such edge triple exists;
+ *   - inst[e1] is the number of such edge triples whose first edge is e1,
+ *     summed over every third vertex w; their sum over all edges is the number
+ *     of temporal triangles.
+ * Both are computed from the definition: pairs are looked at one by one.
+ * ---------------------------------------------------------------------------
+ */
+
+/* Number of (t2, t3) in L2 x L3 with t <= t2 <= t3 and t3 - t <= delta. */
+static uint64_t og_pairs(int64_t t, int64_t delta, const int64_t *L2, int64_t n2,
+                         const int64_t *L3, int64_t n3) {
+    uint64_t c = 0;
+    for (int64_t i = 0; i < n2; i++) {
+        int64_t t2 = L2[i];
+        if (t2 < t) continue;
+        if (t2 - t > delta) break;
+        for (int64_t j = 0; j < n3; j++) {
+            int64_t t3 = L3[j];
+            if (t3 < t2) continue;
+            if (t3 - t > delta) break;
+            c++;
+        }
+    }
+    return c;
+}
+
+/*
+ * inst[] for the edges idx[0..k) (input positions), or for all m edges when idx
+ * is NULL.  Self-loops get 0.  Returns 0, or -1 on bad arguments.
+ */
+int og_triad_instances(const og_graph *g, int64_t k, const int64_t *idx, int64_t delta,
+                       int variant, uint64_t *out, int threads) {
+    if (delta < 0 || variant < 0 || variant > 7) return -1;
+    if (threads > 0) omp_set_num_threads(threads);
+    int64_t cnt = idx ? k : g->m;
+#pragma omp parallel
+    {
+        int32_t *buf = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t q = 0; q < cnt; q++) {
+            int64_t i = idx ? idx[q] : q;
+            int32_t a = g->src[i], b = g->dst[i];
+            out[q] = 0;
+            if (a == b) continue;
+            int64_t need = g->adj_off[a + 1] - g->adj_off[a];
+            int64_t nb = g->adj_off[b + 1] - g->adj_off[b];
+            if (nb < need) need = nb;
+            if (need + 1 > cap) { free(buf); cap = need + 1; buf = (int32_t *)malloc(sizeof(int32_t) * cap); }
+            int64_t nc = og_common(g, a, b, buf);
+            uint64_t s = 0;
+            for (int64_t c = 0; c < nc; c++) {
+                const int64_t *L2, *L3;
+                int64_t n2, n3;
+                og_pick(g, variant, a, b, buf[c], &L2, &n2, &L3, &n3);
+                s += og_pairs(g->t[i], delta, L2, n2, L3, n3);
+            }
+            out[q] = s;
+        }
+        free(buf);
+    }
+    return 0;
+}
+
+/*
+ * The third vertices w, ascending, that make (a, b, w) a solution: some e1 in
+ * E_{a,b} has a temporal triangle with w.  buf holds at least
+ * min(|N(a)|, |N(b)|) ids; out may be NULL.  Returns how many.
+ */
+static int64_t og_triad_ws(const og_graph *g, int32_t a, int32_t b, int64_t delta, int variant,
+                           int32_t *buf, int32_t *out) {
+    const int64_t *L1;
+    int64_t n1 = og_list(g, a, b, &L1, NULL);
+    if (n1 == 0 || a == b) return 0;
+    int64_t nc = og_common(g, a, b, buf); /* ascending: og_common walks a sorted row */
+    int64_t c = 0;
+    for (int64_t j = 0; j < nc; j++) {
+        const int64_t *L2, *L3;
+        int64_t n2, n3;
+        og_pick(g, variant, a, b, buf[j], &L2, &n2, &L3, &n3);
+        for (int64_t i = 0; i < n1; i++) {
+            if (og_exists(L1[i], delta, L2, n2, L3, n3)) {
+                if (out) out[c] = buf[j];
+                c++;
+                break;
+            }
+        }
+    }
+    return c;
+}
+
+/* the directed pairs (x, y) with E_{x,y} non-empty, ascending by (x, y) */
+int64_t og_pair_table(const og_graph *g, int32_t *x, int32_t *y) {
+    for (int64_t p = 0; p < g->np; p++) {
+        if (x) x[p] = (int32_t)(g->pkey[p] / g->n);
+        if (y) y[p] = (int32_t)(g->pkey[p] % g->n);
+    }
+    return g->np;
+}
+
+static int32_t *og_buf_for(const og_graph *g, int32_t a, int32_t b, int32_t **buf, int64_t *cap) {
+    int64_t need = g->adj_off[a + 1] - g->adj_off[a];
+    int64_t nb = g->adj_off[b + 1] - g->adj_off[b];
+    if (nb < need) need = nb;
+    if (need + 1 > *cap) { free(*buf); *cap = need + 1; *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)*cap); }
+    return *buf;
+}
+
+/* cnt[p] = number of solution triples (x_p, y_p, w) of every directed pair p */
+int og_triad_pair_counts(const og_graph *g, int64_t delta, int variant, int64_t *cnt, int threads) {
+    if (delta < 0 || variant < 0 || variant > 7) return -1;
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel
+    {
+        int32_t *buf = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < g->np; p++) {
+            int32_t a = (int32_t)(g->pkey[p] / g->n), b = (int32_t)(g->pkey[p] % g->n);
+            cnt[p] = og_triad_ws(g, a, b, delta, variant, og_buf_for(g, a, b, &buf, &cap), NULL);
+        }
+        free(buf);
+    }
+    return 0;
+}
+
+/* the solution triples (a, b, w), three ids each, pair p's from out + 3 off[p] */
+int og_triad_fill(const og_graph *g, int64_t delta, int variant, const int64_t *off, int32_t *out,
+                  int threads) {
+    if (delta < 0 || variant < 0 || variant > 7) return -1;
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel
+    {
+        int32_t *buf = NULL, *ws = NULL;
+        int64_t cap = 0, wcap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < g->np; p++) {
+            if (off[p + 1] == off[p]) continue;
+            int32_t a = (int32_t)(g->pkey[p] / g->n), b = (int32_t)(g->pkey[p] % g->n);
+            og_buf_for(g, a, b, &buf, &cap);
+            if (cap > wcap) { free(ws); wcap = cap; ws = (int32_t *)malloc(sizeof(int32_t) * (size_t)wcap); }
+            int64_t c = og_triad_ws(g, a, b, delta, variant, buf, ws);
+            for (int64_t j = 0; j < c; j++) {
+                int32_t *o = out + 3 * (off[p] + j);
+                o[0] = a;
+                o[1] = b;
+                o[2] = ws[j];
+            }
+        }
+        free(buf);
+        free(ws);
+    }
+    return 0;
+}
+
+/* the solution third vertices of one directed pair (a, b); out holds min(|N(a)|, |N(b)|) */
+int64_t og_triad_pair(const og_graph *g, int32_t a, int32_t b, int64_t delta, int variant,
+                      int32_t *out) {
+    if (delta < 0 || variant < 0 || variant > 7 || a < 0 || b < 0 || a >= g->n || b >= g->n) return -1;
+    int32_t *buf = NULL;
+    int64_t cap = 0;
+    int64_t c = og_triad_ws(g, a, b, delta, variant, og_buf_for(g, a, b, &buf, &cap), out);
+    free(buf);
+    return c;
+}

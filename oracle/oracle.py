@@ -24,6 +24,12 @@ exists-exists-forall query at theta2, or the edges with count >= 1 for the
 inner exists), the per-vertex marks L_u[v] for every e = (u, v, t) in L, their
 sums over N(u), and the threshold sum >= theta1 * |N(u)| for the vertices whose
 neighbourhood is not empty (the last step runs over N(u)).
+
+Exists-exists-exists queries (paper, Definition of a solution; Section 1: for
+this prefix the problem is temporal triangle counting): the solution triples
+(a, b, w) with at least one temporal triangle e1 in E_{a,b}, e2, e3 in the
+lists the predicate code picks and t(e1) <= t(e2) <= t(e3) <= t(e1) + delta,
+and the number of such edge triples per first edge (``triad_instances``).
 """
 from __future__ import annotations
 
@@ -69,6 +75,16 @@ def _load():
         lib.og_sizes.argtypes = [P, P, ctypes.c_int]
         lib.og_core_numbers.argtypes = [P, P]
         lib.og_num_threads.restype = ctypes.c_int
+        lib.og_triad_instances.restype = ctypes.c_int
+        lib.og_triad_instances.argtypes = [P, i64, P, i64, ctypes.c_int, P, ctypes.c_int]
+        lib.og_pair_table.restype = i64
+        lib.og_pair_table.argtypes = [P, P, P]
+        lib.og_triad_pair_counts.restype = ctypes.c_int
+        lib.og_triad_pair_counts.argtypes = [P, i64, ctypes.c_int, P, ctypes.c_int]
+        lib.og_triad_fill.restype = ctypes.c_int
+        lib.og_triad_fill.argtypes = [P, i64, ctypes.c_int, P, P, ctypes.c_int]
+        lib.og_triad_pair.restype = i64
+        lib.og_triad_pair.argtypes = [P, i32, i32, i64, ctypes.c_int, P]
         _lib = lib
     return _lib
 
@@ -250,3 +266,60 @@ class Oracle:
         sol = (deg[us] >= 1) & (good[us] * theta_den >= theta_num * deg[us])
         return dict(vertices=us.astype(np.int32), solution=sol, good=good[us].astype(np.uint32),
                     edges_counted=int(idx.size))
+
+    # -- exists-exists-exists ---------------------------------------------------------
+    def triad_instances(self, delta: int, variant: int = 0, idx=None) -> np.ndarray:
+        """Temporal triangles whose first edge is each edge of ``idx`` (input
+        positions; all edges by default), over every third vertex; self-loops 0."""
+        lib = _load()
+        if idx is None:
+            out = np.zeros(self.m, dtype=np.uint64)
+            rc = lib.og_triad_instances(self._h, 0, None, int(delta), int(variant), _ptr(out),
+                                        self.threads)
+        else:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            out = np.zeros(idx.shape[0], dtype=np.uint64)
+            rc = lib.og_triad_instances(self._h, idx.shape[0], _ptr(idx), int(delta), int(variant),
+                                        _ptr(out), self.threads)
+        if rc != 0:
+            raise ValueError("bad delta or variant")
+        return out
+
+    def pair_table(self):
+        """The directed pairs (x, y) with at least one temporal edge x -> y, ascending."""
+        lib = _load()
+        k = lib.og_pair_table(self._h, None, None)
+        x = np.zeros(k, dtype=np.int32)
+        y = np.zeros(k, dtype=np.int32)
+        lib.og_pair_table(self._h, _ptr(x), _ptr(y))
+        return x, y
+
+    def triad_pair_counts(self, delta: int, variant: int = 0) -> np.ndarray:
+        """Solution triples of each directed pair of ``pair_table``."""
+        lib = _load()
+        x, _ = self.pair_table()
+        cnt = np.zeros(x.shape[0], dtype=np.int64)
+        if lib.og_triad_pair_counts(self._h, int(delta), int(variant), _ptr(cnt), self.threads) != 0:
+            raise ValueError("bad delta or variant")
+        return cnt
+
+    def triad_solutions(self, delta: int, variant: int = 0) -> np.ndarray:
+        """All solution triples (a, b, w), shape (k, 3), ascending by (a, b, w)."""
+        lib = _load()
+        cnt = self.triad_pair_counts(delta, variant)
+        off = np.zeros(cnt.shape[0] + 1, dtype=np.int64)
+        np.cumsum(cnt, out=off[1:])
+        out = np.zeros((int(off[-1]), 3), dtype=np.int32)
+        if lib.og_triad_fill(self._h, int(delta), int(variant), _ptr(off), _ptr(out), self.threads) != 0:
+            raise ValueError("bad delta or variant")
+        return out
+
+    def triad_pair(self, a: int, b: int, delta: int, variant: int = 0) -> np.ndarray:
+        """The third vertices w (ascending) of the solution triples (a, b, w)."""
+        lib = _load()
+        deg = self.degrees()
+        out = np.zeros(int(min(deg[a], deg[b])) + 1, dtype=np.int32)
+        c = lib.og_triad_pair(self._h, int(a), int(b), int(delta), int(variant), _ptr(out))
+        if c < 0:
+            raise ValueError("bad arguments")
+        return out[:c].copy()

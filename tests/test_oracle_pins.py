@@ -340,3 +340,155 @@ def test_vertex_query_at_agrees_with_whole_graph():
             assert s_ == (u in sol)
             if s_:
                 assert gd == goods[u]
+
+
+# -- exists-exists-exists -------------------------------------------------------------
+TRIAD_GOLD = os.path.join(os.path.dirname(__file__), "golden", "triad_cases.json")
+
+
+def _triad_check(o, n, src, dst, t, delta, variant):
+    want = bf.triads(n, src, dst, t, delta, variant)
+    sol = o.triad_solutions(delta, variant)
+    assert [tuple(r) for r in sol.tolist()] == want["triples"], (variant, delta)
+    assert o.triad_instances(delta, variant).tolist() == want["instances"], (variant, delta)
+
+
+def test_triad_hand_cases():
+    d = json.load(open(TRIAD_GOLD))
+    e = np.array(d["graph"]["edges"], dtype=np.int64)
+    n = d["graph"]["n"]
+    o = Oracle(n, e[:, 0], e[:, 1], e[:, 2])
+    for c in d["cases"]:
+        assert o.triad_solutions(c["delta"], c["variant"]).tolist() == c["triples"], c
+        assert o.triad_instances(c["delta"], c["variant"]).tolist() == c["instances"], c
+        b = bf.triads(n, e[:, 0], e[:, 1], e[:, 2], c["delta"], c["variant"])
+        assert [list(x) for x in b["triples"]] == c["triples"]
+        assert b["instances"] == c["instances"]
+        for a, b_, w in c["triples"]:
+            assert w in o.triad_pair(a, b_, c["delta"], c["variant"]).tolist()
+
+
+def test_triads_match_bruteforce():
+    rng = np.random.default_rng(4321)
+    for it in range(120):
+        g = synth.random_small(rng)
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        for variant in range(8):
+            for delta in (0, 1, 5, INF):
+                _triad_check(o, g.n, g.src, g.dst, g.t, delta, variant)
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_triads_equal_timestamps_reduce_to_matrix_products(variant):
+    """All timestamps equal: every edge triple on (a, b, w) is in temporal order,
+    so inst[e1] = sum over w of mult(L2) * mult(L3), an entry of the product of
+    the multiplicity matrices, and (a, b, w) is a solution when both lists of w
+    are non-empty (the 0/1 matrices)."""
+    rng = np.random.default_rng(70 + variant)
+    n, m = 50, 700
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    t = np.full(m, 777, dtype=np.int64)
+    keep = src != dst
+    C = sp.coo_matrix((np.ones(keep.sum()), (src[keep], dst[keep])), shape=(n, n)).tocsr()
+    C.sum_duplicates()
+    A = C.copy()
+    A.data[:] = 1.0
+    M2c, M3c = (C.T.tocsr() if variant & 1 else C), (C.T.tocsr() if variant & 2 else C)
+    M2, M3 = (A.T.tocsr() if variant & 1 else A), (A.T.tocsr() if variant & 2 else A)
+    Pc = (M2c @ M3c.T).toarray()  # [X, Y] = sum over w of mult(L2) mult(L3)
+    P = (M2 @ M3.T).toarray()     # [X, Y] = #w with both lists non-empty
+    o = Oracle(n, src, dst, t)
+    for delta in (0, INF):
+        inst = o.triad_instances(delta, variant)
+        for i in range(m):
+            a, b = int(src[i]), int(dst[i])
+            X, Y = (b, a) if variant & 4 else (a, b)
+            assert inst[i] == (0 if a == b else int(round(Pc[X, Y]))), (i, a, b)
+        x, y = o.pair_table()
+        XX, YY = (y, x) if variant & 4 else (x, y)
+        assert len(o.triad_solutions(delta, variant)) == int(round(P[XX, YY].sum()))
+        assert (o.triad_pair_counts(delta, variant) == np.round(P[XX, YY]).astype(np.int64)).all()
+
+
+def test_triad_closed_forms():
+    # one transitive triangle a->b, a->w, b->w with multiplicities p, q, r at one time
+    p, q, r = 3, 4, 5
+    src = [0] * p + [0] * q + [1] * r
+    dst = [1] * p + [2] * q + [2] * r
+    o = Oracle(3, src, dst, [9] * (p + q + r))
+    assert o.triad_instances(0, 0).tolist() == [q * r] * p + [0] * (q + r)
+    assert o.triad_solutions(0, 0).tolist() == [[0, 1, 2]]
+    for variant in range(1, 8):
+        # codes 1 and 6 are the cyclic triangle (a->b->w->a); every other code is
+        # a transitive one and matches this triangle under exactly one labelling
+        want = 0 if variant in (1, 6) else 1
+        assert len(o.triad_solutions(0, variant)) == want, variant
+    # L1 = {0}, L2 = L3 = {0, ..., k-1}: pairs t2 <= t3 within delta = k - 1
+    k = 7
+    src = [0] + [0] * k + [1] * k
+    dst = [1] + [2] * k + [2] * k
+    tt = [0] + list(range(k)) + list(range(k))
+    o = Oracle(3, src, dst, tt)
+    for delta in range(k):
+        # t3 <= delta: pairs 0 <= t2 <= t3 <= delta
+        assert int(o.triad_instances(delta, 0)[0]) == (delta + 1) * (delta + 2) // 2
+    # a cyclic triangle at one time solves code 1 in all three rotations
+    o = Oracle(3, [0, 1, 2], [1, 2, 0], [5, 5, 5])
+    assert o.triad_solutions(0, 1).tolist() == [[0, 1, 2], [1, 2, 0], [2, 0, 1]]
+    assert o.triad_instances(0, 1).tolist() == [1, 1, 1]
+    assert o.triad_solutions(0, 0).tolist() == []
+    # temporal order is strict about e2 before e3: t3 < t2 never counts
+    o = Oracle(3, [0, 0, 1], [1, 2, 2], [0, 5, 4])
+    assert o.triad_instances(INF, 0).tolist() == [0, 0, 0]
+
+
+def test_triads_agree_with_counts():
+    """count[e] is the number of w with at least one edge triple on e, so
+    inst[e] >= count[e] with equality to zero together, and the third vertices
+    of the solution triples (a, b, w) are the union over e in E_{a,b} of those w."""
+    g = synth.tiny(seed=6)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    for variant in (0, 1, 6):
+        for delta in (600, 86400):
+            cnt = o.counts(delta, variant).astype(np.int64)
+            inst = o.triad_instances(delta, variant).astype(np.int64)
+            loop = g.src == g.dst
+            assert (inst[~loop] >= cnt[~loop]).all()
+            assert ((inst[~loop] == 0) == (cnt[~loop] == 0)).all()
+            pc = o.triad_pair_counts(delta, variant)
+            x, y = o.pair_table()
+            key = x.astype(np.int64) * g.n + y
+            ekey = g.src.astype(np.int64) * g.n + g.dst
+            mx = np.zeros(len(key), np.int64)
+            sm = np.zeros(len(key), np.int64)
+            pos = np.searchsorted(key, ekey[~loop])
+            np.maximum.at(mx, pos, cnt[~loop])
+            np.add.at(sm, pos, cnt[~loop])
+            assert (pc >= mx).all() and (pc <= sm).all()
+            sol = o.triad_solutions(delta, variant)
+            assert len(sol) == pc.sum()
+
+
+def test_triads_monotone_in_delta_and_time_invariant():
+    g = synth.tiny(seed=8)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    prev_i, prev_s = None, None
+    for delta in (0, 60, 3600, 86400, INF):
+        inst = o.triad_instances(delta, 0)
+        sol = {tuple(r) for r in o.triad_solutions(delta, 0).tolist()}
+        if prev_i is not None:
+            assert (inst >= prev_i).all() and prev_s <= sol
+        prev_i, prev_s = inst, sol
+    # shifting every timestamp leaves the answer unchanged
+    o2 = Oracle(g.n, g.src, g.dst, g.t + 1_000_000)
+    assert np.array_equal(o2.triad_instances(3600, 2), o.triad_instances(3600, 2))
+    assert np.array_equal(o2.triad_solutions(3600, 2), o.triad_solutions(3600, 2))
+
+
+def test_triad_bad_arguments_rejected():
+    o = Oracle(3, [0], [1], [0])
+    with pytest.raises(ValueError):
+        o.triad_instances(-1, 0)
+    with pytest.raises(ValueError):
+        o.triad_solutions(5, 8)
