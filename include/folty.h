@@ -210,6 +210,58 @@ typedef struct {
 
 int folty_run_vertex_query(folty_graph *g, const folty_vertex_query *q, folty_result **out);
 
+/*
+ * Exists-exists-exists query (paper, Definition of a solution: with three
+ * existential quantifiers a solution is a vertex triple; Section 1: for this
+ * prefix the problem is temporal triangle counting).
+ *
+ * For the predicate code `variant` (the lists L2, L3 as for folty_query), the
+ * ordered triple (a, b, w) is a solution when some temporal edges e1 on a -> b,
+ * e2 in L2 and e3 in L3 satisfy t(e1) <= t(e2) <= t(e3) <= t(e1) + delta.  A
+ * temporal triangle is one such edge triple (e1, e2, e3); the number of them is
+ * the temporal triangle count for the code.
+ *
+ * flags (other bits must be 0):
+ *   FOLTY_TRIAD_TRIPLES         list the solution triples (a, b, w), sorted;
+ *                               otherwise only their number is kept;
+ *   FOLTY_TRIAD_INSTANCES       count the temporal triangles as well (each test
+ *                               then counts every (e2, e3), not just the first);
+ *   FOLTY_TRIAD_EDGE_INSTANCES  also keep the count per first edge e1 (implies
+ *                               FOLTY_TRIAD_INSTANCES; 8 bytes per input edge).
+ * FOLTY_EOVERFLOW when the temporal triangles number 2^63 or more, or when more
+ * than 2^31 - 1 solution triples are to be listed (their number is still
+ * reported by a run without FOLTY_TRIAD_TRIPLES).
+ */
+#define FOLTY_TRIAD_TRIPLES 1u
+#define FOLTY_TRIAD_INSTANCES 2u
+#define FOLTY_TRIAD_EDGE_INSTANCES 4u
+
+typedef struct {
+    int64_t delta;         /* >= 0, same unit as t; FOLTY_DELTA_INF = no window */
+    uint8_t variant;       /* predicate code 0..7 */
+    uint8_t flags;         /* FOLTY_TRIAD_* bits */
+    uint8_t reserved[6];   /* must be 0 */
+} folty_triad_query;
+
+int folty_run_triad_query(folty_graph *g, const folty_triad_query *q, folty_result **out);
+
+/*
+ * Exists-exists-exists result: the number of solution triples, the number of
+ * temporal triangles (-1 unless FOLTY_TRIAD_INSTANCES was asked) and, with
+ * FOLTY_TRIAD_TRIPLES, the triples as 3 x n_solutions ids (a, b, w), ascending
+ * by (a, b, w) (else NULL).  Host pointers, valid until folty_result_free.
+ * FOLTY_EINVAL for a result of another query kind.
+ */
+int folty_result_triads(const folty_result *r, int64_t *n_solutions, int64_t *n_instances,
+                        const int32_t **triples);
+
+/*
+ * Temporal triangles per first edge e1, in input order (m_input entries; 0 for
+ * a self-loop), from a run with FOLTY_TRIAD_EDGE_INSTANCES (FOLTY_EINVAL
+ * otherwise).  Host pointer, valid until folty_result_free.
+ */
+int folty_result_edge_instances(const folty_result *r, const uint64_t **instances);
+
 /* The same with caller-owned scratch memory, for concurrent queries on one
  * graph from several threads (one workspace per thread). */
 int folty_workspace_create(folty_workspace **out);

@@ -115,6 +115,40 @@ int folty_run_vertex_query(folty_graph *g, const folty_vertex_query *q, folty_re
     });
 }
 
+int folty_run_triad_query(folty_graph *g, const folty_triad_query *q, folty_result **out) {
+    return guarded([&] {
+        if (!g || !q || !out) fail(FOLTY_EINVAL, "null argument");
+        *out = nullptr;
+        StreamScope sc(g->g.stream);
+        Result *r = run_triad_query(&g->g, *q, g->g.ws);
+        folty_result *h = new folty_result();
+        h->r = std::move(*r);
+        delete r;
+        *out = h;
+    });
+}
+
+int folty_result_triads(const folty_result *r, int64_t *n_solutions, int64_t *n_instances,
+                        const int32_t **triples) {
+    return guarded([&] {
+        if (!r) fail(FOLTY_EINVAL, "result is null");
+        if (!r->r.triad) fail(FOLTY_EINVAL, "not the result of an exists-exists-exists query");
+        if (n_solutions) *n_solutions = r->r.n_triads;
+        if (n_instances) *n_instances = r->r.n_tinst;
+        if (triples) *triples = r->r.trip.empty() ? nullptr : r->r.trip.data();
+    });
+}
+
+int folty_result_edge_instances(const folty_result *r, const uint64_t **instances) {
+    return guarded([&] {
+        if (!r || !instances) fail(FOLTY_EINVAL, "null argument");
+        *instances = nullptr;
+        if (!r->r.triad || r->r.tinst.size() != (size_t)r->r.stats.m_input)
+            fail(FOLTY_EINVAL, "the query did not ask for FOLTY_TRIAD_EDGE_INSTANCES");
+        *instances = r->r.tinst.data();
+    });
+}
+
 int folty_workspace_create(folty_workspace **out) {
     return guarded([&] {
         if (!out) fail(FOLTY_EINVAL, "out is null");

@@ -219,6 +219,8 @@ struct Workspace {
     DevBuf cub;     // library scan/sort temporaries
     DevBuf ilist;   // int32[NI] items with survivors
     DevBuf vtmp;    // vertex queries: per-vertex counts, flags, offsets, output
+    DevBuf tflag;   // exists-exists-exists: uint32[(survivor slots + 3) / 4] solution bits
+    DevBuf tinst;   // exists-exists-exists: uint64[m] temporal triangles per first edge
     PinnedBuf host;
     hipEvent_t ev[8] = {};
     bool events = false;
@@ -245,6 +247,11 @@ struct Result {
     std::vector<uint32_t> n_cert;
     std::vector<int32_t> vert;  // vertex queries: solution vertices, ascending
     std::vector<uint32_t> vgood; // and their neighbours with a qualifying edge
+    bool triad = false;                // an exists-exists-exists result
+    int64_t n_triads = 0;              // its solution triples
+    int64_t n_tinst = -1;              // its temporal triangles (-1: not counted)
+    std::vector<int32_t> trip;         // 3 per listed triple (a, b, w)
+    std::vector<uint64_t> tinst;       // temporal triangles per first edge, input order
     int64_t n_certificates = 0;
     folty_stats stats{};
     bool has_counts = false;
@@ -264,6 +271,14 @@ void check_query(const Graph *g, const folty_query &q);
 Result *run_query(Graph *g, const folty_query &q, Workspace &ws);
 Result *run_query_on(Graph *g, const folty_query &q, Workspace &ws, hipStream_t stream);
 Result *run_vertex_query(Graph *g, const folty_vertex_query &q, Workspace &ws);
+Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws);
+// The time-range filter of one query (query.hip): surviving triangles in their
+// slots (ws.slots), tests per item and their offsets (ws.wbase).  Returns the
+// number of survivor slots; *tests is the test count, or -1 when the one-pass
+// filter left it on the device.  e0, e1 bracket the counting pass.
+int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1, int64_t *tri, int64_t *tests);
+double ev_ms(hipEvent_t a, hipEvent_t b);
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
 void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);
 void fill_stats_from_index(const Index &ix, folty_stats *s);

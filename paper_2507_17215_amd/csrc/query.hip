@@ -236,24 +236,16 @@ __global__ void k_counts_scatter(const uint32_t *__restrict__ count, const int32
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
-template <class F> void dispatch_variant(int v, F &&f) {
-    switch (v) {
-    case 0: f(std::integral_constant<int, 0>{}); break;
-    case 1: f(std::integral_constant<int, 1>{}); break;
-    case 2: f(std::integral_constant<int, 2>{}); break;
-    case 3: f(std::integral_constant<int, 3>{}); break;
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 5: f(std::integral_constant<int, 5>{}); break;
-    case 6: f(std::integral_constant<int, 6>{}); break;
-    default: f(std::integral_constant<int, 7>{}); break;
-    }
-}
+
+} // namespace
 
 double ev_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0;
     FOLTY_HIP(hipEventElapsedTime(&ms, a, b));
     return ms;
 }
+
+namespace {
 
 unsigned enum_grid(int32_t n) {
     int64_t g = ((int64_t)n + WPB - 1) / WPB;
@@ -279,6 +271,8 @@ __global__ void k_item_list(const int32_t *__restrict__ su, int32_t NI, int32_t 
     const int32_t slot = wave_append(nlist, take);
     if (take) list[slot] = (int32_t)it;
 }
+
+} // namespace
 
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
                        hipEvent_t e1, int64_t *tri, int64_t *tests) {
@@ -385,6 +379,8 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
     }
     return survivors;
 }
+
+namespace {
 
 // tests < 0: unknown on the host, the full persistent grid; else a thread per
 // chunk, and chunks of one test when there are few (each chunk's searches are a

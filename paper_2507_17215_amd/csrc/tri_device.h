@@ -62,6 +62,20 @@ template <class T> __device__ inline T wave_inclusive_sum(T x) {
     return x;
 }
 
+// the predicate code as a compile-time constant for kernel templates
+template <class F> void dispatch_variant(int v, F &&f) {
+    switch (v) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    default: f(std::integral_constant<int, 7>{}); break;
+    }
+}
+
 template <class T> __global__ void k_fill(T *p, T v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;

@@ -1,0 +1,440 @@
+// The exists-exists-exists triadic query: solution triples and temporal
+// triangles (paper, Definition of a solution; Section 1, where this prefix is
+// identified with temporal triangle counting).
+//
+// It shares the index and the time-range filter of the exists-exists-forall
+// query: the filter keeps the static triangles with a run (triangle, directed
+// list E_{a,b}) whose three lists can hold t <= t2 <= t3 <= t + delta, and the
+// runs' temporal edges are cut into equal chunks over the grid.  Per chunk:
+//   - solutions: the first-entry search of Theorems 3.1 and 3.2 per edge of
+//     E_{a,b}, stopping at the first edge with a triangle, sets the run's bit;
+//     a run is the ordered triple (a, b, w), so the set bits are the solutions;
+//   - temporal triangles (optional): for an edge at time t, with L2[lo, hi) the
+//     entries of L2 in [t, t + delta], h3 the first entry of L3 after t + delta
+//     and f(j) the first entry of L3 at or after L2[j], the edge closes
+//     sum_{j in [lo, hi)} (h3 - f(j)) = (hi - lo) h3 - (F(hi) - F(lo)) pairs,
+//     F the running sum of f.  lo, hi, h3 and the two search cursors for f only
+//     move forward over a chunk's time-sorted edges, so a chunk costs its edges
+//     plus the entries its windows pass, each with a search from the cursor.
+// The set bits are then counted, and listed as (a, b, w) in original ids,
+// sorted by two stable radix sorts (w, then the pair key a n + b).
+#include <algorithm>
+#include <cstring>
+
+#include "tri_device.h"
+
+namespace folty {
+namespace {
+
+// first position p in [from, n) with L[p] - t > d (n if none); L ascending
+__device__ inline int32_t past_window(const int64_t *__restrict__ L, int32_t from, int32_t n, int64_t t, int64_t d) {
+    if (from >= n || L[from] - t > d) return from;
+    int32_t a = from + 1, b = n;
+    while (a < b) {
+        int32_t mid = (a + b) >> 1;
+        if (L[mid] - t <= d) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+
+struct TriadOut {
+    int64_t delta;
+    uint32_t *flag;                // bit run of byte (slot & 3) of word slot >> 2
+    unsigned long long *inst;      // temporal triangles per sorted edge, or null
+};
+
+// edges [l1s, l1s + cnt) of one run against its lists (L2, L3)
+template <bool INST>
+__device__ inline void triad_chunk(const TriadOut &o, const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt,
+                                   const Span &l2, const Span &l3, int64_t slot, int run, unsigned long long &acc,
+                                   bool &ovf) {
+    const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
+    const int32_t n2 = l2.n, n3 = l3.n;
+    const int64_t d = o.delta;
+    bool any = false;
+    if (!INST) {
+        int32_t c2 = 0, c3 = 0;
+        for (int32_t q = 0; q < cnt; q++) {
+            const int64_t t = ts[l1s + q];
+            c2 = lower_bound_from(L2, c2, n2, t);
+            if (c2 == n2) break; // later edges are no earlier: no t2 for them either
+            const int64_t t2 = L2[c2];
+            if (t2 - t > d) continue;
+            c3 = lower_bound_from(L3, c3, n3, t2);
+            if (c3 == n3) break;
+            if (L3[c3] - t <= d) {
+                any = true;
+                break;
+            }
+        }
+    } else {
+        int32_t lo = lower_bound_from(L2, 0, n2, ts[l1s]);
+        int32_t hi = lo, flo = 0, fhi = 0, h3 = 0;
+        unsigned long long Flo = 0, Fhi = 0; // sums of f over L2[lo0, lo) and L2[lo0, hi)
+        for (int32_t q = 0; q < cnt; q++) {
+            const int32_t e = l1s + q;
+            const int64_t t = ts[e];
+            while (hi < n2 && L2[hi] - t <= d) {
+                fhi = lower_bound_from(L3, fhi, n3, L2[hi]);
+                Fhi += (unsigned)fhi;
+                hi++;
+            }
+            while (lo < hi && L2[lo] < t) {
+                flo = lower_bound_from(L3, flo, n3, L2[lo]);
+                Flo += (unsigned)flo;
+                lo++;
+            }
+            if (lo == hi) {
+                if (lo == n2) break; // no t2 at or after t for this or any later edge
+                continue;
+            }
+            h3 = past_window(L3, h3, n3, t, d);
+            const unsigned long long pairs = (unsigned long long)(hi - lo) * (unsigned)h3 - (Fhi - Flo);
+            if (pairs) {
+                any = true;
+                if (o.inst) atomicAdd(&o.inst[e], pairs);
+                const unsigned long long s = acc + pairs;
+                ovf |= s < acc;
+                acc = s;
+            }
+        }
+    }
+    if (any) atomicOr(&o.flag[slot >> 2], 1u << (((int)(slot & 3) << 3) + run));
+}
+
+// one run (I, J) of a surviving triangle inside the chunk [k, k1); r = tests of
+// this triangle still to skip.  Returns false once the chunk is used up.
+template <int VAR, int I, int J, int RUN, bool INST>
+__device__ inline bool triad_run(const TriLists &T, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k,
+                                 int64_t k1, const TriadOut &o, int64_t slot, unsigned long long &acc, bool &ovf) {
+    Span l1, l2, l3;
+    if (!run_lists<VAR, I, J>(T, dq, l1, l2, l3)) return true;
+    if (r >= l1.n) {
+        r -= l1.n;
+        return true;
+    }
+    int64_t cnt = l1.n - r;
+    if (cnt > k1 - k) cnt = k1 - k;
+    triad_chunk<INST>(o, ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3, slot, RUN, acc, ovf);
+    k += cnt;
+    r = 0;
+    return k < k1;
+}
+
+// run numbers: (x0, x1), (x1, x0), (x0, x2), (x2, x0), (x1, x2), (x2, x1)
+template <int VAR, bool INST>
+__device__ inline void triad_runs(const TriLists &L, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k,
+                                  int64_t k1, const TriadOut &o, int64_t slot, unsigned long long &acc, bool &ovf) {
+    if (triad_run<VAR, 0, 1, 0, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf) &&
+        triad_run<VAR, 1, 0, 1, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf) &&
+        triad_run<VAR, 0, 2, 2, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf) &&
+        triad_run<VAR, 2, 0, 3, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf) &&
+        triad_run<VAR, 1, 2, 4, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf))
+        triad_run<VAR, 2, 1, 5, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf);
+}
+
+// The surviving runs' tests in flat chunks of ipt (the chunking of the count
+// kernel); total[0] += temporal triangles, total[1] = 1 on a 64-bit overflow.
+template <int VAR, bool INST>
+__global__ __launch_bounds__(BLK) void k_triad(const int64_t *__restrict__ wbase, int32_t NI,
+                                               const int64_t *__restrict__ base, const int32_t *__restrict__ su,
+                                               const int32_t *__restrict__ sv, const int64_t *__restrict__ sw,
+                                               const EdgeRec *__restrict__ rec, const int64_t *__restrict__ ts,
+                                               uint32_t dq, TriadOut o, int ipt, unsigned long long *total) {
+    const int64_t all = wbase[NI];
+    const int64_t nchunks = (all + ipt - 1) / ipt;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long acc = 0;
+    bool ovf = false;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
+        int64_t k = c * ipt;
+        const int64_t k1 = k + ipt < all ? k + ipt : all;
+        while (k < k1) {
+            const int64_t k_start = k;
+            int64_t a = 0, b = NI;
+            while (a < b) {
+                int64_t mid = (a + b) >> 1;
+                if (wbase[mid + 1] <= k) a = mid + 1;
+                else b = mid;
+            }
+            const int64_t u = a;
+            int64_t r = k - wbase[u];
+            const int64_t s0 = base[u];
+            const int32_t ns = su[u];
+            if (ns <= 0) break; // cannot happen when the offsets are consistent
+            int32_t lo = 0, hi = ns - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (sw[s0 + mid] <= r) lo = mid;
+                else hi = mid - 1;
+            }
+            r -= sw[s0 + lo];
+            for (int32_t s = lo; s < ns && k < k1; s++) {
+                const int64_t p = s0 + s;
+                TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
+                triad_runs<VAR, INST>(L, dq, ts, r, k, k1, o, p, acc, ovf);
+                r = 0;
+            }
+            if (k == k_start) break; // every survivor has tests, so this never triggers
+        }
+    }
+    if (INST) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long y = __shfl_xor(acc, off);
+            const int oy = __shfl_xor((int)ovf, off);
+            const unsigned long long s = acc + y;
+            ovf = ovf || oy || s < acc;
+            acc = s;
+        }
+        if (lane_id() == 0 && (acc || ovf)) {
+            const unsigned long long old = atomicAdd(&total[0], acc);
+            if (ovf || old + acc < old) atomicOr(&total[1], 1ull);
+        }
+    }
+}
+
+// solutions per flag word (optional) and their total
+__global__ __launch_bounds__(BLK) void k_triad_words(const uint32_t *__restrict__ flag, int64_t nw,
+                                                     int32_t *__restrict__ wcnt, unsigned long long *total) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = __popc(flag[i]);
+        if (wcnt) wcnt[i] = x;
+        c += (unsigned)x;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane_id() == 0 && c) atomicAdd(total, c);
+}
+
+// the endpoints (original ids) of oriented edge q: tail, head
+__device__ inline void oriented_ends(const uint32_t *__restrict__ oeid, const int32_t *__restrict__ slo,
+                                     const int32_t *__restrict__ shi, int32_t q, int32_t &tail, int32_t &head) {
+    const uint32_t x = oeid[q];
+    const uint32_t s = x & 0x7fffffffu;
+    const int32_t lo = slo[s], hi = shi[s];
+    tail = (x >> 31) ? lo : hi;
+    head = (x >> 31) ? hi : lo;
+}
+
+// each set bit as (w, its index, pair key a n + b), at the word's offset
+__global__ __launch_bounds__(BLK) void k_triad_emit(const uint32_t *__restrict__ flag, int64_t nw,
+                                                    const int64_t *__restrict__ woff, const int32_t *__restrict__ sv,
+                                                    const uint32_t *__restrict__ oeid, const int32_t *__restrict__ slo,
+                                                    const int32_t *__restrict__ shi, int64_t n,
+                                                    uint32_t *__restrict__ wkey, int32_t *__restrict__ idx,
+                                                    unsigned long long *__restrict__ pkey) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    uint32_t f = flag[i];
+    if (!f) return;
+    int64_t o = woff[i];
+    for (int j = 0; j < 4; j++) {
+        const uint32_t bits = (f >> (8 * j)) & 0x3fu;
+        if (!bits) continue;
+        const int64_t p = 4 * i + j;
+        int32_t x0, x1, x2, t;
+        oriented_ends(oeid, slo, shi, sv[3 * p], x0, x1);
+        oriented_ends(oeid, slo, shi, sv[3 * p + 1], t, x2);
+        // run -> (a, b, w): (x0,x1,x2) (x1,x0,x2) (x0,x2,x1) (x2,x0,x1) (x1,x2,x0) (x2,x1,x0)
+        const int32_t A[6] = {x0, x1, x0, x2, x1, x2};
+        const int32_t B[6] = {x1, x0, x2, x0, x2, x1};
+        const int32_t W[6] = {x2, x2, x1, x1, x0, x0};
+#pragma unroll
+        for (int run = 0; run < 6; run++) {
+            if (!((bits >> run) & 1u)) continue;
+            wkey[o] = (uint32_t)W[run];
+            idx[o] = (int32_t)o;
+            pkey[o] = (unsigned long long)A[run] * (unsigned long long)n + (unsigned long long)B[run];
+            o++;
+        }
+    }
+}
+
+__global__ void k_gather_u64(const unsigned long long *__restrict__ in, const int32_t *__restrict__ idx, int64_t k,
+                             unsigned long long *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) out[i] = in[idx[i]];
+}
+
+__global__ void k_triad_unpack(const unsigned long long *__restrict__ pkey, const uint32_t *__restrict__ w, int64_t k,
+                               int64_t n, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    const unsigned long long key = pkey[i];
+    out[3 * i] = (int32_t)(key / (unsigned long long)n);
+    out[3 * i + 1] = (int32_t)(key % (unsigned long long)n);
+    out[3 * i + 2] = (int32_t)w[i];
+}
+
+__global__ void k_scatter_u64(const unsigned long long *__restrict__ in, const int32_t *__restrict__ perm, int32_t m,
+                              unsigned long long *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) out[perm[k]] = in[k];
+}
+
+void check_triad(const Graph *g, const folty_triad_query &q) {
+    if (!g->ix.built) fail(FOLTY_ENOTBUILT, "folty_build_index has not been called for this graph");
+    if (q.delta < 0) fail(FOLTY_EINVAL, "delta must be >= 0 (got %lld)", (long long)q.delta);
+    if (q.variant > 7) fail(FOLTY_EINVAL, "variant must be 0..7 (got %u)", (unsigned)q.variant);
+    if (q.flags & ~(FOLTY_TRIAD_TRIPLES | FOLTY_TRIAD_INSTANCES | FOLTY_TRIAD_EDGE_INSTANCES))
+        fail(FOLTY_EINVAL, "unknown triad flags 0x%x", (unsigned)q.flags);
+    for (int i = 0; i < 6; i++)
+        if (q.reserved[i]) fail(FOLTY_EINVAL, "reserved fields of the triad query must be 0");
+}
+
+// the listed triples of nw flag words, sorted by (a, b, w), copied to res->trip
+void list_triples(const Index &ix, const Workspace &ws, int64_t nw, int64_t nsol, Result *res, hipStream_t s) {
+    if (nsol > INT32_MAX) fail(FOLTY_EOVERFLOW, "%lld solution triples exceed the listing limit of 2^31 - 1",
+                               (long long)nsol);
+    DevBuf wcnt, woff, wk, ix0, pk, wk2, ix2, pk2, trip;
+    wcnt.ensure(4 * (size_t)nw + 4);
+    woff.ensure(8 * (size_t)nw + 8);
+    unsigned long long *dummy = ws.scal.as<unsigned long long>() + 12;
+    k_fill<unsigned long long><<<1, 1, 0, s>>>(dummy, 0ull, 1);
+    k_triad_words<<<grid_for(nw, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), nw,
+                                                                     wcnt.as<int32_t>(), dummy);
+    FOLTY_LAUNCHED();
+    DevBuf cub;
+    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, wcnt.as<int32_t>(), woff.as<int64_t>(), nw, s);
+    const size_t k = (size_t)nsol;
+    const int endw = std::max(1, bit_length((uint64_t)ix.n - 1));
+    const int endp = std::max(1, bit_length((uint64_t)ix.n * (uint64_t)ix.n - 1));
+    need = std::max(need, sort_pairs_u32_i32(nullptr, 0, nullptr, nullptr, nullptr, nullptr, (int64_t)k, endw, s));
+    need = std::max(need, sort_pairs_u64_i32(nullptr, 0, nullptr, nullptr, nullptr, nullptr, (int64_t)k, endp, s));
+    cub.ensure(need);
+    exclusive_scan_i32_to_i64(cub.p, need, wcnt.as<int32_t>(), woff.as<int64_t>(), nw, s);
+    wk.ensure(4 * k);
+    ix0.ensure(4 * k);
+    pk.ensure(8 * k);
+    wk2.ensure(4 * k);
+    ix2.ensure(4 * k);
+    pk2.ensure(8 * k);
+    trip.ensure(12 * k);
+    k_triad_emit<<<grid_for(nw, BLK), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), nw, woff.as<int64_t>(),
+                                                   ws.sv.as<int32_t>(), ix.oeid.as<uint32_t>(), ix.slo.as<int32_t>(),
+                                                   ix.shi.as<int32_t>(), ix.n, wk.as<uint32_t>(), ix0.as<int32_t>(),
+                                                   pk.as<unsigned long long>());
+    FOLTY_LAUNCHED();
+    // by w, then stably by the pair key: (a, b, w) order
+    sort_pairs_u32_i32(cub.p, need, wk.as<uint32_t>(), wk2.as<uint32_t>(), ix0.as<int32_t>(), ix2.as<int32_t>(),
+                       (int64_t)k, endw, s);
+    k_gather_u64<<<grid_for((int64_t)k, BLK), BLK, 0, s>>>(pk.as<unsigned long long>(), ix2.as<int32_t>(),
+                                                           (int64_t)k, pk2.as<unsigned long long>());
+    FOLTY_LAUNCHED();
+    sort_pairs_u64_i32(cub.p, need, pk2.as<uint64_t>(), pk.as<uint64_t>(), wk2.as<int32_t>(), wk.as<int32_t>(),
+                       (int64_t)k, endp, s);
+    k_triad_unpack<<<grid_for((int64_t)k, BLK), BLK, 0, s>>>(pk.as<unsigned long long>(), wk.as<uint32_t>(),
+                                                             (int64_t)k, ix.n, trip.as<int32_t>());
+    FOLTY_LAUNCHED();
+    res->trip.resize(3 * k);
+    FOLTY_HIP(hipMemcpyAsync(res->trip.data(), trip.p, 12 * k, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+}
+
+} // namespace
+
+Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
+    check_triad(g, q);
+    if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
+    Index &ix = g->ix;
+    hipStream_t s = g->stream;
+    const bool edge = (q.flags & FOLTY_TRIAD_EDGE_INSTANCES) != 0;
+    const bool inst = edge || (q.flags & FOLTY_TRIAD_INSTANCES) != 0;
+    std::unique_ptr<Result> res(new Result());
+    res->triad = true;
+    res->device = g->device;
+    ws.ensure_events();
+    ws.scal.ensure(128);
+    ws.host.ensure(64);
+    FOLTY_HIP(hipEventRecord(ws.ev[0], s));
+    // [0] temporal triangles, [1] overflow, [2] solutions ([8, 12) belong to the filter)
+    unsigned long long *tot = ws.scal.as<unsigned long long>();
+    k_fill<unsigned long long><<<1, 4, 0, s>>>(tot, 0ull, 4);
+    FOLTY_LAUNCHED();
+    if (edge) {
+        ws.tinst.ensure(8 * (size_t)ix.m + 8);
+        if (ix.m > 0) {
+            k_fill<unsigned long long><<<grid_for(ix.m, BLK), BLK, 0, s>>>(ws.tinst.as<unsigned long long>(), 0ull,
+                                                                         ix.m);
+            FOLTY_LAUNCHED();
+        }
+    }
+    int64_t tests = 0, tri = 0, slots = 0;
+    if (ix.NI > 0) {
+        int64_t known = -1;
+        slots = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known);
+        if (slots > 0) {
+            const int64_t nw = (slots + 3) / 4;
+            ws.tflag.ensure(4 * (size_t)nw);
+            k_fill<uint32_t><<<grid_for(nw, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), 0u, nw);
+            FOLTY_LAUNCHED();
+            TriadOut o{q.delta, ws.tflag.as<uint32_t>(), edge ? ws.tinst.as<unsigned long long>() : nullptr};
+            const int ipt = known >= 0 && known < (int64_t)PERSIST_BLOCKS * BLK ? 1 : IPT;
+            const int64_t want = known < 0 ? PERSIST_BLOCKS : ((known + ipt - 1) / ipt + BLK - 1) / BLK;
+            const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PERSIST_BLOCKS));
+            const uint32_t dq = run_slack(range_slack(q.delta, ix.tshift));
+            dispatch_variant(q.variant, [&](auto V) {
+                constexpr int VAR = decltype(V)::value;
+                if (inst)
+                    k_triad<VAR, true><<<blocks, BLK, 0, s>>>(ws.wbase.as<int64_t>(), ix.NI, ws.slots,
+                                                             ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
+                                                             ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(),
+                                                             ix.ts.as<int64_t>(), dq, o, ipt, tot);
+                else
+                    k_triad<VAR, false><<<blocks, BLK, 0, s>>>(ws.wbase.as<int64_t>(), ix.NI, ws.slots,
+                                                              ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
+                                                              ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(),
+                                                              ix.ts.as<int64_t>(), dq, o, ipt, tot);
+            });
+            FOLTY_LAUNCHED();
+            k_triad_words<<<grid_for(nw, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), nw, nullptr,
+                                                                             tot + 2);
+            FOLTY_LAUNCHED();
+            FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
+        }
+    } else {
+        FOLTY_HIP(hipEventRecord(ws.ev[4], s));
+        FOLTY_HIP(hipEventRecord(ws.ev[5], s));
+    }
+    if (ix.T < 0) ix.T = tri;
+    FOLTY_HIP(hipEventRecord(ws.ev[2], s));
+    unsigned long long *h = ws.host.as<unsigned long long>();
+    FOLTY_HIP(hipMemcpyAsync(h, tot, 24, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipStreamSynchronize(s));
+    if (h[1] || h[0] > (unsigned long long)INT64_MAX)
+        fail(FOLTY_EOVERFLOW, "the temporal triangles number 2^63 or more");
+    res->n_triads = (int64_t)h[2];
+    res->n_tinst = inst ? (int64_t)h[0] : -1;
+    if ((q.flags & FOLTY_TRIAD_TRIPLES) && res->n_triads > 0)
+        list_triples(ix, ws, (slots + 3) / 4, res->n_triads, res.get(), s);
+    FOLTY_HIP(hipEventRecord(ws.ev[3], s));
+    if (edge) {
+        DevBuf out;
+        out.ensure(8 * (size_t)ix.m_input + 8);
+        if (ix.m_input > 0) {
+            k_fill<unsigned long long><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(out.as<unsigned long long>(), 0ull,
+                                                                               ix.m_input);
+            FOLTY_LAUNCHED();
+        }
+        if (ix.m > 0) {
+            k_scatter_u64<<<grid_for(ix.m, BLK), BLK, 0, s>>>(ws.tinst.as<unsigned long long>(),
+                                                              ix.perm.as<int32_t>(), ix.m,
+                                                              out.as<unsigned long long>());
+            FOLTY_LAUNCHED();
+        }
+        res->tinst.resize((size_t)ix.m_input);
+        if (ix.m_input > 0)
+            FOLTY_HIP(hipMemcpyAsync(res->tinst.data(), out.p, 8 * (size_t)ix.m_input, hipMemcpyDeviceToHost, s));
+    }
+    FOLTY_HIP(hipStreamSynchronize(s));
+    fill_stats_from_index(ix, &res->stats);
+    res->stats.tests = tests;
+    res->stats.wedge_ms = ev_ms(ws.ev[4], ws.ev[5]);
+    res->stats.temporal_ms = ev_ms(ws.ev[5], ws.ev[2]);
+    res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
+    res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
+    return res.release();
+}
+
+} // namespace folty

@@ -27,6 +27,7 @@ U32_MAX = 0xFFFFFFFF
 EXPORTS = (
     "folty_last_error", "folty_version", "folty_load_temporal_graph", "folty_build_index",
     "folty_run_fol_query", "folty_run_vertex_query", "folty_result_vertices",
+    "folty_run_triad_query", "folty_result_triads", "folty_result_edge_instances",
     "folty_workspace_create", "folty_workspace_free",
     "folty_run_fol_query_ws", "folty_run_batch", "folty_run_multi", "folty_result_pairs",
     "folty_result_counts", "folty_result_stats", "folty_result_free", "folty_graph_stats",
@@ -104,6 +105,14 @@ class Stats(ctypes.Structure):
 _lib = None
 
 
+TRIAD_TRIPLES, TRIAD_INSTANCES, TRIAD_EDGE_INSTANCES = 1, 2, 4
+
+
+class TriadQuery(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_int64), ("variant", ctypes.c_uint8), ("flags", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8 * 6)]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     """Load the HIP library; raises if it has not been built."""
     global _lib
@@ -128,6 +137,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.folty_run_fol_query.argtypes = [P, ctypes.POINTER(Query), PP]
     lib.folty_run_vertex_query.argtypes = [P, ctypes.POINTER(VertexQuery), PP]
     lib.folty_result_vertices.argtypes = [P, ctypes.POINTER(I64), PP, PP]
+    lib.folty_run_triad_query.argtypes = [P, ctypes.POINTER(TriadQuery), PP]
+    lib.folty_result_triads.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), PP]
+    lib.folty_result_edge_instances.argtypes = [P, PP]
     lib.folty_workspace_create.argtypes = [PP]
     lib.folty_workspace_free.argtypes = [P]
     lib.folty_workspace_free.restype = None
@@ -253,6 +265,29 @@ class Result:
         return (np.ctypeslib.as_array(ctypes.cast(v, ctypes.POINTER(ctypes.c_int32)), (k,)).copy(),
                 np.ctypeslib.as_array(ctypes.cast(g, ctypes.POINTER(ctypes.c_uint32)), (k,)).copy())
 
+    def triads(self) -> dict:
+        """Exists-exists-exists result: solution triples (k x 3, sorted by (a, b, w),
+        None unless listed), their number, and the temporal triangles (-1 if not counted)."""
+        ns, ni, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_void_p()
+        _check(load_library().folty_result_triads(self._h, ctypes.byref(ns), ctypes.byref(ni),
+                                                  ctypes.byref(p)))
+        trip = None
+        if p.value:
+            trip = np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_int32)),
+                                         (ns.value, 3)).copy()
+        elif ns.value == 0:
+            trip = np.zeros((0, 3), np.int32)
+        return dict(n_solutions=ns.value, n_instances=ni.value, triples=trip)
+
+    def edge_instances(self) -> np.ndarray:
+        """Temporal triangles per first edge, input order (0 for a self-loop)."""
+        p = ctypes.c_void_p()
+        _check(load_library().folty_result_edge_instances(self._h, ctypes.byref(p)))
+        m = int(self.stats["m_input"])
+        if m == 0:
+            return np.zeros(0, np.uint64)
+        return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint64)), (m,)).copy()
+
     def close(self):
         if self._h:
             load_library().folty_result_free(self._h)
@@ -330,6 +365,18 @@ class Graph:
         vq.inner = int(inner)
         out = ctypes.c_void_p()
         _check(load_library().folty_run_vertex_query(self._h, ctypes.byref(vq), ctypes.byref(out)))
+        return Result(out)
+
+    def triad_query(self, delta, variant=0, triples=True, instances=True,
+                    edge_instances=False) -> Result:
+        """exists u exists v exists w: solution triples and temporal triangles."""
+        q = TriadQuery()
+        q.delta = int(delta)
+        q.variant = int(variant)
+        q.flags = ((TRIAD_TRIPLES if triples else 0) | (TRIAD_INSTANCES if instances else 0)
+                   | (TRIAD_EDGE_INSTANCES if edge_instances else 0))
+        out = ctypes.c_void_p()
+        _check(load_library().folty_run_triad_query(self._h, ctypes.byref(q), ctypes.byref(out)))
         return Result(out)
 
     def query_raw(self, q: Query) -> Result:

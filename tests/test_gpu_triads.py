@@ -1,0 +1,200 @@
+"""GPU parity of the exists-exists-exists query against the CPU oracle.
+
+Integer work throughout: the solution triples (sorted), their number, the
+temporal triangle count and the per-edge counts must equal the oracle's exactly.
+"""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2507_17215_amd import folty, synth
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "triad_cases.json")
+INF = folty.DELTA_INF
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def assert_triads(G, o, delta, variant, edge=True):
+    r = G.triad_query(delta, variant, triples=True, instances=True, edge_instances=edge)
+    t = r.triads()
+    want = o.triad_solutions(delta, variant)
+    assert t["n_solutions"] == want.shape[0], (t["n_solutions"], want.shape[0])
+    assert np.array_equal(t["triples"], want), "solution triples differ"
+    inst = o.triad_instances(delta, variant)
+    assert t["n_instances"] == int(inst.sum())
+    if edge:
+        got = r.edge_instances()
+        bad = np.nonzero(got != inst)[0]
+        assert bad.size == 0, f"{bad.size} per-edge mismatches, first {bad[:5]}: {got[bad[:5]]} vs {inst[bad[:5]]}"
+    # the solution count alone (no listing, no temporal triangles) agrees
+    r2 = G.triad_query(delta, variant, triples=False, instances=False).triads()
+    assert r2["n_solutions"] == want.shape[0] and r2["n_instances"] == -1
+    return t
+
+
+def test_triad_hand_cases():
+    d = json.load(open(GOLD))
+    e = np.array(d["graph"]["edges"], dtype=np.int64)
+    G = folty.Graph(d["graph"]["n"], e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2]).build()
+    for c in d["cases"]:
+        say("hand", c)
+        r = G.triad_query(c["delta"], c["variant"], edge_instances=True)
+        t = r.triads()
+        assert t["triples"].tolist() == c["triples"]
+        assert r.edge_instances().tolist() == c["instances"]
+        assert t["n_instances"] == sum(c["instances"])
+
+
+def test_triads_random_tiny_all_variants():
+    rng = np.random.default_rng(123)
+    for it in range(40):
+        g = synth.random_small(rng, n_max=14, m_max=120, t_max=25)
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+        for variant in range(8):
+            for delta in (0, 1, 5, INF):
+                say("tiny", it, variant, delta)
+                assert_triads(G, o, delta, variant)
+
+
+def test_triads_tiny_workload_modes_and_orientations():
+    """Two-pass filter on a fresh index, the one-pass filter once a plan made the
+    per-item triangle offsets, the cached triangle list, and other orientations:
+    all equal the oracle."""
+    g = synth.tiny(seed=11)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    cases = [(3600, 0), (86400, 1), (10**6, 3), (INF, 6), (600, 5)]
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    for d, v in cases:
+        say("two-pass", d, v)
+        assert_triads(G, o, d, v)
+    folty.Plan([G], [(0, dict(delta=3600, theta=(1, 2), variant=0))])
+    for d, v in cases:
+        say("one-pass", d, v)
+        assert_triads(G, o, d, v)
+    Gc = folty.Graph(g.n, g.src, g.dst, g.t).build(cache_triangles=True)
+    for mode, seed in ((folty.RANK_DEGREE, 0), (folty.RANK_RANDOM, 3)):
+        Gr = folty.Graph(g.n, g.src, g.dst, g.t).build(rank_mode=mode, rank_seed=seed)
+        for d, v in cases[:3]:
+            say("cached / rank", mode, d, v)
+            assert_triads(Gc, o, d, v, edge=False)
+            assert_triads(Gr, o, d, v, edge=False)
+
+
+def test_triads_long_out_rows():
+    """A hub with ~1500 neighbours under a random order (its out-row exceeds the
+    rows staged in LDS)."""
+    rng = np.random.default_rng(17)
+    g = synth.tiny(seed=23)
+    hub_dst = rng.choice(np.arange(8, g.n, dtype=np.int32), size=1500, replace=False)
+    flip = rng.random(1500) < 0.5
+    hub = np.full(1500, 7, np.int32)
+    src = np.concatenate([g.src, np.where(flip, hub_dst, hub)]).astype(np.int32)
+    dst = np.concatenate([g.dst, np.where(flip, hub, hub_dst)]).astype(np.int32)
+    t = np.concatenate([g.t, rng.integers(0, 1_000_000, 1500)]).astype(np.int64)
+    o = Oracle(g.n, src, dst, t)
+    G = folty.Graph(g.n, src, dst, t).build(rank_mode=folty.RANK_RANDOM, rank_seed=5)
+    assert G.stats()["max_out_degree"] > 512
+    for v in (0, 6):
+        say("long rows", v)
+        assert_triads(G, o, 10**6, v)
+
+
+def test_triads_dense_multigraph():
+    """Few vertices, many parallel edges: long lists, so single runs span many
+    chunks and the per-edge windows hold many entries."""
+    rng = np.random.default_rng(5)
+    n, m = 12, 6000
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    t = rng.integers(0, 50_000, m).astype(np.int64)
+    o = Oracle(n, src, dst, t)
+    G = folty.Graph(n, src, dst, t).build()
+    for d, v in ((0, 0), (10, 0), (300, 1), (5000, 6), (INF, 3)):
+        say("dense", d, v)
+        assert_triads(G, o, d, v)
+
+
+def test_triads_edge_cases_and_errors():
+    say("empty graph")
+    G = folty.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64)).build()
+    t = G.triad_query(10, 0, edge_instances=True).triads()
+    assert t["n_solutions"] == 0 and t["n_instances"] == 0 and t["triples"].shape == (0, 3)
+    say("only self-loops")
+    G = folty.Graph(3, np.array([1, 1, 2], np.int32), np.array([1, 1, 2], np.int32), np.array([0, 5, 9])).build()
+    r = G.triad_query(10, 0, edge_instances=True)
+    assert r.triads()["n_solutions"] == 0 and r.edge_instances().tolist() == [0, 0, 0]
+    say("no triangles")
+    G = folty.Graph(4, np.array([0, 1, 2], np.int32), np.array([1, 2, 3], np.int32), np.array([0, 1, 2])).build()
+    assert G.triad_query(INF, 0).triads()["n_solutions"] == 0
+    say("timestamps near 2^62")
+    big = (1 << 62) - 10
+    e = np.array([[0, 1, big - 5], [0, 2, big - 3], [1, 2, big - 1], [1, 1, big]], dtype=np.int64)
+    G = folty.Graph(3, e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2]).build()
+    for d, want in ((INF, 1), (4, 1), (3, 0)):
+        r = G.triad_query(d, 0, edge_instances=True)
+        assert r.triads()["n_solutions"] == want
+        assert r.edge_instances().tolist() == [want, 0, 0, 0]
+    say("errors")
+    lib = folty.load_library()
+    for kw in (dict(delta=-1), dict(delta=5, variant=8)):
+        with pytest.raises(folty.FoltyError) as ei:
+            G.triad_query(**kw)
+        assert ei.value.code == folty.EINVAL
+    out = ctypes.c_void_p()
+    for flags, res in ((8, 0), (0, 1)):
+        q = folty.TriadQuery()
+        q.delta, q.flags = 5, flags
+        q.reserved[0] = res
+        assert lib.folty_run_triad_query(G._h, ctypes.byref(q), ctypes.byref(out)) == folty.EINVAL
+    G2 = folty.Graph(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([0, 4]))
+    with pytest.raises(folty.FoltyError) as ei:
+        G2.triad_query(5)
+    assert ei.value.code == folty.ENOTBUILT
+    pr = G.query(5, (1, 2))
+    with pytest.raises(folty.FoltyError) as ei:
+        pr.triads()
+    assert ei.value.code == folty.EINVAL
+    with pytest.raises(folty.FoltyError) as ei:
+        G.triad_query(5, 0, edge_instances=False).edge_instances()
+    assert ei.value.code == folty.EINVAL
+
+
+def test_triads_unsorted_input_and_repeat():
+    g = synth.tiny(seed=9)
+    order = np.random.default_rng(1).permutation(g.m)
+    G1 = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    G2 = folty.Graph(g.n, g.src[order], g.dst[order], g.t[order]).build()
+    say("shuffled input")
+    a = G1.triad_query(86400, 0, edge_instances=True)
+    b = G2.triad_query(86400, 0, edge_instances=True)
+    assert np.array_equal(a.triads()["triples"], b.triads()["triples"])
+    assert np.array_equal(a.edge_instances()[order], b.edge_instances())
+    for rep in range(3):
+        c = G1.triad_query(86400, 0, edge_instances=True)
+        assert np.array_equal(c.triads()["triples"], a.triads()["triples"])
+        assert np.array_equal(c.edge_instances(), a.edge_instances())
+
+
+@pytest.mark.timeout(900)
+def test_triads_medium_workload():
+    """n=1M, m=10M: full triples, temporal triangles and per-edge counts at a
+    1e6-second window and at one year (7.2 million solution triples)."""
+    say("medium: generate")
+    g = synth.medium()
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    for d, v in ((10**6, 0), (synth.YEAR_S, 0), (86400, 6)):
+        say("medium", d, v)
+        t = assert_triads(G, o, d, v)
+        say("medium", d, v, "solutions", t["n_solutions"], "temporal triangles", t["n_instances"],
+            "query ms", G.triad_query(d, v, triples=False).stats["query_ms"])
