@@ -242,6 +242,52 @@ def serving_section(folty, synth, full):
     return out
 
 
+def triads_section(folty, G, oracle, g, n, rng, deltas):
+    """Exists-exists-exists queries (solution triples and temporal triangles) on
+    the same index, predicate 0; sampled parity against the oracle: the third
+    vertices of sampled directed pairs, and the temporal triangles of sampled
+    first edges."""
+    res = {}
+    loop = g.src == g.dst
+    for d in deltas:
+        rc = G.triad_query(d, 0, triples=False, instances=False)  # the solution count alone
+        r = G.triad_query(d, 0, triples=True, instances=True, edge_instances=True)
+        t = r.triads()
+        inst = r.edge_instances()
+        trip = t["triples"]
+        key = trip[:, 0].astype(np.int64) * n + trip[:, 1] if trip is not None else np.zeros(0, np.int64)
+        # pairs: some with solutions, some uniform over the edges' pairs
+        pk = np.unique(key)
+        ek = g.src[~loop].astype(np.int64) * n + g.dst[~loop]
+        pick = np.union1d(rng.choice(pk, size=min(200, pk.size), replace=False) if pk.size else pk,
+                          rng.choice(ek, size=min(200, ek.size), replace=False))
+        bad = 0
+        for k in pick.tolist():
+            lo, hi = np.searchsorted(key, k), np.searchsorted(key, k, side="right")
+            want = oracle.triad_pair(k // n, k % n, d, 0)
+            bad += int(not np.array_equal(trip[lo:hi, 2] if trip is not None else want[:0], want))
+        # first edges: uniform plus ones the GPU counts as non-zero
+        nz = np.nonzero(inst)[0]
+        idx = np.union1d(rng.choice(g.m, size=min(2000, g.m), replace=False),
+                         rng.choice(nz, size=min(2000, nz.size), replace=False) if nz.size else nz)
+        ebad = int((oracle.triad_instances(d, 0, idx) != inst[idx]).sum())
+        sums_ok = int(inst.sum()) == t["n_instances"] and (trip is None or trip.shape[0] == t["n_solutions"]) \
+            and rc.triads()["n_solutions"] == t["n_solutions"]
+        mism = bad + ebad + (0 if sums_ok else 1)
+        res[str(d)] = {"predicate": 0, "solution_triples": t["n_solutions"], "temporal_triangles": t["n_instances"],
+                       "count_only_query_ms": rc.stats["query_ms"], "count_only_temporal_ms": rc.stats["temporal_ms"],
+                       "query_ms": r.stats["query_ms"], "wedge_ms": r.stats["wedge_ms"],
+                       "temporal_ms": r.stats["temporal_ms"], "listing_ms": r.stats["threshold_ms"],
+                       "tests": r.stats["tests"], "checked_pairs": int(pick.size), "pair_mismatches": bad,
+                       "checked_edges": int(idx.size), "edge_mismatches": ebad, "totals_consistent": sums_ok,
+                       "mismatches": mism}
+        log(f"triads delta={d}: {t['n_solutions']} solution triples, {t['n_instances']} temporal triangles; "
+            f"count only {rc.stats['query_ms']:.2f} ms, with triangles and listing {r.stats['query_ms']:.2f} ms "
+            f"(listing {r.stats['threshold_ms']:.2f}); {bad} pair and {ebad} edge mismatches over "
+            f"{pick.size} pairs and {idx.size} edges")
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -410,6 +456,8 @@ def main():
             log(f"{name}: {verts.size} solution vertices in {rv.stats['query_ms']:.2f} ms; "
                 f"{bad} mismatches over {pick.size} sampled vertices ({w['edges_counted']} edges counted by the oracle)")
         out["vertex_queries"] = vq
+        out["triads"] = triads_section(folty, G, oracle, g, n, rng, (a.delta, 86_400, synth.YEAR_S))
+        ok = ok and all(v["mismatches"] == 0 for v in out["triads"].values())
         G.close()
         out["parity_sampled"] = {"bit_exact": ok, "deltas": checked}
         # the same index queried at wider windows (device times; per-edge counts kept)
