@@ -492,3 +492,67 @@ def test_triad_bad_arguments_rejected():
         o.triad_instances(-1, 0)
     with pytest.raises(ValueError):
         o.triad_solutions(5, 8)
+
+
+# -- the in-neighbour mechanism: interval lists and segment trees ----------------------
+from oracle import intervals as iv  # noqa: E402
+
+
+def test_segment_tree_worked_example():
+    """The appendix's running example: one vertex's intervals [6, 13] and [8, 10]
+    count once at t = 9 in either insertion order; a second vertex's [8, 14]
+    makes it two."""
+    ts = [1, 3, 5, 7, 9, 10, 12, 15]
+    for order in ([(6, 13), (8, 10)], [(8, 10), (6, 13)]):
+        T = iv.SegmentTree(ts)
+        T.insert_list(order, 0)
+        assert T.lookup(9) == 1
+        assert [T.lookup(x) for x in ts] == [0, 0, 0, 1, 1, 1, 1, 0]
+        T.insert_list([(8, 14)], 1)
+        assert T.lookup(9) == 2
+        assert [T.lookup(x) for x in ts] == [0, 0, 0, 1, 2, 2, 2, 0]
+
+
+def test_segment_tree_counts_distinct_vertices():
+    """Brute force: after every vertex's list, lookup(t) is the number of
+    vertices with at least one interval containing t."""
+    rng = np.random.default_rng(77)
+    for it in range(300):
+        ts = np.unique(rng.integers(0, 60, rng.integers(1, 25))).tolist()
+        T = iv.SegmentTree(ts)
+        lists = {}
+        for z in range(int(rng.integers(1, 7))):
+            L = []
+            for _ in range(int(rng.integers(0, 6))):
+                a = int(rng.integers(-5, 65))
+                L.append((a, a + int(rng.integers(0, 30))))
+            rng.shuffle(L)
+            lists[z] = L
+            T.insert_list(L, z)
+        for x in ts:
+            want = sum(1 for L in lists.values() if any(a <= x <= b for a, b in L))
+            assert T.lookup(x) == want, (it, x)
+
+
+def test_interval_theorem_and_segment_trees_give_the_counts():
+    """The in-neighbour theorem (an edge forms a triangle with w iff an interval
+    of I(w) contains its time) and the segment-tree counts equal the counts of
+    the definition, for every predicate code."""
+    rng = np.random.default_rng(2024)
+    for it in range(60):
+        g = synth.random_small(rng)
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        for variant in range(8):
+            for delta in (0, 1, 5, INF):
+                want = o.counts(delta, variant).tolist()
+                assert iv.counts_via_intervals(g.n, g.src, g.dst, g.t, delta, variant) == want
+                assert iv.counts_via_segment_trees(g.n, g.src, g.dst, g.t, delta, variant) == want
+
+
+def test_interval_list_closed_form():
+    # L2 = {0, 10}, L3 = {4, 30}: t2 = 0 -> t3 = 4, interval [4 - d, 0] for d >= 4;
+    # t2 = 10 -> t3 = 30, interval [30 - d, 10] for d >= 20
+    assert iv.interval_list([0, 10], [4, 30], 3) == []
+    assert iv.interval_list([0, 10], [4, 30], 4) == [(0, 0)]
+    assert iv.interval_list([0, 10], [4, 30], 25) == [(0, 0), (5, 10)]
+    assert iv.interval_list([5], [], 100) == []
