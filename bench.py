@@ -288,6 +288,45 @@ def triads_section(folty, G, oracle, g, n, rng, deltas):
     return res
 
 
+def smaller_side_section(folty, synth, G, oracle, g, rng, k):
+    """The smaller-side evaluation (runs with a shorter L2 counted from the
+    in-neighbour intervals) against the default one: identical counts over all
+    edges, sampled edges against the oracle, and the temporal-step times; on this
+    graph at one year and on a multiplicity-skewed graph."""
+    from oracle.oracle import Oracle
+
+    def compare(Gx, ox, gx, name, d, variant=0):
+        r0 = Gx.query(d, (1, 10), variant)
+        r1 = Gx.query(d, (1, 10), variant, smaller_side=True)
+        c0, c1 = r0.counts(), r1.counts()
+        diff = int((c0 != c1).sum())
+        nz = np.nonzero((c1 != 0xFFFFFFFF) & (c1 > 0))[0]
+        idx = np.union1d(rng.choice(gx.m, size=min(k, gx.m), replace=False),
+                         rng.choice(nz, size=min(k, nz.size), replace=False) if nz.size else nz)
+        bad = int((ox.counts(d, variant, idx) != c1[idx]).sum())
+        same_pairs = r0.pairs() == r1.pairs() and r0.n_certificates == r1.n_certificates
+        row = {"delta": d, "predicate": variant, "tests": r1.stats["tests"],
+               "temporal_ms_default": r0.stats["temporal_ms"], "temporal_ms_smaller_side": r1.stats["temporal_ms"],
+               "query_ms_default": r0.stats["query_ms"], "query_ms_smaller_side": r1.stats["query_ms"],
+               "counts_differing_from_default": diff, "oracle_checked_edges": int(idx.size),
+               "oracle_mismatches": bad, "mismatches": diff + bad + (0 if same_pairs else 1)}
+        log(f"smaller side, {name} delta={d}: temporal {r0.stats['temporal_ms']:.2f} ms by E_ab, "
+            f"{r1.stats['temporal_ms']:.2f} ms from the smaller side; {diff} counts differ, {bad} oracle "
+            f"mismatches over {idx.size} edges")
+        return row
+
+    res = {"large/31536000": compare(G, oracle, g, "large", synth.YEAR_S)}
+    gs = synth.skewed()
+    os_ = Oracle(gs.n, gs.src, gs.dst, gs.t, threads=len(os.sched_getaffinity(0)))
+    Gs = folty.Graph(gs.n, gs.src, gs.dst, gs.t).build()
+    for d in (86_400, synth.YEAR_S):
+        res[f"skewed/{d}"] = compare(Gs, os_, gs, "skewed", d)
+    res["skewed_workload"] = {"n": gs.n, "m": gs.m, **gs.meta, "mismatches": 0}
+    Gs.close()
+    os_.close()
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -457,6 +496,8 @@ def main():
                 f"{bad} mismatches over {pick.size} sampled vertices ({w['edges_counted']} edges counted by the oracle)")
         out["vertex_queries"] = vq
         out["triads"] = triads_section(folty, G, oracle, g, n, rng, (a.delta, 86_400, synth.YEAR_S))
+        out["smaller_side"] = smaller_side_section(folty, synth, G, oracle, g, rng, a.parity_sample)
+        ok = ok and all(v["mismatches"] == 0 for v in out["smaller_side"].values())
         ok = ok and all(v["mismatches"] == 0 for v in out["triads"].values())
         G.close()
         out["parity_sampled"] = {"bit_exact": ok, "deltas": checked}

@@ -104,6 +104,16 @@ typedef struct {
  * gives |Sol| only).  Saves 4 bytes per input edge of device memory and a pass. */
 #define FOLTY_QUERY_NO_COUNTS 1u
 
+/* Query flag: evaluate each run (triangle, list E_{a,b}) from the shorter of
+ * E_{a,b} and the list L2 of edge 2.  From L2 the run uses the paper's in-neighbour
+ * intervals (an edge e on E_{a,b} forms a triangle with w iff some entry t2 of L2,
+ * whose first L3 entry t3 >= t2 lies within delta, has t3 - delta <= t(e) <= t2),
+ * marking their union as edge ranges in a difference array that is prefix-summed
+ * into the counts.  Results are identical; it pays on graphs whose E_{a,b} lists
+ * are much longer than the lists that close them, and costs 4 bytes per edge of
+ * scratch and one scan.  Batched plans and the server ignore it. */
+#define FOLTY_QUERY_SMALLER_SIDE 2u
+
 /* Sizes and timings of a graph's index (folty_graph_stats) or of one query
  * (folty_result_stats; then the graph fields are copied in as well). */
 typedef struct {

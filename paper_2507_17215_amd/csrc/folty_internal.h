@@ -219,6 +219,7 @@ struct Workspace {
     DevBuf cub;     // library scan/sort temporaries
     DevBuf ilist;   // int32[NI] items with survivors
     DevBuf vtmp;    // vertex queries: per-vertex counts, flags, offsets, output
+    DevBuf diff;    // int32[2m+1] interval marks of the smaller-side evaluation and their prefix sum
     DevBuf tflag;   // exists-exists-exists: uint32[(survivor slots + 3) / 4] solution bits
     DevBuf tinst;   // exists-exists-exists: uint64[m] temporal triangles per first edge
     PinnedBuf host;

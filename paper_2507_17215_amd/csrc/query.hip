@@ -227,6 +227,12 @@ __global__ void k_pairs_compact(const uint32_t *__restrict__ ncert, int32_t S, c
     }
 }
 
+// count[e] += the prefix sum of the interval marks at e
+__global__ void k_add_counts(const int32_t *__restrict__ ps, int32_t m, uint32_t *__restrict__ count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        count[e] += (uint32_t)ps[e];
+}
+
 __global__ void k_counts_scatter(const uint32_t *__restrict__ count, const int32_t *__restrict__ perm, int32_t m,
                                  uint32_t *__restrict__ out) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -385,14 +391,14 @@ namespace {
 // tests < 0: unknown on the host, the full persistent grid; else a thread per
 // chunk, and chunks of one test when there are few (each chunk's searches are a
 // chain of dependent loads, so few tests are done fastest all at once)
-template <class Op>
+template <class Op, bool SS = false>
 void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, int64_t tests,
                      hipStream_t s) {
     const int ipt = tests >= 0 && tests < (int64_t)PERSIST_BLOCKS * BLK ? 1 : IPT;
     const int64_t want = tests < 0 ? PERSIST_BLOCKS : ((tests + ipt - 1) / ipt + BLK - 1) / BLK;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PERSIST_BLOCKS));
     dispatch_variant(variant, [&](auto V) {
-        k_temporal<decltype(V)::value, Op><<<blocks, BLK, 0, s>>>(
+        k_temporal<decltype(V)::value, Op, SS><<<blocks, BLK, 0, s>>>(
             ws.wbase.as<int64_t>(), ix.NI, ws.slots, ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
             ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(),
             run_slack(range_slack(dmax, ix.tshift)), op, ipt);
@@ -715,7 +721,8 @@ void check_query(const Graph *g, const folty_query &q) {
     if (q.exclude_other > 1) fail(FOLTY_EINVAL, "exclude_other must be 0 or 1");
     if (q.exclude_other && q.universe == FOLTY_UNIVERSE_COMMON)
         fail(FOLTY_EINVAL, "exclude_other applies to the N(a) and N(b) universes only");
-    if (q.flags & ~FOLTY_QUERY_NO_COUNTS) fail(FOLTY_EINVAL, "unknown query flags 0x%x", (unsigned)q.flags);
+    if (q.flags & ~(FOLTY_QUERY_NO_COUNTS | FOLTY_QUERY_SMALLER_SIDE))
+        fail(FOLTY_EINVAL, "unknown query flags 0x%x", (unsigned)q.flags);
 }
 
 Result *run_query(Graph *g, const folty_query &q, Workspace &ws) { return run_query_on(g, q, ws, g->stream); }
@@ -766,8 +773,23 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
         int64_t known = -1;
         const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known);
         if (survivors > 0) {
-            DirectOp op{q.delta, count};
-            launch_temporal(ix, q.variant, q.delta, ws, op, known, s);
+            if (q.flags & FOLTY_QUERY_SMALLER_SIDE) {
+                // runs with a shorter L2 mark edge ranges in diff; its prefix sum is added at the end
+                ws.diff.ensure(4 * (2 * (size_t)ix.m + 1));
+                int32_t *diff = ws.diff.as<int32_t>(), *ps = diff + ix.m + 1;
+                k_fill<int32_t><<<grid_for(ix.m + 1, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(diff, 0, ix.m + 1);
+                FOLTY_LAUNCHED();
+                DirectOp op{q.delta, count, diff};
+                launch_temporal<DirectOp, true>(ix, q.variant, q.delta, ws, op, known, s);
+                size_t need = inclusive_scan_i32(nullptr, 0, diff, ps, ix.m, s);
+                ws.cub.ensure(need);
+                inclusive_scan_i32(ws.cub.p, need, diff, ps, ix.m, s);
+                k_add_counts<<<grid_for(ix.m, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ps, ix.m, count);
+                FOLTY_LAUNCHED();
+            } else {
+                DirectOp op{q.delta, count};
+                launch_temporal(ix, q.variant, q.delta, ws, op, known, s);
+            }
             FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
         }
     } else {

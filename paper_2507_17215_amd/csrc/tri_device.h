@@ -211,6 +211,7 @@ __device__ inline int32_t lower_bound_from(const int64_t *__restrict__ L, int32_
 struct DirectOp {
     int64_t delta;
     uint32_t *count;
+    int32_t *diff = nullptr; // per sorted edge + 1: +1 / -1 at the ends of edge ranges (interval evaluation)
     __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
                                       const Span &l3) const {
         const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
@@ -225,6 +226,37 @@ struct DirectOp {
             c3 = lower_bound_from(L3, c3, l3.n, t2);
             if (c3 == l3.n) break;
             if (L3[c3] - t <= delta) atomicAdd(&count[e], 1u);
+        }
+    }
+
+    // The same run evaluated from L2 (paper, the in-neighbour theorem: e forms
+    // a triangle with w iff some entry t2 of L2, with t3 the first entry of L3
+    // at or after t2 and t3 - t2 <= delta, has t3 - delta <= t(e) <= t2).
+    // Those intervals have non-decreasing ends, so entry j adds exactly the
+    // times in [max(t3 - delta, t2' + 1), t2] (t2' the entry before it) to the
+    // union of the earlier ones; each such piece is a range of L1 marked +1 / -1
+    // in diff, whose prefix sum over the sorted edges adds one per third vertex.
+    // Entries [j0, j0 + cnt) of L2.
+    __device__ inline void iv(const int64_t *__restrict__ ts, const Span &l1, int32_t j0, int32_t cnt,
+                              const Span &l2, const Span &l3) const {
+        const int64_t *L1 = ts + l1.s, *L2 = ts + l2.s, *L3 = ts + l3.s;
+        int32_t c3 = 0, a = 0, b = 0;
+        for (int32_t q = 0; q < cnt; q++) {
+            const int32_t j = j0 + q;
+            const int64_t t2 = L2[j];
+            c3 = lower_bound_from(L3, c3, l3.n, t2);
+            if (c3 == l3.n) break; // no t3 for this or any later entry
+            const int64_t t3 = L3[c3];
+            if (t3 - t2 > delta) continue; // an empty interval
+            int64_t lo = t3 - delta;
+            if (j > 0 && L2[j - 1] + 1 > lo) lo = L2[j - 1] + 1;
+            if (lo > t2) continue;
+            a = lower_bound_from(L1, a, l1.n, lo);
+            b = lower_bound_from(L1, a > b ? a : b, l1.n, t2 + 1);
+            if (a < b) {
+                atomicAdd(&diff[l1.s + a], 1);
+                atomicAdd(&diff[l1.s + b], -1);
+            }
         }
     }
 };
@@ -264,8 +296,11 @@ struct PoolOp {
 };
 
 // one run of a surviving triangle within the chunk [k, k1); r = tests of this
-// triangle still to skip.  Returns false once the chunk is used up.
-template <int VAR, int I, int J, class Op>
+// triangle still to skip.  Returns false once the chunk is used up.  With SS a
+// run whose L2 is shorter than L1 is evaluated from L2: the chunk's share of the
+// run's |L1| tests, [r, r + cnt), takes the entries [r |L2| / |L1|, (r + cnt)
+// |L2| / |L1|) of L2, so the run's chunks split L2 exactly.
+template <int VAR, int I, int J, class Op, bool SS = false>
 __device__ inline bool chunk_run(const TriLists &T, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k,
                                  int64_t k1, const Op &op) {
     Span l1, l2, l3;
@@ -276,7 +311,16 @@ __device__ inline bool chunk_run(const TriLists &T, uint32_t dq, const int64_t *
     }
     int64_t cnt = l1.n - r;
     if (cnt > k1 - k) cnt = k1 - k;
-    op(ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3);
+    if constexpr (SS) {
+        if (l2.n < l1.n) {
+            const int32_t j0 = (int32_t)(r * l2.n / l1.n), j1 = (int32_t)((r + cnt) * l2.n / l1.n);
+            if (j1 > j0) op.iv(ts, l1, j0, j1 - j0, l2, l3);
+        } else {
+            op(ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3);
+        }
+    } else {
+        op(ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3);
+    }
     k += cnt;
     r = 0;
     return k < k1;
@@ -816,13 +860,13 @@ __global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict
     sink.finish();
 }
 
-template <int VAR, class Op>
+template <int VAR, class Op, bool SS = false>
 __device__ inline void chunk_runs(const TriLists &L, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k, int64_t k1,
                                   const Op &op) {
-    if (chunk_run<VAR, 0, 1>(L, dq, ts, r, k, k1, op) && chunk_run<VAR, 1, 0>(L, dq, ts, r, k, k1, op) &&
-        chunk_run<VAR, 0, 2>(L, dq, ts, r, k, k1, op) && chunk_run<VAR, 2, 0>(L, dq, ts, r, k, k1, op) &&
-        chunk_run<VAR, 1, 2>(L, dq, ts, r, k, k1, op))
-        chunk_run<VAR, 2, 1>(L, dq, ts, r, k, k1, op);
+    if (chunk_run<VAR, 0, 1, Op, SS>(L, dq, ts, r, k, k1, op) && chunk_run<VAR, 1, 0, Op, SS>(L, dq, ts, r, k, k1, op) &&
+        chunk_run<VAR, 0, 2, Op, SS>(L, dq, ts, r, k, k1, op) && chunk_run<VAR, 2, 0, Op, SS>(L, dq, ts, r, k, k1, op) &&
+        chunk_run<VAR, 1, 2, Op, SS>(L, dq, ts, r, k, k1, op))
+        chunk_run<VAR, 2, 1, Op, SS>(L, dq, ts, r, k, k1, op);
 }
 
 template <class Op>
@@ -843,7 +887,7 @@ __device__ inline void chunk_runs_rt(int variant, const TriLists &L, uint32_t dq
 // ---------------------------------------------------------------------------
 // a.6: temporal tests over the surviving runs, flat chunks of IPT tests
 // ---------------------------------------------------------------------------
-template <int VAR, class Op>
+template <int VAR, class Op, bool SS = false>
 __global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wbase, int32_t NI,
                                                   const int64_t *__restrict__ base, const int32_t *__restrict__ su,
                                                   const int32_t *__restrict__ sv, const int64_t *__restrict__ sw,
@@ -879,7 +923,7 @@ __global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wb
             for (int32_t s = lo; s < ns && k < k1; s++) {
                 const int64_t p = s0 + s;
                 TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
-                chunk_runs<VAR>(L, dq, ts, r, k, k1, op);
+                chunk_runs<VAR, Op, SS>(L, dq, ts, r, k, k1, op);
                 r = 0;
             }
             if (k == k_start) break; // every survivor has tests, so this never triggers
