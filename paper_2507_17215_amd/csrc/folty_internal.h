@@ -276,9 +276,10 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws);
 // The time-range filter of one query (query.hip): surviving triangles in their
 // slots (ws.slots), tests per item and their offsets (ws.wbase).  Returns the
 // number of survivor slots; *tests is the test count, or -1 when the one-pass
-// filter left it on the device.  e0, e1 bracket the counting pass.
+// filter left it on the device.  e0, e1 bracket the counting pass.  ss: a run
+// has min(|L1|, |L2|) tests (the smaller-side evaluation), else |L1|.
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1, int64_t *tri, int64_t *tests);
+                       hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss = false);
 double ev_ms(hipEvent_t a, hipEvent_t b);
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
 void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);

@@ -280,8 +280,10 @@ __global__ void k_item_list(const int32_t *__restrict__ su, int32_t NI, int32_t 
 
 } // namespace
 
-int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1, int64_t *tri, int64_t *tests) {
+namespace {
+template <bool SS>
+int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, int64_t *tri, int64_t *tests) {
     *tests = -1; // known on the host only after the two-pass filter
     const int32_t NI = ix.NI;
     ws.su.ensure(4 * ((size_t)NI + 1));
@@ -294,7 +296,7 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
     k_fill<unsigned long long><<<1, 1, 0, s>>>(hits, 0ull, 1);
     FOLTY_LAUNCHED();
     auto sink_for = [&](auto V, auto M) {
-        FilterSink<decltype(V)::value, decltype(M)::value> sink{};
+        FilterSink<decltype(V)::value, decltype(M)::value, SS> sink{};
         sink.base = ws.sbase.as<int64_t>();
         sink.rec = ix.rec.as<EdgeRec>();
         sink.rng = ix.erng.as<uint2>();
@@ -384,6 +386,13 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
         dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.ilist.as<int32_t>(), nl); });
     }
     return survivors;
+}
+} // namespace
+
+int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss) {
+    return ss ? find_survivors_t<true>(ix, variant, dmax, ws, s, e0, e1, tri, tests)
+              : find_survivors_t<false>(ix, variant, dmax, ws, s, e0, e1, tri, tests);
 }
 
 namespace {
@@ -771,9 +780,10 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     int64_t tests = 0, tri = 0;
     if (ix.NI > 0) {
         int64_t known = -1;
-        const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known);
+        const bool ss = (q.flags & FOLTY_QUERY_SMALLER_SIDE) != 0;
+        const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known, ss);
         if (survivors > 0) {
-            if (q.flags & FOLTY_QUERY_SMALLER_SIDE) {
+            if (ss) {
                 // runs with a shorter L2 mark edge ranges in diff; its prefix sum is added at the end
                 ws.diff.ensure(4 * (2 * (size_t)ix.m + 1));
                 int32_t *diff = ws.diff.as<int32_t>(), *ps = diff + ix.m + 1;

@@ -171,14 +171,20 @@ __device__ inline bool run_lists(const TriLists &T, uint32_t dq, Span &l1, Span 
     return true;
 }
 
-template <int VAR, int I, int J> __device__ inline int64_t run_work(const TriLists &T, uint32_t dq) {
-    Span a, b, c;
-    return run_lists<VAR, I, J>(T, dq, a, b, c) ? a.n : 0;
+// Tests of a run: |L1|, or with SS the shorter of |L1| and |L2| (the side the
+// run is evaluated from; see chunk_run).
+template <bool SS> __device__ inline int32_t run_tests(const Span &l1, const Span &l2) {
+    return SS && l2.n < l1.n ? l2.n : l1.n;
 }
 
-template <int VAR> __device__ inline int64_t tri_work(const TriLists &T, uint32_t dq) {
-    return run_work<VAR, 0, 1>(T, dq) + run_work<VAR, 1, 0>(T, dq) + run_work<VAR, 0, 2>(T, dq) +
-           run_work<VAR, 2, 0>(T, dq) + run_work<VAR, 1, 2>(T, dq) + run_work<VAR, 2, 1>(T, dq);
+template <int VAR, int I, int J, bool SS = false> __device__ inline int64_t run_work(const TriLists &T, uint32_t dq) {
+    Span a, b, c;
+    return run_lists<VAR, I, J>(T, dq, a, b, c) ? run_tests<SS>(a, b) : 0;
+}
+
+template <int VAR, bool SS = false> __device__ inline int64_t tri_work(const TriLists &T, uint32_t dq) {
+    return run_work<VAR, 0, 1, SS>(T, dq) + run_work<VAR, 1, 0, SS>(T, dq) + run_work<VAR, 0, 2, SS>(T, dq) +
+           run_work<VAR, 2, 0, SS>(T, dq) + run_work<VAR, 1, 2, SS>(T, dq) + run_work<VAR, 2, 1, SS>(T, dq);
 }
 
 // runtime predicate code (one code per job in a batch)
@@ -296,28 +302,24 @@ struct PoolOp {
 };
 
 // one run of a surviving triangle within the chunk [k, k1); r = tests of this
-// triangle still to skip.  Returns false once the chunk is used up.  With SS a
-// run whose L2 is shorter than L1 is evaluated from L2: the chunk's share of the
-// run's |L1| tests, [r, r + cnt), takes the entries [r |L2| / |L1|, (r + cnt)
-// |L2| / |L1|) of L2, so the run's chunks split L2 exactly.
+// triangle still to skip.  Returns false once the chunk is used up.  With SS (and
+// a filter that counted tests the same way) a run whose L2 is shorter than L1
+// has |L2| tests, the entries of L2, and is evaluated from them.
 template <int VAR, int I, int J, class Op, bool SS = false>
 __device__ inline bool chunk_run(const TriLists &T, uint32_t dq, const int64_t *ts, int64_t &r, int64_t &k,
                                  int64_t k1, const Op &op) {
     Span l1, l2, l3;
     if (!run_lists<VAR, I, J>(T, dq, l1, l2, l3)) return true;
-    if (r >= l1.n) {
-        r -= l1.n;
+    const int32_t w = run_tests<SS>(l1, l2);
+    if (r >= w) {
+        r -= w;
         return true;
     }
-    int64_t cnt = l1.n - r;
+    int64_t cnt = w - r;
     if (cnt > k1 - k) cnt = k1 - k;
     if constexpr (SS) {
-        if (l2.n < l1.n) {
-            const int32_t j0 = (int32_t)(r * l2.n / l1.n), j1 = (int32_t)((r + cnt) * l2.n / l1.n);
-            if (j1 > j0) op.iv(ts, l1, j0, j1 - j0, l2, l3);
-        } else {
-            op(ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3);
-        }
+        if (w < l1.n) op.iv(ts, l1, (int32_t)r, (int32_t)cnt, l2, l3);
+        else op(ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3);
     } else {
         op(ts, l1.s + (int32_t)r, (int32_t)cnt, l2, l3);
     }
@@ -408,7 +410,7 @@ enum FilterMode {
 // meet (8 bytes each), and only then are the three edge records read.  The enumeration order inside an item is fixed, so a
 // counting pass and a later emitting pass agree on every survivor's position.
 // VAR < 0: the predicate code is read from `variant` at run time
-template <int VAR, int MODE> struct FilterSink {
+template <int VAR, int MODE, bool SS = false> struct FilterSink {
     // a run-time predicate code inlines all eight tests: keep the enumeration's
     // code small (one copy of the sink) for those
     static constexpr bool kCompact = VAR < 0;
@@ -447,7 +449,7 @@ template <int VAR, int MODE> struct FilterSink {
         if (h && ranges_meet(pra, prk, dq)) {
             const uint2 r3 = rng[pkb ? c : b];
             if (ranges_meet(pra, r3, dq) && ranges_meet(prk, r3, dq)) {
-                if constexpr (VAR >= 0) wk = tri_work<VAR>(load_lists<false>(rec, a, b, c), run_slack(dq));
+                if constexpr (VAR >= 0) wk = tri_work<VAR, SS>(load_lists<false>(rec, a, b, c), run_slack(dq));
                 else wk = tri_work_rt(variant, load_lists<false>(rec, a, b, c), run_slack(dq));
             }
         }
@@ -849,9 +851,9 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(enum_waves<
 }
 
 // cached triangle list: the same filter, one wavefront per item
-template <int VAR, int MODE>
+template <int VAR, int MODE, bool SS>
 __global__ __launch_bounds__(BLK) void k_filter_cached(const int64_t *__restrict__ base, const int32_t *__restrict__ tri,
-                                                       int32_t NI, FilterSink<VAR, MODE> sink,
+                                                       int32_t NI, FilterSink<VAR, MODE, SS> sink,
                                                        const int32_t *__restrict__ list = nullptr, int32_t nlist = 0) {
     const int w = wave_id();
     const int64_t n = list ? nlist : NI;

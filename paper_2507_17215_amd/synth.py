@@ -230,25 +230,29 @@ def large_family(m: int, seed: int) -> TemporalGraph:
                     communities=max(1, round(200 * m / 7e7)))
 
 
-def skewed(seed: int = 0, n: int = 1_000_000, m_background: int = 5_000_000, heavy: int = 2_000,
-           heavy_k: int = 5_000, light_k: int = 4) -> TemporalGraph:
+def skewed(seed: int = 0, n: int = 1_000_000, m_background: int = 5_000_000, heavy: int = 200,
+           heavy_k: int = 5_000, fan: int = 100, light_k: int = 4) -> TemporalGraph:
     """A multiplicity-skewed graph: the medium generator's background (n vertices,
-    m_background edges) plus ``heavy`` planted triangles (a, b, w) on fresh random
-    vertex triples, each with ``heavy_k`` parallel edges a -> b and ``light_k``
-    edges a -> w and b -> w, all with uniform timestamps over one year.  Edges
-    are returned in timestamp order."""
+    m_background edges) plus ``heavy`` planted pairs a -> b with ``heavy_k``
+    parallel edges each, every pair closed by ``fan`` third vertices w with
+    ``light_k`` edges a -> w and ``light_k`` edges b -> w (vertices drawn without
+    replacement per pair; uniform timestamps over one year).  Each heavy list
+    then meets ``fan`` short closing lists.  Edges are returned in timestamp
+    order."""
     base = generate(n, m_background, 2.1, law="pareto", cap=1000, times="renewal",
                     t_range=YEAR_S, seed=seed)
     rng = _rng(seed + 7919)
-    tri = np.stack([rng.choice(n, size=3, replace=False) for _ in range(heavy)]).astype(np.int32)
-    a, b, w = tri[:, 0], tri[:, 1], tri[:, 2]
-    src = np.concatenate([base.src, np.repeat(a, heavy_k), np.repeat(a, light_k), np.repeat(b, light_k)])
-    dst = np.concatenate([base.dst, np.repeat(b, heavy_k), np.repeat(w, light_k), np.repeat(w, light_k)])
-    extra = heavy * (heavy_k + 2 * light_k)
+    pick = np.stack([rng.choice(n, size=fan + 2, replace=False) for _ in range(heavy)]).astype(np.int32)
+    a, b, w = pick[:, 0], pick[:, 1], pick[:, 2:]
+    src = np.concatenate([base.src, np.repeat(a, heavy_k), np.repeat(np.repeat(a, fan), light_k),
+                          np.repeat(np.repeat(b, fan), light_k)])
+    dst = np.concatenate([base.dst, np.repeat(b, heavy_k), np.repeat(w.reshape(-1), light_k),
+                          np.repeat(w.reshape(-1), light_k)])
+    extra = heavy * (heavy_k + 2 * fan * light_k)
     t = np.concatenate([base.t, rng.integers(0, YEAR_S, size=extra)]).astype(np.int64)
     order = np.argsort(t, kind="stable")
     return TemporalGraph(n=n, src=src[order].astype(np.int32), dst=dst[order].astype(np.int32), t=t[order],
-                         meta=dict(kind="skewed", heavy=heavy, heavy_k=heavy_k, light_k=light_k))
+                         meta=dict(kind="skewed", heavy=heavy, heavy_k=heavy_k, fan=fan, light_k=light_k))
 
 
 def random_small(rng: np.random.Generator, n_max: int = 12, m_max: int = 80,
