@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # the query's dominant kernel, the sources it is compiled from, and the committed
 # counter summary (FETCH_SIZE / WRITE_SIZE per dispatch and the copy-kernel
 # calibration) that gives its measured HBM traffic
-ROOF_KERNEL = "k_tri_enum<FilterSink<0, 0> >"
+ROOF_KERNEL = "k_tri_enum<FilterSink<0, 0, false> >"
 ROOF_SOURCES = ("paper_2507_17215_amd/csrc/tri_device.h", "paper_2507_17215_amd/csrc/query.hip")
 TRAFFIC_SUMMARY = "profiles/k_tri_enum_filter_large_70M_pmc.md"
 COPY_PROBE_BYTES = 1 << 30
@@ -305,7 +305,7 @@ def smaller_side_section(folty, synth, G, oracle, g, rng, k):
                          rng.choice(nz, size=min(k, nz.size), replace=False) if nz.size else nz)
         bad = int((ox.counts(d, variant, idx) != c1[idx]).sum())
         same_pairs = r0.pairs() == r1.pairs() and r0.n_certificates == r1.n_certificates
-        row = {"delta": d, "predicate": variant, "tests": r1.stats["tests"],
+        row = {"delta": d, "predicate": variant, "tests_default": r0.stats["tests"], "tests": r1.stats["tests"],
                "temporal_ms_default": r0.stats["temporal_ms"], "temporal_ms_smaller_side": r1.stats["temporal_ms"],
                "query_ms_default": r0.stats["query_ms"], "query_ms_smaller_side": r1.stats["query_ms"],
                "counts_differing_from_default": diff, "oracle_checked_edges": int(idx.size),
