@@ -331,6 +331,8 @@ int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t
         if (n_certificates) *n_certificates = r->r.n_certificates;
         if (!edge_count) return;
         *edge_count = nullptr;
+        if (r->r.triad) fail(FOLTY_EINVAL, "an exists-exists-exists result has no per-edge certificate counts "
+                                           "(folty_result_edge_instances gives its per-edge numbers)");
         if (!r->r.has_counts) fail(FOLTY_EINVAL, "query ran with FOLTY_QUERY_NO_COUNTS");
         if (!r->r.counts_fetched) {
             FOLTY_HIP(hipSetDevice(r->r.device));
