@@ -243,21 +243,32 @@ struct Graph {
     ~Graph();
 };
 
+// Host arrays of a result are filled by device copies: their elements are left
+// uninitialised on resize instead of being zeroed first.
+template <class T> struct NoInitAlloc : std::allocator<T> {
+    template <class U> struct rebind { using other = NoInitAlloc<U>; };
+    NoInitAlloc() = default;
+    template <class U> NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <class U> void construct(U *p) noexcept { ::new (static_cast<void *>(p)) U; }
+    template <class U, class... A> void construct(U *p, A &&...a) { ::new (static_cast<void *>(p)) U(std::forward<A>(a)...); }
+};
+template <class T> using HostVec = std::vector<T, NoInitAlloc<T>>;
+
 struct Result {
-    std::vector<int32_t> u, v;
-    std::vector<uint32_t> n_cert;
-    std::vector<int32_t> vert;  // vertex queries: solution vertices, ascending
-    std::vector<uint32_t> vgood; // and their neighbours with a qualifying edge
+    HostVec<int32_t> u, v;
+    HostVec<uint32_t> n_cert;
+    HostVec<int32_t> vert;  // vertex queries: solution vertices, ascending
+    HostVec<uint32_t> vgood; // and their neighbours with a qualifying edge
     bool triad = false;                // an exists-exists-exists result
     int64_t n_triads = 0;              // its solution triples
     int64_t n_tinst = -1;              // its temporal triangles (-1: not counted)
-    std::vector<int32_t> trip;         // 3 per listed triple (a, b, w)
-    std::vector<uint64_t> tinst;       // temporal triangles per first edge, input order
+    HostVec<int32_t> trip;             // 3 per listed triple (a, b, w)
+    HostVec<uint64_t> tinst;           // temporal triangles per first edge, input order
     int64_t n_certificates = 0;
     folty_stats stats{};
     bool has_counts = false;
     DevBuf counts_dev;                // uint32[m_input], input order
-    std::vector<uint32_t> counts_host;
+    HostVec<uint32_t> counts_host;
     bool counts_fetched = false;
     int device = 0;
 };

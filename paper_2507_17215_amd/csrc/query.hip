@@ -210,21 +210,68 @@ __global__ __launch_bounds__(BLK) void k_threshold(ThreshArgs A) {
     }
 }
 
-__global__ void k_pairs_compact(const uint32_t *__restrict__ ncert, int32_t S, const int32_t *__restrict__ slo,
-                                 const int32_t *__restrict__ shi, uint64_t *__restrict__ keys,
-                                 uint32_t *__restrict__ vals, int32_t *__restrict__ npairs) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool in = i < 2 * (int64_t)S;
-    uint32_t c = in ? ncert[i] : 0;
-    int32_t slot = wave_append(npairs, c > 0);
-    if (slot >= 0) {
-        int32_t s = (int32_t)(i >> 1);
-        int dir = (int)(i & 1);
-        uint64_t a = (uint64_t)(dir ? shi[s] : slo[s]);
-        uint64_t b = (uint64_t)(dir ? slo[s] : shi[s]);
-        keys[slot] = (a << 32) | b;
-        vals[slot] = c;
+// bits of a vertex id in a pair key (at least 1)
+__host__ __device__ inline int pair_bits(int32_t n) {
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < (int64_t)n) b++;
+    return b;
+}
+
+// Directed pairs with certificates, as keys (a << nbits) | b with their counts.
+// Each block takes BLK x PAIR_ITEMS entries (2 s + dir) and claims its output
+// range with one atomic, so a dense result does not serialise on the counter.
+constexpr int PAIR_ITEMS = 8;
+__global__ __launch_bounds__(BLK) void k_pairs_compact(const uint32_t *__restrict__ ncert, int32_t S,
+                                                       const int32_t *__restrict__ slo, const int32_t *__restrict__ shi,
+                                                       int nbits, uint64_t *__restrict__ keys,
+                                                       uint32_t *__restrict__ vals, int32_t *__restrict__ npairs) {
+    __shared__ int32_t s_wave[BLK / 64];
+    __shared__ int32_t s_base;
+    const int64_t n2 = 2 * (int64_t)S;
+    const int64_t tile = (int64_t)blockIdx.x * BLK * PAIR_ITEMS;
+    uint32_t c[PAIR_ITEMS];
+    int32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < PAIR_ITEMS; j++) {
+        const int64_t i = tile + (int64_t)j * BLK + threadIdx.x;
+        c[j] = i < n2 ? ncert[i] : 0u;
+        mine += c[j] > 0;
     }
+    const int w = threadIdx.x >> 6;
+    const int32_t incl = wave_inclusive_sum(mine);
+    if (lane_id() == 63) s_wave[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int k = 0; k < BLK / 64; k++) {
+            const int32_t x = s_wave[k];
+            s_wave[k] = tot;
+            tot += x;
+        }
+        s_base = tot ? atomicAdd(npairs, tot) : 0;
+    }
+    __syncthreads();
+    int32_t pos = s_base + s_wave[w] + incl - mine;
+#pragma unroll
+    for (int j = 0; j < PAIR_ITEMS; j++) {
+        if (!c[j]) continue;
+        const int64_t i = tile + (int64_t)j * BLK + threadIdx.x;
+        const int32_t e = (int32_t)(i >> 1);
+        const uint64_t a = (uint64_t)((i & 1) ? shi[e] : slo[e]);
+        const uint64_t b = (uint64_t)((i & 1) ? slo[e] : shi[e]);
+        keys[pos] = (a << nbits) | b;
+        vals[pos] = c[j];
+        pos++;
+    }
+}
+
+__global__ void k_pairs_unpack(const uint64_t *__restrict__ keys, int32_t np, int nbits, int32_t *__restrict__ u,
+                               int32_t *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const uint64_t k = keys[i];
+    u[i] = (int32_t)(k >> nbits);
+    v[i] = (int32_t)(k & ((1ull << nbits) - 1));
 }
 
 // count[e] += the prefix sum of the interval marks at e
@@ -522,11 +569,11 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
         A.total = total;
         k_threshold<<<grid_for(m, BLK), BLK, 0, s>>>(A);
         FOLTY_LAUNCHED();
-        ws.pairs_k.ensure(16 * (size_t)S);
-        ws.pairs_v.ensure(8 * (size_t)S);
-        k_pairs_compact<<<grid_for(2 * (int64_t)S, BLK), BLK, 0, s>>>(
-            ws.ncert.as<uint32_t>(), S, ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), ws.pairs_k.as<uint64_t>(),
-            ws.pairs_v.as<uint32_t>(), np);
+        ws.pairs_k.ensure(16 * (size_t)S + 16);
+        ws.pairs_v.ensure(8 * (size_t)S + 8);
+        k_pairs_compact<<<grid_for(2 * (int64_t)S, BLK * PAIR_ITEMS), BLK, 0, s>>>(
+            ws.ncert.as<uint32_t>(), S, ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), pair_bits(ix.n),
+            ws.pairs_k.as<uint64_t>(), ws.pairs_v.as<uint32_t>(), np);
         FOLTY_LAUNCHED();
     }
     ws.host.ensure(64);
@@ -543,20 +590,20 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
     if (npairs > 0) {
         ws.pairs_k2.ensure(8 * (size_t)npairs);
         ws.pairs_v2.ensure(4 * (size_t)npairs);
-        int kb = 32 + bit_length((uint64_t)ix.n);
+        const int nb = pair_bits(ix.n);
         size_t need = sort_pairs_u64_u32(nullptr, 0, ws.pairs_k.as<uint64_t>(), ws.pairs_k2.as<uint64_t>(),
-                                         ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, kb, s);
+                                         ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, 2 * nb, s);
         ws.cub.ensure(need);
         sort_pairs_u64_u32(ws.cub.p, need, ws.pairs_k.as<uint64_t>(), ws.pairs_k2.as<uint64_t>(),
-                           ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, kb, s);
-        std::vector<uint64_t> keys(npairs);
-        FOLTY_HIP(hipMemcpyAsync(keys.data(), ws.pairs_k2.p, 8 * (size_t)npairs, hipMemcpyDeviceToHost, s));
+                           ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, 2 * nb, s);
+        // the unsorted keys are no longer needed: u and v go where they were
+        int32_t *du = reinterpret_cast<int32_t *>(ws.pairs_k.p), *dv = du + npairs;
+        k_pairs_unpack<<<grid_for(npairs, BLK), BLK, 0, s>>>(ws.pairs_k2.as<uint64_t>(), npairs, nb, du, dv);
+        FOLTY_LAUNCHED();
+        FOLTY_HIP(hipMemcpyAsync(res->u.data(), du, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipMemcpyAsync(res->v.data(), dv, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipMemcpyAsync(res->n_cert.data(), ws.pairs_v2.p, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipStreamSynchronize(s));
-        for (int32_t i = 0; i < npairs; i++) {
-            res->u[i] = (int32_t)(keys[i] >> 32);
-            res->v[i] = (int32_t)(keys[i] & 0xffffffffu);
-        }
     }
 }
 
