@@ -404,9 +404,11 @@ int folty_graph_device_bytes(const folty_graph *g, int64_t *bytes);
 void folty_graph_free(folty_graph *g);
 
 /* The library keeps freed device blocks for reuse (allocation and release are
- * slow and a release waits for the whole device).  This hands every cached block
- * of the current device back to the driver; *bytes (if not NULL) receives the
- * amount.  Call it when other code needs the memory. */
+ * slow and a release waits for the whole device), and the pinned host blocks of
+ * freed results' large arrays (up to 4 GiB).  This hands every cached device
+ * block of the current device, and every cached pinned block, back to the
+ * driver; *bytes (if not NULL) receives the amount.  Call it when other code
+ * needs the memory. */
 int folty_release_cached_memory(int64_t *bytes);
 
 #ifdef __cplusplus

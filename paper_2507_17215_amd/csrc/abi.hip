@@ -386,7 +386,7 @@ int folty_graph_device_bytes(const folty_graph *g, int64_t *bytes) {
 
 int folty_release_cached_memory(int64_t *bytes) {
     return guarded([&] {
-        size_t b = dev_trim();
+        size_t b = dev_trim() + host_trim();
         if (bytes) *bytes = (int64_t)b;
     });
 }

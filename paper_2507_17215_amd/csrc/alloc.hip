@@ -135,6 +135,83 @@ size_t dev_trim() {
     return n;
 }
 
+// ---------------------------------------------------------------------------
+// Pinned host blocks for large result arrays.  Results are filled by device
+// copies: into pinned memory they run as a DMA at full speed, and a block taken
+// from the cache has its pages mapped already (a fresh pageable array is copied
+// through a staging buffer and faults on every page).  Released blocks are kept,
+// up to HOST_CACHE_CAP bytes, for the next result.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct HostPool {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;
+    std::map<void *, size_t> live; // block -> its size, for every block handed out
+    size_t cached = 0;
+};
+
+HostPool &host_pool() {
+    static HostPool *p = new HostPool(); // kept until the process ends
+    return *p;
+}
+
+constexpr size_t HOST_CACHE_CAP = size_t(4) << 30;
+
+size_t host_round(size_t b) {
+    const size_t g = size_t(2) << 20;
+    return (b + g - 1) / g * g;
+}
+
+} // namespace
+
+void *host_alloc(size_t bytes) {
+    HostPool &P = host_pool();
+    const size_t want = host_round(bytes);
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.free_blocks.lower_bound(want);
+    if (it != P.free_blocks.end() && it->first <= 2 * want) {
+        void *p = it->second;
+        P.live[p] = it->first;
+        P.cached -= it->first;
+        P.free_blocks.erase(it);
+        return p;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocPortable) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr; // the caller falls back to pageable memory
+    }
+    P.live[p] = want;
+    return p;
+}
+
+bool host_free(void *p) {
+    HostPool &P = host_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.live.find(p);
+    if (it == P.live.end()) return false;
+    const size_t b = it->second;
+    P.live.erase(it);
+    if (P.cached + b > HOST_CACHE_CAP) {
+        (void)hipHostFree(p);
+    } else {
+        P.free_blocks.emplace(b, p);
+        P.cached += b;
+    }
+    return true;
+}
+
+size_t host_trim() {
+    HostPool &P = host_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    size_t n = P.cached;
+    for (auto &kv : P.free_blocks) (void)hipHostFree(kv.second);
+    P.free_blocks.clear();
+    P.cached = 0;
+    return n;
+}
+
 size_t dev_cached() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;

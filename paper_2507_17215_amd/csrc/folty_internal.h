@@ -56,6 +56,12 @@ void *dev_alloc(size_t bytes, size_t *got);
 void dev_free(void *p, size_t bytes);
 size_t dev_trim();   // give every cached block back to the driver; returns bytes
 size_t dev_cached(); // bytes held in the cache
+// pinned host blocks for large result arrays (alloc.hip); host_alloc returns
+// nullptr when pinned memory is not available, host_free false for a pointer
+// it did not hand out
+void *host_alloc(size_t bytes);
+bool host_free(void *p);
+size_t host_trim();  // give the cached pinned blocks back; returns bytes
 
 struct DevBuf {
     void *p = nullptr;
@@ -244,11 +250,20 @@ struct Graph {
 };
 
 // Host arrays of a result are filled by device copies: their elements are left
-// uninitialised on resize instead of being zeroed first.
+// uninitialised on resize instead of being zeroed first, and arrays of 1 MiB and
+// more live in cached pinned blocks (host_alloc).
 template <class T> struct NoInitAlloc : std::allocator<T> {
     template <class U> struct rebind { using other = NoInitAlloc<U>; };
     NoInitAlloc() = default;
     template <class U> NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    T *allocate(size_t n) {
+        if (n * sizeof(T) >= (size_t(1) << 20))
+            if (void *p = host_alloc(n * sizeof(T))) return static_cast<T *>(p);
+        return std::allocator<T>::allocate(n);
+    }
+    void deallocate(T *p, size_t n) {
+        if (!host_free(p)) std::allocator<T>::deallocate(p, n);
+    }
     template <class U> void construct(U *p) noexcept { ::new (static_cast<void *>(p)) U; }
     template <class U, class... A> void construct(U *p, A &&...a) { ::new (static_cast<void *>(p)) U(std::forward<A>(a)...); }
 };
