@@ -762,8 +762,8 @@ void plan_run(Plan *P, Result **outs) {
     if (npairs < 0 || npairs > P->rec_cap)
         fail(FOLTY_EDEVICE, "certificate records exceed their bound (%d > %lld)", npairs, (long long)P->rec_cap);
     P->last_records = npairs;
-    std::vector<uint64_t> keys(npairs);
-    std::vector<uint32_t> vals(npairs);
+    HostVec<uint64_t> keys(npairs);
+    HostVec<uint32_t> vals(npairs);
     if (npairs > 0) {
         P->keys2.ensure(8 * (size_t)npairs);
         P->vals2.ensure(4 * (size_t)npairs);
@@ -783,6 +783,17 @@ void plan_run(Plan *P, Result **outs) {
     std::vector<std::unique_ptr<Result>> res(nq);
     for (int q = 0; q < nq; q++) res[q].reset(new Result());
     const uint64_t nmask = (1ull << P->nbits) - 1ull;
+    {
+        // distinct pairs per query first, so each query's arrays grow once
+        std::vector<int64_t> per(nq, 0);
+        for (int32_t i = 0; i < npairs; i++)
+            if (i == 0 || keys[i] != keys[i - 1]) per[(size_t)(keys[i] >> (2 * P->nbits))]++;
+        for (int q = 0; q < nq; q++) {
+            res[q]->u.reserve((size_t)per[q]);
+            res[q]->v.reserve((size_t)per[q]);
+            res[q]->n_cert.reserve((size_t)per[q]);
+        }
+    }
     for (int32_t i = 0; i < npairs;) {
         uint32_t c = 0;
         int32_t e = i;
