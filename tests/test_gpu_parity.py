@@ -469,3 +469,39 @@ def test_medium_workload_full_counts():
             r = G.vertex_query(d, (1, 10), inner, (1, 4), 0, counts=False)
             want = o.vertex_query(d, 1, 10, 0, inner == folty.INNER_FORALL, 1, 4, counts=pool[:, j])
             assert_vertices(r, want)
+
+
+@pytest.mark.timeout(600)
+def test_large_sparse_id_space():
+    """n = 2^28 with a few hundred edges on ids spread over the whole range: every
+    per-vertex array of the index spans 2^28 entries and the grouping keys use 57
+    bits.  Results equal the oracle's on the same graph with its ids compacted in
+    order (an order-preserving relabelling changes no count and no pair order)."""
+    rng = np.random.default_rng(28)
+    n = 1 << 28
+    k = 24
+    ids = np.sort(np.concatenate([[0, 1, n - 2, n - 1], rng.choice(np.arange(2, n - 2), k - 4, replace=False)]))
+    m = 600
+    cs = rng.integers(0, k, m)
+    cd = rng.integers(0, k, m)
+    t = rng.integers(0, 50, m).astype(np.int64)
+    o = Oracle(k, cs.astype(np.int32), cd.astype(np.int32), t)
+    G = folty.Graph(n, ids[cs].astype(np.int32), ids[cd].astype(np.int32), t).build()
+    say("sparse ids: built", G.stats()["max_core"])
+    for d, v in ((0, 0), (5, 3), (20, 6), (INF, 1)):
+        say("sparse ids", d, v)
+        want = o.query(d, 1, 3, v)
+        r = G.query(d, (1, 3), v)
+        assert np.array_equal(r.counts(), want["counts"])
+        assert np.array_equal(r.pair_u, ids[want["pair_u"]].astype(np.int32))
+        assert np.array_equal(r.pair_v, ids[want["pair_v"]].astype(np.int32))
+        assert np.array_equal(r.n_cert, want["n_cert"])
+        tr = G.triad_query(d, v).triads()
+        ws = o.triad_solutions(d, v)
+        assert np.array_equal(tr["triples"], ids[ws].astype(np.int32))
+        vq = G.vertex_query(d, (1, 2), folty.INNER_EXISTS, variant=v).vertices()[0]
+        wv = o.vertex_query(d, 1, 2, v, inner_forall=False)["vertices"]
+        assert np.array_equal(vq, ids[wv].astype(np.int32))
+    cores = G.core_numbers()
+    assert np.array_equal(cores[ids], o.core_numbers())
+    assert (np.delete(cores, ids) == 0).all()
