@@ -344,7 +344,7 @@ struct Plan {
     DevBuf wu, wbase, nrec, keys, vals, keys2, vals2, cub;
     size_t scan_bytes = 0;
     // launch shape and capture
-    int ipt = 8, tblocks = 4096;
+    int ipt = 1, tblocks = 4096;
     bool tuned = false;
     bool eager = false; // capture refused: launch directly
     bool oneshot = false;
@@ -463,7 +463,7 @@ static void tune(Plan &P) {
         P.tuned = true;
         return;
     }
-    const int ipts[] = {4, 8, 16, 32};
+    const int ipts[] = {1, 2, 4, 8, 16};
     const int blocks[] = {1024, 2048, 4096, 8192};
     double best = 1e30;
     int bi = P.ipt, bb = P.tblocks;

@@ -445,12 +445,17 @@ int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws
 namespace {
 
 // tests < 0: unknown on the host, the full persistent grid; else a thread per
-// chunk, and chunks of one test when there are few (each chunk's searches are a
-// chain of dependent loads, so few tests are done fastest all at once)
+// chunk up to that grid.  Chunks of one test by default: neighbouring lanes then
+// take neighbouring edges of one run, so a wavefront's searches read the same
+// lists (70M-edge graph at one year, 36.8M tests, 2.6 per surviving triangle:
+// 10.2 ms at one test per chunk, 12.0 at 8, 13.9 at 32).  Long runs of cheap
+// tests (many tests per survivor) pay the chunk's item and survivor searches
+// per test instead, and take IPT tests per chunk (a skewed graph with 50 and
+// 5,000 tests per survivor: 2.4 -> 3.4 ms and 0.7 -> 2.4 ms at one test).
 template <class Op, bool SS = false>
 void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, int64_t tests,
-                     hipStream_t s) {
-    const int ipt = tests >= 0 && tests < (int64_t)PERSIST_BLOCKS * BLK ? 1 : IPT;
+                     int64_t survivors, hipStream_t s) {
+    const int ipt = tests >= (int64_t)PERSIST_BLOCKS * BLK && tests >= 16 * survivors ? IPT : 1;
     const int64_t want = tests < 0 ? PERSIST_BLOCKS : ((tests + ipt - 1) / ipt + BLK - 1) / BLK;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PERSIST_BLOCKS));
     dispatch_variant(variant, [&](auto V) {
@@ -837,7 +842,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
                 k_fill<int32_t><<<grid_for(ix.m + 1, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(diff, 0, ix.m + 1);
                 FOLTY_LAUNCHED();
                 DirectOp op{q.delta, count, diff};
-                launch_temporal<DirectOp, true>(ix, q.variant, q.delta, ws, op, known, s);
+                launch_temporal<DirectOp, true>(ix, q.variant, q.delta, ws, op, known, survivors, s);
                 size_t need = inclusive_scan_i32(nullptr, 0, diff, ps, ix.m, s);
                 ws.cub.ensure(need);
                 inclusive_scan_i32(ws.cub.p, need, diff, ps, ix.m, s);
@@ -845,7 +850,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
                 FOLTY_LAUNCHED();
             } else {
                 DirectOp op{q.delta, count};
-                launch_temporal(ix, q.variant, q.delta, ws, op, known, s);
+                launch_temporal(ix, q.variant, q.delta, ws, op, known, survivors, s);
             }
             FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
         }

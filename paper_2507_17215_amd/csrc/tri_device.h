@@ -11,7 +11,7 @@ namespace {
 constexpr int BLK = 256;
 constexpr int WPB = BLK / 64;         // wavefronts per block
 constexpr int CAP = 512;              // N+(u) staged in LDS up to this length
-constexpr int IPT = 8;                // temporal tests per chunk
+constexpr int IPT = 8;                // tests per chunk of the first-hit search of exists-exists-exists
 constexpr int PERSIST_BLOCKS = 4096;
 constexpr int ENUM_BLOCKS = 32768; // 8 x the resident blocks: about a dozen items per wavefront, balanced by the dispatcher
 constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item (about; whole segments)
@@ -887,7 +887,7 @@ __device__ inline void chunk_runs_rt(int variant, const TriLists &L, uint32_t dq
 }
 
 // ---------------------------------------------------------------------------
-// a.6: temporal tests over the surviving runs, flat chunks of IPT tests
+// a.6: temporal tests over the surviving runs, flat chunks of ipt tests
 // ---------------------------------------------------------------------------
 template <int VAR, class Op, bool SS = false>
 __global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wbase, int32_t NI,
