@@ -330,8 +330,8 @@ def smaller_side_section(folty, synth, G, oracle, g, rng, k):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU per process; there is no multi-GPU "
+                                   "path, so --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     if a.copy_probe:
         copy_probe()
