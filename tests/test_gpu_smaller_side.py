@@ -3,6 +3,8 @@ whose list L2 is shorter than E_{a,b} are counted from L2 through the
 in-neighbour intervals and a per-edge difference array.  The counts, pairs and
 |Sol| must equal the oracle's and the default evaluation's exactly.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -99,3 +101,29 @@ def test_smaller_side_medium_workload():
         r0 = G.query(d, (1, 10), v)
         say("medium", d, v, "tests", r.stats["tests"], "temporal ms: default", r0.stats["temporal_ms"],
             "smaller side", r.stats["temporal_ms"])
+
+
+def test_smaller_side_flag_in_vertex_queries_and_plans():
+    """The flag changes no result: vertex queries evaluated from the smaller side
+    equal the default ones, and plans (which always walk E_{a,b}) accept it."""
+    g = synth.tiny(seed=17)
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    for inner in (folty.INNER_FORALL, folty.INNER_EXISTS):
+        vq = folty.VertexQuery()
+        vq.edge = folty.make_query(10**6, (1, 4) if inner == folty.INNER_FORALL else (1, 1), 0,
+                                   smaller_side=True)
+        vq.theta_num, vq.theta_den = 1, 5
+        vq.inner = inner
+        out = ctypes.c_void_p()
+        lib = folty.load_library()
+        assert lib.folty_run_vertex_query(G._h, ctypes.byref(vq), ctypes.byref(out)) == 0
+        a = folty.Result(out)
+        b = G.vertex_query(10**6, (1, 5), inner, (1, 4), 0)
+        say("vertex", inner)
+        assert np.array_equal(a.vertices()[0], b.vertices()[0])
+        assert np.array_equal(a.counts(), b.counts())
+    q = folty.make_query(86400, (1, 3), 3, smaller_side=True)
+    plan = folty.Plan([G], [(0, q)])
+    r = plan.run()[0]
+    ref = G.query(86400, (1, 3), 3)
+    assert r.pairs() == ref.pairs() and np.array_equal(r.counts(), ref.counts())
