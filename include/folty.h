@@ -185,6 +185,15 @@ int folty_build_index(folty_graph *g, const folty_build_opts *opts);
  * Run one query and wait for it (paper, Algorithm ExistExistForAll).  *out
  * receives a result holding the sorted solution pairs; per-edge counts are
  * fetched on demand by folty_result_counts.
+ *
+ * The filter of a query normally enumerates the graph's triangles twice: once to
+ * count survivors, then again over the work items that have any.  After a query
+ * (of any kind) whose second enumeration took at least half as long as the first,
+ * the library counts the triangles per item once (one enumeration pass).  It does so
+ * only when 20 bytes per triangle fit in a quarter of the free device memory.
+ * Later queries on the graph then filter in one pass, with 20 bytes per triangle
+ * of survivor slots in their workspace.  Plans (folty_plan_create) make the same
+ * per-item counts.
  */
 int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out);
 

@@ -216,6 +216,7 @@ struct Workspace {
     DevBuf wbase;   // int64[NI+1] exclusive offsets of wu
     DevBuf sbase;   // int64[NI+1] first survivor slot of each item
     const int64_t *slots = nullptr; // survivor slots of the last filter: sbase or the index's tri_base
+    bool emit_timed = false;        // the last filter's second pass is bracketed by ev[6], ev[7]
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
     DevBuf pairs_v; // uint32[2S]
@@ -332,6 +333,9 @@ void server_destroy(Server *s);
 void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s);
 void ensure_tri_base(Index &ix, hipStream_t s); // caller holds Graph::lazy_mu once the graph is shared
 void ensure_triangles(Graph *g);                 // ensure_tri_base on the graph's stream, under lazy_mu
+// after a two-pass filter that enumerated most items a second time (a wide
+// window), make the per-item triangle offsets so later queries filter in one pass
+void maybe_one_pass(Graph *g, const Workspace &ws);
 
 // library-primitive wrappers (rocPRIM through hipCUB), all on `stream`
 size_t sort_pairs_u64_i32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,

@@ -332,6 +332,7 @@ template <bool SS>
 int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1, int64_t *tri, int64_t *tests) {
     *tests = -1; // known on the host only after the two-pass filter
+    ws.emit_timed = false;
     const int32_t NI = ix.NI;
     ws.su.ensure(4 * ((size_t)NI + 1));
     ws.wu.ensure(8 * ((size_t)NI + 1));
@@ -430,7 +431,10 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
         ws.sv.ensure(12 * (size_t)survivors);
         ws.sw.ensure(8 * (size_t)survivors);
         const int32_t nl = (int32_t)h[3];
+        FOLTY_HIP(hipEventRecord(ws.ev[6], s));
         dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.ilist.as<int32_t>(), nl); });
+        FOLTY_HIP(hipEventRecord(ws.ev[7], s));
+        ws.emit_timed = true;
     }
     return survivors;
 }
@@ -750,6 +754,27 @@ void ensure_tri_base(Index &ix, hipStream_t s) {
     ix.tri_base_ready = true;
 }
 
+// The two-pass filter enumerates the items with survivors a second time; at a
+// wide window that costs about as much as the first pass (70M edges, one year:
+// 7.1 ms on top of the 6.9 ms counting pass).  When the second pass took at
+// least half as long as the first, per-item triangle offsets (one counting
+// enumeration, once per graph) let later queries write survivors into per-item
+// slots in a single pass, at 20 bytes of workspace per static triangle; that is
+// done when it fits in a quarter of the free device memory.
+void maybe_one_pass(Graph *g, const Workspace &ws) {
+    const Index &ix = g->ix;
+    if (ix.tri_base_ready || !ws.emit_timed || ix.T <= 0) return;
+    // the second pass cost at least half the first (events of the finished query)
+    if (2 * ev_ms(ws.ev[6], ws.ev[7]) < ev_ms(ws.ev[4], ws.ev[5])) return;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if ((size_t)ix.T * 20 > fr / 4) return;
+    ensure_triangles(g);
+}
+
 void ensure_triangles(Graph *g) {
     std::lock_guard<std::mutex> lk(g->lazy_mu);
     if (g->ix.tri_base_ready || !g->ix.built) return;
@@ -873,6 +898,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     res->stats.temporal_ms = ev_ms(ws.ev[5], ws.ev[2]);
     res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
     res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
+    maybe_one_pass(g, ws);
     return res.release();
 }
 

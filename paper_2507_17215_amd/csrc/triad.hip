@@ -16,8 +16,9 @@
 //     F the running sum of f.  lo, hi, h3 and the two search cursors for f only
 //     move forward over a chunk's time-sorted edges, so a chunk costs its edges
 //     plus the entries its windows pass, each with a search from the cursor.
-// The set bits are then counted, and listed as (a, b, w) in original ids,
-// sorted by two stable radix sorts (w, then the pair key a n + b).
+// The set bits are then counted item by item over the survivor slots only, and
+// listed as (a, b, w) in original ids, sorted by two stable radix sorts (w, then
+// the pair key a n + b).
 #include <algorithm>
 #include <cstring>
 
@@ -194,13 +195,28 @@ __global__ __launch_bounds__(BLK) void k_triad(const int64_t *__restrict__ wbase
     }
 }
 
-// solutions per flag word (optional) and their total
-__global__ __launch_bounds__(BLK) void k_triad_words(const uint32_t *__restrict__ flag, int64_t nw,
-                                                     int32_t *__restrict__ wcnt, unsigned long long *total) {
+// The survivors of item u sit in slots [base[u], base[u] + su[u]): per-item
+// slots of the one-pass filter (sparse over all triangles) or the compact slots
+// of the two-pass one.  The passes below touch only those slots; slot p's bits
+// are byte p of the flag array.
+__global__ __launch_bounds__(BLK) void k_triad_clear(const int64_t *__restrict__ base, const int32_t *__restrict__ su,
+                                                     int32_t NI, uint8_t *__restrict__ flag8) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < NI; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = base[u], p1 = p0 + su[u];
+        for (int64_t p = p0; p < p1; p++) flag8[p] = 0;
+    }
+}
+
+// solutions per item (optional) and their total
+__global__ __launch_bounds__(BLK) void k_triad_count(const int64_t *__restrict__ base, const int32_t *__restrict__ su,
+                                                     int32_t NI, const uint8_t *__restrict__ flag8,
+                                                     int32_t *__restrict__ icnt, unsigned long long *total) {
     unsigned long long c = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = __popc(flag[i]);
-        if (wcnt) wcnt[i] = x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < NI; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = base[u], p1 = p0 + su[u];
+        int32_t x = 0;
+        for (int64_t p = p0; p < p1; p++) x += __popc(flag8[p] & 0x3fu);
+        if (icnt) icnt[u] = x;
         c += (unsigned)x;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
@@ -217,22 +233,21 @@ __device__ inline void oriented_ends(const uint32_t *__restrict__ oeid, const in
     head = (x >> 31) ? hi : lo;
 }
 
-// each set bit as (w, its index, pair key a n + b), at the word's offset
-__global__ __launch_bounds__(BLK) void k_triad_emit(const uint32_t *__restrict__ flag, int64_t nw,
-                                                    const int64_t *__restrict__ woff, const int32_t *__restrict__ sv,
+// each set bit as (w, its index, pair key a n + b), from the item's offset
+__global__ __launch_bounds__(BLK) void k_triad_emit(const int64_t *__restrict__ base, const int32_t *__restrict__ su,
+                                                    int32_t NI, const int64_t *__restrict__ ioff,
+                                                    const uint8_t *__restrict__ flag8, const int32_t *__restrict__ sv,
                                                     const uint32_t *__restrict__ oeid, const int32_t *__restrict__ slo,
                                                     const int32_t *__restrict__ shi, int64_t n,
                                                     uint32_t *__restrict__ wkey, int32_t *__restrict__ idx,
                                                     unsigned long long *__restrict__ pkey) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
-    uint32_t f = flag[i];
-    if (!f) return;
-    int64_t o = woff[i];
-    for (int j = 0; j < 4; j++) {
-        const uint32_t bits = (f >> (8 * j)) & 0x3fu;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= NI) return;
+    const int64_t p0 = base[u], p1 = p0 + su[u];
+    int64_t o = ioff[u];
+    for (int64_t p = p0; p < p1; p++) {
+        const uint32_t bits = flag8[p] & 0x3fu;
         if (!bits) continue;
-        const int64_t p = 4 * i + j;
         int32_t x0, x1, x2, t;
         oriented_ends(oeid, slo, shi, sv[3 * p], x0, x1);
         oriented_ends(oeid, slo, shi, sv[3 * p + 1], t, x2);
@@ -283,27 +298,28 @@ void check_triad(const Graph *g, const folty_triad_query &q) {
         if (q.reserved[i]) fail(FOLTY_EINVAL, "reserved fields of the triad query must be 0");
 }
 
-// the listed triples of nw flag words, sorted by (a, b, w), copied to res->trip
-void list_triples(const Index &ix, const Workspace &ws, int64_t nw, int64_t nsol, Result *res, hipStream_t s) {
+// the listed triples, sorted by (a, b, w), copied to res->trip
+void list_triples(const Index &ix, const Workspace &ws, int64_t nsol, Result *res, hipStream_t s) {
     if (nsol > INT32_MAX) fail(FOLTY_EOVERFLOW, "%lld solution triples exceed the listing limit of 2^31 - 1",
                                (long long)nsol);
-    DevBuf wcnt, woff, wk, ix0, pk, wk2, ix2, pk2, trip;
-    wcnt.ensure(4 * (size_t)nw + 4);
-    woff.ensure(8 * (size_t)nw + 8);
+    const int32_t NI = ix.NI;
+    DevBuf icnt, ioff, wk, ix0, pk, wk2, ix2, pk2, trip;
+    icnt.ensure(4 * (size_t)NI + 4);
+    ioff.ensure(8 * (size_t)NI + 8);
     unsigned long long *dummy = ws.scal.as<unsigned long long>() + 12;
     k_fill<unsigned long long><<<1, 1, 0, s>>>(dummy, 0ull, 1);
-    k_triad_words<<<grid_for(nw, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), nw,
-                                                                     wcnt.as<int32_t>(), dummy);
+    k_triad_count<<<grid_for(NI, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), NI,
+                                                                     ws.tflag.as<uint8_t>(), icnt.as<int32_t>(), dummy);
     FOLTY_LAUNCHED();
     DevBuf cub;
-    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, wcnt.as<int32_t>(), woff.as<int64_t>(), nw, s);
+    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, icnt.as<int32_t>(), ioff.as<int64_t>(), NI, s);
     const size_t k = (size_t)nsol;
     const int endw = std::max(1, bit_length((uint64_t)ix.n - 1));
     const int endp = std::max(1, bit_length((uint64_t)ix.n * (uint64_t)ix.n - 1));
     need = std::max(need, sort_pairs_u32_i32(nullptr, 0, nullptr, nullptr, nullptr, nullptr, (int64_t)k, endw, s));
     need = std::max(need, sort_pairs_u64_i32(nullptr, 0, nullptr, nullptr, nullptr, nullptr, (int64_t)k, endp, s));
     cub.ensure(need);
-    exclusive_scan_i32_to_i64(cub.p, need, wcnt.as<int32_t>(), woff.as<int64_t>(), nw, s);
+    exclusive_scan_i32_to_i64(cub.p, need, icnt.as<int32_t>(), ioff.as<int64_t>(), NI, s);
     wk.ensure(4 * k);
     ix0.ensure(4 * k);
     pk.ensure(8 * k);
@@ -311,10 +327,10 @@ void list_triples(const Index &ix, const Workspace &ws, int64_t nw, int64_t nsol
     ix2.ensure(4 * k);
     pk2.ensure(8 * k);
     trip.ensure(12 * k);
-    k_triad_emit<<<grid_for(nw, BLK), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), nw, woff.as<int64_t>(),
-                                                   ws.sv.as<int32_t>(), ix.oeid.as<uint32_t>(), ix.slo.as<int32_t>(),
-                                                   ix.shi.as<int32_t>(), ix.n, wk.as<uint32_t>(), ix0.as<int32_t>(),
-                                                   pk.as<unsigned long long>());
+    k_triad_emit<<<grid_for(NI, BLK), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), NI, ioff.as<int64_t>(),
+                                                   ws.tflag.as<uint8_t>(), ws.sv.as<int32_t>(), ix.oeid.as<uint32_t>(),
+                                                   ix.slo.as<int32_t>(), ix.shi.as<int32_t>(), ix.n, wk.as<uint32_t>(),
+                                                   ix0.as<int32_t>(), pk.as<unsigned long long>());
     FOLTY_LAUNCHED();
     // by w, then stably by the pair key: (a, b, w) order
     sort_pairs_u32_i32(cub.p, need, wk.as<uint32_t>(), wk2.as<uint32_t>(), ix0.as<int32_t>(), ix2.as<int32_t>(),
@@ -367,7 +383,8 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
         if (slots > 0) {
             const int64_t nw = (slots + 3) / 4;
             ws.tflag.ensure(4 * (size_t)nw);
-            k_fill<uint32_t><<<grid_for(nw, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), 0u, nw);
+            k_triad_clear<<<grid_for(ix.NI, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), ix.NI,
+                                                                                ws.tflag.as<uint8_t>());
             FOLTY_LAUNCHED();
             TriadOut o{q.delta, ws.tflag.as<uint32_t>(), edge ? ws.tinst.as<unsigned long long>() : nullptr};
             // the first-hit search stops early, so longer chunks skip more of a run
@@ -392,8 +409,8 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
                                                               ix.ts.as<int64_t>(), dq, o, ipt, tot);
             });
             FOLTY_LAUNCHED();
-            k_triad_words<<<grid_for(nw, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.tflag.as<uint32_t>(), nw, nullptr,
-                                                                             tot + 2);
+            k_triad_count<<<grid_for(ix.NI, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), ix.NI,
+                                                                                ws.tflag.as<uint8_t>(), nullptr, tot + 2);
             FOLTY_LAUNCHED();
             FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
         }
@@ -411,7 +428,7 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
     res->n_triads = (int64_t)h[2];
     res->n_tinst = inst ? (int64_t)h[0] : -1;
     if ((q.flags & FOLTY_TRIAD_TRIPLES) && res->n_triads > 0)
-        list_triples(ix, ws, (slots + 3) / 4, res->n_triads, res.get(), s);
+        list_triples(ix, ws, res->n_triads, res.get(), s);
     FOLTY_HIP(hipEventRecord(ws.ev[3], s));
     if (edge) {
         DevBuf out;
@@ -438,6 +455,7 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
     res->stats.temporal_ms = ev_ms(ws.ev[5], ws.ev[2]);
     res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
     res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
+    maybe_one_pass(g, ws);
     return res.release();
 }
 
