@@ -14,6 +14,12 @@
  *   drops directions, parallel edges and self-loops).  A solution is a pair
  *   (a, b) with at least one certificate on it.
  *
+ * The same index also answers the other query shapes of the paper's Definition
+ * of a solution: exists u forall v forall w and exists u forall v exists w
+ * (folty_run_vertex_query, one solution vertex u at a time), and exists u exists
+ * v exists w (folty_run_triad_query: solution triples and temporal triangle
+ * counts).
+ *
  * Conventions for every call:
  *   - Every call returns FOLTY_OK (0) or a negative FOLTY_E* code; on error
  *     folty_last_error() returns a message for the calling thread.
