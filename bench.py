@@ -456,7 +456,7 @@ def main():
             rq = G.query(d, theta, variant)
             key = str(d) if variant == 0 else f"{d}/predicate{variant}"
             by_delta[key] = {k: rq.stats[k] for k in ("query_ms", "wedge_ms", "temporal_ms", "threshold_ms",
-                                                      "tests", "n_pairs", "n_certificates")}
+                                                      "tests", "n_pairs", "n_certificates", "filter_passes")}
             got = rq.counts()
             nz = np.nonzero((got != 0xFFFFFFFF) & (got > 0))[0]
             if nz.size > a.parity_sample:

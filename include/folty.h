@@ -153,6 +153,8 @@ typedef struct {
     double query_ms;          /* device time of the whole query */
     double latency_ms;        /* server: submit to result ready on the host */
     double queue_ms;          /* server: submit to start of its pass */
+    int64_t filter_passes;    /* query: enumeration passes of its filter (1, or 2 when the
+                                 survivors are written by a second pass; 0 without items) */
 } folty_stats;
 
 /* Message for the last failed call on this thread ("" if none).  Valid until the

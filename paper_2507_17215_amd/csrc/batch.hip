@@ -810,6 +810,7 @@ void plan_run(Plan *P, Result **outs) {
         Result *r = res[q].get();
         const Graph *g = P->graphs[P->qgraph[q]];
         fill_stats_from_index(g->ix, &r->stats);
+        r->stats.filter_passes = 1; // plans filter once, into per-item triangle slots
         r->stats.n_pairs = (int64_t)r->u.size();
         r->stats.n_certificates = r->n_certificates;
         r->stats.query_ms = P->last_ms / std::max(1, nq);

@@ -217,6 +217,7 @@ struct Workspace {
     DevBuf sbase;   // int64[NI+1] first survivor slot of each item
     const int64_t *slots = nullptr; // survivor slots of the last filter: sbase or the index's tri_base
     bool emit_timed = false;        // the last filter's second pass is bracketed by ev[6], ev[7]
+    int32_t filter_passes = 0;      // enumeration passes of the last filter
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
     DevBuf pairs_v; // uint32[2S]

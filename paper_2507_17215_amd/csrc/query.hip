@@ -333,6 +333,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
                          hipEvent_t e1, int64_t *tri, int64_t *tests) {
     *tests = -1; // known on the host only after the two-pass filter
     ws.emit_timed = false;
+    ws.filter_passes = 1;
     const int32_t NI = ix.NI;
     ws.su.ensure(4 * ((size_t)NI + 1));
     ws.wu.ensure(8 * ((size_t)NI + 1));
@@ -435,6 +436,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
         dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.ilist.as<int32_t>(), nl); });
         FOLTY_HIP(hipEventRecord(ws.ev[7], s));
         ws.emit_timed = true;
+        ws.filter_passes = 2;
     }
     return survivors;
 }
@@ -855,6 +857,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
         FOLTY_LAUNCHED();
     }
     int64_t tests = 0, tri = 0;
+    ws.filter_passes = 0;
     if (ix.NI > 0) {
         int64_t known = -1;
         const bool ss = (q.flags & FOLTY_QUERY_SMALLER_SIDE) != 0;
@@ -898,6 +901,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     res->stats.temporal_ms = ev_ms(ws.ev[5], ws.ev[2]);
     res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
     res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
+    res->stats.filter_passes = ws.filter_passes;
     maybe_one_pass(g, ws);
     return res.release();
 }

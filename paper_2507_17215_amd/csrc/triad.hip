@@ -377,6 +377,7 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
         }
     }
     int64_t tests = 0, tri = 0, slots = 0;
+    ws.filter_passes = 0;
     if (ix.NI > 0) {
         int64_t known = -1;
         slots = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known);
@@ -455,6 +456,7 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
     res->stats.temporal_ms = ev_ms(ws.ev[5], ws.ev[2]);
     res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
     res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
+    res->stats.filter_passes = ws.filter_passes;
     maybe_one_pass(g, ws);
     return res.release();
 }
