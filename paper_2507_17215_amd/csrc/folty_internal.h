@@ -229,7 +229,7 @@ struct Workspace {
     DevBuf vtmp;    // vertex queries: per-vertex counts, flags, offsets, output
     DevBuf diff;    // int32[2m+1] interval marks of the smaller-side evaluation and their prefix sum
     DevBuf tflag;   // exists-exists-exists: uint32[(survivor slots + 3) / 4] solution bits
-    DevBuf tinst;   // exists-exists-exists: uint64[m] temporal triangles per first edge
+    DevBuf tinst;   // exists-exists-exists: uint64[m_input] temporal triangles per first edge, input order
     PinnedBuf host;
     hipEvent_t ev[8] = {};
     bool events = false;

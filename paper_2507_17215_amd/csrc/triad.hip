@@ -42,7 +42,8 @@ __device__ inline int32_t past_window(const int64_t *__restrict__ L, int32_t fro
 struct TriadOut {
     int64_t delta;
     uint32_t *flag;                // bit run of byte (slot & 3) of word slot >> 2
-    unsigned long long *inst;      // temporal triangles per sorted edge, or null
+    unsigned long long *inst;      // temporal triangles per input edge, or null
+    const int32_t *perm;           // input position of each sorted edge (with inst)
 };
 
 // edges [l1s, l1s + cnt) of one run against its lists (L2, L3)
@@ -94,7 +95,7 @@ __device__ inline void triad_chunk(const TriadOut &o, const int64_t *__restrict_
             const unsigned long long pairs = (unsigned long long)(hi - lo) * (unsigned)h3 - (Fhi - Flo);
             if (pairs) {
                 any = true;
-                if (o.inst) atomicAdd(&o.inst[e], pairs);
+                if (o.inst) atomicAdd(&o.inst[o.perm[e]], pairs);
                 const unsigned long long s = acc + pairs;
                 ovf |= s < acc;
                 acc = s;
@@ -282,11 +283,6 @@ __global__ void k_triad_unpack(const unsigned long long *__restrict__ pkey, cons
     out[3 * i + 2] = (int32_t)w[i];
 }
 
-__global__ void k_scatter_u64(const unsigned long long *__restrict__ in, const int32_t *__restrict__ perm, int32_t m,
-                              unsigned long long *__restrict__ out) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) out[perm[k]] = in[k];
-}
 
 void check_triad(const Graph *g, const folty_triad_query &q) {
     if (!g->ix.built) fail(FOLTY_ENOTBUILT, "folty_build_index has not been called for this graph");
@@ -369,10 +365,11 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
     k_fill<unsigned long long><<<1, 4, 0, s>>>(tot, 0ull, 4);
     FOLTY_LAUNCHED();
     if (edge) {
-        ws.tinst.ensure(8 * (size_t)ix.m + 8);
-        if (ix.m > 0) {
-            k_fill<unsigned long long><<<grid_for(ix.m, BLK), BLK, 0, s>>>(ws.tinst.as<unsigned long long>(), 0ull,
-                                                                         ix.m);
+        // counted straight into input order (self-loops keep their 0)
+        ws.tinst.ensure(8 * (size_t)ix.m_input + 8);
+        if (ix.m_input > 0) {
+            k_fill<unsigned long long><<<grid_for(ix.m_input, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(
+                ws.tinst.as<unsigned long long>(), 0ull, ix.m_input);
             FOLTY_LAUNCHED();
         }
     }
@@ -387,7 +384,8 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
             k_triad_clear<<<grid_for(ix.NI, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), ix.NI,
                                                                                 ws.tflag.as<uint8_t>());
             FOLTY_LAUNCHED();
-            TriadOut o{q.delta, ws.tflag.as<uint32_t>(), edge ? ws.tinst.as<unsigned long long>() : nullptr};
+            TriadOut o{q.delta, ws.tflag.as<uint32_t>(), edge ? ws.tinst.as<unsigned long long>() : nullptr,
+                       ix.perm.as<int32_t>()};
             // the first-hit search stops early, so longer chunks skip more of a run
             // (70M edges, one year: 9.8 ms at 8 tests per chunk, 11.5 at one); the
             // counting of temporal triangles gains from neighbouring lanes on one
@@ -432,22 +430,10 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
         list_triples(ix, ws, res->n_triads, res.get(), s);
     FOLTY_HIP(hipEventRecord(ws.ev[3], s));
     if (edge) {
-        DevBuf out;
-        out.ensure(8 * (size_t)ix.m_input + 8);
-        if (ix.m_input > 0) {
-            k_fill<unsigned long long><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(out.as<unsigned long long>(), 0ull,
-                                                                               ix.m_input);
-            FOLTY_LAUNCHED();
-        }
-        if (ix.m > 0) {
-            k_scatter_u64<<<grid_for(ix.m, BLK), BLK, 0, s>>>(ws.tinst.as<unsigned long long>(),
-                                                              ix.perm.as<int32_t>(), ix.m,
-                                                              out.as<unsigned long long>());
-            FOLTY_LAUNCHED();
-        }
         res->tinst.resize((size_t)ix.m_input);
         if (ix.m_input > 0)
-            FOLTY_HIP(hipMemcpyAsync(res->tinst.data(), out.p, 8 * (size_t)ix.m_input, hipMemcpyDeviceToHost, s));
+            FOLTY_HIP(hipMemcpyAsync(res->tinst.data(), ws.tinst.p, 8 * (size_t)ix.m_input, hipMemcpyDeviceToHost,
+                                     s));
     }
     FOLTY_HIP(hipStreamSynchronize(s));
     fill_stats_from_index(ix, &res->stats);
