@@ -527,7 +527,8 @@ class Server:
 
 
 def release_cached_memory() -> int:
-    """Hand the library's cached device blocks back to the driver; returns bytes."""
+    """Hand the library's cached device blocks and pinned host blocks back to the
+    driver; returns bytes."""
     b = ctypes.c_int64()
     _check(load_library().folty_release_cached_memory(ctypes.byref(b)))
     return b.value

@@ -505,3 +505,24 @@ def test_large_sparse_id_space():
     cores = G.core_numbers()
     assert np.array_equal(cores[ids], o.core_numbers())
     assert (np.delete(cores, ids) == 0).all()
+
+
+def test_cached_memory_release_and_reuse():
+    """Result arrays of 1 MiB or more come from cached pinned host blocks; freeing
+    the result keeps its block, folty_release_cached_memory hands every cached
+    device and host block back, and later queries allocate afresh with the same
+    results."""
+    rng = np.random.default_rng(3)
+    n, m = 50_000, 600_000  # 2.4 MB of per-edge counts
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    t = rng.integers(0, 10**6, m).astype(np.int64)
+    G = folty.Graph(n, src, dst, t).build()
+    first = G.query(10**5, (1, 4), 0).counts()
+    say("release cached memory")
+    freed = folty.release_cached_memory()
+    assert freed >= 4 * m  # at least the counts' pinned block
+    again = G.query(10**5, (1, 4), 0).counts()
+    assert np.array_equal(first, again)
+    o = Oracle(n, src, dst, t)
+    assert np.array_equal(again, o.counts(10**5, 0))
