@@ -199,9 +199,10 @@ int folty_build_index(folty_graph *g, const folty_build_opts *opts);
  * (of any kind) whose second enumeration took at least half as long as the first,
  * the library counts the triangles per item once (one enumeration pass).  It does so
  * only when 20 bytes per triangle fit in a quarter of the free device memory.
- * Later queries on the graph then filter in one pass, with 20 bytes per triangle
- * of survivor slots in their workspace.  Plans (folty_plan_create) make the same
- * per-item counts.
+ * Later queries on the graph whose delta is at least an eighth of that query's
+ * then filter in one pass, with 20 bytes per triangle of survivor slots in their
+ * workspace.  Plans (folty_plan_create) make the same per-item counts, after
+ * which every query filters in one pass.
  */
 int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out);
 

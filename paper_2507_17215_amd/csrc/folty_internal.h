@@ -167,6 +167,7 @@ struct Index {
     int64_t sigma_max = 0;
     std::atomic<int64_t> T{-1}; // static triangles (-1 until a query or ensure_tri_base counted them)
     bool tri_base_ready = false; // tri_base holds per-item triangle offsets
+    int64_t one_pass_from = 0;   // with tri_base: single queries of delta >= this filter in one pass
     int64_t W = 0;           // oriented wedges: sum of C(|N+(x)|, 2)
     int64_t probes = 0;      // closing probes the enumeration makes: sum over (u,v) of |N+(v)|
     int32_t NI = 0;          // enumeration items
@@ -336,7 +337,7 @@ void ensure_tri_base(Index &ix, hipStream_t s); // caller holds Graph::lazy_mu o
 void ensure_triangles(Graph *g);                 // ensure_tri_base on the graph's stream, under lazy_mu
 // after a two-pass filter that enumerated most items a second time (a wide
 // window), make the per-item triangle offsets so later queries filter in one pass
-void maybe_one_pass(Graph *g, const Workspace &ws);
+void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta);
 
 // library-primitive wrappers (rocPRIM through hipCUB), all on `stream`
 size_t sort_pairs_u64_i32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,

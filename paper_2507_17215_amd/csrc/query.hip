@@ -372,7 +372,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
     using CountM = std::integral_constant<int, FILTER_COUNT>;
     using EmitM = std::integral_constant<int, FILTER_EMIT>;
     using BothM = std::integral_constant<int, FILTER_BOTH>;
-    if (ix.tri_base_ready) {
+    if (ix.tri_base_ready && dmax >= ix.one_pass_from) {
         // per-item triangle offsets exist: one pass writes survivors into them
         ws.sv.ensure(12 * (size_t)ix.T + 12);
         ws.sw.ensure(8 * (size_t)ix.T + 8);
@@ -762,9 +762,13 @@ void ensure_tri_base(Index &ix, hipStream_t s) {
 // least half as long as the first, per-item triangle offsets (one counting
 // enumeration, once per graph) let later queries write survivors into per-item
 // slots in a single pass, at 20 bytes of workspace per static triangle; that is
-// done when it fits in a quarter of the free device memory.
-void maybe_one_pass(Graph *g, const Workspace &ws) {
-    const Index &ix = g->ix;
+// done when it fits in a quarter of the free device memory.  Windows well below
+// the one that showed the cost (under an eighth of it) keep the two passes: their
+// second pass is short, and the one pass writes into slots sized for every
+// triangle (70M edges: 5.4-5.6 ms for one pass against 5.0-5.2 ms for the
+// counting pass at 1 hour and 1 day).
+void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta) {
+    Index &ix = g->ix;
     if (ix.tri_base_ready || !ws.emit_timed || ix.T <= 0) return;
     // the second pass cost at least half the first (events of the finished query)
     if (2 * ev_ms(ws.ev[6], ws.ev[7]) < ev_ms(ws.ev[4], ws.ev[5])) return;
@@ -774,6 +778,10 @@ void maybe_one_pass(Graph *g, const Workspace &ws) {
         return;
     }
     if ((size_t)ix.T * 20 > fr / 4) return;
+    {
+        std::lock_guard<std::mutex> lk(g->lazy_mu);
+        if (!ix.tri_base_ready) ix.one_pass_from = delta / 8;
+    }
     ensure_triangles(g);
 }
 
@@ -902,7 +910,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
     res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
     res->stats.filter_passes = ws.filter_passes;
-    maybe_one_pass(g, ws);
+    maybe_one_pass(g, ws, q.delta);
     return res.release();
 }
 

@@ -443,7 +443,7 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
     res->stats.threshold_ms = ev_ms(ws.ev[2], ws.ev[3]);
     res->stats.query_ms = ev_ms(ws.ev[0], ws.ev[3]);
     res->stats.filter_passes = ws.filter_passes;
-    maybe_one_pass(g, ws);
+    maybe_one_pass(g, ws, q.delta);
     return res.release();
 }
 
