@@ -5,10 +5,11 @@
  * stdin:  n m, then m lines "src dst t", then query lines:
  *           Q delta theta_num theta_den variant universe exclude_other
  *           T delta variant flags
+ *           V delta theta_num theta_den inner inner_num inner_den variant
  * stdout: for Q: "COUNTS" and the m per-edge counts, "PAIRS k" and k lines
  *         "u v n_cert", "NCERT |Sol|"; for T: "TRIADS n_solutions n_instances",
  *         the listed triples one per line, and "INST" with the per-edge counts
- *         when asked for.
+ *         when asked for; for V: "VERTICES k" and k lines "vertex good".
  * On an error it prints "ERROR code message" to stderr and exits with 2.
  */
 #include <stdio.h>
@@ -88,6 +89,26 @@ int main(void) {
                 for (long long i = 0; i < m; i++) printf(" %llu", (unsigned long long)inst[i]);
                 printf("\n");
             }
+        } else if (strcmp(kind, "V") == 0) {
+            long long delta;
+            unsigned num, den, inner, inum, iden, variant;
+            if (scanf("%lld %u %u %u %u %u %u", &delta, &num, &den, &inner, &inum, &iden, &variant) != 7) return 1;
+            folty_vertex_query q;
+            memset(&q, 0, sizeof q);
+            q.edge.delta = (int64_t)delta;
+            q.edge.theta_num = inum;
+            q.edge.theta_den = iden;
+            q.edge.variant = (uint8_t)variant;
+            q.theta_num = num;
+            q.theta_den = den;
+            q.inner = (uint8_t)inner;
+            check(folty_run_vertex_query(g, &q, &r), "vertex query");
+            int64_t nv = 0;
+            const int32_t *vs = NULL;
+            const uint32_t *good = NULL;
+            check(folty_result_vertices(r, &nv, &vs, &good), "vertices");
+            printf("VERTICES %lld\n", (long long)nv);
+            for (int64_t i = 0; i < nv; i++) printf("%d %u\n", vs[i], good[i]);
         } else {
             return 1;
         }

@@ -3,8 +3,8 @@
 * CPU: the header compiles as strict C99 with warnings as errors, the program
   links against libfolty.so, and without a GPU the first call fails loudly with
   FOLTY_EDEVICE (no CPU fallback).
-* GPU: the program's counts, pairs, |Sol| and exists-exists-exists triples equal
-  the hand-derived golden values.
+* GPU: the program's counts, pairs, |Sol|, exists-exists-exists triples and
+  vertex-query answers equal the hand-derived golden values.
 """
 import json
 import os
@@ -71,3 +71,18 @@ def test_c_client_matches_golden_values(tmp_path):
         assert [[int(x) for x in out[pos + 1 + i].split()] for i in range(ns)] == c["triples"]
         assert out[pos + 1 + ns] == "INST" + "".join(f" {x}" for x in c["instances"])
         pos += 2 + ns
+    v = json.load(open(os.path.join(GOLD, "vertex_cases.json")))
+    lines = []
+    for c in v["cases"]:
+        inner = 1 if c["inner"] == "exists" else 0
+        it = c.get("inner_theta", [1, 1])
+        lines.append(f"V {c['delta']} {c['theta'][0]} {c['theta'][1]} {inner} {it[0]} {it[1]} 0")
+    p = run_client(exe, v["graph"]["n"], v["graph"]["edges"], lines)
+    assert p.returncode == 0, p.stderr
+    out = p.stdout.splitlines()
+    pos = 0
+    for c in v["cases"]:
+        k = int(out[pos].split()[1])
+        got = [[int(x) for x in out[pos + 1 + i].split()] for i in range(k)]
+        assert got == [[a, b] for a, b in zip(c["vertices"], c["good"])], c
+        pos += 1 + k
