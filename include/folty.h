@@ -273,6 +273,11 @@ typedef struct {
 
 int folty_run_triad_query(folty_graph *g, const folty_triad_query *q, folty_result **out);
 
+/* The same with caller-owned scratch memory (see folty_workspace_create), for
+ * exists-exists-exists queries on one graph from several threads at once. */
+int folty_run_triad_query_ws(folty_graph *g, const folty_triad_query *q, folty_workspace *ws,
+                             folty_result **out);
+
 /*
  * Exists-exists-exists result: the number of solution triples, the number of
  * temporal triangles (-1 unless FOLTY_TRIAD_INSTANCES was asked) and, with

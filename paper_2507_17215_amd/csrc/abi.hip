@@ -128,6 +128,20 @@ int folty_run_triad_query(folty_graph *g, const folty_triad_query *q, folty_resu
     });
 }
 
+int folty_run_triad_query_ws(folty_graph *g, const folty_triad_query *q, folty_workspace *ws,
+                             folty_result **out) {
+    return guarded([&] {
+        if (!g || !q || !ws || !out) fail(FOLTY_EINVAL, "null argument");
+        *out = nullptr;
+        StreamScope sc(g->g.stream);
+        Result *r = run_triad_query(&g->g, *q, ws->ws);
+        folty_result *h = new folty_result();
+        h->r = std::move(*r);
+        delete r;
+        *out = h;
+    });
+}
+
 int folty_result_triads(const folty_result *r, int64_t *n_solutions, int64_t *n_instances,
                         const int32_t **triples) {
     return guarded([&] {

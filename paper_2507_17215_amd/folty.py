@@ -28,7 +28,8 @@ U32_MAX = 0xFFFFFFFF
 EXPORTS = (
     "folty_last_error", "folty_version", "folty_load_temporal_graph", "folty_build_index",
     "folty_run_fol_query", "folty_run_vertex_query", "folty_result_vertices",
-    "folty_run_triad_query", "folty_result_triads", "folty_result_edge_instances",
+    "folty_run_triad_query", "folty_run_triad_query_ws", "folty_result_triads",
+    "folty_result_edge_instances",
     "folty_workspace_create", "folty_workspace_free",
     "folty_run_fol_query_ws", "folty_run_batch", "folty_run_multi", "folty_result_pairs",
     "folty_result_counts", "folty_result_stats", "folty_result_free", "folty_graph_stats",
@@ -139,6 +140,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.folty_run_vertex_query.argtypes = [P, ctypes.POINTER(VertexQuery), PP]
     lib.folty_result_vertices.argtypes = [P, ctypes.POINTER(I64), PP, PP]
     lib.folty_run_triad_query.argtypes = [P, ctypes.POINTER(TriadQuery), PP]
+    lib.folty_run_triad_query_ws.argtypes = [P, ctypes.POINTER(TriadQuery), P, PP]
     lib.folty_result_triads.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), PP]
     lib.folty_result_edge_instances.argtypes = [P, PP]
     lib.folty_workspace_create.argtypes = [PP]
@@ -372,7 +374,7 @@ class Graph:
         return Result(out)
 
     def triad_query(self, delta, variant=0, triples=True, instances=True,
-                    edge_instances=False) -> Result:
+                    edge_instances=False, workspace: Workspace | None = None) -> Result:
         """exists u exists v exists w: solution triples and temporal triangles."""
         q = TriadQuery()
         q.delta = int(delta)
@@ -380,7 +382,11 @@ class Graph:
         q.flags = ((TRIAD_TRIPLES if triples else 0) | (TRIAD_INSTANCES if instances else 0)
                    | (TRIAD_EDGE_INSTANCES if edge_instances else 0))
         out = ctypes.c_void_p()
-        _check(load_library().folty_run_triad_query(self._h, ctypes.byref(q), ctypes.byref(out)))
+        lib = load_library()
+        if workspace is None:
+            _check(lib.folty_run_triad_query(self._h, ctypes.byref(q), ctypes.byref(out)))
+        else:
+            _check(lib.folty_run_triad_query_ws(self._h, ctypes.byref(q), workspace._h, ctypes.byref(out)))
         return Result(out)
 
     def query_raw(self, q: Query) -> Result:

@@ -198,3 +198,35 @@ def test_triads_medium_workload():
         t = assert_triads(G, o, d, v)
         say("medium", d, v, "solutions", t["n_solutions"], "temporal triangles", t["n_instances"],
             "query ms", G.triad_query(d, v, triples=False).stats["query_ms"])
+
+
+def test_triads_from_threads_with_workspaces():
+    """Concurrent exists-exists-exists queries on one graph, each thread with its
+    own workspace, give the results of the same queries run alone."""
+    import threading
+    g = synth.tiny(seed=14)
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    cases = [(3600, 0), (86400, 1), (10**6, 6), (INF, 3)]
+    alone = {c: G.triad_query(c[0], c[1], edge_instances=True) for c in cases}
+    want = {c: (r.triads(), r.edge_instances()) for c, r in alone.items()}
+    errors = []
+
+    def work(c):
+        try:
+            ws = folty.Workspace()
+            for _ in range(3):
+                r = G.triad_query(c[0], c[1], edge_instances=True, workspace=ws)
+                t = r.triads()
+                assert t["n_solutions"] == want[c][0]["n_solutions"]
+                assert np.array_equal(t["triples"], want[c][0]["triples"])
+                assert np.array_equal(r.edge_instances(), want[c][1])
+        except Exception as e:  # reported below
+            errors.append((c, repr(e)))
+
+    say("threads", len(cases))
+    ts = [threading.Thread(target=work, args=(c,)) for c in cases]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors
