@@ -134,7 +134,8 @@ typedef struct {
     int64_t wedges;           /* sum over x of C(|N+(x)|, 2): oriented wedges, one closing probe each */
     int64_t triangles;        /* static triangles (counted by the first query or stats call) */
     int64_t max_multiplicity; /* sigma_max: longest list E_{x,y} */
-    int64_t peel_rounds;      /* rounds of the min-degree peeling */
+    int64_t peel_rounds;      /* rounds of the min-degree peeling within a level: the levels peel
+                                 at once, so this is the most rounds any one level needs */
     int64_t closing_probes;   /* membership probes of the enumeration: sum over oriented edges
                                  (u,v) of min(|N+(u)|, |N+(v)|) */
     int64_t enum_items;       /* work items the enumeration is split into */
@@ -155,6 +156,7 @@ typedef struct {
     double queue_ms;          /* server: submit to start of its pass */
     int64_t filter_passes;    /* query: enumeration passes of its filter (1, or 2 when the
                                  survivors are written by a second pass; 0 without items) */
+    int64_t core_sweeps;      /* h-index sweeps that settled the core numbers */
 } folty_stats;
 
 /* Message for the last failed call on this thread ("" if none).  Valid until the

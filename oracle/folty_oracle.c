@@ -263,19 +263,44 @@ static uint32_t og_count_one(const og_graph *g, int64_t i, int64_t delta, int va
  * count[] for the edges idx[0..k) (input positions), or for all m edges when
  * idx is NULL (then out is indexed by input position).  Self-loops get
  * UINT32_MAX.  Returns 0, or -1 on bad arguments.
+ *
+ * For all edges the common neighbours of a pair are found once and serve every
+ * temporal edge of its list E_{a,b}, as the paper's practical algorithm does
+ * per static edge (Algorithm PRACTICAL-EEA); the per-edge test is the same.
  */
 int og_counts(const og_graph *g, int64_t k, const int64_t *idx, int64_t delta, int variant,
               uint32_t *out, int threads) {
     if (delta < 0 || variant < 0 || variant > 7) return -1;
     if (threads > 0) omp_set_num_threads(threads);
-    int64_t cnt = idx ? k : g->m;
+    if (!idx) {
+        for (int64_t i = 0; i < g->m; i++)
+            if (g->src[i] == g->dst[i]) out[i] = UINT32_MAX;
+#pragma omp parallel
+        {
+            int32_t *buf = NULL;
+            int64_t cap = 0;
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t p = 0; p < g->np; p++) {
+                int32_t a = (int32_t)(g->pkey[p] / g->n), b = (int32_t)(g->pkey[p] % g->n);
+                int64_t need = g->adj_off[a + 1] - g->adj_off[a];
+                int64_t nb = g->adj_off[b + 1] - g->adj_off[b];
+                if (nb < need) need = nb;
+                if (need + 1 > cap) { free(buf); cap = need + 1; buf = (int32_t *)malloc(sizeof(int32_t) * cap); }
+                int64_t nc = og_common(g, a, b, buf);
+                for (int64_t j = g->poff[p]; j < g->poff[p + 1]; j++)
+                    out[g->pidx[j]] = og_count_one(g, g->pidx[j], delta, variant, buf, nc);
+            }
+            free(buf);
+        }
+        return 0;
+    }
 #pragma omp parallel
     {
         int32_t *buf = NULL;
         int64_t cap = 0;
 #pragma omp for schedule(dynamic, 64)
-        for (int64_t q = 0; q < cnt; q++) {
-            int64_t i = idx ? idx[q] : q;
+        for (int64_t q = 0; q < k; q++) {
+            int64_t i = idx[q];
             int32_t a = g->src[i], b = g->dst[i];
             if (a == b) { out[q] = UINT32_MAX; continue; }
             int64_t need = g->adj_off[a + 1] - g->adj_off[a];
@@ -403,6 +428,65 @@ void og_core_numbers(const og_graph *g, int32_t *core) {
     }
     for (int32_t x = 0; x < n; x++) core[x] = (int32_t)deg[x];
     free(deg); free(bin); free(pos); free(vert);
+}
+
+/*
+ * The degeneracy ordering as level-synchronous min-degree peeling (Section
+ * "Main Ideas", Preliminaries: repeatedly remove a vertex of minimum degree).
+ * Level k starts once no remaining vertex has degree below k; each round of
+ * the level removes, all at once, every remaining vertex whose degree among the
+ * remaining vertices is at most k, until a round finds none.  core[x] = k is
+ * the level of x and rnd[x] the round of that level in which x went (0 for the
+ * first).  Ordering vertices by (core, rnd, id) leaves each vertex at most k
+ * neighbours after it: they were all still there when its round began.
+ * Vertices whose degree passes above the current level wait in a bucket of
+ * their degree (stale bucket entries are skipped).
+ */
+void og_peel_levels(const og_graph *g, int32_t *core, int32_t *rnd) {
+    int32_t n = g->n;
+    int64_t maxd = 0;
+    int64_t *dc = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    for (int32_t x = 0; x < n; x++) {
+        dc[x] = g->adj_off[x + 1] - g->adj_off[x];
+        if (dc[x] > maxd) maxd = dc[x];
+    }
+    int64_t cap = (int64_t)n + g->adj_off[n] + 1;
+    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * ((size_t)maxd + 1));
+    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    int32_t *val = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    int64_t used = 0;
+    for (int64_t d = 0; d <= maxd; d++) head[d] = -1;
+    for (int32_t x = 0; x < n; x++) {
+        val[used] = x; next[used] = head[dc[x]]; head[dc[x]] = used; used++;
+    }
+    char *gone = (char *)calloc((size_t)n + 1, 1);
+    char *queued = (char *)calloc((size_t)n + 1, 1);
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *nxt = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    for (int64_t k = 0; k <= maxd; k++) {
+        int64_t nc = 0;
+        for (int64_t e = head[k]; e >= 0; e = next[e]) {
+            int32_t x = val[e];
+            if (!gone[x] && !queued[x] && dc[x] == k) { queued[x] = 1; cur[nc++] = x; }
+        }
+        for (int32_t r = 0; nc > 0; r++) {
+            for (int64_t i = 0; i < nc; i++) { gone[cur[i]] = 1; core[cur[i]] = (int32_t)k; rnd[cur[i]] = r; }
+            int64_t nn = 0;
+            for (int64_t i = 0; i < nc; i++) {
+                int32_t x = cur[i];
+                for (int64_t j = g->adj_off[x]; j < g->adj_off[x + 1]; j++) {
+                    int32_t u = g->adj[j];
+                    if (gone[u]) continue;
+                    dc[u]--;
+                    if (dc[u] == k) { if (!queued[u]) { queued[u] = 1; nxt[nn++] = u; } }
+                    else if (dc[u] > k) { val[used] = u; next[used] = head[dc[u]]; head[dc[u]] = used; used++; }
+                }
+            }
+            int32_t *t = cur; cur = nxt; nxt = t;
+            nc = nn;
+        }
+    }
+    free(dc); free(head); free(next); free(val); free(gone); free(queued); free(cur); free(nxt);
 }
 
 int og_num_threads(void) { return omp_get_max_threads(); }

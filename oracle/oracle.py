@@ -74,6 +74,7 @@ def _load():
         lib.og_common_counts.argtypes = [P, i64, P, P, ctypes.c_int]
         lib.og_sizes.argtypes = [P, P, ctypes.c_int]
         lib.og_core_numbers.argtypes = [P, P]
+        lib.og_peel_levels.argtypes = [P, P, P]
         lib.og_num_threads.restype = ctypes.c_int
         lib.og_triad_instances.restype = ctypes.c_int
         lib.og_triad_instances.argtypes = [P, i64, P, i64, ctypes.c_int, P, ctypes.c_int]
@@ -181,6 +182,22 @@ class Oracle:
         out = np.zeros(self.n, dtype=np.int32)
         _load().og_core_numbers(self._h, _ptr(out))
         return out
+
+    def peel_levels(self):
+        """Level and round of each vertex in level-synchronous min-degree
+        peeling: (core numbers, round within the level)."""
+        core = np.zeros(self.n, dtype=np.int32)
+        rnd = np.zeros(self.n, dtype=np.int32)
+        _load().og_peel_levels(self._h, _ptr(core), _ptr(rnd))
+        return core, rnd
+
+    def degeneracy_rank(self) -> np.ndarray:
+        """Position of each vertex when ordered by (core, round within the level, id)."""
+        core, rnd = self.peel_levels()
+        order = np.lexsort((np.arange(self.n), rnd, core))
+        rank = np.empty(self.n, dtype=np.int32)
+        rank[order] = np.arange(self.n, dtype=np.int32)
+        return rank
 
     # -- threshold step and solutions ----------------------------------------------
     def universe_sizes(self, idx=None, universe: int = 0, exclude_other: bool = False):

@@ -173,7 +173,8 @@ struct Index {
     int32_t NI = 0;          // enumeration items
     int32_t max_core = 0;
     int32_t max_out = 0;
-    int64_t peel_rounds = 0;
+    int64_t peel_rounds = 0;  // rounds of the all-levels peel (the most any one level needs)
+    int64_t core_sweeps = 0;  // h-index sweeps until the core numbers settled
     int32_t rank_mode = 0;
     bool built = false;
     bool tri_cached = false;
@@ -357,6 +358,15 @@ size_t inclusive_scan_i32(void *tmp, size_t tmp_bytes, const int32_t *in, int32_
                           hipStream_t stream);
 size_t exclusive_scan_i32(void *tmp, size_t tmp_bytes, const int32_t *in, int32_t *out, int64_t n,
                           hipStream_t stream);
+
+// core numbers and degeneracy rank keys (core.hip)
+struct CoreStats {
+    int32_t sweeps = 0;   // h-index sweeps with work
+    int32_t rounds = 0;   // rounds of the all-levels peel
+    int32_t global_h = 0; // h-index of the degree sequence (the starting bound)
+};
+int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const int32_t *deg, int32_t *core,
+                   uint32_t *key, hipStream_t s, CoreStats *out);
 
 inline int bit_length(uint64_t x) {
     int b = 0;

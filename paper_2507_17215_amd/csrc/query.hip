@@ -927,6 +927,7 @@ void fill_stats_from_index(const Index &ix, folty_stats *s) {
     s->triangles = ix.T;
     s->max_multiplicity = ix.sigma_max;
     s->peel_rounds = ix.peel_rounds;
+    s->core_sweeps = ix.core_sweeps;
     s->closing_probes = ix.probes;
     s->enum_items = ix.NI;
     s->build_ms = ix.build_ms;

@@ -98,7 +98,7 @@ class Stats(ctypes.Structure):
         "closing_probes", "enum_items", "batch_size", "tests",
         "n_pairs", "n_certificates")] + [(f, ctypes.c_double) for f in (
             "build_ms", "wedge_ms", "temporal_ms", "threshold_ms", "query_ms", "latency_ms",
-            "queue_ms")] + [("filter_passes", ctypes.c_int64)]
+            "queue_ms")] + [("filter_passes", ctypes.c_int64), ("core_sweeps", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     assert folty.Query.variant.offset == 16
     assert folty.Query.flags.offset == 19
     assert ctypes.sizeof(folty.BuildOpts) == 16
-    assert ctypes.sizeof(folty.Stats) == 18 * 8 + 7 * 8 + 8
+    assert ctypes.sizeof(folty.Stats) == 18 * 8 + 7 * 8 + 2 * 8
     assert ctypes.sizeof(folty.VertexQuery) == 40
     assert ctypes.sizeof(folty.TriadQuery) == 16
     assert folty.TriadQuery.variant.offset == 8 and folty.TriadQuery.flags.offset == 9

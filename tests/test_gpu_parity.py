@@ -116,11 +116,12 @@ def test_index_matches_oracle_static_quantities():
         core = o.core_numbers()
         assert np.array_equal(G.core_numbers(), core)
         assert st["max_core"] == core.max()
-        # the rank (core, peel round, id) bounds every out-degree by the degeneracy
-        assert G.out_degrees().max() <= core.max()
-        assert st["max_out_degree"] <= st["max_core"]
+        # the rank is the order (core, round within the level, id) of level-synchronous
+        # min-degree peeling, which leaves every vertex at most core(x) out-edges
         ranks = G.ranks()
-        assert np.array_equal(np.sort(ranks), np.arange(g.n))
+        assert np.array_equal(ranks, o.degeneracy_rank())
+        assert (G.out_degrees() <= core).all()
+        assert st["max_out_degree"] <= st["max_core"]
         od = G.out_degrees()
         assert st["wedges"] == int((od.astype(np.int64) * (od - 1) // 2).sum())
 
@@ -445,7 +446,10 @@ def test_medium_workload_full_counts():
     say("medium: gpu build")
     G = gpu_graph(g)
     st = G.stats()
-    assert np.array_equal(G.core_numbers(), o.core_numbers())
+    core = o.core_numbers()
+    assert np.array_equal(G.core_numbers(), core)
+    assert np.array_equal(G.ranks(), o.degeneracy_rank())
+    assert (G.out_degrees() <= core).all()
     assert st["max_out_degree"] <= st["max_core"]
     for j, d in enumerate(deltas):
         for th in ((1, 4), (1, 2), (3, 4)):

@@ -192,6 +192,84 @@ def test_core_numbers_match_networkx():
         assert all(core[x] == want[x] for x in range(gen.n))
 
 
+def _peel_rounds_networkx(n, src, dst):
+    """Level-synchronous min-degree peeling restated on networkx: at level k,
+    rounds remove every remaining vertex whose degree in the subgraph induced
+    by the remaining vertices is at most k (degrees from networkx)."""
+    G = _nx_graph(n, src, dst)
+    core = np.full(n, -1, np.int64)
+    rnd = np.full(n, -1, np.int64)
+    left = set(range(n))
+    k = 0
+    while left:
+        H = G.subgraph(left)
+        if min(d for _, d in H.degree()) > k:
+            k += 1
+            continue
+        r = 0
+        while True:
+            H = G.subgraph(left)
+            out = [v for v, d in H.degree() if d <= k]
+            if not out:
+                break
+            for v in out:
+                core[v], rnd[v] = k, r
+            left -= set(out)
+            r += 1
+        k += 1
+    return core, rnd
+
+
+def test_peel_levels_hand_cases():
+    # path 0-1-2-3-4: level 1 takes the two ends, then their neighbours, then the middle
+    o = Oracle(5, np.array([0, 1, 2, 3], np.int32), np.array([1, 2, 3, 4], np.int32), np.zeros(4, np.int64))
+    core, rnd = o.peel_levels()
+    assert core.tolist() == [1, 1, 1, 1, 1] and rnd.tolist() == [0, 1, 2, 1, 0]
+    assert o.degeneracy_rank().tolist() == [0, 2, 4, 3, 1]
+    # star with the centre at the lowest id: the leaves go first, the centre one round later,
+    # so the centre keeps no out-edge (an order by (core, id) alone would give it five)
+    o = Oracle(6, np.zeros(5, np.int32), np.arange(1, 6, dtype=np.int32), np.zeros(5, np.int64))
+    core, rnd = o.peel_levels()
+    assert core.tolist() == [1] * 6 and rnd.tolist() == [1, 0, 0, 0, 0, 0]
+    assert o.degeneracy_rank().tolist() == [5, 0, 1, 2, 3, 4]
+    # triangle 0-1-2 with a pendant 3 on 2: level 1 takes 3; level 2 takes the triangle at once
+    o = Oracle(4, np.array([0, 1, 2, 2], np.int32), np.array([1, 2, 0, 3], np.int32), np.zeros(4, np.int64))
+    core, rnd = o.peel_levels()
+    assert core.tolist() == [2, 2, 2, 1] and rnd.tolist() == [0, 0, 0, 0]
+
+
+def test_peel_levels_match_networkx_rounds():
+    rng = np.random.default_rng(77)
+    cases = [synth.random_small(rng, n_max=30, m_max=90) for _ in range(60)]
+    cases += [synth.bruteforce_size()]
+    for g in cases:
+        o = Oracle(g.n, g.src, g.dst, g.t)
+        core, rnd = o.peel_levels()
+        want_core, want_rnd = _peel_rounds_networkx(g.n, g.src, g.dst)
+        assert np.array_equal(core, want_core) and np.array_equal(rnd, want_rnd)
+
+
+def test_peel_levels_core_numbers_and_out_degree_bound():
+    import networkx as nx
+    for gen in (synth.tiny(), synth.bruteforce_size(),
+                synth.generate(3000, 40000, 2.0, law="pareto", cap=50, times="uniform",
+                               t_range=1000, seed=5, communities=3, c_min=40, c_max=80, c_p=0.5)):
+        o = Oracle(gen.n, gen.src, gen.dst, gen.t)
+        core, _ = o.peel_levels()
+        assert np.array_equal(core, o.core_numbers())
+        want = nx.core_number(_nx_graph(gen.n, gen.src, gen.dst))
+        assert all(core[x] == want[x] for x in range(gen.n))
+        # every vertex has at most core(x) neighbours ranked after it
+        rank = o.degeneracy_rank()
+        keep = gen.src != gen.dst
+        a, b = gen.src[keep].astype(np.int64), gen.dst[keep].astype(np.int64)
+        k = np.unique(np.minimum(a, b) * gen.n + np.maximum(a, b))
+        lo, hi = k // gen.n, k % gen.n
+        tail = np.where(rank[lo] < rank[hi], lo, hi)
+        out = np.bincount(tail, minlength=gen.n)
+        assert (out <= core).all()
+
+
 def test_theta_zero_and_one():
     g = synth.bruteforce_size()
     o = Oracle(g.n, g.src, g.dst, g.t)
