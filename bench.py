@@ -1,14 +1,18 @@
 """Benchmark: the thresholded exists-exists-forall query on a 70M-edge temporal graph.
 
 One step is the whole hot path over device-resident inputs: load + validate the
-edge list, build the index (grouping sort, static edge table, degrees, GPU
-min-degree peeling, orientation, triangle counts), then one query (wedge
-enumeration + closing probe, temporal tests, threshold, pair reduction) ending
-with the sorted solution pairs on the host.
+edge list, build the index (grouping sort, static edge table, degrees, core
+numbers and the degeneracy rank, orientation, triangle counts), then one query
+(wedge enumeration + closing probe, temporal tests, threshold, pair reduction)
+ending with the sorted solution pairs on the host.
 
 Prints ONE JSON line.  `value` is wedge checks per second over the whole step.
-Also checks sampled per-edge counts of the timed configuration against the CPU
-oracle and times the oracle on a bounded sample of the same workload.
+Outside the timed steps it checks every per-edge count, the pair list, the
+certificate counts and |Sol| of the timed query against the CPU oracle run over
+all edges, and reports that oracle run's wall time as the CPU baseline; checks
+the small and medium workloads, the batched plans and served requests against
+the oracle; and times the batched and served forms against the same queries run
+one at a time.
 """
 from __future__ import annotations
 
@@ -25,9 +29,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "wedge-checks/sec & query wall-time at 70M edges (bit-exact); batched queries/sec, p99"
 HBM_PEAK_GBS = 8000.0
+# vector ALU issue of the whole chip: 256 CUs x 4 SIMDs, one wave64 instruction
+# every 4 cycles per SIMD, 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 # the query's dominant kernel, the sources it is compiled from, and the committed
 # counter summary (FETCH_SIZE / WRITE_SIZE per dispatch and the copy-kernel
-# calibration) that gives its measured HBM traffic
+# calibration, SQ_INSTS_VALU) that gives its measured HBM traffic and issue rate
 ROOF_KERNEL = "k_tri_enum<FilterSink<0, 0, false> >"
 ROOF_SOURCES = ("paper_2507_17215_amd/csrc/tri_device.h", "paper_2507_17215_amd/csrc/query.hip")
 TRAFFIC_SUMMARY = "profiles/k_tri_enum_filter_large_70M_pmc.md"
@@ -46,17 +53,19 @@ def parse():
     p.add_argument("--scale", type=float, default=1.0,
                    help="fraction of the 70M-edge workload (for quick local runs)")
     p.add_argument("--delta", type=int, default=3600)
-    p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-parity", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=3_000_000,
-                   help="temporal edges in the oracle's timed sample")
+    p.add_argument("--no-cpu-baseline", action="store_true",
+                   help="skip the oracle run over all edges (and with it the full parity check)")
+    p.add_argument("--no-parity", action="store_true", help="skip every check against the oracle")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the vertex, exists-exists-exists and smaller-side sections")
+    p.add_argument("--no-configs", action="store_true", help="skip the small and medium workloads")
     p.add_argument("--parity-sample", type=int, default=4000)
     p.add_argument("--cache-dir", default=None,
                    help="keep the generated graph here as .npy files and reuse it")
     p.add_argument("--no-batch", action="store_true", help="skip the batched section")
     p.add_argument("--no-serve", action="store_true", help="skip the serving section")
-    p.add_argument("--serve-full", action="store_true",
-                   help="serving on all eight graphs (up to 7e7 edges) at five arrival rates")
+    p.add_argument("--serve-small", action="store_true",
+                   help="serving on the five smaller graphs at two rates only")
     p.add_argument("--copy-probe", action="store_true",
                    help="only copy a 1 GiB device buffer three times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -71,10 +80,11 @@ def sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, scaled by the same counters' reading for a plain copy of known size;
-    None when the summary is missing or the kernel's sources changed since."""
+def counter_summary():
+    """The dominant kernel's counters from the committed summary: HBM bytes per
+    launch (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads
+    for a plain copy of known size) and VALU instructions per launch; None when
+    the summary is missing or the kernel's sources changed since."""
     path = os.path.join(ROOT, TRAFFIC_SUMMARY)
     if not os.path.exists(path):
         return None, "no counter summary"
@@ -89,7 +99,20 @@ def measured_traffic():
         return None, "kernel sources changed since the counters were taken"
     f_fetch = rec["copy_bytes"] / (rec["copy_fetch_kib"] * 1024.0)
     f_write = rec["copy_bytes"] / (rec["copy_write_kib"] * 1024.0)
-    return rec["fetch_kib"] * 1024.0 * f_fetch + rec["write_kib"] * 1024.0 * f_write, "ok"
+    out = {"traffic": rec["fetch_kib"] * 1024.0 * f_fetch + rec["write_kib"] * 1024.0 * f_write,
+           "valu_insts": rec.get("valu_insts")}
+    return out, "ok"
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_probe():
@@ -117,11 +140,25 @@ def load_or_generate(synth, n, m, comm, cache_dir):
     return g
 
 
-def batched_section(folty, synth, steps):
+def check_against(res, want):
+    """Mismatches between a GPU result and an oracle answer (pairs, certificate
+    counts, |Sol|)."""
+    u, v, k = res.pair_u, res.pair_v, res.n_cert
+    same = (np.array_equal(u, want["pair_u"]) and np.array_equal(v, want["pair_v"])
+            and np.array_equal(k, want["n_cert"]) and res.n_certificates == want["n_certificates"])
+    return 0 if same else 1
+
+
+def batched_section(folty, synth, steps, oracle_check, threads, rng):
     """64 mixed queries on one resident 10M-edge graph, and one query on each of
     32 graphs of 1e3..1e6 edges: plans (one launch sequence each, replayed from a
-    HIP graph) against the same queries run one at a time."""
+    HIP graph) against the same queries run one at a time.  The plans' results are
+    checked against the oracle: on the 32 graphs every edge, pair and certificate;
+    on the 10M-edge graph every pair and certificate count (from the oracle's
+    counts over all edges in its many-window pass) and the per-edge counts of
+    sampled edges plus edges the GPU counts as non-zero."""
     import torch
+    from oracle.oracle import Oracle
     out = {}
     g = synth.c1_family(10_000_000, seed=0)
     G = folty.Graph(g.n, g.src, g.dst, g.t).build()
@@ -157,28 +194,105 @@ def batched_section(folty, synth, steps):
         log(f"batched {name}: plan {plan_s * 1e3:.2f} ms ({n / plan_s:.0f} q/s), sequential "
             f"{seq_s * 1e3:.2f} ms ({n / seq_s:.0f} q/s), identical results: {same}")
         plan.close()
+    if oracle_check:
+        # the same plans with per-edge counts kept, against the oracle
+        t0 = time.perf_counter()
+        plan = folty.Plan([G], [(0, dict(q, counts=True)) for q in qs])
+        res = plan.run()
+        o = Oracle(g.n, g.src, g.dst, g.t, threads=threads)
+        bad_pairs = bad_edges = checked = 0
+        for variant in (0, 3):
+            ds = sorted({q["delta"] for q in qs if q["variant"] == variant})
+            pool = o.counts_pool(ds, variant)
+            for q, r in zip(qs, res):
+                if q["variant"] != variant:
+                    continue
+                col = pool[:, ds.index(q["delta"])]
+                want = o.query(q["delta"], q["theta"][0], q["theta"][1], variant, counts=col)
+                bad_pairs += check_against(r, want)
+                got = r.counts()
+                nz = np.nonzero((got != 0xFFFFFFFF) & (got > 0))[0]
+                idx = np.union1d(rng.choice(g.m, size=4000, replace=False),
+                                 rng.choice(nz, size=min(4000, nz.size), replace=False) if nz.size else nz)
+                bad_edges += int((got[idx] != col[idx]).sum())
+                checked += int(idx.size)
+        o.close()
+        plan.close()
+        plan = folty.Plan(Gs, [(i, dict(q, counts=True)) for i, q in enumerate(q32)])
+        res32 = plan.run()
+        bad32 = 0
+        for x, q, r in zip(graphs, q32, res32):
+            ox = Oracle(x.n, x.src, x.dst, x.t, threads=threads)
+            want = ox.query(q["delta"], q["theta"][0], q["theta"][1], q["variant"])
+            bad32 += check_against(r, want) + int((r.counts() != want["counts"]).sum())
+            ox.close()
+        plan.close()
+        out["oracle_check"] = {"one_graph_64_queries": {"queries": len(qs), "pair_mismatches": bad_pairs,
+                                                        "edges_checked": checked, "edge_mismatches": bad_edges,
+                                                        "pairs_from": "oracle counts over all 10M edges"},
+                               "graphs_32_one_query_each": {"graphs": len(graphs), "mismatches": bad32,
+                                                            "checked": "every edge, pair and certificate"},
+                               "bit_exact": bad_pairs + bad_edges + bad32 == 0,
+                               "seconds": time.perf_counter() - t0}
+        log(f"batched vs oracle: {bad_pairs} pair and {bad_edges} edge mismatches on the 10M graph "
+            f"(64 queries), {bad32} on the 32 graphs ({time.perf_counter() - t0:.1f}s)")
+    G.close()
+    for x in Gs:
+        x.close()
     return out
 
 
-def serving_section(folty, synth, full):
-    """Poisson arrivals of queries on resident graphs through the continuous-
-    batching server; per-request latency is submit to result on the host."""
+SERVE_REQUESTS = {10: 100, 30: 300, 100: 1000, 300: 2000, 1000: 2000}
+
+
+def serving_section(folty, synth, big, small, oracle_check, threads, rng):
+    """Poisson arrivals of queries on eight resident graphs (five of the tiny-graph
+    generator, 1e5..1e7 edges; two of the large-graph generator, 2e7 and 4e7
+    edges; and the 70M-edge graph itself) through the continuous-batching server;
+    per-request latency is submit to result on the host.  Every served result is
+    compared with the same query run alone, a sample of them with the oracle;
+    then all requests of one mix are submitted at once and the served rate is
+    compared with the same queries run one at a time; then the same under a
+    16 GiB budget."""
     import threading
+    import torch
+    from oracle.oracle import Oracle
     sizes = [100_000, 300_000, 1_000_000, 3_000_000, 10_000_000]
     gs = [synth.c1_family(m, seed=10 + i) for i, m in enumerate(sizes)]
-    if full:
-        gs += [synth.large_family(m, seed=20 + i) for i, m in enumerate((20_000_000, 40_000_000, 70_000_000))]
+    if not small:
+        gs += [synth.large_family(m, seed=20 + i) for i, m in enumerate((20_000_000, 40_000_000))]
     Gs = [folty.Graph(x.n, x.src, x.dst, x.t).build() for x in gs]
-    rng = np.random.default_rng(5)
+    if not small:
+        gs.append(big[0])
+        Gs.append(big[1])
+    for G in Gs:
+        G.stats()
     pool = sorted({int(round(np.exp(rng.uniform(np.log(60), np.log(604800))))) for _ in range(16)})
-    rates = (10, 30, 100, 300, 1000) if full else (100, 1000)
-    per_rate = 2000 if full else 400
+    rates = (100, 1000) if small else (10, 30, 100, 300, 1000)
     srv = folty.Server(workers=4, max_batch=16)
     out = {"graphs_edges": [x.m for x in gs], "delta_pool": pool, "rates": {}}
-    for rate in rates:
-        reqs = [(int(rng.integers(0, len(Gs))),
+    oracles, pools = {}, {}
+
+    def oracle_answer(gi, q):
+        # five tiny-generator graphs: every window of the pool in one oracle pass
+        x = gs[gi]
+        if gi not in oracles:
+            oracles[gi] = Oracle(x.n, x.src, x.dst, x.t, threads=threads)
+        key = (gi, q["variant"])
+        if key not in pools:
+            pools[key] = oracles[gi].counts_pool(pool, q["variant"])
+        col = pools[key][:, pool.index(q["delta"])]
+        return oracles[gi].query(q["delta"], q["theta"][0], q["theta"][1], q["variant"], counts=col)
+
+    def mix(k):
+        return [(int(rng.integers(0, len(Gs))),
                  dict(delta=int(rng.choice(pool)), theta=(int(rng.integers(1, 10)), 10),
-                      variant=int(rng.choice([0, 3])), counts=False)) for _ in range(per_rate)]
+                      variant=int(rng.choice([0, 3])), counts=False)) for _ in range(k)]
+
+    oracle_bad = oracle_checked = 0
+    for rate in rates:
+        per_rate = SERVE_REQUESTS[rate]
+        reqs = mix(per_rate)
         gaps = rng.exponential(1.0 / rate, size=per_rate)
         tickets = [None] * per_rate
 
@@ -202,43 +316,136 @@ def serving_section(folty, synth, full):
         wall = time.perf_counter() - t0
         lat = np.array([r.stats["latency_ms"] for r in res])
         bs = np.array([r.stats["batch_size"] for r in res])
-        # a sample of requests rerun alone must give the same answer
-        pick = rng.choice(per_rate, size=min(20, per_rate), replace=False)
-        same = all(res[i].pairs() == Gs[reqs[i][0]].query(**reqs[i][1]).pairs() for i in pick)
+        # every request rerun alone must give the same answer; a sample against the oracle
+        alone_bad = sum(1 for r, (gi, q) in zip(res, reqs) if r.pairs() != Gs[gi].query(**q).pairs())
+        if oracle_check:
+            small_idx = [i for i, (gi, q) in enumerate(reqs) if gi < len(sizes)]
+            for i in rng.choice(small_idx, size=min(40, len(small_idx)), replace=False):
+                gi, q = reqs[int(i)]
+                oracle_bad += check_against(res[int(i)], oracle_answer(gi, q))
+                oracle_checked += 1
         out["rates"][str(rate)] = {"requests": per_rate, "p50_ms": float(np.percentile(lat, 50)),
                                    "p99_ms": float(np.percentile(lat, 99)),
                                    "achieved_queries_per_s": per_rate / wall,
-                                   "mean_batch": float(bs.mean()), "same_as_alone": same}
+                                   "mean_batch": float(bs.mean()), "max_batch": int(bs.max()),
+                                   "mismatches_vs_alone": alone_bad}
         log(f"serving {rate} q/s: p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms, "
-            f"achieved {per_rate / wall:.0f} q/s, mean batch {bs.mean():.2f}, same as alone: {same}")
+            f"achieved {per_rate / wall:.0f} q/s, mean batch {bs.mean():.2f}, {alone_bad} differ from alone")
+    # saturated: all requests at once, against the same queries one at a time
+    reqs = mix(2000)
+    for gi, q in reqs[:50]:
+        Gs[gi].query(**q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = [Gs[gi].query(**q) for gi, q in reqs]
+    seq_s = time.perf_counter() - t0
+    info0 = srv.info()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(Gs[gi], **q) for gi, q in reqs]
+    res = [srv.wait(t) for t in tickets]
+    sat_s = time.perf_counter() - t0
+    info1 = srv.info()
+    bad = sum(1 for r, a in zip(res, alone) if r.pairs() != a.pairs() or r.n_certificates != a.n_certificates)
+    bs = np.array([r.stats["batch_size"] for r in res])
+    out["saturated"] = {"requests": len(reqs), "served_queries_per_s": len(reqs) / sat_s,
+                        "sequential_queries_per_s": len(reqs) / seq_s, "speedup": seq_s / sat_s,
+                        "mean_batch": float(bs.mean()),
+                        "passes_with_several_requests": info1["batches"] - info0["batches"],
+                        "peak_concurrent_passes": info1["peak_concurrent_passes"],
+                        "mismatches_vs_alone": bad}
+    log(f"serving saturated: {len(reqs)} requests at once served at {len(reqs) / sat_s:.0f} q/s, one at a "
+        f"time {len(reqs) / seq_s:.0f} q/s (x{seq_s / sat_s:.2f}); mean batch {bs.mean():.2f}, "
+        f"{info1['batches'] - info0['batches']} shared passes, up to {info1['peak_concurrent_passes']} passes at "
+        f"once, {bad} differ from alone")
     out["server"] = srv.info()
     srv.close()
-    if full:
-        # the same mix under a 16 GB device budget: requests wait for admission
+    out["oracle_check"] = {"requests_checked": oracle_checked, "mismatches": oracle_bad,
+                           "how": "sampled served requests on the five tiny-generator graphs: pairs, "
+                                  "certificate counts and |Sol| from the oracle's counts over all edges"}
+    if not small:
+        # the same mix under a 16 GiB device budget: requests wait for admission
         srv = folty.Server(workers=4, max_batch=16, hbm_budget_bytes=16 << 30)
         n_req = 500
-        reqs = [(int(rng.integers(0, len(Gs))),
-                 dict(delta=int(rng.choice(pool)), theta=(int(rng.integers(1, 10)), 10),
-                      variant=int(rng.choice([0, 3])), counts=False)) for _ in range(n_req)]
+        reqs = mix(n_req)
         t0 = time.perf_counter()
         tickets = [srv.submit(Gs[gi], **q) for gi, q in reqs]
         res = [srv.wait(t) for t in tickets]
         wall = time.perf_counter() - t0
         lat = np.array([r.stats["latency_ms"] for r in res])
         qwait = np.array([r.stats["queue_ms"] for r in res])
-        pick = rng.choice(n_req, size=20, replace=False)
-        same = all(res[i].pairs() == Gs[reqs[i][0]].query(**reqs[i][1]).pairs() for i in pick)
+        bad = sum(1 for r, (gi, q) in zip(res, reqs) if r.pairs() != Gs[gi].query(**q).pairs())
         info = srv.info()
         srv.close()
         out["budget_16GiB"] = {"requests": n_req, "submitted_at_once": True,
                                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                                "queue_p50_ms": float(np.percentile(qwait, 50)),
                                "queue_p99_ms": float(np.percentile(qwait, 99)),
-                               "achieved_queries_per_s": n_req / wall, "same_as_alone": same, "server": info}
+                               "achieved_queries_per_s": n_req / wall, "mismatches_vs_alone": bad, "server": info}
         log(f"serving under a 16 GiB budget: {n_req} requests at once, p50 {np.percentile(lat, 50):.2f} ms, "
             f"p99 {np.percentile(lat, 99):.2f} ms, queue p99 {np.percentile(qwait, 99):.2f} ms, "
-            f"{n_req / wall:.0f} q/s, peak in use {info['peak_in_use_bytes'] / 2**30:.1f} GiB, "
-            f"rejected {info['rejected']}, same as alone: {same}")
+            f"{n_req / wall:.0f} q/s, peak counted {info['peak_in_use_bytes'] / 2**30:.1f} GiB, "
+            f"rejected {info['rejected']}, {bad} differ from alone")
+    for o in oracles.values():
+        o.close()
+    for G in Gs[:len(Gs) - (0 if small else 1)]:
+        G.close()
+    return out
+
+
+def configs_section(folty, synth, threads):
+    """The small workload (n=2,000, m=20,000; delta 3600, theta 1/2) and the
+    medium one (n=1M, m=10M; the nine queries delta in {600, 3600, 86400} x theta
+    in {1/4, 1/2, 3/4}): every edge, pair and certificate against the oracle, and
+    the oracle's time for the query (median of three runs on all host cores; the
+    small workload also on one core)."""
+    from oracle.oracle import Oracle
+    out = {}
+    g = synth.tiny()
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    r = G.query(3600, (1, 2), 0)
+    o = Oracle(g.n, g.src, g.dst, g.t, threads=threads)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        w = o.query(3600, 1, 2, 0)
+        times.append(time.perf_counter() - t0)
+    o1 = Oracle(g.n, g.src, g.dst, g.t, threads=1)
+    t0 = time.perf_counter()
+    o1.query(3600, 1, 2, 0)
+    t1 = time.perf_counter() - t0
+    bad = check_against(r, w) + int((r.counts() != w["counts"]).sum())
+    out["small"] = {"n": g.n, "m": g.m, "n_pairs": int(w["pair_u"].size), "n_certificates": w["n_certificates"],
+                    "gpu_query_ms": r.stats["query_ms"], "oracle_s_median_of_3": float(np.median(times)),
+                    "oracle_s_one_core": t1, "mismatches": bad}
+    o.close()
+    o1.close()
+    G.close()
+    log(f"small workload: {bad} mismatches; oracle {np.median(times) * 1e3:.1f} ms ({threads} cores), "
+        f"{t1 * 1e3:.1f} ms (one core); GPU query {r.stats['query_ms']:.2f} ms")
+    g = synth.medium()
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build()
+    o = Oracle(g.n, g.src, g.dst, g.t, threads=threads)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        o.query(3600, 1, 2, 0)
+        times.append(time.perf_counter() - t0)
+    deltas = [600, 3600, 86400]
+    pool = o.counts_pool(deltas, 0)
+    bad = 0
+    qms = {}
+    for j, d in enumerate(deltas):
+        for th in ((1, 4), (1, 2), (3, 4)):
+            r = G.query(d, th, 0)
+            w = o.query(d, th[0], th[1], 0, counts=pool[:, j])
+            bad += check_against(r, w) + int((r.counts() != pool[:, j]).sum())
+            qms[f"{d}/{th[0]}/{th[1]}"] = r.stats["query_ms"]
+    out["medium"] = {"n": g.n, "m": g.m, "queries": 9, "gpu_query_ms": qms,
+                     "oracle_s_median_of_3": float(np.median(times)), "mismatches": bad,
+                     "oracle_one_core": "not timed (about the all-core time times the core count)"}
+    o.close()
+    G.close()
+    log(f"medium workload: {bad} mismatches over 9 queries; oracle {np.median(times):.2f} s ({threads} cores)")
     return out
 
 
@@ -394,19 +601,32 @@ def main():
     wedge_ms = med("wedge_ms", qstats)
     build_ms = med("build_ms", bstats)
 
-    # the dominant kernel of the query: wedge enumeration, closing probe and the
-    # per-triangle time-range filter.  Algorithmic bytes: 12 B per wedge check
-    # (a neighbour id and the closing-edge probe) and 48 B per static triangle
-    # (its three oriented-edge records' list bounds); the kernel's own duration
-    # comes from HIP events on the graph's stream around that launch alone.
+    # The dominant kernel of the query: wedge enumeration, closing probe and the
+    # per-triangle time-range filter; its duration comes from HIP events on the
+    # graph's stream around that launch alone.  Its HBM traffic per launch is the
+    # counter-measured one (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of
+    # known size); its algorithmic bytes are 12 B per wedge check (a neighbour id
+    # and the closing-edge probe) and 48 B per static triangle (three
+    # oriented-edge records' list bounds).  The counters show it limited by
+    # vector-instruction issue, not by HBM.
     roof_bytes = 12 * W + 48 * T
-    achieved = roof_bytes / (wedge_ms * 1e-3) / 1e9 if wedge_ms > 0 else 0.0
-    traffic, traffic_note = measured_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": ROOF_KERNEL, "kernel_ms": round(wedge_ms, 4),
-                "algorithmic_bytes": int(roof_bytes), "traffic_note": traffic_note,
-                "traffic_gbs": round(traffic / (wedge_ms * 1e-3) / 1e9, 2) if traffic and wedge_ms > 0 else None}
+    alg_gbs = roof_bytes / (wedge_ms * 1e-3) / 1e9 if wedge_ms > 0 else 0.0
+    cs, cs_note = counter_summary()
+    roofline = {"kernel": ROOF_KERNEL, "kernel_ms": round(wedge_ms, 4), "counters": cs_note,
+                "algorithmic_bytes": int(roof_bytes), "algorithmic_gbs": round(alg_gbs, 2),
+                "algorithmic_frac": round(alg_gbs / HBM_PEAK_GBS, 5)}
+    if cs is not None and wedge_ms > 0:
+        gbs = cs["traffic"] / (wedge_ms * 1e-3) / 1e9
+        roofline.update({"bound": "alu", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": cs["traffic"],
+                         "frac_basis": "HBM bytes from FETCH_SIZE + WRITE_SIZE per launch (calibrated)"})
+        if cs.get("valu_insts"):
+            roofline["valu_issue_frac"] = round(cs["valu_insts"] / (wedge_ms * 1e-3) / VALU_PEAK_WAVE_INSTS, 4)
+    else:
+        # no counters for these sources: the algorithmic figure, labelled as such
+        roofline.update({"bound": "hbm", "achieved": round(alg_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(alg_gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                         "frac_basis": "algorithmic bytes (no counter summary for the current sources)"})
 
     out = {
         "metric": METRIC,
@@ -428,6 +648,7 @@ def main():
         "wedges": W, "triangles": T, "temporal_tests": S, "n_pairs": P,
         "n_certificates": qs["n_certificates"], "max_core": qs["max_core"],
         "max_out_degree": qs["max_out_degree"], "peel_rounds": qs["peel_rounds"],
+        "core_sweeps": qs["core_sweeps"],
         "static_edges": qs["static_edges"], "directed_pairs": qs["directed_pairs"],
         "closing_probes": qs["closing_probes"], "enum_items": qs["enum_items"],
         "query_only_wedge_checks_per_s": W / (query_ms * 1e-3) if query_ms > 0 else None,
@@ -435,24 +656,53 @@ def main():
         "roofline": roofline,
     }
 
+    from oracle.oracle import Oracle
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(123)
+    G = folty.Graph(n, src, dst, tt).build()  # resident: checks, extra sections, serving
     oracle = None
-    if not (a.no_parity and a.no_cpu_baseline):
-        from oracle.oracle import Oracle
-        threads = len(os.sched_getaffinity(0))
+    ok = True
+    if not a.no_parity and not a.no_cpu_baseline:
+        # The timed query in full against the oracle run over every edge; that
+        # run's wall time (index, per-edge counts, threshold and pairs) is the
+        # CPU baseline of the whole job, measured, on all host cores.
+        rq = G.query(a.delta, theta, 0)
+        got = rq.counts()
         t1 = time.perf_counter()
         oracle = Oracle(n, g.src, g.dst, g.t, threads=threads)
-        oracle_build_s = time.perf_counter() - t1
-        log(f"oracle index built in {oracle_build_s:.1f}s on {threads} threads")
+        t2 = time.perf_counter()
+        cnt = oracle.counts(a.delta, 0)
+        t3 = time.perf_counter()
+        want = oracle.query(a.delta, theta[0], theta[1], 0, counts=cnt)
+        t4 = time.perf_counter()
+        full_s = t4 - t1
+        bad_edges = int((got != cnt).sum())
+        bad_pairs = check_against(rq, want)
+        ok = ok and bad_edges == 0 and bad_pairs == 0
+        out["parity_full"] = {"bit_exact": bad_edges == 0 and bad_pairs == 0, "edges": int(got.size),
+                              "edge_mismatches": bad_edges, "pair_list_equal": bad_pairs == 0,
+                              "n_pairs": int(want["pair_u"].size), "n_certificates": int(want["n_certificates"]),
+                              "nonzero_counts": int(((cnt > 0) & (cnt != 0xFFFFFFFF)).sum()),
+                              "delta": a.delta, "theta": "1/2", "predicate": 0}
+        out["cpu_baseline"] = {
+            "value": W / full_s, "unit": "wedge-checks/s", "cores": threads, "kind": "oracle",
+            "sample": f"none: the whole timed job on the CPU, measured once: oracle index over all {m} edges "
+                      f"({t2 - t1:.1f}s), per-edge counts of all {m} edges ({t3 - t2:.1f}s), threshold and "
+                      f"pairs ({t4 - t3:.1f}s); W from the GPU orientation",
+            "full_job_s": full_s, "cpu_model": cpu_model()}
+        log(f"full parity delta={a.delta}: {bad_edges} edge mismatches over {got.size} edges, pair list "
+            f"{'equal' if bad_pairs == 0 else 'DIFFERENT'} ({want['pair_u'].size} pairs, "
+            f"{want['n_certificates']} certificates); oracle {full_s:.1f}s on {threads} cores")
+    elif not a.no_parity:
+        oracle = Oracle(n, g.src, g.dst, g.t, threads=threads)
     if not a.no_parity:
-        # per delta: a uniform sample of edges, plus every edge the GPU counts as
-        # non-zero (so a wrongly non-zero count cannot hide among the zeros)
-        rng = np.random.default_rng(123)
+        # other windows and predicates on the same index: a uniform sample of
+        # edges, plus every edge the GPU counts as non-zero (so a wrongly
+        # non-zero count cannot hide among the zeros)
         sample = np.sort(rng.choice(m, size=min(a.parity_sample, m), replace=False))
-        G = folty.Graph(n, src, dst, tt).build()
-        ok = True
         checked = {}
         by_delta = {}
-        for d, variant in ((a.delta, 0), (86_400, 0), (synth.YEAR_S, 0), (synth.YEAR_S, 3), (synth.YEAR_S, 6)):
+        for d, variant in ((86_400, 0), (synth.YEAR_S, 0), (synth.YEAR_S, 3), (synth.YEAR_S, 6)):
             rq = G.query(d, theta, variant)
             key = str(d) if variant == 0 else f"{d}/predicate{variant}"
             by_delta[key] = {k: rq.stats[k] for k in ("query_ms", "wedge_ms", "temporal_ms", "threshold_ms",
@@ -469,58 +719,54 @@ def main():
                             "oracle_nonzero": int((want > 0).sum()), "mismatches": bad}
             log(f"parity delta={d} predicate {variant}: {bad} mismatches over {idx.size} edges ({sample.size} "
                 f"uniform + {nz.size} the GPU counts as non-zero; oracle non-zero: {int((want > 0).sum())})")
-        # vertex queries (exists-forall-forall, exists-forall-exists) on the same
-        # index, one-year window; checked against the oracle on sampled vertices
-        # (each decided from the counts of its own outgoing edges)
-        vq = {}
-        outdeg = np.bincount(g.src[g.src != g.dst], minlength=n)
-        small = np.nonzero((outdeg >= 1) & (outdeg <= 2000))[0]
-        for name, inner in (("exists_forall_forall", folty.INNER_FORALL), ("exists_forall_exists", folty.INNER_EXISTS)):
-            rv = G.vertex_query(synth.YEAR_S, (1, 10), inner, (1, 10), 0, counts=False)
-            verts, good = rv.vertices()
-            pick = np.union1d(rng.choice(small, size=min(200, small.size), replace=False),
-                              rng.choice(np.intersect1d(verts, small), size=min(200, np.intersect1d(verts, small).size),
-                                         replace=False) if verts.size else np.zeros(0, np.int64))
-            w = oracle.vertex_query_at(pick, synth.YEAR_S, 1, 10, 0, inner == folty.INNER_FORALL, 1, 10)
-            gpu_sol = np.isin(w["vertices"], verts)
-            gmap = dict(zip(verts.tolist(), good.tolist()))
-            bad = int((gpu_sol != w["solution"]).sum()) + sum(
-                1 for u, s_, gd in zip(w["vertices"].tolist(), w["solution"].tolist(), w["good"].tolist())
-                if s_ and gmap.get(u) != gd)
-            ok = ok and bad == 0
-            vq[name] = {"delta": synth.YEAR_S, "theta": "1/10", "inner_theta": "1/10" if inner == folty.INNER_FORALL else None,
-                        "solution_vertices": int(verts.size), "query_ms": rv.stats["query_ms"],
-                        "threshold_ms": rv.stats["threshold_ms"], "checked_vertices": int(pick.size),
-                        "oracle_edges_counted": w["edges_counted"], "mismatches": bad}
-            log(f"{name}: {verts.size} solution vertices in {rv.stats['query_ms']:.2f} ms; "
-                f"{bad} mismatches over {pick.size} sampled vertices ({w['edges_counted']} edges counted by the oracle)")
-        out["vertex_queries"] = vq
-        out["triads"] = triads_section(folty, G, oracle, g, n, rng, (a.delta, 86_400, synth.YEAR_S))
-        out["smaller_side"] = smaller_side_section(folty, synth, G, oracle, g, rng, a.parity_sample)
-        ok = ok and all(v["mismatches"] == 0 for v in out["smaller_side"].values())
-        ok = ok and all(v["mismatches"] == 0 for v in out["triads"].values())
-        G.close()
         out["parity_sampled"] = {"bit_exact": ok, "deltas": checked}
-        # the same index queried at wider windows (device times; per-edge counts kept)
         out["query_by_delta"] = by_delta
-    if not a.no_cpu_baseline:
-        rng = np.random.default_rng(7)
-        k = min(a.cpu_sample, m)
-        idx = np.sort(rng.choice(m, size=k, replace=False))
-        t1 = time.perf_counter()
-        oracle.counts(a.delta, 0, idx)
-        sample_s = time.perf_counter() - t1
-        est_full_s = oracle_build_s + sample_s * m / k
-        out["cpu_baseline"] = {
-            "value": W / est_full_s, "unit": "wedge-checks/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle index over all {m} edges ({oracle_build_s:.1f}s) + per-edge counts for "
-                      f"{k} uniformly sampled edges ({sample_s:.1f}s), extrapolated linearly in "
-                      f"edges to the whole job ({est_full_s:.1f}s); W from the GPU orientation",
-            "est_full_job_s": est_full_s}
+        if not a.no_extras:
+            # vertex queries (exists-forall-forall, exists-forall-exists) on the same
+            # index, one-year window; checked against the oracle on sampled vertices
+            # (each decided from the counts of its own outgoing edges)
+            vq = {}
+            outdeg = np.bincount(g.src[g.src != g.dst], minlength=n)
+            small = np.nonzero((outdeg >= 1) & (outdeg <= 2000))[0]
+            for name, inner in (("exists_forall_forall", folty.INNER_FORALL),
+                                ("exists_forall_exists", folty.INNER_EXISTS)):
+                rv = G.vertex_query(synth.YEAR_S, (1, 10), inner, (1, 10), 0, counts=False)
+                verts, good = rv.vertices()
+                sol_small = np.intersect1d(verts, small)
+                pick = np.union1d(rng.choice(small, size=min(200, small.size), replace=False),
+                                  rng.choice(sol_small, size=min(200, sol_small.size), replace=False)
+                                  if verts.size else np.zeros(0, np.int64))
+                w = oracle.vertex_query_at(pick, synth.YEAR_S, 1, 10, 0, inner == folty.INNER_FORALL, 1, 10)
+                gpu_sol = np.isin(w["vertices"], verts)
+                gmap = dict(zip(verts.tolist(), good.tolist()))
+                bad = int((gpu_sol != w["solution"]).sum()) + sum(
+                    1 for u, s_, gd in zip(w["vertices"].tolist(), w["solution"].tolist(), w["good"].tolist())
+                    if s_ and gmap.get(u) != gd)
+                ok = ok and bad == 0
+                vq[name] = {"delta": synth.YEAR_S, "theta": "1/10",
+                            "inner_theta": "1/10" if inner == folty.INNER_FORALL else None,
+                            "solution_vertices": int(verts.size), "query_ms": rv.stats["query_ms"],
+                            "threshold_ms": rv.stats["threshold_ms"], "checked_vertices": int(pick.size),
+                            "oracle_edges_counted": w["edges_counted"], "mismatches": bad}
+                log(f"{name}: {verts.size} solution vertices in {rv.stats['query_ms']:.2f} ms; "
+                    f"{bad} mismatches over {pick.size} sampled vertices ({w['edges_counted']} edges counted "
+                    f"by the oracle)")
+            out["vertex_queries"] = vq
+            out["triads"] = triads_section(folty, G, oracle, g, n, rng, (a.delta, 86_400, synth.YEAR_S))
+            out["smaller_side"] = smaller_side_section(folty, synth, G, oracle, g, rng, a.parity_sample)
+            ok = ok and all(v["mismatches"] == 0 for v in out["smaller_side"].values())
+            ok = ok and all(v["mismatches"] == 0 for v in out["triads"].values())
+        out["parity_sampled"]["bit_exact"] = ok
+        if not a.no_configs:
+            out["configs"] = configs_section(folty, synth, threads)
+    if oracle is not None:
+        oracle.close()
+        oracle = None
     if not a.no_batch:
-        out["batched"] = batched_section(folty, synth, max(3, a.steps))
+        out["batched"] = batched_section(folty, synth, max(3, a.steps), not a.no_parity, threads, rng)
     if not a.no_serve:
-        out["serving"] = serving_section(folty, synth, a.serve_full)
+        out["serving"] = serving_section(folty, synth, (g, G), a.serve_small, not a.no_parity, threads, rng)
+    G.close()
     print(json.dumps(out))
 
 

@@ -355,8 +355,11 @@ void folty_plan_free(folty_plan *p);
  * requests on the same graph (up to max_batch) and run them as one pass, so
  * requests that arrive while others run join the next pass.  A request is
  * started only when its device memory (estimated from its graph's index sizes)
- * fits in the budget beside the requests in flight; requests whose estimate
- * exceeds the whole budget are rejected at submit with FOLTY_ENOMEM.
+ * fits in the budget beside the requests in flight and the workspace buffers
+ * the workers keep (a worker gives its buffers back when the oldest request
+ * does not fit; the library's cache of freed blocks is handed back to the
+ * driver when it would push the device past the budget); requests whose
+ * estimate exceeds the whole budget are rejected at submit with FOLTY_ENOMEM.
  *   workers           concurrent passes (streams); 0 = 4
  *   max_batch         requests per pass; 0 = 16
  *   hbm_budget_bytes  0 = the FOLTY_HBM_BUDGET environment variable (bytes) if
@@ -376,7 +379,13 @@ typedef struct {
     int64_t submitted, completed, rejected, queued;
     int64_t batches;          /* passes that served more than one request */
     int64_t batched_requests; /* requests served in such passes */
-    int64_t budget_bytes, in_use_bytes, peak_in_use_bytes;
+    int64_t budget_bytes;
+    int64_t in_use_bytes;     /* counted against the budget: estimates of the requests in
+                                 flight plus the workspace buffers workers keep */
+    int64_t peak_in_use_bytes;
+    int64_t kept_bytes;       /* of in_use_bytes: workspace buffers kept between passes */
+    int64_t peak_concurrent_passes; /* most passes running on the device at once */
+    int64_t trimmed_bytes;    /* cached device blocks handed back to stay within the budget */
 } folty_server_info;
 
 int folty_server_create(const folty_server_opts *opts, folty_server **out);

@@ -135,6 +135,24 @@ size_t dev_trim() {
     return n;
 }
 
+size_t dev_trim_to(size_t keep) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    Pool &P = pool_for(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    size_t n = 0;
+    while (P.cached > keep && !P.free_blocks.empty()) {
+        auto it = std::prev(P.free_blocks.end());
+        Block b = it->second;
+        P.free_blocks.erase(it);
+        P.cached -= b.bytes;
+        n += b.bytes;
+        if (b.ev) (void)hipEventSynchronize(b.ev); // the last stream that used it is done with it
+        drop_block(b);
+    }
+    return n;
+}
+
 // ---------------------------------------------------------------------------
 // Pinned host blocks for large result arrays.  Results are filled by device
 // copies: into pinned memory they run as a DMA at full speed, and a block taken

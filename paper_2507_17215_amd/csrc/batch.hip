@@ -491,6 +491,31 @@ static void tune(Plan &P) {
     g_tune[bucket] = {bi, bb};
 }
 
+// Device bytes plan_create and plan_run take for these queries on one graph
+// (the buffers of each job, one per predicate code: window histogram, touched
+// mask, survivor slots; the certificate records of every query, their sorted
+// copies and the sort's scratch; per-edge counts handed back), so that a
+// server can admit a batch by what its plan will hold.
+int64_t plan_footprint(const Graph *g, const folty_query *qs, int nq) {
+    const Index &ix = g->ix;
+    std::map<int, std::vector<int64_t>> lv; // predicate code -> windows
+    int64_t b = 0;
+    for (int q = 0; q < nq; q++) {
+        lv[qs[q].variant].push_back(qs[q].delta);
+        b += 24 * (2 * (int64_t)ix.S + (int64_t)ix.m / 64 + 2); // records, sorted copies, sort scratch
+        if (!(qs[q].flags & FOLTY_QUERY_NO_COUNTS)) b += 4 * ix.m_input;
+    }
+    const int64_t T = std::max<int64_t>(0, ix.T.load());
+    for (auto &kv : lv) {
+        auto &d = kv.second;
+        std::sort(d.begin(), d.end());
+        d.erase(std::unique(d.begin(), d.end()), d.end());
+        b += 4 * hist_words(ix.m, padded_levels(d.size())) + 8 * ((int64_t)ix.m / 64 + 1) + 8 * (int64_t)d.size();
+        b += 20 * T + 4 * (int64_t)ix.NI + 16 * ((int64_t)ix.NI + 1);
+    }
+    return b + (1 << 20);
+}
+
 Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t *qgraph, int nq, bool oneshot) {
     if (ng <= 0 || nq < 0) fail(FOLTY_EINVAL, "a plan needs at least one graph");
     for (int i = 0; i < ng; i++)

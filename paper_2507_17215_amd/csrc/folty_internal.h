@@ -55,6 +55,7 @@ struct StreamScope {
 void *dev_alloc(size_t bytes, size_t *got);
 void dev_free(void *p, size_t bytes);
 size_t dev_trim();   // give every cached block back to the driver; returns bytes
+size_t dev_trim_to(size_t keep); // give back cached blocks, largest first, until at most keep bytes stay
 size_t dev_cached(); // bytes held in the cache
 // pinned host blocks for large result arrays (alloc.hip); host_alloc returns
 // nullptr when pinned memory is not available, host_free false for a pointer
@@ -166,7 +167,9 @@ struct Index {
     int64_t P = 0;           // non-empty directed lists
     int64_t sigma_max = 0;
     std::atomic<int64_t> T{-1}; // static triangles (-1 until a query or ensure_tri_base counted them)
-    bool tri_base_ready = false; // tri_base holds per-item triangle offsets
+    // tri_base holds per-item triangle offsets; stored (release) after tri_base, T and
+    // one_pass_from are final, so a reader that loads it (acquire) sees them
+    std::atomic<bool> tri_base_ready{false};
     int64_t one_pass_from = 0;   // with tri_base: single queries of delta >= this filter in one pass
     int64_t W = 0;           // oriented wedges: sum of C(|N+(x)|, 2)
     int64_t probes = 0;      // closing probes the enumeration makes: sum over (u,v) of |N+(v)|
@@ -219,6 +222,7 @@ struct Workspace {
     DevBuf sbase;   // int64[NI+1] first survivor slot of each item
     const int64_t *slots = nullptr; // survivor slots of the last filter: sbase or the index's tri_base
     bool emit_timed = false;        // the last filter's second pass is bracketed by ev[6], ev[7]
+    int32_t emit_items = 0;         // items the last filter's second pass enumerated again
     int32_t filter_passes = 0;      // enumeration passes of the last filter
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
@@ -237,6 +241,7 @@ struct Workspace {
     bool events = false;
     ~Workspace();
     void ensure_events();
+    size_t device_bytes() const; // device memory its buffers hold
 };
 
 struct Graph {
@@ -322,6 +327,8 @@ struct Plan;
 Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t *qgraph, int nq,
                   bool oneshot = false);
 void plan_run(Plan *p, Result **outs);
+int64_t plan_footprint(const Graph *g, const folty_query *qs, int nq); // device bytes of such a plan
+int64_t query_footprint(const Graph *g, const folty_query &q);         // of one single query
 void plan_free(Plan *p);
 void plan_info(const Plan *p, folty_plan_info *info);
 

@@ -333,6 +333,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
                          hipEvent_t e1, int64_t *tri, int64_t *tests) {
     *tests = -1; // known on the host only after the two-pass filter
     ws.emit_timed = false;
+    ws.emit_items = 0;
     ws.filter_passes = 1;
     const int32_t NI = ix.NI;
     ws.su.ensure(4 * ((size_t)NI + 1));
@@ -372,7 +373,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
     using CountM = std::integral_constant<int, FILTER_COUNT>;
     using EmitM = std::integral_constant<int, FILTER_EMIT>;
     using BothM = std::integral_constant<int, FILTER_BOTH>;
-    if (ix.tri_base_ready && dmax >= ix.one_pass_from) {
+    if (ix.tri_base_ready.load(std::memory_order_acquire) && dmax >= ix.one_pass_from) {
         // per-item triangle offsets exist: one pass writes survivors into them
         ws.sv.ensure(12 * (size_t)ix.T + 12);
         ws.sw.ensure(8 * (size_t)ix.T + 8);
@@ -436,6 +437,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
         dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.ilist.as<int32_t>(), nl); });
         FOLTY_HIP(hipEventRecord(ws.ev[7], s));
         ws.emit_timed = true;
+        ws.emit_items = nl;
         ws.filter_passes = 2;
     }
     return survivors;
@@ -544,8 +546,15 @@ void finish_vertex(const Graph *g, const folty_vertex_query &vq, Workspace &ws, 
 }
 
 // any: qualify edges with count >= 1 (the inner exists of a vertex query)
-void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, Workspace &ws, Result *res,
-                  hipStream_t s, bool any = false) {
+// Threshold step: certificates, per-pair certificate counts and the compacted
+// pair keys (unsorted, in ws).  Returns |Sol| and the number of pairs.
+struct PairCounts {
+    int64_t ncerts;
+    int32_t npairs;
+};
+
+PairCounts threshold_pairs(const Graph *g, const folty_query &q, const uint32_t *count, Workspace &ws,
+                           hipStream_t s, bool any) {
     const Index &ix = g->ix;
     const int32_t S = ix.S, m = ix.m;
     ws.ncert.ensure(8 * (size_t)S + 8);
@@ -594,43 +603,65 @@ void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, W
     int32_t npairs;
     memcpy(&ncerts, ws.host.p, 8);
     memcpy(&npairs, ws.host.as<char>() + 16, 4);
-    res->n_certificates = (int64_t)ncerts;
+    return PairCounts{(int64_t)ncerts, npairs};
+}
+
+// sort the pair keys of threshold_pairs and unpack them: u, v and the
+// certificate counts, sorted by (u, v), in ws
+void sort_pairs(const Graph *g, Workspace &ws, int32_t npairs, hipStream_t s, int32_t **du, int32_t **dv,
+                uint32_t **dn) {
+    const Index &ix = g->ix;
+    ws.pairs_k2.ensure(8 * (size_t)npairs);
+    ws.pairs_v2.ensure(4 * (size_t)npairs);
+    const int nb = pair_bits(ix.n);
+    size_t need = sort_pairs_u64_u32(nullptr, 0, ws.pairs_k.as<uint64_t>(), ws.pairs_k2.as<uint64_t>(),
+                                     ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, 2 * nb, s);
+    ws.cub.ensure(need);
+    sort_pairs_u64_u32(ws.cub.p, need, ws.pairs_k.as<uint64_t>(), ws.pairs_k2.as<uint64_t>(),
+                       ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, 2 * nb, s);
+    // the unsorted keys are no longer needed: u and v go where they were
+    *du = reinterpret_cast<int32_t *>(ws.pairs_k.p);
+    *dv = *du + npairs;
+    *dn = ws.pairs_v2.as<uint32_t>();
+    k_pairs_unpack<<<grid_for(npairs, BLK), BLK, 0, s>>>(ws.pairs_k2.as<uint64_t>(), npairs, nb, *du, *dv);
+    FOLTY_LAUNCHED();
+}
+
+void finish_query(const Graph *g, const folty_query &q, const uint32_t *count, Workspace &ws, Result *res,
+                  hipStream_t s, bool any = false) {
+    const PairCounts pc = threshold_pairs(g, q, count, ws, s, any);
+    const int32_t npairs = pc.npairs;
+    res->n_certificates = pc.ncerts;
     res->u.resize(npairs);
     res->v.resize(npairs);
     res->n_cert.resize(npairs);
     if (npairs > 0) {
-        ws.pairs_k2.ensure(8 * (size_t)npairs);
-        ws.pairs_v2.ensure(4 * (size_t)npairs);
-        const int nb = pair_bits(ix.n);
-        size_t need = sort_pairs_u64_u32(nullptr, 0, ws.pairs_k.as<uint64_t>(), ws.pairs_k2.as<uint64_t>(),
-                                         ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, 2 * nb, s);
-        ws.cub.ensure(need);
-        sort_pairs_u64_u32(ws.cub.p, need, ws.pairs_k.as<uint64_t>(), ws.pairs_k2.as<uint64_t>(),
-                           ws.pairs_v.as<uint32_t>(), ws.pairs_v2.as<uint32_t>(), npairs, 2 * nb, s);
-        // the unsorted keys are no longer needed: u and v go where they were
-        int32_t *du = reinterpret_cast<int32_t *>(ws.pairs_k.p), *dv = du + npairs;
-        k_pairs_unpack<<<grid_for(npairs, BLK), BLK, 0, s>>>(ws.pairs_k2.as<uint64_t>(), npairs, nb, du, dv);
-        FOLTY_LAUNCHED();
+        int32_t *du, *dv;
+        uint32_t *dn;
+        sort_pairs(g, ws, npairs, s, &du, &dv, &dn);
         FOLTY_HIP(hipMemcpyAsync(res->u.data(), du, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipMemcpyAsync(res->v.data(), dv, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
-        FOLTY_HIP(hipMemcpyAsync(res->n_cert.data(), ws.pairs_v2.p, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
+        FOLTY_HIP(hipMemcpyAsync(res->n_cert.data(), dn, 4 * (size_t)npairs, hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipStreamSynchronize(s));
     }
 }
 
-void keep_counts(const Graph *g, const uint32_t *count, Result *res, hipStream_t s) {
+// per-edge counts in input order (0xFFFFFFFF for self-loops) into out
+void scatter_counts(const Graph *g, const uint32_t *count, uint32_t *out, hipStream_t s) {
     const Index &ix = g->ix;
-    res->counts_dev.ensure(4 * (size_t)ix.m_input + 4);
     if (ix.m_input > 0) {
-        k_fill<uint32_t><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(res->counts_dev.as<uint32_t>(),
-                                                                            0xffffffffu, ix.m_input);
+        k_fill<uint32_t><<<grid_for(ix.m_input, BLK), BLK, 0, s>>>(out, 0xffffffffu, ix.m_input);
         FOLTY_LAUNCHED();
     }
     if (ix.m > 0) {
-        k_counts_scatter<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m,
-                                                                       res->counts_dev.as<uint32_t>());
+        k_counts_scatter<<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, ix.perm.as<int32_t>(), ix.m, out);
         FOLTY_LAUNCHED();
     }
+}
+
+void keep_counts(const Graph *g, const uint32_t *count, Result *res, hipStream_t s) {
+    res->counts_dev.ensure(4 * (size_t)g->ix.m_input + 4);
+    scatter_counts(g, count, res->counts_dev.as<uint32_t>(), s);
     res->has_counts = true;
     res->device = g->device;
 }
@@ -713,7 +744,7 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     // triangle slots per item are made on first use (plans, the server's memory
     // estimate, the cached list): a single query counts its survivors itself
     ix.T = -1;
-    ix.tri_base_ready = false;
+    ix.tri_base_ready.store(false, std::memory_order_release);
     ix.tri_cached = false;
     ix.tri.release();
     if (cache) {
@@ -732,7 +763,7 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
 // triangles of each enumeration item, their exclusive offsets (the slots of a
 // one-pass filter and of the cached list) and the triangle count
 void ensure_tri_base(Index &ix, hipStream_t s) {
-    if (ix.tri_base_ready) return;
+    if (ix.tri_base_ready.load(std::memory_order_acquire)) return;
     const int32_t ni = ix.NI;
     ix.tri_base.ensure(8 * ((size_t)ni + 1));
     DevBuf tri_it, cub;
@@ -753,25 +784,26 @@ void ensure_tri_base(Index &ix, hipStream_t s) {
     FOLTY_HIP(hipMemcpyAsync(&T, ix.tri_base.as<int64_t>() + ni, 8, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
     ix.T = T;
-    ix.tri_base_ready = true;
+    ix.tri_base_ready.store(true, std::memory_order_release);
 }
 
 // The two-pass filter enumerates the items with survivors a second time; at a
 // wide window that costs about as much as the first pass (70M edges, one year:
-// 7.1 ms on top of the 6.9 ms counting pass).  When the second pass took at
-// least half as long as the first, per-item triangle offsets (one counting
+// 7.1 ms on top of the 6.9 ms counting pass).  When at least half of the items
+// had survivors (items hold about the same number of probes, so the second pass
+// then costs at least half the first), per-item triangle offsets (one counting
 // enumeration, once per graph) let later queries write survivors into per-item
 // slots in a single pass, at 20 bytes of workspace per static triangle; that is
-// done when it fits in a quarter of the free device memory.  Windows well below
-// the one that showed the cost (under an eighth of it) keep the two passes: their
-// second pass is short, and the one pass writes into slots sized for every
-// triangle (70M edges: 5.4-5.6 ms for one pass against 5.0-5.2 ms for the
-// counting pass at 1 hour and 1 day).
+// done when it fits in a quarter of the free device memory.  The rule depends
+// only on the graph and the query, so a graph's code path does not depend on
+// timing.  Windows well below the one that met it (under an eighth of it) keep
+// the two passes: their second pass is short, and the one pass writes into slots
+// sized for every triangle (70M edges: 5.4-5.6 ms for one pass against 5.0-5.2 ms
+// for the counting pass at 1 hour and 1 day).
 void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta) {
     Index &ix = g->ix;
-    if (ix.tri_base_ready || !ws.emit_timed || ix.T <= 0) return;
-    // the second pass cost at least half the first (events of the finished query)
-    if (2 * ev_ms(ws.ev[6], ws.ev[7]) < ev_ms(ws.ev[4], ws.ev[5])) return;
+    if (ix.tri_base_ready.load(std::memory_order_acquire) || !ws.emit_timed || ix.T <= 0) return;
+    if (2 * (int64_t)ws.emit_items < (int64_t)ix.NI) return;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
         (void)hipGetLastError();
@@ -780,14 +812,14 @@ void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta) {
     if ((size_t)ix.T * 20 > fr / 4) return;
     {
         std::lock_guard<std::mutex> lk(g->lazy_mu);
-        if (!ix.tri_base_ready) ix.one_pass_from = delta / 8;
+        if (!ix.tri_base_ready.load(std::memory_order_acquire)) ix.one_pass_from = delta / 8;
     }
     ensure_triangles(g);
 }
 
 void ensure_triangles(Graph *g) {
     std::lock_guard<std::mutex> lk(g->lazy_mu);
-    if (g->ix.tri_base_ready || !g->ix.built) return;
+    if (g->ix.tri_base_ready.load(std::memory_order_acquire) || !g->ix.built) return;
     FOLTY_HIP(hipSetDevice(g->device));
     StreamScope sc(g->stream);
     ensure_tri_base(g->ix, g->stream);
@@ -846,16 +878,14 @@ Result *run_vertex_query(Graph *g, const folty_vertex_query &vq, Workspace &ws) 
     return run_query_impl(g, q, ws, g->stream, &vq);
 }
 
-static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s,
-                              const folty_vertex_query *vq) {
-    if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
+// The counts of a query (paper, Algorithm ExistExistForAll, the out- and
+// in-count arrays summed): filter, temporal tests, per-edge counts in sorted
+// edge order in ws.count.  Events: ev[0] start, ev[4]/ev[5] around the counting
+// filter pass, ev[2] after the tests.  *tests receives the number of temporal
+// tests by a copy on the stream: read it after the stream is synchronised.
+static const uint32_t *query_counts(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s,
+                                    int64_t *tests) {
     Index &ix = g->ix;
-    if (q.universe == FOLTY_UNIVERSE_COMMON) {
-        std::lock_guard<std::mutex> lk(g->lazy_mu);
-        ensure_tcnt(ix, s);
-        FOLTY_HIP(hipStreamSynchronize(s));
-    }
-    std::unique_ptr<Result> res(new Result());
     ws.ensure_events();
     FOLTY_HIP(hipEventRecord(ws.ev[0], s));
     ws.count.ensure(4 * (size_t)ix.m + 4);
@@ -864,7 +894,8 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
         k_fill<uint32_t><<<grid_for(ix.m, BLK), BLK, 0, s>>>(count, 0u, ix.m);
         FOLTY_LAUNCHED();
     }
-    int64_t tests = 0, tri = 0;
+    int64_t tri = 0;
+    *tests = 0;
     ws.filter_passes = 0;
     if (ix.NI > 0) {
         int64_t known = -1;
@@ -888,7 +919,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
                 DirectOp op{q.delta, count};
                 launch_temporal(ix, q.variant, q.delta, ws, op, known, survivors, s);
             }
-            FOLTY_HIP(hipMemcpyAsync(&tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
+            FOLTY_HIP(hipMemcpyAsync(tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));
         }
     } else {
         FOLTY_HIP(hipEventRecord(ws.ev[4], s));
@@ -896,6 +927,21 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     }
     if (ix.T < 0) ix.T = tri; // every query enumerates every triangle once
     FOLTY_HIP(hipEventRecord(ws.ev[2], s));
+    return count;
+}
+
+static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s,
+                              const folty_vertex_query *vq) {
+    if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
+    Index &ix = g->ix;
+    if (q.universe == FOLTY_UNIVERSE_COMMON) {
+        std::lock_guard<std::mutex> lk(g->lazy_mu);
+        ensure_tcnt(ix, s);
+        FOLTY_HIP(hipStreamSynchronize(s));
+    }
+    std::unique_ptr<Result> res(new Result());
+    int64_t tests = 0;
+    const uint32_t *count = query_counts(g, q, ws, s, &tests);
     finish_query(g, q, count, ws, res.get(), s, vq && vq->inner == FOLTY_INNER_EXISTS);
     if (vq) finish_vertex(g, *vq, ws, res.get(), s);
     FOLTY_HIP(hipEventRecord(ws.ev[3], s));
@@ -912,6 +958,20 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     res->stats.filter_passes = ws.filter_passes;
     maybe_one_pass(g, ws, q.delta);
     return res.release();
+}
+
+// Device bytes one single query takes beyond the resident index: per-edge
+// counts, per-item survivor counts and offsets, survivor slots (at most one per
+// triangle), the smaller-side difference array, per-pair certificate counts,
+// pair keys and their sorted copies, sort and scan scratch, and the per-edge
+// counts handed back.
+int64_t query_footprint(const Graph *g, const folty_query &q) {
+    const Index &ix = g->ix;
+    const int64_t T = std::max<int64_t>(0, ix.T.load());
+    int64_t b = 4 * (int64_t)ix.m + 32 * ((int64_t)ix.NI + 1) + 20 * T + 56 * (int64_t)ix.S;
+    if (q.flags & FOLTY_QUERY_SMALLER_SIDE) b += 8 * (int64_t)ix.m + 4;
+    if (!(q.flags & FOLTY_QUERY_NO_COUNTS)) b += 4 * ix.m_input;
+    return b + (1 << 20);
 }
 
 void fill_stats_from_index(const Index &ix, folty_stats *s) {
@@ -936,6 +996,14 @@ void fill_stats_from_index(const Index &ix, folty_stats *s) {
 Workspace::~Workspace() {
     if (events)
         for (auto &e : ev) (void)hipEventDestroy(e);
+}
+
+size_t Workspace::device_bytes() const {
+    const DevBuf *b[] = {&count, &sv, &sw, &su, &wu, &wbase, &sbase, &ncert, &pairs_k, &pairs_v, &pairs_k2,
+                         &pairs_v2, &scal, &cub, &ilist, &vtmp, &diff, &tflag, &tinst};
+    size_t t = 0;
+    for (auto *x : b) t += x->bytes;
+    return t;
 }
 
 void Workspace::ensure_events() {

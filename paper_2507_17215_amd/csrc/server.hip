@@ -9,6 +9,13 @@
 // otherwise it waits at the head of the queue.  Several workers run at once,
 // so their kernels overlap on the device.  Latency is measured from submit to
 // the moment the result is ready on the host.
+//
+// Memory counted against the budget: the estimates of the passes in flight (a
+// single query's buffers, or the plan of a batch) plus the buffers each
+// worker's workspace keeps between passes.  A worker that
+// finds the head request does not fit gives its own workspace back; freed
+// blocks stay in the library's cache, which is handed back to the driver when
+// cache and counted memory together pass the budget.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -24,19 +31,6 @@ namespace {
 double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
-// device bytes one query on this graph needs beyond the resident index
-int64_t query_footprint(const Graph *g) {
-    const Index &ix = g->ix;
-    int64_t b = 0;
-    b += 4 * hist_words(ix.m, 4);          // window histogram (one level, padded to four)
-    b += 20 * ix.T + 8 * (int64_t)ix.NI;   // survivors and their slots
-    b += 4 * (int64_t)ix.NI + 16 * ((int64_t)ix.NI + 1);
-    // certificate records (key + count), their sorted copy and the sort's scratch
-    b += 36 * (2 * (int64_t)ix.S + (int64_t)ix.m / 64 + 2);
-    b += 4 * ix.m_input;                   // per-edge counts handed back
-    return b;
 }
 
 } // namespace
@@ -55,7 +49,12 @@ struct Server {
         std::string err;
     };
     int device = 0;
-    int64_t budget = 0, in_use = 0, peak_use = 0;
+    int64_t budget = 0, in_use = 0, peak_use = 0; // in_use: estimates of the requests in flight
+    std::vector<int64_t> kept;                    // per worker: bytes its workspace keeps
+    int64_t kept_total = 0;
+    int active = 0, peak_active = 0;              // passes running at once
+    int64_t held() const { return in_use + kept_total; }
+    bool fits(int64_t b) const { return held() + b <= budget; }
     int max_batch = 16;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -67,50 +66,85 @@ struct Server {
     bool stop = false;
     std::vector<std::thread> workers;
 
-    void worker_main();
+    std::atomic<int64_t> trimmed_bytes{0};
+    void worker_main(int me);
+    void trim_if_over();
     ~Server();
 };
 
-void Server::worker_main() {
+void Server::worker_main(int me) {
     if (hipSetDevice(device) != hipSuccess) return;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
-    Workspace ws;
+    std::unique_ptr<Workspace> ws(new Workspace());
+    auto set_kept = [&](int64_t b) { // caller holds mu
+        kept_total += b - kept[me];
+        kept[me] = b;
+    };
     for (;;) {
         std::vector<Req> take;
         int64_t bytes = 0;
+        bool give_back = false;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stop || (!queue.empty() && in_use + queue.front().bytes <= budget); });
+            // wake to start the head request, or to give this worker's buffers back
+            // when the head does not fit
+            cv_work.wait(lk, [&] {
+                return stop || (!queue.empty() && (fits(queue.front().bytes) || kept[me] > 0));
+            });
             if (stop && queue.empty()) break;
-            if (queue.empty() || in_use + queue.front().bytes > budget) continue;
-            // the head, plus queued requests on the same graph that also fit
-            Req head = queue.front();
-            queue.pop_front();
-            take.push_back(head);
-            bytes = head.bytes;
-            for (auto it = queue.begin(); it != queue.end() && (int)take.size() < max_batch;) {
-                if (it->g == head.g && in_use + bytes + it->bytes <= budget) {
-                    bytes += it->bytes;
-                    take.push_back(*it);
-                    it = queue.erase(it);
-                } else {
+            if (queue.empty()) continue;
+            if (!fits(queue.front().bytes)) {
+                give_back = kept[me] > 0;
+                if (give_back) set_kept(0);
+            } else {
+                // the head, plus queued requests on the same graph while the plan
+                // of them all still fits
+                Req head = queue.front();
+                queue.pop_front();
+                take.push_back(head);
+                bytes = head.bytes;
+                std::vector<folty_query> qs(1, head.q);
+                for (auto it = queue.begin(); it != queue.end() && (int)take.size() < max_batch;) {
+                    if (it->g == head.g) {
+                        qs.push_back(it->q);
+                        const int64_t b = plan_footprint(head.g, qs.data(), (int)qs.size());
+                        if (fits(b)) {
+                            bytes = b;
+                            take.push_back(*it);
+                            it = queue.erase(it);
+                            continue;
+                        }
+                        qs.pop_back();
+                    }
                     ++it;
                 }
-            }
-            in_use += bytes;
-            peak_use = std::max(peak_use, in_use);
-            if (take.size() > 1) {
-                batches++;
-                batched_requests += (int64_t)take.size();
+                in_use += bytes;
+                peak_use = std::max(peak_use, held());
+                active++;
+                peak_active = std::max(peak_active, active);
+                if (take.size() > 1) {
+                    batches++;
+                    batched_requests += (int64_t)take.size();
+                }
             }
         }
+        if (give_back) {
+            {
+                StreamScope sc(s);
+                ws.reset(new Workspace());
+            }
+            trim_if_over();
+            cv_work.notify_all();
+            continue;
+        }
+        if (take.empty()) continue;
         std::vector<Done> out(take.size());
         const double t_start = now_ms();
         try {
             StreamScope sc(s);
             if (take.size() == 1) {
-                out[0].r = run_query_on(take[0].g, take[0].q, ws, s);
+                out[0].r = run_query_on(take[0].g, take[0].q, *ws, s);
             } else {
                 std::vector<folty_query> qs(take.size());
                 std::vector<int32_t> qg(take.size(), 0);
@@ -142,9 +176,13 @@ void Server::worker_main() {
             }
         }
         const double t_end = now_ms();
+        const int64_t ws_bytes = (int64_t)ws->device_bytes();
         {
             std::lock_guard<std::mutex> lk(mu);
             in_use -= bytes;
+            active--;
+            set_kept(ws_bytes);
+            peak_use = std::max(peak_use, held());
             for (size_t i = 0; i < take.size(); i++) {
                 if (out[i].r) {
                     out[i].r->stats.queue_ms = t_start - take[i].t_submit;
@@ -155,11 +193,30 @@ void Server::worker_main() {
                 completed++;
             }
         }
+        trim_if_over();
         cv_done.notify_all();
         cv_work.notify_all();
     }
+    {
+        StreamScope sc(s);
+        ws.reset();
+    }
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
+}
+
+// blocks the library keeps cached count too once they would push the device
+// past the budget: then the largest go back to the driver until they fit
+void Server::trim_if_over() {
+    int64_t h;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        h = held();
+    }
+    if (h + (int64_t)dev_cached() > budget) {
+        (void)hipSetDevice(device);
+        trimmed_bytes += (int64_t)dev_trim_to((size_t)std::max<int64_t>(0, budget - h));
+    }
 }
 
 Server::~Server() {
@@ -189,14 +246,15 @@ Server *server_create(const folty_server_opts *o) {
     }
     S->budget = budget;
     S->max_batch = opts.max_batch;
-    for (int i = 0; i < opts.workers; i++) S->workers.emplace_back([s = S.get()] { s->worker_main(); });
+    S->kept.assign(opts.workers, 0);
+    for (int i = 0; i < opts.workers; i++) S->workers.emplace_back([s = S.get(), i] { s->worker_main(i); });
     return S.release();
 }
 
 int64_t server_submit(Server *S, Graph *g, const folty_query &q) {
     check_query(g, q);
     ensure_triangles(g); // the footprint bound needs the triangle count
-    const int64_t bytes = query_footprint(g);
+    const int64_t bytes = query_footprint(g, q);
     std::lock_guard<std::mutex> lk(S->mu);
     if (bytes > S->budget) {
         S->rejected++;
@@ -236,8 +294,11 @@ void server_info(Server *S, folty_server_info *info) {
     info->batches = S->batches;
     info->batched_requests = S->batched_requests;
     info->budget_bytes = S->budget;
-    info->in_use_bytes = S->in_use;
+    info->in_use_bytes = S->held();
     info->peak_in_use_bytes = S->peak_use;
+    info->kept_bytes = S->kept_total;
+    info->peak_concurrent_passes = S->peak_active;
+    info->trimmed_bytes = S->trimmed_bytes.load();
 }
 
 void server_destroy(Server *S) { delete S; }

@@ -85,7 +85,8 @@ class ServerOpts(ctypes.Structure):
 class ServerInfo(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in (
         "submitted", "completed", "rejected", "queued", "batches", "batched_requests",
-        "budget_bytes", "in_use_bytes", "peak_in_use_bytes")]
+        "budget_bytes", "in_use_bytes", "peak_in_use_bytes", "kept_bytes", "peak_concurrent_passes",
+        "trimmed_bytes")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

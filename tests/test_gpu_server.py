@@ -58,10 +58,23 @@ def test_served_results_equal_alone_results():
         t.start()
     for t in threads:
         t.join()
+    # a burst on one graph while the others are still queued: requests that wait
+    # together share a pass, and passes of several workers run at once
+    burst = [(1, dict(delta=int(d), theta=(1, 4), variant=int(v)))
+             for d, v in zip(rng.choice([600, 86400, 10**6], size=24), rng.choice([0, 3], size=24))]
+    burst_alone = [Gs[gi].query(**q) for gi, q in burst]
+    burst_tickets = [srv.submit(Gs[gi], **q) for gi, q in burst]
     served = [srv.wait(t) for t in tickets]
+    burst_served = [srv.wait(t) for t in burst_tickets]
     info = srv.info()
     say("server info", info)
-    assert info["completed"] == len(qs) and info["rejected"] == 0
+    assert info["completed"] == len(qs) + len(burst) and info["rejected"] == 0
+    assert info["batches"] > 0 and info["batched_requests"] > info["batches"]
+    assert info["peak_concurrent_passes"] > 1
+    assert max(s.stats["batch_size"] for s in burst_served) > 1
+    for a, s in zip(burst_alone, burst_served):
+        assert s.pairs() == a.pairs() and s.n_certificates == a.n_certificates
+        assert np.array_equal(s.counts(), a.counts())
     for (gi, q), a, s in zip(qs, alone, served):
         assert s.pairs() == a.pairs()
         assert s.n_certificates == a.n_certificates
@@ -107,6 +120,43 @@ def test_budget_forces_waits_and_rejects_oversized():
     assert ei.value.code == folty.ENOMEM
     assert tiny.info()["rejected"] == 1
     tiny.close()
+
+
+def test_budget_bounds_device_memory():
+    """Under a budget that holds about two requests, the device memory the server
+    takes (requests in flight, workspaces kept between passes, cached blocks)
+    stays within it: free device memory while serving never falls more than the
+    budget (plus a small allowance for runtime objects) below what it was."""
+    import torch
+    gs = [synth.c1_family(2_000_000, seed=31), synth.c1_family(1_000_000, seed=32), synth.tiny(seed=33)]
+    Gs = [folty.Graph(g.n, g.src, g.dst, g.t).build() for g in gs]
+    rng = np.random.default_rng(9)
+    qs = [(int(rng.integers(0, 2)), dict(delta=int(rng.choice([600, 86400, 10**6])), theta=(1, 4),
+                                         variant=int(rng.choice([0, 3])), counts=False)) for _ in range(40)]
+    alone = [Gs[gi].query(**q).pairs() for gi, q in qs]
+    # what one worker keeps after a request on the largest graph
+    probe = folty.Server(workers=1, hbm_budget_bytes=1 << 40)
+    probe.wait(probe.submit(Gs[0], delta=10**6, counts=False))
+    kept = probe.info()["kept_bytes"]
+    probe.close()
+    budget = int(2.5 * kept)
+    folty.release_cached_memory()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    srv = folty.Server(workers=4, max_batch=4, hbm_budget_bytes=budget)
+    say("bounded server: budget", budget, "kept by one worker", kept)
+    tickets = [srv.submit(Gs[gi], **q) for gi, q in qs]
+    growth = 0
+    for (gi, q), a, t in zip(qs, alone, tickets):
+        s = srv.wait(t)
+        assert s.pairs() == a
+        growth = max(growth, free0 - torch.cuda.mem_get_info()[0])
+    info = srv.info()
+    say("bounded info", info, "largest growth", growth)
+    assert info["peak_in_use_bytes"] <= budget
+    assert growth <= budget + (32 << 20)
+    srv.close()
+    folty.release_cached_memory()
 
 
 def test_poll_and_ticket_errors():
