@@ -410,6 +410,35 @@ int folty_result_pairs(const folty_result *r, int64_t *n_pairs, const int32_t **
 int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t **edge_count);
 
 /*
+ * The query of folty_run_fol_query for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  It calls no hipMalloc or hipFree and no allocating library
+ * routine.  Its scratch (per-edge counts, survivors, per-pair certificate counts,
+ * pair keys, sort and scan scratch) is a fixed device array of
+ * FOLTY_NOALLOC_SCRATCH_BYTES that every device the library runs on holds until
+ * the process ends; a query needing more fails with FOLTY_ENOMEM and a message
+ * giving the size.  That is enough for graphs of about a million temporal edges.
+ *   g, q            as for folty_run_fol_query; FOLTY_QUERY_NO_COUNTS is ignored
+ *                   (edge_count decides), and the universe N(a) & N(b) needs the
+ *                   graph's per-edge triangle counts to exist already (built by a
+ *                   folty_run_fol_query with that universe), else FOLTY_EINVAL.
+ *   pair_u, pair_v, n_cert  device arrays of pair_cap entries (caller-owned):
+ *                   the solution pairs sorted by (u, v) and their certificate
+ *                   counts.  More than pair_cap pairs: FOLTY_EOVERFLOW, with
+ *                   *n_pairs set (then the arrays are not written).
+ *   edge_count      device uint32[m_input] (caller-owned) for the per-edge counts in
+ *                   input order (0xFFFFFFFF: self-loop), or NULL.
+ *   n_pairs, n_certificates  host outputs: pairs and |Sol|.
+ * Runs on the graph's stream and returns when the outputs are written.  All
+ * calls on one device share its scratch, so the library runs them one at a
+ * time (the first call on a device also sets the scratch up).
+ */
+#define FOLTY_NOALLOC_SCRATCH_BYTES (64u << 20)
+int folty_run_fol_query_noalloc(folty_graph *g, const folty_query *q, int32_t *pair_u, int32_t *pair_v,
+                                uint32_t *n_cert, int64_t pair_cap, uint32_t *edge_count, int64_t *n_pairs,
+                                int64_t *n_certificates);
+
+/*
  * Solution vertices of a vertex query in ascending id order, and for each the
  * number of its neighbours v with a qualifying edge from it to v.  Host
  * pointers, valid until folty_result_free; *n_vertices = 0 for a pair query.

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libfolty.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["primitives.hip", "core.hip", "index.hip", "query.hip", "batch.hip", "triad.hip", "server.hip", "alloc.hip", "abi.hip"]
+SOURCES = ["primitives.hip", "core.hip", "index.hip", "query.hip", "batch.hip", "triad.hip", "server.hip", "alloc.hip", "noalloc.hip", "abi.hip"]
 ARCH = "gfx950"
 
 

@@ -102,6 +102,17 @@ int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out
     });
 }
 
+int folty_run_fol_query_noalloc(folty_graph *g, const folty_query *q, int32_t *pair_u, int32_t *pair_v,
+                                uint32_t *n_cert, int64_t pair_cap, uint32_t *edge_count, int64_t *n_pairs,
+                                int64_t *n_certificates) {
+    return guarded([&] {
+        if (!g || !q || !n_pairs || !n_certificates) fail(FOLTY_EINVAL, "null argument");
+        *n_pairs = 0;
+        *n_certificates = 0;
+        run_query_noalloc(&g->g, *q, pair_u, pair_v, n_cert, pair_cap, edge_count, n_pairs, n_certificates);
+    });
+}
+
 int folty_run_vertex_query(folty_graph *g, const folty_vertex_query *q, folty_result **out) {
     return guarded([&] {
         if (!g || !q || !out) fail(FOLTY_EINVAL, "null argument");

@@ -33,6 +33,7 @@ std::mutex g_pools_mu;
 std::map<int, Pool *> g_pools;
 
 thread_local hipStream_t t_stream = nullptr;
+thread_local ArenaScope *t_arena = nullptr;
 
 Pool &pool_for(int dev) {
     std::lock_guard<std::mutex> lk(g_pools_mu);
@@ -58,7 +59,20 @@ void drop_block(Block &b) {
 StreamScope::StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
 StreamScope::~StreamScope() { t_stream = prev; }
 
+ArenaScope::ArenaScope(void *b, size_t c) : base(static_cast<char *>(b)), cap(c), prev(t_arena) { t_arena = this; }
+ArenaScope::~ArenaScope() { t_arena = prev; }
+
 void *dev_alloc(size_t bytes, size_t *got) {
+    if (ArenaScope *a = t_arena) {
+        const size_t want = (bytes + 255) & ~size_t(255);
+        if (a->off + want > a->cap)
+            fail(FOLTY_ENOMEM, "this call needs more than the %zu bytes of its fixed device scratch (%zu in use, "
+                 "%zu more asked for)", a->cap, a->off, want);
+        void *p = a->base + a->off;
+        a->off += want;
+        *got = want;
+        return p;
+    }
     int dev = 0;
     FOLTY_HIP(hipGetDevice(&dev));
     Pool &P = pool_for(dev);
@@ -101,6 +115,8 @@ void *dev_alloc(size_t bytes, size_t *got) {
 
 void dev_free(void *p, size_t bytes) {
     if (!p) return;
+    for (ArenaScope *a = t_arena; a; a = a->prev)
+        if (static_cast<char *>(p) >= a->base && static_cast<char *>(p) < a->base + a->cap) return;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipFree(p);

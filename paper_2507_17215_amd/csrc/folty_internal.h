@@ -64,6 +64,19 @@ void *host_alloc(size_t bytes);
 bool host_free(void *p);
 size_t host_trim();  // give the cached pinned blocks back; returns bytes
 
+// While an ArenaScope is alive, the device buffers its thread asks for are
+// carved one after another from [base, base + cap) instead of the allocator
+// (FOLTY_ENOMEM, naming the size, when the next one does not fit) and handing
+// them back does nothing.  Nothing else allocates device memory on that thread
+// meanwhile.
+struct ArenaScope {
+    char *base;
+    size_t cap, off = 0;
+    ArenaScope *prev;
+    ArenaScope(void *b, size_t c);
+    ~ArenaScope();
+};
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -87,6 +100,11 @@ struct DevBuf {
         release();
         p = dev_alloc(b ? b : 256, &bytes);
     }
+    // drop the pointer without handing the memory back (memory an ArenaScope lent)
+    void forget() {
+        p = nullptr;
+        bytes = 0;
+    }
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -94,12 +112,20 @@ struct DevBuf {
 struct PinnedBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool own = true; // false: p is host memory lent by the owner of this buffer, never freed here
     PinnedBuf() = default;
     PinnedBuf(const PinnedBuf &) = delete;
     PinnedBuf &operator=(const PinnedBuf &) = delete;
-    ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+    ~PinnedBuf() { if (p && own) (void)hipHostFree(p); }
+    void lend(void *q, size_t b) {
+        if (p && own) (void)hipHostFree(p);
+        p = q;
+        bytes = b;
+        own = false;
+    }
     void ensure(size_t b) {
         if (b <= bytes && p) return;
+        if (!own) fail(FOLTY_EINVAL, "a lent host buffer of %zu bytes cannot grow to %zu", bytes, b);
         if (p) (void)hipHostFree(p);
         p = nullptr;
         FOLTY_HIP(hipHostMalloc(&p, b ? b : 64, hipHostMallocDefault));
@@ -242,6 +268,7 @@ struct Workspace {
     ~Workspace();
     void ensure_events();
     size_t device_bytes() const; // device memory its buffers hold
+    void forget_buffers();       // forget every device buffer (memory an ArenaScope lent)
 };
 
 struct Graph {
@@ -316,6 +343,16 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws);
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
                        hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss = false);
 double ev_ms(hipEvent_t a, hipEvent_t b);
+// The single query with its outputs in the caller's device memory: the sorted
+// pairs (at most pair_cap; FOLTY_EOVERFLOW beyond, with *n_pairs set), and
+// per-edge counts in input order when edge_count is not null.  Uses ws and
+// nothing else, and builds no lazy index part (FOLTY_EINVAL for a universe
+// whose per-edge triangle counts do not exist yet).
+void run_query_into(Graph *g, const folty_query &q, Workspace &ws, int32_t *pair_u, int32_t *pair_v,
+                    uint32_t *n_cert, int64_t pair_cap, uint32_t *edge_count, int64_t *n_pairs,
+                    int64_t *n_certificates);
+void run_query_noalloc(Graph *g, const folty_query &q, int32_t *pair_u, int32_t *pair_v, uint32_t *n_cert,
+                       int64_t pair_cap, uint32_t *edge_count, int64_t *n_pairs, int64_t *n_certificates);
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &ws, Result **outs);
 void run_multi(Graph *const *gs, const folty_query *qs, int ng, Workspace &ws, Result **outs);
 void fill_stats_from_index(const Index &ix, folty_stats *s);

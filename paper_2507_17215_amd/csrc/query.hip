@@ -930,6 +930,40 @@ static const uint32_t *query_counts(Graph *g, const folty_query &q, Workspace &w
     return count;
 }
 
+void run_query_into(Graph *g, const folty_query &q, Workspace &ws, int32_t *pair_u, int32_t *pair_v,
+                    uint32_t *n_cert, int64_t pair_cap, uint32_t *edge_count, int64_t *n_pairs,
+                    int64_t *n_certificates) {
+    check_query(g, q);
+    if (pair_cap < 0) fail(FOLTY_EINVAL, "pair_cap must be >= 0");
+    if (pair_cap > 0 && (!pair_u || !pair_v || !n_cert)) fail(FOLTY_EINVAL, "null pair output array");
+    if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
+    const Index &ix = g->ix;
+    if (q.universe == FOLTY_UNIVERSE_COMMON && !ix.tcnt_ready)
+        fail(FOLTY_EINVAL, "the universe N(a) & N(b) needs the graph's per-edge triangle counts, which this call "
+                           "does not build: run one query with that universe through folty_run_fol_query first");
+    hipStream_t s = g->stream;
+    int64_t tests = 0;
+    const uint32_t *count = query_counts(g, q, ws, s, &tests);
+    const PairCounts pc = threshold_pairs(g, q, count, ws, s, false);
+    *n_pairs = pc.npairs;
+    *n_certificates = pc.ncerts;
+    if (edge_count) scatter_counts(g, count, edge_count, s);
+    if (pc.npairs > pair_cap) {
+        FOLTY_HIP(hipStreamSynchronize(s));
+        fail(FOLTY_EOVERFLOW, "%d solution pairs do not fit the %lld the caller's arrays hold", pc.npairs,
+             (long long)pair_cap);
+    }
+    if (pc.npairs > 0) {
+        int32_t *du, *dv;
+        uint32_t *dn;
+        sort_pairs(g, ws, pc.npairs, s, &du, &dv, &dn);
+        FOLTY_HIP(hipMemcpyAsync(pair_u, du, 4 * (size_t)pc.npairs, hipMemcpyDeviceToDevice, s));
+        FOLTY_HIP(hipMemcpyAsync(pair_v, dv, 4 * (size_t)pc.npairs, hipMemcpyDeviceToDevice, s));
+        FOLTY_HIP(hipMemcpyAsync(n_cert, dn, 4 * (size_t)pc.npairs, hipMemcpyDeviceToDevice, s));
+    }
+    FOLTY_HIP(hipStreamSynchronize(s));
+}
+
 static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hipStream_t s,
                               const folty_vertex_query *vq) {
     if (hipSetDevice(g->device) != hipSuccess) fail(FOLTY_EDEVICE, "hipSetDevice failed");
@@ -1004,6 +1038,12 @@ size_t Workspace::device_bytes() const {
     size_t t = 0;
     for (auto *x : b) t += x->bytes;
     return t;
+}
+
+void Workspace::forget_buffers() {
+    DevBuf *b[] = {&count, &sv, &sw, &su, &wu, &wbase, &sbase, &ncert, &pairs_k, &pairs_v, &pairs_k2,
+                   &pairs_v2, &scal, &cub, &ilist, &vtmp, &diff, &tflag, &tinst};
+    for (auto *x : b) x->forget();
 }
 
 void Workspace::ensure_events() {

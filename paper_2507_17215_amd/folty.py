@@ -27,7 +27,7 @@ U32_MAX = 0xFFFFFFFF
 
 EXPORTS = (
     "folty_last_error", "folty_version", "folty_load_temporal_graph", "folty_build_index",
-    "folty_run_fol_query", "folty_run_vertex_query", "folty_result_vertices",
+    "folty_run_fol_query", "folty_run_fol_query_noalloc", "folty_run_vertex_query", "folty_result_vertices",
     "folty_run_triad_query", "folty_run_triad_query_ws", "folty_result_triads",
     "folty_result_edge_instances",
     "folty_workspace_create", "folty_workspace_free",
@@ -138,6 +138,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.folty_load_temporal_graph.argtypes = [I32, I64, P, P, P, I32, P, PP]
     lib.folty_build_index.argtypes = [P, ctypes.POINTER(BuildOpts)]
     lib.folty_run_fol_query.argtypes = [P, ctypes.POINTER(Query), PP]
+    lib.folty_run_fol_query_noalloc.argtypes = [P, ctypes.POINTER(Query), P, P, P, I64, P, ctypes.POINTER(I64),
+                                                ctypes.POINTER(I64)]
     lib.folty_run_vertex_query.argtypes = [P, ctypes.POINTER(VertexQuery), PP]
     lib.folty_result_vertices.argtypes = [P, ctypes.POINTER(I64), PP, PP]
     lib.folty_run_triad_query.argtypes = [P, ctypes.POINTER(TriadQuery), PP]
@@ -346,6 +348,31 @@ class Graph:
         o = BuildOpts(int(rank_mode), 1 if cache_triangles else 0, int(rank_seed))
         _check(load_library().folty_build_index(self._h, ctypes.byref(o)))
         return self
+
+    def query_noalloc(self, delta, theta=(1, 2), variant=0, universe=UNIVERSE_DST, exclude_other=False,
+                      pair_u=None, pair_v=None, n_cert=None, edge_count=None, smaller_side=False) -> dict:
+        """folty_run_fol_query_noalloc: the library allocates nothing; the outputs are the
+        caller's int32/int32/uint32 (as int32) device tensors of equal length (the pair
+        capacity) and, if given, an int32 device tensor of m entries for the per-edge counts.
+        Returns n_pairs, n_certificates and the tensors cut to n_pairs."""
+        q = make_query(delta, theta, variant, universe, exclude_other, True, smaller_side)
+        cap = 0 if pair_u is None else int(pair_u.numel())
+        ptr = lambda x: ctypes.c_void_p(x.data_ptr()) if x is not None else None
+        for x in (pair_u, pair_v, n_cert, edge_count):
+            if x is not None and (not x.is_cuda or x.dtype.itemsize != 4 or not x.is_contiguous()):
+                raise ValueError("outputs are contiguous 4-byte device tensors")
+        if pair_u is not None and not (pair_v.numel() == n_cert.numel() == cap):
+            raise ValueError("pair_u, pair_v and n_cert must have the same length")
+        if edge_count is not None and edge_count.numel() < self.m:
+            raise ValueError("edge_count needs m entries")
+        npairs, ncert = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().folty_run_fol_query_noalloc(self._h, ctypes.byref(q), ptr(pair_u), ptr(pair_v),
+                                                          ptr(n_cert), cap, ptr(edge_count), ctypes.byref(npairs),
+                                                          ctypes.byref(ncert)))
+        k = int(npairs.value)
+        return {"n_pairs": k, "n_certificates": int(ncert.value),
+                "pair_u": None if pair_u is None else pair_u[:k], "pair_v": None if pair_v is None else pair_v[:k],
+                "n_cert": None if n_cert is None else n_cert[:k], "edge_count": edge_count}
 
     def query(self, delta, theta=(1, 2), variant=0, universe=UNIVERSE_DST,
               exclude_other=False, counts=True, workspace: Workspace | None = None,
