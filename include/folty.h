@@ -38,6 +38,7 @@
 #ifndef FOLTY_H
 #define FOLTY_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -78,11 +79,26 @@ typedef struct folty_graph folty_graph;
 typedef struct folty_result folty_result;
 typedef struct folty_workspace folty_workspace;
 
+/* A caller-supplied device allocator (PyTorch's, say).  alloc returns `bytes` of
+ * device memory to be used on `stream` (NULL when it cannot: FOLTY_ENOMEM); free
+ * hands such memory back, after which only later work on that stream may use it
+ * again.  ctx is passed through. */
+typedef void *(*folty_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*folty_free_fn)(void *p, size_t bytes, void *stream, void *ctx);
+
 typedef struct {
     int32_t rank_mode;       /* FOLTY_RANK_*; default FOLTY_RANK_DEGENERACY */
     int32_t cache_triangles; /* 1: keep the static triangle list in the index, so queries
                                 skip wedge enumeration; 0 (default): enumerate per query */
     uint64_t rank_seed;      /* seed for FOLTY_RANK_RANDOM */
+    /* Device memory of the index (every array it keeps, the build's temporaries and
+     * index parts made later on first use) comes from alloc/free, on the graph's
+     * stream, when both are set; NULL: the library's caching allocator.  They are
+     * called on the threads that call into the library for this graph, and must
+     * stay valid until folty_graph_free. */
+    folty_alloc_fn alloc;
+    folty_free_fn free;
+    void *alloc_ctx;
 } folty_build_opts;
 
 /*
@@ -341,8 +357,15 @@ typedef struct {
     int32_t records;         /* certificate records of the last run (one per run of a directed
                                 pair within a wavefront, before merging) */
     double last_run_ms;      /* device time of the last run (launch sequence to sorted pairs) */
+    int32_t tune_source;     /* 0: default launch shape (little work), 1: timed on this plan's
+                                first run, 2: taken from the tuning table */
+    int32_t reserved;
 } folty_plan_info;
 
+/* The launch shapes timed by plans are kept per workload bucket (log2 of the
+ * test and edge counts) for the life of the process and, when the environment
+ * variable FOLTY_TUNE_CACHE names a file, in that file as JSON, read on first
+ * use and rewritten when an entry is added. */
 int folty_plan_create(folty_graph *const *graphs, int32_t n_graphs, const folty_query *qs,
                       const int32_t *query_graph, int32_t nq, folty_plan **out);
 int folty_plan_run(folty_plan *p, folty_result **outs);

@@ -34,6 +34,7 @@ std::map<int, Pool *> g_pools;
 
 thread_local hipStream_t t_stream = nullptr;
 thread_local ArenaScope *t_arena = nullptr;
+thread_local const AllocHook *t_hook = nullptr;
 
 Pool &pool_for(int dev) {
     std::lock_guard<std::mutex> lk(g_pools_mu);
@@ -58,6 +59,11 @@ void drop_block(Block &b) {
 
 StreamScope::StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
 StreamScope::~StreamScope() { t_stream = prev; }
+
+HookScope::HookScope(const AllocHook *h) : prev(t_hook) { t_hook = h && h->set() ? h : nullptr; }
+HookScope::~HookScope() { t_hook = prev; }
+// an arena on the thread takes precedence over any caller's allocator
+const AllocHook *current_hook() { return t_arena ? nullptr : t_hook; }
 
 ArenaScope::ArenaScope(void *b, size_t c) : base(static_cast<char *>(b)), cap(c), prev(t_arena) { t_arena = this; }
 ArenaScope::~ArenaScope() { t_arena = prev; }

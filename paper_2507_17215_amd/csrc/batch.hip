@@ -22,6 +22,10 @@
 // few candidates on the plan's own work and remembered per workload size.
 #include <algorithm>
 #include <cstring>
+#include <unistd.h>
+
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -311,9 +315,94 @@ double ev_ms2(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-// temporal-kernel launch shape chosen per workload size (log2 of the test count)
+// Temporal-kernel launch shapes chosen by timing, per workload bucket: the
+// log2 of the plan's test count and of its edge count.  The table is kept in
+// memory and, when FOLTY_TUNE_CACHE names a file, in that file as JSON
+//   {"arch": "gfx950", "entries": [{"tests_log2": T, "edges_log2": E,
+//    "tests_per_chunk": I, "blocks": B, "ms": M}, ...]}
+// read on first use and rewritten (through a temporary file and a rename)
+// whenever an entry is added.  Entries of another arch are ignored.
+struct TuneEntry {
+    int ipt, blocks;
+    double ms;
+};
 std::mutex g_tune_mu;
-std::map<int, std::pair<int, int>> g_tune; // bucket -> (ipt, blocks)
+std::map<std::pair<int, int>, TuneEntry> g_tune;
+std::string g_tune_loaded;  // file the table was last read from
+std::string g_tune_written; // file the table was last written to
+
+std::string tune_path() {
+    const char *p = getenv("FOLTY_TUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+// numbers after "key": in one entry's text
+bool tune_field(const std::string &e, const char *key, double *out) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t i = e.find(k);
+    if (i == std::string::npos) return false;
+    i = e.find(':', i + k.size());
+    if (i == std::string::npos) return false;
+    char *end = nullptr;
+    *out = strtod(e.c_str() + i + 1, &end);
+    return end != e.c_str() + i + 1;
+}
+
+// caller holds g_tune_mu
+void tune_load() {
+    const std::string path = tune_path();
+    if (path.empty() || path == g_tune_loaded) return;
+    g_tune_loaded = path;
+    FILE *f = fopen(path.c_str(), "rb");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+    fclose(f);
+    if (text.find("\"arch\": \"gfx950\"") == std::string::npos) return;
+    size_t at = text.find("\"entries\"");
+    while (at != std::string::npos) {
+        const size_t a = text.find('{', at), b = a == std::string::npos ? a : text.find('}', a);
+        if (a == std::string::npos || b == std::string::npos) break;
+        const std::string e = text.substr(a, b - a + 1);
+        double t, m, i, bl, ms = 0;
+        if (tune_field(e, "tests_log2", &t) && tune_field(e, "edges_log2", &m) &&
+            tune_field(e, "tests_per_chunk", &i) && tune_field(e, "blocks", &bl) && i >= 1 && i <= 64 &&
+            bl >= 1 && bl <= (1 << 20)) {
+            tune_field(e, "ms", &ms);
+            g_tune[{(int)t, (int)m}] = TuneEntry{(int)i, (int)bl, ms};
+        }
+        at = b + 1;
+    }
+}
+
+// caller holds g_tune_mu
+void tune_save() {
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [");
+    bool first = true;
+    for (auto &kv : g_tune) {
+        fprintf(f, "%s\n  {\"tests_log2\": %d, \"edges_log2\": %d, \"tests_per_chunk\": %d, \"blocks\": %d, "
+                   "\"ms\": %.4f}", first ? "" : ",", kv.first.first, kv.first.second, kv.second.ipt,
+                kv.second.blocks, kv.second.ms);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
+    else g_tune_written = path;
+}
+
+int log2_ceil(int64_t x) {
+    int b = 0;
+    while ((1ll << b) < x && b < 62) b++;
+    return b;
+}
 
 } // namespace
 
@@ -346,6 +435,7 @@ struct Plan {
     // launch shape and capture
     int ipt = 1, tblocks = 4096;
     bool tuned = false;
+    int tune_source = 0; // 0: default shape, 1: timed by this plan, 2: from the tuning table
     bool eager = false; // capture refused: launch directly
     bool oneshot = false;
     hipGraph_t graph = nullptr;
@@ -447,15 +537,17 @@ static void tune(Plan &P) {
     FOLTY_HIP(hipMemcpyAsync(&tests, P.wbase.as<int64_t>() + P.items, 8, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
     P.last_tests = tests;
-    int bucket = 0;
-    while ((1ll << bucket) < tests && bucket < 62) bucket++;
+    const std::pair<int, int> bucket{log2_ceil(tests), log2_ceil(P.total_w)};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
         auto it = g_tune.find(bucket);
         if (it != g_tune.end()) {
-            P.ipt = it->second.first;
-            P.tblocks = it->second.second;
+            P.ipt = it->second.ipt;
+            P.tblocks = it->second.blocks;
             P.tuned = true;
+            P.tune_source = 2;
+            if (tune_path() != g_tune_written) tune_save(); // a file named since the entry was made
             return;
         }
     }
@@ -486,9 +578,11 @@ static void tune(Plan &P) {
     P.ipt = bi;
     P.tblocks = bb;
     P.tuned = true;
+    P.tune_source = 1;
     P.dirty = true; // the tries left counts behind
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[bucket] = {bi, bb};
+    g_tune[bucket] = TuneEntry{bi, bb, best};
+    tune_save();
 }
 
 // Device bytes plan_create and plan_run take for these queries on one graph
@@ -547,6 +641,7 @@ Plan *plan_create(Graph *const *gs, int ng, const folty_query *qs, const int32_t
     for (int q = 0; q < nq; q++)
         if (qs[q].universe == FOLTY_UNIVERSE_COMMON) {
             std::lock_guard<std::mutex> lk(gs[qgraph[q]]->lazy_mu);
+            HookScope hs(&gs[qgraph[q]]->hook);
             ensure_tcnt(gs[qgraph[q]]->ix, s);
             FOLTY_HIP(hipStreamSynchronize(s));
         }
@@ -873,6 +968,7 @@ void plan_info(const Plan *P, folty_plan_info *info) {
     info->temporal_blocks = P->tblocks;
     info->captured = P->exec != nullptr;
     info->last_run_ms = P->last_ms;
+    info->tune_source = P->tune_source;
 }
 
 void run_batch(Graph *g, const folty_query *qs, int nq, Workspace &, Result **outs) {

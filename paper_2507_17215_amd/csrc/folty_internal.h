@@ -64,6 +64,23 @@ void *host_alloc(size_t bytes);
 bool host_free(void *p);
 size_t host_trim();  // give the cached pinned blocks back; returns bytes
 
+// A caller's allocator (folty_build_opts) and the scope in which the device
+// buffers a thread asks for come from it; a buffer remembers where its memory
+// came from and hands it back there.
+struct AllocHook {
+    folty_alloc_fn alloc = nullptr;
+    folty_free_fn free = nullptr;
+    void *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    bool set() const { return alloc && free; }
+};
+struct HookScope {
+    const AllocHook *prev;
+    explicit HookScope(const AllocHook *h);
+    ~HookScope();
+};
+const AllocHook *current_hook();
+
 // While an ArenaScope is alive, the device buffers its thread asks for are
 // carved one after another from [base, base + cap) instead of the allocator
 // (FOLTY_ENOMEM, naming the size, when the next one does not fit) and handing
@@ -80,25 +97,39 @@ struct ArenaScope {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    AllocHook hook; // the caller's allocator p came from (unset: the library's)
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), hook(o.hook) { o.p = nullptr; o.bytes = 0; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; hook = o.hook; o.p = nullptr; o.bytes = 0; }
         return *this;
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) dev_free(p, bytes);
+        if (p) {
+            if (hook.set()) hook.free(p, bytes, hook.stream, hook.ctx);
+            else dev_free(p, bytes);
+        }
         p = nullptr;
         bytes = 0;
+        hook = AllocHook{};
     }
     // grow to at least b bytes; contents are not kept
     void ensure(size_t b) {
         if (b <= bytes && p) return;
         release();
-        p = dev_alloc(b ? b : 256, &bytes);
+        const AllocHook *h = current_hook();
+        if (h) {
+            const size_t want = ((b ? b : 256) + 255) & ~size_t(255);
+            p = h->alloc(want, h->stream, h->ctx);
+            if (!p) fail(FOLTY_ENOMEM, "the caller's allocator returned no memory for %zu bytes", want);
+            bytes = want;
+            hook = *h;
+        } else {
+            p = dev_alloc(b ? b : 256, &bytes);
+        }
     }
     // drop the pointer without handing the memory back (memory an ArenaScope lent)
     void forget() {
@@ -274,6 +305,7 @@ struct Workspace {
 struct Graph {
     int device = 0;
     hipStream_t stream = nullptr;
+    AllocHook hook; // the caller's allocator for the index (folty_build_opts), if any
     bool own_stream = false;
     // inputs (device copies) until the index is built
     DevBuf src, dst, t;

@@ -413,8 +413,13 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     if (opts) o = *opts;
     if (o.rank_mode < 0 || o.rank_mode > 2) fail(FOLTY_EINVAL, "unknown rank_mode %d", o.rank_mode);
     if (g->ix.m_input > 0 && !g->src.p) fail(FOLTY_EINVAL, "graph inputs were released");
+    if ((o.alloc == nullptr) != (o.free == nullptr)) fail(FOLTY_EINVAL, "alloc and free must both be set or both be null");
     Index &ix = g->ix;
     hipStream_t s = g->stream;
+    // index memory from the caller's allocator when given (buffers of an earlier
+    // build go back to wherever they came from)
+    g->hook = AllocHook{o.alloc, o.free, o.alloc_ctx, s};
+    HookScope hs(&g->hook);
     const int32_t n = ix.n;
     const int64_t min = ix.m_input;
     ix.built = false;

@@ -822,6 +822,7 @@ void ensure_triangles(Graph *g) {
     if (g->ix.tri_base_ready.load(std::memory_order_acquire) || !g->ix.built) return;
     FOLTY_HIP(hipSetDevice(g->device));
     StreamScope sc(g->stream);
+    HookScope hs(&g->hook);
     ensure_tri_base(g->ix, g->stream);
 }
 
@@ -970,6 +971,7 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
     Index &ix = g->ix;
     if (q.universe == FOLTY_UNIVERSE_COMMON) {
         std::lock_guard<std::mutex> lk(g->lazy_mu);
+        HookScope hs(&g->hook);
         ensure_tcnt(ix, s);
         FOLTY_HIP(hipStreamSynchronize(s));
     }

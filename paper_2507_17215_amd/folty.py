@@ -46,9 +46,32 @@ class FoltyError(RuntimeError):
         self.code = code
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class BuildOpts(ctypes.Structure):
     _fields_ = [("rank_mode", ctypes.c_int32), ("cache_triangles", ctypes.c_int32),
-                ("rank_seed", ctypes.c_uint64)]
+                ("rank_seed", ctypes.c_uint64), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
+
+
+def torch_allocator():
+    """(alloc, free) callbacks that take the index's device memory from PyTorch's
+    caching allocator, on the stream the library names."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:
+            return None
+
+    def free(p, nbytes, stream, ctx):
+        torch.cuda.caching_allocator_delete(p)
+
+    return ALLOC_FN(alloc), FREE_FN(free)
 
 
 class Query(ctypes.Structure):
@@ -62,7 +85,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_jobs", ctypes.c_int32), ("n_queries", ctypes.c_int32), ("items", ctypes.c_int64),
                 ("tests", ctypes.c_int64), ("tests_per_chunk", ctypes.c_int32),
                 ("temporal_blocks", ctypes.c_int32), ("captured", ctypes.c_int32),
-                ("records", ctypes.c_int32), ("last_run_ms", ctypes.c_double)]
+                ("records", ctypes.c_int32), ("last_run_ms", ctypes.c_double),
+                ("tune_source", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -344,8 +368,15 @@ class Graph:
         self.n, self.m = int(n), m
 
     def build(self, rank_mode: int = RANK_DEGENERACY, cache_triangles: bool = False,
-              rank_seed: int = 0) -> "Graph":
+              rank_seed: int = 0, allocator=None) -> "Graph":
+        """allocator: None (the library's own) or "torch" (PyTorch's caching allocator)
+        for the index's device memory."""
         o = BuildOpts(int(rank_mode), 1 if cache_triangles else 0, int(rank_seed))
+        if allocator == "torch":
+            self._alloc_cbs = torch_allocator()  # kept alive as long as the graph
+            o.alloc, o.free = self._alloc_cbs
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
         _check(load_library().folty_build_index(self._h, ctypes.byref(o)))
         return self
 

@@ -39,7 +39,8 @@ def test_struct_layouts_match_header():
     assert folty.Query.theta_num.offset == 8
     assert folty.Query.variant.offset == 16
     assert folty.Query.flags.offset == 19
-    assert ctypes.sizeof(folty.BuildOpts) == 16
+    assert ctypes.sizeof(folty.BuildOpts) == 40
+    assert folty.BuildOpts.alloc.offset == 16 and folty.BuildOpts.alloc_ctx.offset == 32
     assert ctypes.sizeof(folty.Stats) == 18 * 8 + 7 * 8 + 2 * 8
     assert ctypes.sizeof(folty.VertexQuery) == 40
     assert ctypes.sizeof(folty.TriadQuery) == 16

@@ -126,6 +126,29 @@ def test_index_matches_oracle_static_quantities():
         assert st["wedges"] == int((od.astype(np.int64) * (od - 1) // 2).sum())
 
 
+def test_index_memory_from_torch_allocator():
+    """folty_build_opts' allocator hook: the index (and parts made on first use)
+    lives in PyTorch's caching allocator, results are unchanged, and freeing the
+    graph hands the memory back to PyTorch."""
+    import torch
+    g = synth.tiny(seed=51)
+    base = gpu_graph(g)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    G = folty.Graph(g.n, g.src, g.dst, g.t).build(allocator="torch")
+    held = torch.cuda.memory_allocated() - before
+    say("torch allocator: index", G.device_bytes(), "bytes, torch holds", held)
+    assert held >= G.device_bytes() > 0
+    G.stats()  # per-item triangle offsets, made on first use
+    for delta, theta, variant, universe in ((10**6, (1, 4), 0, 0), (200_000, (1, 2), 3, 2), (3600, (0, 1), 6, 1)):
+        a, b = G.query(delta, theta, variant, universe), base.query(delta, theta, variant, universe)
+        assert a.pairs() == b.pairs() and np.array_equal(a.counts(), b.counts())
+    assert torch.cuda.memory_allocated() - before >= G.device_bytes()
+    G.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+
+
 def test_orientation_does_not_change_results():
     g = synth.tiny(seed=3)
     base = gpu_graph(g).query(10**6, (1, 4), 0).counts()
@@ -225,6 +248,50 @@ def test_plan_replays_match_single_queries_and_oracle():
     info = plan.info()
     assert info["n_queries"] == len(queries)
     assert info["n_jobs"] <= len(queries)
+
+
+def test_tuning_table_persists_across_processes(tmp_path):
+    """A plan's timed launch shape goes to the FOLTY_TUNE_CACHE file as JSON, and a
+    fresh process takes it from there instead of timing again.  Plans with too
+    little temporal work (under 2^20 tests) keep the default shape untimed; these
+    short windows on a 16M-edge graph give about 1.7M tests."""
+    import json
+    import os
+    import subprocess
+    import sys
+    path = str(tmp_path / "tune.json")
+    os.environ["FOLTY_TUNE_CACHE"] = path
+    template = ("from paper_2507_17215_amd import folty, synth\n"
+                "g = synth.c1_family(16_000_000, seed=3)\n"
+                "G = folty.Graph(g.n, g.src, g.dst, g.t).build()\n"
+                "qs = [dict(delta=d, theta=(1, 4), variant=v) for d in (60, 300, 1800, 7200) for v in (0, 3)]\n"
+                "p = folty.Plan([G], [(0, q) for q in qs])\n"
+                "p.run()\n"
+                "i = p.info()\n"
+                "print(i['tests'], i['tune_source'], i['tests_per_chunk'], i['temporal_blocks'])\n")
+    try:
+        code = template
+        ns = {}
+        exec(compile(code, "plan", "exec"), ns)
+        info = ns["i"]
+        say("tuning workload", info["tests"], info["tune_source"])
+        ns.clear()
+        assert info["tests"] >= 1 << 20, "too little work for the tuner"
+        with open(path) as fh:
+            table = json.load(fh)
+        say("tuning table", table)
+        assert table["arch"] == "gfx950" and table["entries"]
+        e = table["entries"][0]
+        assert {"tests_log2", "edges_log2", "tests_per_chunk", "blocks", "ms"} <= set(e)
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                             env=dict(os.environ), cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        assert out.returncode == 0, out.stderr[-2000:]
+        tests, source, ipt, blocks = map(int, out.stdout.split())
+        say("fresh process", tests, source, ipt, blocks)
+        assert tests == info["tests"] and source == 2
+        assert any(x["tests_per_chunk"] == ipt and x["blocks"] == blocks for x in table["entries"])
+    finally:
+        del os.environ["FOLTY_TUNE_CACHE"]
 
 
 def test_plan_with_empty_and_loop_only_graphs():
