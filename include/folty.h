@@ -136,6 +136,18 @@ typedef struct {
  * scratch and one scan.  Batched plans and the server ignore it. */
 #define FOLTY_QUERY_SMALLER_SIDE 2u
 
+/* Query flag: filter in one enumeration pass that writes surviving triangles
+ * into per-item slots sized for every static triangle (12 bytes of workspace per
+ * triangle; the graph's per-item triangle offsets are made first if missing,
+ * one enumeration pass, kept with the graph).  Without it a query counts
+ * survivors in one pass and enumerates the items that have any a second time,
+ * unless an earlier query on the graph found that second pass re-enumerating
+ * half of the items or triangles (a wide window): then queries of at least an
+ * eighth of that window filter in one pass by themselves.  Results are
+ * identical either way.  Single and vertex queries (plans always use the
+ * slots; exists-exists-exists queries follow the graph's switch). */
+#define FOLTY_QUERY_ONE_PASS 4u
+
 /* Sizes and timings of a graph's index (folty_graph_stats) or of one query
  * (folty_result_stats; then the graph fields are copied in as well). */
 typedef struct {
@@ -214,13 +226,18 @@ int folty_build_index(folty_graph *g, const folty_build_opts *opts);
  *
  * The filter of a query normally enumerates the graph's triangles twice: once to
  * count survivors, then again over the work items that have any.  After a query
- * (of any kind) whose second enumeration took at least half as long as the first,
- * the library counts the triangles per item once (one enumeration pass).  It does so
- * only when 20 bytes per triangle fit in a quarter of the free device memory.
- * Later queries on the graph whose delta is at least an eighth of that query's
- * then filter in one pass, with 20 bytes per triangle of survivor slots in their
- * workspace.  Plans (folty_plan_create) make the same per-item counts, after
- * which every query filters in one pass.
+ * (of any kind) whose second enumeration covered at least half of the items or
+ * half of the triangles, the library keeps the per-item triangle offsets (from
+ * the counts of its first pass), when 12 bytes per triangle fit in a quarter of
+ * the free device memory.  Later queries on the graph whose delta is at least an
+ * eighth of that query's then filter in one pass, with 12 bytes per triangle of
+ * survivor slots in their workspace (FOLTY_QUERY_ONE_PASS asks for that on any
+ * query).  The choice depends only on the graph and the queries run before.
+ *
+ * The temporal tests go one surviving triangle per thread; a triangle with many
+ * tests is cut into pieces of 32 tests, run one per thread from a list of at
+ * most 2^22 pieces (16 bytes each; the environment variable FOLTY_MAX_PIECES
+ * lowers the limit), and pieces beyond it run where they were cut.
  */
 int folty_run_fol_query(folty_graph *g, const folty_query *q, folty_result **out);
 
@@ -444,7 +461,8 @@ int folty_result_counts(folty_result *r, int64_t *n_certificates, const uint32_t
  *   g, q            as for folty_run_fol_query; FOLTY_QUERY_NO_COUNTS is ignored
  *                   (edge_count decides), and the universe N(a) & N(b) needs the
  *                   graph's per-edge triangle counts to exist already (built by a
- *                   folty_run_fol_query with that universe), else FOLTY_EINVAL.
+ *                   folty_run_fol_query with that universe), else FOLTY_EINVAL;
+ *                   so does FOLTY_QUERY_ONE_PASS the per-item triangle offsets.
  *   pair_u, pair_v, n_cert  device arrays of pair_cap entries (caller-owned):
  *                   the solution pairs sorted by (u, v) and their certificate
  *                   counts.  More than pair_cap pairs: FOLTY_EOVERFLOW, with

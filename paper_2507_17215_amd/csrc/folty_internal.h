@@ -224,10 +224,12 @@ struct Index {
     int64_t P = 0;           // non-empty directed lists
     int64_t sigma_max = 0;
     std::atomic<int64_t> T{-1}; // static triangles (-1 until a query or ensure_tri_base counted them)
-    // tri_base holds per-item triangle offsets; stored (release) after tri_base, T and
-    // one_pass_from are final, so a reader that loads it (acquire) sees them
+    // tri_base holds per-item triangle offsets; stored (release) after tri_base and
+    // T are final, so a reader that loads it (acquire) sees them
     std::atomic<bool> tri_base_ready{false};
-    int64_t one_pass_from = 0;   // with tri_base: single queries of delta >= this filter in one pass
+    // single queries of delta >= this filter in one pass (INT64_MAX: none, until
+    // a query's second filter pass re-enumerated half of the items or triangles)
+    std::atomic<int64_t> one_pass_from{INT64_MAX};
     int64_t W = 0;           // oriented wedges: sum of C(|N+(x)|, 2)
     int64_t probes = 0;      // closing probes the enumeration makes: sum over (u,v) of |N+(v)|
     int32_t NI = 0;          // enumeration items
@@ -272,14 +274,19 @@ struct Index {
 struct Workspace {
     DevBuf count;   // uint32[m]
     DevBuf sv;      // int32[3 x survivors] surviving triangles (oriented edges), in their item's slots
-    DevBuf sw;      // int64[survivors]     test offset of each survivor inside its item
     DevBuf su;      // int32[NI]   survivors per item
     DevBuf wu;      // int64[NI+1] tests per item
     DevBuf wbase;   // int64[NI+1] exclusive offsets of wu
-    DevBuf sbase;   // int64[NI+1] first survivor slot of each item
-    const int64_t *slots = nullptr; // survivor slots of the last filter: sbase or the index's tri_base
+    DevBuf sbase;   // int64[NI+1] exclusive offsets of su: the dense index of each item's first survivor
+    DevBuf tri_it;  // int32[NI+1] triangles per item, from the last counting filter pass
+    DevBuf pieces;  // Piece[]     the temporal step's pieces of survivors with many tests
+    DevBuf gitem;   // int32[]     per group of 64 survivors, the item of its first (sparse slots)
+    const int64_t *slots = nullptr; // first slot of each item's survivors in sv: sbase (dense) or the index's tri_base
     bool emit_timed = false;        // the last filter's second pass is bracketed by ev[6], ev[7]
+    bool counted_items = false;     // tri_it holds every item's triangles (a counting pass ran)
+    const Index *tri_it_of = nullptr; // the index that counting pass enumerated
     int32_t emit_items = 0;         // items the last filter's second pass enumerated again
+    int64_t emit_triangles = 0;     // triangles those items hold
     int32_t filter_passes = 0;      // enumeration passes of the last filter
     DevBuf ncert;   // uint32[2S]
     DevBuf pairs_k; // uint64[2S]
@@ -372,8 +379,13 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws);
 // number of survivor slots; *tests is the test count, or -1 when the one-pass
 // filter left it on the device.  e0, e1 bracket the counting pass.  ss: a run
 // has min(|L1|, |L2|) tests (the smaller-side evaluation), else |L1|.
+// one_pass: write survivors into the per-item triangle slots in one pass (when
+// the index has them), else count first and emit the items with survivors.
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss = false);
+                       hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss, bool one_pass);
+// whether query q on g filters in one pass; with FOLTY_QUERY_ONE_PASS the
+// per-item triangle offsets are made first if missing
+bool use_one_pass(Graph *g, const folty_query &q);
 double ev_ms(hipEvent_t a, hipEvent_t b);
 // The single query with its outputs in the caller's device memory: the sorted
 // pairs (at most pair_cap; FOLTY_EOVERFLOW beyond, with *n_pairs set), and
@@ -412,8 +424,9 @@ void server_destroy(Server *s);
 void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s);
 void ensure_tri_base(Index &ix, hipStream_t s); // caller holds Graph::lazy_mu once the graph is shared
 void ensure_triangles(Graph *g);                 // ensure_tri_base on the graph's stream, under lazy_mu
-// after a two-pass filter that enumerated most items a second time (a wide
-// window), make the per-item triangle offsets so later queries filter in one pass
+// after a two-pass filter whose second pass enumerated half of the items or of
+// the triangles again (a wide window), make the per-item triangle offsets (from
+// the counting pass's per-item triangles) so later wide queries filter in one pass
 void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta);
 
 // library-primitive wrappers (rocPRIM through hipCUB), all on `stream`

@@ -316,13 +316,17 @@ unsigned enum_grid(int32_t n) {
 // instead.  e0 and e1 bracket the (first) enumeration launch alone, so its
 // duration is measured on the stream it runs on.  Returns the number of
 // survivors (an upper bound in the one-pass case); *tri gets the triangle count.
-// the items with at least one survivor (any order: each item writes its own slots)
-__global__ void k_item_list(const int32_t *__restrict__ su, int32_t NI, int32_t *__restrict__ list,
-                            int32_t *__restrict__ nlist) {
+// the items with at least one survivor (any order: each item writes its own
+// slots), and the triangles those items hold
+__global__ void k_item_list(const int32_t *__restrict__ su, const int32_t *__restrict__ tri_it, int32_t NI,
+                            int32_t *__restrict__ list, int32_t *__restrict__ nlist,
+                            unsigned long long *__restrict__ tri_listed) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool take = it < NI && su[it] > 0;
     const int32_t slot = wave_append(nlist, take);
     if (take) list[slot] = (int32_t)it;
+    const int64_t t = wave_inclusive_sum((int64_t)(take ? tri_it[it] : 0));
+    if (lane_id() == 63 && t > 0) atomicAdd(tri_listed, (unsigned long long)t);
 }
 
 } // namespace
@@ -330,13 +334,16 @@ __global__ void k_item_list(const int32_t *__restrict__ su, int32_t NI, int32_t 
 namespace {
 template <bool SS>
 int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                         hipEvent_t e1, int64_t *tri, int64_t *tests) {
+                         hipEvent_t e1, int64_t *tri, int64_t *tests, bool one_pass) {
     *tests = -1; // known on the host only after the two-pass filter
     ws.emit_timed = false;
     ws.emit_items = 0;
+    ws.emit_triangles = 0;
+    ws.counted_items = false;
     ws.filter_passes = 1;
     const int32_t NI = ix.NI;
     ws.su.ensure(4 * ((size_t)NI + 1));
+    ws.tri_it.ensure(4 * ((size_t)NI + 1));
     ws.wu.ensure(8 * ((size_t)NI + 1));
     ws.wbase.ensure(8 * ((size_t)NI + 1));
     ws.sbase.ensure(8 * ((size_t)NI + 1));
@@ -353,10 +360,11 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
         sink.dq = range_slack(dmax, ix.tshift);
         sink.variant = variant;
         sink.sv = ws.sv.as<int32_t>();
-        sink.sw = ws.sw.as<int64_t>();
+        sink.sw = nullptr; // the temporal step finds each survivor's tests itself
         sink.su = ws.su.as<int32_t>();
         sink.wu = ws.wu.as<int64_t>();
         sink.hits = hits;
+        sink.tri_it = ws.tri_it.as<int32_t>();
         return sink;
     };
     // all items, or the nlist items of list
@@ -373,10 +381,9 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
     using CountM = std::integral_constant<int, FILTER_COUNT>;
     using EmitM = std::integral_constant<int, FILTER_EMIT>;
     using BothM = std::integral_constant<int, FILTER_BOTH>;
-    if (ix.tri_base_ready.load(std::memory_order_acquire) && dmax >= ix.one_pass_from) {
+    if (one_pass && ix.tri_base_ready.load(std::memory_order_acquire)) {
         // per-item triangle offsets exist: one pass writes survivors into them
         ws.sv.ensure(12 * (size_t)ix.T + 12);
-        ws.sw.ensure(8 * (size_t)ix.T + 8);
         FOLTY_HIP(hipEventRecord(e0, s));
         dispatch_variant(variant, [&](auto V) {
             auto sink = sink_for(V, BothM{});
@@ -390,14 +397,19 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
             FOLTY_LAUNCHED();
         });
         FOLTY_HIP(hipEventRecord(e1, s));
+        // su[NI] = wu[NI] = 0 so that the exclusive scans leave the totals at [NI]
+        k_fill<int32_t><<<1, 1, 0, s>>>(ws.su.as<int32_t>() + NI, 0, 1);
         k_fill<int64_t><<<1, 1, 0, s>>>(ws.wu.as<int64_t>() + NI, (int64_t)0, 1);
         FOLTY_LAUNCHED();
-        size_t need = exclusive_scan_i64(nullptr, 0, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
+        size_t need = std::max(
+            exclusive_scan_i64(nullptr, 0, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s),
+            exclusive_scan_i32_to_i64(nullptr, 0, ws.su.as<int32_t>(), ws.sbase.as<int64_t>(), (int64_t)NI + 1, s));
         ws.cub.ensure(need);
         exclusive_scan_i64(ws.cub.p, need, ws.wu.as<int64_t>(), ws.wbase.as<int64_t>(), (int64_t)NI + 1, s);
+        exclusive_scan_i32_to_i64(ws.cub.p, need, ws.su.as<int32_t>(), ws.sbase.as<int64_t>(), (int64_t)NI + 1, s);
         *tri = ix.T;
         ws.slots = ix.tri_base.as<int64_t>();
-        return ix.T; // an upper bound: the temporal kernel reads the exact counts
+        return ix.T; // an upper bound: the temporal step reads the exact count
     }
     ws.slots = ws.sbase.as<int64_t>();
     FOLTY_HIP(hipEventRecord(e0, s));
@@ -415,9 +427,11 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
     exclusive_scan_i32_to_i64(ws.cub.p, need, ws.su.as<int32_t>(), ws.sbase.as<int64_t>(), (int64_t)NI + 1, s);
     // the items with survivors, for the emitting pass
     ws.ilist.ensure(4 * ((size_t)NI + 1));
-    int32_t *nlist = reinterpret_cast<int32_t *>(ws.scal.as<unsigned long long>() + 9);
-    k_fill<int32_t><<<1, 1, 0, s>>>(nlist, 0, 1);
-    k_item_list<<<grid_for(NI, BLK), BLK, 0, s>>>(ws.su.as<int32_t>(), NI, ws.ilist.as<int32_t>(), nlist);
+    unsigned long long *sc = ws.scal.as<unsigned long long>();
+    int32_t *nlist = reinterpret_cast<int32_t *>(sc + 9);
+    k_fill<unsigned long long><<<1, 2, 0, s>>>(sc + 9, 0ull, 2); // nlist, triangles of the listed items
+    k_item_list<<<grid_for(NI, BLK), BLK, 0, s>>>(ws.su.as<int32_t>(), ws.tri_it.as<int32_t>(), NI,
+                                                 ws.ilist.as<int32_t>(), nlist, sc + 10);
     FOLTY_LAUNCHED();
     int64_t *h = ws.host.as<int64_t>();
     h[3] = 0;
@@ -425,19 +439,22 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
     FOLTY_HIP(hipMemcpyAsync(h + 3, nlist, 4, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipMemcpyAsync(h + 1, hits, 8, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipMemcpyAsync(h + 2, ws.wbase.as<int64_t>() + NI, 8, hipMemcpyDeviceToHost, s));
+    FOLTY_HIP(hipMemcpyAsync(h + 4, sc + 10, 8, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
     const int64_t survivors = h[0];
     *tri = h[1];
     *tests = h[2];
+    ws.counted_items = true; // tri_it holds every item's triangles
+    ws.tri_it_of = &ix;
     if (survivors > 0) {
         ws.sv.ensure(12 * (size_t)survivors);
-        ws.sw.ensure(8 * (size_t)survivors);
         const int32_t nl = (int32_t)h[3];
         FOLTY_HIP(hipEventRecord(ws.ev[6], s));
         dispatch_variant(variant, [&](auto V) { run(V, EmitM{}, ws.ilist.as<int32_t>(), nl); });
         FOLTY_HIP(hipEventRecord(ws.ev[7], s));
         ws.emit_timed = true;
         ws.emit_items = nl;
+        ws.emit_triangles = h[4];
         ws.filter_passes = 2;
     }
     return survivors;
@@ -445,34 +462,30 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
 } // namespace
 
 int64_t find_survivors(const Index &ix, int variant, int64_t dmax, Workspace &ws, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss) {
-    return ss ? find_survivors_t<true>(ix, variant, dmax, ws, s, e0, e1, tri, tests)
-              : find_survivors_t<false>(ix, variant, dmax, ws, s, e0, e1, tri, tests);
+                       hipEvent_t e1, int64_t *tri, int64_t *tests, bool ss, bool one_pass) {
+    return ss ? find_survivors_t<true>(ix, variant, dmax, ws, s, e0, e1, tri, tests, one_pass)
+              : find_survivors_t<false>(ix, variant, dmax, ws, s, e0, e1, tri, tests, one_pass);
+}
+
+bool use_one_pass(Graph *g, const folty_query &q) {
+    if (q.flags & FOLTY_QUERY_ONE_PASS) {
+        ensure_triangles(g);
+        return true;
+    }
+    return q.delta >= g->ix.one_pass_from.load(std::memory_order_relaxed);
 }
 
 namespace {
 
-// tests < 0: unknown on the host, the full persistent grid; else a thread per
-// chunk up to that grid.  Chunks of one test by default: neighbouring lanes then
-// take neighbouring edges of one run, so a wavefront's searches read the same
-// lists (70M-edge graph at one year, 36.8M tests, 2.6 per surviving triangle:
-// 10.2 ms at one test per chunk, 12.0 at 8, 13.9 at 32).  Long runs of cheap
-// tests (many tests per survivor) pay the chunk's item and survivor searches
-// per test instead, and take IPT tests per chunk (a skewed graph with 50 and
-// 5,000 tests per survivor: 2.4 -> 3.4 ms and 0.7 -> 2.4 ms at one test).
+// per-edge counts of the survivors' runs (a.6)
 template <class Op, bool SS = false>
-void launch_temporal(const Index &ix, int variant, int64_t dmax, const Workspace &ws, const Op &op, int64_t tests,
+void launch_temporal(const Index &ix, int variant, int64_t dmax, Workspace &ws, const Op &op, int64_t tests,
                      int64_t survivors, hipStream_t s) {
-    const int ipt = tests >= (int64_t)PERSIST_BLOCKS * BLK && tests >= 16 * survivors ? IPT : 1;
-    const int64_t want = tests < 0 ? PERSIST_BLOCKS : ((tests + ipt - 1) / ipt + BLK - 1) / BLK;
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PERSIST_BLOCKS));
+    const uint32_t dq = run_slack(range_slack(dmax, ix.tshift));
     dispatch_variant(variant, [&](auto V) {
-        k_temporal<decltype(V)::value, Op, SS><<<blocks, BLK, 0, s>>>(
-            ws.wbase.as<int64_t>(), ix.NI, ws.slots, ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
-            ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(), ix.ts.as<int64_t>(),
-            run_slack(range_slack(dmax, ix.tshift)), op, ipt);
+        launch_tests(ix, ws, CountRunner<decltype(V)::value, Op, SS>{dq, ix.ts.as<int64_t>(), op}, survivors, tests,
+                     s);
     });
-    FOLTY_LAUNCHED();
 }
 
 // threshold + pairs for one query given device counts (sorted edge order)
@@ -760,26 +773,18 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     }
 }
 
-// triangles of each enumeration item, their exclusive offsets (the slots of a
-// one-pass filter and of the cached list) and the triangle count
-void ensure_tri_base(Index &ix, hipStream_t s) {
-    if (ix.tri_base_ready.load(std::memory_order_acquire)) return;
+
+// per-item triangle offsets from per-item triangle counts tri_it[0, NI) (the
+// counting filter's, or a CountSink pass); tri_it[NI] is set to 0 here
+static void tri_base_from_counts(Index &ix, int32_t *tri_it, hipStream_t s) {
     const int32_t ni = ix.NI;
     ix.tri_base.ensure(8 * ((size_t)ni + 1));
-    DevBuf tri_it, cub;
-    tri_it.ensure(4 * ((size_t)ni + 1));
-    k_fill<int32_t><<<1, 1, 0, s>>>(tri_it.as<int32_t>() + ni, 0, 1);
+    DevBuf cub;
+    k_fill<int32_t><<<1, 1, 0, s>>>(tri_it + ni, 0, 1);
     FOLTY_LAUNCHED();
-    if (ni > 0) {
-        CountSink cs{tri_it.as<int32_t>(), 0};
-        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(),
-                                                 ix.seg.as<int4>(), ni, cs);
-        FOLTY_LAUNCHED();
-    }
-    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(),
-                                            (int64_t)ni + 1, s);
+    size_t need = exclusive_scan_i32_to_i64(nullptr, 0, tri_it, ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
     cub.ensure(need);
-    exclusive_scan_i32_to_i64(cub.p, need, tri_it.as<int32_t>(), ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
+    exclusive_scan_i32_to_i64(cub.p, need, tri_it, ix.tri_base.as<int64_t>(), (int64_t)ni + 1, s);
     int64_t T = 0;
     FOLTY_HIP(hipMemcpyAsync(&T, ix.tri_base.as<int64_t>() + ni, 8, hipMemcpyDeviceToHost, s));
     FOLTY_HIP(hipStreamSynchronize(s));
@@ -787,34 +792,57 @@ void ensure_tri_base(Index &ix, hipStream_t s) {
     ix.tri_base_ready.store(true, std::memory_order_release);
 }
 
-// The two-pass filter enumerates the items with survivors a second time; at a
-// wide window that costs about as much as the first pass (70M edges, one year:
-// 7.1 ms on top of the 6.9 ms counting pass).  When at least half of the items
-// had survivors (items hold about the same number of probes, so the second pass
-// then costs at least half the first), per-item triangle offsets (one counting
-// enumeration, once per graph) let later queries write survivors into per-item
-// slots in a single pass, at 20 bytes of workspace per static triangle; that is
-// done when it fits in a quarter of the free device memory.  The rule depends
-// only on the graph and the query, so a graph's code path does not depend on
-// timing.  Windows well below the one that met it (under an eighth of it) keep
-// the two passes: their second pass is short, and the one pass writes into slots
-// sized for every triangle (70M edges: 5.4-5.6 ms for one pass against 5.0-5.2 ms
-// for the counting pass at 1 hour and 1 day).
+// triangles of each enumeration item, their exclusive offsets (the slots of a
+// one-pass filter and of the cached list) and the triangle count
+void ensure_tri_base(Index &ix, hipStream_t s) {
+    if (ix.tri_base_ready.load(std::memory_order_acquire)) return;
+    const int32_t ni = ix.NI;
+    DevBuf tri_it;
+    tri_it.ensure(4 * ((size_t)ni + 1));
+    if (ni > 0) {
+        CountSink cs{tri_it.as<int32_t>(), 0};
+        k_tri_enum<<<enum_grid(ni), BLK, 0, s>>>(ix.item.as<EnumItem>(), ix.oadj.as<int32_t>(),
+                                                 ix.seg.as<int4>(), ni, cs);
+        FOLTY_LAUNCHED();
+    }
+    tri_base_from_counts(ix, tri_it.as<int32_t>(), s);
+}
+
+// The two-pass filter enumerates the items with survivors a second time.  At a
+// wide window those are the items that hold most triangles, and the second
+// pass costs about as much as the first (70M edges, one year: 7.1 ms on top of
+// the 6.9 ms counting pass).  When the second pass enumerated at least half of
+// the items or half of the triangles again, later queries of about this window
+// or wider (from an eighth of it) filter in one pass instead, writing survivors
+// into per-item triangle slots: 12 bytes of workspace per static triangle, so
+// only when that fits in a quarter of the free device memory.  The offsets come
+// from the counting pass's per-item triangle counts (no extra enumeration).
+// The rule depends only on the graph and the queries, never on timing.  Narrow
+// windows keep the two passes: their second pass is short, and the one pass
+// writes into slots sized for every triangle (70M edges: 5.4-5.6 ms for one
+// pass against 5.0-5.2 ms for the counting pass at 1 hour and 1 day).
 void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta) {
     Index &ix = g->ix;
-    if (ix.tri_base_ready.load(std::memory_order_acquire) || !ws.emit_timed || ix.T <= 0) return;
-    if (2 * (int64_t)ws.emit_items < (int64_t)ix.NI) return;
+    if (!ws.emit_timed || !ws.counted_items || ws.tri_it_of != &ix || ix.T <= 0) return;
+    if (2 * (int64_t)ws.emit_items < (int64_t)ix.NI && 2 * ws.emit_triangles < ix.T) return;
+    if (delta / 8 >= ix.one_pass_from.load(std::memory_order_relaxed)) return;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
         (void)hipGetLastError();
         return;
     }
-    if ((size_t)ix.T * 20 > fr / 4) return;
-    {
-        std::lock_guard<std::mutex> lk(g->lazy_mu);
-        if (!ix.tri_base_ready.load(std::memory_order_acquire)) ix.one_pass_from = delta / 8;
+    if (!ix.tri_base_ready.load(std::memory_order_acquire) && (size_t)ix.T * 12 > fr / 4) return;
+    std::lock_guard<std::mutex> lk(g->lazy_mu);
+    if (!ix.tri_base_ready.load(std::memory_order_acquire)) {
+        FOLTY_HIP(hipSetDevice(g->device));
+        StreamScope sc(g->stream);
+        HookScope hs(&g->hook);
+        // the counting pass left its per-item triangles in the workspace, on a
+        // stream the caller has synchronised
+        tri_base_from_counts(ix, ws.tri_it.as<int32_t>(), g->stream);
     }
-    ensure_triangles(g);
+    if (delta / 8 < ix.one_pass_from.load(std::memory_order_relaxed))
+        ix.one_pass_from.store(delta / 8, std::memory_order_relaxed);
 }
 
 void ensure_triangles(Graph *g) {
@@ -850,7 +878,7 @@ void check_query(const Graph *g, const folty_query &q) {
     if (q.exclude_other > 1) fail(FOLTY_EINVAL, "exclude_other must be 0 or 1");
     if (q.exclude_other && q.universe == FOLTY_UNIVERSE_COMMON)
         fail(FOLTY_EINVAL, "exclude_other applies to the N(a) and N(b) universes only");
-    if (q.flags & ~(FOLTY_QUERY_NO_COUNTS | FOLTY_QUERY_SMALLER_SIDE))
+    if (q.flags & ~(FOLTY_QUERY_NO_COUNTS | FOLTY_QUERY_SMALLER_SIDE | FOLTY_QUERY_ONE_PASS))
         fail(FOLTY_EINVAL, "unknown query flags 0x%x", (unsigned)q.flags);
 }
 
@@ -901,7 +929,9 @@ static const uint32_t *query_counts(Graph *g, const folty_query &q, Workspace &w
     if (ix.NI > 0) {
         int64_t known = -1;
         const bool ss = (q.flags & FOLTY_QUERY_SMALLER_SIDE) != 0;
-        const int64_t survivors = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known, ss);
+        const bool one = use_one_pass(g, q);
+        const int64_t survivors =
+            find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known, ss, one);
         if (survivors > 0) {
             if (ss) {
                 // runs with a shorter L2 mark edge ranges in diff; its prefix sum is added at the end
@@ -942,6 +972,9 @@ void run_query_into(Graph *g, const folty_query &q, Workspace &ws, int32_t *pair
     if (q.universe == FOLTY_UNIVERSE_COMMON && !ix.tcnt_ready)
         fail(FOLTY_EINVAL, "the universe N(a) & N(b) needs the graph's per-edge triangle counts, which this call "
                            "does not build: run one query with that universe through folty_run_fol_query first");
+    if ((q.flags & FOLTY_QUERY_ONE_PASS) && !ix.tri_base_ready.load(std::memory_order_acquire))
+        fail(FOLTY_EINVAL, "FOLTY_QUERY_ONE_PASS needs the graph's per-item triangle offsets, which this call does "
+                           "not build: run one query with that flag through folty_run_fol_query first");
     hipStream_t s = g->stream;
     int64_t tests = 0;
     const uint32_t *count = query_counts(g, q, ws, s, &tests);
@@ -1004,7 +1037,10 @@ static Result *run_query_impl(Graph *g, const folty_query &q, Workspace &ws, hip
 int64_t query_footprint(const Graph *g, const folty_query &q) {
     const Index &ix = g->ix;
     const int64_t T = std::max<int64_t>(0, ix.T.load());
-    int64_t b = 4 * (int64_t)ix.m + 32 * ((int64_t)ix.NI + 1) + 20 * T + 56 * (int64_t)ix.S;
+    // counts; per item su, tri_it, wu, wbase, sbase, ilist; survivors and their
+    // groups; pieces; pair step
+    int64_t b = 4 * (int64_t)ix.m + 36 * ((int64_t)ix.NI + 1) + 12 * T + 4 * (T / 64 + 3) +
+                (int64_t)sizeof(Piece) * piece_slots(T, -1) + 56 * (int64_t)ix.S;
     if (q.flags & FOLTY_QUERY_SMALLER_SIDE) b += 8 * (int64_t)ix.m + 4;
     if (!(q.flags & FOLTY_QUERY_NO_COUNTS)) b += 4 * ix.m_input;
     return b + (1 << 20);
@@ -1035,16 +1071,16 @@ Workspace::~Workspace() {
 }
 
 size_t Workspace::device_bytes() const {
-    const DevBuf *b[] = {&count, &sv, &sw, &su, &wu, &wbase, &sbase, &ncert, &pairs_k, &pairs_v, &pairs_k2,
-                         &pairs_v2, &scal, &cub, &ilist, &vtmp, &diff, &tflag, &tinst};
+    const DevBuf *b[] = {&count, &sv, &su, &wu, &wbase, &sbase, &tri_it, &pieces, &gitem, &ncert, &pairs_k, &pairs_v,
+                         &pairs_k2, &pairs_v2, &scal, &cub, &ilist, &vtmp, &diff, &tflag, &tinst};
     size_t t = 0;
     for (auto *x : b) t += x->bytes;
     return t;
 }
 
 void Workspace::forget_buffers() {
-    DevBuf *b[] = {&count, &sv, &sw, &su, &wu, &wbase, &sbase, &ncert, &pairs_k, &pairs_v, &pairs_k2,
-                   &pairs_v2, &scal, &cub, &ilist, &vtmp, &diff, &tflag, &tinst};
+    DevBuf *b[] = {&count, &sv, &su, &wu, &wbase, &sbase, &tri_it, &pieces, &gitem, &ncert, &pairs_k, &pairs_v,
+                   &pairs_k2, &pairs_v2, &scal, &cub, &ilist, &vtmp, &diff, &tflag, &tinst};
     for (auto *x : b) x->forget();
 }
 

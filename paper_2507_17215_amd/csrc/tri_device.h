@@ -3,6 +3,8 @@
 // tests.  See query.hip for what each step computes and where the paper says so.
 #pragma once
 
+#include <cstdlib>
+
 #include "folty_internal.h"
 
 namespace folty {
@@ -11,7 +13,6 @@ namespace {
 constexpr int BLK = 256;
 constexpr int WPB = BLK / 64;         // wavefronts per block
 constexpr int CAP = 512;              // N+(u) staged in LDS up to this length
-constexpr int IPT = 8;                // tests per chunk of the first-hit search of exists-exists-exists
 constexpr int PERSIST_BLOCKS = 4096;
 constexpr int ENUM_BLOCKS = 32768; // 8 x the resident blocks: about a dozen items per wavefront, balanced by the dispatcher
 constexpr int32_t CHUNK = 4096;       // closing probes per enumeration item (about; whole segments)
@@ -420,12 +421,14 @@ template <int VAR, int MODE, bool SS = false> struct FilterSink {
     int64_t dq;       // range_slack(dmax, shift)
     int variant;
     int32_t *sv;      // EMIT, BOTH: survivors (three oriented edges each)
-    int64_t *sw;      // EMIT, BOTH: test offset of each survivor inside its item
+    int64_t *sw;      // EMIT, BOTH: test offset of each survivor inside its item (null: not kept)
     int32_t *su;      // COUNT, BOTH: survivors per item
     int64_t *wu;      // COUNT, BOTH: tests per item
     unsigned long long *hits; // COUNT: triangles seen (added once per wavefront)
+    int32_t *tri_it;  // COUNT: triangles of each item (null: not kept)
     int64_t slot;
     int32_t ns;
+    int32_t nt;
     int64_t work;
     unsigned long long nhit;
     uint2 pra, prk; // ranges of edge (x0, x1) and of the known one of (x0, x2) / (x1, x2)
@@ -440,10 +443,11 @@ template <int VAR, int MODE, bool SS = false> struct FilterSink {
     __device__ void begin(int64_t it) {
         if constexpr (MODE != FILTER_COUNT) slot = base[it];
         ns = 0;
+        nt = 0;
         work = 0;
     }
     __device__ void hit(bool h, int32_t a, int32_t b, int32_t c) {
-        if constexpr (MODE == FILTER_COUNT) nhit += (unsigned long long)__popcll(__ballot(h));
+        if constexpr (MODE == FILTER_COUNT) nt += (int32_t)__popcll(__ballot(h));
         int64_t wk = 0;
         // the two ranges loaded ahead first; the third edge's only if they meet
         if (h && ranges_meet(pra, prk, dq)) {
@@ -463,7 +467,7 @@ template <int VAR, int MODE, bool SS = false> struct FilterSink {
                 sv[3 * pos] = a;
                 sv[3 * pos + 1] = b;
                 sv[3 * pos + 2] = c;
-                sw[pos] = work + incl - wk;
+                if (sw) sw[pos] = work + incl - wk;
             }
         }
         ns += (int32_t)__popcll(mask);
@@ -475,6 +479,10 @@ template <int VAR, int MODE, bool SS = false> struct FilterSink {
                 su[it] = ns;
                 wu[it] = work;
             }
+        }
+        if constexpr (MODE == FILTER_COUNT) {
+            nhit += (unsigned long long)nt;
+            if (tri_it && lane_id() == 0) tri_it[it] = nt;
         }
     }
     __device__ void finish() {
@@ -887,50 +895,275 @@ __device__ inline void chunk_runs_rt(int variant, const TriLists &L, uint32_t dq
 }
 
 // ---------------------------------------------------------------------------
-// a.6: temporal tests over the surviving runs, flat chunks of ipt tests
+// a.6: scheduling the tests of the surviving triangles
 // ---------------------------------------------------------------------------
-template <int VAR, class Op, bool SS = false>
-__global__ __launch_bounds__(BLK) void k_temporal(const int64_t *__restrict__ wbase, int32_t NI,
-                                                  const int64_t *__restrict__ base, const int32_t *__restrict__ su,
-                                                  const int32_t *__restrict__ sv, const int64_t *__restrict__ sw,
-                                                  const EdgeRec *__restrict__ rec, const int64_t *__restrict__ ts,
-                                                  uint32_t dq, Op op, int ipt) {
-    const int64_t total = wbase[NI];
-    const int64_t nchunks = (total + ipt - 1) / ipt;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
-        int64_t k = c * ipt;
-        const int64_t k1 = k + ipt < total ? k + ipt : total;
-        while (k < k1) {
-            const int64_t k_start = k;
-            // the item whose tests contain k, then the survivor inside it
-            int64_t a = 0, b = NI;
-            while (a < b) {
-                int64_t mid = (a + b) >> 1;
-                if (wbase[mid + 1] <= k) a = mid + 1;
-                else b = mid;
+// Survivors are reached through a dense index q in [0, sbase[NI]): item u holds
+// q in [sbase[u], sbase[u + 1]), at slots slot_base[u] + (q - sbase[u]) of the
+// filter's output (slot_base null: the slots are dense, slot = q).  A wavefront
+// takes a group of 64 consecutive survivors, one per lane.  A survivor with at
+// most LIGHT_TESTS tests is run by the group; one with more is cut into pieces
+// of PIECE_TESTS, appended to a list that a second kernel runs one piece per
+// thread, each piece starting its L2 and L3 cursors with one binary search (the
+// merge-path split of a long run over neighbouring threads).  No test pays a
+// search over items or survivors.  Pieces past the list's capacity run where
+// they were cut, so any capacity gives the same result.
+//
+// How a group runs its light tests depends on the runner.  Flat runners (the
+// per-edge counts): the lanes stage their survivors' six list spans in LDS, and
+// the group's tests, concatenated, go one per lane, so neighbouring lanes take
+// neighbouring tests of one run and their loads coalesce; each test finds its
+// survivor by a search over 64 prefix sums in LDS and its cursors by binary
+// search.  Other runners (the exists-exists-exists counting, whose window
+// bookkeeping is shared by the tests of a run): each lane runs its own
+// survivor's tests in order.
+constexpr int64_t LIGHT_TESTS = 16;
+constexpr int64_t PIECE_TESTS = 32;
+
+struct Piece {
+    int64_t slot; // survivor slot
+    int64_t k0;   // first test of the piece among the survivor's tests
+};
+
+// the largest u in [a, b) with sbase[u] <= q (sbase ascending, sbase[a] <= q)
+__device__ inline int32_t item_of(const int64_t *__restrict__ sbase, int32_t a, int32_t b, int64_t q) {
+    int32_t lo = a, hi = b - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (sbase[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// For sparse slots: gitem[g] = the item of survivor 64 g, for every group g
+// with 64 g < sbase[NI], and gitem[g] = NI - 1 for the group past the last.
+__global__ __launch_bounds__(BLK) void k_group_items(const int64_t *__restrict__ sbase, int32_t NI, int64_t ngroups,
+                                                     int32_t *__restrict__ gitem) {
+    const int64_t nsurv = sbase[NI];
+    for (int64_t g = (int64_t)blockIdx.x * BLK + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * BLK) {
+        const int64_t q0 = g * 64;
+        if (q0 >= nsurv) {
+            if (q0 - 64 < nsurv) gitem[g] = NI - 1;
+            break;
+        }
+        gitem[g] = item_of(sbase, 0, NI, q0);
+    }
+}
+
+// The survivor slot of dense index q in group g (q < sbase[NI]).
+__device__ inline int64_t survivor_slot(const int64_t *__restrict__ sbase, const int64_t *__restrict__ slot_base,
+                                        const int32_t *__restrict__ gitem, int64_t g, int64_t q) {
+    if (!slot_base) return q;
+    const int32_t u = item_of(sbase, gitem[g], gitem[g + 1] + 1, q);
+    return slot_base[u] + (q - sbase[u]);
+}
+
+// list index of E_{x_a, x_b} in TriLists order (d01, d10, d02, d20, d12, d21)
+constexpr int list_id(int a, int b) { return a == 0 ? (b == 1 ? 0 : 2) : a == 1 ? (b == 0 ? 1 : 4) : (b == 0 ? 3 : 5); }
+
+// One light group's survivors in LDS: start and length of each directed list,
+// the runs that can count (bit k: run k in the order of chunk_runs), and the
+// inclusive prefix of the survivors' tests.
+struct FlatLds {
+    int32_t incl[64];
+    int32_t ls[6][64];
+    int32_t ln[6][64];
+    uint32_t live[64];
+};
+
+// run k = (I, J) of survivor si holds test r (r < that run's tests): run it
+template <int VAR, int I, int J, bool SS, class Op>
+__device__ inline bool flat_run(const FlatLds &F, int si, int k, int64_t &r, const int64_t *__restrict__ ts,
+                                const Op &op) {
+    if (!((F.live[si] >> k) & 1u)) return false;
+    using P = Pick<VAR, I, J>;
+    constexpr int i1 = list_id(I, J), i2 = list_id(P::L2a, P::L2b), i3 = list_id(P::L3a, P::L3b);
+    const int32_t n1 = F.ln[i1][si], n2 = F.ln[i2][si];
+    const int32_t nt = SS && n2 < n1 ? n2 : n1;
+    if (r >= nt) {
+        r -= nt;
+        return false;
+    }
+    Span l1, l2, l3;
+    l1.s = F.ls[i1][si];
+    l1.n = n1;
+    l2.s = F.ls[i2][si];
+    l2.n = n2;
+    l3.s = F.ls[i3][si];
+    l3.n = F.ln[i3][si];
+    if (SS && nt < n1) op.iv(ts, l1, (int32_t)r, 1, l2, l3);
+    else op(ts, l1.s + (int32_t)r, 1, l2, l3);
+    return true;
+}
+
+// Runs the tests of the per-edge counts: work() is the survivor's number of
+// tests, run() takes tests [r, k1) of it in order, flat() its test r alone.
+template <int VAR, class Op, bool SS> struct CountRunner {
+    static constexpr bool kFlat = true;
+    uint32_t dq;
+    const int64_t *ts;
+    Op op;
+    __device__ inline int64_t work(const TriLists &L) const { return tri_work<VAR, SS>(L, dq); }
+    __device__ inline void run(const TriLists &L, int64_t, int64_t r, int64_t k1) {
+        int64_t k = r;
+        chunk_runs<VAR, Op, SS>(L, dq, ts, r, k, k1, op);
+    }
+    // the runs that can count, as bits in the order of chunk_runs
+    __device__ inline uint32_t live(const TriLists &L) const {
+        Span a, b, c;
+        return (uint32_t)run_lists<VAR, 0, 1>(L, dq, a, b, c) | (uint32_t)run_lists<VAR, 1, 0>(L, dq, a, b, c) << 1 |
+               (uint32_t)run_lists<VAR, 0, 2>(L, dq, a, b, c) << 2 | (uint32_t)run_lists<VAR, 2, 0>(L, dq, a, b, c) << 3 |
+               (uint32_t)run_lists<VAR, 1, 2>(L, dq, a, b, c) << 4 | (uint32_t)run_lists<VAR, 2, 1>(L, dq, a, b, c) << 5;
+    }
+    __device__ inline void flat(const FlatLds &F, int si, int64_t r) const {
+        flat_run<VAR, 0, 1, SS>(F, si, 0, r, ts, op) || flat_run<VAR, 1, 0, SS>(F, si, 1, r, ts, op) ||
+            flat_run<VAR, 0, 2, SS>(F, si, 2, r, ts, op) || flat_run<VAR, 2, 0, SS>(F, si, 3, r, ts, op) ||
+            flat_run<VAR, 1, 2, SS>(F, si, 4, r, ts, op) || flat_run<VAR, 2, 1, SS>(F, si, 5, r, ts, op);
+    }
+    __device__ inline void finish() {}
+};
+
+// the pieces of this lane's survivor (np > 0: a heavy one), reserved for the
+// whole wavefront at once; those past the capacity run here
+template <class R>
+__device__ inline void cut_pieces(R &runner, const TriLists &L, int64_t slot, int64_t w, int64_t np,
+                                  Piece *__restrict__ pieces, unsigned long long *__restrict__ npieces, int64_t cap) {
+    if (!__ballot(np > 0)) return;
+    const int64_t incl = wave_inclusive_sum(np);
+    unsigned long long at = 0;
+    if (lane_id() == 63) at = atomicAdd(npieces, (unsigned long long)incl);
+    const int64_t first = (int64_t)__shfl((long long)at, 63) + incl - np;
+    for (int64_t i = 0; i < np; i++) {
+        const int64_t k0 = i * PIECE_TESTS;
+        if (first + i < cap) pieces[first + i] = Piece{slot, k0};
+        else runner.run(L, slot, k0, k0 + PIECE_TESTS < w ? k0 + PIECE_TESTS : w);
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(BLK) void k_tests_light(const int64_t *__restrict__ sbase,
+                                                     const int64_t *__restrict__ slot_base,
+                                                     const int32_t *__restrict__ gitem, int32_t NI,
+                                                     const int32_t *__restrict__ sv, const EdgeRec *__restrict__ rec,
+                                                     R runner, Piece *__restrict__ pieces,
+                                                     unsigned long long *__restrict__ npieces, int64_t cap) {
+    __shared__ FlatLds flds[R::kFlat ? WPB : 1];
+    const int w = wave_id();
+    const int lane = lane_id();
+    const int64_t nsurv = sbase[NI];
+    const int64_t ng = (nsurv + 63) / 64;
+    for (int64_t g = (int64_t)blockIdx.x * WPB + w; g < ng; g += (int64_t)gridDim.x * WPB) {
+        const int64_t q = g * 64 + lane;
+        const bool on = q < nsurv;
+        int64_t slot = 0, wk = 0, np = 0;
+        TriLists L{};
+        if (on) {
+            slot = survivor_slot(sbase, slot_base, gitem, g, q);
+            L = load_lists(rec, sv[3 * slot], sv[3 * slot + 1], sv[3 * slot + 2]);
+            wk = runner.work(L);
+            if (wk > LIGHT_TESTS) np = (wk + PIECE_TESTS - 1) / PIECE_TESTS;
+        }
+        cut_pieces(runner, L, slot, wk, np, pieces, npieces, cap);
+        const int64_t light = np ? 0 : wk;
+        if constexpr (R::kFlat) {
+            FlatLds &F = flds[w];
+            const int32_t incl = (int32_t)wave_inclusive_sum(light);
+            const int32_t total = __shfl(incl, 63);
+            if (total == 0) continue;
+            F.incl[lane] = incl;
+            const TriLists &T = L;
+            F.ls[0][lane] = T.d01.s, F.ln[0][lane] = T.d01.n;
+            F.ls[1][lane] = T.d10.s, F.ln[1][lane] = T.d10.n;
+            F.ls[2][lane] = T.d02.s, F.ln[2][lane] = T.d02.n;
+            F.ls[3][lane] = T.d20.s, F.ln[3][lane] = T.d20.n;
+            F.ls[4][lane] = T.d12.s, F.ln[4][lane] = T.d12.n;
+            F.ls[5][lane] = T.d21.s, F.ln[5][lane] = T.d21.n;
+            F.live[lane] = light ? runner.live(L) : 0u;
+            wave_sync();
+            for (int32_t t = lane; t < total; t += 64) {
+                // the survivor whose tests hold t: the first si with incl[si] > t
+                int a = 0, b = 63;
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (F.incl[mid] > t) b = mid;
+                    else a = mid + 1;
+                }
+                runner.flat(F, a, (int64_t)(t - (a ? F.incl[a - 1] : 0)));
             }
-            const int64_t u = a;
-            int64_t r = k - wbase[u];
-            const int64_t s0 = base[u];
-            const int32_t ns = su[u];
-            if (ns <= 0) break; // cannot happen when the offsets are consistent
-            int32_t lo = 0, hi = ns - 1;
-            while (lo < hi) {
-                int32_t mid = (lo + hi + 1) >> 1;
-                if (sw[s0 + mid] <= r) lo = mid;
-                else hi = mid - 1;
-            }
-            r -= sw[s0 + lo];
-            for (int32_t s = lo; s < ns && k < k1; s++) {
-                const int64_t p = s0 + s;
-                TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
-                chunk_runs<VAR, Op, SS>(L, dq, ts, r, k, k1, op);
-                r = 0;
-            }
-            if (k == k_start) break; // every survivor has tests, so this never triggers
+            wave_sync(); // the LDS is rewritten by the next group
+        } else {
+            if (light) runner.run(L, slot, 0, light);
         }
     }
+    runner.finish();
+}
+
+template <class R>
+__global__ __launch_bounds__(BLK) void k_tests_pieces(const Piece *__restrict__ pieces,
+                                                      const unsigned long long *__restrict__ npieces, int64_t cap,
+                                                      const int32_t *__restrict__ sv,
+                                                      const EdgeRec *__restrict__ rec, R runner) {
+    const int64_t n = (int64_t)*npieces < cap ? (int64_t)*npieces : cap;
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+        const Piece pc = pieces[i];
+        const TriLists L = load_lists(rec, sv[3 * pc.slot], sv[3 * pc.slot + 1], sv[3 * pc.slot + 2]);
+        runner.run(L, pc.slot, pc.k0, pc.k0 + PIECE_TESTS);
+    }
+    runner.finish();
+}
+
+constexpr int64_t MAX_PIECES = 1 << 22; // 64 MB of pieces at most; the rest run where they are cut
+constexpr int64_t MIN_PIECES = 1 << 16; // room for this many whatever the survivors
+constexpr int64_t LIGHT_BLOCKS = 16384;
+constexpr int64_t PIECE_BLOCKS = 8192;
+
+// the piece list's capacity limit: MAX_PIECES, or FOLTY_MAX_PIECES (>= 1) when set
+inline int64_t max_pieces() {
+    static const int64_t v = [] {
+        const char *e = getenv("FOLTY_MAX_PIECES");
+        const long long x = e ? atoll(e) : 0;
+        return x >= 1 ? (int64_t)x : MAX_PIECES;
+    }();
+    return v;
+}
+
+// Pieces a query's list holds: no more than its tests can fill (when known), and
+// at most one per survivor (at least MIN_PIECES, at most the limit), so that
+// 16 * piece_slots(T, -1) bounds the list's memory on a graph of T triangles.
+inline int64_t piece_slots(int64_t survivors, int64_t tests) {
+    int64_t b = std::max<int64_t>(survivors + 1, MIN_PIECES);
+    if (tests >= 0) b = std::min<int64_t>(b, tests / PIECE_TESTS + tests / (LIGHT_TESTS + 1) + 1);
+    return std::max<int64_t>(1, std::min<int64_t>(b, max_pieces()));
+}
+
+// The tests of the survivors of the last filter (see k_tests_light): survivors is
+// their number, or an upper bound when the filter ran in one pass; tests is
+// their number of tests, or < 0 when unknown on the host.
+template <class R>
+void launch_tests(const Index &ix, Workspace &ws, const R &runner, int64_t survivors, int64_t tests, hipStream_t s) {
+    const int64_t cap = piece_slots(survivors, tests);
+    ws.pieces.ensure(sizeof(Piece) * (size_t)cap);
+    ws.scal.ensure(128);
+    unsigned long long *np = ws.scal.as<unsigned long long>() + 14;
+    k_fill<unsigned long long><<<1, 1, 0, s>>>(np, 0ull, 1);
+    FOLTY_LAUNCHED();
+    const int64_t groups = (survivors + 63) / 64; // an upper bound when survivors is one
+    const int64_t *sparse = ws.slots == ws.sbase.as<int64_t>() ? nullptr : ws.slots;
+    if (sparse) {
+        ws.gitem.ensure(4 * ((size_t)groups + 2));
+        const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 1 + BLK - 1) / BLK, LIGHT_BLOCKS));
+        k_group_items<<<gb, BLK, 0, s>>>(ws.sbase.as<int64_t>(), ix.NI, groups + 1, ws.gitem.as<int32_t>());
+        FOLTY_LAUNCHED();
+    }
+    const unsigned lb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + WPB - 1) / WPB, LIGHT_BLOCKS));
+    k_tests_light<<<lb, BLK, 0, s>>>(ws.sbase.as<int64_t>(), sparse, ws.gitem.as<int32_t>(), ix.NI,
+                                     ws.sv.as<int32_t>(), ix.rec.as<EdgeRec>(), runner, ws.pieces.as<Piece>(), np,
+                                     cap);
+    FOLTY_LAUNCHED();
+    const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + BLK - 1) / BLK, PIECE_BLOCKS));
+    k_tests_pieces<<<pb, BLK, 0, s>>>(ws.pieces.as<Piece>(), np, cap, ws.sv.as<int32_t>(), ix.rec.as<EdgeRec>(),
+                                      runner);
+    FOLTY_LAUNCHED();
 }
 
 } // namespace

@@ -136,65 +136,39 @@ __device__ inline void triad_runs(const TriLists &L, uint32_t dq, const int64_t 
         triad_run<VAR, 2, 1, 5, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf);
 }
 
-// The surviving runs' tests in flat chunks of ipt (the chunking of the count
-// kernel); total[0] += temporal triangles, total[1] = 1 on a 64-bit overflow.
-template <int VAR, bool INST>
-__global__ __launch_bounds__(BLK) void k_triad(const int64_t *__restrict__ wbase, int32_t NI,
-                                               const int64_t *__restrict__ base, const int32_t *__restrict__ su,
-                                               const int32_t *__restrict__ sv, const int64_t *__restrict__ sw,
-                                               const EdgeRec *__restrict__ rec, const int64_t *__restrict__ ts,
-                                               uint32_t dq, TriadOut o, int ipt, unsigned long long *total) {
-    const int64_t all = wbase[NI];
-    const int64_t nchunks = (all + ipt - 1) / ipt;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// The surviving runs' tests, scheduled as the count's (k_tests_light, then the
+// pieces of survivors with many tests); total[0] += temporal triangles, total[1]
+// = 1 on a 64-bit overflow.
+template <int VAR, bool INST> struct TriadRunner {
+    static constexpr bool kFlat = false; // a run's tests share their window bookkeeping
+    uint32_t dq;
+    const int64_t *ts;
+    TriadOut o;
+    unsigned long long *total;
     unsigned long long acc = 0;
     bool ovf = false;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
-        int64_t k = c * ipt;
-        const int64_t k1 = k + ipt < all ? k + ipt : all;
-        while (k < k1) {
-            const int64_t k_start = k;
-            int64_t a = 0, b = NI;
-            while (a < b) {
-                int64_t mid = (a + b) >> 1;
-                if (wbase[mid + 1] <= k) a = mid + 1;
-                else b = mid;
+    __device__ inline int64_t work(const TriLists &L) const { return tri_work<VAR, false>(L, dq); }
+    __device__ inline void run(const TriLists &L, int64_t slot, int64_t r, int64_t k1) {
+        int64_t k = r;
+        triad_runs<VAR, INST>(L, dq, ts, r, k, k1, o, slot, acc, ovf);
+    }
+    // every lane of the wavefront calls this once, at the end
+    __device__ inline void finish() {
+        if constexpr (INST) {
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long y = __shfl_xor(acc, off);
+                const int oy = __shfl_xor((int)ovf, off);
+                const unsigned long long s = acc + y;
+                ovf = ovf || oy || s < acc;
+                acc = s;
             }
-            const int64_t u = a;
-            int64_t r = k - wbase[u];
-            const int64_t s0 = base[u];
-            const int32_t ns = su[u];
-            if (ns <= 0) break; // cannot happen when the offsets are consistent
-            int32_t lo = 0, hi = ns - 1;
-            while (lo < hi) {
-                int32_t mid = (lo + hi + 1) >> 1;
-                if (sw[s0 + mid] <= r) lo = mid;
-                else hi = mid - 1;
+            if (lane_id() == 0 && (acc || ovf)) {
+                const unsigned long long old = atomicAdd(&total[0], acc);
+                if (ovf || old + acc < old) atomicOr(&total[1], 1ull);
             }
-            r -= sw[s0 + lo];
-            for (int32_t s = lo; s < ns && k < k1; s++) {
-                const int64_t p = s0 + s;
-                TriLists L = load_lists(rec, sv[3 * p], sv[3 * p + 1], sv[3 * p + 2]);
-                triad_runs<VAR, INST>(L, dq, ts, r, k, k1, o, p, acc, ovf);
-                r = 0;
-            }
-            if (k == k_start) break; // every survivor has tests, so this never triggers
         }
     }
-    if (INST) {
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long y = __shfl_xor(acc, off);
-            const int oy = __shfl_xor((int)ovf, off);
-            const unsigned long long s = acc + y;
-            ovf = ovf || oy || s < acc;
-            acc = s;
-        }
-        if (lane_id() == 0 && (acc || ovf)) {
-            const unsigned long long old = atomicAdd(&total[0], acc);
-            if (ovf || old + acc < old) atomicOr(&total[1], 1ull);
-        }
-    }
-}
+};
 
 // The survivors of item u sit in slots [base[u], base[u] + su[u]): per-item
 // slots of the one-pass filter (sparse over all triangles) or the compact slots
@@ -377,7 +351,8 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
     ws.filter_passes = 0;
     if (ix.NI > 0) {
         int64_t known = -1;
-        slots = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known);
+        const bool one = q.delta >= ix.one_pass_from.load(std::memory_order_relaxed);
+        slots = find_survivors(ix, q.variant, q.delta, ws, s, ws.ev[4], ws.ev[5], &tri, &known, false, one);
         if (slots > 0) {
             const int64_t nw = (slots + 3) / 4;
             ws.tflag.ensure(4 * (size_t)nw);
@@ -386,26 +361,13 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
             FOLTY_LAUNCHED();
             TriadOut o{q.delta, ws.tflag.as<uint32_t>(), edge ? ws.tinst.as<unsigned long long>() : nullptr,
                        ix.perm.as<int32_t>()};
-            // the first-hit search stops early, so longer chunks skip more of a run
-            // (70M edges, one year: 9.8 ms at 8 tests per chunk, 11.5 at one); the
-            // counting of temporal triangles gains from neighbouring lanes on one
-            // run instead (17.3 ms at one test per chunk, 19.8 at 8)
-            const int ipt = inst || (known >= 0 && known < (int64_t)PERSIST_BLOCKS * BLK) ? 1 : IPT;
-            const int64_t want = known < 0 ? PERSIST_BLOCKS : ((known + ipt - 1) / ipt + BLK - 1) / BLK;
-            const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PERSIST_BLOCKS));
             const uint32_t dq = run_slack(range_slack(q.delta, ix.tshift));
             dispatch_variant(q.variant, [&](auto V) {
                 constexpr int VAR = decltype(V)::value;
                 if (inst)
-                    k_triad<VAR, true><<<blocks, BLK, 0, s>>>(ws.wbase.as<int64_t>(), ix.NI, ws.slots,
-                                                             ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
-                                                             ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(),
-                                                             ix.ts.as<int64_t>(), dq, o, ipt, tot);
+                    launch_tests(ix, ws, TriadRunner<VAR, true>{dq, ix.ts.as<int64_t>(), o, tot}, slots, known, s);
                 else
-                    k_triad<VAR, false><<<blocks, BLK, 0, s>>>(ws.wbase.as<int64_t>(), ix.NI, ws.slots,
-                                                              ws.su.as<int32_t>(), ws.sv.as<int32_t>(),
-                                                              ws.sw.as<int64_t>(), ix.rec.as<EdgeRec>(),
-                                                              ix.ts.as<int64_t>(), dq, o, ipt, tot);
+                    launch_tests(ix, ws, TriadRunner<VAR, false>{dq, ix.ts.as<int64_t>(), o, tot}, slots, known, s);
             });
             FOLTY_LAUNCHED();
             k_triad_count<<<grid_for(ix.NI, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), ix.NI,

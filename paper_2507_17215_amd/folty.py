@@ -23,6 +23,7 @@ UNIVERSE_DST, UNIVERSE_SRC, UNIVERSE_COMMON = 0, 1, 2
 RANK_DEGENERACY, RANK_DEGREE, RANK_RANDOM = 0, 1, 2
 QUERY_NO_COUNTS = 1
 QUERY_SMALLER_SIDE = 2
+QUERY_ONE_PASS = 4
 U32_MAX = 0xFFFFFFFF
 
 EXPORTS = (
@@ -225,12 +226,13 @@ def to_theta(theta) -> tuple:
 
 
 def make_query(delta, theta=(1, 2), variant=0, universe=UNIVERSE_DST, exclude_other=False,
-               counts=True, smaller_side=False) -> Query:
+               counts=True, smaller_side=False, one_pass=False) -> Query:
     num, den = to_theta(theta)
     if delta is None or delta == float("inf"):
         delta = DELTA_INF
     return Query(int(delta), num, den, int(variant), int(universe), 1 if exclude_other else 0,
-                 (0 if counts else QUERY_NO_COUNTS) | (QUERY_SMALLER_SIDE if smaller_side else 0))
+                 (0 if counts else QUERY_NO_COUNTS) | (QUERY_SMALLER_SIDE if smaller_side else 0)
+                 | (QUERY_ONE_PASS if one_pass else 0))
 
 
 def _array_arg(x, dtype):
@@ -407,10 +409,11 @@ class Graph:
 
     def query(self, delta, theta=(1, 2), variant=0, universe=UNIVERSE_DST,
               exclude_other=False, counts=True, workspace: Workspace | None = None,
-              smaller_side=False) -> Result:
+              smaller_side=False, one_pass=False) -> Result:
         """The exists-exists-forall query; smaller_side evaluates each run from the
-        shorter of E_{a,b} and L2 (in-neighbour intervals), with identical results."""
-        q = make_query(delta, theta, variant, universe, exclude_other, counts, smaller_side)
+        shorter of E_{a,b} and L2 (in-neighbour intervals), one_pass filters in one
+        enumeration pass (per-item triangle slots); results are identical."""
+        q = make_query(delta, theta, variant, universe, exclude_other, counts, smaller_side, one_pass)
         out = ctypes.c_void_p()
         lib = load_library()
         if workspace is None:

@@ -415,22 +415,91 @@ def test_vertex_queries_match_oracle():
 
 
 def test_single_query_one_pass_and_two_pass_agree():
-    """A fresh index filters in two passes (count, then emit only items with
-    survivors); once a plan has made the per-item triangle offsets, single
-    queries filter in one pass into those slots.  Both equal the oracle."""
+    """A fresh index filters in two passes (count, then emit only the items with
+    survivors); with one_pass a query writes survivors into per-item triangle
+    slots in one pass (the offsets are made on first use).  A plan that makes the
+    offsets does not switch later queries by itself.  All equal the oracle."""
     g = synth.tiny(seed=21)
     o = Oracle(g.n, g.src, g.dst, g.t)
     G = gpu_graph(g)
     qs = [(10**6, (1, 4), 0), (3600, (1, 2), 3), (0, (0, 1), 6), (INF, (1, 3), 0)]
     first = [G.query(d, th, v) for d, th, v in qs]
-    say("two-pass stats", first[0].stats["triangles"], first[0].stats["tests"])
-    folty.Plan([G], [(0, dict(delta=qs[0][0], theta=qs[0][1], variant=qs[0][2]))])
+    say("two-pass stats", first[0].stats["triangles"], first[0].stats["tests"],
+        [r.stats["filter_passes"] for r in first])
+    assert first[0].stats["filter_passes"] == 2
+    G2 = gpu_graph(g)
+    folty.Plan([G2], [(0, dict(delta=qs[0][0], theta=qs[0][1], variant=qs[0][2]))])
+    assert G2.query(*qs[1]).stats["filter_passes"] == 2
     for (d, th, v), r1 in zip(qs, first):
-        r2 = G.query(d, th, v)
+        r2 = G.query(d, th, v, one_pass=True)
+        assert r2.stats["filter_passes"] == 1
         want = o.query(d, th[0], th[1], v)
         assert_same(r1, want)
         assert_same(r2, want)
         assert r2.stats["triangles"] == r1.stats["triangles"]
+        assert r2.stats["tests"] == r1.stats["tests"]
+
+
+def test_wide_window_switches_later_queries_to_one_pass():
+    """A query whose second filter pass re-enumerates most items (every window
+    at delta = INF) makes the per-item offsets from its own counting pass; later
+    queries of at least an eighth of its window filter in one pass by
+    themselves, narrower ones keep two.  Results equal the oracle throughout."""
+    g = synth.tiny(seed=22)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    G = gpu_graph(g)
+    r0 = G.query(INF, (1, 4), 0)
+    assert r0.stats["filter_passes"] == 2
+    r1 = G.query(INF, (1, 4), 0)
+    r2 = G.query(3600, (1, 4), 0)
+    say("passes", r0.stats["filter_passes"], r1.stats["filter_passes"], r2.stats["filter_passes"])
+    assert r1.stats["filter_passes"] == 1
+    assert r2.stats["filter_passes"] == 2
+    want = o.query(INF, 1, 4, 0)
+    assert_same(r0, want)
+    assert_same(r1, want)
+    assert_same(r2, o.query(3600, 1, 4, 0))
+    assert r1.stats["triangles"] == r0.stats["triangles"] and r1.stats["tests"] == r0.stats["tests"]
+
+
+def test_piece_list_capacity_does_not_change_results():
+    """Triangles with more tests than one thread runs are cut into pieces of 32
+    tests; pieces past the list's capacity run where they are cut.  With the
+    capacity forced down to 3 pieces (FOLTY_MAX_PIECES, read once per process,
+    so in a child process) counts, pairs and exists-exists-exists results equal
+    the oracle, in both filter modes."""
+    import os
+    import subprocess
+    import sys
+    code = r"""
+import numpy as np
+from oracle.oracle import Oracle
+from paper_2507_17215_amd import folty
+rng = np.random.default_rng(8)
+n = 40
+src = list(rng.integers(0, n, 3000)); dst = list(rng.integers(0, n, 3000)); t = list(rng.integers(0, 100_000, 3000))
+for a, b in ((0, 1), (1, 0), (2, 3), (5, 9)):
+    src += [a] * 4000; dst += [b] * 4000; t += list(rng.integers(0, 100_000, 4000))
+src, dst, t = np.array(src, np.int32), np.array(dst, np.int32), np.array(t, np.int64)
+o = Oracle(n, src, dst, t)
+G = folty.Graph(n, src, dst, t).build()
+for d, v, one in ((50, 0, False), (5000, 3, False), (30_000, 6, True), (folty.DELTA_INF, 0, True)):
+    r = G.query(d, (1, 4), v, one_pass=one)
+    want = o.query(d, 1, 4, v)
+    assert np.array_equal(r.counts(), want["counts"]), (d, v)
+    assert r.n_certificates == want["n_certificates"]
+    assert np.array_equal(r.pair_u, want["pair_u"]) and np.array_equal(r.pair_v, want["pair_v"])
+    assert r.stats["filter_passes"] == 1 or not one
+    tr = G.triad_query(d, v, edge_instances=True)
+    assert np.array_equal(tr.triads()["triples"], o.triad_solutions(d, v)), (d, v)
+    assert np.array_equal(tr.edge_instances(), o.triad_instances(d, v)), (d, v)
+print("ok")
+"""
+    env = dict(os.environ, FOLTY_MAX_PIECES="3")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    say("capacity 3:", out.stdout.strip(), out.stderr[-1500:])
+    assert out.returncode == 0 and out.stdout.strip() == "ok"
 
 
 def test_device_tensor_inputs():

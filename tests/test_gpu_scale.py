@@ -111,6 +111,7 @@ def test_wide_timestamps_tiny_workload_all_query_kinds():
             assert_same(r, o.query(q["delta"], 1, 4, q["variant"]))
     plan.close()
     # the one-pass filter (per-item triangle slots) on the same timestamps
-    G.stats()
     for d in (3_600_001, 10**9 + 7):
-        assert_same(G.query(d, (1, 4), 0), o.query(d, 1, 4, 0))
+        r = G.query(d, (1, 4), 0, one_pass=True)
+        assert r.stats["filter_passes"] == 1
+        assert_same(r, o.query(d, 1, 4, 0))
