@@ -273,13 +273,13 @@ struct Index {
 // per-query scratch; one per concurrent caller
 struct Workspace {
     DevBuf count;   // uint32[m]
-    DevBuf sv;      // int32[3 x survivors] surviving triangles (oriented edges), in their item's slots
+    DevBuf sv;      // int32[3 x slots] surviving triangles (oriented edges), in their item's slots
     DevBuf su;      // int32[NI]   survivors per item
     DevBuf wu;      // int64[NI+1] tests per item
     DevBuf wbase;   // int64[NI+1] exclusive offsets of wu
     DevBuf sbase;   // int64[NI+1] exclusive offsets of su: the dense index of each item's first survivor
     DevBuf tri_it;  // int32[NI+1] triangles per item, from the last counting filter pass
-    DevBuf pieces;  // Piece[]     the temporal step's pieces of survivors with many tests
+    DevBuf pieces;  // Heavy[]     the temporal step's survivors with many tests
     DevBuf gitem;   // int32[]     per group of 64 survivors, the item of its first (sparse slots)
     const int64_t *slots = nullptr; // first slot of each item's survivors in sv: sbase (dense) or the index's tri_base
     bool emit_timed = false;        // the last filter's second pass is bracketed by ev[6], ev[7]

@@ -383,7 +383,7 @@ int64_t find_survivors_t(const Index &ix, int variant, int64_t dmax, Workspace &
     using BothM = std::integral_constant<int, FILTER_BOTH>;
     if (one_pass && ix.tri_base_ready.load(std::memory_order_acquire)) {
         // per-item triangle offsets exist: one pass writes survivors into them
-        ws.sv.ensure(12 * (size_t)ix.T + 12);
+        ws.sv.ensure(12 * ((size_t)ix.T + 1));
         FOLTY_HIP(hipEventRecord(e0, s));
         dispatch_variant(variant, [&](auto V) {
             auto sink = sink_for(V, BothM{});
@@ -483,8 +483,10 @@ void launch_temporal(const Index &ix, int variant, int64_t dmax, Workspace &ws, 
                      int64_t survivors, hipStream_t s) {
     const uint32_t dq = run_slack(range_slack(dmax, ix.tshift));
     dispatch_variant(variant, [&](auto V) {
-        launch_tests(ix, ws, CountRunner<decltype(V)::value, Op, SS>{dq, ix.ts.as<int64_t>(), op}, survivors, tests,
-                     s);
+        launch_tests(ix, ws,
+                     CountRunner<decltype(V)::value, Op, SS>{dq, ix.ts.as<int64_t>(), op, ws.sv.as<int32_t>(),
+                                                             ix.rec.as<EdgeRec>()},
+                     survivors, tests, s);
     });
 }
 
@@ -1039,8 +1041,8 @@ int64_t query_footprint(const Graph *g, const folty_query &q) {
     const int64_t T = std::max<int64_t>(0, ix.T.load());
     // counts; per item su, tri_it, wu, wbase, sbase, ilist; survivors and their
     // groups; pieces; pair step
-    int64_t b = 4 * (int64_t)ix.m + 36 * ((int64_t)ix.NI + 1) + 12 * T + 4 * (T / 64 + 3) +
-                (int64_t)sizeof(Piece) * piece_slots(T, -1) + 56 * (int64_t)ix.S;
+    int64_t b = 4 * (int64_t)ix.m + 36 * ((int64_t)ix.NI + 1) + 12 * (T + 1) + 4 * (T / 64 + 3) +
+                (int64_t)sizeof(Heavy) * heavy_slots(T, -1) + 56 * (int64_t)ix.S;
     if (q.flags & FOLTY_QUERY_SMALLER_SIDE) b += 8 * (int64_t)ix.m + 4;
     if (!(q.flags & FOLTY_QUERY_NO_COUNTS)) b += 4 * ix.m_input;
     return b + (1 << 20);

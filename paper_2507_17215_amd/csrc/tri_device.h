@@ -901,12 +901,15 @@ __device__ inline void chunk_runs_rt(int variant, const TriLists &L, uint32_t dq
 // q in [sbase[u], sbase[u + 1]), at slots slot_base[u] + (q - sbase[u]) of the
 // filter's output (slot_base null: the slots are dense, slot = q).  A wavefront
 // takes a group of 64 consecutive survivors, one per lane.  A survivor with at
-// most LIGHT_TESTS tests is run by the group; one with more is cut into pieces
-// of PIECE_TESTS, appended to a list that a second kernel runs one piece per
-// thread, each piece starting its L2 and L3 cursors with one binary search (the
-// merge-path split of a long run over neighbouring threads).  No test pays a
-// search over items or survivors.  Pieces past the list's capacity run where
-// they were cut, so any capacity gives the same result.
+// most LIGHT_TESTS tests is run by the group.  One with more (a heavy survivor)
+// gets an entry in a list and a range of piece numbers, both from one packed
+// counter, so entries are in the order of their pieces; a second kernel runs
+// piece p (tests [32 i, 32 i + 32) of its survivor) per thread, finding its
+// entry by binary search over the entries' first pieces and starting its L2 and
+// L3 cursors with one binary search each (the merge-path split of a long run
+// over neighbouring threads).  No test pays a search over items or survivors.
+// Heavy survivors past the list's capacity run where they were found, so any
+// capacity gives the same result.
 //
 // How a group runs its light tests depends on the runner.  Flat runners (the
 // per-edge counts): the lanes stage their survivors' six list spans in LDS, and
@@ -919,10 +922,13 @@ __device__ inline void chunk_runs_rt(int variant, const TriLists &L, uint32_t dq
 constexpr int64_t LIGHT_TESTS = 16;
 constexpr int64_t PIECE_TESTS = 32;
 
-struct Piece {
-    int64_t slot; // survivor slot
-    int64_t k0;   // first test of the piece among the survivor's tests
+struct Heavy {
+    int64_t slot;  // survivor slot
+    int64_t first; // its first piece number
 };
+// the counter of heavy survivors: entries in bits 40-63, piece numbers in 0-39
+constexpr int HEAVY_SHIFT = 40;
+constexpr unsigned long long PIECE_MASK = (1ull << HEAVY_SHIFT) - 1;
 
 // the largest u in [a, b) with sbase[u] <= q (sbase ascending, sbase[a] <= q)
 __device__ inline int32_t item_of(const int64_t *__restrict__ sbase, int32_t a, int32_t b, int64_t q) {
@@ -996,13 +1002,20 @@ __device__ inline bool flat_run(const FlatLds &F, int si, int k, int64_t &r, con
     return true;
 }
 
-// Runs the tests of the per-edge counts: work() is the survivor's number of
-// tests, run() takes tests [r, k1) of it in order, flat() its test r alone.
+// Runs the tests of the per-edge counts: work() is a survivor's number of
+// tests, run() takes tests [r, k1) of it in order, flat() its test r alone,
+// from the spans stage() put in LDS.
 template <int VAR, class Op, bool SS> struct CountRunner {
     static constexpr bool kFlat = true;
+    using Surv = TriLists;
     uint32_t dq;
     const int64_t *ts;
     Op op;
+    const int32_t *sv; // survivors as three oriented edges
+    const EdgeRec *rec;
+    __device__ inline TriLists load(int64_t slot) const {
+        return load_lists(rec, sv[3 * slot], sv[3 * slot + 1], sv[3 * slot + 2]);
+    }
     __device__ inline int64_t work(const TriLists &L) const { return tri_work<VAR, SS>(L, dq); }
     __device__ inline void run(const TriLists &L, int64_t, int64_t r, int64_t k1) {
         int64_t k = r;
@@ -1015,6 +1028,15 @@ template <int VAR, class Op, bool SS> struct CountRunner {
                (uint32_t)run_lists<VAR, 0, 2>(L, dq, a, b, c) << 2 | (uint32_t)run_lists<VAR, 2, 0>(L, dq, a, b, c) << 3 |
                (uint32_t)run_lists<VAR, 1, 2>(L, dq, a, b, c) << 4 | (uint32_t)run_lists<VAR, 2, 1>(L, dq, a, b, c) << 5;
     }
+    __device__ inline void stage(FlatLds &F, int lane, const TriLists &T, bool light) const {
+        F.ls[0][lane] = T.d01.s, F.ln[0][lane] = T.d01.n;
+        F.ls[1][lane] = T.d10.s, F.ln[1][lane] = T.d10.n;
+        F.ls[2][lane] = T.d02.s, F.ln[2][lane] = T.d02.n;
+        F.ls[3][lane] = T.d20.s, F.ln[3][lane] = T.d20.n;
+        F.ls[4][lane] = T.d12.s, F.ln[4][lane] = T.d12.n;
+        F.ls[5][lane] = T.d21.s, F.ln[5][lane] = T.d21.n;
+        F.live[lane] = light ? live(T) : 0u;
+    }
     __device__ inline void flat(const FlatLds &F, int si, int64_t r) const {
         flat_run<VAR, 0, 1, SS>(F, si, 0, r, ts, op) || flat_run<VAR, 1, 0, SS>(F, si, 1, r, ts, op) ||
             flat_run<VAR, 0, 2, SS>(F, si, 2, r, ts, op) || flat_run<VAR, 2, 0, SS>(F, si, 3, r, ts, op) ||
@@ -1023,47 +1045,59 @@ template <int VAR, class Op, bool SS> struct CountRunner {
     __device__ inline void finish() {}
 };
 
-// the pieces of this lane's survivor (np > 0: a heavy one), reserved for the
-// whole wavefront at once; those past the capacity run here
+// Lanes with np > 0 (heavy survivors, np pieces each) take list entries and
+// piece numbers for the whole wavefront with one atomic.  A survivor whose
+// entry lies past cap runs here; the piece numbers it reserved follow every
+// listed one.  `full` is set once this wavefront's atomic returned an entry
+// count of cap or more, after which it lists nothing: each wavefront adds at
+// most 64 entries past cap, so the entry count stays below cap + 64 x (the
+// grid's wavefronts), far below 2^24.
 template <class R>
-__device__ inline void cut_pieces(R &runner, const TriLists &L, int64_t slot, int64_t w, int64_t np,
-                                  Piece *__restrict__ pieces, unsigned long long *__restrict__ npieces, int64_t cap) {
+__device__ inline void defer_heavy(R &runner, const typename R::Surv &S, int64_t slot, int64_t w, int64_t np,
+                                   Heavy *__restrict__ heavy, unsigned long long *__restrict__ counter, int64_t cap,
+                                   bool &full) {
     if (!__ballot(np > 0)) return;
-    const int64_t incl = wave_inclusive_sum(np);
-    unsigned long long at = 0;
-    if (lane_id() == 63) at = atomicAdd(npieces, (unsigned long long)incl);
-    const int64_t first = (int64_t)__shfl((long long)at, 63) + incl - np;
-    for (int64_t i = 0; i < np; i++) {
-        const int64_t k0 = i * PIECE_TESTS;
-        if (first + i < cap) pieces[first + i] = Piece{slot, k0};
-        else runner.run(L, slot, k0, k0 + PIECE_TESTS < w ? k0 + PIECE_TESTS : w);
+    if (full) {
+        if (np > 0) runner.run(S, slot, 0, w);
+        return;
     }
+    const unsigned long long add = np > 0 ? (1ull << HEAVY_SHIFT) | (unsigned long long)np : 0ull;
+    const unsigned long long incl = wave_inclusive_sum(add);
+    unsigned long long at = 0;
+    if (lane_id() == 63) at = atomicAdd(counter, incl);
+    at = __shfl(at, 63);
+    full = (int64_t)(at >> HEAVY_SHIFT) + 64 >= cap;
+    if (np == 0) return;
+    const unsigned long long mine = at + incl - add;
+    const int64_t e = (int64_t)(mine >> HEAVY_SHIFT);
+    if (e < cap) heavy[e] = Heavy{slot, (int64_t)(mine & PIECE_MASK)};
+    else runner.run(S, slot, 0, w);
 }
 
 template <class R>
 __global__ __launch_bounds__(BLK) void k_tests_light(const int64_t *__restrict__ sbase,
                                                      const int64_t *__restrict__ slot_base,
-                                                     const int32_t *__restrict__ gitem, int32_t NI,
-                                                     const int32_t *__restrict__ sv, const EdgeRec *__restrict__ rec,
-                                                     R runner, Piece *__restrict__ pieces,
-                                                     unsigned long long *__restrict__ npieces, int64_t cap) {
+                                                     const int32_t *__restrict__ gitem, int32_t NI, R runner,
+                                                     Heavy *__restrict__ heavy,
+                                                     unsigned long long *__restrict__ counter, int64_t cap) {
     __shared__ FlatLds flds[R::kFlat ? WPB : 1];
     const int w = wave_id();
     const int lane = lane_id();
     const int64_t nsurv = sbase[NI];
     const int64_t ng = (nsurv + 63) / 64;
+    bool full = false;
     for (int64_t g = (int64_t)blockIdx.x * WPB + w; g < ng; g += (int64_t)gridDim.x * WPB) {
         const int64_t q = g * 64 + lane;
         const bool on = q < nsurv;
         int64_t slot = 0, wk = 0, np = 0;
-        TriLists L{};
+        typename R::Surv S{};
         if (on) {
             slot = survivor_slot(sbase, slot_base, gitem, g, q);
-            L = load_lists(rec, sv[3 * slot], sv[3 * slot + 1], sv[3 * slot + 2]);
-            wk = runner.work(L);
+            S = runner.load(slot);
+            wk = runner.work(S);
             if (wk > LIGHT_TESTS) np = (wk + PIECE_TESTS - 1) / PIECE_TESTS;
         }
-        cut_pieces(runner, L, slot, wk, np, pieces, npieces, cap);
+        defer_heavy(runner, S, slot, wk, np, heavy, counter, cap, full);
         const int64_t light = np ? 0 : wk;
         if constexpr (R::kFlat) {
             FlatLds &F = flds[w];
@@ -1071,14 +1105,7 @@ __global__ __launch_bounds__(BLK) void k_tests_light(const int64_t *__restrict__
             const int32_t total = __shfl(incl, 63);
             if (total == 0) continue;
             F.incl[lane] = incl;
-            const TriLists &T = L;
-            F.ls[0][lane] = T.d01.s, F.ln[0][lane] = T.d01.n;
-            F.ls[1][lane] = T.d10.s, F.ln[1][lane] = T.d10.n;
-            F.ls[2][lane] = T.d02.s, F.ln[2][lane] = T.d02.n;
-            F.ls[3][lane] = T.d20.s, F.ln[3][lane] = T.d20.n;
-            F.ls[4][lane] = T.d12.s, F.ln[4][lane] = T.d12.n;
-            F.ls[5][lane] = T.d21.s, F.ln[5][lane] = T.d21.n;
-            F.live[lane] = light ? runner.live(L) : 0u;
+            runner.stage(F, lane, S, light != 0);
             wave_sync();
             for (int32_t t = lane; t < total; t += 64) {
                 // the survivor whose tests hold t: the first si with incl[si] > t
@@ -1092,48 +1119,61 @@ __global__ __launch_bounds__(BLK) void k_tests_light(const int64_t *__restrict__
             }
             wave_sync(); // the LDS is rewritten by the next group
         } else {
-            if (light) runner.run(L, slot, 0, light);
+            if (light) runner.run(S, slot, 0, light);
         }
     }
     runner.finish();
 }
 
 template <class R>
-__global__ __launch_bounds__(BLK) void k_tests_pieces(const Piece *__restrict__ pieces,
-                                                      const unsigned long long *__restrict__ npieces, int64_t cap,
-                                                      const int32_t *__restrict__ sv,
-                                                      const EdgeRec *__restrict__ rec, R runner) {
-    const int64_t n = (int64_t)*npieces < cap ? (int64_t)*npieces : cap;
-    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
-        const Piece pc = pieces[i];
-        const TriLists L = load_lists(rec, sv[3 * pc.slot], sv[3 * pc.slot + 1], sv[3 * pc.slot + 2]);
-        runner.run(L, pc.slot, pc.k0, pc.k0 + PIECE_TESTS);
+__global__ __launch_bounds__(BLK) void k_tests_pieces(const Heavy *__restrict__ heavy,
+                                                      const unsigned long long *__restrict__ counter, int64_t cap,
+                                                      R runner) {
+    const unsigned long long c = *counter;
+    const int64_t ne = (int64_t)(c >> HEAVY_SHIFT) < cap ? (int64_t)(c >> HEAVY_SHIFT) : cap;
+    const int64_t np = (int64_t)(c & PIECE_MASK);
+    if (ne > 0) {
+        for (int64_t p = (int64_t)blockIdx.x * BLK + threadIdx.x; p < np; p += (int64_t)gridDim.x * BLK) {
+            // the last entry whose first piece is <= p (entry 0 starts at piece 0)
+            int64_t a = 0, b = ne - 1;
+            while (a < b) {
+                const int64_t mid = (a + b + 1) >> 1;
+                if (heavy[mid].first <= p) a = mid;
+                else b = mid - 1;
+            }
+            const Heavy h = heavy[a];
+            const int64_t k0 = (p - h.first) * PIECE_TESTS;
+            // pieces past the last listed survivor's belong to ones that ran
+            // where they were found: k0 lies past every run, nothing is tested
+            runner.run(runner.load(h.slot), h.slot, k0, k0 + PIECE_TESTS);
+        }
     }
     runner.finish();
 }
 
-constexpr int64_t MAX_PIECES = 1 << 22; // 64 MB of pieces at most; the rest run where they are cut
-constexpr int64_t MIN_PIECES = 1 << 16; // room for this many whatever the survivors
+constexpr int64_t MAX_HEAVY = 1 << 22; // 64 MB of heavy-survivor entries at most
+constexpr int64_t MIN_HEAVY = 1 << 16; // room for this many whatever the survivors
 constexpr int64_t LIGHT_BLOCKS = 16384;
 constexpr int64_t PIECE_BLOCKS = 8192;
 
-// the piece list's capacity limit: MAX_PIECES, or FOLTY_MAX_PIECES (>= 1) when set
-inline int64_t max_pieces() {
+// the heavy list's capacity limit: MAX_HEAVY, or FOLTY_MAX_HEAVY (>= 1) when set
+inline int64_t max_heavy() {
     static const int64_t v = [] {
-        const char *e = getenv("FOLTY_MAX_PIECES");
+        const char *e = getenv("FOLTY_MAX_HEAVY");
         const long long x = e ? atoll(e) : 0;
-        return x >= 1 ? (int64_t)x : MAX_PIECES;
+        return x >= 1 ? (int64_t)std::min<long long>(x, MAX_HEAVY) : MAX_HEAVY;
     }();
     return v;
 }
 
-// Pieces a query's list holds: no more than its tests can fill (when known), and
-// at most one per survivor (at least MIN_PIECES, at most the limit), so that
-// 16 * piece_slots(T, -1) bounds the list's memory on a graph of T triangles.
-inline int64_t piece_slots(int64_t survivors, int64_t tests) {
-    int64_t b = std::max<int64_t>(survivors + 1, MIN_PIECES);
-    if (tests >= 0) b = std::min<int64_t>(b, tests / PIECE_TESTS + tests / (LIGHT_TESTS + 1) + 1);
-    return std::max<int64_t>(1, std::min<int64_t>(b, max_pieces()));
+// Entries a query's heavy list holds: no more than its tests can fill (when
+// known), and at most one per survivor (at least MIN_HEAVY, at most the limit),
+// so that 16 * heavy_slots(T, -1) bounds the list's memory on a graph of T
+// triangles.
+inline int64_t heavy_slots(int64_t survivors, int64_t tests) {
+    int64_t b = std::max<int64_t>(survivors + 1, MIN_HEAVY);
+    if (tests >= 0) b = std::min<int64_t>(b, tests / (LIGHT_TESTS + 1) + 1);
+    return std::max<int64_t>(1, std::min<int64_t>(b, max_heavy()));
 }
 
 // The tests of the survivors of the last filter (see k_tests_light): survivors is
@@ -1141,8 +1181,8 @@ inline int64_t piece_slots(int64_t survivors, int64_t tests) {
 // their number of tests, or < 0 when unknown on the host.
 template <class R>
 void launch_tests(const Index &ix, Workspace &ws, const R &runner, int64_t survivors, int64_t tests, hipStream_t s) {
-    const int64_t cap = piece_slots(survivors, tests);
-    ws.pieces.ensure(sizeof(Piece) * (size_t)cap);
+    const int64_t cap = heavy_slots(survivors, tests);
+    ws.pieces.ensure(sizeof(Heavy) * (size_t)cap);
     ws.scal.ensure(128);
     unsigned long long *np = ws.scal.as<unsigned long long>() + 14;
     k_fill<unsigned long long><<<1, 1, 0, s>>>(np, 0ull, 1);
@@ -1156,13 +1196,15 @@ void launch_tests(const Index &ix, Workspace &ws, const R &runner, int64_t survi
         FOLTY_LAUNCHED();
     }
     const unsigned lb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + WPB - 1) / WPB, LIGHT_BLOCKS));
-    k_tests_light<<<lb, BLK, 0, s>>>(ws.sbase.as<int64_t>(), sparse, ws.gitem.as<int32_t>(), ix.NI,
-                                     ws.sv.as<int32_t>(), ix.rec.as<EdgeRec>(), runner, ws.pieces.as<Piece>(), np,
-                                     cap);
+    k_tests_light<<<lb, BLK, 0, s>>>(ws.sbase.as<int64_t>(), sparse, ws.gitem.as<int32_t>(), ix.NI, runner,
+                                     ws.pieces.as<Heavy>(), np, cap);
     FOLTY_LAUNCHED();
-    const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + BLK - 1) / BLK, PIECE_BLOCKS));
-    k_tests_pieces<<<pb, BLK, 0, s>>>(ws.pieces.as<Piece>(), np, cap, ws.sv.as<int32_t>(), ix.rec.as<EdgeRec>(),
-                                      runner);
+    // the pieces are numbered on the device; with the tests known, no more
+    // threads than pieces
+    const int64_t most = tests >= 0 ? tests / PIECE_TESTS + std::min<int64_t>(cap, tests / (LIGHT_TESTS + 1)) + 1
+                                    : (int64_t)PIECE_BLOCKS * BLK;
+    const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((most + BLK - 1) / BLK, PIECE_BLOCKS));
+    k_tests_pieces<<<pb, BLK, 0, s>>>(ws.pieces.as<Heavy>(), np, cap, runner);
     FOLTY_LAUNCHED();
 }
 

@@ -141,12 +141,18 @@ __device__ inline void triad_runs(const TriLists &L, uint32_t dq, const int64_t 
 // = 1 on a 64-bit overflow.
 template <int VAR, bool INST> struct TriadRunner {
     static constexpr bool kFlat = false; // a run's tests share their window bookkeeping
+    using Surv = TriLists;
     uint32_t dq;
     const int64_t *ts;
     TriadOut o;
     unsigned long long *total;
+    const int32_t *sv;  // survivors as three oriented edges
+    const EdgeRec *rec;
     unsigned long long acc = 0;
     bool ovf = false;
+    __device__ inline TriLists load(int64_t slot) const {
+        return load_lists(rec, sv[3 * slot], sv[3 * slot + 1], sv[3 * slot + 2]);
+    }
     __device__ inline int64_t work(const TriLists &L) const { return tri_work<VAR, false>(L, dq); }
     __device__ inline void run(const TriLists &L, int64_t slot, int64_t r, int64_t k1) {
         int64_t k = r;
@@ -364,10 +370,14 @@ Result *run_triad_query(Graph *g, const folty_triad_query &q, Workspace &ws) {
             const uint32_t dq = run_slack(range_slack(q.delta, ix.tshift));
             dispatch_variant(q.variant, [&](auto V) {
                 constexpr int VAR = decltype(V)::value;
+                const int32_t *sv = ws.sv.as<int32_t>();
+                const EdgeRec *rec = ix.rec.as<EdgeRec>();
                 if (inst)
-                    launch_tests(ix, ws, TriadRunner<VAR, true>{dq, ix.ts.as<int64_t>(), o, tot}, slots, known, s);
+                    launch_tests(ix, ws, TriadRunner<VAR, true>{dq, ix.ts.as<int64_t>(), o, tot, sv, rec}, slots, known,
+                                 s);
                 else
-                    launch_tests(ix, ws, TriadRunner<VAR, false>{dq, ix.ts.as<int64_t>(), o, tot}, slots, known, s);
+                    launch_tests(ix, ws, TriadRunner<VAR, false>{dq, ix.ts.as<int64_t>(), o, tot, sv, rec}, slots,
+                                 known, s);
             });
             FOLTY_LAUNCHED();
             k_triad_count<<<grid_for(ix.NI, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ws.slots, ws.su.as<int32_t>(), ix.NI,

@@ -462,12 +462,12 @@ def test_wide_window_switches_later_queries_to_one_pass():
     assert r1.stats["triangles"] == r0.stats["triangles"] and r1.stats["tests"] == r0.stats["tests"]
 
 
-def test_piece_list_capacity_does_not_change_results():
-    """Triangles with more tests than one thread runs are cut into pieces of 32
-    tests; pieces past the list's capacity run where they are cut.  With the
-    capacity forced down to 3 pieces (FOLTY_MAX_PIECES, read once per process,
-    so in a child process) counts, pairs and exists-exists-exists results equal
-    the oracle, in both filter modes."""
+def test_heavy_list_capacity_does_not_change_results():
+    """Surviving triangles with more than 16 tests are listed and their tests run
+    in pieces of 32; those past the list's capacity run where they were found.
+    With the capacity forced down to 3 triangles (FOLTY_MAX_HEAVY, read once per
+    process, so in a child process) counts, pairs and exists-exists-exists
+    results equal the oracle, in both filter modes."""
     import os
     import subprocess
     import sys
@@ -495,7 +495,7 @@ for d, v, one in ((50, 0, False), (5000, 3, False), (30_000, 6, True), (folty.DE
     assert np.array_equal(tr.edge_instances(), o.triad_instances(d, v)), (d, v)
 print("ok")
 """
-    env = dict(os.environ, FOLTY_MAX_PIECES="3")
+    env = dict(os.environ, FOLTY_MAX_HEAVY="3")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env,
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     say("capacity 3:", out.stdout.strip(), out.stderr[-1500:])
