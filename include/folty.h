@@ -234,9 +234,9 @@ int folty_build_index(folty_graph *g, const folty_build_opts *opts);
  * survivor slots in their workspace (FOLTY_QUERY_ONE_PASS asks for that on any
  * query).  The choice depends only on the graph and the queries run before.
  *
- * The temporal tests of surviving triangles with up to 16 tests run 64
+ * The temporal tests of surviving triangles with up to 64 tests run 64
  * triangles to a wavefront, one test per lane; a triangle with more is listed
- * and its tests run in pieces of 32, one piece per thread.  The list holds at
+ * and its tests run in pieces of 4, one piece per thread.  The list holds at
  * most 2^22 triangles (16 bytes each; the environment variable FOLTY_MAX_HEAVY
  * lowers the limit); triangles beyond it run where they were found, with the
  * same results.

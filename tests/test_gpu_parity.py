@@ -463,8 +463,8 @@ def test_wide_window_switches_later_queries_to_one_pass():
 
 
 def test_heavy_list_capacity_does_not_change_results():
-    """Surviving triangles with more than 16 tests are listed and their tests run
-    in pieces of 32; those past the list's capacity run where they were found.
+    """Surviving triangles with more than 64 tests are listed and their tests run
+    in pieces of 4; those past the list's capacity run where they were found.
     With the capacity forced down to 3 triangles (FOLTY_MAX_HEAVY, read once per
     process, so in a child process) counts, pairs and exists-exists-exists
     results equal the oracle, in both filter modes."""
