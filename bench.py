@@ -68,6 +68,9 @@ def parse():
                    help="serving on the five smaller graphs at two rates only")
     p.add_argument("--copy-probe", action="store_true",
                    help="only copy a 1 GiB device buffer three times (calibrates HBM byte counters)")
+    p.add_argument("--profile-queries", action="store_true",
+                   help="after the timed steps, run a fixed sequence of queries on the 70M-edge graph "
+                        "(no oracle) for profilers, print the JSON line and stop")
     return p.parse_args()
 
 
@@ -113,6 +116,35 @@ def cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def profile_queries(folty, synth, n, src, dst, tt, theta):
+    """A fixed sequence for profilers, in order: on a fresh index, one day and one
+    year with predicate 0 (two filter passes each; the one-year query's second
+    pass re-enumerates most triangles, so later wide windows filter in one
+    pass), then one year with predicates 0 and 3 (one pass), the smaller-side
+    evaluation at one year, and the exists-exists-exists query at one year
+    (counting only, then with temporal triangles, per-edge counts and listing)."""
+    Y = synth.YEAR_S
+    G = folty.Graph(n, src, dst, tt).build()
+    seq = []
+
+    def note(name, st):
+        row = {"query": name}
+        row.update({k: st[k] for k in ("query_ms", "wedge_ms", "temporal_ms", "tests", "filter_passes")})
+        seq.append(row)
+        log(f"profile {name}: query {st['query_ms']:.2f} ms, filter {st['wedge_ms']:.2f} ms, temporal "
+            f"{st['temporal_ms']:.2f} ms, {st['tests']} tests, {st['filter_passes']} filter passes")
+
+    for name, d, v, ss in (("1 day, predicate 0", 86_400, 0, False), ("1 year, predicate 0", Y, 0, False),
+                           ("1 year, predicate 0, again", Y, 0, False), ("1 year, predicate 3", Y, 3, False),
+                           ("1 year, predicate 0, smaller side", Y, 0, True)):
+        note(name, G.query(d, theta, v, counts=False, smaller_side=ss).stats)
+    for name, kw in (("triads 1 year, counting", dict(triples=False, instances=False)),
+                     ("triads 1 year, triangles and listing", dict(triples=True, instances=True,
+                                                                    edge_instances=True))):
+        note(name, G.triad_query(Y, 0, **kw).stats)
+    return seq
 
 
 def copy_probe():
@@ -659,6 +691,10 @@ def main():
     from oracle.oracle import Oracle
     threads = len(os.sched_getaffinity(0))
     rng = np.random.default_rng(123)
+    if a.profile_queries:
+        out["profile_queries"] = profile_queries(folty, synth, n, src, dst, tt, theta)
+        print(json.dumps(out), flush=True)
+        return
     G = folty.Graph(n, src, dst, tt).build()  # resident: checks, extra sections, serving
     oracle = None
     ok = True

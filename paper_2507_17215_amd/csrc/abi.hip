@@ -40,7 +40,13 @@ void fail(int code, const char *fmt, ...) {
 }
 
 Graph::~Graph() {
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    if (own_stream && stream) {
+        // the index's buffers are freed after this body, with no stream of
+        // their own; blocks freed on this stream before lose their events here
+        (void)hipStreamSynchronize(stream);
+        dev_forget_stream(stream);
+        (void)hipStreamDestroy(stream);
+    }
 }
 
 template <class F> static int guarded(F &&f) {

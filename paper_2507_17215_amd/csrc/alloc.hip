@@ -91,8 +91,18 @@ void *dev_alloc(size_t bytes, size_t *got) {
             P.free_blocks.erase(it);
             P.cached -= b.bytes;
             if (b.ev) {
-                if (!t_stream) (void)hipEventSynchronize(b.ev);
-                else if (b.stream != t_stream) (void)hipStreamWaitEvent(t_stream, b.ev, 0);
+                // the block's last use must be done before the new owner's work
+                // (the same stream orders it by itself)
+                hipError_t e = hipSuccess;
+                if (!t_stream) e = hipEventSynchronize(b.ev);
+                else if (b.stream != t_stream) e = hipStreamWaitEvent(t_stream, b.ev, 0);
+                if (e != hipSuccess) {
+                    // no wait could be set up: wait for the whole device, and keep
+                    // the failed call's error from being reported by a later check
+                    (void)hipGetLastError();
+                    (void)hipDeviceSynchronize();
+                    (void)hipGetLastError();
+                }
                 (void)hipEventDestroy(b.ev);
             }
             *got = b.bytes;
@@ -142,6 +152,27 @@ void dev_free(void *p, size_t bytes) {
     std::lock_guard<std::mutex> lk(P.mu);
     P.free_blocks.emplace(bytes, b);
     P.cached += bytes;
+}
+
+// A stream is about to be destroyed: the cached blocks whose last use was on it
+// wait for that use now and drop its event, so no later owner waits on an event
+// of a destroyed stream.
+void dev_forget_stream(hipStream_t s) {
+    if (!s) return;
+    std::lock_guard<std::mutex> lk(g_pools_mu);
+    for (auto &kv : g_pools) {
+        Pool &P = *kv.second;
+        std::lock_guard<std::mutex> lp(P.mu);
+        for (auto &fb : P.free_blocks) {
+            Block &b = fb.second;
+            if (b.stream != s || !b.ev) continue;
+            (void)hipEventSynchronize(b.ev);
+            (void)hipEventDestroy(b.ev);
+            b.ev = nullptr;
+            b.stream = nullptr;
+        }
+    }
+    (void)hipGetLastError();
 }
 
 size_t dev_trim() {

@@ -475,6 +475,8 @@ Plan::~Plan() {
         keys2.release();
         vals2.release();
         cub.release();
+        (void)hipStreamSynchronize(stream);
+        dev_forget_stream(stream);
         (void)hipStreamDestroy(stream);
     }
 }
@@ -607,6 +609,13 @@ int64_t plan_footprint(const Graph *g, const folty_query *qs, int nq) {
         b += 4 * hist_words(ix.m, padded_levels(d.size())) + 8 * ((int64_t)ix.m / 64 + 1) + 8 * (int64_t)d.size();
         b += 20 * T + 4 * (int64_t)ix.NI + 16 * ((int64_t)ix.NI + 1);
     }
+    // library scratch: the scan over the jobs' items and the sort of up to
+    // 2 S certificate records per query (sizes only)
+    const int64_t items = (int64_t)lv.size() * ((int64_t)ix.NI + 1);
+    const int64_t recs = std::min<int64_t>((int64_t)nq * 2 * (int64_t)ix.S, INT32_MAX); // the sort's limit
+    const int kb = bit_length((uint64_t)std::max(1, nq)) + 2 * bit_length((uint64_t)ix.n);
+    b += (int64_t)std::max(exclusive_scan_i64(nullptr, 0, nullptr, nullptr, items + 1, nullptr),
+                           sort_pairs_u64_u32(nullptr, 0, nullptr, nullptr, nullptr, nullptr, recs, kb, nullptr));
     return b + (1 << 20);
 }
 

@@ -590,13 +590,13 @@ __global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool
     }
 }
 
-// Marking of sweep s, for a dropped vertex u (value xo -> h) and its neighbour w:
-//  - a long row w with a kept histogram (not `rescan`): u moves from level
-//    min(xo, c(w)) to min(h, c(w)); w is listed when its top level lost u, the
-//    only way its own value can become too high;
-//  - any other w is listed when its value is above h (a neighbour at or below h
-//    is not affected by the drop).
-// Each vertex is listed once per sweep.
+// Marking of sweep s, for a dropped vertex u (value xo -> h) and its neighbour w.
+// A vertex w that is not listed holds a value with count(>= c(w)) >= c(w) over
+// its neighbours' values; u's drop lowers that count only if xo >= c(w) > h,
+// so exactly those w are listed (also when w read xo or h during the sweep:
+// either way its value counted u only if c(w) <= xo).  Long rows with a kept
+// histogram (not `rescan`) also move u from level min(xo, c(w)) to h whenever
+// c(w) > h.  Each vertex is listed once per sweep.
 // J entries of one lane at a time: every dependent load and atomic of the batch
 // is issued before any result is used
 template <int J>
@@ -604,18 +604,18 @@ __device__ inline void mark_batch(const CoreBufs &B, Pusher &p, const int32_t (&
                                   const bool (&ok)[J], int32_t xo, int32_t h, int32_t tag, bool rescan) {
     bool cand[J], want[J];
     int32_t dw[J], st[J];
+    const bool keep = B.hbw > 0 && !rescan;
 #pragma unroll
     for (int j = 0; j < J; j++) {
         cand[j] = ok[j] && cw[j] > h;
-        dw[j] = cand[j] ? B.deg[w[j]] : 0;
+        dw[j] = cand[j] && (keep || cw[j] <= xo) ? B.deg[w[j]] : 0;
     }
-    const bool keep = B.hbw > 0 && !rescan;
     int32_t id[J];
 #pragma unroll
     for (int j = 0; j < J; j++) id[j] = (keep && cand[j] && dw[j] > C1_MAX) ? B.bigid[w[j]] : -1;
 #pragma unroll
     for (int j = 0; j < J; j++) {
-        want[j] = cand[j];
+        want[j] = cand[j] && cw[j] <= xo;
         if (id[j] >= 0) {
             const int32_t bo = xo < cw[j] ? xo : cw[j]; // h < cw here, so the new level is h
             int32_t *gh = B.gh + (int64_t)id[j] * B.hbw;

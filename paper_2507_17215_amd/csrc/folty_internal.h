@@ -57,6 +57,7 @@ void dev_free(void *p, size_t bytes);
 size_t dev_trim();   // give every cached block back to the driver; returns bytes
 size_t dev_trim_to(size_t keep); // give back cached blocks, largest first, until at most keep bytes stay
 size_t dev_cached(); // bytes held in the cache
+void dev_forget_stream(hipStream_t s); // call before destroying a stream blocks were freed on
 // pinned host blocks for large result arrays (alloc.hip); host_alloc returns
 // nullptr when pinned memory is not available, host_free false for a pointer
 // it did not hand out

@@ -1045,7 +1045,15 @@ int64_t query_footprint(const Graph *g, const folty_query &q) {
                 (int64_t)sizeof(Heavy) * heavy_slots(T, -1) + 56 * (int64_t)ix.S;
     if (q.flags & FOLTY_QUERY_SMALLER_SIDE) b += 8 * (int64_t)ix.m + 4;
     if (!(q.flags & FOLTY_QUERY_NO_COUNTS)) b += 4 * ix.m_input;
-    return b + (1 << 20);
+    // the library scratch the query's sorts and scans ask for (sizes only)
+    const int64_t S2 = 2 * (int64_t)ix.S, NI1 = (int64_t)ix.NI + 1;
+    const size_t scratch = std::max({sort_pairs_u64_u32(nullptr, 0, nullptr, nullptr, nullptr, nullptr, S2,
+                                                        2 * pair_bits(ix.n), nullptr),
+                                     exclusive_scan_i64(nullptr, 0, nullptr, nullptr, NI1, nullptr),
+                                     exclusive_scan_i32_to_i64(nullptr, 0, nullptr, nullptr, NI1, nullptr),
+                                     inclusive_scan_i32(nullptr, 0, nullptr, nullptr, ix.m, nullptr),
+                                     exclusive_scan_i32(nullptr, 0, nullptr, nullptr, ix.n, nullptr)});
+    return b + (int64_t)scratch + (1 << 20);
 }
 
 void fill_stats_from_index(const Index &ix, folty_stats *s) {

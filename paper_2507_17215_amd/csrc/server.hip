@@ -202,6 +202,7 @@ void Server::worker_main(int me) {
         ws.reset();
     }
     (void)hipStreamSynchronize(s);
+    dev_forget_stream(s);
     (void)hipStreamDestroy(s);
 }
 
