@@ -430,7 +430,7 @@ void ensure_triangles(Graph *g);                 // ensure_tri_base on the graph
 // the counting pass's per-item triangles) so later wide queries filter in one pass
 void maybe_one_pass(Graph *g, const Workspace &ws, int64_t delta);
 
-// library-primitive wrappers (rocPRIM through hipCUB), all on `stream`
+// library-primitive wrappers (rocPRIM), all on `stream`
 size_t sort_pairs_u64_i32(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,
                           const int32_t *vin, int32_t *vout, int64_t n, int end_bit,
                           hipStream_t stream);

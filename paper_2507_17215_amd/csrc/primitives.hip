@@ -1,85 +1,103 @@
-// Library primitives (radix sort, prefix scan) from rocPRIM through hipCUB.
+// Library primitives (radix sort, prefix scan), called from rocPRIM directly.
 // Each wrapper returns the temporary storage it needs when tmp is null, and
 // otherwise runs on `stream`.  Used for grouping edges, orienting the static
 // graph and sorting the output pairs; the query's own kernels are in query.hip.
-#include <hipcub/hipcub.hpp>
+//
+// Radix sorts of keys wider than 24 bits use 9-bit digits with 1024-thread
+// tiles of 8 keys each; the others keep rocPRIM's tuned gfx950 configuration
+// (8-bit digits).  Measured on gfx950, keys with 32-bit values:
+//   70M keys of 45 bits: 3.65 ms tuned default, 3.41 ms 9-bit digits;
+//   26M keys of 45 bits: 1.50 -> 1.35 ms;  26M keys of 32 bits: 0.91 -> 0.87 ms;
+//   26M keys of 22 bits: 0.70 ms either way (3 passes of 8 bits, 3 of 9).
+// Wider digits do not pay (10 bits: 4.90 ms for the 70M keys; 11 and 12 bits
+// exceed the LDS of one workgroup).
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "folty_internal.h"
 
 namespace folty {
 
-#define FOLTY_CUB(call)                                                                  \
+#define FOLTY_PRIM(call)                                                                 \
     do {                                                                                 \
         hipError_t e_ = (call);                                                          \
         if (e_ != hipSuccess)                                                            \
             fail(FOLTY_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));                 \
     } while (0)
 
-template <class K, class V>
-static size_t sort_pairs(void *tmp, size_t tmp_bytes, const K *kin, K *kout, const V *vin,
-                         V *vout, int64_t n, int end_bit, hipStream_t s) {
+namespace {
+
+using WideKeys = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<256, 12>, rocprim::kernel_config<1024, 8>, 9,
+                                        rocprim::block_radix_rank_algorithm::match>>;
+
+template <class Cfg, class K, class V>
+size_t sort_with(void *tmp, size_t tmp_bytes, const K *kin, K *kout, const V *vin, V *vout, int64_t n, int end_bit,
+                 hipStream_t s) {
     size_t need = 0;
-    if (end_bit < 1) end_bit = 1;
-    if (end_bit > (int)(8 * sizeof(K))) end_bit = 8 * sizeof(K);
-    FOLTY_CUB(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, 0,
-                                                 end_bit, s));
+    FOLTY_PRIM((rocprim::radix_sort_pairs<Cfg>(nullptr, need, kin, kout, vin, vout, (size_t)n, 0u,
+                                               (unsigned)end_bit, s)));
     if (!tmp) return need;
     if (tmp_bytes < need) fail(FOLTY_EDEVICE, "sort scratch too small");
-    FOLTY_CUB(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, kin, kout, vin, vout, (int)n, 0,
-                                                 end_bit, s));
+    FOLTY_PRIM((rocprim::radix_sort_pairs<Cfg>(tmp, need, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)end_bit,
+                                               s)));
     return need;
 }
 
-size_t sort_pairs_u64_i32(void *tmp, size_t tb, const uint64_t *kin, uint64_t *kout,
-                          const int32_t *vin, int32_t *vout, int64_t n, int end_bit,
-                          hipStream_t s) {
-    return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
-}
-size_t sort_pairs_u64_u32(void *tmp, size_t tb, const uint64_t *kin, uint64_t *kout,
-                          const uint32_t *vin, uint32_t *vout, int64_t n, int end_bit,
-                          hipStream_t s) {
-    return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
-}
-size_t sort_pairs_u32_i32(void *tmp, size_t tb, const uint32_t *kin, uint32_t *kout,
-                          const int32_t *vin, int32_t *vout, int64_t n, int end_bit,
-                          hipStream_t s) {
-    return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
+// stable ascending sort of (key, value) pairs on bits [0, end_bit) of the keys
+template <class K, class V>
+size_t sort_pairs(void *tmp, size_t tmp_bytes, const K *kin, K *kout, const V *vin, V *vout, int64_t n, int end_bit,
+                  hipStream_t s) {
+    if (end_bit < 1) end_bit = 1;
+    if (end_bit > (int)(8 * sizeof(K))) end_bit = 8 * sizeof(K);
+    if (end_bit > 24) return sort_with<WideKeys>(tmp, tmp_bytes, kin, kout, vin, vout, n, end_bit, s);
+    return sort_with<rocprim::default_config>(tmp, tmp_bytes, kin, kout, vin, vout, n, end_bit, s);
 }
 
-size_t exclusive_scan_i64(void *tmp, size_t tb, const int64_t *in, int64_t *out, int64_t n,
-                          hipStream_t s) {
+template <class In, class Out>
+size_t scan_exclusive(void *tmp, size_t tb, const In *in, Out *out, int64_t n, hipStream_t s) {
     size_t need = 0;
-    FOLTY_CUB(hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, n, s));
+    FOLTY_PRIM(rocprim::exclusive_scan(nullptr, need, in, out, (Out)0, (size_t)n, rocprim::plus<Out>(), s));
     if (!tmp) return need;
-    FOLTY_CUB(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, n, s));
+    FOLTY_PRIM(rocprim::exclusive_scan(tmp, tb, in, out, (Out)0, (size_t)n, rocprim::plus<Out>(), s));
     return need;
+}
+
+} // namespace
+
+size_t sort_pairs_u64_i32(void *tmp, size_t tb, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
+                          int32_t *vout, int64_t n, int end_bit, hipStream_t s) {
+    return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
+}
+size_t sort_pairs_u64_u32(void *tmp, size_t tb, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
+                          uint32_t *vout, int64_t n, int end_bit, hipStream_t s) {
+    return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
+}
+size_t sort_pairs_u32_i32(void *tmp, size_t tb, const uint32_t *kin, uint32_t *kout, const int32_t *vin,
+                          int32_t *vout, int64_t n, int end_bit, hipStream_t s) {
+    return sort_pairs(tmp, tb, kin, kout, vin, vout, n, end_bit, s);
+}
+
+size_t exclusive_scan_i64(void *tmp, size_t tb, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+    return scan_exclusive(tmp, tb, in, out, n, s);
 }
 
 size_t exclusive_scan_i32_to_i64(void *tmp, size_t tb, const int32_t *in, int64_t *out, int64_t n,
                                  hipStream_t s) {
-    size_t need = 0;
-    FOLTY_CUB(hipcub::DeviceScan::ExclusiveScan(nullptr, need, in, out, hipcub::Sum(),
-                                                (int64_t)0, n, s));
-    if (!tmp) return need;
-    FOLTY_CUB(hipcub::DeviceScan::ExclusiveScan(tmp, tb, in, out, hipcub::Sum(), (int64_t)0, n, s));
-    return need;
+    return scan_exclusive(tmp, tb, in, out, n, s);
 }
 
-size_t inclusive_scan_i32(void *tmp, size_t tb, const int32_t *in, int32_t *out, int64_t n,
-                          hipStream_t s) {
-    size_t need = 0;
-    FOLTY_CUB(hipcub::DeviceScan::InclusiveSum(nullptr, need, in, out, n, s));
-    if (!tmp) return need;
-    FOLTY_CUB(hipcub::DeviceScan::InclusiveSum(tmp, tb, in, out, n, s));
-    return need;
+size_t exclusive_scan_i32(void *tmp, size_t tb, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+    return scan_exclusive(tmp, tb, in, out, n, s);
 }
 
-size_t exclusive_scan_i32(void *tmp, size_t tb, const int32_t *in, int32_t *out, int64_t n,
-                          hipStream_t s) {
+size_t inclusive_scan_i32(void *tmp, size_t tb, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
     size_t need = 0;
-    FOLTY_CUB(hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, n, s));
+    FOLTY_PRIM(rocprim::inclusive_scan(nullptr, need, in, out, (size_t)n, rocprim::plus<int32_t>(), s));
     if (!tmp) return need;
-    FOLTY_CUB(hipcub::DeviceScan::ExclusiveSum(tmp, tb, in, out, n, s));
+    FOLTY_PRIM(rocprim::inclusive_scan(tmp, tb, in, out, (size_t)n, rocprim::plus<int32_t>(), s));
     return need;
 }
 
