@@ -47,6 +47,12 @@ constexpr int32_t HG_BINS = 1 << 16; // degree histogram for the global h-index
 constexpr int32_t HG_LDS = 1024;     // degrees below this are counted in LDS first
 constexpr int PB_CAP = 256;          // buffered list entries per wavefront and class
 constexpr int RESCAN_SWEEPS = 8;     // sweeps that rescan long rows before their histograms are kept
+// Sweeps that evaluate every vertex, without marking: early on most vertices
+// drop in each sweep, and a marking pass over their rows plus a sweep over the
+// listed ones costs more than one sweep over all (70M edges: sweep over all
+// 0.74 ms; marking + listed sweep 1.58, 1.18, 0.89, 0.66 ms for sweeps 1-4).
+constexpr int DENSE_SWEEPS = 4;
+static_assert(DENSE_SWEEPS >= 1 && DENSE_SWEEPS <= RESCAN_SWEEPS, "kept histograms need every drop marked");
 
 __device__ inline int lane_id() { return __lane_id(); }
 
@@ -451,19 +457,20 @@ __device__ inline int32_t h_block(const int32_t *c, const int32_t *__restrict__ 
     }
 }
 
-// Sweep s, rows up to C1_MAX: re-evaluate the listed vertices from their rows;
-// the ones whose value drops are listed for the marking kernel.  With `rescan`,
-// the listed long rows' chunks also add their histograms into the rows' global
-// histograms (zero beforehand), which k_core_finish reads after this kernel.
-__global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan) {
+// Sweep s, rows up to C1_MAX: re-evaluate the listed vertices (`dense`: every
+// vertex) from their rows; the ones whose value drops are listed for the
+// marking kernel.  With `rescan`, the listed long rows' chunks also add their
+// histograms into the rows' global histograms (zero beforehand), which
+// k_core_finish reads after this kernel.
+__global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense) {
     __shared__ PushLds P;
     __shared__ int32_t s_h[HX_BINS];
     int32_t *ctr = B.ctr;
     const int par = s & 1;
-    const int32_t *in_cnt = s == 0 ? ctr + CT_ALL : ctr + CT_H + 4 * par;
+    const int32_t *in_cnt = dense ? ctr + CT_ALL : ctr + CT_H + 4 * par;
     const int32_t n0 = in_cnt[0], n1 = in_cnt[1], n2 = in_cnt[2];
-    const int32_t *L0 = s == 0 ? B.all[0] : B.pool[3 * par + 0];
-    const int32_t *L1 = s == 0 ? B.all[1] : B.pool[3 * par + 1];
+    const int32_t *L0 = dense ? B.all[0] : B.pool[3 * par + 0];
+    const int32_t *L1 = dense ? B.all[1] : B.pool[3 * par + 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int j = 0; j < 4; j++) {
             ctr[CT_H + 4 * (par ^ 1) + j] = 0; // filled by this sweep's marking kernel
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
     const int t = threadIdx.x;
     if (rescan && B.hbw > 0) {
         const int32_t n3 = in_cnt[3];
-        const int2 *L3 = s == 0 ? B.allc : B.poolc[1 + par];
+        const int2 *L3 = dense ? B.allc : B.poolc[1 + par];
         for (int32_t i = blockIdx.x; i < n3; i += gridDim.x) {
             const int2 ck = L3[i];
             const int32_t v = ck.x;
@@ -541,12 +548,12 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
 // histograms do not fit, from its row).  With `rescan` the histogram was made
 // by this sweep's k_core_sweep and is cleared after use; otherwise it is the
 // kept one, and a drop to h folds its levels above h into level h.
-__global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan) {
+__global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan, bool dense) {
     __shared__ HxLds H;
     int32_t *ctr = B.ctr;
     const int par = s & 1;
-    const int32_t n2 = s == 0 ? ctr[CT_ALL + 2] : ctr[CT_H + 4 * par + 2];
-    const int32_t *L2 = s == 0 ? B.all[2] : B.pool[3 * par + 2];
+    const int32_t n2 = dense ? ctr[CT_ALL + 2] : ctr[CT_H + 4 * par + 2];
+    const int32_t *L2 = dense ? B.all[2] : B.pool[3 * par + 2];
     const ListSet D = list_set(B.pool[6], B.pool[7], nullptr, B.poolc[0], ctr + CT_D + 4 * par, BIG_CHUNKS);
     const int t = threadIdx.x;
     for (int32_t i = blockIdx.x; i < n2; i += gridDim.x) {
@@ -955,9 +962,12 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     bool rescan = true;
     for (;;) {
         for (int i = 0; i < batch; i++, sw++) {
-            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan);
-            k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan);
-            k_core_mark<<<GRID, BLK, 0, s>>>(B, sw, rescan);
+            // dense sweeps need no lists; the last one's drops are marked for
+            // the first listed sweep
+            const bool dense = sw < DENSE_SWEEPS;
+            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan, dense);
+            k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan, dense);
+            if (sw + 1 >= DENSE_SWEEPS) k_core_mark<<<GRID, BLK, 0, s>>>(B, sw, rescan);
         }
         FOLTY_LAUNCHED();
         if (rescan && B.hbw > 0 && nbig > 0) {
