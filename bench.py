@@ -714,8 +714,16 @@ def main():
         full_s = t4 - t1
         bad_edges = int((got != cnt).sum())
         bad_pairs = check_against(rq, want)
-        ok = ok and bad_edges == 0 and bad_pairs == 0
-        out["parity_full"] = {"bit_exact": bad_edges == 0 and bad_pairs == 0, "edges": int(got.size),
+        # core numbers and the degeneracy rank of the same index, every vertex
+        # (outside the CPU baseline: the oracle's counts do not need them)
+        t5 = time.perf_counter()
+        bad_core = int((G.core_numbers() != oracle.core_numbers()).sum())
+        bad_rank = int((G.ranks() != oracle.degeneracy_rank()).sum())
+        rank_s = time.perf_counter() - t5
+        ok = ok and bad_edges == 0 and bad_pairs == 0 and bad_core == 0 and bad_rank == 0
+        out["parity_full"] = {"bit_exact": bad_edges == 0 and bad_pairs == 0 and bad_core == 0 and bad_rank == 0,
+                              "edges": int(got.size), "vertices": int(n),
+                              "core_mismatches": bad_core, "rank_mismatches": bad_rank,
                               "edge_mismatches": bad_edges, "pair_list_equal": bad_pairs == 0,
                               "n_pairs": int(want["pair_u"].size), "n_certificates": int(want["n_certificates"]),
                               "nonzero_counts": int(((cnt > 0) & (cnt != 0xFFFFFFFF)).sum()),
@@ -728,7 +736,8 @@ def main():
             "full_job_s": full_s, "cpu_model": cpu_model()}
         log(f"full parity delta={a.delta}: {bad_edges} edge mismatches over {got.size} edges, pair list "
             f"{'equal' if bad_pairs == 0 else 'DIFFERENT'} ({want['pair_u'].size} pairs, "
-            f"{want['n_certificates']} certificates); oracle {full_s:.1f}s on {threads} cores")
+            f"{want['n_certificates']} certificates); oracle {full_s:.1f}s on {threads} cores; "
+            f"{bad_core} core and {bad_rank} rank mismatches over {n} vertices (oracle peel {rank_s:.1f}s)")
     elif not a.no_parity:
         oracle = Oracle(n, g.src, g.dst, g.t, threads=threads)
     if not a.no_parity:

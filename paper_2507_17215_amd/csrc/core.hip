@@ -37,7 +37,7 @@ namespace {
 constexpr int BLK = 256;
 constexpr int WPB = BLK / 64;
 constexpr int GRID = 2048;           // persistent grid of the sweep and round kernels
-constexpr int FIN_GRID = 256;        // grid of the kernels over long rows only
+constexpr int FIN_GRID = 2048;       // grid of the kernels over long rows only (a block per row, latency-bound)
 constexpr int32_t C0_MAX = 16;       // rows up to this length: one lane per vertex
 constexpr int32_t C1_MAX = 1024;     // up to this length: one wavefront per vertex (16 entries per lane)
 constexpr int32_t CH = 2048;         // row work on longer rows goes in chunks of this many entries
@@ -99,7 +99,9 @@ struct CoreBufs {
     const int64_t *uoff;
     const int32_t *uadj;
     const int32_t *deg;
-    int32_t *c;     // upper bound of the core number; the core number at the end
+    uint16_t *c;    // upper bound of the core number; the core number at the end (values
+                    // are at most the h-index of the degrees, below 2^16 for fewer than
+                    // 2^31 static edges; 16 bits halve the bytes every gather moves)
     int32_t *old;   // value before this sweep's drop
     int32_t *stamp; // 1 + the sweep that last listed the vertex
     int32_t *cnt;   // remaining neighbours in the vertex's level (rounds)
@@ -107,6 +109,13 @@ struct CoreBufs {
     int32_t *bigid; // slot of a class-2 vertex (its place in all[2] and in gh)
     int32_t *gh;    // per class-2 vertex: how many neighbours hold each value, capped at its own
     int32_t hbw;    // histogram levels per class-2 vertex (0: they do not fit; rows are rescanned)
+    // Once the histograms are kept: each class-2 row reordered by its
+    // neighbours' values at that point (capped at the row's own value x0),
+    // highest first, in hadj at the row's place in uadj; pc[k] = how many of
+    // its entries had value >= k then (k <= x0).  Values only fall, so a
+    // neighbour whose value is >= k now lies in the first pc[k] entries.
+    const int32_t *hadj; // null while rows are rescanned
+    const int32_t *pc;
     int32_t *ctr;
     int32_t *all[3];
     int2 *allc;
@@ -116,6 +125,11 @@ struct CoreBufs {
                       // rounds: frontier chunks by round mod 3
     int32_t n;
 };
+
+// entries of class-2 row v (reordered) whose value was >= k at the reorder; k <= x0
+__device__ inline int32_t big_prefix(const CoreBufs &B, int32_t v, int32_t k) {
+    return B.pc[(int64_t)B.bigid[v] * B.hbw + k];
+}
 
 __device__ inline ListSet list_set(int32_t *l0, int32_t *l1, int32_t *l2, int2 *ch, int32_t *cnt, int big) {
     ListSet L;
@@ -267,7 +281,7 @@ __global__ __launch_bounds__(BLK) void k_core_init(CoreBufs B) {
         int cls = -1;
         if (v < B.n) {
             const int32_t d = B.deg[v];
-            B.c[v] = d < hg ? d : hg;
+            B.c[v] = (uint16_t)(d < hg ? d : hg);
             B.stamp[v] = 0;
             B.cnt[v] = 0;
             B.lr[v] = -1;
@@ -332,11 +346,83 @@ __global__ __launch_bounds__(BLK) void k_big_hist(CoreBufs B) {
     }
 }
 
+// Reorder of the class-2 rows when their histograms start being kept, from the
+// same values as k_big_hist (nothing changes them in between).  k_big_prefix:
+// per row, pc[k] = entries at level >= k (level = min(value, x0)) from the
+// fresh histogram, and the write cursor of level k = entries above it.
+__global__ __launch_bounds__(BLK) void k_big_prefix(CoreBufs B, int32_t *__restrict__ pc, int32_t *__restrict__ cur) {
+    __shared__ int32_t s_h[HX_BINS];
+    __shared__ int32_t s_sum[BLK];
+    const int32_t n2 = B.ctr[CT_ALL + 2];
+    const int t = threadIdx.x;
+    for (int32_t i = blockIdx.x; i < n2; i += gridDim.x) {
+        const int32_t v = B.all[2][i];
+        const int32_t x = B.c[v];
+        const int64_t row = (int64_t)B.bigid[v] * B.hbw;
+        for (int32_t k = t; k <= x; k += BLK) s_h[k] = B.gh[row + k];
+        __syncthreads();
+        // thread t sums the levels [t * per, (t + 1) * per), then walks them top down
+        const int32_t per = (x + 1 + BLK - 1) / BLK;
+        const int32_t lo = t * per, hi = lo + per < x + 1 ? lo + per : x + 1;
+        int32_t part = 0;
+        for (int32_t k = lo; k < hi; k++) part += s_h[k];
+        s_sum[t] = part;
+        __syncthreads();
+        int32_t above = 0;
+        for (int k = t + 1; k < BLK; k++) above += s_sum[k];
+        for (int32_t k = hi - 1; k >= lo; k--) {
+            cur[row + k] = above;
+            above += s_h[k];
+            pc[row + k] = above;
+        }
+        for (int32_t k = x + 1 + t; k < B.hbw; k += BLK) pc[row + k] = 0;
+        __syncthreads();
+    }
+}
+
+// k_big_scatter: each chunk reserves, per level, a range of its row's level
+// (one global atomic per level present), then places its entries in LDS order.
+__global__ __launch_bounds__(BLK) void k_big_scatter(CoreBufs B, int32_t *__restrict__ cur,
+                                                     int32_t *__restrict__ hadj) {
+    __shared__ int32_t s_h[HX_BINS];
+    const int32_t n2 = B.ctr[CT_ALL + 3];
+    const int t = threadIdx.x;
+    for (int32_t i = blockIdx.x; i < n2; i += gridDim.x) {
+        const int2 ck = B.allc[i];
+        const int32_t v = ck.x;
+        const int64_t b = B.uoff[v];
+        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
+        const int32_t x = B.c[v];
+        const int32_t lo = ck.y * CH, hi = lo + CH < d ? lo + CH : d;
+        for (int32_t k = t; k <= x; k += BLK) s_h[k] = 0;
+        __syncthreads();
+        const ChunkRow r = load_chunk(B.uadj, b, lo, hi);
+        int32_t y[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; j++) {
+            y[j] = r.ok[j] ? B.c[r.u[j]] : -1;
+            y[j] = y[j] < x ? y[j] : x;
+        }
+#pragma unroll
+        for (int j = 0; j < CPT; j++)
+            if (y[j] >= 0) atomicAdd(&s_h[y[j]], 1);
+        __syncthreads();
+        int32_t *cr = cur + (int64_t)B.bigid[v] * B.hbw;
+        for (int32_t k = t; k <= x; k += BLK)
+            if (s_h[k]) s_h[k] = atomicAdd(&cr[k], s_h[k]);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; j++)
+            if (y[j] >= 0) hadj[b + atomicAdd(&s_h[y[j]], 1)] = r.u[j];
+        __syncthreads();
+    }
+}
+
 // ---- h-index evaluations ---------------------------------------------------------------
 // H capped at x (the current value): the largest h <= x with count(>= h) >= h.
 // count(ge) >= ge for ge = count(>= x) < x, so the search runs over [ge, x - 1].
 
-__device__ inline int32_t h_lane(const int32_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
+__device__ inline int32_t h_lane(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
                                  int32_t x) {
     int32_t u[C0_MAX], val[C0_MAX];
 #pragma unroll
@@ -361,7 +447,7 @@ __device__ inline int32_t h_lane(const int32_t *c, const int32_t *__restrict__ a
 }
 
 // one wavefront; x, b, d are wavefront-uniform
-__device__ inline int32_t h_wave(const int32_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
+__device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
                                  int32_t x) {
     const int lane = lane_id();
     constexpr int PER = C1_MAX / 64;
@@ -432,7 +518,7 @@ __device__ inline int32_t window_best(HxLds &L, int32_t bot, int32_t top, int32_
 // One block over a whole row: LDS histograms of windows of at most HX_BINS
 // levels, from the top down until one holds the answer.  Used only when the
 // per-row histograms would not fit (h-index of the degrees at or above HX_BINS).
-__device__ inline int32_t h_block(const int32_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
+__device__ inline int32_t h_block(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
                                   int32_t x, HxLds &L) {
     const int t = threadIdx.x;
     int32_t top = x;
@@ -591,7 +677,8 @@ __global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool
         if (t == 0 && h < x) {
             B.old[v] = x;
             B.c[v] = h;
-            push_chunks(D, v, d);
+            // a reordered row is marked only where values were above h
+            push_chunks(D, v, B.pc && !rescan ? big_prefix(B, v, h + 1) : d);
         }
         __syncthreads();
     }
@@ -650,14 +737,17 @@ __global__ __launch_bounds__(BLK) void k_core_mark(CoreBufs B, int32_t s, bool r
     const int32_t tag = s + 1;
     const int lane = lane_id();
     const int t = threadIdx.x;
+    const bool sorted = B.pc && !rescan;
+    const int32_t *big_adj = sorted ? B.hadj : B.uadj;
     for (int32_t i = blockIdx.x; i < n3; i += gridDim.x) {
         const int2 ck = B.poolc[0][i];
         const int32_t v = ck.x;
         const int64_t b = B.uoff[v];
-        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
         const int32_t h = B.c[v], xo = B.old[v];
+        // reordered rows: only neighbours whose value was above h can have c(w) > h
+        const int32_t d = sorted ? big_prefix(B, v, h + 1) : (int32_t)(B.uoff[v + 1] - b);
         const int32_t lo = ck.y * CH, hi = lo + CH < d ? lo + CH : d;
-        const ChunkRow r = load_chunk(B.uadj, b, lo, hi);
+        const ChunkRow r = load_chunk(big_adj, b, lo, hi);
         int32_t cw[CPT];
 #pragma unroll
         for (int j = 0; j < CPT; j++) cw[j] = r.ok[j] ? B.c[r.u[j]] : 0;
@@ -723,10 +813,12 @@ __global__ __launch_bounds__(BLK) void k_level_count(CoreBufs B) {
         const int2 ck = B.allc[i];
         const int32_t v = ck.x;
         const int64_t b = B.uoff[v];
-        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
         const int32_t k = B.c[v];
+        // reordered rows: a neighbour of core >= k had a value >= k at the reorder
+        const int32_t d = B.pc ? big_prefix(B, v, k) : (int32_t)(B.uoff[v + 1] - b);
         const int32_t lo = ck.y * CH, hi = lo + CH < d ? lo + CH : d;
-        const ChunkRow r = load_chunk(B.uadj, b, lo, hi);
+        if (lo >= hi) continue; // block-uniform
+        const ChunkRow r = load_chunk(B.pc ? B.hadj : B.uadj, b, lo, hi);
         int32_t part = 0;
 #pragma unroll
         for (int j = 0; j < CPT; j++) part += (r.ok[j] && B.c[r.u[j]] >= k) ? 1 : 0;
@@ -819,10 +911,12 @@ __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
         const int32_t v = ck.x;
         if (ck.y == 0 && t == 0) B.lr[v] = r;
         const int64_t b = B.uoff[v];
-        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
         const int32_t k = B.c[v];
+        // reordered rows: a neighbour of core k had a value >= k at the reorder
+        const int32_t d = B.pc ? big_prefix(B, v, k) : (int32_t)(B.uoff[v + 1] - b);
         const int32_t lo = ck.y * CH, hi = lo + CH < d ? lo + CH : d;
-        const ChunkRow rw = load_chunk(B.uadj, b, lo, hi);
+        if (lo >= hi) continue; // block-uniform
+        const ChunkRow rw = load_chunk(B.pc ? B.hadj : B.uadj, b, lo, hi);
         int32_t cu[CPT];
 #pragma unroll
         for (int j = 0; j < CPT; j++) cu[j] = rw.ok[j] ? B.c[rw.u[j]] : -1;
@@ -876,12 +970,13 @@ __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
 
 // rank key core * R + round within the level (R = the rounds taken); the sort
 // that follows breaks ties by id
-__global__ void k_level_keys(const int32_t *__restrict__ c, const int32_t *__restrict__ lr, int32_t n, uint32_t R,
-                             uint32_t *__restrict__ key, int32_t *ctr) {
+__global__ void k_level_keys(const uint16_t *__restrict__ c, const int32_t *__restrict__ lr, int32_t n, uint32_t R,
+                             uint32_t *__restrict__ key, int32_t *__restrict__ core, int32_t *ctr) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int32_t r = lr[v];
     if (r < 0) atomicAdd(&ctr[CT_LEFT], 1);
+    core[v] = c[v];
     key[v] = (uint32_t)c[v] * R + (uint32_t)(r < 0 ? 0 : r);
 }
 
@@ -901,8 +996,9 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     FOLTY_HIP(hipStreamSynchronize(s));
     // chunk lists: every class-2 row has more than C1_MAX entries
     const int64_t chunk_cap = adj_n / CH + adj_n / (C1_MAX + 1) + 1;
-    DevBuf ctr, hist, old, stamp, cnt, lr, bigid, all, allc, pool, poolc;
+    DevBuf ctr, hist, val, old, stamp, cnt, lr, bigid, all, allc, pool, poolc;
     ctr.ensure(4 * CT_WORDS);
+    val.ensure(2 * (size_t)n);
     hist.ensure(4 * (size_t)HG_BINS);
     old.ensure(4 * (size_t)n);
     stamp.ensure(4 * (size_t)n);
@@ -919,7 +1015,7 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     B.uoff = uoff;
     B.uadj = uadj;
     B.deg = deg;
-    B.c = core;
+    B.c = val.as<uint16_t>();
     B.old = old.as<int32_t>();
     B.stamp = stamp.as<int32_t>();
     B.cnt = cnt.as<int32_t>();
@@ -942,8 +1038,9 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     };
     read_ctr();
     const int32_t hg = h[CT_HG], nbig = h[CT_ALL + 2];
+    if (hg > UINT16_MAX) fail(FOLTY_EOVERFLOW, "degree h-index %d does not fit 16-bit core values", hg);
     // per class-2 vertex: a histogram over the levels 0..hg
-    DevBuf gh;
+    DevBuf gh, pc, cur, hadj;
     B.hbw = hg < HX_BINS ? hg + 1 : 0;
     if (B.hbw > 0 && nbig > 0) {
         gh.ensure(4 * (size_t)B.hbw * (size_t)nbig);
@@ -971,8 +1068,17 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
         }
         FOLTY_LAUNCHED();
         if (rescan && B.hbw > 0 && nbig > 0) {
-            k_big_hist<<<GRID, BLK, 0, s>>>(B); // from the current values
+            // histograms and reordered rows from the current values
+            const size_t hn = (size_t)B.hbw * (size_t)nbig;
+            pc.ensure(4 * hn);
+            cur.ensure(4 * hn);
+            hadj.ensure(4 * (size_t)adj_n + 4);
+            k_big_hist<<<GRID, BLK, 0, s>>>(B);
+            k_big_prefix<<<FIN_GRID, BLK, 0, s>>>(B, pc.as<int32_t>(), cur.as<int32_t>());
+            k_big_scatter<<<GRID, BLK, 0, s>>>(B, cur.as<int32_t>(), hadj.as<int32_t>());
             FOLTY_LAUNCHED();
+            B.hadj = hadj.as<int32_t>();
+            B.pc = pc.as<int32_t>();
         }
         rescan = false;
         read_ctr();
@@ -1002,7 +1108,8 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     const uint64_t max_key = (uint64_t)hg * (uint64_t)rounds + (uint64_t)(rounds - 1);
     if (max_key > UINT32_MAX)
         fail(FOLTY_EOVERFLOW, "rank keys need %d bits (h-index %d, %d rounds)", bit_length(max_key), hg, rounds);
-    k_level_keys<<<grid_for(n, BLK), BLK, 0, s>>>(core, lr.as<int32_t>(), n, (uint32_t)rounds, key, ctr.as<int32_t>());
+    k_level_keys<<<grid_for(n, BLK), BLK, 0, s>>>(B.c, lr.as<int32_t>(), n, (uint32_t)rounds, key, core,
+                                                  ctr.as<int32_t>());
     FOLTY_LAUNCHED();
     read_ctr();
     if (h[CT_LEFT] != 0) fail(FOLTY_EDEVICE, "%d vertices were not removed by the level rounds", h[CT_LEFT]);
