@@ -46,11 +46,14 @@ constexpr int32_t HX_BINS = 4096;    // LDS histogram of the h-index of a long r
 constexpr int32_t HG_BINS = 1 << 16; // degree histogram for the global h-index
 constexpr int32_t HG_LDS = 1024;     // degrees below this are counted in LDS first
 constexpr int PB_CAP = 256;          // buffered list entries per wavefront and class
-constexpr int RESCAN_SWEEPS = 8;     // sweeps that rescan long rows before their histograms are kept
+// Sweeps that rescan long rows before their histograms are kept and the rows
+// reordered (70M edges, build ms: 4 -> 19.8, 3 -> 19.9, 5 -> 20.0, 8 -> 20.3).
+constexpr int RESCAN_SWEEPS = 4;
 // Sweeps that evaluate every vertex, without marking: early on most vertices
 // drop in each sweep, and a marking pass over their rows plus a sweep over the
 // listed ones costs more than one sweep over all (70M edges: sweep over all
-// 0.74 ms; marking + listed sweep 1.58, 1.18, 0.89, 0.66 ms for sweeps 1-4).
+// 0.6 ms; marking + listed sweep 1.58, 1.18, 0.89, 0.66 ms for sweeps 1-4 with
+// 32-bit values; build ms with 4 rescanning sweeps: 2 dense 20.5, 3 20.1, 4 19.8).
 constexpr int DENSE_SWEEPS = 4;
 static_assert(DENSE_SWEEPS >= 1 && DENSE_SWEEPS <= RESCAN_SWEEPS, "kept histograms need every drop marked");
 
@@ -543,14 +546,82 @@ __device__ inline int32_t h_block(const uint16_t *c, const int32_t *__restrict__
     }
 }
 
+// Sweep s, long rows: a listed row is re-evaluated from its histogram (or, if
+// histograms do not fit, from its row).  With `rescan` the histogram was made
+// by this sweep's k_core_sweep and is cleared after use; otherwise it is the
+// kept one, and a drop to h folds its levels above h into level h.  Every
+// thread of the block calls this.
+__device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bool dense, HxLds &H) {
+    int32_t *ctr = B.ctr;
+    const int par = s & 1;
+    const int32_t n2 = dense ? ctr[CT_ALL + 2] : ctr[CT_H + 4 * par + 2];
+    const int32_t *L2 = dense ? B.all[2] : B.pool[3 * par + 2];
+    const ListSet D = list_set(B.pool[6], B.pool[7], nullptr, B.poolc[0], ctr + CT_D + 4 * par, BIG_CHUNKS);
+    const int t = threadIdx.x;
+    for (int32_t i = blockIdx.x; i < n2; i += gridDim.x) {
+        const int32_t v = L2[i];
+        const int32_t x = B.c[v];
+        const int64_t b = B.uoff[v];
+        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
+        int32_t h = x;
+        if (B.hbw > 0 && rescan) {
+            int32_t *gh = B.gh + (int64_t)B.bigid[v] * B.hbw;
+            for (int32_t k = t; k <= x; k += BLK) {
+                H.hist[k] = gh[k];
+                gh[k] = 0;
+            }
+            __syncthreads();
+            h = window_best(H, 0, x, 0);
+        } else if (B.hbw > 0) {
+            int32_t *gh = B.gh + (int64_t)B.bigid[v] * B.hbw;
+            if (gh[x] < x) { // block-uniform: only this block writes gh[v] during the sweep
+                for (int32_t k = t; k <= x; k += BLK) H.hist[k] = gh[k];
+                __syncthreads();
+                h = window_best(H, 0, x, 0);
+                // level h now holds every value at or above h
+                int32_t part = 0;
+                for (int32_t k = h + 1 + t; k <= x; k += BLK) {
+                    part += H.hist[k];
+                    gh[k] = 0;
+                }
+                part = wave_sum(part);
+                if (lane_id() == 0 && part) atomicAdd(&gh[h], part);
+            }
+        } else {
+            h = h_block(B.c, B.uadj, b, d, x, H);
+        }
+        if (t == 0 && h < x) {
+            B.old[v] = x;
+            B.c[v] = h;
+            // a reordered row is marked only where values were above h
+            push_chunks(D, v, B.pc && !rescan ? big_prefix(B, v, h + 1) : d);
+        }
+        __syncthreads();
+    }
+}
+
+// A separate launch only when this sweep's k_core_sweep builds the histograms.
+__global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan, bool dense) {
+    __shared__ HxLds H;
+    finish_rows(B, s, rescan, dense, H);
+}
+
 // Sweep s, rows up to C1_MAX: re-evaluate the listed vertices (`dense`: every
 // vertex) from their rows; the ones whose value drops are listed for the
-// marking kernel.  With `rescan`, the listed long rows' chunks also add their
-// histograms into the rows' global histograms (zero beforehand), which
-// k_core_finish reads after this kernel.
-__global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense) {
+// marking kernel.  With `rescan` (and histograms that fit), the listed long
+// rows' chunks also add their histograms into the rows' global histograms
+// (zero beforehand), which k_core_finish reads after this kernel; otherwise the
+// long rows are evaluated here too (`fused`), from the kept histograms, which
+// only the marking kernels change.
+union SweepLds {
+    int32_t h[HX_BINS];
+    HxLds H;
+};
+
+__global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense, bool fused) {
     __shared__ PushLds P;
-    __shared__ int32_t s_h[HX_BINS];
+    __shared__ SweepLds U;
+    int32_t *s_h = U.h;
     int32_t *ctr = B.ctr;
     const int par = s & 1;
     const int32_t *in_cnt = dense ? ctr + CT_ALL : ctr + CT_H + 4 * par;
@@ -567,6 +638,7 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
     Pusher p = make_pusher(&P, list_set(B.pool[6], B.pool[7], nullptr, B.poolc[0], ctr + CT_D + 4 * par, BIG_CHUNKS));
     const int lane = lane_id();
     const int t = threadIdx.x;
+    if (fused) finish_rows(B, s, rescan, dense, U.H);
     if (rescan && B.hbw > 0) {
         const int32_t n3 = in_cnt[3];
         const int2 *L3 = dense ? B.allc : B.poolc[1 + par];
@@ -628,60 +700,6 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
         push(p, cls, v, 0);
     }
     push_finish(p);
-}
-
-// Sweep s, long rows: a listed row is re-evaluated from its histogram (or, if
-// histograms do not fit, from its row).  With `rescan` the histogram was made
-// by this sweep's k_core_sweep and is cleared after use; otherwise it is the
-// kept one, and a drop to h folds its levels above h into level h.
-__global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan, bool dense) {
-    __shared__ HxLds H;
-    int32_t *ctr = B.ctr;
-    const int par = s & 1;
-    const int32_t n2 = dense ? ctr[CT_ALL + 2] : ctr[CT_H + 4 * par + 2];
-    const int32_t *L2 = dense ? B.all[2] : B.pool[3 * par + 2];
-    const ListSet D = list_set(B.pool[6], B.pool[7], nullptr, B.poolc[0], ctr + CT_D + 4 * par, BIG_CHUNKS);
-    const int t = threadIdx.x;
-    for (int32_t i = blockIdx.x; i < n2; i += gridDim.x) {
-        const int32_t v = L2[i];
-        const int32_t x = B.c[v];
-        const int64_t b = B.uoff[v];
-        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
-        int32_t h = x;
-        if (B.hbw > 0 && rescan) {
-            int32_t *gh = B.gh + (int64_t)B.bigid[v] * B.hbw;
-            for (int32_t k = t; k <= x; k += BLK) {
-                H.hist[k] = gh[k];
-                gh[k] = 0;
-            }
-            __syncthreads();
-            h = window_best(H, 0, x, 0);
-        } else if (B.hbw > 0) {
-            int32_t *gh = B.gh + (int64_t)B.bigid[v] * B.hbw;
-            if (gh[x] < x) { // block-uniform: nothing else writes gh[v] in this kernel
-                for (int32_t k = t; k <= x; k += BLK) H.hist[k] = gh[k];
-                __syncthreads();
-                h = window_best(H, 0, x, 0);
-                // level h now holds every value at or above h
-                int32_t part = 0;
-                for (int32_t k = h + 1 + t; k <= x; k += BLK) {
-                    part += H.hist[k];
-                    gh[k] = 0;
-                }
-                part = wave_sum(part);
-                if (lane_id() == 0 && part) atomicAdd(&gh[h], part);
-            }
-        } else {
-            h = h_block(B.c, B.uadj, b, d, x, H);
-        }
-        if (t == 0 && h < x) {
-            B.old[v] = x;
-            B.c[v] = h;
-            // a reordered row is marked only where values were above h
-            push_chunks(D, v, B.pc && !rescan ? big_prefix(B, v, h + 1) : d);
-        }
-        __syncthreads();
-    }
 }
 
 // Marking of sweep s, for a dropped vertex u (value xo -> h) and its neighbour w.
@@ -1053,7 +1071,8 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     // bound them; the cap turns a logic error into an error code
     // The first sweeps drop many vertices at once; long rows are rescanned then,
     // since keeping their histograms would send every drop next to a hub to the
-    // same few counters.  After them the histograms are made once and kept.
+    // same few counters.  After them the histograms are made once and kept, and
+    // the long rows reordered by their neighbours' values.
     int32_t sw = 0;
     int batch = RESCAN_SWEEPS;
     bool rescan = true;
@@ -1062,8 +1081,9 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
             // dense sweeps need no lists; the last one's drops are marked for
             // the first listed sweep
             const bool dense = sw < DENSE_SWEEPS;
-            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan, dense);
-            k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan, dense);
+            const bool fused = !(rescan && B.hbw > 0);
+            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan, dense, fused);
+            if (!fused) k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan, dense);
             if (sw + 1 >= DENSE_SWEEPS) k_core_mark<<<GRID, BLK, 0, s>>>(B, sw, rescan);
         }
         FOLTY_LAUNCHED();
@@ -1085,7 +1105,9 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
         const int par = sw & 1; // the lists the next sweep would read
         if (h[CT_H + 4 * par] + h[CT_H + 4 * par + 1] + h[CT_H + 4 * par + 2] == 0) break;
         if ((int64_t)sw > adj_n + 64) fail(FOLTY_EDEVICE, "core sweeps did not settle in %d sweeps", sw);
-        batch = batch < 16 ? 2 * batch : 16;
+        // 16 sweeps, then 8 at a time: an empty sweep costs about 5 us of
+        // launches, a counter read about as much as 3 of them
+        batch = batch == RESCAN_SWEEPS ? 16 : 8;
     }
     const int32_t sweeps = h[CT_SWEEPS];
 

@@ -3,14 +3,16 @@
 // otherwise runs on `stream`.  Used for grouping edges, orienting the static
 // graph and sorting the output pairs; the query's own kernels are in query.hip.
 //
-// Radix sorts of keys wider than 24 bits use 9-bit digits with 1024-thread
-// tiles of 8 keys each; the others keep rocPRIM's tuned gfx950 configuration
-// (8-bit digits).  Measured on gfx950, keys with 32-bit values:
-//   70M keys of 45 bits: 3.65 ms tuned default, 3.41 ms 9-bit digits;
-//   26M keys of 45 bits: 1.50 -> 1.35 ms;  26M keys of 32 bits: 0.91 -> 0.87 ms;
-//   26M keys of 22 bits: 0.70 ms either way (3 passes of 8 bits, 3 of 9).
-// Wider digits do not pay (10 bits: 4.90 ms for the 70M keys; 11 and 12 bits
-// exceed the LDS of one workgroup).
+// Radix sorts use 9-bit digits with 1024-thread tiles of 8 keys each, and a
+// digit-histogram pass of 512 threads x 32 keys per block (with 256 x 12 keys
+// per block that pass takes as long as a whole scatter pass, about as many
+// global atomics as keys / 1.2 landing on a few thousand counters).  Measured on gfx950,
+// keys with 32-bit values, rocPRIM default -> this configuration:
+//   70M keys of 45 bits 3.65 -> 3.04 ms;  26M keys of 44 bits 1.48 -> 1.22 ms;
+//   26M keys of 22 bits 0.69 -> 0.55 ms;  4M keys of 32 bits 0.18 -> 0.17 ms.
+// Histogram blocks of 256 x 12 keys: 3.36 / 1.32 / 0.69 / 0.19 ms.  8-bit
+// digits were slower at every size, 10-bit digits much slower (4.90 ms for the
+// 70M keys), and 11 or 12 bits exceed the LDS of one workgroup.
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -28,9 +30,9 @@ namespace folty {
 
 namespace {
 
-using WideKeys = rocprim::radix_sort_config<
+using Onesweep = rocprim::radix_sort_config<
     rocprim::default_config, rocprim::default_config,
-    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<256, 12>, rocprim::kernel_config<1024, 8>, 9,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<512, 32>, rocprim::kernel_config<1024, 8>, 9,
                                         rocprim::block_radix_rank_algorithm::match>>;
 
 template <class Cfg, class K, class V>
@@ -52,8 +54,7 @@ size_t sort_pairs(void *tmp, size_t tmp_bytes, const K *kin, K *kout, const V *v
                   hipStream_t s) {
     if (end_bit < 1) end_bit = 1;
     if (end_bit > (int)(8 * sizeof(K))) end_bit = 8 * sizeof(K);
-    if (end_bit > 24) return sort_with<WideKeys>(tmp, tmp_bytes, kin, kout, vin, vout, n, end_bit, s);
-    return sort_with<rocprim::default_config>(tmp, tmp_bytes, kin, kout, vin, vout, n, end_bit, s);
+    return sort_with<Onesweep>(tmp, tmp_bytes, kin, kout, vin, vout, n, end_bit, s);
 }
 
 template <class In, class Out>
