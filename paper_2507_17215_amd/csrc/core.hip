@@ -425,8 +425,10 @@ __global__ __launch_bounds__(BLK) void k_big_scatter(CoreBufs B, int32_t *__rest
 // H capped at x (the current value): the largest h <= x with count(>= h) >= h.
 // count(ge) >= ge for ge = count(>= x) < x, so the search runs over [ge, x - 1].
 
+// Both also give ge_out = count(>= the answer) over the row, which is the
+// vertex's count of neighbours at or above its own value.
 __device__ inline int32_t h_lane(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
-                                 int32_t x) {
+                                 int32_t x, int32_t &ge_out) {
     int32_t u[C0_MAX], val[C0_MAX];
 #pragma unroll
     for (int j = 0; j < C0_MAX; j++) u[j] = j < d ? adj[b + j] : 0;
@@ -439,19 +441,23 @@ __device__ inline int32_t h_lane(const uint16_t *c, const int32_t *__restrict__ 
         return k;
     };
     const int32_t ge = count(x);
-    if (ge >= x) return x;
+    if (ge >= x) {
+        ge_out = ge;
+        return x;
+    }
     int32_t lo = ge, hi = x - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
         if (count(mid) >= mid) lo = mid;
         else hi = mid - 1;
     }
+    ge_out = count(lo);
     return lo;
 }
 
 // one wavefront; x, b, d are wavefront-uniform
 __device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
-                                 int32_t x) {
+                                 int32_t x, int32_t &ge_out) {
     const int lane = lane_id();
     constexpr int PER = C1_MAX / 64;
     int32_t u[PER], val[PER];
@@ -469,13 +475,17 @@ __device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ 
         return wave_sum(k);
     };
     const int32_t ge = count(x);
-    if (ge >= x) return x;
+    if (ge >= x) {
+        ge_out = ge;
+        return x;
+    }
     int32_t lo = ge, hi = x - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
         if (count(mid) >= mid) lo = mid;
         else hi = mid - 1;
     }
+    ge_out = count(lo);
     return lo;
 }
 
@@ -672,8 +682,10 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
         const int64_t b = B.uoff[v];
         const int32_t d = (int32_t)(B.uoff[v + 1] - b);
         const int32_t x = B.c[v];
-        const int32_t h = h_wave(B.c, B.uadj, b, d, x);
+        int32_t ge;
+        const int32_t h = h_wave(B.c, B.uadj, b, d, x, ge);
         const bool drop = lane == 0 && h < x;
+        if (lane == 0) B.cnt[v] = ge;
         if (drop) {
             B.old[v] = x;
             B.c[v] = h;
@@ -690,7 +702,9 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
             const int64_t b = B.uoff[v];
             const int32_t d = (int32_t)(B.uoff[v + 1] - b);
             const int32_t x = B.c[v];
-            const int32_t h = h_lane(B.c, B.uadj, b, d, x);
+            int32_t ge;
+            const int32_t h = h_lane(B.c, B.uadj, b, d, x, ge);
+            B.cnt[v] = ge;
             if (h < x) {
                 B.old[v] = x;
                 B.c[v] = h;
@@ -818,8 +832,12 @@ __global__ __launch_bounds__(BLK) void k_core_mark(CoreBufs B, int32_t s, bool r
 
 // ---- the levels' rounds, all levels at once ------------------------------------------------
 // cnt(v) = |{u in N(v) : core(u) >= core(v)}|; a vertex with cnt(v) <= core(v)
-// goes in round 0 of its level (long rows: their chunks add partial counts, and
-// k_level_big decides).
+// goes in round 0 of its level.  Rows up to C1_MAX hold the count their last
+// h-index evaluation stored: it is exact once the values settle, since a later
+// drop of a neighbour from at or above the vertex's value to below it lists the
+// vertex for another evaluation.  Long rows read level core(v) of their kept
+// histogram in k_level_big, or, when histograms do not fit, their chunks add
+// partial counts here and k_level_big decides.
 __global__ __launch_bounds__(BLK) void k_level_count(CoreBufs B) {
     __shared__ PushLds P;
     int32_t *ctr = B.ctr;
@@ -827,83 +845,69 @@ __global__ __launch_bounds__(BLK) void k_level_count(CoreBufs B) {
     Pusher p = make_pusher(&P, list_set(B.pool[0], B.pool[1], nullptr, B.poolc[0], ctr + CT_F + 0, BIG_CHUNKS));
     const int lane = lane_id();
     const int t = threadIdx.x;
-    for (int32_t i = blockIdx.x; i < n3; i += gridDim.x) {
-        const int2 ck = B.allc[i];
-        const int32_t v = ck.x;
-        const int64_t b = B.uoff[v];
-        const int32_t k = B.c[v];
-        // reordered rows: a neighbour of core >= k had a value >= k at the reorder
-        const int32_t d = B.pc ? big_prefix(B, v, k) : (int32_t)(B.uoff[v + 1] - b);
-        const int32_t lo = ck.y * CH, hi = lo + CH < d ? lo + CH : d;
-        if (lo >= hi) continue; // block-uniform
-        const ChunkRow r = load_chunk(B.pc ? B.hadj : B.uadj, b, lo, hi);
-        int32_t part = 0;
+    if (B.hbw == 0) {
+        for (int32_t i = blockIdx.x; i < n3; i += gridDim.x) {
+            const int2 ck = B.allc[i];
+            const int32_t v = ck.x;
+            const int64_t b = B.uoff[v];
+            const int32_t k = B.c[v];
+            const int32_t d = (int32_t)(B.uoff[v + 1] - b);
+            const int32_t lo = ck.y * CH, hi = lo + CH < d ? lo + CH : d;
+            const ChunkRow r = load_chunk(B.uadj, b, lo, hi);
+            int32_t part = 0;
 #pragma unroll
-        for (int j = 0; j < CPT; j++) part += (r.ok[j] && B.c[r.u[j]] >= k) ? 1 : 0;
-        part = wave_sum(part);
-        if (lane == 0 && part) atomicAdd(&B.cnt[v], part);
+            for (int j = 0; j < CPT; j++) part += (r.ok[j] && B.c[r.u[j]] >= k) ? 1 : 0;
+            part = wave_sum(part);
+            if (lane == 0 && part) atomicAdd(&B.cnt[v], part);
+        }
     }
-    const int64_t gwave = ((int64_t)blockIdx.x * BLK + t) >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * WPB;
-    for (int64_t i = gwave; i < n1; i += nwaves) {
-        const int32_t v = B.all[1][i];
-        const int64_t b = B.uoff[v];
-        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
-        const int32_t k = B.c[v];
-        constexpr int PER = C1_MAX / 64;
-        int32_t u[PER];
-#pragma unroll
-        for (int j = 0; j < PER; j++) u[j] = lane + 64 * j < d ? B.uadj[b + lane + 64 * j] : 0;
-        int32_t cnt = 0;
-#pragma unroll
-        for (int j = 0; j < PER; j++) cnt += (lane + 64 * j < d && B.c[u[j]] >= k) ? 1 : 0;
-        cnt = wave_sum(cnt);
-        if (lane == 0) B.cnt[v] = cnt;
-        push(p, lane == 0 && cnt <= k ? 1 : -1, v, d);
-    }
+    // rows of classes 0 and 1, one lane per vertex
     const int64_t stride = (int64_t)gridDim.x * BLK;
-    for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < n0; base += stride) {
+    for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < (int64_t)n0 + n1; base += stride) {
         const int64_t i = base + lane;
         int cls = -1;
         int32_t v = 0;
-        if (i < n0) {
-            v = B.all[0][i];
-            const int64_t b = B.uoff[v];
-            const int32_t d = (int32_t)(B.uoff[v + 1] - b);
-            const int32_t k = B.c[v];
-            int32_t u[C0_MAX];
-#pragma unroll
-            for (int j = 0; j < C0_MAX; j++) u[j] = j < d ? B.uadj[b + j] : 0;
-            int32_t cnt = 0;
-#pragma unroll
-            for (int j = 0; j < C0_MAX; j++) cnt += (j < d && B.c[u[j]] >= k) ? 1 : 0;
-            B.cnt[v] = cnt;
-            if (cnt <= k) cls = 0;
+        if (i < (int64_t)n0 + n1) {
+            const int j = i < n0 ? 0 : 1;
+            v = j == 0 ? B.all[0][i] : B.all[1][i - n0];
+            if (B.cnt[v] <= B.c[v]) cls = j;
         }
         push(p, cls, v, 0);
     }
     push_finish(p);
 }
 
-// round 0 of the long rows, once their chunks' counts are complete
+// round 0 of the long rows, from their kept histograms or their chunks' counts
 __global__ __launch_bounds__(BLK) void k_level_big(CoreBufs B) {
     const int32_t n2 = B.ctr[CT_ALL + 2];
     const ListSet F = list_set(B.pool[0], B.pool[1], nullptr, B.poolc[0], B.ctr + CT_F + 0, BIG_CHUNKS);
     for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n2; i += (int64_t)gridDim.x * BLK) {
         const int32_t v = B.all[2][i];
-        if (B.cnt[v] <= B.c[v]) push_chunks(F, v, (int32_t)(B.uoff[v + 1] - B.uoff[v]));
+        const int32_t k = B.c[v];
+        int32_t cnt = B.cnt[v];
+        if (B.hbw > 0) {
+            cnt = B.gh[(int64_t)B.bigid[v] * B.hbw + k]; // the level holds every value >= k
+            B.cnt[v] = cnt;
+        }
+        if (cnt <= k) push_chunks(F, v, (int32_t)(B.uoff[v + 1] - B.uoff[v]));
     }
 }
 
 // removing v (core k) takes one from each same-core neighbour; the one step
 // from k + 1 to k puts the neighbour in the next round.  Neighbours already
-// removed, or removed in this round, are at k or below and never cross.
+// removed, or removed in this round, are at k or below and never cross, so
+// they are skipped after round 0: counts only fall during the rounds, so a
+// plain read of k or less is final, and a stale read is larger and only costs
+// the atomic.  (In round 0 few neighbours are settled and the read only adds
+// latency: 70M edges, round 0 307 -> 360 us with it, later rounds 2x faster.)
 template <int J>
 __device__ inline void level_batch(const CoreBufs &B, Pusher &p, const int32_t (&u)[J], const int32_t (&cu)[J],
-                                   const bool (&ok)[J], int32_t k) {
-    int32_t old[J], du[J];
+                                   const bool (&ok)[J], int32_t k, bool skip) {
+    int32_t now[J], old[J], du[J];
 #pragma unroll
-    for (int j = 0; j < J; j++) old[j] = (ok[j] && cu[j] == k) ? atomicSub(&B.cnt[u[j]], 1) : 0;
+    for (int j = 0; j < J; j++) now[j] = (ok[j] && cu[j] == k) ? (skip ? B.cnt[u[j]] : k + 1) : 0;
+#pragma unroll
+    for (int j = 0; j < J; j++) old[j] = now[j] > k ? atomicSub(&B.cnt[u[j]], 1) : 0;
 #pragma unroll
     for (int j = 0; j < J; j++) du[j] = (ok[j] && cu[j] == k && old[j] == k + 1) ? B.deg[u[j]] : -1;
     for (int j = 0; j < J; j++) push(p, du[j] >= 0 ? row_class(du[j]) : -1, u[j], du[j]);
@@ -938,7 +942,7 @@ __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
         int32_t cu[CPT];
 #pragma unroll
         for (int j = 0; j < CPT; j++) cu[j] = rw.ok[j] ? B.c[rw.u[j]] : -1;
-        level_batch<CPT>(B, p, rw.u, cu, rw.ok, k);
+        level_batch<CPT>(B, p, rw.u, cu, rw.ok, k, r > 0);
     }
     const int64_t gwave = ((int64_t)blockIdx.x * BLK + t) >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * WPB;
@@ -958,7 +962,7 @@ __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
         }
 #pragma unroll
         for (int j = 0; j < PER; j++) cu[j] = ok[j] ? B.c[u[j]] : -1;
-        level_batch<PER>(B, p, u, cu, ok, k);
+        level_batch<PER>(B, p, u, cu, ok, k, r > 0);
     }
     const int64_t stride = (int64_t)gridDim.x * BLK;
     for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < n0; base += stride) {
@@ -981,7 +985,7 @@ __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
         }
 #pragma unroll
         for (int j = 0; j < C0_MAX; j++) cu[j] = ok[j] ? B.c[u[j]] : -1;
-        level_batch<C0_MAX>(B, p, u, cu, ok, k);
+        level_batch<C0_MAX>(B, p, u, cu, ok, k, r > 0);
     }
     push_finish(p);
 }

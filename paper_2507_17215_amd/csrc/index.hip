@@ -48,18 +48,39 @@ struct ValOut {
     unsigned long long descents;
 };
 
+// VU edges per thread and step, each a coalesced load of its own, all in flight
+// before any is used; the previous timestamp comes from the lane below.
+constexpr int VU = 4;
 __global__ void k_validate(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
                            const int64_t *__restrict__ t, int64_t m, int32_t n, ValOut *out) {
     unsigned long long loops = 0, tmax = 0, desc = 0, bad = ~0ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-        int32_t a = src[i], b = dst[i];
-        int64_t ti = t[i];
-        bool ok = a >= 0 && a < n && b >= 0 && b < n && ti >= 0 && ti < (int64_t(1) << 62);
-        if (!ok) bad = (unsigned long long)i < bad ? (unsigned long long)i : bad;
-        loops += (a == b);
-        if (ok && (unsigned long long)ti > tmax) tmax = (unsigned long long)ti;
-        if (i > 0 && t[i - 1] > ti) desc++;
+    const int lane = lane_id();
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < m; i0 += VU * stride) {
+        int32_t a[VU], b[VU];
+        int64_t ti[VU], tp[VU];
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+            const int64_t i = i0 + u * stride + lane;
+            const bool in = i < m;
+            a[u] = in ? src[i] : 0;
+            b[u] = in ? dst[i] : 0;
+            ti[u] = in ? t[i] : 0;
+            tp[u] = (lane == 0 && in && i > 0) ? t[i - 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+            const int64_t i = i0 + u * stride + lane;
+            const int64_t below = __shfl_up(ti[u], 1);
+            if (i >= m) continue;
+            const int64_t prev = lane == 0 ? tp[u] : below;
+            const bool ok = a[u] >= 0 && a[u] < n && b[u] >= 0 && b[u] < n && ti[u] >= 0 &&
+                            ti[u] < (int64_t(1) << 62);
+            if (!ok) bad = (unsigned long long)i < bad ? (unsigned long long)i : bad;
+            loops += (a[u] == b[u]);
+            if (ok && (unsigned long long)ti[u] > tmax) tmax = (unsigned long long)ti[u];
+            if (i > 0 && prev > ti[u]) desc++;
+        }
     }
     // one atomic per wavefront and quantity
     for (int o = 32; o > 0; o >>= 1) {
@@ -128,6 +149,24 @@ __global__ void k_gather_sorted(const int32_t *__restrict__ pos, const int32_t *
     ts[k] = t[i];
 }
 
+// x / n and x % n for x < n^2 and 1 <= n < 2^31 (keys lo * n + hi), from a
+// double-precision product with 1/n (inv_n, rounded once on the host) and one
+// correction step: the estimate is within one of the quotient (below 2^31), in
+// place of a software 64-bit division of about a hundred instructions.
+__device__ inline void divmod_n(uint64_t x, uint64_t n, double inv_n, int32_t &q, int32_t &r) {
+    int64_t qq = (int64_t)((double)x * inv_n);
+    int64_t rr = (int64_t)(x - (uint64_t)qq * n);
+    if (rr < 0) {
+        qq--;
+        rr += (int64_t)n;
+    } else if (rr >= (int64_t)n) {
+        qq++;
+        rr -= (int64_t)n;
+    }
+    q = (int32_t)qq;
+    r = (int32_t)rr;
+}
+
 __global__ void k_static_flags(const uint64_t *__restrict__ key, int32_t m, int32_t *__restrict__ flag) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
@@ -135,7 +174,7 @@ __global__ void k_static_flags(const uint64_t *__restrict__ key, int32_t m, int3
 }
 
 __global__ void k_static_table(const uint64_t *__restrict__ key, int32_t *__restrict__ sid, int32_t m,
-                               int64_t n, int32_t *__restrict__ soff, int32_t *__restrict__ smid,
+                               int64_t n, double inv_n, int32_t *__restrict__ soff, int32_t *__restrict__ smid,
                                int32_t *__restrict__ slo, int32_t *__restrict__ shi) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
@@ -146,8 +185,10 @@ __global__ void k_static_table(const uint64_t *__restrict__ key, int32_t *__rest
     bool first = (k == 0) || ((key[k - 1] >> 1) != pk);
     if (first) {
         soff[s] = (int32_t)k;
-        slo[s] = (int32_t)(pk / (uint64_t)n);
-        shi[s] = (int32_t)(pk % (uint64_t)n);
+        int32_t lo, hi;
+        divmod_n(pk, (uint64_t)n, inv_n, lo, hi);
+        slo[s] = lo;
+        shi[s] = hi;
     }
     if ((kk & 1ull) && (first || (key[k - 1] & 1ull) == 0)) smid[s] = (int32_t)k;
     if (k == m - 1) soff[s + 1] = m;
@@ -280,12 +321,14 @@ __global__ void k_orient_keys(const int32_t *__restrict__ slo, const int32_t *__
     val[s] = (uint32_t)s | (a < b ? 0x80000000u : 0u);
 }
 
-__global__ void k_orient_unpack(const uint64_t *__restrict__ key, int32_t S, int64_t n,
+__global__ void k_orient_unpack(const uint64_t *__restrict__ key, int32_t S, int64_t n, double inv_n,
                                 int32_t *__restrict__ oadj, int32_t *__restrict__ otail) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= S) return;
-    oadj[j] = (int32_t)(key[j] % (uint64_t)n);
-    otail[j] = (int32_t)(key[j] / (uint64_t)n);
+    int32_t tail, head;
+    divmod_n(key[j], (uint64_t)n, inv_n, tail, head);
+    oadj[j] = head;
+    otail[j] = tail;
 }
 
 // oriented CSR rows: row x starts at the first key >= x * n
@@ -513,7 +556,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     } else {
         k_fill<int32_t><<<grid_for(S, BLK), BLK, 0, s>>>(ix.smid.as<int32_t>(), -1, S);
         k_static_table<<<grid_for(m, BLK), BLK, 0, s>>>(pkey2.as<uint64_t>(), ix.sid.as<int32_t>(), m, n,
-                                                        ix.soff.as<int32_t>(), ix.smid.as<int32_t>(),
+                                                        1.0 / (double)n, ix.soff.as<int32_t>(), ix.smid.as<int32_t>(),
                                                         ix.slo.as<int32_t>(), ix.shi.as<int32_t>());
         k_fix_smid_stats<<<grid_for(S, BLK, 2048), BLK, 0, s>>>(ix.soff.as<int32_t>(), ix.smid.as<int32_t>(), S,
                                                                 pstat.as<PairStats>());
@@ -608,8 +651,8 @@ void build_index(Graph *g, const folty_build_opts *opts) {
                                              ix.oeid.as<uint32_t>(), S, kb, s);
             sort_pairs_u64_u32(cub_ensure(need), need, key.as<uint64_t>(), key2.as<uint64_t>(), val.as<uint32_t>(),
                                ix.oeid.as<uint32_t>(), S, kb, s);
-            k_orient_unpack<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.oadj.as<int32_t>(),
-                                                             ix.otail.as<int32_t>());
+            k_orient_unpack<<<grid_for(S, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, 1.0 / (double)n,
+                                                             ix.oadj.as<int32_t>(), ix.otail.as<int32_t>());
             FOLTY_LAUNCHED();
         }
         k_orient_rows<<<grid_for((int64_t)n + 1, BLK), BLK, 0, s>>>(key2.as<uint64_t>(), S, n, ix.ooff.as<int32_t>());
