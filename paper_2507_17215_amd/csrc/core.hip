@@ -28,6 +28,8 @@
 //     peeled at once: the dependent rounds are only as many as the most any one
 //     level needs, and every vertex gets the same round within its level as in
 //     the level-by-level peel.
+#include <cmath>
+
 #include "folty_internal.h"
 
 namespace folty {
@@ -43,7 +45,8 @@ constexpr int32_t C1_MAX = 1024;     // up to this length: one wavefront per ver
 constexpr int32_t CH = 2048;         // row work on longer rows goes in chunks of this many entries
 constexpr int32_t CPT = CH / BLK;    // chunk entries per thread
 constexpr int32_t HX_BINS = 4096;    // LDS histogram of the h-index of a long row
-constexpr int32_t HG_BINS = 1 << 16; // degree histogram for the global h-index
+constexpr int32_t HG_BINS = (1 << 16) + 1; // degree histogram for the global h-index: levels up to 2^16 - 1,
+                                           // and one bin above
 constexpr int32_t HG_LDS = 1024;     // degrees below this are counted in LDS first
 constexpr int PB_CAP = 256;          // buffered list entries per wavefront and class
 // Sweeps that rescan long rows before their histograms are kept and the rows
@@ -230,37 +233,48 @@ __device__ inline Pusher make_pusher(PushLds *P, const ListSet &L) {
 }
 
 // ---- global h-index of the degrees: an upper bound of every core number -----------
-__global__ __launch_bounds__(BLK) void k_deg_hist(const int32_t *__restrict__ deg, int32_t n,
+// degrees above `cap` are counted in bin cap
+__global__ __launch_bounds__(BLK) void k_deg_hist(const int32_t *__restrict__ deg, int32_t n, int32_t cap,
                                                   int32_t *__restrict__ hist) {
     __shared__ int32_t s_h[HG_LDS];
     for (int i = threadIdx.x; i < HG_LDS; i += BLK) s_h[i] = 0;
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * BLK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLK) {
         int32_t d = deg[v];
+        d = d < cap ? d : cap;
         if (d < HG_LDS) atomicAdd(&s_h[d], 1);
-        else atomicAdd(&hist[d < HG_BINS ? d : HG_BINS - 1], 1);
+        else atomicAdd(&hist[d], 1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < HG_LDS; i += BLK)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
-// the largest h with at least h counts at or above h; thread t owns the bins
-// [HG_BINS - (t + 1) * per, HG_BINS - t * per) and walks them from the top
-__global__ __launch_bounds__(BLK) void k_global_h(const int32_t *__restrict__ hist, int32_t *ctr) {
-    constexpr int per = HG_BINS / BLK;
+// the largest h with at least h counts at or above h.  h vertices of degree >= h
+// hold h^2 <= sum of degrees entries, so h <= top = floor(sqrt(sum)) (at most
+// 2^16 - 1 for fewer than 2^31 static edges); bin top + 1 counts every degree
+// above top, and thread t walks the levels top - t * per down to
+// top - (t + 1) * per + 1.
+__global__ __launch_bounds__(BLK) void k_global_h(const int32_t *__restrict__ hist, int32_t top, int32_t *ctr) {
     __shared__ int64_t s_tot[BLK];
     __shared__ int32_t s_best;
     const int t = threadIdx.x;
-    const int32_t hi = HG_BINS - 1 - t * per;
+    const int64_t high = t == 0 ? hist[top + 1] : 0;
+    const int32_t per = (top + 1 + BLK - 1) / BLK;
+    const int32_t hi = top - t * per;
     int64_t mine = 0;
-    for (int i = 0; i < per; i++) mine += hist[hi - i];
+    for (int32_t i = 0; i < per && hi - i >= 0; i++) mine += hist[hi - i];
     s_tot[t] = mine;
     if (t == 0) s_best = 0;
     __syncthreads();
     int64_t above = 0;
-    for (int k = 0; k < t; k++) above += s_tot[k];
-    for (int i = 0; i < per; i++) {
+    for (int k = 0; k < BLK; k++) above += k < t ? s_tot[k] : 0;
+    // every thread needs the total above top: one more pass over s_tot
+    __syncthreads();
+    s_tot[t] = high;
+    __syncthreads();
+    for (int k = 0; k < BLK; k++) above += s_tot[k];
+    for (int32_t i = 0; i < per && hi - i >= 0; i++) {
         const int32_t h = hi - i;
         above += hist[h];
         if (above >= h) {
@@ -282,18 +296,38 @@ __global__ __launch_bounds__(BLK) void k_core_init(CoreBufs B) {
     for (int64_t base = (int64_t)blockIdx.x * BLK; base < B.n; base += stride) {
         const int64_t v = base + threadIdx.x;
         int cls = -1;
+        int32_t d = 0;
         if (v < B.n) {
-            const int32_t d = B.deg[v];
+            d = B.deg[v];
             B.c[v] = (uint16_t)(d < hg ? d : hg);
             B.stamp[v] = 0;
             B.cnt[v] = 0;
             B.lr[v] = -1;
             cls = row_class(d);
-            if (cls == 2) {
-                const int32_t id = atomicAdd(&B.ctr[CT_ALL + 2], 1);
+        }
+        // class-2 vertices: slots and chunk ranges with one atomic each per
+        // wavefront (thousands of them would serialise on two counters)
+        const bool big = cls == 2;
+        const unsigned long long bm = __ballot(big);
+        if (bm) {
+            const int32_t nch = big ? (d + CH - 1) / CH : 0;
+            int32_t incl = nch;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(incl, o);
+                if (lane_id() >= o) incl += y;
+            }
+            int32_t id0 = 0, ch0 = 0;
+            if (lane_id() == 63) {
+                id0 = atomicAdd(&B.ctr[CT_ALL + 2], (int32_t)__popcll(bm));
+                ch0 = atomicAdd(&B.ctr[CT_ALL + 3], incl);
+            }
+            id0 = __shfl(id0, 63);
+            ch0 = __shfl(ch0, 63);
+            if (big) {
+                const int32_t id = id0 + (int32_t)__popcll(bm & ((1ull << lane_id()) - 1ull));
                 B.bigid[v] = id;
                 B.all[2][id] = (int32_t)v;
-                push_chunks(p.L, (int32_t)v, d);
+                for (int32_t i = 0; i < nch; i++) B.allc[ch0 + incl - nch + i] = make_int2((int32_t)v, i);
             }
         }
         push(p, cls < 2 ? cls : -1, (int32_t)v, 0);
@@ -561,7 +595,7 @@ __device__ inline int32_t h_block(const uint16_t *c, const int32_t *__restrict__
 // by this sweep's k_core_sweep and is cleared after use; otherwise it is the
 // kept one, and a drop to h folds its levels above h into level h.  Every
 // thread of the block calls this.
-__device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bool dense, HxLds &H) {
+__device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bool dense, bool list, HxLds &H) {
     int32_t *ctr = B.ctr;
     const int par = s & 1;
     const int32_t n2 = dense ? ctr[CT_ALL + 2] : ctr[CT_H + 4 * par + 2];
@@ -604,16 +638,16 @@ __device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bo
             B.old[v] = x;
             B.c[v] = h;
             // a reordered row is marked only where values were above h
-            push_chunks(D, v, B.pc && !rescan ? big_prefix(B, v, h + 1) : d);
+            if (list) push_chunks(D, v, B.pc && !rescan ? big_prefix(B, v, h + 1) : d);
         }
         __syncthreads();
     }
 }
 
 // A separate launch only when this sweep's k_core_sweep builds the histograms.
-__global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan, bool dense) {
+__global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan, bool dense, bool list) {
     __shared__ HxLds H;
-    finish_rows(B, s, rescan, dense, H);
+    finish_rows(B, s, rescan, dense, list, H);
 }
 
 // Sweep s, rows up to C1_MAX: re-evaluate the listed vertices (`dense`: every
@@ -628,7 +662,10 @@ union SweepLds {
     HxLds H;
 };
 
-__global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense, bool fused) {
+// `list`: the drops are listed for a marking pass (not after the dense sweeps
+// before the last one, whose drops no pass reads).
+__global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense, bool fused,
+                                                    bool list) {
     __shared__ PushLds P;
     __shared__ SweepLds U;
     int32_t *s_h = U.h;
@@ -648,7 +685,7 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
     Pusher p = make_pusher(&P, list_set(B.pool[6], B.pool[7], nullptr, B.poolc[0], ctr + CT_D + 4 * par, BIG_CHUNKS));
     const int lane = lane_id();
     const int t = threadIdx.x;
-    if (fused) finish_rows(B, s, rescan, dense, U.H);
+    if (fused) finish_rows(B, s, rescan, dense, list, U.H);
     if (rescan && B.hbw > 0) {
         const int32_t n3 = in_cnt[3];
         const int2 *L3 = dense ? B.allc : B.poolc[1 + par];
@@ -690,7 +727,7 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
             B.old[v] = x;
             B.c[v] = h;
         }
-        push(p, drop ? 1 : -1, v, d);
+        if (list) push(p, drop ? 1 : -1, v, d);
     }
     const int64_t stride = (int64_t)gridDim.x * BLK;
     for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < n0; base += stride) {
@@ -711,7 +748,7 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
                 cls = 0;
             }
         }
-        push(p, cls, v, 0);
+        if (list) push(p, cls, v, 0);
     }
     push_finish(p);
 }
@@ -1050,8 +1087,13 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
     for (int j = 0; j < 3; j++) B.poolc[j] = poolc.as<int2>() + (size_t)j * chunk_cap;
     B.n = n;
     const unsigned g_all = grid_for(n, BLK, GRID);
-    k_deg_hist<<<g_all, BLK, 0, s>>>(deg, n, hist.as<int32_t>());
-    k_global_h<<<1, BLK, 0, s>>>(hist.as<int32_t>(), ctr.as<int32_t>());
+    int64_t top = (int64_t)std::sqrt((double)adj_n);
+    while ((top + 1) * (top + 1) <= adj_n) top++;
+    while (top > 0 && top * top > adj_n) top--;
+    if (top > HG_BINS - 2) fail(FOLTY_EOVERFLOW, "%lld adjacency entries exceed the degree histogram", (long long)adj_n);
+    // a few blocks: each merges its LDS bins into the same global counters
+    k_deg_hist<<<grid_for(n, BLK, 256), BLK, 0, s>>>(deg, n, (int32_t)top + 1, hist.as<int32_t>());
+    k_global_h<<<1, BLK, 0, s>>>(hist.as<int32_t>(), (int32_t)top, ctr.as<int32_t>());
     k_core_init<<<g_all, BLK, 0, s>>>(B);
     FOLTY_LAUNCHED();
     auto read_ctr = [&]() {
@@ -1086,9 +1128,10 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
             // the first listed sweep
             const bool dense = sw < DENSE_SWEEPS;
             const bool fused = !(rescan && B.hbw > 0);
-            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan, dense, fused);
-            if (!fused) k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan, dense);
-            if (sw + 1 >= DENSE_SWEEPS) k_core_mark<<<GRID, BLK, 0, s>>>(B, sw, rescan);
+            const bool list = sw + 1 >= DENSE_SWEEPS; // a marking pass follows
+            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan, dense, fused, list);
+            if (!fused) k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan, dense, list);
+            if (list) k_core_mark<<<GRID, BLK, 0, s>>>(B, sw, rescan);
         }
         FOLTY_LAUNCHED();
         if (rescan && B.hbw > 0 && nbig > 0) {

@@ -242,8 +242,8 @@ __global__ void k_fix_smid_stats(const int32_t *__restrict__ soff, int32_t *__re
 // halves are already ascending.  hkey/hval: the table's (hi, lo) pairs stably
 // sorted by hi.  With loff[v] = #edges with lo < v and hoff[v] = #edges with
 // hi < v, row v starts at loff[v] + hoff[v].
-__device__ inline int64_t lower_bound_i32(const int32_t *__restrict__ a, int64_t len, int32_t x) {
-    int64_t lo = 0, hi = len;
+// first position in a[lo, hi) holding a value >= x (hi if none)
+__device__ inline int64_t lower_bound_i32(const int32_t *__restrict__ a, int64_t lo, int64_t hi, int32_t x) {
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
         if (a[mid] < x) lo = mid + 1;
@@ -252,11 +252,28 @@ __device__ inline int64_t lower_bound_i32(const int32_t *__restrict__ a, int64_t
     return lo;
 }
 
-__global__ void k_adj_rows(const int32_t *__restrict__ slo, const int32_t *__restrict__ hkey, int32_t S, int32_t n,
-                           int32_t *__restrict__ loff, int32_t *__restrict__ hoff, int64_t *__restrict__ uoff) {
-    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One block per 256 consecutive vertices: four threads bound the block's
+// positions in both key arrays, then each vertex searches only that range (the
+// rows of 256 neighbouring vertices, a few cache lines shared by the block)
+// instead of all S keys.
+__global__ __launch_bounds__(BLK) void k_adj_rows(const int32_t *__restrict__ slo, const int32_t *__restrict__ hkey,
+                                                  int32_t S, int32_t n, int32_t *__restrict__ loff,
+                                                  int32_t *__restrict__ hoff, int64_t *__restrict__ uoff) {
+    __shared__ int64_t s_b[4];
+    const int64_t x0 = (int64_t)blockIdx.x * BLK;
+    const int64_t x1 = x0 + BLK - 1 < n ? x0 + BLK - 1 : n; // last vertex of the block (n: the end)
+    const int t = threadIdx.x;
+    if (t < 4) {
+        const int32_t *a = t < 2 ? slo : hkey;
+        const int64_t xx = (t & 1) ? x1 + 1 : x0;
+        s_b[t] = lower_bound_i32(a, 0, S, xx > n ? n : (int32_t)xx);
+        if ((t & 1) && x1 + 1 > n) s_b[t] = S;
+    }
+    __syncthreads();
+    const int64_t x = x0 + t;
     if (x > n) return;
-    const int64_t a = lower_bound_i32(slo, S, (int32_t)x), b = lower_bound_i32(hkey, S, (int32_t)x);
+    const int64_t a = lower_bound_i32(slo, s_b[0], s_b[1], (int32_t)x);
+    const int64_t b = lower_bound_i32(hkey, s_b[2], s_b[3], (int32_t)x);
     loff[x] = (int32_t)a;
     hoff[x] = (int32_t)b;
     uoff[x] = a + b;
