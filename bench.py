@@ -596,7 +596,7 @@ def main():
     query_wall = []
 
     def step():
-        G = folty.Graph(n, src, dst, tt)
+        G = folty.Graph(n, src, dst, tt, borrow=True)  # the resident inputs, read in place
         G.build()
         tq = time.perf_counter()
         r = G.query(a.delta, theta, 0, counts=False)  # returns with the sorted pairs on the host

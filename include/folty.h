@@ -56,7 +56,10 @@ enum {
     FOLTY_EBUSY = -6      /* server: result not ready yet */
 };
 
-enum { FOLTY_MEM_HOST = 0, FOLTY_MEM_DEVICE = 1 };
+/* Where the arrays handed to folty_load_temporal_graph live.  HOST and DEVICE
+ * arrays are copied; DEVICE_BORROWED arrays are read where they are, and the
+ * caller keeps them allocated and unchanged until folty_graph_free. */
+enum { FOLTY_MEM_HOST = 0, FOLTY_MEM_DEVICE = 1, FOLTY_MEM_DEVICE_BORROWED = 2 };
 
 /* delta meaning "no window" */
 #define FOLTY_DELTA_INF INT64_MAX
@@ -202,10 +205,16 @@ const char *folty_version(void);
  *   src, dst  int32[m], t int64[m] with 0 <= t < 2^62; host or device memory as
  *             mem_kind says.  Order is free (the paper assumes time order; this
  *             library sorts).  Self-loops are accepted and ignored by the query.
+ *   mem_kind  FOLTY_MEM_HOST or FOLTY_MEM_DEVICE: the arrays are copied (the
+ *             caller may free them once this returns); FOLTY_MEM_DEVICE_BORROWED:
+ *             device arrays read in place by this call and every build, which
+ *             the caller keeps allocated and unchanged until folty_graph_free
+ *             (saves a device copy of 16 bytes per edge).  Any other value:
+ *             FOLTY_EINVAL.
  *   stream    hipStream_t to run on, or NULL.
  *   out       receives the graph handle.
  * Validates ids and timestamps on the device (FOLTY_EINVAL with the first bad
- * position in the message).  The inputs are copied.
+ * position in the message).
  */
 int folty_load_temporal_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                               const int64_t *t, int32_t mem_kind, void *stream,

@@ -315,8 +315,11 @@ struct Graph {
     hipStream_t stream = nullptr;
     AllocHook hook; // the caller's allocator for the index (folty_build_opts), if any
     bool own_stream = false;
-    // inputs (device copies) until the index is built
+    // inputs: device copies, or the caller's device arrays (borrowed); in_* point
+    // at whichever holds them
     DevBuf src, dst, t;
+    const int32_t *in_src = nullptr, *in_dst = nullptr;
+    const int64_t *in_t = nullptr;
     bool sorted_by_time = false;
     int64_t tmax = 0;
     Index ix;

@@ -422,7 +422,8 @@ void load_graph(Graph *g, int32_t n, int64_t m, const int32_t *src, const int32_
     if (m < 0) fail(FOLTY_EINVAL, "m must be >= 0");
     if (m >= (int64_t(1) << 31) - 1) fail(FOLTY_EOVERFLOW, "m = %lld needs 64-bit edge ids", (long long)m);
     if (m > 0 && (!src || !dst || !t)) fail(FOLTY_EINVAL, "null input array");
-    if (mem_kind != FOLTY_MEM_HOST && mem_kind != FOLTY_MEM_DEVICE) fail(FOLTY_EINVAL, "bad mem_kind");
+    if (mem_kind != FOLTY_MEM_HOST && mem_kind != FOLTY_MEM_DEVICE && mem_kind != FOLTY_MEM_DEVICE_BORROWED)
+        fail(FOLTY_EINVAL, "bad mem_kind %d", mem_kind);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
         (void)hipGetLastError();
@@ -439,22 +440,30 @@ void load_graph(Graph *g, int32_t n, int64_t m, const int32_t *src, const int32_
     StreamScope sc(s);
     g->ix.n = n;
     g->ix.m_input = m;
-    g->src.ensure(sizeof(int32_t) * m);
-    g->dst.ensure(sizeof(int32_t) * m);
-    g->t.ensure(sizeof(int64_t) * m);
-    hipMemcpyKind kind = mem_kind == FOLTY_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    if (m > 0) {
-        FOLTY_HIP(hipMemcpyAsync(g->src.p, src, sizeof(int32_t) * m, kind, s));
-        FOLTY_HIP(hipMemcpyAsync(g->dst.p, dst, sizeof(int32_t) * m, kind, s));
-        FOLTY_HIP(hipMemcpyAsync(g->t.p, t, sizeof(int64_t) * m, kind, s));
+    if (mem_kind == FOLTY_MEM_DEVICE_BORROWED) {
+        g->in_src = src;
+        g->in_dst = dst;
+        g->in_t = t;
+    } else {
+        g->src.ensure(sizeof(int32_t) * m);
+        g->dst.ensure(sizeof(int32_t) * m);
+        g->t.ensure(sizeof(int64_t) * m);
+        hipMemcpyKind kind = mem_kind == FOLTY_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        if (m > 0) {
+            FOLTY_HIP(hipMemcpyAsync(g->src.p, src, sizeof(int32_t) * m, kind, s));
+            FOLTY_HIP(hipMemcpyAsync(g->dst.p, dst, sizeof(int32_t) * m, kind, s));
+            FOLTY_HIP(hipMemcpyAsync(g->t.p, t, sizeof(int64_t) * m, kind, s));
+        }
+        g->in_src = g->src.as<int32_t>();
+        g->in_dst = g->dst.as<int32_t>();
+        g->in_t = g->t.as<int64_t>();
     }
     DevBuf vo;
     vo.ensure(sizeof(ValOut));
     k_init_val<<<1, 1, 0, s>>>(vo.as<ValOut>());
     FOLTY_LAUNCHED();
     if (m > 0) {
-        k_validate<<<grid_for(m, BLK, 4096), BLK, 0, s>>>(g->src.as<int32_t>(), g->dst.as<int32_t>(),
-                                                          g->t.as<int64_t>(), m, n, vo.as<ValOut>());
+        k_validate<<<grid_for(m, BLK, 4096), BLK, 0, s>>>(g->in_src, g->in_dst, g->in_t, m, n, vo.as<ValOut>());
         FOLTY_LAUNCHED();
     }
     ValOut h{};
@@ -472,7 +481,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     folty_build_opts o{};
     if (opts) o = *opts;
     if (o.rank_mode < 0 || o.rank_mode > 2) fail(FOLTY_EINVAL, "unknown rank_mode %d", o.rank_mode);
-    if (g->ix.m_input > 0 && !g->src.p) fail(FOLTY_EINVAL, "graph inputs were released");
+    if (g->ix.m_input > 0 && !g->in_src) fail(FOLTY_EINVAL, "graph inputs were released");
     if ((o.alloc == nullptr) != (o.free == nullptr)) fail(FOLTY_EINVAL, "alloc and free must both be set or both be null");
     Index &ix = g->ix;
     hipStream_t s = g->stream;
@@ -507,7 +516,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         tkeys2.ensure(8 * min);
         idx_t.ensure(4 * min);
         idx_t2.ensure(4 * min);
-        k_iota_tkeys<<<grid_for(min, BLK), BLK, 0, s>>>(g->t.as<int64_t>(), tkeys.as<uint64_t>(),
+        k_iota_tkeys<<<grid_for(min, BLK), BLK, 0, s>>>(g->in_t, tkeys.as<uint64_t>(),
                                                         idx_t.as<int32_t>(), min);
         FOLTY_LAUNCHED();
         int tb = bit_length((uint64_t)g->tmax);
@@ -524,7 +533,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
         pkey2.ensure(8 * min);
         pos.ensure(4 * min);
         pos2.ensure(4 * min);
-        k_pair_keys<<<grid_for(min, BLK), BLK, 0, s>>>(idx_time, g->src.as<int32_t>(), g->dst.as<int32_t>(),
+        k_pair_keys<<<grid_for(min, BLK), BLK, 0, s>>>(idx_time, g->in_src, g->in_dst,
                                                        n, pkey.as<uint64_t>(), pos.as<int32_t>(), min);
         FOLTY_LAUNCHED();
         int kb = bit_length(2ull * (uint64_t)n * (uint64_t)n);
@@ -539,7 +548,7 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     ix.perm.ensure(4 * (size_t)m);
     ix.sid.ensure(4 * (size_t)m);
     if (m > 0) {
-        k_gather_sorted<<<grid_for(m, BLK), BLK, 0, s>>>(pos2.as<int32_t>(), idx_time, g->t.as<int64_t>(),
+        k_gather_sorted<<<grid_for(m, BLK), BLK, 0, s>>>(pos2.as<int32_t>(), idx_time, g->in_t,
                                                          ix.perm.as<int32_t>(), ix.ts.as<int64_t>(), m);
         FOLTY_LAUNCHED();
     }

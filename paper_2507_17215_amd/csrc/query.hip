@@ -32,33 +32,44 @@ namespace {
 // ---------------------------------------------------------------------------
 // index helpers
 // ---------------------------------------------------------------------------
-__global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const int32_t *__restrict__ soff,
-                            const int32_t *__restrict__ smid, const int64_t *__restrict__ ts, int32_t S,
-                            int32_t tshift, EdgeRec *__restrict__ rec, uint2 *__restrict__ erng) {
+// The records of the static edges in their own order, lists lo -> hi first:
+// soff, smid and the lists' end timestamps are read in the order they are
+// stored, so this pass streams.
+__global__ void k_static_recs(const int32_t *__restrict__ soff, const int32_t *__restrict__ smid,
+                              const int64_t *__restrict__ ts, int32_t S, int32_t tshift,
+                              EdgeRec *__restrict__ srec) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S) return;
+    const int32_t a = soff[e], mid = smid[e], b = soff[e + 1];
+    EdgeRec r;
+    r.fs = a;
+    r.fn = mid - a;
+    r.bs = mid;
+    r.bn = b - mid;
+    r.flo = r.fn ? (uint32_t)(ts[a] >> tshift) : 0;
+    r.fhi = r.fn ? (uint32_t)(ts[mid - 1] >> tshift) : 0;
+    r.blo = r.bn ? (uint32_t)(ts[mid] >> tshift) : 0;
+    r.bhi = r.bn ? (uint32_t)(ts[b - 1] >> tshift) : 0;
+    srec[e] = r;
+}
+
+// Oriented edge p (static edge e, tail lo when bit 31 of its id is set): one
+// 32-byte read of e's record, lists swapped when the tail is hi.
+__global__ void k_edge_recs(const uint32_t *__restrict__ oeid, const EdgeRec *__restrict__ srec, int32_t S,
+                            EdgeRec *__restrict__ rec, uint2 *__restrict__ erng) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S) return;
-    uint32_t id = oeid[p];
-    int32_t e = (int32_t)(id & 0x7fffffffu);
-    int32_t a = soff[e], mid = smid[e], b = soff[e + 1];
-    int32_t fs, fn, bs, bn;
-    if (id >> 31) {
-        fs = a; fn = mid - a; bs = mid; bn = b - mid;
-    } else {
-        fs = mid; fn = b - mid; bs = a; bn = mid - a;
+    const uint32_t id = oeid[p];
+    const EdgeRec q = srec[id & 0x7fffffffu];
+    EdgeRec r = q;
+    if (!(id >> 31)) {
+        r.fs = q.bs, r.fn = q.bn, r.flo = q.blo, r.fhi = q.bhi;
+        r.bs = q.fs, r.bn = q.fn, r.blo = q.flo, r.bhi = q.fhi;
     }
-    EdgeRec r;
-    r.fn = fn;
-    r.bn = bn;
-    r.fs = fs;
-    r.bs = bs;
-    r.flo = fn ? (uint32_t)(ts[fs] >> tshift) : 0;
-    r.fhi = fn ? (uint32_t)(ts[fs + fn - 1] >> tshift) : 0;
-    r.blo = bn ? (uint32_t)(ts[bs] >> tshift) : 0;
-    r.bhi = bn ? (uint32_t)(ts[bs + bn - 1] >> tshift) : 0;
     rec[p] = r;
     // a static edge has at least one temporal edge, so one of the lists is non-empty
-    uint32_t lo = fn ? r.flo : r.blo, hi = fn ? r.fhi : r.bhi;
-    if (fn && bn) {
+    uint32_t lo = r.fn ? r.flo : r.blo, hi = r.fn ? r.fhi : r.bhi;
+    if (r.fn && r.bn) {
         lo = r.blo < lo ? r.blo : lo;
         hi = r.bhi > hi ? r.bhi : hi;
     }
@@ -689,9 +700,12 @@ void index_triangles(Index &ix, bool cache, DevBuf &cub, hipStream_t s) {
     ix.erng.ensure(sizeof(uint2) * ((size_t)S + 1));
     ix.tcnt_ready = false;
     if (S > 0) {
-        k_edge_recs<<<grid_for(S, BLK), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), ix.soff.as<int32_t>(),
-                                                                ix.smid.as<int32_t>(), ix.ts.as<int64_t>(), S,
-                                                                ix.tshift, ix.rec.as<EdgeRec>(), ix.erng.as<uint2>());
+        DevBuf srec;
+        srec.ensure(sizeof(EdgeRec) * (size_t)S);
+        k_static_recs<<<grid_for(S, BLK), BLK, 0, s>>>(ix.soff.as<int32_t>(), ix.smid.as<int32_t>(),
+                                                       ix.ts.as<int64_t>(), S, ix.tshift, srec.as<EdgeRec>());
+        k_edge_recs<<<grid_for(S, BLK), BLK, 0, s>>>(ix.oeid.as<uint32_t>(), srec.as<EdgeRec>(), S,
+                                                     ix.rec.as<EdgeRec>(), ix.erng.as<uint2>());
         FOLTY_LAUNCHED();
     }
     // probe segments grouped by (owner, mode), their probe prefix, and items

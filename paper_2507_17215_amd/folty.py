@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfolty.so")
 
 OK, EINVAL, ENOTBUILT, ENOMEM, EDEVICE, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
-MEM_HOST, MEM_DEVICE = 0, 1
+MEM_HOST, MEM_DEVICE, MEM_DEVICE_BORROWED = 0, 1, 2
 DELTA_INF = (1 << 63) - 1
 UNIVERSE_DST, UNIVERSE_SRC, UNIVERSE_COMMON = 0, 1, 2
 RANK_DEGENERACY, RANK_DEGREE, RANK_RANDOM = 0, 1, 2
@@ -354,7 +354,10 @@ class Workspace:
 class Graph:
     """A temporal multigraph resident on the GPU with its query index."""
 
-    def __init__(self, n: int, src, dst, t, stream=None):
+    def __init__(self, n: int, src, dst, t, stream=None, borrow: bool = False):
+        """borrow: device tensors are read in place instead of copied; the graph
+        keeps references to them, and the caller must not change them while the
+        graph lives."""
         lib = load_library()
         ps, ks, a1 = _array_arg(src, np.int32)
         pd, kd, a2 = _array_arg(dst, np.int32)
@@ -364,6 +367,11 @@ class Graph:
         m = int(a1.shape[0])
         if int(a2.shape[0]) != m or int(a3.shape[0]) != m:
             raise ValueError("src, dst and t must have the same length")
+        if borrow:
+            if ks != MEM_DEVICE:
+                raise ValueError("borrow=True needs device tensors")
+            ks = MEM_DEVICE_BORROWED
+            self._inputs = (a1, a2, a3)
         self._h = ctypes.c_void_p()
         st = ctypes.c_void_p(stream) if stream else None
         _check(lib.folty_load_temporal_graph(int(n), m, ps, pd, pt, ks, st, ctypes.byref(self._h)))
@@ -494,6 +502,7 @@ class Graph:
         if getattr(self, "_h", None):
             load_library().folty_graph_free(self._h)
             self._h = None
+        self._inputs = None  # borrowed tensors: the library no longer reads them
 
     def __del__(self):
         try:

@@ -149,6 +149,46 @@ def test_index_memory_from_torch_allocator():
     assert torch.cuda.memory_allocated() == before
 
 
+def test_borrowed_device_inputs_equal_copied_ones():
+    """FOLTY_MEM_DEVICE_BORROWED: the build reads the caller's device arrays in
+    place; index, counts and pairs equal those of a graph built from copies, the
+    arrays are left unchanged, and they are read again by a second build.  An
+    unknown mem_kind is rejected."""
+    import ctypes
+    import torch
+    g = synth.generate(3000, 40000, 2.0, law="pareto", cap=50, times="uniform", t_range=100_000, seed=52,
+                       communities=3, c_min=40, c_max=80, c_p=0.5)
+    o = Oracle(g.n, g.src, g.dst, g.t)
+    dev = torch.device("cuda:0")
+    src, dst, tt = (torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.t))
+    keep = [x.clone() for x in (src, dst, tt)]
+    G = folty.Graph(g.n, src, dst, tt, borrow=True).build()
+    C = folty.Graph(g.n, src, dst, tt).build()
+    assert G.stats()["static_edges"] == C.stats()["static_edges"]
+    assert np.array_equal(G.core_numbers(), o.core_numbers())
+    cnt = o.counts(5000, 0)
+    for rebuild in (False, True):
+        if rebuild:
+            G.build(rank_mode=folty.RANK_DEGREE)
+        for delta, th, v in ((5000, (1, 2), 0), (20_000, (1, 4), 3)):
+            say("borrowed", rebuild, delta, th, v)
+            a, b = G.query(delta, th, v), C.query(delta, th, v)
+            assert np.array_equal(a.counts(), b.counts()) and a.pairs() == b.pairs()
+            if delta == 5000:
+                assert np.array_equal(a.counts(), cnt)
+    torch.cuda.synchronize()
+    for x, y in zip((src, dst, tt), keep):
+        assert torch.equal(x, y)
+    G.close()
+    C.close()
+    lib = folty.load_library()
+    h = ctypes.c_void_p()
+    rc = lib.folty_load_temporal_graph(g.n, len(g.src), ctypes.c_void_p(src.data_ptr()),
+                                       ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(tt.data_ptr()), 3, None,
+                                       ctypes.byref(h))
+    assert rc == folty.EINVAL and not h.value
+
+
 def test_orientation_does_not_change_results():
     g = synth.tiny(seed=3)
     base = gpu_graph(g).query(10**6, (1, 4), 0).counts()
