@@ -523,21 +523,34 @@ __device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ 
     return lo;
 }
 
-struct HxLds {
-    int32_t hist[HX_BINS];
-    int32_t tsum[BLK];
-    int32_t best;
+// A block's histogram workspace in dynamic LDS: bins levels (the per-row
+// histogram width, or HX_BINS for windowed evaluation), a sum per thread and the
+// answer.  Sized to the graph, so kernels that carry it keep their occupancy
+// (70M edges: 1,468 levels, 7 KB instead of 17 KB).
+struct HxView {
+    int32_t *hist;
+    int32_t *tsum;
+    int32_t *best;
 };
+__device__ inline HxView hx_view(int32_t *base, int32_t bins) {
+    HxView v;
+    v.hist = base;
+    v.tsum = base + bins;
+    v.best = base + bins + BLK;
+    return v;
+}
+__host__ __device__ inline int32_t hx_bins(int32_t hbw) { return hbw > 0 ? hbw : HX_BINS; }
+inline size_t hx_bytes(int32_t hbw) { return 4 * ((size_t)hx_bins(hbw) + BLK + 1); }
 
 // With hist[i] = how many values equal bot + i (values above top counted in
 // `above`): the largest h in [bot, top] with count(>= h) >= h, or -1.  Thread t
 // walks the levels top - t * per down to top - (t + 1) * per + 1.
-__device__ inline int32_t window_best(HxLds &L, int32_t bot, int32_t top, int32_t above) {
+__device__ inline int32_t window_best(const HxView &L, int32_t bot, int32_t top, int32_t above) {
     const int t = threadIdx.x;
     const int32_t nb = top - bot + 1;
     const int32_t per = (nb + BLK - 1) / BLK;
     const int32_t hi_t = top - t * per;
-    if (t == 0) L.best = -1;
+    if (t == 0) *L.best = -1;
     int32_t s = 0;
     for (int32_t i = 0; i < per; i++) {
         const int32_t h = hi_t - i;
@@ -552,12 +565,12 @@ __device__ inline int32_t window_best(HxLds &L, int32_t bot, int32_t top, int32_
         if (h < bot) break;
         run += L.hist[h - bot];
         if (run >= h) {
-            atomicMax(&L.best, h);
+            atomicMax(L.best, h);
             break;
         }
     }
     __syncthreads();
-    const int32_t best = L.best;
+    const int32_t best = *L.best;
     __syncthreads();
     return best;
 }
@@ -566,7 +579,7 @@ __device__ inline int32_t window_best(HxLds &L, int32_t bot, int32_t top, int32_
 // levels, from the top down until one holds the answer.  Used only when the
 // per-row histograms would not fit (h-index of the degrees at or above HX_BINS).
 __device__ inline int32_t h_block(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
-                                  int32_t x, HxLds &L) {
+                                  int32_t x, const HxView &L) {
     const int t = threadIdx.x;
     int32_t top = x;
     int32_t above = 0;
@@ -595,7 +608,8 @@ __device__ inline int32_t h_block(const uint16_t *c, const int32_t *__restrict__
 // by this sweep's k_core_sweep and is cleared after use; otherwise it is the
 // kept one, and a drop to h folds its levels above h into level h.  Every
 // thread of the block calls this.
-__device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bool dense, bool list, HxLds &H) {
+__device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bool dense, bool list,
+                                   const HxView &H) {
     int32_t *ctr = B.ctr;
     const int par = s & 1;
     const int32_t n2 = dense ? ctr[CT_ALL + 2] : ctr[CT_H + 4 * par + 2];
@@ -646,8 +660,8 @@ __device__ inline void finish_rows(const CoreBufs &B, int32_t s, bool rescan, bo
 
 // A separate launch only when this sweep's k_core_sweep builds the histograms.
 __global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool rescan, bool dense, bool list) {
-    __shared__ HxLds H;
-    finish_rows(B, s, rescan, dense, list, H);
+    extern __shared__ int32_t dyn[];
+    finish_rows(B, s, rescan, dense, list, hx_view(dyn, hx_bins(B.hbw)));
 }
 
 // Sweep s, rows up to C1_MAX: re-evaluate the listed vertices (`dense`: every
@@ -657,18 +671,14 @@ __global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool
 // (zero beforehand), which k_core_finish reads after this kernel; otherwise the
 // long rows are evaluated here too (`fused`), from the kept histograms, which
 // only the marking kernels change.
-union SweepLds {
-    int32_t h[HX_BINS];
-    HxLds H;
-};
 
 // `list`: the drops are listed for a marking pass (not after the dense sweeps
 // before the last one, whose drops no pass reads).
 __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense, bool fused,
                                                     bool list) {
     __shared__ PushLds P;
-    __shared__ SweepLds U;
-    int32_t *s_h = U.h;
+    extern __shared__ int32_t dyn[]; // hx_bytes(B.hbw): the long rows' histograms
+    int32_t *s_h = dyn;
     int32_t *ctr = B.ctr;
     const int par = s & 1;
     const int32_t *in_cnt = dense ? ctr + CT_ALL : ctr + CT_H + 4 * par;
@@ -685,7 +695,7 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
     Pusher p = make_pusher(&P, list_set(B.pool[6], B.pool[7], nullptr, B.poolc[0], ctr + CT_D + 4 * par, BIG_CHUNKS));
     const int lane = lane_id();
     const int t = threadIdx.x;
-    if (fused) finish_rows(B, s, rescan, dense, list, U.H);
+    if (fused) finish_rows(B, s, rescan, dense, list, hx_view(dyn, hx_bins(B.hbw)));
     if (rescan && B.hbw > 0) {
         const int32_t n3 = in_cnt[3];
         const int2 *L3 = dense ? B.allc : B.poolc[1 + par];
@@ -1129,8 +1139,8 @@ int core_rank_keys(int32_t n, const int64_t *uoff, const int32_t *uadj, const in
             const bool dense = sw < DENSE_SWEEPS;
             const bool fused = !(rescan && B.hbw > 0);
             const bool list = sw + 1 >= DENSE_SWEEPS; // a marking pass follows
-            k_core_sweep<<<GRID, BLK, 0, s>>>(B, sw, rescan, dense, fused, list);
-            if (!fused) k_core_finish<<<FIN_GRID, BLK, 0, s>>>(B, sw, rescan, dense, list);
+            k_core_sweep<<<GRID, BLK, hx_bytes(B.hbw), s>>>(B, sw, rescan, dense, fused, list);
+            if (!fused) k_core_finish<<<FIN_GRID, BLK, hx_bytes(B.hbw), s>>>(B, sw, rescan, dense, list);
             if (list) k_core_mark<<<GRID, BLK, 0, s>>>(B, sw, rescan);
         }
         FOLTY_LAUNCHED();
