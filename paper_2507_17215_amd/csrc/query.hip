@@ -963,7 +963,8 @@ static const uint32_t *query_counts(Graph *g, const folty_query &q, Workspace &w
                 k_add_counts<<<grid_for(ix.m, BLK, PERSIST_BLOCKS), BLK, 0, s>>>(ps, ix.m, count);
                 FOLTY_LAUNCHED();
             } else {
-                DirectOp op{q.delta, count};
+                DirectShortOp op{q.delta, count};
+                op.inl = ix.tshift == 0; // the records' end timestamps are exact
                 launch_temporal(ix, q.variant, q.delta, ws, op, known, survivors, s);
             }
             FOLTY_HIP(hipMemcpyAsync(tests, ws.wbase.as<int64_t>() + ix.NI, 8, hipMemcpyDeviceToHost, s));

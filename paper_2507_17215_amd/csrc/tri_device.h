@@ -214,25 +214,41 @@ __device__ inline int32_t lower_bound_from(const int64_t *__restrict__ L, int32_
     return a;
 }
 
-// cnt consecutive temporal edges of L1 starting at l1s against (L2, L3)
-struct DirectOp {
+// Entry k of a list of at most two entries, from its record's first and last
+// timestamps (exact when the timestamps fit 32 bits, tshift = 0).
+__device__ inline int64_t short_at(const Span &l, int32_t k) { return (int64_t)(k == 0 ? l.lo : l.hi); }
+__device__ inline int32_t short_lower_bound(const Span &l, int32_t from, int64_t key) {
+    int32_t p = from;
+    while (p < l.n && short_at(l, p) < key) p++;
+    return p;
+}
+
+// cnt consecutive temporal edges of L1 starting at l1s against (L2, L3).  With
+// SHORT and `inl` (timestamps below 2^32) a list of one or two entries is read
+// from its span's first and last timestamps instead of ts: most lists are that
+// short, and their entries are scattered reads that no neighbouring test
+// shares.  (A compile-time switch: the branches cost registers where unused.)
+template <bool SHORT> struct DirectOpT {
+    static constexpr bool kShort = SHORT;
     int64_t delta;
     uint32_t *count;
     int32_t *diff = nullptr; // per sorted edge + 1: +1 / -1 at the ends of edge ranges (interval evaluation)
+    bool inl = false;
     __device__ inline void operator()(const int64_t *__restrict__ ts, int32_t l1s, int32_t cnt, const Span &l2,
                                       const Span &l3) const {
         const int64_t *L2 = ts + l2.s, *L3 = ts + l3.s;
+        const bool s2 = SHORT && inl && l2.n <= 2, s3 = SHORT && inl && l3.n <= 2;
         int32_t c2 = 0, c3 = 0;
         for (int32_t q = 0; q < cnt; q++) {
             int32_t e = l1s + q;
             int64_t t = ts[e];
-            c2 = lower_bound_from(L2, c2, l2.n, t);
+            c2 = s2 ? short_lower_bound(l2, c2, t) : lower_bound_from(L2, c2, l2.n, t);
             if (c2 == l2.n) break; // later edges are no earlier: no t2 for them either
-            int64_t t2 = L2[c2];
+            int64_t t2 = s2 ? short_at(l2, c2) : L2[c2];
             if (t2 - t > delta) continue;
-            c3 = lower_bound_from(L3, c3, l3.n, t2);
+            c3 = s3 ? short_lower_bound(l3, c3, t2) : lower_bound_from(L3, c3, l3.n, t2);
             if (c3 == l3.n) break;
-            if (L3[c3] - t <= delta) atomicAdd(&count[e], 1u);
+            if ((s3 ? short_at(l3, c3) : L3[c3]) - t <= delta) atomicAdd(&count[e], 1u);
         }
     }
 
@@ -267,6 +283,8 @@ struct DirectOp {
         }
     }
 };
+using DirectOp = DirectOpT<false>;      // plain tests (also the interval evaluation)
+using DirectShortOp = DirectOpT<true>;  // short lists from their spans' end timestamps
 
 // the smallest window per (e, w) into a histogram over sorted window levels:
 // level j counts w whose smallest window lies in (lv[j-1], lv[j]]
@@ -973,16 +991,23 @@ constexpr int list_id(int a, int b) { return a == 0 ? (b == 1 ? 0 : 2) : a == 1 
 // One light group's survivors in LDS: start and length of each directed list,
 // the runs that can count (bit k: run k in the order of chunk_runs), and the
 // inclusive prefix of the survivors' tests.
-struct FlatLds {
+// SHORT also keeps each list's first and last timestamp (3 KB more per
+// wavefront), for tests that read short lists from them.
+template <bool SHORT> struct FlatLds;
+template <> struct FlatLds<false> {
     int32_t incl[64];
     int32_t ls[6][64];
     int32_t ln[6][64];
     uint32_t live[64];
 };
+template <> struct FlatLds<true> : FlatLds<false> {
+    uint32_t lo[6][64]; // first and last timestamp >> tshift
+    uint32_t hi[6][64];
+};
 
 // run k = (I, J) of survivor si holds test r (r < that run's tests): run it
-template <int VAR, int I, int J, bool SS, class Op>
-__device__ inline bool flat_run(const FlatLds &F, int si, int k, int64_t &r, const int64_t *__restrict__ ts,
+template <int VAR, int I, int J, bool SS, class Op, bool SHORT>
+__device__ inline bool flat_run(const FlatLds<SHORT> &F, int si, int k, int64_t &r, const int64_t *__restrict__ ts,
                                 const Op &op) {
     if (!((F.live[si] >> k) & 1u)) return false;
     using P = Pick<VAR, I, J>;
@@ -993,13 +1018,19 @@ __device__ inline bool flat_run(const FlatLds &F, int si, int k, int64_t &r, con
         r -= nt;
         return false;
     }
-    Span l1, l2, l3;
+    Span l1{}, l2{}, l3{};
     l1.s = F.ls[i1][si];
     l1.n = n1;
     l2.s = F.ls[i2][si];
     l2.n = n2;
     l3.s = F.ls[i3][si];
     l3.n = F.ln[i3][si];
+    if constexpr (SHORT) {
+        l2.lo = F.lo[i2][si];
+        l2.hi = F.hi[i2][si];
+        l3.lo = F.lo[i3][si];
+        l3.hi = F.hi[i3][si];
+    }
     if (SS && nt < n1) op.iv(ts, l1, (int32_t)r, 1, l2, l3);
     else op(ts, l1.s + (int32_t)r, 1, l2, l3);
     return true;
@@ -1010,6 +1041,9 @@ __device__ inline bool flat_run(const FlatLds &F, int si, int k, int64_t &r, con
 // from the spans stage() put in LDS.
 template <int VAR, class Op, bool SS> struct CountRunner {
     static constexpr bool kFlat = true;
+    static constexpr bool kShort = Op::kShort && !SS; // staging keeps the lists' end timestamps
+    static_assert(!(Op::kShort && SS), "short lists are read only by the plain evaluation");
+    using Flat = FlatLds<kShort>;
     using Surv = TriLists;
     uint32_t dq;
     const int64_t *ts;
@@ -1031,16 +1065,20 @@ template <int VAR, class Op, bool SS> struct CountRunner {
                (uint32_t)run_lists<VAR, 0, 2>(L, dq, a, b, c) << 2 | (uint32_t)run_lists<VAR, 2, 0>(L, dq, a, b, c) << 3 |
                (uint32_t)run_lists<VAR, 1, 2>(L, dq, a, b, c) << 4 | (uint32_t)run_lists<VAR, 2, 1>(L, dq, a, b, c) << 5;
     }
-    __device__ inline void stage(FlatLds &F, int lane, const TriLists &T, bool light) const {
-        F.ls[0][lane] = T.d01.s, F.ln[0][lane] = T.d01.n;
-        F.ls[1][lane] = T.d10.s, F.ln[1][lane] = T.d10.n;
-        F.ls[2][lane] = T.d02.s, F.ln[2][lane] = T.d02.n;
-        F.ls[3][lane] = T.d20.s, F.ln[3][lane] = T.d20.n;
-        F.ls[4][lane] = T.d12.s, F.ln[4][lane] = T.d12.n;
-        F.ls[5][lane] = T.d21.s, F.ln[5][lane] = T.d21.n;
+    __device__ inline void stage(Flat &F, int lane, const TriLists &T, bool light) const {
+        const Span *sp[6] = {&T.d01, &T.d10, &T.d02, &T.d20, &T.d12, &T.d21};
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            F.ls[k][lane] = sp[k]->s;
+            F.ln[k][lane] = sp[k]->n;
+            if constexpr (kShort) {
+                F.lo[k][lane] = sp[k]->lo;
+                F.hi[k][lane] = sp[k]->hi;
+            }
+        }
         F.live[lane] = light ? live(T) : 0u;
     }
-    __device__ inline void flat(const FlatLds &F, int si, int64_t r) const {
+    __device__ inline void flat(const Flat &F, int si, int64_t r) const {
         flat_run<VAR, 0, 1, SS>(F, si, 0, r, ts, op) || flat_run<VAR, 1, 0, SS>(F, si, 1, r, ts, op) ||
             flat_run<VAR, 0, 2, SS>(F, si, 2, r, ts, op) || flat_run<VAR, 2, 0, SS>(F, si, 3, r, ts, op) ||
             flat_run<VAR, 1, 2, SS>(F, si, 4, r, ts, op) || flat_run<VAR, 2, 1, SS>(F, si, 5, r, ts, op);
@@ -1083,7 +1121,7 @@ __global__ __launch_bounds__(BLK) void k_tests_light(const int64_t *__restrict__
                                                      const int32_t *__restrict__ gitem, int32_t NI, R runner,
                                                      Heavy *__restrict__ heavy,
                                                      unsigned long long *__restrict__ counter, int64_t cap) {
-    __shared__ FlatLds flds[R::kFlat ? WPB : 1];
+    __shared__ typename R::Flat flds[R::kFlat ? WPB : 1];
     const int w = wave_id();
     const int lane = lane_id();
     const int64_t nsurv = sbase[NI];
@@ -1103,7 +1141,7 @@ __global__ __launch_bounds__(BLK) void k_tests_light(const int64_t *__restrict__
         defer_heavy(runner, S, slot, wk, np, heavy, counter, cap, full);
         const int64_t light = np ? 0 : wk;
         if constexpr (R::kFlat) {
-            FlatLds &F = flds[w];
+            typename R::Flat &F = flds[w];
             const int32_t incl = (int32_t)wave_inclusive_sum(light);
             const int32_t total = __shfl(incl, 63);
             if (total == 0) continue;

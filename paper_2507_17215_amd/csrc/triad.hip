@@ -141,6 +141,7 @@ __device__ inline void triad_runs(const TriLists &L, uint32_t dq, const int64_t 
 // = 1 on a 64-bit overflow.
 template <int VAR, bool INST> struct TriadRunner {
     static constexpr bool kFlat = false; // a run's tests share their window bookkeeping
+    using Flat = FlatLds<false>;
     using Surv = TriLists;
     uint32_t dq;
     const int64_t *ts;
