@@ -189,6 +189,51 @@ def test_borrowed_device_inputs_equal_copied_ones():
     assert rc == folty.EINVAL and not h.value
 
 
+def test_short_lists_on_and_off_agree():
+    """Lists of one or two entries are read from their records' end timestamps
+    when every timestamp is below 2^32; the tiny workload's clock scaled by 5,000
+    (up to 5e9) turns that off.  Both graphs, at matching windows and all 8
+    predicate codes, give the oracle's counts, pairs and certificate counts."""
+    g = synth.tiny(seed=61)
+    k = 5000
+    t2 = g.t * k + 7
+    assert g.t.max() < 2**32 <= t2.max()
+    G1, G2 = gpu_graph(g), folty.Graph(g.n, g.src, g.dst, t2).build()
+    o1, o2 = Oracle(g.n, g.src, g.dst, g.t), Oracle(g.n, g.src, g.dst, t2)
+    for delta in (2000, 50_000, 400_000):
+        for v in range(8):
+            say("short lists", delta, v)
+            want = o1.query(delta, 1, 2, v)
+            assert_same(G1.query(delta, (1, 2), v), want)
+            assert_same(G2.query(delta * k, (1, 2), v), o2.query(delta * k, 1, 2, v))
+            assert np.array_equal(G2.query(delta * k, (1, 2), v).counts(), want["counts"])
+
+
+def test_core_numbers_when_row_histograms_do_not_fit():
+    """A 4,200-vertex clique makes the degree h-index 4,199, past the levels a
+    long row's kept histogram may hold: its rows are evaluated from windowed
+    block histograms and never reordered, and level counts come from row chunks.
+    A path hangs off the clique and a few vertices join both, so cores 1, 2 and
+    4,199 and several rounds occur.  Core numbers and ranks equal the oracle's."""
+    k = 4200
+    iu, ju = np.triu_indices(k, 1)
+    path = np.arange(k, k + 300)
+    src = np.concatenate([iu, path[:-1], [k + 5, k + 7, k + 9], path[:3]]).astype(np.int32)
+    dst = np.concatenate([ju, path[1:], [0, 1, 2], [10, 11, 12]]).astype(np.int32)
+    n = k + 300
+    t = np.arange(len(src), dtype=np.int64)
+    say("clique: edges", len(src))
+    o = Oracle(n, src, dst, t)
+    G = folty.Graph(n, src, dst, t).build()
+    core = o.core_numbers()
+    assert core.max() == k - 1
+    assert np.array_equal(G.core_numbers(), core)
+    assert np.array_equal(G.ranks(), o.degeneracy_rank())
+    st = G.stats()
+    assert st["max_core"] == k - 1 and st["max_out_degree"] <= k - 1
+    G.close()
+
+
 def test_orientation_does_not_change_results():
     g = synth.tiny(seed=3)
     base = gpu_graph(g).query(10**6, (1, 4), 0).counts()
