@@ -259,7 +259,6 @@ __global__ __launch_bounds__(BLK) void k_global_h(const int32_t *__restrict__ hi
     __shared__ int64_t s_tot[BLK];
     __shared__ int32_t s_best;
     const int t = threadIdx.x;
-    const int64_t high = t == 0 ? hist[top + 1] : 0;
     const int32_t per = (top + 1 + BLK - 1) / BLK;
     const int32_t hi = top - t * per;
     int64_t mine = 0;
@@ -267,13 +266,8 @@ __global__ __launch_bounds__(BLK) void k_global_h(const int32_t *__restrict__ hi
     s_tot[t] = mine;
     if (t == 0) s_best = 0;
     __syncthreads();
-    int64_t above = 0;
-    for (int k = 0; k < BLK; k++) above += k < t ? s_tot[k] : 0;
-    // every thread needs the total above top: one more pass over s_tot
-    __syncthreads();
-    s_tot[t] = high;
-    __syncthreads();
-    for (int k = 0; k < BLK; k++) above += s_tot[k];
+    int64_t above = hist[top + 1];
+    for (int k = 0; k < t; k++) above += s_tot[k];
     for (int32_t i = 0; i < per && hi - i >= 0; i++) {
         const int32_t h = hi - i;
         above += hist[h];
@@ -305,8 +299,8 @@ __global__ __launch_bounds__(BLK) void k_core_init(CoreBufs B) {
             B.lr[v] = -1;
             cls = row_class(d);
         }
-        // class-2 vertices: slots and chunk ranges with one atomic each per
-        // wavefront (thousands of them would serialise on two counters)
+        // class-2 vertices: slots and chunk ranges, one atomic per wavefront on
+        // each of the two counters
         const bool big = cls == 2;
         const unsigned long long bm = __ballot(big);
         if (bm) {
@@ -670,10 +664,9 @@ __global__ __launch_bounds__(BLK) void k_core_finish(CoreBufs B, int32_t s, bool
 // rows' chunks also add their histograms into the rows' global histograms
 // (zero beforehand), which k_core_finish reads after this kernel; otherwise the
 // long rows are evaluated here too (`fused`), from the kept histograms, which
-// only the marking kernels change.
-
-// `list`: the drops are listed for a marking pass (not after the dense sweeps
-// before the last one, whose drops no pass reads).
+// only the marking kernels change.  `list`: the drops are listed for a marking
+// pass (not after the dense sweeps before the last one, whose drops no pass
+// reads).
 __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool rescan, bool dense, bool fused,
                                                     bool list) {
     __shared__ PushLds P;
