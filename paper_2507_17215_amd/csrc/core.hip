@@ -484,22 +484,22 @@ __device__ inline int32_t h_lane(const uint16_t *c, const int32_t *__restrict__ 
 }
 
 // one wavefront; x, b, d are wavefront-uniform
-__device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
-                                 int32_t x, int32_t &ge_out) {
+template <int NJ>
+__device__ inline int32_t h_wave_n(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
+                                   int32_t x, int32_t &ge_out) {
     const int lane = lane_id();
-    constexpr int PER = C1_MAX / 64;
-    int32_t u[PER], val[PER];
+    int32_t u[NJ], val[NJ];
 #pragma unroll
-    for (int j = 0; j < PER; j++) {
+    for (int j = 0; j < NJ; j++) {
         const int32_t i = lane + 64 * j;
         u[j] = i < d ? adj[b + i] : 0;
     }
 #pragma unroll
-    for (int j = 0; j < PER; j++) val[j] = lane + 64 * j < d ? c[u[j]] : -1;
+    for (int j = 0; j < NJ; j++) val[j] = lane + 64 * j < d ? c[u[j]] : -1;
     auto count = [&](int32_t h) {
         int32_t k = 0;
 #pragma unroll
-        for (int j = 0; j < PER; j++) k += val[j] >= h ? 1 : 0;
+        for (int j = 0; j < NJ; j++) k += val[j] >= h ? 1 : 0;
         return wave_sum(k);
     };
     const int32_t ge = count(x);
@@ -515,6 +515,18 @@ __device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ 
     }
     ge_out = count(lo);
     return lo;
+}
+
+// NJ = the row's 64-entry slots rounded up to a power of two (wavefront-uniform):
+// most rows of this class fill one or two slots of the sixteen
+__device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
+                                 int32_t x, int32_t &ge_out) {
+    static_assert(C1_MAX / 64 == 16, "slot classes");
+    if (d <= 64) return h_wave_n<1>(c, adj, b, d, x, ge_out);
+    if (d <= 128) return h_wave_n<2>(c, adj, b, d, x, ge_out);
+    if (d <= 256) return h_wave_n<4>(c, adj, b, d, x, ge_out);
+    if (d <= 512) return h_wave_n<8>(c, adj, b, d, x, ge_out);
+    return h_wave_n<16>(c, adj, b, d, x, ge_out);
 }
 
 // A block's histogram workspace in dynamic LDS: bins levels (the per-row
@@ -797,6 +809,23 @@ __device__ inline void mark_batch(const CoreBufs &B, Pusher &p, const int32_t (&
     for (int j = 0; j < J; j++) push(p, st[j] != tag ? row_class(dw[j]) : -1, w[j], dw[j]);
 }
 
+// a row of at most 64 * NJ entries, one wavefront (NJ wavefront-uniform)
+template <int NJ>
+__device__ inline void mark_row(const CoreBufs &B, Pusher &p, int64_t b, int32_t d, int32_t xo, int32_t h,
+                                int32_t tag, bool rescan) {
+    const int lane = lane_id();
+    int32_t u[NJ], cw[NJ];
+    bool ok[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        ok[j] = lane + 64 * j < d;
+        u[j] = ok[j] ? B.uadj[b + lane + 64 * j] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; j++) cw[j] = ok[j] ? B.c[u[j]] : 0;
+    mark_batch<NJ>(B, p, u, cw, ok, xo, h, tag, rescan);
+}
+
 __global__ __launch_bounds__(BLK) void k_core_mark(CoreBufs B, int32_t s, bool rescan) {
     __shared__ PushLds P;
     int32_t *ctr = B.ctr;
@@ -832,17 +861,11 @@ __global__ __launch_bounds__(BLK) void k_core_mark(CoreBufs B, int32_t s, bool r
         const int64_t b = B.uoff[v];
         const int32_t d = (int32_t)(B.uoff[v + 1] - b);
         const int32_t h = B.c[v], xo = B.old[v];
-        constexpr int PER = C1_MAX / 64;
-        int32_t u[PER], cw[PER];
-        bool ok[PER];
-#pragma unroll
-        for (int j = 0; j < PER; j++) {
-            ok[j] = lane + 64 * j < d;
-            u[j] = ok[j] ? B.uadj[b + lane + 64 * j] : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < PER; j++) cw[j] = ok[j] ? B.c[u[j]] : 0;
-        mark_batch<PER>(B, p, u, cw, ok, xo, h, tag, rescan);
+        if (d <= 64) mark_row<1>(B, p, b, d, xo, h, tag, rescan);
+        else if (d <= 128) mark_row<2>(B, p, b, d, xo, h, tag, rescan);
+        else if (d <= 256) mark_row<4>(B, p, b, d, xo, h, tag, rescan);
+        else if (d <= 512) mark_row<8>(B, p, b, d, xo, h, tag, rescan);
+        else mark_row<16>(B, p, b, d, xo, h, tag, rescan);
     }
     const int64_t stride = (int64_t)gridDim.x * BLK;
     for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < n0; base += stride) {
@@ -953,6 +976,22 @@ __device__ inline void level_batch(const CoreBufs &B, Pusher &p, const int32_t (
     for (int j = 0; j < J; j++) push(p, du[j] >= 0 ? row_class(du[j]) : -1, u[j], du[j]);
 }
 
+// a row of at most 64 * NJ entries, one wavefront (NJ wavefront-uniform)
+template <int NJ>
+__device__ inline void level_row(const CoreBufs &B, Pusher &p, int64_t b, int32_t d, int32_t k, bool skip) {
+    const int lane = lane_id();
+    int32_t u[NJ], cu[NJ];
+    bool ok[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        ok[j] = lane + 64 * j < d;
+        u[j] = ok[j] ? B.uadj[b + lane + 64 * j] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; j++) cu[j] = ok[j] ? B.c[u[j]] : -1;
+    level_batch<NJ>(B, p, u, cu, ok, k, skip);
+}
+
 __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
     __shared__ PushLds P;
     int32_t *ctr = B.ctr;
@@ -992,17 +1031,11 @@ __global__ __launch_bounds__(BLK) void k_level_round(CoreBufs B, int32_t r) {
         const int64_t b = B.uoff[v];
         const int32_t d = (int32_t)(B.uoff[v + 1] - b);
         const int32_t k = B.c[v];
-        constexpr int PER = C1_MAX / 64;
-        int32_t u[PER], cu[PER];
-        bool ok[PER];
-#pragma unroll
-        for (int j = 0; j < PER; j++) {
-            ok[j] = lane + 64 * j < d;
-            u[j] = ok[j] ? B.uadj[b + lane + 64 * j] : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < PER; j++) cu[j] = ok[j] ? B.c[u[j]] : -1;
-        level_batch<PER>(B, p, u, cu, ok, k, r > 0);
+        if (d <= 64) level_row<1>(B, p, b, d, k, r > 0);
+        else if (d <= 128) level_row<2>(B, p, b, d, k, r > 0);
+        else if (d <= 256) level_row<4>(B, p, b, d, k, r > 0);
+        else if (d <= 512) level_row<8>(B, p, b, d, k, r > 0);
+        else level_row<16>(B, p, b, d, k, r > 0);
     }
     const int64_t stride = (int64_t)gridDim.x * BLK;
     for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < n0; base += stride) {
