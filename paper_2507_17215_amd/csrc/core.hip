@@ -529,6 +529,41 @@ __device__ inline int32_t h_wave(const uint16_t *c, const int32_t *__restrict__ 
     return h_wave_n<16>(c, adj, b, d, x, ge_out);
 }
 
+// A row of at most 64 entries over a group of 16 lanes (four entries each); b,
+// d and x are uniform within the group, and sums stay inside it.
+__device__ inline int32_t h_group16(const uint16_t *c, const int32_t *__restrict__ adj, int64_t b, int32_t d,
+                                    int32_t x, int32_t &ge_out) {
+    const int gl = lane_id() & 15;
+    int32_t u[4], val[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int32_t i = gl + 16 * j;
+        u[j] = i < d ? adj[b + i] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) val[j] = gl + 16 * j < d ? c[u[j]] : -1;
+    auto count = [&](int32_t h) {
+        int32_t k = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) k += val[j] >= h ? 1 : 0;
+        for (int o = 8; o > 0; o >>= 1) k += __shfl_xor(k, o);
+        return k;
+    };
+    const int32_t ge = count(x);
+    if (ge >= x) {
+        ge_out = ge;
+        return x;
+    }
+    int32_t lo = ge, hi = x - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (count(mid) >= mid) lo = mid;
+        else hi = mid - 1;
+    }
+    ge_out = count(lo);
+    return lo;
+}
+
 // A block's histogram workspace in dynamic LDS: bins levels (the per-row
 // histogram width, or HX_BINS for windowed evaluation), a sum per thread and the
 // answer.  Sized to the graph, so kernels that carry it keep their occupancy
@@ -729,20 +764,48 @@ __global__ __launch_bounds__(BLK) void k_core_sweep(CoreBufs B, int32_t s, bool 
     }
     const int64_t gwave = ((int64_t)blockIdx.x * BLK + t) >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * WPB;
-    for (int64_t i = gwave; i < n1; i += nwaves) {
-        const int32_t v = L1[i];
-        const int64_t b = B.uoff[v];
-        const int32_t d = (int32_t)(B.uoff[v + 1] - b);
-        const int32_t x = B.c[v];
-        int32_t ge;
-        const int32_t h = h_wave(B.c, B.uadj, b, d, x, ge);
-        const bool drop = lane == 0 && h < x;
-        if (lane == 0) B.cnt[v] = ge;
-        if (drop) {
-            B.old[v] = x;
-            B.c[v] = h;
+    // four list entries per wavefront and step: rows of at most 64 entries take
+    // a group of 16 lanes each, longer ones the whole wavefront in turn
+    for (int64_t i0 = gwave * 4; i0 < n1; i0 += nwaves * 4) {
+        const int grp = lane >> 4, gl = lane & 15;
+        const int64_t i = i0 + grp;
+        int32_t v = -1, d = 0, x = 0;
+        int64_t b = 0;
+        if (i < n1) {
+            v = L1[i];
+            b = B.uoff[v];
+            d = (int32_t)(B.uoff[v + 1] - b);
+            x = B.c[v];
+        }
+        const bool small = v >= 0 && d <= 64;
+        bool drop = false;
+        if (small) { // uniform within the group
+            int32_t ge;
+            const int32_t h = h_group16(B.c, B.uadj, b, d, x, ge);
+            drop = gl == 0 && h < x;
+            if (gl == 0) B.cnt[v] = ge;
+            if (drop) {
+                B.old[v] = x;
+                B.c[v] = h;
+            }
         }
         if (list) push(p, drop ? 1 : -1, v, d);
+        unsigned long long big = __ballot(gl == 0 && v >= 0 && !small);
+        while (big) {
+            const int src = __ffsll((long long)big) - 1;
+            big &= big - 1;
+            const int32_t vv = __shfl(v, src), dd = __shfl(d, src), xx = __shfl(x, src);
+            const int64_t bb = __shfl(b, src);
+            int32_t ge;
+            const int32_t h = h_wave(B.c, B.uadj, bb, dd, xx, ge);
+            const bool dr = lane == 0 && h < xx;
+            if (lane == 0) B.cnt[vv] = ge;
+            if (dr) {
+                B.old[vv] = xx;
+                B.c[vv] = h;
+            }
+            if (list) push(p, dr ? 1 : -1, vv, dd);
+        }
     }
     const int64_t stride = (int64_t)gridDim.x * BLK;
     for (int64_t base = (int64_t)blockIdx.x * BLK + (t & ~63); base < n0; base += stride) {
