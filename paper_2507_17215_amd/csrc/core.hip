@@ -54,9 +54,9 @@ constexpr int PB_CAP = 256;          // buffered list entries per wavefront and 
 constexpr int RESCAN_SWEEPS = 4;
 // Sweeps that evaluate every vertex, without marking: early on most vertices
 // drop in each sweep, and a marking pass over their rows plus a sweep over the
-// listed ones costs more than one sweep over all (70M edges: sweep over all
-// 0.6 ms; marking + listed sweep 1.58, 1.18, 0.89, 0.66 ms for sweeps 1-4 with
-// 32-bit values; build ms with 4 rescanning sweeps: 2 dense 20.5, 3 20.1, 4 19.8).
+// listed ones costs more than one sweep over all (70M edges, 32-bit values:
+// sweep over all 0.74 ms; marking + listed sweep 1.58, 1.18, 0.89, 0.66 ms for
+// sweeps 1-4; build ms with 4 rescanning sweeps: 2 dense 20.5, 3 20.1, 4 19.8).
 constexpr int DENSE_SWEEPS = 4;
 static_assert(DENSE_SWEEPS >= 1 && DENSE_SWEEPS <= RESCAN_SWEEPS, "kept histograms need every drop marked");
 
