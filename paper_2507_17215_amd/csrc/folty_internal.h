@@ -449,6 +449,8 @@ size_t exclusive_scan_i32_to_i64(void *tmp, size_t tmp_bytes, const int32_t *in,
                                  int64_t n, hipStream_t stream);
 size_t inclusive_scan_i32(void *tmp, size_t tmp_bytes, const int32_t *in, int32_t *out, int64_t n,
                           hipStream_t stream);
+size_t inclusive_scan_pair_starts(void *tmp, size_t tb, const uint64_t *key, int32_t *out, int64_t n,
+                                  hipStream_t s);
 size_t exclusive_scan_i32(void *tmp, size_t tmp_bytes, const int32_t *in, int32_t *out, int64_t n,
                           hipStream_t stream);
 

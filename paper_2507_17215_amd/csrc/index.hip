@@ -167,12 +167,6 @@ __device__ inline void divmod_n(uint64_t x, uint64_t n, double inv_n, int32_t &q
     r = (int32_t)rr;
 }
 
-__global__ void k_static_flags(const uint64_t *__restrict__ key, int32_t m, int32_t *__restrict__ flag) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    flag[k] = (k == 0 || (key[k] >> 1) != (key[k - 1] >> 1)) ? 1 : 0;
-}
-
 __global__ void k_static_table(const uint64_t *__restrict__ key, int32_t *__restrict__ sid, int32_t m,
                                int64_t n, double inv_n, int32_t *__restrict__ soff, int32_t *__restrict__ smid,
                                int32_t *__restrict__ slo, int32_t *__restrict__ shi) {
@@ -559,12 +553,9 @@ void build_index(Graph *g, const folty_build_opts *opts) {
     // ---- static edge table -----------------------------------------------------
     int32_t S = 0;
     if (m > 0) {
-        DevBuf flag;
-        flag.ensure(4 * (size_t)m);
-        k_static_flags<<<grid_for(m, BLK), BLK, 0, s>>>(pkey2.as<uint64_t>(), m, flag.as<int32_t>());
-        FOLTY_LAUNCHED();
-        size_t need = inclusive_scan_i32(nullptr, 0, flag.as<int32_t>(), ix.sid.as<int32_t>(), m, s);
-        inclusive_scan_i32(cub_ensure(need), need, flag.as<int32_t>(), ix.sid.as<int32_t>(), m, s);
+        // sid[k] = 1 + the static pair of sorted edge k (k_static_table makes it 0-based)
+        size_t need = inclusive_scan_pair_starts(nullptr, 0, pkey2.as<uint64_t>(), ix.sid.as<int32_t>(), m, s);
+        inclusive_scan_pair_starts(cub_ensure(need), need, pkey2.as<uint64_t>(), ix.sid.as<int32_t>(), m, s);
         FOLTY_HIP(hipMemcpyAsync(hb.p, ix.sid.as<int32_t>() + (m - 1), 4, hipMemcpyDeviceToHost, s));
         FOLTY_HIP(hipStreamSynchronize(s));
         S = *hb.as<int32_t>();

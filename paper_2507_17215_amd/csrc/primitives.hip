@@ -16,6 +16,8 @@
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "folty_internal.h"
 
@@ -92,6 +94,26 @@ size_t exclusive_scan_i32_to_i64(void *tmp, size_t tb, const int32_t *in, int64_
 
 size_t exclusive_scan_i32(void *tmp, size_t tb, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
     return scan_exclusive(tmp, tb, in, out, n, s);
+}
+
+namespace {
+// 1 where a new (lo, hi) pair starts in the sorted grouping keys (key >> 1)
+struct PairStart {
+    const uint64_t *key;
+    __device__ int32_t operator()(int64_t k) const { return k == 0 || (key[k] >> 1) != (key[k - 1] >> 1); }
+};
+} // namespace
+
+// out[k] = 1 + the index of the static pair of sorted key k: an inclusive scan
+// of pair starts computed from the keys as the scan reads them
+size_t inclusive_scan_pair_starts(void *tmp, size_t tb, const uint64_t *key, int32_t *out, int64_t n,
+                                  hipStream_t s) {
+    auto in = rocprim::make_transform_iterator(rocprim::counting_iterator<int64_t>(0), PairStart{key});
+    size_t need = 0;
+    FOLTY_PRIM(rocprim::inclusive_scan(nullptr, need, in, out, (size_t)n, rocprim::plus<int32_t>(), s));
+    if (!tmp) return need;
+    FOLTY_PRIM(rocprim::inclusive_scan(tmp, tb, in, out, (size_t)n, rocprim::plus<int32_t>(), s));
+    return need;
 }
 
 size_t inclusive_scan_i32(void *tmp, size_t tb, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
