@@ -48,7 +48,11 @@ constexpr int32_t HX_BINS = 4096;    // LDS histogram of the h-index of a long r
 constexpr int32_t HG_BINS = (1 << 16) + 1; // degree histogram for the global h-index: levels up to 2^16 - 1,
                                            // and one bin above
 constexpr int32_t HG_LDS = 1024;     // degrees below this are counted in LDS first
-constexpr int PB_CAP = 256;          // buffered list entries per wavefront and class
+// Buffered list entries per wavefront and class.  Every flush is an atomic on
+// one of a few counters, and those serialise (about 10 ns each): listing all 4M
+// vertices of the 70M-edge graph took 172 us with 256 entries, 79 us with 1024
+// (the level counts' frontier 127 -> 42 us); 32 KB of LDS per block.
+constexpr int PB_CAP = 1024;
 // Sweeps that rescan long rows before their histograms are kept and the rows
 // reordered (70M edges, build ms: 4 -> 19.8, 3 -> 19.9, 5 -> 20.0, 8 -> 20.3).
 constexpr int RESCAN_SWEEPS = 4;
